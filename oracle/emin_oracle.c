@@ -1,0 +1,861 @@
+/*
+ * Plain FP64 CPU oracle for the EMIN-AMG Q2-Q1 grid-transfer setup of
+ * Prokopenko & Tuminaro (arXiv:1607.02489).  TEST INFRASTRUCTURE ONLY:
+ * the parity reference for the HIP path, sharing no code with it.
+ *
+ * Paper map of this file:
+ *   orc_filter / orc_symmetrize  -- sec. 4.1, eq. (e:filtering): drop weak
+ *       couplings of Z = B B^T (and of the velocity block) and lump them to
+ *       the diagonal so row sums are preserved (Alg. 2,
+ *       form_aux_block_diagonal).
+ *   orc_coarsen_pressure         -- Alg. 3 (find_coarse_pressures) with
+ *       update_heuristics and find_extra_dist3_Cpoints (sec. 4.1).
+ *   orc_pressure_pattern         -- sec. 4.1, N^(p)_ij = 1 iff j in S_i.
+ *   orc_midpoints                -- Alg. 4 (find_velocity_Cpoints), sec. 4.2.
+ *   orc_velocity_pattern         -- sec. 4.2: C^(v) within graph distance 3
+ *       in the nodal graph of the filtered velocity block, plus the extra
+ *       velocity C points for F^(v) far from every C^(v).
+ *   orc_emin                     -- sec. 4.3, eq. (min_problem): constrained
+ *       energy minimisation from the row-normalised binary pattern, by CG
+ *       on the subspace that keeps the pattern and the constraint.
+ *   orc_rap                      -- Alg. 1: A_{l+1} = R A P with R = P^T.
+ *
+ * Readings where the paper is silent (vertex 0 as the initial vertex, argmin
+ * ties by index, h1 over C within distance 4, the extra-point thresholds,
+ * the mid-point closeness test in squared form, C rows fixed to injection)
+ * are stated at the function that takes them.
+ *
+ * parity unpinned: the thresholds of orc_coarsen_pressure's extra-point pass
+ * (the paper gives no constants); only invariants pin that pass.
+ */
+#include "emin_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+void orc_free(void *p) { free(p); }
+
+void orc_csr_free(orc_csr *a) {
+  if (!a) return;
+  free(a->rowptr); free(a->col); free(a->val);
+  a->rowptr = NULL; a->col = NULL; a->val = NULL;
+}
+
+static int csr_alloc(orc_csr *a, int64_t nrows, int64_t ncols, int64_t nnz, int with_val) {
+  a->nrows = nrows; a->ncols = ncols;
+  a->rowptr = (int64_t *)calloc((size_t)(nrows + 1), sizeof(int64_t));
+  a->col = (int32_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t));
+  a->val = with_val ? (double *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(double)) : NULL;
+  return (a->rowptr && a->col && (!with_val || a->val)) ? ORC_OK : ORC_ERR_ARG;
+}
+
+static int cmp_i32(const void *a, const void *b) {
+  int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+  return (x > y) - (x < y);
+}
+
+/* ------------------------------------------------------------------ */
+/* generic sparse helpers                                              */
+/* ------------------------------------------------------------------ */
+int orc_transpose(const orc_csr *A, orc_csr *At) {
+  int64_t nnz = A->rowptr[A->nrows];
+  if (csr_alloc(At, A->ncols, A->nrows, nnz, A->val != NULL)) return ORC_ERR_ARG;
+  for (int64_t e = 0; e < nnz; e++) At->rowptr[A->col[e] + 1]++;
+  for (int64_t i = 0; i < At->nrows; i++) At->rowptr[i + 1] += At->rowptr[i];
+  int64_t *fill = (int64_t *)malloc((size_t)(At->nrows + 1) * sizeof(int64_t));
+  memcpy(fill, At->rowptr, (size_t)(At->nrows + 1) * sizeof(int64_t));
+  for (int64_t i = 0; i < A->nrows; i++)
+    for (int64_t e = A->rowptr[i]; e < A->rowptr[i + 1]; e++) {
+      int64_t p = fill[A->col[e]]++;
+      At->col[p] = (int32_t)i;
+      if (A->val) At->val[p] = A->val[e];
+    }
+  free(fill);
+  return ORC_OK;
+}
+
+/* C = A*B.  For every row i, k runs over A's row in ascending order and,
+ * for each k, j over B's row k; c_ij accumulates a_ik*b_kj in that order
+ * starting from 0.0.  The pattern is structural (no value-based dropping). */
+int orc_spgemm(const orc_csr *A, const orc_csr *B, orc_csr *C) {
+  if (A->ncols != B->nrows) return ORC_ERR_SHAPE;
+  int64_t n = A->nrows, m = B->ncols;
+  int64_t *marker = (int64_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+  for (int64_t j = 0; j < m; j++) marker[j] = -1;
+  /* symbolic */
+  int64_t *rp = (int64_t *)calloc((size_t)(n + 1), sizeof(int64_t));
+  for (int64_t i = 0; i < n; i++) {
+    int64_t c = 0;
+    for (int64_t e = A->rowptr[i]; e < A->rowptr[i + 1]; e++) {
+      int32_t k = A->col[e];
+      for (int64_t f = B->rowptr[k]; f < B->rowptr[k + 1]; f++) {
+        int32_t j = B->col[f];
+        if (marker[j] != i) { marker[j] = i; c++; }
+      }
+    }
+    rp[i + 1] = rp[i] + c;
+  }
+  int with_val = (A->val != NULL && B->val != NULL);
+  if (csr_alloc(C, n, m, rp[n], with_val)) { free(marker); free(rp); return ORC_ERR_ARG; }
+  memcpy(C->rowptr, rp, (size_t)(n + 1) * sizeof(int64_t));
+  free(rp);
+  for (int64_t j = 0; j < m; j++) marker[j] = -1;
+  double *acc = (double *)malloc((size_t)(m > 0 ? m : 1) * sizeof(double));
+  for (int64_t i = 0; i < n; i++) {
+    int64_t base = C->rowptr[i], c = 0;
+    for (int64_t e = A->rowptr[i]; e < A->rowptr[i + 1]; e++) {
+      int32_t k = A->col[e];
+      for (int64_t f = B->rowptr[k]; f < B->rowptr[k + 1]; f++) {
+        int32_t j = B->col[f];
+        if (marker[j] != i) { marker[j] = i; C->col[base + c++] = j; acc[j] = 0.0; }
+        if (with_val) {
+          double prod = A->val[e] * B->val[f];
+          acc[j] = acc[j] + prod;
+        }
+      }
+    }
+    qsort(C->col + base, (size_t)c, sizeof(int32_t), cmp_i32);
+    if (with_val)
+      for (int64_t t = 0; t < c; t++) C->val[base + t] = acc[C->col[base + t]];
+  }
+  free(marker); free(acc);
+  return ORC_OK;
+}
+
+static double diag_of(const orc_csr *A, int64_t i) {
+  for (int64_t e = A->rowptr[i]; e < A->rowptr[i + 1]; e++)
+    if (A->col[e] == i) return A->val[e];
+  return 0.0;
+}
+
+/* Eq. (e:filtering): an off-diagonal z_ij is dropped when
+ * |z_ij| <= tau1 sqrt(|z_ii z_jj|); evaluated squared (keep iff
+ * z_ij*z_ij > t2*|z_ii*z_jj| with t2 = tau1*tau1), so no square root.
+ * Dropped entries are lumped into the diagonal (ascending j), which keeps
+ * every row sum.  The output always stores the diagonal. */
+int orc_filter(const orc_csr *A, double tau1, orc_csr *At, uint8_t *keep) {
+  if (A->nrows != A->ncols || !A->val) return ORC_ERR_SHAPE;
+  int64_t n = A->nrows;
+  double t2 = tau1 * tau1;
+  double *d = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+  for (int64_t i = 0; i < n; i++) d[i] = diag_of(A, i);
+  int64_t nnz = A->rowptr[n];
+  uint8_t *k = (uint8_t *)malloc((size_t)(nnz > 0 ? nnz : 1));
+  int64_t *rp = (int64_t *)calloc((size_t)(n + 1), sizeof(int64_t));
+  for (int64_t i = 0; i < n; i++) {
+    int64_t c = 1; /* diagonal */
+    for (int64_t e = A->rowptr[i]; e < A->rowptr[i + 1]; e++) {
+      int32_t j = A->col[e];
+      if (j == i) { k[e] = 1; continue; }
+      double v = A->val[e];
+      double lhs = v * v;
+      double rhs = t2 * fabs(d[i] * d[j]);
+      k[e] = (uint8_t)(lhs > rhs);
+      c += k[e];
+    }
+    rp[i + 1] = rp[i] + c;
+  }
+  if (csr_alloc(At, n, n, rp[n], 1)) { free(d); free(k); free(rp); return ORC_ERR_ARG; }
+  memcpy(At->rowptr, rp, (size_t)(n + 1) * sizeof(int64_t));
+  free(rp);
+  for (int64_t i = 0; i < n; i++) {
+    double lump = d[i];
+    for (int64_t e = A->rowptr[i]; e < A->rowptr[i + 1]; e++)
+      if (A->col[e] != i && !k[e]) lump = lump + A->val[e];
+    int64_t p = At->rowptr[i];
+    int placed = 0;
+    for (int64_t e = A->rowptr[i]; e < A->rowptr[i + 1]; e++) {
+      int32_t j = A->col[e];
+      if (!placed && j > i) { At->col[p] = (int32_t)i; At->val[p] = lump; p++; placed = 1; }
+      if (j == i) continue;
+      if (k[e]) { At->col[p] = j; At->val[p] = A->val[e]; p++; }
+    }
+    if (!placed) { At->col[p] = (int32_t)i; At->val[p] = lump; p++; }
+  }
+  if (keep) memcpy(keep, k, (size_t)nnz);
+  free(k); free(d);
+  return ORC_OK;
+}
+
+/* M = (A + A^T)/2 on the union of both patterns; m_ij = (a_ij + a_ji)*0.5
+ * with a missing entry read as 0.0 (exactly A when A is symmetric).  For a
+ * non-symmetric (Oseen) block this is the operator whose energy is
+ * trace(P^T A P) (sec. 4.3 takes the A-norm). */
+int orc_symmetrize(const orc_csr *A, orc_csr *M) {
+  if (A->nrows != A->ncols) return ORC_ERR_SHAPE;
+  orc_csr T;
+  if (orc_transpose(A, &T)) return ORC_ERR_ARG;
+  int64_t n = A->nrows;
+  int64_t *rp = (int64_t *)calloc((size_t)(n + 1), sizeof(int64_t));
+  for (int64_t i = 0; i < n; i++) {
+    int64_t a = A->rowptr[i], ae = A->rowptr[i + 1], b = T.rowptr[i], be = T.rowptr[i + 1], c = 0;
+    while (a < ae || b < be) {
+      if (b >= be || (a < ae && A->col[a] < T.col[b])) a++;
+      else if (a >= ae || T.col[b] < A->col[a]) b++;
+      else { a++; b++; }
+      c++;
+    }
+    rp[i + 1] = rp[i] + c;
+  }
+  if (csr_alloc(M, n, n, rp[n], 1)) { orc_csr_free(&T); free(rp); return ORC_ERR_ARG; }
+  memcpy(M->rowptr, rp, (size_t)(n + 1) * sizeof(int64_t));
+  free(rp);
+  for (int64_t i = 0; i < n; i++) {
+    int64_t a = A->rowptr[i], ae = A->rowptr[i + 1], b = T.rowptr[i], be = T.rowptr[i + 1];
+    int64_t p = M->rowptr[i];
+    while (a < ae || b < be) {
+      double x = 0.0, y = 0.0; int32_t j;
+      if (b >= be || (a < ae && A->col[a] < T.col[b])) { j = A->col[a]; x = A->val[a]; a++; }
+      else if (a >= ae || T.col[b] < A->col[a]) { j = T.col[b]; y = T.val[b]; b++; }
+      else { j = A->col[a]; x = A->val[a]; y = T.val[b]; a++; b++; }
+      M->col[p] = j; M->val[p] = (x + y) * 0.5; p++;
+    }
+  }
+  orc_csr_free(&T);
+  return ORC_OK;
+}
+
+/* A Dirichlet row (sec. 3: eliminated boundary dofs) is an identity-like
+ * row: every stored off-diagonal value is exactly 0.0. */
+int orc_dirichlet(const orc_csr *A, uint8_t *dir) {
+  for (int64_t i = 0; i < A->nrows; i++) {
+    uint8_t d = 1;
+    for (int64_t e = A->rowptr[i]; e < A->rowptr[i + 1]; e++)
+      if (A->col[e] != i && A->val[e] != 0.0) d = 0;
+    dir[i] = d;
+  }
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* graph distances                                                     */
+/* ------------------------------------------------------------------ */
+/* Breadth-first search from src up to depth maxd over the whole graph.
+ * dist[] must be -1 everywhere on entry; visited vertices (src first, then
+ * in BFS order) are written to list and their distances into dist.  The
+ * caller resets dist for the listed vertices. */
+static int64_t bfs(const orc_csr *G, int32_t src, int maxd, int32_t *dist, int32_t *list) {
+  int64_t head = 0, tail = 0;
+  list[tail++] = src; dist[src] = 0;
+  while (head < tail) {
+    int32_t v = list[head++];
+    if (dist[v] == maxd) continue;
+    for (int64_t e = G->rowptr[v]; e < G->rowptr[v + 1]; e++) {
+      int32_t w = G->col[e];
+      if (w == v || dist[w] >= 0) continue;
+      dist[w] = dist[v] + 1;
+      list[tail++] = w;
+    }
+  }
+  return tail;
+}
+
+static double euclid(const double *x, int dim, int64_t a, int64_t b) {
+  double s = 0.0;
+  for (int d = 0; d < dim; d++) {
+    double t = x[a * dim + d] - x[b * dim + d];
+    s = s + t * t;
+  }
+  return sqrt(s);
+}
+
+/* growable per-vertex S lists */
+typedef struct { int32_t *c; int32_t *d; int32_t n, cap; } slist;
+
+static void slist_push(slist *s, int32_t c, int32_t d) {
+  if (s->n == s->cap) {
+    s->cap = s->cap ? 2 * s->cap : 4;
+    s->c = (int32_t *)realloc(s->c, (size_t)s->cap * sizeof(int32_t));
+    s->d = (int32_t *)realloc(s->d, (size_t)s->cap * sizeof(int32_t));
+  }
+  s->c[s->n] = c; s->d[s->n] = d; s->n++;
+}
+
+enum { ST_U = 0, ST_CAND = 1, ST_F = 2, ST_C = 3 };
+
+/* Alg. 3, sec. 4.1.  Readings:
+ *  - the initial "arbitrary vertex" is vertex 0 (the lower-left corner in
+ *    lexicographic order, the paper's p_{0,0} example);
+ *  - distance = fewest edge traversals in the undirected graph G;
+ *  - update_heuristics: for every vertex j with 1 <= dist(k,j) <= 4 of the
+ *    new C point k: cnt_j += 1, rs_j += 1/|x_j - x_k|, gs_j += dist, and
+ *    h1_j = cnt_j/rs_j is the harmonic mean of the Euclidean distances to
+ *    the C points within distance 4 (h2_j = gs_j/cnt_j, the mean graph
+ *    distance, is kept for the extra-point pass);
+ *  - next k = argmin over Cand of (h1, index); with Cand empty, the
+ *    smallest-index unmarked vertex.
+ * find_extra_dist3_Cpoints (thresholds are the project's own; the paper
+ * gives none): in ascending order, pass 1 converts an F vertex j with
+ * |S_j| = 1 whose C point c is at graph distance 3 and |x_j - x_c| >
+ * 2.5*ebar_j (ebar_j = mean Euclidean length of j's graph edges); pass 2
+ * converts j with |S_j| = 2, both at graph distance 3, mean Euclidean
+ * distance > 2.5*ebar_j, and distance from x_j to the segment between the
+ * two C points > 1.0*ebar_j.  A converted vertex is added to the S set of
+ * every vertex within distance 3 of it. */
+int orc_coarsen_pressure(const orc_csr *G, const double *x, int dim,
+                         uint8_t *is_c, orc_csr *S, int32_t **sdist,
+                         int32_t **order_out, int64_t *n_c, int64_t *n_alg3) {
+  int64_t n = G->nrows;
+  uint8_t *st = (uint8_t *)calloc((size_t)(n > 0 ? n : 1), 1);
+  int32_t *cnt = (int32_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
+  int32_t *gs = (int32_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
+  double *rs = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+  int32_t *dist = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  int32_t *list = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  int32_t *order = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  slist *sl = (slist *)calloc((size_t)(n > 0 ? n : 1), sizeof(slist));
+  for (int64_t i = 0; i < n; i++) dist[i] = -1;
+  int64_t nc = 0;
+  int64_t k = n > 0 ? 0 : -1;
+  while (k >= 0) {
+    int64_t nv = bfs(G, (int32_t)k, 4, dist, list);
+    for (int64_t t = 0; t < nv; t++) {
+      int32_t v = list[t];
+      if (dist[v] <= 3) slist_push(&sl[v], (int32_t)k, dist[v]);
+    }
+    st[k] = ST_C;
+    order[nc++] = (int32_t)k;
+    for (int64_t t = 0; t < nv; t++) {
+      int32_t v = list[t];
+      int32_t dv = dist[v];
+      if (dv >= 1 && dv <= 3 && (st[v] == ST_U || st[v] == ST_CAND)) st[v] = ST_F;
+      if (dv == 4 && st[v] == ST_U) st[v] = ST_CAND;
+      if (dv >= 1) {
+        cnt[v] += 1;
+        rs[v] = rs[v] + 1.0 / euclid(x, dim, v, k);
+        gs[v] += dv;
+      }
+    }
+    for (int64_t t = 0; t < nv; t++) dist[list[t]] = -1;
+    /* next C point: argmin over Cand of (h1, index) */
+    int64_t best = -1; double bh = 0.0;
+    for (int64_t j = 0; j < n; j++) {
+      if (st[j] != ST_CAND) continue;
+      double h1 = (double)cnt[j] / rs[j];
+      if (best < 0 || h1 < bh) { best = j; bh = h1; }
+    }
+    if (best < 0)
+      for (int64_t j = 0; j < n; j++)
+        if (st[j] == ST_U) { best = j; break; }
+    k = best;
+  }
+  *n_alg3 = nc;
+  /* find_extra_dist3_Cpoints */
+  double *ebar = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+  for (int64_t j = 0; j < n; j++) {
+    double s = 0.0; int64_t deg = 0;
+    for (int64_t e = G->rowptr[j]; e < G->rowptr[j + 1]; e++) {
+      if (G->col[e] == j) continue;
+      s = s + euclid(x, dim, j, G->col[e]);
+      deg++;
+    }
+    ebar[j] = deg ? s / (double)deg : 0.0;
+  }
+  for (int pass = 1; pass <= 2; pass++) {
+    for (int64_t j = 0; j < n; j++) {
+      if (st[j] != ST_F) continue;
+      int conv = 0;
+      if (pass == 1 && sl[j].n == 1) {
+        int32_t c = sl[j].c[0];
+        conv = sl[j].d[0] == 3 && euclid(x, dim, j, c) > 2.5 * ebar[j];
+      } else if (pass == 2 && sl[j].n == 2) {
+        int32_t a = sl[j].c[0], b = sl[j].c[1];
+        if (sl[j].d[0] == 3 && sl[j].d[1] == 3) {
+          double ea = euclid(x, dim, j, a), eb = euclid(x, dim, j, b);
+          if (0.5 * (ea + eb) > 2.5 * ebar[j]) {
+            /* distance from x_j to the segment [x_a, x_b] */
+            double num = 0.0, den = 0.0;
+            for (int d = 0; d < dim; d++) {
+              double ab = x[b * dim + d] - x[a * dim + d];
+              double aj = x[j * dim + d] - x[a * dim + d];
+              num = num + aj * ab;
+              den = den + ab * ab;
+            }
+            double t = den > 0.0 ? num / den : 0.0;
+            if (t < 0.0) t = 0.0;
+            if (t > 1.0) t = 1.0;
+            double s = 0.0;
+            for (int d = 0; d < dim; d++) {
+              double ab = x[b * dim + d] - x[a * dim + d];
+              double q = x[a * dim + d] + t * ab;
+              double r = x[j * dim + d] - q;
+              s = s + r * r;
+            }
+            conv = sqrt(s) > 1.0 * ebar[j];
+          }
+        }
+      }
+      if (!conv) continue;
+      st[j] = ST_C;
+      order[nc++] = (int32_t)j;
+      int64_t nv = bfs(G, (int32_t)j, 3, dist, list);
+      for (int64_t t = 0; t < nv; t++) slist_push(&sl[list[t]], (int32_t)j, dist[list[t]]);
+      for (int64_t t = 0; t < nv; t++) dist[list[t]] = -1;
+    }
+  }
+  free(ebar);
+  /* outputs: flags, S sorted by fine index (with distances) */
+  int64_t tot = 0;
+  for (int64_t i = 0; i < n; i++) tot += sl[i].n;
+  csr_alloc(S, n, n, tot, 0);
+  int32_t *sd = (int32_t *)malloc((size_t)(tot > 0 ? tot : 1) * sizeof(int32_t));
+  for (int64_t i = 0; i < n; i++) {
+    is_c[i] = (uint8_t)(st[i] == ST_C);
+    int64_t b = S->rowptr[i];
+    S->rowptr[i + 1] = b + sl[i].n;
+    /* insertion sort of (c, d) by c: lists are short */
+    for (int32_t t = 0; t < sl[i].n; t++) {
+      int32_t c = sl[i].c[t], d = sl[i].d[t];
+      int64_t p = b + t;
+      while (p > b && S->col[p - 1] > c) { S->col[p] = S->col[p - 1]; sd[p] = sd[p - 1]; p--; }
+      S->col[p] = c; sd[p] = d;
+    }
+    free(sl[i].c); free(sl[i].d);
+  }
+  *sdist = sd;
+  *order_out = order;
+  *n_c = nc;
+  free(sl); free(st); free(cnt); free(gs); free(rs); free(dist); free(list);
+  return ORC_OK;
+}
+
+/* sec. 4.1: N^(p)_ij = 1 iff j in S_i, columns numbered by the position of
+ * the C point in ascending fine order.  A C row interpolates by injection
+ * from itself only (its pattern is {self}). */
+int orc_pressure_pattern(const orc_csr *S, const uint8_t *is_c, orc_csr *N) {
+  int64_t n = S->nrows;
+  int32_t *cid = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  int64_t nc = 0;
+  for (int64_t i = 0; i < n; i++) cid[i] = is_c[i] ? (int32_t)nc++ : -1;
+  int64_t *rp = (int64_t *)calloc((size_t)(n + 1), sizeof(int64_t));
+  for (int64_t i = 0; i < n; i++)
+    rp[i + 1] = rp[i] + (is_c[i] ? 1 : (S->rowptr[i + 1] - S->rowptr[i]));
+  csr_alloc(N, n, nc, rp[n], 0);
+  memcpy(N->rowptr, rp, (size_t)(n + 1) * sizeof(int64_t));
+  free(rp);
+  for (int64_t i = 0; i < n; i++) {
+    int64_t p = N->rowptr[i];
+    if (is_c[i]) { N->col[p] = cid[i]; continue; }
+    for (int64_t e = S->rowptr[i]; e < S->rowptr[i + 1]; e++) N->col[p++] = cid[S->col[e]];
+  }
+  free(cid);
+  return ORC_OK;
+}
+
+/* Alg. 4 (find_velocity_Cpoints), sec. 4.2.  Readings:
+ *  - F vertices are visited by (|S_i| descending, index ascending), as the
+ *    paper's implementation orders the loop; vertices with |S_i| < 2 are
+ *    skipped (their barycentre is a C point itself);
+ *  - X_i = sum of x_c over S_i (ascending index) divided by |S_i|;
+ *  - B_i = { j in F : S_i subset of S_j }, found from the F vertices that
+ *    interpolate from one C point of S_i;
+ *  - m = argmin over B_i of (|x_j - X_i|^2, index);
+ *  - the closeness scale t_i is the diagonal of the bounding box of B_i and
+ *    |.|_* is Euclidean; the test is taken squared: m joins C-bar unless a
+ *    j in (B_i intersect C-bar) has |x_j - x_m|^2 < tau2^2 * t_i^2. */
+int orc_midpoints(const orc_csr *S, const uint8_t *is_c, const double *x,
+                  int dim, double tau2_sq, uint8_t *cbar, int64_t *n_added) {
+  int64_t n = S->nrows;
+  orc_csr ST;   /* for each C point, the vertices whose S set holds it */
+  orc_transpose(S, &ST);
+  int64_t nf = 0;
+  int32_t *ord = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  for (int64_t i = 0; i < n; i++)
+    if (!is_c[i] && S->rowptr[i + 1] - S->rowptr[i] >= 2) ord[nf++] = (int32_t)i;
+  /* stable insertion into order: (|S| desc, index asc) via counting by size */
+  int64_t maxs = 0;
+  for (int64_t t = 0; t < nf; t++) {
+    int64_t s = S->rowptr[ord[t] + 1] - S->rowptr[ord[t]];
+    if (s > maxs) maxs = s;
+  }
+  int32_t *sorted = (int32_t *)malloc((size_t)(nf > 0 ? nf : 1) * sizeof(int32_t));
+  int64_t q = 0;
+  for (int64_t s = maxs; s >= 2; s--)
+    for (int64_t t = 0; t < nf; t++)
+      if (S->rowptr[ord[t] + 1] - S->rowptr[ord[t]] == s) sorted[q++] = ord[t];
+  free(ord);
+  int32_t *Bl = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  int64_t added = 0;
+  for (int64_t t = 0; t < nf; t++) {
+    int32_t i = sorted[t];
+    int64_t s0 = S->rowptr[i], s1 = S->rowptr[i + 1];
+    int64_t si = s1 - s0;
+    double X[3] = {0.0, 0.0, 0.0};
+    for (int d = 0; d < dim; d++) {
+      double acc = 0.0;
+      for (int64_t e = s0; e < s1; e++) acc = acc + x[(int64_t)S->col[e] * dim + d];
+      X[d] = acc / (double)si;
+    }
+    /* B_i */
+    int32_t c0 = S->col[s0];
+    int64_t nb = 0;
+    for (int64_t e = ST.rowptr[c0]; e < ST.rowptr[c0 + 1]; e++) {
+      int32_t j = ST.col[e];
+      if (is_c[j]) continue;
+      int sub = 1;
+      for (int64_t a = s0; a < s1 && sub; a++) {
+        int found = 0;
+        for (int64_t b = S->rowptr[j]; b < S->rowptr[j + 1]; b++)
+          if (S->col[b] == S->col[a]) { found = 1; break; }
+        sub = found;
+      }
+      if (sub) Bl[nb++] = j;
+    }
+    /* closest to the target, and the bounding box of B_i */
+    int32_t m = -1; double md = 0.0;
+    double lo[3], hi[3];
+    for (int64_t b = 0; b < nb; b++) {
+      int32_t j = Bl[b];
+      double d2 = 0.0;
+      for (int d = 0; d < dim; d++) {
+        double r = x[(int64_t)j * dim + d] - X[d];
+        d2 = d2 + r * r;
+      }
+      if (m < 0 || d2 < md || (d2 == md && j < m)) { m = j; md = d2; }
+      for (int d = 0; d < dim; d++) {
+        double v = x[(int64_t)j * dim + d];
+        if (b == 0 || v < lo[d]) lo[d] = v;
+        if (b == 0 || v > hi[d]) hi[d] = v;
+      }
+    }
+    double w2 = 0.0;
+    for (int d = 0; d < dim; d++) {
+      double w = hi[d] - lo[d];
+      w2 = w2 + w * w;
+    }
+    double thr = tau2_sq * w2;
+    int ok = 1;
+    for (int64_t b = 0; b < nb && ok; b++) {
+      int32_t j = Bl[b];
+      if (!cbar[j]) continue;
+      double d2 = 0.0;
+      for (int d = 0; d < dim; d++) {
+        double r = x[(int64_t)j * dim + d] - x[(int64_t)m * dim + d];
+        d2 = d2 + r * r;
+      }
+      if (d2 < thr) ok = 0;
+    }
+    if (ok && !cbar[m]) { cbar[m] = 1; added++; }
+  }
+  *n_added = added;
+  free(Bl); free(sorted); orc_csr_free(&ST);
+  return ORC_OK;
+}
+
+/* sec. 4.2: row i of N^(v) holds every C^(v) vertex within distance 3 of i
+ * in the nodal graph of the filtered velocity block; a C row is {self}; a
+ * Dirichlet row is empty.  Extra points: in ascending order, a
+ * non-Dirichlet F vertex with no C^(v) within distance 3 becomes C^(v)
+ * (and covers its own distance-3 ball from then on). */
+int orc_velocity_pattern(const orc_csr *G, const uint8_t *dir, uint8_t *cv,
+                         orc_csr *N, int64_t *n_extra) {
+  int64_t n = G->nrows;
+  int32_t *dist = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  int32_t *list = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  uint8_t *cov = (uint8_t *)calloc((size_t)(n > 0 ? n : 1), 1);
+  for (int64_t i = 0; i < n; i++) dist[i] = -1;
+  for (int64_t c = 0; c < n; c++) {
+    if (!cv[c]) continue;
+    int64_t nv = bfs(G, (int32_t)c, 3, dist, list);
+    for (int64_t t = 0; t < nv; t++) { cov[list[t]] = 1; dist[list[t]] = -1; }
+  }
+  int64_t ex = 0;
+  for (int64_t i = 0; i < n; i++) {
+    if (cv[i] || dir[i] || cov[i]) continue;
+    cv[i] = 1; ex++;
+    int64_t nv = bfs(G, (int32_t)i, 3, dist, list);
+    for (int64_t t = 0; t < nv; t++) { cov[list[t]] = 1; dist[list[t]] = -1; }
+  }
+  *n_extra = ex;
+  int32_t *cid = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  int64_t nc = 0;
+  for (int64_t i = 0; i < n; i++) cid[i] = cv[i] ? (int32_t)nc++ : -1;
+  slist *sl = (slist *)calloc((size_t)(n > 0 ? n : 1), sizeof(slist));
+  for (int64_t c = 0; c < n; c++) {
+    if (!cv[c]) continue;
+    int64_t nv = bfs(G, (int32_t)c, 3, dist, list);
+    for (int64_t t = 0; t < nv; t++) {
+      int32_t v = list[t];
+      if (v != c && !cv[v] && !dir[v]) slist_push(&sl[v], cid[c], dist[v]);
+      dist[v] = -1;
+    }
+  }
+  int64_t *rp = (int64_t *)calloc((size_t)(n + 1), sizeof(int64_t));
+  for (int64_t i = 0; i < n; i++) rp[i + 1] = rp[i] + (cv[i] ? 1 : sl[i].n);
+  csr_alloc(N, n, nc, rp[n], 0);
+  memcpy(N->rowptr, rp, (size_t)(n + 1) * sizeof(int64_t));
+  free(rp);
+  for (int64_t i = 0; i < n; i++) {
+    int64_t p = N->rowptr[i];
+    if (cv[i]) N->col[p] = cid[i];
+    else {
+      for (int32_t t = 0; t < sl[i].n; t++) N->col[p + t] = sl[i].c[t];
+      qsort(N->col + p, (size_t)sl[i].n, sizeof(int32_t), cmp_i32);
+    }
+    free(sl[i].c); free(sl[i].d);
+  }
+  free(sl); free(cid); free(dist); free(list); free(cov);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* EMIN-AMG (sec. 4.3)                                                 */
+/* ------------------------------------------------------------------ */
+/* Y = mask_N(M X): for every (i,j) in N, sum over k in M's row i
+ * (ascending) of m_ik * x_kj, where x_kj is X's entry at (k,j) or 0. */
+static void masked_spmm(const orc_csr *M, const orc_csr *N, const double *X, double *Y) {
+  for (int64_t i = 0; i < N->nrows; i++)
+    for (int64_t s = N->rowptr[i]; s < N->rowptr[i + 1]; s++) {
+      int32_t j = N->col[s];
+      double acc = 0.0;
+      for (int64_t e = M->rowptr[i]; e < M->rowptr[i + 1]; e++) {
+        int32_t k = M->col[e];
+        double xk = 0.0;
+        for (int64_t t = N->rowptr[k]; t < N->rowptr[k + 1]; t++)
+          if (N->col[t] == j) { xk = X[t]; break; }
+        acc = acc + M->val[e] * xk;
+      }
+      Y[s] = acc;
+    }
+}
+
+/* Orthogonal projection onto the tangent space of the constraints
+ * P W_c = W (one mode): C rows are fixed (set to 0); an F row r becomes
+ * r - (r.w / w.w) w with w = W_c restricted to the row's pattern. */
+static void project(const orc_csr *N, const int32_t *cidx, const double *Wc,
+                    const double *G, double *X) {
+  for (int64_t i = 0; i < N->nrows; i++) {
+    int64_t a = N->rowptr[i], b = N->rowptr[i + 1];
+    if (cidx[i] >= 0) { for (int64_t s = a; s < b; s++) X[s] = 0.0; continue; }
+    if (!(G[i] > 0.0)) continue;
+    double dot = 0.0;
+    for (int64_t s = a; s < b; s++) dot = dot + X[s] * Wc[N->col[s]];
+    double f = dot / G[i];
+    for (int64_t s = a; s < b; s++) X[s] = X[s] - f * Wc[N->col[s]];
+  }
+}
+
+static double fdot(int64_t nnz, const double *a, const double *b) {
+  double s = 0.0;
+  for (int64_t e = 0; e < nnz; e++) s = s + a[e] * b[e];
+  return s;
+}
+
+/* eq. (min_problem): minimise sum_j |P_j|_M^2 = trace(P^T M P) over P with
+ * the pattern N and P W_c = W.  Start (sec. 4.3): the binary pattern with
+ * each row scaled to meet its constraint (1/|N_i| for a 0/1 mode), i.e.
+ * P0_ij = W_i Wc_j / sum_{l in N_i} Wc_l^2; C rows are fixed injections.
+ * Then `iters` steps of CG on the subspace of pattern-supported,
+ * constraint-preserving updates (the constrained CG the paper cites),
+ * unpreconditioned, stopping early only if the residual vanishes. */
+int orc_emin(const orc_csr *M, orc_csr *P, const int32_t *cidx,
+             const double *W, const double *Wc, int iters,
+             double *energy, double *rho_out, double *gamma_out, int *its_done) {
+  int64_t n = P->nrows, nnz = P->rowptr[n];
+  if (M->nrows != n || M->ncols != n) return ORC_ERR_SHAPE;
+  if (!P->val) P->val = (double *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(double));
+  double *G = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+  int status = ORC_OK;
+  for (int64_t i = 0; i < n; i++) {
+    int64_t a = P->rowptr[i], b = P->rowptr[i + 1];
+    double g = 0.0;
+    for (int64_t s = a; s < b; s++) g = g + Wc[P->col[s]] * Wc[P->col[s]];
+    G[i] = g;
+    if (cidx[i] >= 0) { for (int64_t s = a; s < b; s++) P->val[s] = 1.0; continue; }
+    if (g > 0.0) {
+      for (int64_t s = a; s < b; s++) P->val[s] = (W[i] * Wc[P->col[s]]) / g;
+    } else {
+      for (int64_t s = a; s < b; s++) P->val[s] = 0.0;
+      if (W[i] != 0.0) status = ORC_ERR_INFEASIBLE;
+    }
+  }
+  size_t bytes = (size_t)(nnz > 0 ? nnz : 1) * sizeof(double);
+  double *R = (double *)malloc(bytes), *Z = (double *)malloc(bytes), *Q = (double *)malloc(bytes);
+  double *MP = (double *)malloc(bytes);
+  masked_spmm(M, P, P->val, MP);
+  if (energy) energy[0] = fdot(nnz, P->val, MP);
+  for (int64_t e = 0; e < nnz; e++) R[e] = -MP[e];
+  project(P, cidx, Wc, G, R);
+  for (int64_t e = 0; e < nnz; e++) Z[e] = R[e];
+  double rho = fdot(nnz, R, R);
+  if (rho_out) rho_out[0] = rho;
+  int it = 0;
+  for (; it < iters && status == ORC_OK; it++) {
+    if (rho == 0.0) break;
+    masked_spmm(M, P, Z, Q);
+    double gam = fdot(nnz, Z, Q);
+    if (gamma_out) gamma_out[it] = gam;
+    if (!(gam > 0.0)) { status = ORC_ERR_BREAKDOWN; break; }
+    double alpha = rho / gam;
+    for (int64_t e = 0; e < nnz; e++) P->val[e] = P->val[e] + alpha * Z[e];
+    project(P, cidx, Wc, G, Q);
+    for (int64_t e = 0; e < nnz; e++) R[e] = R[e] - alpha * Q[e];
+    double rho2 = fdot(nnz, R, R);
+    double beta = rho2 / rho;
+    for (int64_t e = 0; e < nnz; e++) Z[e] = R[e] + beta * Z[e];
+    rho = rho2;
+    if (rho_out) rho_out[it + 1] = rho;
+    if (energy) { masked_spmm(M, P, P->val, MP); energy[it + 1] = fdot(nnz, P->val, MP); }
+  }
+  if (its_done) *its_done = it;
+  free(G); free(R); free(Z); free(Q); free(MP);
+  return status;
+}
+
+/* Alg. 1: A_{l+1} = R A P with R = P^T (the symmetric choice of sec. 4.3).
+ * The velocity prolongator is I_d (x) Pv (sec. 4: each component uses the
+ * same pattern and P^(v) is block diagonal by component), so the coarse
+ * velocity block is I_d (x) (Pv^T Ahat Pv) and the coarse divergence is
+ * Pp^T Bdiv (I_d (x) Pv).  The zero (2,2) block stays zero. */
+int orc_rap(const orc_csr *Ahat, const orc_csr *Bdiv, int dim,
+            const orc_csr *Pv, const orc_csr *Pp, orc_csr *Ac, orc_csr *Bc) {
+  int64_t nv = Ahat->nrows, nvc = Pv->ncols;
+  if (Pv->nrows != nv || Bdiv->ncols != dim * nv || Pp->nrows != Bdiv->nrows) return ORC_ERR_SHAPE;
+  orc_csr T, PvT, X, U, PpT;
+  orc_spgemm(Ahat, Pv, &T);
+  orc_transpose(Pv, &PvT);
+  orc_spgemm(&PvT, &T, Ac);
+  /* X = I_d (x) Pv */
+  int64_t pn = Pv->rowptr[nv];
+  csr_alloc(&X, dim * nv, dim * nvc, dim * pn, 1);
+  for (int c = 0; c < dim; c++)
+    for (int64_t i = 0; i < nv; i++) {
+      int64_t r = c * nv + i;
+      X.rowptr[r + 1] = X.rowptr[r] + (Pv->rowptr[i + 1] - Pv->rowptr[i]);
+      int64_t p = X.rowptr[r];
+      for (int64_t e = Pv->rowptr[i]; e < Pv->rowptr[i + 1]; e++, p++) {
+        X.col[p] = (int32_t)(c * nvc + Pv->col[e]);
+        X.val[p] = Pv->val[e];
+      }
+    }
+  orc_spgemm(Bdiv, &X, &U);
+  orc_transpose(Pp, &PpT);
+  orc_spgemm(&PpT, &U, Bc);
+  orc_csr_free(&T); orc_csr_free(&PvT); orc_csr_free(&X); orc_csr_free(&U); orc_csr_free(&PpT);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* one level: Alg. 2 (form_interpolation) + EMIN + RAP + coordinates    */
+/* ------------------------------------------------------------------ */
+static int check_csr(const orc_csr *A) {
+  if (!A->rowptr || !A->col) return ORC_ERR_ARG;
+  for (int64_t i = 0; i < A->nrows; i++) {
+    if (A->rowptr[i + 1] < A->rowptr[i]) return ORC_ERR_PATTERN;
+    for (int64_t e = A->rowptr[i]; e < A->rowptr[i + 1]; e++) {
+      if (A->col[e] < 0 || A->col[e] >= A->ncols) return ORC_ERR_PATTERN;
+      if (e > A->rowptr[i] && A->col[e] <= A->col[e - 1]) return ORC_ERR_PATTERN;
+    }
+  }
+  return ORC_OK;
+}
+
+static int32_t *cidx_of(const uint8_t *flag, int64_t n, int64_t *nc) {
+  int32_t *c = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  int64_t k = 0;
+  for (int64_t i = 0; i < n; i++) c[i] = flag[i] ? (int32_t)k++ : -1;
+  *nc = k;
+  return c;
+}
+
+int orc_level(int dim, const orc_csr *Ahat, const orc_csr *Bdiv,
+              const double *xv, const int32_t *p2v,
+              double tau1_v, double tau1_p, double tau2_sq, int iters,
+              orc_level_t *L) {
+  memset(L, 0, sizeof(*L));
+  L->dim = dim;
+  int64_t nv = Ahat->nrows, np = Bdiv->nrows;
+  if (dim < 1 || dim > 3 || iters < 0) return L->status = ORC_ERR_ARG;
+  if (Ahat->ncols != nv || Bdiv->ncols != dim * nv) return L->status = ORC_ERR_SHAPE;
+  int st = check_csr(Ahat);
+  if (!st) st = check_csr(Bdiv);
+  if (st) return L->status = st;
+  for (int64_t i = 0; i < np; i++)
+    if (p2v[i] < 0 || p2v[i] >= nv) return L->status = ORC_ERR_ARG;
+
+  /* form_aux_block_diagonal: Z = B B^T, filtered; filtered velocity block */
+  orc_csr BT, Z, Atp, Atv;
+  orc_transpose(Bdiv, &BT);
+  orc_spgemm(Bdiv, &BT, &Z);
+  L->nnz_z = Z.rowptr[np];
+  L->keep_p = (uint8_t *)malloc((size_t)(L->nnz_z > 0 ? L->nnz_z : 1));
+  L->keep_v = (uint8_t *)malloc((size_t)(Ahat->rowptr[nv] > 0 ? Ahat->rowptr[nv] : 1));
+  orc_filter(&Z, tau1_p, &Atp, L->keep_p);
+  orc_filter(Ahat, tau1_v, &Atv, L->keep_v);
+  orc_symmetrize(&Atp, &L->Mp);
+  orc_symmetrize(&Atv, &L->Mv);
+  orc_csr_free(&BT); orc_csr_free(&Z); orc_csr_free(&Atp); orc_csr_free(&Atv);
+  L->dir = (uint8_t *)malloc((size_t)(nv > 0 ? nv : 1));
+  orc_dirichlet(Ahat, L->dir);
+
+  /* pressure coordinates are those of the co-located velocity nodes */
+  double *xp = (double *)malloc((size_t)(np > 0 ? np : 1) * dim * sizeof(double));
+  for (int64_t i = 0; i < np; i++)
+    for (int d = 0; d < dim; d++) xp[i * dim + d] = xv[(int64_t)p2v[i] * dim + d];
+
+  L->is_cp = (uint8_t *)malloc((size_t)(np > 0 ? np : 1));
+  orc_coarsen_pressure(&L->Mp, xp, dim, L->is_cp, &L->S, &L->sdist, &L->order, &L->n_cp, &L->n_alg3);
+  orc_pressure_pattern(&L->S, L->is_cp, &L->Pp);
+  L->cbar = (uint8_t *)malloc((size_t)(np > 0 ? np : 1));
+  memcpy(L->cbar, L->is_cp, (size_t)np);
+  orc_midpoints(&L->S, L->is_cp, xp, dim, tau2_sq, L->cbar, &L->n_mid);
+  L->is_cv = (uint8_t *)calloc((size_t)(nv > 0 ? nv : 1), 1);
+  for (int64_t i = 0; i < np; i++)
+    if (L->cbar[i]) L->is_cv[p2v[i]] = 1;
+  orc_velocity_pattern(&L->Mv, L->dir, L->is_cv, &L->Pv, &L->n_extra_v);
+  int64_t ncv, ncp;
+  int32_t *cv_id = cidx_of(L->is_cv, nv, &ncv);
+  int32_t *cp_id = cidx_of(L->is_cp, np, &ncp);
+  L->n_cv = ncv;
+
+  /* near-nullspace modes: velocity = 1 off the Dirichlet set, pressure = 1 */
+  double *Wv = (double *)malloc((size_t)(nv > 0 ? nv : 1) * sizeof(double));
+  double *Wp = (double *)malloc((size_t)(np > 0 ? np : 1) * sizeof(double));
+  double *Wvc = (double *)malloc((size_t)(ncv > 0 ? ncv : 1) * sizeof(double));
+  double *Wpc = (double *)malloc((size_t)(ncp > 0 ? ncp : 1) * sizeof(double));
+  for (int64_t i = 0; i < nv; i++) {
+    Wv[i] = L->dir[i] ? 0.0 : 1.0;
+    if (cv_id[i] >= 0) Wvc[cv_id[i]] = Wv[i];
+  }
+  for (int64_t i = 0; i < np; i++) {
+    Wp[i] = 1.0;
+    if (cp_id[i] >= 0) Wpc[cp_id[i]] = 1.0;
+  }
+  L->energy_v = (double *)calloc((size_t)iters + 1, sizeof(double));
+  L->energy_p = (double *)calloc((size_t)iters + 1, sizeof(double));
+  L->rho_v = (double *)calloc((size_t)iters + 1, sizeof(double));
+  L->rho_p = (double *)calloc((size_t)iters + 1, sizeof(double));
+  st = orc_emin(&L->Mv, &L->Pv, cv_id, Wv, Wvc, iters, L->energy_v, L->rho_v, NULL, &L->its_v);
+  if (!st) st = orc_emin(&L->Mp, &L->Pp, cp_id, Wp, Wpc, iters, L->energy_p, L->rho_p, NULL, &L->its_p);
+  free(Wv); free(Wp); free(Wvc); free(Wpc);
+  if (!st) st = orc_rap(Ahat, Bdiv, dim, &L->Pv, &L->Pp, &L->Ac, &L->Bc);
+  /* coarse descriptors: coordinates by injection, co-location map */
+  if (!st) {
+    L->xv_c = (double *)malloc((size_t)(ncv > 0 ? ncv : 1) * dim * sizeof(double));
+    for (int64_t i = 0; i < nv; i++)
+      if (cv_id[i] >= 0)
+        for (int d = 0; d < dim; d++) L->xv_c[(int64_t)cv_id[i] * dim + d] = xv[i * dim + d];
+    L->p2v_c = (int32_t *)malloc((size_t)(ncp > 0 ? ncp : 1) * sizeof(int32_t));
+    for (int64_t i = 0; i < np; i++)
+      if (cp_id[i] >= 0) {
+        int32_t v = cv_id[p2v[i]];
+        if (v < 0) { st = ORC_ERR_PATTERN; break; }
+        L->p2v_c[cp_id[i]] = v;
+      }
+  }
+  free(cv_id); free(cp_id); free(xp);
+  return L->status = st;
+}
+
+void orc_level_free(orc_level_t *L) {
+  orc_csr_free(&L->Mv); orc_csr_free(&L->Mp);
+  free(L->keep_v); free(L->keep_p); free(L->dir);
+  free(L->is_cp); orc_csr_free(&L->S); free(L->sdist); free(L->order);
+  free(L->cbar); free(L->is_cv);
+  orc_csr_free(&L->Pv); orc_csr_free(&L->Pp);
+  free(L->energy_v); free(L->energy_p); free(L->rho_v); free(L->rho_p);
+  orc_csr_free(&L->Ac); orc_csr_free(&L->Bc);
+  free(L->xv_c); free(L->p2v_c);
+  memset(L, 0, sizeof(*L));
+}

@@ -1,0 +1,85 @@
+"""Independent checkers used by the tests (no oracle or library code).
+
+Graph distances come from scipy's csgraph BFS, dense products from numpy,
+and the constrained energy minimum from a dense KKT solve.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+from scipy.sparse import csgraph
+
+from paper_1607_02489_amd.synth import CSR
+
+
+def graph_of(M: CSR) -> sp.csr_matrix:
+    """Undirected unweighted graph of a matrix's off-diagonal structure."""
+    A = sp.csr_matrix((np.ones(M.nnz), M.col, M.rowptr), shape=(M.nrows, M.ncols))
+    A = A + A.T
+    A.setdiag(0)
+    A.eliminate_zeros()
+    A.data[:] = 1.0
+    return A
+
+
+def hop_dist(G: sp.csr_matrix, sources, limit=None) -> np.ndarray:
+    """Hop distances from each source (rows) to every vertex (inf if none)."""
+    d = csgraph.shortest_path(G, method="D", unweighted=True, indices=np.asarray(sources))
+    return np.atleast_2d(d)
+
+
+def dense(m: CSR) -> np.ndarray:
+    out = np.zeros((m.nrows, m.ncols))
+    rows = np.repeat(np.arange(m.nrows), np.diff(m.rowptr))
+    out[rows, m.col] = m.val if m.val is not None else 1.0
+    return out
+
+
+def kkt_emin(M: np.ndarray, N: CSR, cidx: np.ndarray, W: np.ndarray, Wc: np.ndarray):
+    """Dense solve of min trace(P^T M P) s.t. P on pattern N, C rows fixed to
+    injection, P Wc = W on the other rows.  Returns P's values on N."""
+    n = N.nrows
+    rows = np.repeat(np.arange(n), np.diff(N.rowptr))
+    cols = N.col
+    free = cidx[rows] < 0
+    fixed_val = np.where(free, 0.0, 1.0)
+    fi = np.nonzero(free)[0]
+    nf = fi.size
+    # energy sum_j P_j^T M P_j couples entries (i,j),(k,j) of the same column
+    H = np.zeros((nf, nf))
+    b = np.zeros(nf)
+    bycol = {}
+    for e in range(N.nnz):
+        bycol.setdefault(cols[e], []).append(e)
+    pos = -np.ones(N.nnz, dtype=np.int64)
+    pos[fi] = np.arange(nf)
+    for j, ents in bycol.items():
+        for e in ents:
+            for f in ents:
+                mik = M[rows[e], rows[f]]
+                if mik == 0.0:
+                    continue
+                if free[e] and free[f]:
+                    H[pos[e], pos[f]] += mik
+                elif free[e] and not free[f]:
+                    b[pos[e]] += mik * fixed_val[f]
+    frows = sorted(set(rows[fi].tolist()))
+    Cm = np.zeros((len(frows), nf))
+    w = np.zeros(len(frows))
+    for r, i in enumerate(frows):
+        for e in range(N.rowptr[i], N.rowptr[i + 1]):
+            Cm[r, pos[e]] = Wc[cols[e]]
+        w[r] = W[i]
+    K = np.block([[2 * H, Cm.T], [Cm, np.zeros((len(frows), len(frows)))]])
+    rhs = np.concatenate([-2 * b, w])
+    sol = np.linalg.lstsq(K, rhs, rcond=None)[0]
+    vals = fixed_val.copy()
+    vals[fi] = sol[:nf]
+    return vals
+
+
+def relfro(a, b) -> float:
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
