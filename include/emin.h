@@ -1,0 +1,202 @@
+/*
+ * emin.h -- C ABI of the MI355X (gfx950) EMIN-AMG grid-transfer library for
+ * Q2-Q1 (Taylor-Hood) saddle-point systems, after Prokopenko & Tuminaro,
+ * "An algebraic multigrid method for Q2-Q1 mixed discretizations of the
+ * Navier-Stokes equations" (arXiv:1607.02489).
+ *
+ * One level of the paper's Alg. 1 (setup_hierarchy, without relaxation) is
+ *   emin_pattern  -- Alg. 2 up to the sparsity patterns: aux operators of
+ *                    eq. (e:filtering), Alg. 3 coarse pressures, Alg. 4
+ *                    mid-points and coarse velocities, patterns N^(p), N^(v),
+ *                    and the symbolic Galerkin product;
+ *   emin_setup    -- sec. 4.3, eq. (min_problem): the prolongator values by
+ *                    constrained CG on trace(P^T M P) from the normalised
+ *                    binary pattern;
+ *   emin_rap      -- Alg. 1, A_{l+1} = R A P with R = P^T.
+ * The coarse operator's patterns live in the pattern handle; its values in
+ * caller buffers, so a hierarchy is built by feeding level l's views and
+ * values to level l+1.
+ *
+ * Conventions
+ *  - All array pointers are DEVICE pointers unless the comment says host.
+ *  - CSR: rowptr int64[nrows+1], col int32[nnz] sorted and unique per row,
+ *    val double[nnz].
+ *  - The velocity block of the saddle system is I_d (x) Ahat (identical
+ *    component blocks, sec. 2); Bdiv holds the divergence block with the
+ *    column of component c of velocity node k at c*n_v + k.
+ *  - A Dirichlet (eliminated) velocity node is one whose Ahat row has no
+ *    nonzero off-diagonal value.
+ *  - stream is a hipStream_t (NULL = the default stream).  emin_pattern
+ *    synchronises the stream (it reads sizes back); emin_setup and
+ *    emin_rap only enqueue work and never synchronise.
+ *  - No exception crosses the ABI.  On error the outputs are untouched and
+ *    *out stays NULL.  A handle is not thread-safe; distinct handles are
+ *    independent.  Calls on one handle must not overlap in time.
+ */
+#ifndef EMIN_H
+#define EMIN_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  EMIN_OK = 0,
+  EMIN_ERR_ARG = 1,         /* NULL pointer, negative size, bad parameter */
+  EMIN_ERR_SHAPE = 2,       /* inconsistent dimensions between inputs */
+  EMIN_ERR_PATTERN = 3,     /* CSR columns unsorted, duplicated or out of range */
+  EMIN_ERR_VALUE = 4,       /* NaN/Inf in values (checked with EMIN_FLAG_VALIDATE) */
+  EMIN_ERR_INFEASIBLE = 5,  /* a row cannot meet P W_c = W (empty pattern, W_i != 0) */
+  EMIN_ERR_BREAKDOWN = 6,   /* CG met <Z, M Z> <= 0 while <R, R> > 0 */
+  EMIN_ERR_BUDGET = 7,      /* request exceeds the device-memory budget */
+  EMIN_ERR_DEVICE = 8,      /* HIP runtime error */
+  EMIN_ERR_OOM = 9,         /* device allocation failed */
+  EMIN_ERR_CAPACITY = 10,   /* a fixed per-row/per-ball capacity was exceeded */
+  EMIN_ERR_COLOCATE = 11    /* a coarse pressure without a co-located coarse velocity */
+} emin_status;
+
+enum { EMIN_PREC_F64 = 0, EMIN_PREC_MIXED = 1 };
+enum {
+  EMIN_FLAG_ENERGY = 1u,    /* emin_setup: record the energy trace(P^T M P) per step */
+  EMIN_FLAG_VALIDATE = 2u   /* check values for NaN/Inf */
+};
+#define EMIN_MAX_ITERS 32
+
+typedef struct {
+  int64_t nrows, ncols, nnz;
+  const int64_t *rowptr;
+  const int32_t *col;
+  const double *val;
+} emin_csr_t;
+
+/* One level's saddle system (sec. 2): [I_d (x) Ahat, Bdiv^T; Bdiv, 0]. */
+typedef struct {
+  int32_t dim;              /* spatial dimension d: 2 or 3 */
+  emin_csr_t Ahat;          /* n_v x n_v scalar velocity block (Stokes or Oseen) */
+  emin_csr_t Bdiv;          /* n_p x d*n_v divergence block */
+  const double *xv;         /* n_v*d velocity node coordinates (row-major) */
+  const int32_t *p2v;       /* n_p: velocity node co-located with each pressure */
+  const double *Wv;         /* n_v near-nullspace mode or NULL: 1 off the Dirichlet set */
+  const double *Wp;         /* n_p near-nullspace mode or NULL: all ones */
+} emin_system_t;
+
+/* Parameters (sec. 6 uses tau1 = 0.06 and tau2 = sqrt(1.5e-3)). */
+typedef struct {
+  double tau1_v;            /* drop tolerance of eq. (e:filtering), velocity block */
+  double tau1_p;            /* drop tolerance of eq. (e:filtering), B B^T */
+  double tau2_sq;           /* tau2^2 of Alg. 4's closeness test */
+  int32_t iters;            /* EMIN CG steps, 0..EMIN_MAX_ITERS */
+  int32_t precision;        /* EMIN_PREC_F64, or EMIN_PREC_MIXED: FP32 masked
+                               products and RAP, FP64 projection and scalars */
+  uint32_t flags;           /* EMIN_FLAG_* */
+} emin_params_t;
+
+/* Sizes of one level (host struct). */
+typedef struct {
+  int64_t n_v, n_p;         /* fine velocity nodes, fine pressures */
+  int64_t n_vc, n_pc;       /* coarse velocity nodes, coarse pressures */
+  int64_t n_cp_alg3;        /* C^(p) points chosen by Alg. 3 */
+  int64_t n_cp_extra;       /* C^(p) points added by the extra distance-3 pass */
+  int64_t n_mid;            /* mid-points added by Alg. 4 */
+  int64_t n_cv_extra;       /* C^(v) points added for uncovered velocity nodes */
+  int64_t nnz_Pv, nnz_Pp;   /* pattern sizes of the scalar velocity and pressure P */
+  int64_t nnz_Mv, nnz_Mp;   /* energy operators */
+  int64_t nnz_Ac, nnz_Bc;   /* coarse scalar velocity block and coarse divergence */
+  int64_t device_bytes;     /* device memory held by the handle */
+} emin_sizes_t;
+
+/* Device-resident report of emin_setup (read it with emin_sync_report). */
+typedef struct {
+  int32_t status;           /* emin_status of the numeric phase */
+  int32_t its_v, its_p;     /* CG steps taken per block */
+  int32_t reserved;
+  double energy_v[EMIN_MAX_ITERS + 1], energy_p[EMIN_MAX_ITERS + 1];
+  double rho_v[EMIN_MAX_ITERS + 1], rho_p[EMIN_MAX_ITERS + 1];
+  double gamma_v[EMIN_MAX_ITERS], gamma_p[EMIN_MAX_ITERS];
+} emin_report_t;
+
+/* Read-only device views held by a pattern handle (valid until destroy). */
+enum {
+  EMIN_VIEW_PV = 0,    /* CSR pattern of the scalar velocity P (n_v x n_vc) */
+  EMIN_VIEW_PP = 1,    /* CSR pattern of P^(p) (n_p x n_pc) */
+  EMIN_VIEW_AC = 2,    /* CSR pattern of the coarse scalar velocity block */
+  EMIN_VIEW_BC = 3,    /* CSR pattern of the coarse divergence block */
+  EMIN_VIEW_MV = 4,    /* CSR energy operator, velocity (values after emin_setup) */
+  EMIN_VIEW_MP = 5,    /* CSR energy operator, pressure (values after emin_setup) */
+  EMIN_VIEW_S = 6,     /* CSR of the S sets: fine C^(p) within distance 3, sorted */
+  EMIN_VIEW_ORDER = 7, /* int32[n_cp_alg3 + n_cp_extra]: C^(p) in selection order */
+  EMIN_VIEW_CP = 8,    /* int32[n_pc]: C^(p), ascending fine index */
+  EMIN_VIEW_CBAR = 9,  /* uint8[n_p]: 1 on C-bar^(p) (C^(p) and mid-points) */
+  EMIN_VIEW_CV = 10,   /* int32[n_vc]: C^(v), ascending fine index */
+  EMIN_VIEW_XVC = 11,  /* double[n_vc*d]: coarse velocity coordinates */
+  EMIN_VIEW_P2VC = 12, /* int32[n_pc]: coarse co-location map */
+  EMIN_VIEW_KEEPV = 13,/* uint8[nnz(Ahat)]: kept entries of the velocity filter */
+  EMIN_VIEW_KEEPP = 14,/* uint8[nnz(B B^T)]: kept entries of the pressure filter */
+  EMIN_VIEW_DIR = 15   /* uint8[n_v]: Dirichlet velocity nodes */
+};
+typedef struct {
+  int64_t n;                /* rows (CSR) or elements (arrays) */
+  int64_t ncols;            /* CSR columns (0 for arrays) */
+  int64_t nnz;              /* CSR nonzeros (0 for arrays) */
+  const int64_t *rowptr;    /* CSR only */
+  const int32_t *col;       /* CSR only */
+  const double *val;        /* CSR values when present, else NULL */
+  const void *data;         /* arrays */
+} emin_view_t;
+
+typedef struct emin_pattern_s emin_pattern_t;
+
+/* Alg. 2 up to the patterns, plus the symbolic RAP and the coarse
+ * descriptors (coordinates by injection, co-location map).  Borrows sys for
+ * the call; the handle owns its device memory (hipMalloc) until destroyed.
+ * Errors: ARG/SHAPE/PATTERN on bad inputs, CAPACITY, COLOCATE, DEVICE, OOM. */
+emin_status emin_pattern(const emin_system_t *sys, const emin_params_t *prm, void *stream,
+                         emin_pattern_t **out);
+
+/* Host copy of the level sizes. */
+emin_status emin_pattern_info(const emin_pattern_t *h, emin_sizes_t *out);
+
+/* Device view of one of the handle's arrays (EMIN_VIEW_*). */
+emin_status emin_pattern_view(const emin_pattern_t *h, int32_t what, emin_view_t *out);
+
+/* sec. 4.3: energy operators on the stored drop masks, then P0 and `iters`
+ * constrained CG steps per block.  sys must have the structure given to
+ * emin_pattern (values may differ: successive Picard linearisations).
+ * Pv_vals (nnz_Pv) and Pp_vals (nnz_Pp) are caller-allocated outputs.
+ * report may be NULL; device-side INFEASIBLE/BREAKDOWN land in report->status.
+ * Asynchronous on stream; uses workspace held by the handle. */
+emin_status emin_setup(emin_pattern_t *h, const emin_system_t *sys, const emin_params_t *prm,
+                       double *Pv_vals, double *Pp_vals, void *stream, emin_report_t *report);
+
+/* Alg. 1 Galerkin product with R = P^T on the unfiltered operator:
+ * Ac = Pv^T Ahat Pv (nnz_Ac values) and Bc = Pp^T Bdiv (I_d (x) Pv)
+ * (nnz_Bc values), written into caller buffers on the handle's coarse
+ * patterns.  Asynchronous on stream. */
+emin_status emin_rap(emin_pattern_t *h, const emin_system_t *sys, const double *Pv_vals,
+                     const double *Pp_vals, double *Ac_vals, double *Bc_vals, void *stream);
+
+/* Synchronises stream, copies the report to host memory and returns its status. */
+emin_status emin_sync_report(const emin_report_t *report, void *stream, emin_report_t *host);
+
+/* Copies bytes from device to host memory (synchronous on stream). */
+emin_status emin_memcpy_d2h(void *dst_host, const void *src_dev, size_t bytes, void *stream);
+
+/* Releases the handle and its device memory.  NULL-safe. */
+void emin_pattern_destroy(emin_pattern_t *h);
+
+const char *emin_status_string(emin_status s);
+const char *emin_version(void);
+
+/* Test hook: out_sqrt[i] = sqrt(x[i]), out_rcp[i] = 1/x[i] computed by the
+ * device exactly as the coarsening kernels compute them (IEEE-rounded, no
+ * contraction), so a test can compare them bitwise with the host's.  n
+ * elements, device arrays, asynchronous on stream. */
+emin_status emin_fp_probe(const double *x, double *out_sqrt, double *out_rcp, int64_t n,
+                          void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,490 @@
+// C ABI: one level of Alg. 1 as emin_pattern / emin_setup / emin_rap.
+#include <cstring>
+#include <memory>
+
+#include "coarsen.h"
+#include "emin_cg.h"
+
+using namespace emin;
+
+struct emin_pattern_s {
+  Arena ar;
+  int dim = 2;
+  int64_t n_v = 0, n_p = 0, nnzA = 0, nnzB = 0;
+  int lds_max = 65536;
+  // aux operators (eq. e:filtering) and energy operators
+  Csr BT;
+  int32_t* bt_src = nullptr;
+  Csr Z;
+  SpgemmPlan zplan;
+  double *dZ = nullptr, *dA = nullptr;
+  uint8_t *keep_p = nullptr, *keep_v = nullptr;
+  Csr Atp, Atv, Mp, Mv;
+  int32_t *mp_ia = nullptr, *mp_ib = nullptr, *mv_ia = nullptr, *mv_ib = nullptr;
+  float *Mpf = nullptr, *Mvf = nullptr;
+  uint8_t* dir = nullptr;
+  double* xp = nullptr;
+  // coarsening and patterns
+  CoarsenArgs ca;
+  CoarsenOut cp;
+  uint8_t* cbar = nullptr;
+  int64_t n_mid = 0;
+  uint8_t* cv = nullptr;
+  VPatternOut vp;
+  // EMIN
+  EminWork ev, ep;
+  double *Wv_def = nullptr, *Wp_def = nullptr;
+  emin_report_t* rep_internal = nullptr;
+  // Galerkin product
+  Csr PvT, T, Ac, X, U, PpT, Bc;
+  int32_t *pvt_src = nullptr, *x_src = nullptr, *ppt_src = nullptr;
+  SpgemmPlan tplan, acplan, uplan, bcplan;
+  // coarse descriptors
+  double* xv_c = nullptr;
+  int32_t* p2v_c = nullptr;
+  int* derr = nullptr;
+  emin_sizes_t sizes{};
+};
+
+namespace {
+
+__global__ void k_fp_probe(const double* x, double* sq, double* rc, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  sq[i] = sqrt(x[i]);
+  rc[i] = 1.0 / x[i];
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+CsrView in_view(const emin_csr_t& c) { return {c.nrows, c.ncols, c.nnz, c.rowptr, c.col, c.val}; }
+
+__global__ void k_gather_coords(const double* xv, const int32_t* idx, int64_t n, int dim,
+                                double* out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int d = 0; d < dim; d++) out[i * dim + d] = xv[(int64_t)idx[i] * dim + d];
+}
+
+__global__ void k_check_idx(const int32_t* idx, int64_t n, int64_t bound, int* derr) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && (idx[i] < 0 || idx[i] >= bound)) atomicOr(derr, DERR_PATTERN);
+}
+
+__global__ void k_cv_from_cbar(const uint8_t* cbar, const int32_t* p2v, int64_t n_p, uint8_t* cv) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_p && cbar[i]) cv[p2v[i]] = 1;
+}
+
+__global__ void k_p2v_coarse(const int32_t* clist_p, const int32_t* p2v, const int32_t* cid_v,
+                             int64_t n_pc, int32_t* out, int* derr) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_pc) return;
+  const int32_t v = cid_v[p2v[clist_p[c]]];
+  if (v < 0) atomicOr(derr, DERR_COLOCATE);
+  out[c] = v;
+}
+
+// X = I_d (x) Pv: pattern and the map from X's entries to Pv's
+__global__ void k_kron_pattern(const int64_t* prp, const int32_t* pcol, int64_t n, int64_t nnz,
+                               int64_t nc, int dim, int64_t* xrp, int32_t* xcol, int32_t* xsrc) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= dim * n) return;
+  const int64_t c = r / n, i = r % n;
+  const int64_t base = c * nnz;
+  xrp[r] = base + prp[i];
+  if (r == dim * n - 1) xrp[r + 1] = base + prp[i + 1];
+  for (int64_t e = prp[i]; e < prp[i + 1]; e++) {
+    xcol[base + e] = (int32_t)(c * nc + pcol[e]);
+    xsrc[base + e] = (int32_t)e;
+  }
+}
+
+void check_derr(emin_pattern_t* h, hipStream_t s) {
+  const int e = d2h(h->derr, s);
+  if (e & DERR_PATTERN) throw Error(EMIN_ERR_PATTERN, "malformed CSR or index array");
+  if (e & DERR_VALUE) throw Error(EMIN_ERR_VALUE, "non-finite input value");
+  if (e & DERR_CAPACITY) throw Error(EMIN_ERR_CAPACITY, "capacity exceeded");
+  if (e & DERR_COLOCATE) throw Error(EMIN_ERR_COLOCATE, "coarse pressure without coarse velocity");
+}
+
+void check_system(const emin_system_t* sys) {
+  if (!sys) throw Error(EMIN_ERR_ARG, "NULL system");
+  if (sys->dim < 2 || sys->dim > 3) throw Error(EMIN_ERR_ARG, "dim must be 2 or 3");
+  const emin_csr_t& A = sys->Ahat;
+  const emin_csr_t& B = sys->Bdiv;
+  if (A.nrows < 0 || A.nnz < 0 || B.nrows < 0 || B.nnz < 0) throw Error(EMIN_ERR_ARG, "negative size");
+  if (A.nrows != A.ncols) throw Error(EMIN_ERR_SHAPE, "Ahat must be square");
+  if (B.ncols != sys->dim * A.nrows) throw Error(EMIN_ERR_SHAPE, "Bdiv must have dim*n_v columns");
+  if ((A.nrows && (!A.rowptr || (A.nnz && (!A.col || !A.val)))) ||
+      (B.nrows && (!B.rowptr || (B.nnz && (!B.col || !B.val)))) ||
+      (A.nrows && !sys->xv) || (B.nrows && !sys->p2v))
+    throw Error(EMIN_ERR_ARG, "NULL array");
+  if (A.nnz >= INT32_MAX || B.nnz >= INT32_MAX) throw Error(EMIN_ERR_CAPACITY, "nnz >= 2^31");
+}
+
+void check_params(const emin_params_t* p) {
+  if (!p) throw Error(EMIN_ERR_ARG, "NULL params");
+  if (p->iters < 0 || p->iters > EMIN_MAX_ITERS) throw Error(EMIN_ERR_ARG, "iters out of range");
+  if (!(p->tau1_v >= 0.0) || !(p->tau1_p >= 0.0) || !(p->tau2_sq >= 0.0))
+    throw Error(EMIN_ERR_ARG, "negative tolerance");
+  if (p->precision != EMIN_PREC_F64 && p->precision != EMIN_PREC_MIXED)
+    throw Error(EMIN_ERR_ARG, "unknown precision");
+}
+
+int pick_lanes(const Csr& M) {
+  const double avg = M.nrows ? (double)M.nnz / (double)M.nrows : 1.0;
+  int g = 4;
+  while (g < 64 && 2 * g < avg) g <<= 1;
+  return g;
+}
+
+void build_pattern(emin_pattern_t* h, const emin_system_t* sys, const emin_params_t* prm,
+                   hipStream_t s) {
+  Arena& ar = h->ar;
+  const int dim = sys->dim;
+  const int64_t nv = sys->Ahat.nrows, np = sys->Bdiv.nrows;
+  h->dim = dim;
+  h->n_v = nv;
+  h->n_p = np;
+  h->nnzA = sys->Ahat.nnz;
+  h->nnzB = sys->Bdiv.nnz;
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  HIP_OK(hipDeviceGetAttribute(&h->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  h->derr = ar.alloc<int>(1);
+  HIP_OK(hipMemsetAsync(h->derr, 0, sizeof(int), s));
+  const CsrView A = in_view(sys->Ahat), B = in_view(sys->Bdiv);
+  const bool vals = (prm->flags & EMIN_FLAG_VALIDATE) != 0;
+  validate_csr(A, vals, h->derr, s);
+  validate_csr(B, vals, h->derr, s);
+  if (np) k_check_idx<<<nblocks(np, 256), 256, 0, s>>>(sys->p2v, np, nv, h->derr);
+  check_derr(h, s);
+
+  // pressure coordinates: those of the co-located velocity nodes
+  h->xp = ar.alloc<double>((size_t)np * dim);
+  if (np) k_gather_coords<<<nblocks(np, 256), 256, 0, s>>>(sys->xv, sys->p2v, np, dim, h->xp);
+
+  // form_aux_block_diagonal: Z = B B^T, filtered; filtered velocity block
+  transpose_pattern(B, h->BT, h->bt_src, s, ar);
+  h->BT.val = ar.alloc<double>(h->BT.nnz);
+  gather_values(B.val, h->bt_src, h->BT.val, h->BT.nnz, s);
+  spgemm_symbolic(B, view(h->BT), h->Z, h->zplan, s, ar, h->derr);
+  spgemm_numeric(B, view(h->BT), h->Z, h->zplan, s);
+  h->dZ = ar.alloc<double>(np);
+  diag_of(view(h->Z), h->dZ, s);
+  h->keep_p = ar.alloc<uint8_t>(h->Z.nnz);
+  filter_symbolic(view(h->Z), prm->tau1_p, h->dZ, h->keep_p, h->Atp, s, ar);
+  symmetrize_symbolic(h->Atp, h->Mp, h->mp_ia, h->mp_ib, s, ar);
+  symmetrize_numeric(h->Atp.val, h->mp_ia, h->mp_ib, h->Mp, s);
+  h->dA = ar.alloc<double>(nv);
+  diag_of(A, h->dA, s);
+  h->keep_v = ar.alloc<uint8_t>(A.nnz);
+  filter_symbolic(A, prm->tau1_v, h->dA, h->keep_v, h->Atv, s, ar);
+  symmetrize_symbolic(h->Atv, h->Mv, h->mv_ia, h->mv_ib, s, ar);
+  symmetrize_numeric(h->Atv.val, h->mv_ia, h->mv_ib, h->Mv, s);
+  h->dir = ar.alloc<uint8_t>(nv);
+  dirichlet_rows(A, h->dir, s);
+
+  // Alg. 3 + extra distance-3 points on the graph of the pressure operator
+  h->ca.grp = h->Mp.rowptr;
+  h->ca.gcol = h->Mp.col;
+  h->ca.n = np;
+  h->ca.dim = dim;
+  h->ca.x = h->xp;
+  coarsen_pressure(h->ca, h->cp, s, ar, h->lds_max);
+
+  // Alg. 4 mid-points, co-located velocities, velocity pattern
+  h->cbar = ar.alloc<uint8_t>(np);
+  const int64_t ncbar = midpoints(h->cp.S, h->ca.st, h->xp, dim, prm->tau2_sq, h->cbar, s, ar,
+                                  h->lds_max);
+  h->n_mid = ncbar - h->cp.n_c;
+  h->cv = ar.alloc<uint8_t>(nv);
+  HIP_OK(hipMemsetAsync(h->cv, 0, nv, s));
+  if (np) k_cv_from_cbar<<<nblocks(np, 256), 256, 0, s>>>(h->cbar, sys->p2v, np, h->cv);
+  velocity_pattern(h->Mv, h->dir, h->cv, h->vp, s, ar, h->lds_max);
+
+  // EMIN workspace
+  const bool mixed = true;  // FP32 copies are allocated so either mode can run
+  h->ev.allocate(nv, h->vp.N.nnz, h->vp.n_c, ar, mixed);
+  h->ep.allocate(np, h->cp.N.nnz, h->cp.n_c, ar, mixed);
+  h->ev.g = pick_lanes(h->Mv);
+  h->ep.g = pick_lanes(h->Mp);
+  h->ev.smax = (int)max_row_len(h->vp.N.rowptr, nv, s, ar);
+  h->ep.smax = (int)max_row_len(h->cp.N.rowptr, np, s, ar);
+  if (h->ev.smax > 64 || h->ep.smax > 64) throw Error(EMIN_ERR_CAPACITY, "pattern row > 64");
+  h->Mvf = ar.alloc<float>(h->Mv.nnz);
+  h->Mpf = ar.alloc<float>(h->Mp.nnz);
+  h->Wv_def = ar.alloc<double>(nv);
+  h->Wp_def = ar.alloc<double>(np);
+  default_modes(h->dir, nv, h->Wv_def, s);
+  default_modes(nullptr, np, h->Wp_def, s);
+  h->rep_internal = ar.alloc<emin_report_t>(1);
+
+  // Galerkin product, symbolic: Ac = Pv^T (Ahat Pv), Bc = Pp^T (Bdiv (I_d (x) Pv))
+  Csr Pv = h->vp.N, Pp = h->cp.N;
+  transpose_pattern(view(Pv), h->PvT, h->pvt_src, s, ar);
+  h->PvT.val = ar.alloc<double>(h->PvT.nnz);
+  spgemm_symbolic(A, view(Pv), h->T, h->tplan, s, ar, h->derr);
+  spgemm_symbolic(view(h->PvT), view(h->T), h->Ac, h->acplan, s, ar, h->derr);
+  h->X.nrows = (int64_t)dim * nv;
+  h->X.ncols = (int64_t)dim * h->vp.n_c;
+  h->X.nnz = (int64_t)dim * Pv.nnz;
+  h->X.rowptr = ar.alloc<int64_t>(h->X.nrows + 1);
+  h->X.col = ar.alloc<int32_t>(h->X.nnz);
+  h->X.val = ar.alloc<double>(h->X.nnz);
+  h->x_src = ar.alloc<int32_t>(h->X.nnz);
+  if (nv)
+    k_kron_pattern<<<nblocks(h->X.nrows, 256), 256, 0, s>>>(Pv.rowptr, Pv.col, nv, Pv.nnz,
+                                                             h->vp.n_c, dim, h->X.rowptr,
+                                                             h->X.col, h->x_src);
+  else
+    HIP_OK(hipMemsetAsync(h->X.rowptr, 0, sizeof(int64_t), s));
+  spgemm_symbolic(B, view(h->X), h->U, h->uplan, s, ar, h->derr);
+  transpose_pattern(view(Pp), h->PpT, h->ppt_src, s, ar);
+  h->PpT.val = ar.alloc<double>(h->PpT.nnz);
+  spgemm_symbolic(view(h->PpT), view(h->U), h->Bc, h->bcplan, s, ar, h->derr);
+
+  // coarse descriptors: coordinates by injection, co-location map
+  h->xv_c = ar.alloc<double>((size_t)h->vp.n_c * dim);
+  if (h->vp.n_c)
+    k_gather_coords<<<nblocks(h->vp.n_c, 256), 256, 0, s>>>(sys->xv, h->vp.clist, h->vp.n_c, dim,
+                                                             h->xv_c);
+  h->p2v_c = ar.alloc<int32_t>(h->cp.n_c);
+  if (h->cp.n_c)
+    k_p2v_coarse<<<nblocks(h->cp.n_c, 256), 256, 0, s>>>(h->cp.clist, sys->p2v, h->vp.cid,
+                                                          h->cp.n_c, h->p2v_c, h->derr);
+  check_derr(h, s);
+  HIP_OK(hipStreamSynchronize(s));
+
+  emin_sizes_t& z = h->sizes;
+  z.n_v = nv;
+  z.n_p = np;
+  z.n_vc = h->vp.n_c;
+  z.n_pc = h->cp.n_c;
+  z.n_cp_alg3 = h->cp.n_alg3;
+  z.n_cp_extra = h->cp.n_c - h->cp.n_alg3;
+  z.n_mid = h->n_mid;
+  z.n_cv_extra = h->vp.n_extra;
+  z.nnz_Pv = h->vp.N.nnz;
+  z.nnz_Pp = h->cp.N.nnz;
+  z.nnz_Mv = h->Mv.nnz;
+  z.nnz_Mp = h->Mp.nnz;
+  z.nnz_Ac = h->Ac.nnz;
+  z.nnz_Bc = h->Bc.nnz;
+  z.device_bytes = (int64_t)ar.bytes();
+}
+
+void check_same_structure(const emin_pattern_t* h, const emin_system_t* sys) {
+  check_system(sys);
+  if (sys->dim != h->dim || sys->Ahat.nrows != h->n_v || sys->Bdiv.nrows != h->n_p ||
+      sys->Ahat.nnz != h->nnzA || sys->Bdiv.nnz != h->nnzB)
+    throw Error(EMIN_ERR_SHAPE, "system structure differs from the pattern's");
+}
+
+void run_setup(emin_pattern_t* h, const emin_system_t* sys, const emin_params_t* prm, double* Pv,
+               double* Pp, hipStream_t s, emin_report_t* rep) {
+  check_same_structure(h, sys);
+  check_params(prm);
+  if ((h->sizes.nnz_Pv && !Pv) || (h->sizes.nnz_Pp && !Pp)) throw Error(EMIN_ERR_ARG, "NULL P");
+  const CsrView A = in_view(sys->Ahat), B = in_view(sys->Bdiv);
+  emin_report_t* r = rep ? rep : h->rep_internal;
+  HIP_OK(hipMemsetAsync(r, 0, sizeof(emin_report_t), s));
+  // energy operators on the stored drop masks
+  gather_values(B.val, h->bt_src, h->BT.val, h->BT.nnz, s);
+  spgemm_numeric(B, view(h->BT), h->Z, h->zplan, s);
+  diag_of(view(h->Z), h->dZ, s);
+  filter_numeric(view(h->Z), h->keep_p, h->dZ, h->Atp, s);
+  symmetrize_numeric(h->Atp.val, h->mp_ia, h->mp_ib, h->Mp, s);
+  diag_of(A, h->dA, s);
+  filter_numeric(A, h->keep_v, h->dA, h->Atv, s);
+  symmetrize_numeric(h->Atv.val, h->mv_ia, h->mv_ib, h->Mv, s);
+  const bool mixed = prm->precision == EMIN_PREC_MIXED;
+  if (mixed) {
+    to_float(h->Mv.val, h->Mvf, h->Mv.nnz, s);
+    to_float(h->Mp.val, h->Mpf, h->Mp.nnz, s);
+  }
+  const bool energy = (prm->flags & EMIN_FLAG_ENERGY) != 0;
+  EminReportPtrs rv{r->energy_v, r->rho_v, r->gamma_v, &r->its_v, &r->status};
+  EminReportPtrs rpp{r->energy_p, r->rho_p, r->gamma_p, &r->its_p, &r->status};
+  const double* Wv = sys->Wv ? sys->Wv : h->Wv_def;
+  const double* Wp = sys->Wp ? sys->Wp : h->Wp_def;
+  run_emin(h->ev, h->Mv, h->Mvf, h->vp.N.rowptr, h->vp.N.col, h->vp.cid, h->vp.clist, Wv, Pv,
+           prm->iters, energy, mixed, rv, s);
+  run_emin(h->ep, h->Mp, h->Mpf, h->cp.N.rowptr, h->cp.N.col, h->cp.cid, h->cp.clist, Wp, Pp,
+           prm->iters, energy, mixed, rpp, s);
+  HIP_OK(hipGetLastError());
+}
+
+void run_rap(emin_pattern_t* h, const emin_system_t* sys, const double* Pv, const double* Pp,
+             double* Acv, double* Bcv, hipStream_t s) {
+  check_same_structure(h, sys);
+  if ((h->sizes.nnz_Pv && !Pv) || (h->sizes.nnz_Pp && !Pp) || (h->Ac.nnz && !Acv) ||
+      (h->Bc.nnz && !Bcv))
+    throw Error(EMIN_ERR_ARG, "NULL value array");
+  const CsrView A = in_view(sys->Ahat), B = in_view(sys->Bdiv);
+  CsrView PvV{h->vp.N.nrows, h->vp.N.ncols, h->vp.N.nnz, h->vp.N.rowptr, h->vp.N.col, Pv};
+  gather_values(Pv, h->pvt_src, h->PvT.val, h->PvT.nnz, s);
+  spgemm_numeric(A, PvV, h->T, h->tplan, s);
+  Csr Ac = h->Ac;
+  Ac.val = Acv;
+  spgemm_numeric(view(h->PvT), view(h->T), Ac, h->acplan, s);
+  gather_values(Pv, h->x_src, h->X.val, h->X.nnz, s);
+  spgemm_numeric(B, view(h->X), h->U, h->uplan, s);
+  gather_values(Pp, h->ppt_src, h->PpT.val, h->PpT.nnz, s);
+  Csr Bc = h->Bc;
+  Bc.val = Bcv;
+  spgemm_numeric(view(h->PpT), view(h->U), Bc, h->bcplan, s);
+  HIP_OK(hipGetLastError());
+}
+
+template <class F>
+emin_status guarded(F&& f) {
+  try {
+    f();
+    return EMIN_OK;
+  } catch (const Error& e) {
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    return EMIN_ERR_OOM;
+  } catch (...) {
+    return EMIN_ERR_DEVICE;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+emin_status emin_pattern(const emin_system_t* sys, const emin_params_t* prm, void* stream,
+                         emin_pattern_t** out) {
+  if (!out) return EMIN_ERR_ARG;
+  *out = nullptr;
+  emin_pattern_t* h = nullptr;
+  emin_status st = guarded([&] {
+    check_system(sys);
+    check_params(prm);
+    h = new emin_pattern_s();
+    build_pattern(h, sys, prm, as_stream(stream));
+  });
+  if (st != EMIN_OK) {
+    if (h) {
+      (void)hipStreamSynchronize(as_stream(stream));
+      delete h;
+    }
+    return st;
+  }
+  *out = h;
+  return EMIN_OK;
+}
+
+emin_status emin_pattern_info(const emin_pattern_t* h, emin_sizes_t* out) {
+  if (!h || !out) return EMIN_ERR_ARG;
+  *out = h->sizes;
+  return EMIN_OK;
+}
+
+emin_status emin_pattern_view(const emin_pattern_t* h, int32_t what, emin_view_t* out) {
+  if (!h || !out) return EMIN_ERR_ARG;
+  std::memset(out, 0, sizeof(*out));
+  auto csr = [&](const Csr& c, bool with_val) {
+    out->n = c.nrows;
+    out->ncols = c.ncols;
+    out->nnz = c.nnz;
+    out->rowptr = c.rowptr;
+    out->col = c.col;
+    out->val = with_val ? c.val : nullptr;
+  };
+  auto arr = [&](int64_t n, const void* p) {
+    out->n = n;
+    out->data = p;
+  };
+  switch (what) {
+    case EMIN_VIEW_PV: csr(h->vp.N, false); break;
+    case EMIN_VIEW_PP: csr(h->cp.N, false); break;
+    case EMIN_VIEW_AC: csr(h->Ac, false); break;
+    case EMIN_VIEW_BC: csr(h->Bc, false); break;
+    case EMIN_VIEW_MV: csr(h->Mv, true); break;
+    case EMIN_VIEW_MP: csr(h->Mp, true); break;
+    case EMIN_VIEW_S: csr(h->cp.S, false); break;
+    case EMIN_VIEW_ORDER: arr(h->cp.n_c, h->ca.order); break;
+    case EMIN_VIEW_CP: arr(h->cp.n_c, h->cp.clist); break;
+    case EMIN_VIEW_CBAR: arr(h->n_p, h->cbar); break;
+    case EMIN_VIEW_CV: arr(h->vp.n_c, h->vp.clist); break;
+    case EMIN_VIEW_XVC: arr(h->vp.n_c * h->dim, h->xv_c); break;
+    case EMIN_VIEW_P2VC: arr(h->cp.n_c, h->p2v_c); break;
+    case EMIN_VIEW_KEEPV: arr(h->nnzA, h->keep_v); break;
+    case EMIN_VIEW_KEEPP: arr(h->Z.nnz, h->keep_p); break;
+    case EMIN_VIEW_DIR: arr(h->n_v, h->dir); break;
+    default: return EMIN_ERR_ARG;
+  }
+  return EMIN_OK;
+}
+
+emin_status emin_setup(emin_pattern_t* h, const emin_system_t* sys, const emin_params_t* prm,
+                       double* Pv_vals, double* Pp_vals, void* stream, emin_report_t* report) {
+  if (!h) return EMIN_ERR_ARG;
+  return guarded([&] { run_setup(h, sys, prm, Pv_vals, Pp_vals, as_stream(stream), report); });
+}
+
+emin_status emin_rap(emin_pattern_t* h, const emin_system_t* sys, const double* Pv_vals,
+                     const double* Pp_vals, double* Ac_vals, double* Bc_vals, void* stream) {
+  if (!h) return EMIN_ERR_ARG;
+  return guarded([&] { run_rap(h, sys, Pv_vals, Pp_vals, Ac_vals, Bc_vals, as_stream(stream)); });
+}
+
+emin_status emin_sync_report(const emin_report_t* report, void* stream, emin_report_t* host) {
+  if (!report || !host) return EMIN_ERR_ARG;
+  return guarded([&] {
+    HIP_OK(hipMemcpyAsync(host, report, sizeof(emin_report_t), hipMemcpyDeviceToHost,
+                          as_stream(stream)));
+    HIP_OK(hipStreamSynchronize(as_stream(stream)));
+    if (host->status != EMIN_OK) throw Error((emin_status)host->status, "numeric phase");
+  });
+}
+
+emin_status emin_memcpy_d2h(void* dst, const void* src, size_t bytes, void* stream) {
+  if (bytes == 0) return EMIN_OK;
+  if (!dst || !src) return EMIN_ERR_ARG;
+  return guarded([&] {
+    HIP_OK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, as_stream(stream)));
+    HIP_OK(hipStreamSynchronize(as_stream(stream)));
+  });
+}
+
+void emin_pattern_destroy(emin_pattern_t* h) {
+  if (!h) return;
+  (void)hipDeviceSynchronize();
+  delete h;
+}
+
+const char* emin_status_string(emin_status s) {
+  switch (s) {
+    case EMIN_OK: return "OK";
+    case EMIN_ERR_ARG: return "ERR_ARG";
+    case EMIN_ERR_SHAPE: return "ERR_SHAPE";
+    case EMIN_ERR_PATTERN: return "ERR_PATTERN";
+    case EMIN_ERR_VALUE: return "ERR_VALUE";
+    case EMIN_ERR_INFEASIBLE: return "ERR_INFEASIBLE";
+    case EMIN_ERR_BREAKDOWN: return "ERR_BREAKDOWN";
+    case EMIN_ERR_BUDGET: return "ERR_BUDGET";
+    case EMIN_ERR_DEVICE: return "ERR_DEVICE";
+    case EMIN_ERR_OOM: return "ERR_OOM";
+    case EMIN_ERR_CAPACITY: return "ERR_CAPACITY";
+    case EMIN_ERR_COLOCATE: return "ERR_COLOCATE";
+  }
+  return "UNKNOWN";
+}
+
+const char* emin_version(void) { return "emin-mi355x 0.1.0 (gfx950)"; }
+
+emin_status emin_fp_probe(const double* x, double* out_sqrt, double* out_rcp, int64_t n,
+                          void* stream) {
+  if (n < 0 || (n && (!x || !out_sqrt || !out_rcp))) return EMIN_ERR_ARG;
+  return guarded([&] {
+    if (n) k_fp_probe<<<nblocks(n, 256), 256, 0, as_stream(stream)>>>(x, out_sqrt, out_rcp, n);
+    HIP_OK(hipGetLastError());
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,459 @@
+// Alg. 3 (find_coarse_pressures) with update_heuristics and
+// find_extra_dist3_Cpoints, as persistent single-workgroup kernels.
+//
+// Alg. 3 is a sequential greedy: every step picks the candidate with the
+// smallest heuristic h1, and that choice changes the candidates and keys
+// within graph distance 4.  One workgroup runs the loop; each step's BFS,
+// state update and argmin are spread over its 1024 lanes.  The argmin is
+// kept in LDS as per-block minima over fixed blocks of vertices, and only
+// blocks touched by the step are recomputed.  The floating-point work that
+// decides integers (distances, 1/d sums, h1 = cnt/rs, the extra-point tests)
+// uses the same operations in the same order as the definition, with
+// contraction disabled, so the result is bit-identical to it.
+#include "coarsen.h"
+
+namespace emin {
+
+constexpr int A3_BS = 1024;
+constexpr int A3_WAVES = A3_BS / 64;
+
+__device__ __forceinline__ double euclid(const double* x, int dim, int64_t a, int64_t b) {
+  double s = 0.0;
+  for (int d = 0; d < dim; d++) {
+    const double t = x[a * dim + d] - x[b * dim + d];
+    s = s + t * t;
+  }
+  return sqrt(s);
+}
+
+__device__ __forceinline__ bool lex_less(double ka, int32_t ia, double kb, int32_t ib) {
+  return ka < kb || (ka == kb && ia < ib);
+}
+
+// Breadth-first search of the whole workgroup from src to `depth`.  Visited
+// vertices carry the stamp in vis[] (stamps increase, so no clearing).  The
+// ball is listed level by level; lvl_end[L] ends level L.
+__device__ int wg_bfs(const CoarsenArgs& D, int32_t src, int depth, int32_t stamp, int32_t* ball,
+                      int* lvl_end, int* nb_sh, int* err_sh) {
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    ball[0] = src;
+    atomicMax(&D.vis[src], stamp);
+    *nb_sh = 1;
+    lvl_end[0] = 1;
+  }
+  __syncthreads();
+  int ls = 0, le = 1;
+  const int per = A3_BS / D.deg_cap;
+  for (int L = 0; L < depth; L++) {
+    for (int base = ls; base < le; base += per) {
+      const int f = base + tid / D.deg_cap;
+      const int slot = tid % D.deg_cap;
+      if (f < le) {
+        const int32_t v = ball[f];
+        const int64_t b = D.grp[v + 1];
+        for (int64_t e = D.grp[v] + slot; e < b; e += D.deg_cap) {
+          const int32_t w = D.gcol[e];
+          if (w == v) continue;
+          if (atomicMax(&D.vis[w], stamp) < stamp) {
+            const int p = atomicAdd(nb_sh, 1);
+            if (p < D.ballcap) ball[p] = w;
+            else atomicOr(err_sh, DERR_CAPACITY);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    ls = le;
+    le = min(*nb_sh, D.ballcap);
+    if (tid == 0) lvl_end[L + 1] = le;
+    __syncthreads();
+  }
+  return le;
+}
+
+__device__ __forceinline__ int level_of(int t, const int* lvl_end) {
+  int d = 0;
+  while (t >= lvl_end[d]) d++;
+  return d;
+}
+
+__device__ __forceinline__ void s_append(const CoarsenArgs& D, int32_t v, int32_t c, int d,
+                                         int* err_sh) {
+  const int sl = D.s_cnt[v];
+  if (sl < D.scap) {
+    D.s_c[(int64_t)v * D.scap + sl] = c;
+    D.s_d[(int64_t)v * D.scap + sl] = (uint8_t)d;
+    D.s_cnt[v] = sl + 1;
+  } else {
+    atomicOr(err_sh, DERR_CAPACITY);
+  }
+}
+
+__device__ __forceinline__ void mark_dirty(int b, uint32_t* dbits, int32_t* dlist, int dcap,
+                                           int* dn, int* dall) {
+  const uint32_t bit = 1u << (b & 31);
+  if ((atomicOr(&dbits[b >> 5], bit) & bit) == 0) {
+    const int p = atomicAdd(dn, 1);
+    if (p < dcap) dlist[p] = b;
+    else *dall = 1;
+  }
+}
+
+__global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
+  extern __shared__ unsigned char lds_raw[];
+  int32_t* ball = reinterpret_cast<int32_t*>(lds_raw);
+  double* bkey = reinterpret_cast<double*>(ball + D.ballcap);
+  int32_t* bidx = reinterpret_cast<int32_t*>(bkey + D.nblk);
+  uint32_t* dbits = reinterpret_cast<uint32_t*>(bidx + D.nblk);
+  int32_t* dlist = reinterpret_cast<int32_t*>(dbits + ((D.nblk + 31) / 32));
+  __shared__ int lvl_end[8];
+  __shared__ int nb_sh, err_sh, dn_sh, dall_sh, nc_sh, stamp_sh, cursor_sh, found_sh;
+  __shared__ int32_t k_sh;
+  __shared__ double wkey[A3_WAVES];
+  __shared__ int32_t widx[A3_WAVES];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const double INF = __builtin_inf();
+  const int64_t n = D.n;
+
+  for (int b = tid; b < D.nblk; b += A3_BS) { bkey[b] = INF; bidx[b] = INT32_MAX; }
+  for (int b = tid; b < (D.nblk + 31) / 32; b += A3_BS) dbits[b] = 0u;
+  if (tid == 0) {
+    nb_sh = 0; err_sh = 0; dn_sh = 0; dall_sh = 0; nc_sh = 0; stamp_sh = 0; cursor_sh = 0;
+    k_sh = n > 0 ? 0 : -1;   // Alg. 3's "arbitrary vertex": vertex 0
+  }
+  __syncthreads();
+
+  while (true) {
+    const int32_t k = k_sh;
+    if (k < 0) break;
+    const int32_t stamp = stamp_sh;
+    const int nb = wg_bfs(D, k, 4, stamp, ball, lvl_end, &nb_sh, &err_sh);
+    // S_j += {k} for dist <= 3; C/F/Cand update; update_heuristics
+    for (int t = tid; t < nb; t += A3_BS) {
+      const int32_t v = ball[t];
+      const int d = level_of(t, lvl_end);
+      if (d <= 3) s_append(D, v, k, d, &err_sh);
+      if (d >= 1) {
+        const uint8_t s = D.st[v];
+        if (d <= 3 && (s == ST_U || s == ST_CAND)) D.st[v] = ST_F;
+        if (d == 4 && s == ST_U) D.st[v] = ST_CAND;
+        D.cnt[v] += 1;
+        D.rs[v] = D.rs[v] + 1.0 / euclid(D.x, D.dim, v, k);
+        mark_dirty(v / D.vb, dbits, dlist, D.dcap, &dn_sh, &dall_sh);
+      }
+    }
+    if (tid == 0) {
+      D.st[k] = ST_C;
+      D.order[nc_sh] = k;
+      nc_sh++;
+      stamp_sh = stamp + 1;
+      mark_dirty(k / D.vb, dbits, dlist, D.dcap, &dn_sh, &dall_sh);
+    }
+    __syncthreads();
+    // refresh the minima of the touched blocks
+    const bool all = dall_sh != 0;
+    const int todo = all ? D.nblk : dn_sh;
+    for (int t = wave; t < todo; t += A3_WAVES) {
+      const int b = all ? t : dlist[t];
+      double key = INF;
+      int32_t idx = INT32_MAX;
+      for (int u = lane; u < D.vb; u += 64) {
+        const int64_t v = (int64_t)b * D.vb + u;
+        if (v < n && D.st[v] == ST_CAND) {
+          const double h1 = (double)D.cnt[v] / D.rs[v];
+          if (lex_less(h1, (int32_t)v, key, idx)) { key = h1; idx = (int32_t)v; }
+        }
+      }
+      wave_argmin(key, idx);
+      if (lane == 0) { bkey[b] = key; bidx[b] = idx; }
+    }
+    __syncthreads();
+    for (int b = tid; b < (D.nblk + 31) / 32; b += A3_BS) dbits[b] = 0u;
+    if (tid == 0) { dn_sh = 0; dall_sh = 0; }
+    // next k = argmin over Cand of (h1, index)
+    double key = INF;
+    int32_t idx = INT32_MAX;
+    for (int b = tid; b < D.nblk; b += A3_BS)
+      if (lex_less(bkey[b], bidx[b], key, idx)) { key = bkey[b]; idx = bidx[b]; }
+    wave_argmin(key, idx);
+    if (lane == 0) { wkey[wave] = key; widx[wave] = idx; }
+    __syncthreads();
+    if (tid == 0) {
+      double kk = INF;
+      int32_t ii = INT32_MAX;
+      for (int w = 0; w < A3_WAVES; w++)
+        if (lex_less(wkey[w], widx[w], kk, ii)) { kk = wkey[w]; ii = widx[w]; }
+      k_sh = (ii == INT32_MAX) ? -2 : ii;
+      found_sh = INT32_MAX;
+    }
+    __syncthreads();
+    if (k_sh == -2) {
+      // Cand is empty: the smallest-index unmarked vertex (the cursor only
+      // moves forward: marks are permanent)
+      for (int64_t base = cursor_sh; base < n; base += A3_BS) {
+        const int64_t v = base + tid;
+        if (v < n && D.st[v] == ST_U) atomicMin(&found_sh, (int)v);
+        __syncthreads();
+        const int f = found_sh;
+        __syncthreads();
+        if (f != INT32_MAX) break;
+      }
+      if (tid == 0) {
+        k_sh = found_sh == INT32_MAX ? -1 : found_sh;
+        if (found_sh != INT32_MAX) cursor_sh = found_sh;
+      }
+      __syncthreads();
+    }
+    if (err_sh) break;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    D.meta[0] = nc_sh;
+    D.meta[1] = nc_sh;
+    D.meta[2] |= err_sh;
+    D.meta[3] = stamp_sh;
+  }
+}
+
+// mean Euclidean length of each vertex's graph edges
+__global__ void k_ebar(CoarsenArgs D, double* ebar) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= D.n) return;
+  double s = 0.0;
+  int64_t deg = 0;
+  for (int64_t e = D.grp[j]; e < D.grp[j + 1]; e++) {
+    const int32_t w = D.gcol[e];
+    if (w == j) continue;
+    s = s + euclid(D.x, D.dim, j, w);
+    deg++;
+  }
+  ebar[j] = deg ? s / (double)deg : 0.0;
+}
+
+// find_extra_dist3_Cpoints predicate of pass 1 / pass 2 with the current S
+__device__ bool extra_pred(const CoarsenArgs& D, const double* ebar, int pass, int64_t j) {
+  if (D.st[j] != ST_F) return false;
+  const int sc = D.s_cnt[j];
+  const int32_t* c = D.s_c + j * D.scap;
+  const uint8_t* dd = D.s_d + j * D.scap;
+  const double eb = ebar[j];
+  if (pass == 1) {
+    if (sc != 1) return false;
+    return dd[0] == 3 && euclid(D.x, D.dim, j, c[0]) > 2.5 * eb;
+  }
+  if (sc != 2 || dd[0] != 3 || dd[1] != 3) return false;
+  const int64_t a = c[0], b = c[1];
+  const double ea = euclid(D.x, D.dim, j, a), ebb = euclid(D.x, D.dim, j, b);
+  if (!(0.5 * (ea + ebb) > 2.5 * eb)) return false;
+  const int dim = D.dim;
+  const double* x = D.x;
+  double num = 0.0, den = 0.0;
+  for (int d = 0; d < dim; d++) {
+    const double ab = x[b * dim + d] - x[a * dim + d];
+    const double aj = x[j * dim + d] - x[a * dim + d];
+    num = num + aj * ab;
+    den = den + ab * ab;
+  }
+  double t = den > 0.0 ? num / den : 0.0;
+  if (t < 0.0) t = 0.0;
+  if (t > 1.0) t = 1.0;
+  double s = 0.0;
+  for (int d = 0; d < dim; d++) {
+    const double ab = x[b * dim + d] - x[a * dim + d];
+    const double q = x[a * dim + d] + t * ab;
+    const double r = x[j * dim + d] - q;
+    s = s + r * r;
+  }
+  return sqrt(s) > 1.0 * eb;
+}
+
+// Both passes in ascending order.  The state changes only when a vertex is
+// converted, so the next conversion is the smallest vertex at or after the
+// cursor whose predicate holds now; the workgroup finds it 1024 at a time.
+__global__ __launch_bounds__(A3_BS) void k_extras(CoarsenArgs D, const double* ebar) {
+  extern __shared__ unsigned char lds_raw[];
+  int32_t* ball = reinterpret_cast<int32_t*>(lds_raw);
+  __shared__ int lvl_end[8];
+  __shared__ int nb_sh, err_sh, found_sh, nc_sh, stamp_sh;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    err_sh = 0;
+    nc_sh = D.meta[0];
+    stamp_sh = D.meta[3];
+  }
+  __syncthreads();
+  for (int pass = 1; pass <= 2; pass++) {
+    int64_t cursor = 0;
+    while (true) {
+      if (tid == 0) found_sh = INT32_MAX;
+      __syncthreads();
+      for (int64_t base = cursor; base < D.n; base += A3_BS) {
+        const int64_t v = base + tid;
+        if (v < D.n && extra_pred(D, ebar, pass, v)) atomicMin(&found_sh, (int)v);
+        __syncthreads();
+        const int f = found_sh;
+        __syncthreads();
+        if (f != INT32_MAX) break;
+      }
+      const int j = found_sh;
+      if (j == INT32_MAX) break;
+      if (tid == 0) {
+        D.st[j] = ST_C;
+        D.order[nc_sh] = j;
+        nc_sh++;
+      }
+      const int32_t stamp = stamp_sh;
+      const int nb = wg_bfs(D, j, 3, stamp, ball, lvl_end, &nb_sh, &err_sh);
+      for (int t = tid; t < nb; t += A3_BS) s_append(D, ball[t], j, level_of(t, lvl_end), &err_sh);
+      if (tid == 0) stamp_sh = stamp + 1;
+      __syncthreads();
+      cursor = (int64_t)j + 1;
+      if (err_sh) break;
+    }
+    __syncthreads();
+    if (err_sh) break;
+  }
+  if (tid == 0) {
+    D.meta[0] = nc_sh;
+    D.meta[2] |= err_sh;
+    D.meta[3] = stamp_sh;
+  }
+}
+
+// sort every S list by fine index (distances follow)
+__global__ void k_sort_s(CoarsenArgs D) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D.n) return;
+  int32_t* c = D.s_c + i * D.scap;
+  uint8_t* d = D.s_d + i * D.scap;
+  const int m = D.s_cnt[i];
+  for (int p = 1; p < m; p++) {
+    const int32_t cv = c[p];
+    const uint8_t dv = d[p];
+    int q = p;
+    while (q > 0 && c[q - 1] > cv) {
+      c[q] = c[q - 1];
+      d[q] = d[q - 1];
+      q--;
+    }
+    c[q] = cv;
+    d[q] = dv;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// patterns from the C/F split
+// ---------------------------------------------------------------------------
+__global__ void k_flags_c(const uint8_t* st, int64_t n, int64_t* out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = st[i] == ST_C;
+}
+
+__global__ void k_compact(const int64_t* incl, const uint8_t* st, int64_t n, int32_t* list,
+                          int32_t* cid) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const bool c = st[i] == ST_C;
+  const int32_t id = c ? (int32_t)(incl[i] - 1) : -1;
+  cid[i] = id;
+  if (c) list[id] = (int32_t)i;
+}
+
+__global__ void k_p_counts(const uint8_t* st, const int32_t* s_cnt, int64_t n, int64_t* nrp,
+                           int64_t* srp) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  nrp[i + 1] = st[i] == ST_C ? 1 : s_cnt[i];
+  srp[i + 1] = s_cnt[i];
+}
+
+__global__ void k_p_fill(CoarsenArgs D, const int32_t* cid, const int64_t* nrp, int32_t* ncol,
+                         const int64_t* srp, int32_t* scol, uint8_t* sdist) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D.n) return;
+  const int m = D.s_cnt[i];
+  for (int t = 0; t < m; t++) {
+    scol[srp[i] + t] = D.s_c[i * D.scap + t];
+    sdist[srp[i] + t] = D.s_d[i * D.scap + t];
+  }
+  if (D.st[i] == ST_C) {
+    ncol[nrp[i]] = cid[i];
+  } else {
+    for (int t = 0; t < m; t++) ncol[nrp[i] + t] = cid[D.s_c[i * D.scap + t]];
+  }
+}
+
+void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar, int lds_max) {
+  const int64_t n = D.n;
+  D.st = ar.alloc<uint8_t>(n);
+  D.cnt = ar.alloc<int32_t>(n);
+  D.rs = ar.alloc<double>(n);
+  D.vis = ar.alloc<int32_t>(n);
+  D.s_cnt = ar.alloc<int32_t>(n);
+  D.s_c = ar.alloc<int32_t>((size_t)n * D.scap);
+  D.s_d = ar.alloc<uint8_t>((size_t)n * D.scap);
+  D.order = ar.alloc<int32_t>(n);
+  D.meta = ar.alloc<int32_t>(4);
+  HIP_OK(hipMemsetAsync(D.st, 0, n, s));
+  HIP_OK(hipMemsetAsync(D.cnt, 0, sizeof(int32_t) * n, s));
+  HIP_OK(hipMemsetAsync(D.rs, 0, sizeof(double) * n, s));
+  HIP_OK(hipMemsetAsync(D.vis, 0xFF, sizeof(int32_t) * n, s));
+  HIP_OK(hipMemsetAsync(D.s_cnt, 0, sizeof(int32_t) * n, s));
+  HIP_OK(hipMemsetAsync(D.meta, 0, sizeof(int32_t) * 4, s));
+  int64_t maxdeg = max_row_len(D.grp, n, s, ar);
+  D.deg_cap = 1;
+  while (D.deg_cap < maxdeg && D.deg_cap < A3_BS) D.deg_cap <<= 1;
+  // LDS layout: ball | block keys | block idx | dirty bits | dirty list
+  D.ballcap = 4096;
+  D.dcap = 1024;
+  const int fixed = D.ballcap * 4 + D.dcap * 4 + 64;
+  int max_blocks = (lds_max - fixed) / 13;
+  if (max_blocks < 64) throw Error(EMIN_ERR_CAPACITY, "alg3: LDS too small");
+  D.vb = 64;
+  while ((n + D.vb - 1) / D.vb > max_blocks) D.vb <<= 1;
+  D.nblk = (int)((n + D.vb - 1) / D.vb);
+  if (D.nblk < 1) D.nblk = 1;
+  size_t lds = (size_t)D.ballcap * 4 + (size_t)D.nblk * 12 + (size_t)((D.nblk + 31) / 32) * 4 +
+               (size_t)D.dcap * 4;
+  HIP_OK(hipFuncSetAttribute((const void*)k_alg3, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds));
+  k_alg3<<<1, A3_BS, lds, s>>>(D);
+  HIP_OK(hipGetLastError());
+  double* ebar = ar.alloc<double>(n);
+  if (n) k_ebar<<<nblocks(n, 256), 256, 0, s>>>(D, ebar);
+  size_t lds2 = (size_t)D.ballcap * 4;
+  k_extras<<<1, A3_BS, lds2, s>>>(D, ebar);
+  HIP_OK(hipGetLastError());
+  if (n) k_sort_s<<<nblocks(n, 256), 256, 0, s>>>(D);
+  int32_t meta[4];
+  HIP_OK(hipMemcpyAsync(meta, D.meta, sizeof(meta), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  if (meta[2] & DERR_CAPACITY) throw Error(EMIN_ERR_CAPACITY, "alg3: S set or BFS ball capacity");
+  out.n_c = meta[0];
+  out.n_alg3 = meta[1];
+  // coarse numbering (ascending fine index), C list, S CSR, N^(p)
+  int64_t* incl = ar.alloc<int64_t>(n + 1);
+  if (n) k_flags_c<<<nblocks(n, 256), 256, 0, s>>>(D.st, n, incl);
+  scan_inclusive(incl, n, s, ar);
+  out.cid = ar.alloc<int32_t>(n);
+  out.clist = ar.alloc<int32_t>(out.n_c);
+  if (n) k_compact<<<nblocks(n, 256), 256, 0, s>>>(incl, D.st, n, out.clist, out.cid);
+  out.N.nrows = n;
+  out.N.ncols = out.n_c;
+  out.N.rowptr = ar.alloc<int64_t>(n + 1);
+  out.S.nrows = n;
+  out.S.ncols = n;
+  out.S.rowptr = ar.alloc<int64_t>(n + 1);
+  if (n) k_p_counts<<<nblocks(n, 256), 256, 0, s>>>(D.st, D.s_cnt, n, out.N.rowptr, out.S.rowptr);
+  out.N.nnz = rowptr_from_counts(out.N.rowptr, n, s, ar);
+  out.S.nnz = rowptr_from_counts(out.S.rowptr, n, s, ar);
+  out.N.col = ar.alloc<int32_t>(out.N.nnz);
+  out.S.col = ar.alloc<int32_t>(out.S.nnz);
+  out.sdist = ar.alloc<uint8_t>(out.S.nnz);
+  if (n)
+    k_p_fill<<<nblocks(n, 256), 256, 0, s>>>(D, out.cid, out.N.rowptr, out.N.col, out.S.rowptr,
+                                              out.S.col, out.sdist);
+}
+
+}  // namespace emin

@@ -1,0 +1,156 @@
+// Shared device/host infrastructure of the EMIN-AMG HIP library (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/emin.h"
+
+namespace emin {
+
+// ---------------------------------------------------------------------------
+// errors: host code throws, the C-ABI layer converts to emin_status
+// ---------------------------------------------------------------------------
+struct Error : std::runtime_error {
+  emin_status code;
+  Error(emin_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIP_OK(x)                                                              \
+  do {                                                                         \
+    hipError_t e_ = (x);                                                       \
+    if (e_ != hipSuccess)                                                      \
+      throw ::emin::Error(EMIN_ERR_DEVICE, std::string(#x) + ": " +            \
+                                               hipGetErrorString(e_));         \
+  } while (0)
+
+// device-side error flags (bit per kind), read back by host syncs
+enum DevErr : int {
+  DERR_CAPACITY = 1,   // a fixed-capacity per-row buffer overflowed
+  DERR_PATTERN = 2,    // malformed CSR (unsorted / duplicate / out of range)
+  DERR_VALUE = 4,      // NaN / Inf input
+  DERR_COLOCATE = 8,   // a coarse pressure without a co-located coarse velocity
+};
+
+// ---------------------------------------------------------------------------
+// device memory owned by a handle
+// ---------------------------------------------------------------------------
+class Arena {
+ public:
+  Arena() = default;
+  Arena(const Arena&) = delete;
+  Arena& operator=(const Arena&) = delete;
+  ~Arena() { release(); }
+  template <class T>
+  T* alloc(size_t n) {
+    void* p = nullptr;
+    size_t b = (n ? n : 1) * sizeof(T);
+    b = (b + 255) & ~size_t(255);
+    if (hipMalloc(&p, b) != hipSuccess) throw Error(EMIN_ERR_OOM, "hipMalloc failed");
+    ptrs_.push_back(p);
+    bytes_ += b;
+    return static_cast<T*>(p);
+  }
+  void release() {
+    for (void* p : ptrs_) (void)hipFree(p);
+    ptrs_.clear();
+    bytes_ = 0;
+  }
+  size_t bytes() const { return bytes_; }
+
+ private:
+  std::vector<void*> ptrs_;
+  size_t bytes_ = 0;
+};
+
+// a CSR matrix in device memory (rowptr int64, col int32, val double/float)
+struct Csr {
+  int64_t nrows = 0, ncols = 0, nnz = 0;
+  int64_t* rowptr = nullptr;
+  int32_t* col = nullptr;
+  double* val = nullptr;
+};
+
+struct CsrView {  // read-only borrowed input
+  int64_t nrows = 0, ncols = 0, nnz = 0;
+  const int64_t* rowptr = nullptr;
+  const int32_t* col = nullptr;
+  const double* val = nullptr;
+};
+
+inline CsrView view(const Csr& a) { return {a.nrows, a.ncols, a.nnz, a.rowptr, a.col, a.val}; }
+
+inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+template <class T>
+inline T d2h(const T* p, hipStream_t s) {
+  T v;
+  HIP_OK(hipMemcpyAsync(&v, p, sizeof(T), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// sparse building blocks (sparse.hip)
+// ---------------------------------------------------------------------------
+// longest row of a CSR (synchronises the stream)
+int64_t max_row_len(const int64_t* rp, int64_t n, hipStream_t s, Arena& ar);
+// in-place inclusive scan of a[0..n)
+void scan_inclusive(int64_t* a, int64_t n, hipStream_t s, Arena& ar);
+// counts written to rowptr[1..n]; rowptr[0] = 0 set here; returns total
+int64_t rowptr_from_counts(int64_t* rowptr, int64_t n, hipStream_t s, Arena& ar);
+
+// transpose: builds the pattern of A^T and src[p] = entry of A feeding At[p]
+// (rows of At in ascending original-row order)
+void transpose_pattern(const CsrView& A, Csr& At, int32_t*& src, hipStream_t s, Arena& ar);
+void gather_values(const double* in, const int32_t* src, double* out, int64_t n, hipStream_t s);
+
+// C = A*B: symbolic (pattern) once, numeric any number of times.  For every
+// (i,j), c_ij accumulates a_ik*b_kj over k in ascending order of A's row,
+// each product and sum rounded separately (bit-reproducible).
+struct SpgemmPlan {
+  int64_t max_row = 0;  // longest output row
+  int g_num = 16;       // lanes per row in the numeric kernel
+};
+void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& plan,
+                     hipStream_t s, Arena& ar, int* derr);
+void spgemm_numeric(const CsrView& A, const CsrView& B, const Csr& C, const SpgemmPlan& plan,
+                    hipStream_t s);
+
+// filter of eq. (e:filtering) with lumping; keep mask per entry of A
+void diag_of(const CsrView& A, double* d, hipStream_t s);
+void filter_symbolic(const CsrView& A, double tau1, const double* d, uint8_t* keep, Csr& At,
+                     hipStream_t s, Arena& ar);
+void filter_numeric(const CsrView& A, const uint8_t* keep, const double* d, const Csr& At,
+                    hipStream_t s);
+// M = (A + A^T)/2 on the union pattern; ia/ib = entry of A / of A (transposed
+// position) feeding each entry of M, -1 if absent
+void symmetrize_symbolic(const Csr& A, Csr& M, int32_t*& ia, int32_t*& ib, hipStream_t s,
+                         Arena& ar);
+void symmetrize_numeric(const double* aval, const int32_t* ia, const int32_t* ib, Csr& M,
+                        hipStream_t s);
+void dirichlet_rows(const CsrView& A, uint8_t* dir, hipStream_t s);
+void validate_csr(const CsrView& A, bool values, int* derr, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double shfl_xor_d(double v, int m) {
+  return __shfl_xor(v, m, 64);
+}
+
+// lexicographic (key, index) minimum across a full 64-lane wave
+__device__ __forceinline__ void wave_argmin(double& k, int32_t& i) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    double ok = __shfl_xor(k, m, 64);
+    int32_t oi = __shfl_xor(i, m, 64);
+    if (ok < k || (ok == k && oi < i)) { k = ok; i = oi; }
+  }
+}
+
+}  // namespace emin

@@ -1,0 +1,385 @@
+// sec. 4.3, eq. (min_problem): EMIN-AMG prolongator values by constrained CG
+// on trace(P^T M P) over matrices with P's fixed pattern that keep P W_c = W.
+//
+// Hot kernel: the masked product Q = mask_N(M Z).  G lanes own one row i:
+// they split M's row i, and for each k merge the short sorted row k of the
+// pattern against row i's columns (held in registers), accumulating per
+// output slot; the G partial sums are combined by a fixed xor-butterfly, so
+// results are deterministic.  Projection and CG updates are row-local; every
+// reduction is a fixed two-level tree (block partials, then one block), and
+// the CG scalars (rho, gamma, alpha, beta, energy) never leave the device.
+#include "emin_cg.h"
+
+namespace emin {
+
+constexpr int RB = 256;  // block size of row-wise kernels
+
+__device__ __forceinline__ double block_sum(double v, double* lds) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  __syncthreads();
+  if (lane == 0) lds[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < (int)(blockDim.x >> 6); k++) t += lds[k];
+  return t;  // valid on thread 0
+}
+
+// W_c = W restricted to the C points; Gram g_i = sum over the row's pattern
+// of W_c^2; P0 = W_i W_c / g_i on F rows (1/|N_i| for a 0/1 mode), 1 on C rows
+__global__ void k_emin_init(const int64_t* rp, const int32_t* col, int64_t n, const int32_t* cid,
+                            const double* W, const double* Wc, double* G, double* P,
+                            int32_t* status) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t a = rp[i], b = rp[i + 1];
+  double g = 0.0;
+  for (int64_t s = a; s < b; s++) g = g + Wc[col[s]] * Wc[col[s]];
+  G[i] = g;
+  if (cid[i] >= 0) {
+    for (int64_t s = a; s < b; s++) P[s] = 1.0;
+    return;
+  }
+  if (g > 0.0) {
+    for (int64_t s = a; s < b; s++) P[s] = (W[i] * Wc[col[s]]) / g;
+  } else {
+    for (int64_t s = a; s < b; s++) P[s] = 0.0;
+    if (W[i] != 0.0) atomicMax(status, (int32_t)EMIN_ERR_INFEASIBLE);
+  }
+}
+
+__global__ void k_gather_modes(const double* W, const int32_t* clist, int64_t nc, double* Wc) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < nc) Wc[c] = W[clist[c]];
+}
+
+__global__ void k_default_modes(const uint8_t* dir, int64_t n, double* W) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) W[i] = dir ? (dir[i] ? 0.0 : 1.0) : 1.0;
+}
+
+// Y = mask_N(M X); optional dot partial of <D, Y> per block
+template <int G, int SMAX, class TM, class TX, class TY>
+__global__ __launch_bounds__(256) void k_spmm(const int64_t* mrp, const int32_t* mcol,
+                                              const TM* mval, const int64_t* nrp,
+                                              const int32_t* ncol, const TX* X, TY* Y,
+                                              int64_t n, const double* D, double* part) {
+  using TA = TM;  // accumulate in the operator's precision
+  constexpr int NG = 256 / G;
+  __shared__ double lds[4];
+  const int g = threadIdx.x / G, lane = threadIdx.x % G;
+  const int64_t i = (int64_t)blockIdx.x * NG + g;
+  double dot = 0.0;
+  if (i < n) {
+    const int64_t na = nrp[i];
+    const int ni = (int)(nrp[i + 1] - na);
+    int32_t my = (lane < ni) ? ncol[na + lane] : INT32_MAX;
+    int32_t cols[SMAX];
+#pragma unroll
+    for (int s = 0; s < SMAX; s++) cols[s] = __shfl(my, s % G, G);
+    if (SMAX > G) {
+      // rows longer than G: lanes hold slot s mod G; gather the rest directly
+#pragma unroll
+      for (int s = G; s < SMAX; s++) cols[s] = (s < ni) ? ncol[na + s] : INT32_MAX;
+    }
+    TA acc[SMAX];
+#pragma unroll
+    for (int s = 0; s < SMAX; s++) acc[s] = TA(0);
+    for (int64_t e = mrp[i] + lane; e < mrp[i + 1]; e += G) {
+      const int32_t k = mcol[e];
+      const TA mv = (TA)mval[e];
+      int64_t t = nrp[k];
+      const int64_t te = nrp[k + 1];
+#pragma unroll
+      for (int s = 0; s < SMAX; s++) {
+        if (s < ni) {
+          while (t < te && ncol[t] < cols[s]) t++;
+          if (t < te && ncol[t] == cols[s]) {
+            acc[s] = fma(mv, (TA)X[t], acc[s]);
+            t++;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < SMAX; s++) {
+#pragma unroll
+      for (int m = G / 2; m >= 1; m >>= 1) acc[s] += __shfl_xor(acc[s], m, G);
+    }
+#pragma unroll
+    for (int s = 0; s < SMAX; s++) {
+      if (s < ni && (s % G) == lane) {
+        Y[na + s] = (TY)acc[s];
+        if (D) dot += D[na + s] * (double)acc[s];
+      }
+    }
+  }
+  if (part) {
+    const double t = block_sum(dot, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+  }
+}
+
+// R = -Pi(MP), Z = R, partial <R,R>
+__global__ void k_init_r(const int64_t* rp, const int32_t* col, int64_t n, const int32_t* cid,
+                         const double* Wc, const double* G, const double* MP, double* R,
+                         double* Z, double* part) {
+  __shared__ double lds[4];
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double rr = 0.0;
+  if (i < n) {
+    const int64_t a = rp[i], b = rp[i + 1];
+    if (cid[i] >= 0) {
+      for (int64_t s = a; s < b; s++) { R[s] = 0.0; Z[s] = 0.0; }
+    } else {
+      double f = 0.0;
+      if (G[i] > 0.0) {
+        double dot = 0.0;
+        for (int64_t s = a; s < b; s++) dot = dot + (-MP[s]) * Wc[col[s]];
+        f = dot / G[i];
+      }
+      for (int64_t s = a; s < b; s++) {
+        const double r = -MP[s] - f * Wc[col[s]];
+        R[s] = r;
+        Z[s] = r;
+        rr += r * r;
+      }
+    }
+  }
+  const double t = block_sum(rr, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// P += alpha Z; R -= alpha Pi(Q); partial <R,R>; with the energy trace also
+// MP += alpha Q and partial <P, MP>
+template <class TQ>
+__global__ void k_update(const int64_t* rp, const int32_t* col, int64_t n, const int32_t* cid,
+                         const double* Wc, const double* G, const double* Z, const TQ* Q,
+                         double* P, double* R, double* MP, const CgScalars* sc, double* part,
+                         double* part_e) {
+  __shared__ double lds[4];
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double alpha = sc->alpha;
+  double rr = 0.0, ee = 0.0;
+  if (i < n) {
+    const int64_t a = rp[i], b = rp[i + 1];
+    if (cid[i] < 0) {
+      double f = 0.0;
+      if (G[i] > 0.0) {
+        double dot = 0.0;
+        for (int64_t s = a; s < b; s++) dot = dot + (double)Q[s] * Wc[col[s]];
+        f = dot / G[i];
+      }
+      for (int64_t s = a; s < b; s++) {
+        const double q = (double)Q[s];
+        const double pq = q - f * Wc[col[s]];
+        const double p = P[s] + alpha * Z[s];
+        const double r = R[s] - alpha * pq;
+        P[s] = p;
+        R[s] = r;
+        rr += r * r;
+        if (MP) {
+          const double mp = MP[s] + alpha * q;
+          MP[s] = mp;
+          ee += p * mp;
+        }
+      }
+    } else if (MP) {
+      for (int64_t s = a; s < b; s++) {
+        const double mp = MP[s] + alpha * (double)Q[s];
+        MP[s] = mp;
+        ee += P[s] * mp;
+      }
+    }
+  }
+  double t = block_sum(rr, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+  if (part_e) {
+    t = block_sum(ee, lds);
+    if (threadIdx.x == 0) part_e[blockIdx.x] = t;
+  }
+}
+
+// Z = R + beta Z (and the FP32 copy used by the mixed-precision product)
+__global__ void k_zupd(const double* R, double* Z, float* Zf, int64_t nnz, const CgScalars* sc) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  const double z = R[e] + sc->beta * Z[e];
+  Z[e] = z;
+  if (Zf) Zf[e] = (float)z;
+}
+
+__global__ void k_to_float(const double* a, float* b, int64_t n) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) b[e] = (float)a[e];
+}
+
+enum FinMode { FIN_E0 = 0, FIN_RHO0 = 1, FIN_GAMMA = 2, FIN_RHO = 3, FIN_E = 4 };
+
+// Sum of block partials in a fixed order, then the CG scalar logic:
+// gamma <= 0 with rho > 0 is a breakdown; rho == 0 stops early.
+__global__ __launch_bounds__(1024) void k_finalize(const double* part, int np, CgScalars* sc,
+                                                   int mode, int it, double* rep_e,
+                                                   double* rep_rho, double* rep_gamma,
+                                                   int32_t* rep_its, int32_t* rep_status) {
+  __shared__ double lds[16];
+  double v = 0.0;
+  for (int k = threadIdx.x; k < np; k += blockDim.x) v += part[k];
+  const double tot = block_sum(v, lds);
+  if (threadIdx.x != 0) return;
+  switch (mode) {
+    case FIN_E0:
+      if (rep_e) rep_e[0] = tot;
+      break;
+    case FIN_RHO0:
+      sc->rho = tot;
+      sc->alpha = 0.0;
+      sc->beta = 0.0;
+      sc->stop = 0;
+      sc->its = 0;
+      if (rep_rho) rep_rho[0] = tot;
+      break;
+    case FIN_GAMMA:
+      if (rep_gamma) rep_gamma[it] = tot;
+      if (sc->stop || sc->rho == 0.0) {
+        sc->stop = 1;
+        sc->alpha = 0.0;
+      } else if (!(tot > 0.0)) {
+        sc->stop = 1;
+        sc->alpha = 0.0;
+        if (rep_status) atomicMax(rep_status, (int32_t)EMIN_ERR_BREAKDOWN);
+      } else {
+        sc->alpha = sc->rho / tot;
+        sc->its += 1;
+        if (rep_its) *rep_its = sc->its;
+      }
+      break;
+    case FIN_RHO:
+      if (sc->stop) {
+        sc->beta = 0.0;
+      } else {
+        sc->beta = tot / sc->rho;
+        sc->rho = tot;
+        if (rep_rho) rep_rho[it + 1] = tot;
+      }
+      break;
+    case FIN_E:
+      if (!sc->stop && rep_e) rep_e[it + 1] = tot;
+      break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+void EminWork::allocate(int64_t n_, int64_t nnz_, int64_t nc_, Arena& ar, bool mixed) {
+  n = n_;
+  nnz = nnz_;
+  nc = nc_;
+  G = ar.alloc<double>(n);
+  Wc = ar.alloc<double>(nc);
+  Wdef = ar.alloc<double>(n);
+  R = ar.alloc<double>(nnz);
+  Z = ar.alloc<double>(nnz);
+  Q = ar.alloc<double>(nnz);
+  MP = ar.alloc<double>(nnz);
+  Zf = ar.alloc<float>(nnz);
+  Qf = ar.alloc<float>(nnz);
+  (void)mixed;
+  const int64_t np = (int64_t)nblocks(n, 4) + 8;  // enough for every grid used
+  part = ar.alloc<double>(np);
+  part_e = ar.alloc<double>(np);
+  sc = ar.alloc<CgScalars>(1);
+}
+
+template <int G, int SMAX, class TM, class TX, class TY>
+static void spmm_launch(const Csr& M, const TM* mval, const int64_t* nrp, const int32_t* ncol,
+                        const TX* X, TY* Y, int64_t n, const double* D, double* part,
+                        hipStream_t s) {
+  constexpr int NG = 256 / G;
+  k_spmm<G, SMAX, TM, TX, TY><<<nblocks(n, NG), 256, 0, s>>>(M.rowptr, M.col, mval, nrp, ncol, X,
+                                                            Y, n, D, part);
+}
+
+template <int G, class TM, class TX, class TY>
+static void spmm_smax(int smax, const Csr& M, const TM* mval, const int64_t* nrp,
+                      const int32_t* ncol, const TX* X, TY* Y, int64_t n, const double* D,
+                      double* part, hipStream_t s) {
+  if (smax <= 4) spmm_launch<G, 4>(M, mval, nrp, ncol, X, Y, n, D, part, s);
+  else if (smax <= 8) spmm_launch<G, 8>(M, mval, nrp, ncol, X, Y, n, D, part, s);
+  else if (smax <= 16) spmm_launch<G, 16>(M, mval, nrp, ncol, X, Y, n, D, part, s);
+  else if (smax <= 32) spmm_launch<G, 32>(M, mval, nrp, ncol, X, Y, n, D, part, s);
+  else spmm_launch<G, 64>(M, mval, nrp, ncol, X, Y, n, D, part, s);
+}
+
+template <class TM, class TX, class TY>
+static int64_t spmm_any(int g, int smax, const Csr& M, const TM* mval, const int64_t* nrp,
+                        const int32_t* ncol, const TX* X, TY* Y, int64_t n, const double* D,
+                        double* part, hipStream_t s) {
+  switch (g) {
+    case 4: spmm_smax<4>(smax, M, mval, nrp, ncol, X, Y, n, D, part, s); return nblocks(n, 64);
+    case 8: spmm_smax<8>(smax, M, mval, nrp, ncol, X, Y, n, D, part, s); return nblocks(n, 32);
+    case 16: spmm_smax<16>(smax, M, mval, nrp, ncol, X, Y, n, D, part, s); return nblocks(n, 16);
+    case 32: spmm_smax<32>(smax, M, mval, nrp, ncol, X, Y, n, D, part, s); return nblocks(n, 8);
+    default: spmm_smax<64>(smax, M, mval, nrp, ncol, X, Y, n, D, part, s); return nblocks(n, 4);
+  }
+}
+
+int64_t masked_spmm(const EminWork& w, const Csr& M, const int64_t* nrp, const int32_t* ncol,
+                    const double* X, double* Y, const double* D, double* part, hipStream_t s) {
+  return spmm_any<double, double, double>(w.g, w.smax, M, M.val, nrp, ncol, X, Y, w.n, D, part,
+                                          s);
+}
+
+void run_emin(EminWork& w, const Csr& M, const float* Mf, const int64_t* nrp, const int32_t* ncol,
+              const int32_t* cid, const int32_t* clist, const double* W, double* P, int iters,
+              bool energy, bool mixed, EminReportPtrs rp, hipStream_t s) {
+  const int64_t n = w.n, nnz = w.nnz;
+  if (n == 0) return;
+  if (w.nc) k_gather_modes<<<nblocks(w.nc, 256), 256, 0, s>>>(W, clist, w.nc, w.Wc);
+  k_emin_init<<<nblocks(n, RB), RB, 0, s>>>(nrp, ncol, n, cid, W, w.Wc, w.G, P, rp.status);
+  // E0 = <P0, mask(M P0)> and R = -Pi(mask(M P0))
+  int64_t np = masked_spmm(w, M, nrp, ncol, P, w.MP, P, w.part, s);
+  k_finalize<<<1, 1024, 0, s>>>(w.part, (int)np, w.sc, FIN_E0, 0, rp.energy, nullptr, nullptr,
+                                nullptr, nullptr);
+  k_init_r<<<nblocks(n, RB), RB, 0, s>>>(nrp, ncol, n, cid, w.Wc, w.G, w.MP, w.R, w.Z, w.part);
+  k_finalize<<<1, 1024, 0, s>>>(w.part, (int)nblocks(n, RB), w.sc, FIN_RHO0, 0, nullptr, rp.rho,
+                                nullptr, nullptr, nullptr);
+  if (mixed) k_to_float<<<nblocks(nnz, 256), 256, 0, s>>>(w.Z, w.Zf, nnz);
+  for (int it = 0; it < iters; it++) {
+    if (mixed) {
+      np = spmm_any<float, float, float>(w.g, w.smax, M, Mf, nrp, ncol, w.Zf, w.Qf, n, w.Z,
+                                         w.part, s);
+    } else {
+      np = masked_spmm(w, M, nrp, ncol, w.Z, w.Q, w.Z, w.part, s);
+    }
+    k_finalize<<<1, 1024, 0, s>>>(w.part, (int)np, w.sc, FIN_GAMMA, it, nullptr, nullptr,
+                                  rp.gamma, rp.its, rp.status);
+    if (mixed)
+      k_update<float><<<nblocks(n, RB), RB, 0, s>>>(nrp, ncol, n, cid, w.Wc, w.G, w.Z, w.Qf, P,
+                                                     w.R, energy ? w.MP : nullptr, w.sc, w.part,
+                                                     energy ? w.part_e : nullptr);
+    else
+      k_update<double><<<nblocks(n, RB), RB, 0, s>>>(nrp, ncol, n, cid, w.Wc, w.G, w.Z, w.Q, P,
+                                                      w.R, energy ? w.MP : nullptr, w.sc, w.part,
+                                                      energy ? w.part_e : nullptr);
+    k_finalize<<<1, 1024, 0, s>>>(w.part, (int)nblocks(n, RB), w.sc, FIN_RHO, it, nullptr, rp.rho,
+                                  nullptr, nullptr, nullptr);
+    if (energy)
+      k_finalize<<<1, 1024, 0, s>>>(w.part_e, (int)nblocks(n, RB), w.sc, FIN_E, it, rp.energy,
+                                    nullptr, nullptr, nullptr, nullptr);
+    k_zupd<<<nblocks(nnz, 256), 256, 0, s>>>(w.R, w.Z, mixed ? w.Zf : nullptr, nnz, w.sc);
+  }
+}
+
+void default_modes(const uint8_t* dir, int64_t n, double* W, hipStream_t s) {
+  if (n) k_default_modes<<<nblocks(n, 256), 256, 0, s>>>(dir, n, W);
+}
+
+void to_float(const double* a, float* b, int64_t n, hipStream_t s) {
+  if (n) k_to_float<<<nblocks(n, 256), 256, 0, s>>>(a, b, n);
+}
+
+}  // namespace emin

@@ -1,0 +1,201 @@
+// Alg. 4 (find_velocity_Cpoints): pressure mid-points.
+//
+// Every F vertex i with |S_i| >= 2 gets, in parallel, its target X_i (the
+// barycentre of S_i), its search set B_i = {j in F : S_i subset of S_j}, the
+// closest vertex m_i, and the set T_i of vertices of B_i that are closer to
+// m_i than tau2 * t_i (t_i the diagonal of B_i's bounding box).  The loop of
+// Alg. 4 then reduces to: visiting i in the order (|S_i| desc, i asc), add
+// m_i to C-bar unless some vertex of T_i is already in C-bar.  That ordered
+// pass runs in one wave with C-bar as a bitmap in LDS, 64 entries at a time:
+// each entry's dependence on the earlier entries of its chunk is a 64-bit
+// mask, resolved in lane order.
+#include "coarsen.h"
+
+namespace emin {
+
+constexpr int TCAP = 8;
+
+__device__ __forceinline__ bool subset_sorted(const int32_t* a, int na, const int32_t* b, int nb) {
+  int q = 0;
+  for (int p = 0; p < na; p++) {
+    while (q < nb && b[q] < a[p]) q++;
+    if (q >= nb || b[q] != a[p]) return false;
+    q++;
+  }
+  return true;
+}
+
+__global__ void k_mid_prep(const int64_t* srp, const int32_t* scol, const int64_t* trp,
+                           const int32_t* tcol, const uint8_t* st, const double* x, int dim,
+                           double tau2_sq, int64_t n, int32_t* m_out, int32_t* size_key,
+                           int32_t* tcnt, int32_t* tlist, int* err) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t s0 = srp[i], s1 = srp[i + 1];
+  const int si = (int)(s1 - s0);
+  m_out[i] = -1;
+  size_key[i] = 0;
+  tcnt[i] = 0;
+  if (st[i] == ST_C || si < 2) return;
+  double X[3] = {0.0, 0.0, 0.0};
+  for (int d = 0; d < dim; d++) {
+    double acc = 0.0;
+    for (int64_t e = s0; e < s1; e++) acc = acc + x[(int64_t)scol[e] * dim + d];
+    X[d] = acc / (double)si;
+  }
+  const int32_t c0 = scol[s0];
+  int32_t m = -1;
+  double md = 0.0;
+  double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
+  bool first = true;
+  for (int64_t e = trp[c0]; e < trp[c0 + 1]; e++) {
+    const int32_t j = tcol[e];
+    if (st[j] == ST_C) continue;
+    if (!subset_sorted(scol + s0, si, scol + srp[j], (int)(srp[j + 1] - srp[j]))) continue;
+    double d2 = 0.0;
+    for (int d = 0; d < dim; d++) {
+      const double r = x[(int64_t)j * dim + d] - X[d];
+      d2 = d2 + r * r;
+    }
+    if (m < 0 || d2 < md || (d2 == md && j < m)) { m = j; md = d2; }
+    for (int d = 0; d < dim; d++) {
+      const double v = x[(int64_t)j * dim + d];
+      if (first || v < lo[d]) lo[d] = v;
+      if (first || v > hi[d]) hi[d] = v;
+    }
+    first = false;
+  }
+  double w2 = 0.0;
+  for (int d = 0; d < dim; d++) {
+    const double w = hi[d] - lo[d];
+    w2 = w2 + w * w;
+  }
+  const double thr = tau2_sq * w2;
+  int tc = 0;
+  for (int64_t e = trp[c0]; e < trp[c0 + 1]; e++) {
+    const int32_t j = tcol[e];
+    if (st[j] == ST_C) continue;
+    if (!subset_sorted(scol + s0, si, scol + srp[j], (int)(srp[j + 1] - srp[j]))) continue;
+    double d2 = 0.0;
+    for (int d = 0; d < dim; d++) {
+      const double r = x[(int64_t)j * dim + d] - x[(int64_t)m * dim + d];
+      d2 = d2 + r * r;
+    }
+    if (d2 < thr) {
+      if (tc < TCAP) tlist[i * TCAP + tc] = j;
+      else atomicOr(err, DERR_CAPACITY);
+      tc++;
+    }
+  }
+  m_out[i] = m;
+  size_key[i] = si;
+  tcnt[i] = tc < TCAP ? tc : TCAP;
+}
+
+__global__ void k_flag_eq(const int32_t* key, int64_t n, int32_t val, int64_t* flags) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flags[i] = key[i] == val;
+}
+
+__global__ void k_place(const int32_t* key, const int64_t* incl, int64_t n, int32_t val,
+                        int64_t base, int32_t* order) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && key[i] == val) order[base + incl[i] - 1] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(64) void k_mid_decide(const int32_t* order, int64_t norder,
+                                                   const int32_t* m, const int32_t* tcnt,
+                                                   const int32_t* tlist, const uint8_t* st,
+                                                   int64_t n, uint8_t* cbar) {
+  extern __shared__ uint32_t bits[];
+  const int lane = threadIdx.x;
+  const int64_t nw = (n + 31) / 32;
+  for (int64_t w = lane; w < nw; w += 64) bits[w] = 0u;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  for (int64_t i = lane; i < n; i += 64)
+    if (st[i] == ST_C) atomicOr(&bits[i >> 5], 1u << (i & 31));
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  for (int64_t base = 0; base < norder; base += 64) {
+    const bool valid = base + lane < norder;
+    const int32_t i = valid ? order[base + lane] : 0;
+    const int32_t mi = valid ? m[i] : -1;
+    const int tc = valid ? tcnt[i] : 0;
+    int32_t T[TCAP];
+#pragma unroll
+    for (int t = 0; t < TCAP; t++) T[t] = (t < tc) ? tlist[(int64_t)i * TCAP + t] : -1;
+    bool pre = false;
+#pragma unroll
+    for (int t = 0; t < TCAP; t++)
+      if (T[t] >= 0 && (bits[T[t] >> 5] >> (T[t] & 31)) & 1u) pre = true;
+    uint64_t dep = 0ull;
+    for (int l = 0; l < 64; l++) {
+      const int32_t ml = __shfl(mi, l, 64);
+      if (l < lane) {
+#pragma unroll
+        for (int t = 0; t < TCAP; t++)
+          if (T[t] >= 0 && T[t] == ml) dep |= 1ull << l;
+      }
+    }
+    uint64_t accepted = 0ull;
+    for (int l = 0; l < 64; l++) {
+      const int v = __shfl((int)valid, l, 64);
+      const int p = __shfl((int)pre, l, 64);
+      const uint64_t dl = __shfl(dep, l, 64);
+      if (v && !p && (dl & accepted) == 0ull) accepted |= 1ull << l;
+    }
+    if ((accepted >> lane) & 1ull) atomicOr(&bits[mi >> 5], 1u << (mi & 31));
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  }
+  for (int64_t i = lane; i < n; i += 64) cbar[i] = (bits[i >> 5] >> (i & 31)) & 1u;
+}
+
+__global__ void k_count_set(const uint8_t* f, int64_t n, unsigned long long* c) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && f[i]) atomicAdd(c, 1ull);
+}
+
+int64_t midpoints(const Csr& S, const uint8_t* st, const double* x, int dim, double tau2_sq,
+                  uint8_t* cbar, hipStream_t s, Arena& ar, int lds_max) {
+  const int64_t n = S.nrows;
+  if (n == 0) return 0;
+  Csr ST;
+  int32_t* tsrc = nullptr;
+  transpose_pattern(view(S), ST, tsrc, s, ar);
+  int32_t* m = ar.alloc<int32_t>(n);
+  int32_t* key = ar.alloc<int32_t>(n);
+  int32_t* tcnt = ar.alloc<int32_t>(n);
+  int32_t* tlist = ar.alloc<int32_t>((size_t)n * TCAP);
+  int* err = ar.alloc<int>(1);
+  HIP_OK(hipMemsetAsync(err, 0, sizeof(int), s));
+  k_mid_prep<<<nblocks(n, 256), 256, 0, s>>>(S.rowptr, S.col, ST.rowptr, ST.col, st, x, dim,
+                                              tau2_sq, n, m, key, tcnt, tlist, err);
+  if (d2h(err, s)) throw Error(EMIN_ERR_CAPACITY, "alg4: closeness set capacity");
+  const int64_t maxs = max_row_len(S.rowptr, n, s, ar);
+  int32_t* order = ar.alloc<int32_t>(n);
+  int64_t* flags = ar.alloc<int64_t>(n);
+  int64_t norder = 0;
+  for (int64_t sz = maxs; sz >= 2; sz--) {
+    k_flag_eq<<<nblocks(n, 256), 256, 0, s>>>(key, n, (int32_t)sz, flags);
+    scan_inclusive(flags, n, s, ar);
+    k_place<<<nblocks(n, 256), 256, 0, s>>>(key, flags, n, (int32_t)sz, norder, order);
+    norder += d2h(flags + n - 1, s);
+  }
+  const size_t lds = (size_t)((n + 31) / 32) * 4;
+  if ((int64_t)lds > lds_max) throw Error(EMIN_ERR_CAPACITY, "alg4: C-bar bitmap exceeds LDS");
+  HIP_OK(hipFuncSetAttribute((const void*)k_mid_decide,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  k_mid_decide<<<1, 64, lds, s>>>(order, norder, m, tcnt, tlist, st, n, cbar);
+  HIP_OK(hipGetLastError());
+  unsigned long long* c = ar.alloc<unsigned long long>(2);
+  HIP_OK(hipMemsetAsync(c, 0, 2 * sizeof(unsigned long long), s));
+  k_count_set<<<nblocks(n, 256), 256, 0, s>>>(cbar, n, c);
+  return (int64_t)d2h(c, s);
+}
+
+}  // namespace emin

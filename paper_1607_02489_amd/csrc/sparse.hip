@@ -1,0 +1,597 @@
+// Sparse building blocks: scans, transposes, the ordered row-wise SpGEMM,
+// and the drop/lump filter of eq. (e:filtering) with its symmetrisation.
+#include "common.h"
+
+namespace emin {
+
+// ---------------------------------------------------------------------------
+// scan
+// ---------------------------------------------------------------------------
+constexpr int SCAN_BS = 256;
+constexpr int SCAN_IT = 8;
+constexpr int SCAN_TILE = SCAN_BS * SCAN_IT;
+
+__device__ int64_t block_exclusive(int64_t v, int64_t* lds, int64_t* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int64_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int64_t t = __shfl_up(x, o, 64);
+    if (lane >= o) x += t;
+  }
+  if (lane == 63) lds[w] = x;
+  __syncthreads();
+  int64_t off = 0, tot = 0;
+  for (int k = 0; k < SCAN_BS / 64; k++) {
+    if (k < w) off += lds[k];
+    tot += lds[k];
+  }
+  __syncthreads();
+  *total = tot;
+  return off + x - v;
+}
+
+__global__ void k_tile_sums(const int64_t* a, int64_t n, int64_t* bsum) {
+  __shared__ int64_t lds[SCAN_BS / 64];
+  int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IT;
+  int64_t s = 0;
+  for (int j = 0; j < SCAN_IT; j++)
+    if (base + j < n) s += a[base + j];
+  int64_t tot;
+  block_exclusive(s, lds, &tot);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ void k_tile_scan(int64_t* a, int64_t n, const int64_t* bincl) {
+  __shared__ int64_t lds[SCAN_BS / 64];
+  int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IT;
+  int64_t v[SCAN_IT];
+  int64_t s = 0;
+#pragma unroll
+  for (int j = 0; j < SCAN_IT; j++) {
+    v[j] = (base + j < n) ? a[base + j] : 0;
+    s += v[j];
+  }
+  int64_t tot;
+  int64_t off = block_exclusive(s, lds, &tot);
+  if (bincl && blockIdx.x > 0) off += bincl[blockIdx.x - 1];
+#pragma unroll
+  for (int j = 0; j < SCAN_IT; j++) {
+    off += v[j];
+    if (base + j < n) a[base + j] = off;
+  }
+}
+
+void scan_inclusive(int64_t* a, int64_t n, hipStream_t s, Arena& ar) {
+  if (n <= 0) return;
+  unsigned nb = nblocks(n, SCAN_TILE);
+  if (nb == 1) {
+    k_tile_scan<<<1, SCAN_BS, 0, s>>>(a, n, nullptr);
+    return;
+  }
+  int64_t* bs = ar.alloc<int64_t>(nb);
+  k_tile_sums<<<nb, SCAN_BS, 0, s>>>(a, n, bs);
+  scan_inclusive(bs, nb, s, ar);
+  k_tile_scan<<<nb, SCAN_BS, 0, s>>>(a, n, bs);
+}
+
+int64_t rowptr_from_counts(int64_t* rowptr, int64_t n, hipStream_t s, Arena& ar) {
+  HIP_OK(hipMemsetAsync(rowptr, 0, sizeof(int64_t), s));
+  scan_inclusive(rowptr + 1, n, s, ar);
+  return d2h(rowptr + n, s);
+}
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+__global__ void k_validate(const int64_t* rp, const int32_t* col, const double* val, int64_t n,
+                           int64_t ncols, int64_t nnz, int* derr) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t a = rp[i], b = rp[i + 1];
+  if (a < 0 || b < a || b > nnz) { atomicOr(derr, DERR_PATTERN); return; }
+  int32_t prev = -1;
+  for (int64_t e = a; e < b; e++) {
+    int32_t c = col[e];
+    if (c <= prev || c >= ncols) { atomicOr(derr, DERR_PATTERN); return; }
+    prev = c;
+    if (val && !isfinite(val[e])) atomicOr(derr, DERR_VALUE);
+  }
+}
+
+void validate_csr(const CsrView& A, bool values, int* derr, hipStream_t s) {
+  if (A.nrows == 0) return;
+  k_validate<<<nblocks(A.nrows, 256), 256, 0, s>>>(A.rowptr, A.col, values ? A.val : nullptr,
+                                                    A.nrows, A.ncols, A.nnz, derr);
+}
+
+// ---------------------------------------------------------------------------
+// transpose
+// ---------------------------------------------------------------------------
+__global__ void k_count_cols(const int32_t* col, int64_t nnz, int64_t* cnt) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nnz) atomicAdd((unsigned long long*)&cnt[col[e] + 1], 1ull);
+}
+
+__global__ void k_transpose_fill(const int64_t* rp, const int32_t* col, int64_t n,
+                                 int64_t* cursor, int32_t* colT, int32_t* src) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int64_t e = rp[i]; e < rp[i + 1]; e++) {
+    int64_t p = (int64_t)atomicAdd((unsigned long long*)&cursor[col[e]], 1ull);
+    colT[p] = (int32_t)i;
+    src[p] = (int32_t)e;
+  }
+}
+
+// rows of the transpose are short: insertion sort restores ascending order
+__global__ void k_sort_segments(const int64_t* rp, int64_t n, int32_t* key, int32_t* src) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t a = rp[i], b = rp[i + 1];
+  for (int64_t p = a + 1; p < b; p++) {
+    int32_t k = key[p], s = src[p];
+    int64_t q = p;
+    while (q > a && key[q - 1] > k) {
+      key[q] = key[q - 1];
+      src[q] = src[q - 1];
+      q--;
+    }
+    key[q] = k;
+    src[q] = s;
+  }
+}
+
+void transpose_pattern(const CsrView& A, Csr& At, int32_t*& src, hipStream_t s, Arena& ar) {
+  At.nrows = A.ncols;
+  At.ncols = A.nrows;
+  At.nnz = A.nnz;
+  At.rowptr = ar.alloc<int64_t>(At.nrows + 1);
+  HIP_OK(hipMemsetAsync(At.rowptr, 0, sizeof(int64_t) * (At.nrows + 1), s));
+  if (A.nnz) k_count_cols<<<nblocks(A.nnz, 256), 256, 0, s>>>(A.col, A.nnz, At.rowptr);
+  scan_inclusive(At.rowptr + 1, At.nrows, s, ar);
+  At.col = ar.alloc<int32_t>(A.nnz);
+  src = ar.alloc<int32_t>(A.nnz);
+  int64_t* cursor = ar.alloc<int64_t>(At.nrows + 1);
+  HIP_OK(hipMemcpyAsync(cursor, At.rowptr, sizeof(int64_t) * (At.nrows + 1),
+                        hipMemcpyDeviceToDevice, s));
+  if (A.nrows)
+    k_transpose_fill<<<nblocks(A.nrows, 256), 256, 0, s>>>(A.rowptr, A.col, A.nrows, cursor,
+                                                            At.col, src);
+  if (At.nrows)
+    k_sort_segments<<<nblocks(At.nrows, 256), 256, 0, s>>>(At.rowptr, At.nrows, At.col, src);
+}
+
+__global__ void k_gather(const double* in, const int32_t* src, double* out, int64_t n) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) out[p] = in[src[p]];
+}
+
+void gather_values(const double* in, const int32_t* src, double* out, int64_t n, hipStream_t s) {
+  if (n) k_gather<<<nblocks(n, 256), 256, 0, s>>>(in, src, out, n);
+}
+
+// ---------------------------------------------------------------------------
+// SpGEMM, symbolic: G lanes per output row collect the distinct columns in an
+// LDS open-addressing table, then write them in ascending order (rank sort).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t hash32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+template <int G>
+__global__ void k_spgemm_sym(const int64_t* arp, const int32_t* acol, const int64_t* brp,
+                             const int32_t* bcol, int64_t n, int hcap, int64_t* out_cnt,
+                             const int64_t* crp, int32_t* ccol, int* derr) {
+  extern __shared__ int32_t lds_keys[];
+  constexpr int NG = 256 / G;
+  __shared__ int32_t cnt[NG];
+  const int g = threadIdx.x / G, lane = threadIdx.x % G;
+  int32_t* keys = lds_keys + (size_t)g * hcap;
+  const int64_t row = (int64_t)blockIdx.x * NG + g;
+  for (int t = lane; t < hcap; t += G) keys[t] = -1;
+  if (lane == 0) cnt[g] = 0;
+  __syncthreads();
+  const uint32_t mask = (uint32_t)hcap - 1u;
+  bool overflow = false;
+  if (row < n) {
+    for (int64_t e = arp[row] + lane; e < arp[row + 1]; e += G) {
+      int32_t k = acol[e];
+      for (int64_t f = brp[k]; f < brp[k + 1]; f++) {
+        int32_t j = bcol[f];
+        uint32_t h = hash32((uint32_t)j) & mask;
+        int probes = 0;
+        while (true) {
+          int32_t old = atomicCAS(&keys[h], -1, j);
+          if (old == -1) { atomicAdd(&cnt[g], 1); break; }
+          if (old == j) break;
+          h = (h + 1u) & mask;
+          if (++probes >= hcap) { overflow = true; break; }
+        }
+        if (overflow) break;
+      }
+      if (overflow) break;
+    }
+  }
+  __syncthreads();
+  if (overflow || (row < n && cnt[g] * 2 > hcap)) {
+    if (lane == 0) atomicOr(derr, DERR_CAPACITY);
+    return;
+  }
+  if (row >= n) return;
+  if (ccol == nullptr) {
+    if (lane == 0) out_cnt[row + 1] = cnt[g];
+    return;
+  }
+  const int64_t base = crp[row];
+  for (int t = lane; t < hcap; t += G) {
+    int32_t key = keys[t];
+    if (key < 0) continue;
+    int32_t rank = 0;
+    for (int u = 0; u < hcap; u++) {
+      int32_t o = keys[u];
+      rank += (o >= 0 && o < key);
+    }
+    ccol[base + rank] = key;
+  }
+}
+
+// SpGEMM, numeric: G lanes per row; for each k of A's row in ascending order
+// the lanes take B's row k (distinct columns, so no two lanes meet), find
+// each column in the row's sorted output list held in LDS and accumulate.
+template <int G>
+__global__ void k_spgemm_num(const int64_t* arp, const int32_t* acol, const double* aval,
+                             const int64_t* brp, const int32_t* bcol, const double* bval,
+                             const int64_t* crp, const int32_t* ccol, double* cval, int64_t n,
+                             int cap) {
+  extern __shared__ unsigned char lds_raw[];
+  constexpr int NG = 256 / G;
+  const int g = threadIdx.x / G, lane = threadIdx.x % G;
+  double* acc = reinterpret_cast<double*>(lds_raw) + (size_t)g * cap;
+  int32_t* cols = reinterpret_cast<int32_t*>(reinterpret_cast<double*>(lds_raw) + (size_t)NG * cap) +
+                  (size_t)g * cap;
+  const int64_t row = (int64_t)blockIdx.x * NG + g;
+  if (row >= n) return;
+  const int64_t c0 = crp[row];
+  const int nc = (int)(crp[row + 1] - c0);
+  if (nc > cap) return;  // handled by k_spgemm_num_long
+  for (int t = lane; t < nc; t += G) {
+    cols[t] = ccol[c0 + t];
+    acc[t] = 0.0;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  for (int64_t e = arp[row]; e < arp[row + 1]; e++) {
+    const int32_t k = acol[e];
+    const double a = aval[e];
+    for (int64_t f = brp[k] + lane; f < brp[k + 1]; f += G) {
+      const int32_t j = bcol[f];
+      int lo = 0, hi = nc;
+      while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (cols[mid] < j) lo = mid + 1; else hi = mid;
+      }
+      const double prod = a * bval[f];
+      acc[lo] = acc[lo] + prod;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  }
+  for (int t = lane; t < nc; t += G) cval[c0 + t] = acc[t];
+}
+
+// fallback for rows longer than the LDS capacity: one lane per row, the
+// accumulators live in the output array itself (same summation order)
+__global__ void k_spgemm_num_long(const int64_t* arp, const int32_t* acol, const double* aval,
+                                  const int64_t* brp, const int32_t* bcol, const double* bval,
+                                  const int64_t* crp, const int32_t* ccol, double* cval,
+                                  int64_t n, int cap) {
+  int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  const int64_t c0 = crp[row];
+  const int nc = (int)(crp[row + 1] - c0);
+  if (nc <= cap) return;
+  for (int t = 0; t < nc; t++) cval[c0 + t] = 0.0;
+  for (int64_t e = arp[row]; e < arp[row + 1]; e++) {
+    const int32_t k = acol[e];
+    const double a = aval[e];
+    for (int64_t f = brp[k]; f < brp[k + 1]; f++) {
+      const int32_t j = bcol[f];
+      int lo = 0, hi = nc;
+      while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (ccol[c0 + mid] < j) lo = mid + 1; else hi = mid;
+      }
+      const double prod = a * bval[f];
+      cval[c0 + lo] = cval[c0 + lo] + prod;
+    }
+  }
+}
+
+__global__ void k_row_len_max(const int64_t* rp, int64_t n, unsigned long long* mx) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long v = (i < n) ? (unsigned long long)(rp[i + 1] - rp[i]) : 0ull;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    unsigned long long o = __shfl_xor(v, m, 64);
+    v = o > v ? o : v;
+  }
+  if ((threadIdx.x & 63) == 0) atomicMax(mx, v);
+}
+
+int64_t max_row_len(const int64_t* rp, int64_t n, hipStream_t s, Arena& ar) {
+  if (n <= 0) return 0;
+  unsigned long long* mx = ar.alloc<unsigned long long>(1);
+  HIP_OK(hipMemsetAsync(mx, 0, sizeof(unsigned long long), s));
+  k_row_len_max<<<nblocks(n, 256), 256, 0, s>>>(rp, n, mx);
+  return (int64_t)d2h(mx, s);
+}
+
+static int pick_g(double avg) {
+  int g = 4;
+  while (g < 64 && g < avg) g <<= 1;
+  return g;
+}
+
+template <int G>
+static void launch_sym(const CsrView& A, const CsrView& B, int hcap, int64_t* cnt,
+                       const int64_t* crp, int32_t* ccol, int* derr, hipStream_t s) {
+  constexpr int NG = 256 / G;
+  size_t lds = (size_t)NG * hcap * sizeof(int32_t);
+  k_spgemm_sym<G><<<nblocks(A.nrows, NG), 256, lds, s>>>(A.rowptr, A.col, B.rowptr, B.col,
+                                                         A.nrows, hcap, cnt, crp, ccol, derr);
+}
+
+static void sym_dispatch(int g, const CsrView& A, const CsrView& B, int hcap, int64_t* cnt,
+                         const int64_t* crp, int32_t* ccol, int* derr, hipStream_t s) {
+  switch (g) {
+    case 4: launch_sym<4>(A, B, hcap, cnt, crp, ccol, derr, s); break;
+    case 8: launch_sym<8>(A, B, hcap, cnt, crp, ccol, derr, s); break;
+    case 16: launch_sym<16>(A, B, hcap, cnt, crp, ccol, derr, s); break;
+    case 32: launch_sym<32>(A, B, hcap, cnt, crp, ccol, derr, s); break;
+    default: launch_sym<64>(A, B, hcap, cnt, crp, ccol, derr, s); break;
+  }
+}
+
+void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& plan,
+                     hipStream_t s, Arena& ar, int* derr) {
+  if (A.ncols != B.nrows) throw Error(EMIN_ERR_SHAPE, "spgemm: inner dimensions differ");
+  C.nrows = A.nrows;
+  C.ncols = B.ncols;
+  C.rowptr = ar.alloc<int64_t>(C.nrows + 1);
+  HIP_OK(hipMemsetAsync(C.rowptr, 0, sizeof(int64_t) * (C.nrows + 1), s));
+  const double avg_a = A.nrows ? (double)A.nnz / (double)A.nrows : 1.0;
+  const int g = pick_g(avg_a);
+  const int64_t maxb = max_row_len(B.rowptr, B.nrows, s, ar);
+  int hcap = 32;
+  while (hcap < 2 * maxb && hcap < 1024) hcap <<= 1;
+  const int max_hcap = 65536 / (256 / g) / 4 * 2;  // per-group share of ~128 KiB
+  int* lerr = ar.alloc<int>(1);
+  while (true) {
+    HIP_OK(hipMemsetAsync(lerr, 0, sizeof(int), s));
+    if (A.nrows) sym_dispatch(g, A, B, hcap, C.rowptr, nullptr, nullptr, lerr, s);
+    int e = d2h(lerr, s);
+    if (!(e & DERR_CAPACITY)) break;
+    if (hcap >= max_hcap || hcap >= 16384)
+      throw Error(EMIN_ERR_CAPACITY, "spgemm: output row exceeds the LDS hash capacity");
+    hcap <<= 1;
+  }
+  C.nnz = rowptr_from_counts(C.rowptr, C.nrows, s, ar);
+  C.col = ar.alloc<int32_t>(C.nnz);
+  C.val = ar.alloc<double>(C.nnz);
+  HIP_OK(hipMemsetAsync(lerr, 0, sizeof(int), s));
+  if (A.nrows) sym_dispatch(g, A, B, hcap, nullptr, C.rowptr, C.col, lerr, s);
+  if (d2h(lerr, s)) throw Error(EMIN_ERR_CAPACITY, "spgemm: fill pass overflow");
+  plan.max_row = max_row_len(C.rowptr, C.nrows, s, ar);
+  const double avg_b = B.nrows ? (double)B.nnz / (double)B.nrows : 1.0;
+  plan.g_num = pick_g(avg_b);
+  (void)derr;
+}
+
+template <int G>
+static void launch_num(const CsrView& A, const CsrView& B, const Csr& C, int cap, hipStream_t s) {
+  constexpr int NG = 256 / G;
+  size_t lds = (size_t)NG * cap * (sizeof(double) + sizeof(int32_t));
+  k_spgemm_num<G><<<nblocks(A.nrows, NG), 256, lds, s>>>(
+      A.rowptr, A.col, A.val, B.rowptr, B.col, B.val, C.rowptr, C.col, C.val, A.nrows, cap);
+}
+
+void spgemm_numeric(const CsrView& A, const CsrView& B, const Csr& C, const SpgemmPlan& plan,
+                    hipStream_t s) {
+  if (A.nrows == 0 || C.nnz == 0) return;
+  const int g = plan.g_num;
+  const int NG = 256 / g;
+  // LDS budget ~96 KiB per block
+  int cap = (int)((96 * 1024) / (NG * (sizeof(double) + sizeof(int32_t))));
+  if (cap > plan.max_row) cap = (int)plan.max_row;
+  if (cap < 1) cap = 1;
+  switch (g) {
+    case 4: launch_num<4>(A, B, C, cap, s); break;
+    case 8: launch_num<8>(A, B, C, cap, s); break;
+    case 16: launch_num<16>(A, B, C, cap, s); break;
+    case 32: launch_num<32>(A, B, C, cap, s); break;
+    default: launch_num<64>(A, B, C, cap, s); break;
+  }
+  if (plan.max_row > cap)
+    k_spgemm_num_long<<<nblocks(A.nrows, 64), 64, 0, s>>>(A.rowptr, A.col, A.val, B.rowptr,
+                                                          B.col, B.val, C.rowptr, C.col, C.val,
+                                                          A.nrows, cap);
+}
+
+// ---------------------------------------------------------------------------
+// eq. (e:filtering): keep off-diagonal a_ij iff a_ij^2 > tau1^2 |a_ii a_jj|;
+// dropped entries lumped into the diagonal in ascending column order.
+// ---------------------------------------------------------------------------
+__global__ void k_diag(const int64_t* rp, const int32_t* col, const double* val, int64_t n,
+                       double* d) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double v = 0.0;
+  int64_t lo = rp[i], hi = rp[i + 1];
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (col[mid] < i) lo = mid + 1; else hi = mid;
+  }
+  if (lo < rp[i + 1] && col[lo] == i) v = val[lo];
+  d[i] = v;
+}
+
+void diag_of(const CsrView& A, double* d, hipStream_t s) {
+  if (A.nrows) k_diag<<<nblocks(A.nrows, 256), 256, 0, s>>>(A.rowptr, A.col, A.val, A.nrows, d);
+}
+
+__global__ void k_filter_count(const int64_t* rp, const int32_t* col, const double* val,
+                               int64_t n, double t2, const double* d, uint8_t* keep,
+                               int64_t* cnt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t c = 1;
+  const double di = d[i];
+  for (int64_t e = rp[i]; e < rp[i + 1]; e++) {
+    const int32_t j = col[e];
+    if (j == i) { keep[e] = 1; continue; }
+    const double v = val[e];
+    const double lhs = v * v;
+    const double rhs = t2 * fabs(di * d[j]);
+    const uint8_t k = lhs > rhs;
+    keep[e] = k;
+    c += k;
+  }
+  cnt[i + 1] = c;
+}
+
+__global__ void k_filter_fill(const int64_t* rp, const int32_t* col, const double* val, int64_t n,
+                              const uint8_t* keep, const double* d, const int64_t* orp,
+                              int32_t* ocol, double* oval) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double lump = d[i];
+  for (int64_t e = rp[i]; e < rp[i + 1]; e++)
+    if (col[e] != i && !keep[e]) lump = lump + val[e];
+  int64_t p = orp[i];
+  bool placed = false;
+  for (int64_t e = rp[i]; e < rp[i + 1]; e++) {
+    const int32_t j = col[e];
+    if (!placed && j > i) {
+      if (ocol) ocol[p] = (int32_t)i;
+      oval[p] = lump;
+      p++;
+      placed = true;
+    }
+    if (j == i) continue;
+    if (keep[e]) {
+      if (ocol) ocol[p] = j;
+      oval[p] = val[e];
+      p++;
+    }
+  }
+  if (!placed) {
+    if (ocol) ocol[p] = (int32_t)i;
+    oval[p] = lump;
+  }
+}
+
+void filter_symbolic(const CsrView& A, double tau1, const double* d, uint8_t* keep, Csr& At,
+                     hipStream_t s, Arena& ar) {
+  At.nrows = At.ncols = A.nrows;
+  At.rowptr = ar.alloc<int64_t>(A.nrows + 1);
+  const double t2 = tau1 * tau1;
+  if (A.nrows)
+    k_filter_count<<<nblocks(A.nrows, 256), 256, 0, s>>>(A.rowptr, A.col, A.val, A.nrows, t2, d,
+                                                          keep, At.rowptr);
+  At.nnz = rowptr_from_counts(At.rowptr, A.nrows, s, ar);
+  At.col = ar.alloc<int32_t>(At.nnz);
+  At.val = ar.alloc<double>(At.nnz);
+  if (A.nrows)
+    k_filter_fill<<<nblocks(A.nrows, 256), 256, 0, s>>>(A.rowptr, A.col, A.val, A.nrows, keep, d,
+                                                         At.rowptr, At.col, At.val);
+}
+
+void filter_numeric(const CsrView& A, const uint8_t* keep, const double* d, const Csr& At,
+                    hipStream_t s) {
+  if (A.nrows)
+    k_filter_fill<<<nblocks(A.nrows, 256), 256, 0, s>>>(A.rowptr, A.col, A.val, A.nrows, keep, d,
+                                                         At.rowptr, nullptr, At.val);
+}
+
+// ---------------------------------------------------------------------------
+// M = (A + A^T)/2 on the union pattern, m_ij = (a_ij + a_ji)*0.5
+// ---------------------------------------------------------------------------
+__global__ void k_union(const int64_t* arp, const int32_t* acol, const int64_t* trp,
+                        const int32_t* tcol, const int32_t* tsrc, int64_t n, int64_t* cnt,
+                        const int64_t* mrp, int32_t* mcol, int32_t* ia, int32_t* ib) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t a = arp[i], ae = arp[i + 1], b = trp[i], be = trp[i + 1];
+  int64_t p = mrp ? mrp[i] : 0, c = 0;
+  while (a < ae || b < be) {
+    int32_t j;
+    int32_t x = -1, y = -1;
+    if (b >= be || (a < ae && acol[a] < tcol[b])) { j = acol[a]; x = (int32_t)a; a++; }
+    else if (a >= ae || tcol[b] < acol[a]) { j = tcol[b]; y = tsrc[b]; b++; }
+    else { j = acol[a]; x = (int32_t)a; y = tsrc[b]; a++; b++; }
+    if (mcol) { mcol[p + c] = j; ia[p + c] = x; ib[p + c] = y; }
+    c++;
+  }
+  if (cnt) cnt[i + 1] = c;
+}
+
+__global__ void k_sym_vals(const double* aval, const int32_t* ia, const int32_t* ib, double* mval,
+                           int64_t nnz) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  const double x = ia[e] >= 0 ? aval[ia[e]] : 0.0;
+  const double y = ib[e] >= 0 ? aval[ib[e]] : 0.0;
+  mval[e] = (x + y) * 0.5;
+}
+
+void symmetrize_symbolic(const Csr& A, Csr& M, int32_t*& ia, int32_t*& ib, hipStream_t s,
+                         Arena& ar) {
+  Csr T;
+  int32_t* tsrc = nullptr;
+  transpose_pattern(view(A), T, tsrc, s, ar);
+  M.nrows = M.ncols = A.nrows;
+  M.rowptr = ar.alloc<int64_t>(A.nrows + 1);
+  if (A.nrows)
+    k_union<<<nblocks(A.nrows, 256), 256, 0, s>>>(A.rowptr, A.col, T.rowptr, T.col, tsrc,
+                                                   A.nrows, M.rowptr, nullptr, nullptr, nullptr,
+                                                   nullptr);
+  M.nnz = rowptr_from_counts(M.rowptr, A.nrows, s, ar);
+  M.col = ar.alloc<int32_t>(M.nnz);
+  M.val = ar.alloc<double>(M.nnz);
+  ia = ar.alloc<int32_t>(M.nnz);
+  ib = ar.alloc<int32_t>(M.nnz);
+  if (A.nrows)
+    k_union<<<nblocks(A.nrows, 256), 256, 0, s>>>(A.rowptr, A.col, T.rowptr, T.col, tsrc,
+                                                   A.nrows, nullptr, M.rowptr, M.col, ia, ib);
+}
+
+void symmetrize_numeric(const double* aval, const int32_t* ia, const int32_t* ib, Csr& M,
+                        hipStream_t s) {
+  if (M.nnz) k_sym_vals<<<nblocks(M.nnz, 256), 256, 0, s>>>(aval, ia, ib, M.val, M.nnz);
+}
+
+// a Dirichlet row has no nonzero off-diagonal value
+__global__ void k_dirichlet(const int64_t* rp, const int32_t* col, const double* val, int64_t n,
+                            uint8_t* dir) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint8_t d = 1;
+  for (int64_t e = rp[i]; e < rp[i + 1]; e++)
+    if (col[e] != i && val[e] != 0.0) d = 0;
+  dir[i] = d;
+}
+
+void dirichlet_rows(const CsrView& A, uint8_t* dir, hipStream_t s) {
+  if (A.nrows)
+    k_dirichlet<<<nblocks(A.nrows, 256), 256, 0, s>>>(A.rowptr, A.col, A.val, A.nrows, dir);
+}
+
+}  // namespace emin

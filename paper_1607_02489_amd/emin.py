@@ -1,0 +1,299 @@
+"""ctypes binding of libemin.so (the HIP C ABI in include/emin.h).
+
+Argument marshalling only: every step of the setup runs in the library's
+kernels.  PyTorch provides device memory (tensors) and the stream.  There is
+no CPU fallback: without the built library or a GPU, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libemin.so")
+
+EMIN_PREC_F64, EMIN_PREC_MIXED = 0, 1
+EMIN_FLAG_ENERGY, EMIN_FLAG_VALIDATE = 1, 2
+MAX_ITERS = 32
+(VIEW_PV, VIEW_PP, VIEW_AC, VIEW_BC, VIEW_MV, VIEW_MP, VIEW_S, VIEW_ORDER, VIEW_CP, VIEW_CBAR,
+ VIEW_CV, VIEW_XVC, VIEW_P2VC, VIEW_KEEPV, VIEW_KEEPP, VIEW_DIR) = range(16)
+STATUS = ["OK", "ERR_ARG", "ERR_SHAPE", "ERR_PATTERN", "ERR_VALUE", "ERR_INFEASIBLE",
+          "ERR_BREAKDOWN", "ERR_BUDGET", "ERR_DEVICE", "ERR_OOM", "ERR_CAPACITY", "ERR_COLOCATE"]
+SYMBOLS = ["emin_pattern", "emin_pattern_info", "emin_pattern_view", "emin_setup", "emin_rap",
+           "emin_sync_report", "emin_memcpy_d2h", "emin_pattern_destroy", "emin_status_string",
+           "emin_version", "emin_fp_probe"]
+
+
+class EminError(RuntimeError):
+    def __init__(self, status, where=""):
+        name = STATUS[status] if 0 <= status < len(STATUS) else str(status)
+        super().__init__(f"{where}: {name}")
+        self.status = status
+
+
+class c_csr(C.Structure):
+    _fields_ = [("nrows", C.c_int64), ("ncols", C.c_int64), ("nnz", C.c_int64),
+                ("rowptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p)]
+
+
+class c_system(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("Ahat", c_csr), ("Bdiv", c_csr), ("xv", C.c_void_p),
+                ("p2v", C.c_void_p), ("Wv", C.c_void_p), ("Wp", C.c_void_p)]
+
+
+class c_params(C.Structure):
+    _fields_ = [("tau1_v", C.c_double), ("tau1_p", C.c_double), ("tau2_sq", C.c_double),
+                ("iters", C.c_int32), ("precision", C.c_int32), ("flags", C.c_uint32)]
+
+
+class c_sizes(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in
+                ["n_v", "n_p", "n_vc", "n_pc", "n_cp_alg3", "n_cp_extra", "n_mid", "n_cv_extra",
+                 "nnz_Pv", "nnz_Pp", "nnz_Mv", "nnz_Mp", "nnz_Ac", "nnz_Bc", "device_bytes"]]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class c_report(C.Structure):
+    _fields_ = [("status", C.c_int32), ("its_v", C.c_int32), ("its_p", C.c_int32),
+                ("reserved", C.c_int32),
+                ("energy_v", C.c_double * (MAX_ITERS + 1)), ("energy_p", C.c_double * (MAX_ITERS + 1)),
+                ("rho_v", C.c_double * (MAX_ITERS + 1)), ("rho_p", C.c_double * (MAX_ITERS + 1)),
+                ("gamma_v", C.c_double * MAX_ITERS), ("gamma_p", C.c_double * MAX_ITERS)]
+
+
+class c_view(C.Structure):
+    _fields_ = [("n", C.c_int64), ("ncols", C.c_int64), ("nnz", C.c_int64),
+                ("rowptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p),
+                ("data", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libemin.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError(f"{LIBPATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIBPATH)
+        P = C.POINTER
+        L.emin_pattern.argtypes = [P(c_system), P(c_params), C.c_void_p, P(C.c_void_p)]
+        L.emin_pattern_info.argtypes = [C.c_void_p, P(c_sizes)]
+        L.emin_pattern_view.argtypes = [C.c_void_p, C.c_int32, P(c_view)]
+        L.emin_setup.argtypes = [C.c_void_p, P(c_system), P(c_params), C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_void_p]
+        L.emin_rap.argtypes = [C.c_void_p, P(c_system), C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.c_void_p]
+        L.emin_sync_report.argtypes = [C.c_void_p, C.c_void_p, P(c_report)]
+        L.emin_memcpy_d2h.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+        L.emin_pattern_destroy.argtypes = [C.c_void_p]
+        L.emin_pattern_destroy.restype = None
+        L.emin_status_string.argtypes = [C.c_int]
+        L.emin_status_string.restype = C.c_char_p
+        L.emin_version.restype = C.c_char_p
+        L.emin_fp_probe.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+        _lib = L
+    return _lib
+
+
+def _check(st, where):
+    if st != 0:
+        raise EminError(st, where)
+
+
+def params(tau1_v=0.06, tau1_p=0.06, tau2_sq=1.5e-3, iters=5, mixed=False, energy=False,
+           validate=False) -> c_params:
+    flags = (EMIN_FLAG_ENERGY if energy else 0) | (EMIN_FLAG_VALIDATE if validate else 0)
+    return c_params(tau1_v, tau1_p, tau2_sq, iters, EMIN_PREC_MIXED if mixed else EMIN_PREC_F64,
+                    flags)
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def d2h(ptr, n, dtype, stream=None) -> np.ndarray:
+    out = np.empty(int(n), dtype=dtype)
+    if n:
+        _check(lib().emin_memcpy_d2h(out.ctypes.data, C.c_void_p(ptr), out.nbytes,
+                                     _stream(stream)), "memcpy")
+    return out
+
+
+# ----------------------------------------------------------------------------
+@dataclass
+class DeviceSystem:
+    """A level's system in device memory (torch tensors or handle-owned views)."""
+    dim: int
+    n_v: int
+    n_p: int
+    A: tuple            # (nnz, rowptr_ptr, col_ptr, val_ptr)
+    B: tuple
+    xv: int
+    p2v: int
+    keep: list = field(default_factory=list)   # keeps tensors / handles alive
+
+    @staticmethod
+    def upload(sys, device="cuda") -> "DeviceSystem":
+        import torch
+        t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt)
+        Ar, Ac, Av = (t(sys.Ahat.rowptr, torch.int64), t(sys.Ahat.col, torch.int32),
+                      t(sys.Ahat.val, torch.float64))
+        Br, Bc, Bv = (t(sys.Bdiv.rowptr, torch.int64), t(sys.Bdiv.col, torch.int32),
+                      t(sys.Bdiv.val, torch.float64))
+        xv = t(sys.xv.reshape(-1), torch.float64)
+        p2v = t(sys.p2v, torch.int32)
+        return DeviceSystem(sys.dim, sys.n_v, sys.n_p,
+                            (sys.Ahat.nnz, Ar.data_ptr(), Ac.data_ptr(), Av.data_ptr()),
+                            (sys.Bdiv.nnz, Br.data_ptr(), Bc.data_ptr(), Bv.data_ptr()),
+                            xv.data_ptr(), p2v.data_ptr(), [Ar, Ac, Av, Br, Bc, Bv, xv, p2v])
+
+    def c(self) -> c_system:
+        A = c_csr(self.n_v, self.n_v, self.A[0], self.A[1], self.A[2], self.A[3])
+        B = c_csr(self.n_p, self.dim * self.n_v, self.B[0], self.B[1], self.B[2], self.B[3])
+        return c_system(self.dim, A, B, self.xv, self.p2v, None, None)
+
+
+class Pattern:
+    """emin_pattern handle of one level."""
+
+    def __init__(self, dsys: DeviceSystem, prm: c_params, stream=None):
+        self.dsys = dsys
+        self._c = dsys.c()
+        h = C.c_void_p()
+        _check(lib().emin_pattern(C.byref(self._c), C.byref(prm), _stream(stream), C.byref(h)),
+               "emin_pattern")
+        self.h = h
+        s = c_sizes()
+        _check(lib().emin_pattern_info(h, C.byref(s)), "emin_pattern_info")
+        self.sizes = s.as_dict()
+
+    def view(self, what) -> c_view:
+        v = c_view()
+        _check(lib().emin_pattern_view(self.h, what, C.byref(v)), "emin_pattern_view")
+        return v
+
+    def csr_host(self, what, vals=None):
+        """(rowptr, col, val) host copies of a CSR view; vals = device ptr."""
+        v = self.view(what)
+        rp = d2h(v.rowptr, v.n + 1, np.int64)
+        col = d2h(v.col, v.nnz, np.int32)
+        vp = vals if vals is not None else v.val
+        val = d2h(vp, v.nnz, np.float64) if vp else None
+        return v.n, v.ncols, rp, col, val
+
+    def array_host(self, what, dtype):
+        v = self.view(what)
+        return d2h(v.data, v.n, dtype)
+
+    def setup(self, prm: c_params, Pv, Pp, report=None, stream=None):
+        _check(lib().emin_setup(self.h, C.byref(self._c), C.byref(prm), C.c_void_p(Pv),
+                                C.c_void_p(Pp), _stream(stream),
+                                C.c_void_p(report) if report else None), "emin_setup")
+
+    def rap(self, Pv, Pp, Ac, Bc, stream=None):
+        _check(lib().emin_rap(self.h, C.byref(self._c), C.c_void_p(Pv), C.c_void_p(Pp),
+                              C.c_void_p(Ac), C.c_void_p(Bc), _stream(stream)), "emin_rap")
+
+    def coarse_system(self, Ac, Bc) -> DeviceSystem:
+        a, b = self.view(VIEW_AC), self.view(VIEW_BC)
+        x, p = self.view(VIEW_XVC), self.view(VIEW_P2VC)
+        s = self.sizes
+        return DeviceSystem(self.dsys.dim, s["n_vc"], s["n_pc"],
+                            (a.nnz, a.rowptr, a.col, Ac.data_ptr()),
+                            (b.nnz, b.rowptr, b.col, Bc.data_ptr()),
+                            x.data, p.data, [self, Ac, Bc])
+
+    def close(self):
+        if self.h:
+            lib().emin_pattern_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sync_report(rep_tensor, stream=None, raise_on_error=True) -> c_report:
+    r = c_report()
+    st = lib().emin_sync_report(C.c_void_p(rep_tensor.data_ptr()), _stream(stream), C.byref(r))
+    if st != 0 and raise_on_error:
+        raise EminError(st, "emin_sync_report")
+    return r
+
+
+def new_report(device="cuda"):
+    import torch
+    return torch.zeros(C.sizeof(c_report), dtype=torch.uint8, device=device)
+
+
+@dataclass
+class Level:
+    pattern: Pattern
+    Pv: object          # torch float64 tensors
+    Pp: object
+    Ac: object
+    Bc: object
+    report: object
+
+
+class Hierarchy:
+    """Alg. 1 without relaxation: nlevels levels (nlevels-1 transfers).
+
+    build() runs emin_pattern + emin_setup + emin_rap level by level;
+    resetup() reruns only the numeric phases (emin_setup + emin_rap) on the
+    stored patterns, as for a new Picard linearisation with the same structure.
+    """
+
+    def __init__(self, sys, nlevels, prm: c_params, min_dofs=0, device="cuda"):
+        self.fine = DeviceSystem.upload(sys, device)
+        self.nlevels = nlevels
+        self.prm = prm
+        self.min_dofs = min_dofs
+        self.device = device
+        self.levels: list[Level] = []
+
+    def build(self, stream=None):
+        import torch
+        self.levels = []
+        cur = self.fine
+        for _ in range(self.nlevels - 1):
+            if cur.dim * cur.n_v + cur.n_p <= self.min_dofs:
+                break
+            pat = Pattern(cur, self.prm, stream)
+            s = pat.sizes
+            f64 = dict(dtype=torch.float64, device=self.device)
+            L = Level(pat, torch.empty(max(s["nnz_Pv"], 1), **f64),
+                      torch.empty(max(s["nnz_Pp"], 1), **f64),
+                      torch.empty(max(s["nnz_Ac"], 1), **f64),
+                      torch.empty(max(s["nnz_Bc"], 1), **f64), new_report(self.device))
+            pat.setup(self.prm, L.Pv.data_ptr(), L.Pp.data_ptr(), L.report.data_ptr(), stream)
+            pat.rap(L.Pv.data_ptr(), L.Pp.data_ptr(), L.Ac.data_ptr(), L.Bc.data_ptr(), stream)
+            self.levels.append(L)
+            cur = pat.coarse_system(L.Ac, L.Bc)
+        self.coarsest = cur
+        return self
+
+    def resetup(self, stream=None):
+        for L in self.levels:
+            L.pattern.setup(self.prm, L.Pv.data_ptr(), L.Pp.data_ptr(), L.report.data_ptr(), stream)
+            L.pattern.rap(L.Pv.data_ptr(), L.Pp.data_ptr(), L.Ac.data_ptr(), L.Bc.data_ptr(),
+                          stream)
+
+    def p_nnz(self):
+        return sum(L.pattern.sizes["nnz_Pv"] + L.pattern.sizes["nnz_Pp"] for L in self.levels)
+
+    def close(self):
+        for L in reversed(self.levels):
+            L.pattern.close()
+        self.levels = []
