@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""EMIN-AMG setup benchmark on one MI355X.
+
+A step is one pass of the whole hot path over one synthetic Q2-Q1 system:
+for every level of the hierarchy, emin_pattern (aux operators, Alg. 3,
+Alg. 4, patterns, symbolic RAP), emin_setup (constrained CG) and emin_rap.
+The inputs are resident in device memory before the timed region.
+
+Metric: P-nnz * iterations per second, counting the computed entries
+sum over levels of (nnz(Pv) + nnz(Pp)) times the CG iterations.
+The JSON line also carries the live roofline of the masked product (HIP
+events around its launches, algorithmic bytes per launch), the incremental
+(numeric-only) setup rate, p50/p99 step latency, and the CPU oracle's rate on
+the same workload as a reported baseline.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # 2-D Oseen (Picard), 256x256 Q2-Q1, Re=100, 4-level FP64 hierarchy, 5 steps/level
+    "oseen2d_256": dict(make=lambda s: s.oseen2d(256), nlevels=4, iters=5, tau1_v=0.06,
+                        tau1_p=0.06, mixed=False, min_dofs=0,
+                        desc="2-D Oseen Q2-Q1 256x256, Re=100, 4-level FP64 hierarchy, 5 EMIN CG steps per level"),
+    # 3-D Stokes 48^3 Q2-Q1, jitter 0.05h; 3-D drop tolerances
+    "stokes3d_48": dict(make=lambda s: s.stokes3d(48), nlevels=4, iters=5, tau1_v=0.038,
+                        tau1_p=0.04, mixed=False, min_dofs=1000,
+                        desc="3-D Stokes Q2-Q1 48^3, jitter 0.05h, hierarchy to <=1000 dofs, 5 EMIN CG steps per level"),
+    # 2-D Stokes 8x8 (smallest; parity case)
+    "stokes2d_8": dict(make=lambda s: s.stokes2d_small(), nlevels=2, iters=5, tau1_v=0.06,
+                       tau1_p=0.06, mixed=False, min_dofs=0,
+                       desc="2-D Stokes Q2-Q1 8x8, jitter 0.1h, one transfer, 5 EMIN CG steps"),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = min(len(xs) - 1, max(0, int(round(q / 100.0 * (len(xs) - 1)))))
+    return xs[k]
+
+
+def cpu_baseline(system, wl, seconds, p_nnz_iters):
+    """The oracle (single-threaded C, FP64) on the same workload, repeated
+    until `seconds` of CPU work have been spent."""
+    from oracle import oracle as O
+    times = []
+    t_end = time.perf_counter() + seconds
+    while True:
+        t0 = time.perf_counter()
+        O.hierarchy(system, wl["nlevels"], tau1_v=wl["tau1_v"], tau1_p=wl["tau1_p"],
+                    iters=wl["iters"], min_dofs=wl["min_dofs"])
+        times.append(time.perf_counter() - t0)
+        if time.perf_counter() >= t_end:
+            break
+    mean = sum(times) / len(times)
+    return dict(value=p_nnz_iters / mean, unit="P-nnz*iters/s", cores=1, kind="oracle",
+                sample=f"{len(times)} full hierarchy setups of the same workload "
+                       f"({sum(times):.1f} s of CPU work, mean {mean * 1e3:.0f} ms)",
+                ms_per_setup=mean * 1e3)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="oseen2d_256", choices=sorted(WORKLOADS))
+    ap.add_argument("--mixed", action="store_true", help="FP32 masked products, FP64 projection/scalars")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1607_02489_amd import emin as E
+    from paper_1607_02489_amd import synth
+
+    wl = WORKLOADS[args.workload]
+    mixed = args.mixed or wl["mixed"]
+    t0 = time.perf_counter()
+    system = wl["make"](synth)
+    log(f"[bench] generated {args.workload}: dofs={system.dofs} in {time.perf_counter() - t0:.1f}s")
+    torch.cuda.init()
+    prm = E.params(wl["tau1_v"], wl["tau1_p"], 1.5e-3, wl["iters"], mixed=mixed)
+    H = E.Hierarchy(system, wl["nlevels"], prm, min_dofs=wl["min_dofs"])
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+
+    for w in range(args.warmup):
+        H.build()
+        torch.cuda.synchronize()
+        H.close()
+        log(f"[bench] warmup {w + 1}/{args.warmup} done")
+
+    if not args.no_profile:
+        E.profile_enable(True)
+        E.profile_collect()
+    lat = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        H.build()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+        if k < args.steps - 1:
+            H.close()
+        log(f"[bench] step {k + 1}/{args.steps}: {lat[-1] * 1e3:.1f} ms")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    prof = E.profile_collect() if not args.no_profile else {}
+    E.profile_enable(False)
+
+    levels = [L.pattern.sizes for L in H.levels]
+    p_nnz = H.p_nnz()
+    p_nnz_iters = p_nnz * wl["iters"]
+    p_nnz_expanded = sum(system.dim * s["nnz_Pv"] + s["nnz_Pp"] for s in levels) * wl["iters"]
+    ms_per_step = elapsed / args.steps * 1e3
+    value = p_nnz_iters / (elapsed / args.steps)
+
+    # numeric-only re-setup on the stored patterns (a new Picard linearisation)
+    inc = []
+    for _ in range(max(3, args.steps)):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        H.resetup()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        inc.append(e0.elapsed_time(e1))
+    for L in H.levels:
+        E.sync_report(L.report)
+    inc_ms = sorted(inc)[len(inc) // 2]
+
+    roof = None
+    if "spmm" in prof:
+        sp = prof["spmm"]
+        avg_ms = sp["ms"] / sp["launches"]
+        bytes_per = sp["bytes"] / sp["launches"]
+        achieved = bytes_per / (avg_ms * 1e-3) / 1e9
+        roof = dict(kernel="masked_spmm (k_spmm)", bound="hbm", achieved=round(achieved, 1),
+                    peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=None, launches=sp["launches"], avg_us=round(avg_ms * 1e3, 2),
+                    algorithmic_bytes_per_launch=round(bytes_per),
+                    share_of_step=round(sp["ms"] / (elapsed * 1e3), 4))
+    breakdown = {k: dict(launches=v["launches"], ms_per_step=round(v["ms"] / args.steps, 3))
+                 for k, v in prof.items()}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"[bench] CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
+        cpu = cpu_baseline(system, wl, args.cpu_seconds, p_nnz_iters)
+
+    H.close()
+    out = {
+        "metric": "EMIN setup P-nnz*iters/s",
+        "value": value,
+        "unit": "P-nnz*iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if mixed else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": wl["desc"], "dofs": system.dofs,
+                   "levels": len(levels) + 1, "iters": wl["iters"], "tau1_v": wl["tau1_v"],
+                   "tau1_p": wl["tau1_p"], "tau2_sq": 1.5e-3,
+                   "precision": "mixed" if mixed else "fp64"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "p50_ms": pct(lat, 50) * 1e3,
+        "p99_ms": pct(lat, 99) * 1e3,
+        "p_nnz_iters": p_nnz_iters,
+        "p_nnz_iters_expanded_dxPv": p_nnz_expanded,
+        "incremental_setup": {"ms": inc_ms, "value": p_nnz_iters / (inc_ms * 1e-3),
+                              "what": "emin_setup + emin_rap on all levels, patterns reused"},
+        "kernel_ms_per_step": breakdown,
+        "level_sizes": [{k: s[k] for k in ("n_v", "n_p", "n_vc", "n_pc", "nnz_Pv", "nnz_Pp",
+                                             "nnz_Mv", "nnz_Mp", "nnz_Ac", "nnz_Bc")}
+                        for s in levels],
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -189,6 +189,29 @@ void emin_pattern_destroy(emin_pattern_t *h);
 const char *emin_status_string(emin_status s);
 const char *emin_version(void);
 
+/* Kernel-class profiling with HIP events recorded on the launch stream
+ * around each instrumented kernel.  Disabled by default.  collect
+ * synchronises on the recorded events, sums launches / device time (ms) /
+ * algorithmic bytes and flops per class into out[0..nkinds) (host array),
+ * and clears the records. */
+enum {
+  EMIN_PROF_SPMM = 0,       /* masked product Q = mask_N(M Z) */
+  EMIN_PROF_UPDATE = 1,     /* projection + CG update */
+  EMIN_PROF_SPGEMM = 2,     /* numeric sparse products (B B^T, RAP) */
+  EMIN_PROF_ALG3 = 3,       /* Alg. 3 greedy + extra points */
+  EMIN_PROF_ALG4 = 4,       /* Alg. 4 mid-points */
+  EMIN_PROF_VPAT = 5,       /* velocity pattern */
+  EMIN_PROF_N = 8
+};
+typedef struct {
+  int64_t launches;
+  double total_ms;
+  double bytes;
+  double flops;
+} emin_kstat_t;
+emin_status emin_profile_enable(int enable);
+emin_status emin_profile_collect(emin_kstat_t *out, int32_t nkinds);
+
 /* Test hook: out_sqrt[i] = sqrt(x[i]), out_rcp[i] = 1/x[i] computed by the
  * device exactly as the coarsening kernels compute them (IEEE-rounded, no
  * contraction), so a test can compare them bitwise with the host's.  n

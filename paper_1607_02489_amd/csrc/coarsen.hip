@@ -11,6 +11,7 @@
 // uses the same operations in the same order as the definition, with
 // contraction disabled, so the result is bit-identical to it.
 #include "coarsen.h"
+#include "prof.h"
 
 namespace emin {
 
@@ -418,6 +419,8 @@ void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar,
                (size_t)D.dcap * 4;
   HIP_OK(hipFuncSetAttribute((const void*)k_alg3, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)lds));
+  {
+  prof::Scope ps(s, EMIN_PROF_ALG3, 0.0);
   k_alg3<<<1, A3_BS, lds, s>>>(D);
   HIP_OK(hipGetLastError());
   double* ebar = ar.alloc<double>(n);
@@ -425,6 +428,7 @@ void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar,
   size_t lds2 = (size_t)D.ballcap * 4;
   k_extras<<<1, A3_BS, lds2, s>>>(D, ebar);
   HIP_OK(hipGetLastError());
+  }
   if (n) k_sort_s<<<nblocks(n, 256), 256, 0, s>>>(D);
   int32_t meta[4];
   HIP_OK(hipMemcpyAsync(meta, D.meta, sizeof(meta), hipMemcpyDeviceToHost, s));

@@ -9,6 +9,7 @@
 // reduction is a fixed two-level tree (block partials, then one block), and
 // the CG scalars (rho, gamma, alpha, beta, energy) never leave the device.
 #include "emin_cg.h"
+#include "prof.h"
 
 namespace emin {
 
@@ -327,8 +328,16 @@ static int64_t spmm_any(int g, int smax, const Csr& M, const TM* mval, const int
   }
 }
 
+// algorithmic bytes of one masked product: M (col + val) and row pointers,
+// the pattern's columns, X read once and Y written once
+static double spmm_bytes(const EminWork& w, const Csr& M, bool mixed) {
+  const double vb = mixed ? 4.0 : 8.0;
+  return (4.0 + vb) * (double)M.nnz + (4.0 + 2.0 * vb) * (double)w.nnz + 16.0 * (double)(w.n + 1);
+}
+
 int64_t masked_spmm(const EminWork& w, const Csr& M, const int64_t* nrp, const int32_t* ncol,
                     const double* X, double* Y, const double* D, double* part, hipStream_t s) {
+  prof::Scope ps(s, EMIN_PROF_SPMM, spmm_bytes(w, M, false));
   return spmm_any<double, double, double>(w.g, w.smax, M, M.val, nrp, ncol, X, Y, w.n, D, part,
                                           s);
 }
@@ -350,6 +359,7 @@ void run_emin(EminWork& w, const Csr& M, const float* Mf, const int64_t* nrp, co
   if (mixed) k_to_float<<<nblocks(nnz, 256), 256, 0, s>>>(w.Z, w.Zf, nnz);
   for (int it = 0; it < iters; it++) {
     if (mixed) {
+      prof::Scope ps(s, EMIN_PROF_SPMM, spmm_bytes(w, M, true));
       np = spmm_any<float, float, float>(w.g, w.smax, M, Mf, nrp, ncol, w.Zf, w.Qf, n, w.Z,
                                          w.part, s);
     } else {
@@ -357,6 +367,10 @@ void run_emin(EminWork& w, const Csr& M, const float* Mf, const int64_t* nrp, co
     }
     k_finalize<<<1, 1024, 0, s>>>(w.part, (int)np, w.sc, FIN_GAMMA, it, nullptr, nullptr,
                                   rp.gamma, rp.its, rp.status);
+    {
+    const double ub = (mixed ? 40.0 : 44.0) * (double)nnz + 20.0 * (double)n +
+                      (energy ? 16.0 * (double)nnz : 0.0);
+    prof::Scope pu(s, EMIN_PROF_UPDATE, ub);
     if (mixed)
       k_update<float><<<nblocks(n, RB), RB, 0, s>>>(nrp, ncol, n, cid, w.Wc, w.G, w.Z, w.Qf, P,
                                                      w.R, energy ? w.MP : nullptr, w.sc, w.part,
@@ -365,6 +379,7 @@ void run_emin(EminWork& w, const Csr& M, const float* Mf, const int64_t* nrp, co
       k_update<double><<<nblocks(n, RB), RB, 0, s>>>(nrp, ncol, n, cid, w.Wc, w.G, w.Z, w.Q, P,
                                                       w.R, energy ? w.MP : nullptr, w.sc, w.part,
                                                       energy ? w.part_e : nullptr);
+    }
     k_finalize<<<1, 1024, 0, s>>>(w.part, (int)nblocks(n, RB), w.sc, FIN_RHO, it, nullptr, rp.rho,
                                   nullptr, nullptr, nullptr);
     if (energy)

@@ -10,6 +10,7 @@
 // each entry's dependence on the earlier entries of its chunk is a 64-bit
 // mask, resolved in lane order.
 #include "coarsen.h"
+#include "prof.h"
 
 namespace emin {
 
@@ -190,7 +191,10 @@ int64_t midpoints(const Csr& S, const uint8_t* st, const double* x, int dim, dou
   if ((int64_t)lds > lds_max) throw Error(EMIN_ERR_CAPACITY, "alg4: C-bar bitmap exceeds LDS");
   HIP_OK(hipFuncSetAttribute((const void*)k_mid_decide,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  k_mid_decide<<<1, 64, lds, s>>>(order, norder, m, tcnt, tlist, st, n, cbar);
+  {
+    prof::Scope ps(s, EMIN_PROF_ALG4, 0.0);
+    k_mid_decide<<<1, 64, lds, s>>>(order, norder, m, tcnt, tlist, st, n, cbar);
+  }
   HIP_OK(hipGetLastError());
   unsigned long long* c = ar.alloc<unsigned long long>(2);
   HIP_OK(hipMemsetAsync(c, 0, 2 * sizeof(unsigned long long), s));

@@ -1,0 +1,82 @@
+// HIP-event profiler of kernel classes (see prof.h).
+#include "prof.h"
+
+#include <mutex>
+
+namespace emin {
+namespace prof {
+namespace {
+
+struct Rec {
+  int kind;
+  double bytes, flops;
+  hipEvent_t e0, e1;
+};
+
+std::mutex mu;
+bool on = false;
+std::vector<Rec> recs;
+std::vector<hipEvent_t> pool;
+
+hipEvent_t get_event() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIP_OK(hipEventCreate(&e));
+  return e;
+}
+
+}  // namespace
+
+bool enabled() { return on; }
+
+int begin(hipStream_t s, int kind, double bytes, double flops) {
+  std::lock_guard<std::mutex> g(mu);
+  Rec r{kind, bytes, flops, get_event(), get_event()};
+  HIP_OK(hipEventRecord(r.e0, s));
+  recs.push_back(r);
+  return (int)recs.size() - 1;
+}
+
+void end(int token, hipStream_t s) {
+  std::lock_guard<std::mutex> g(mu);
+  if (token >= 0 && token < (int)recs.size()) (void)hipEventRecord(recs[token].e1, s);
+}
+
+}  // namespace prof
+}  // namespace emin
+
+extern "C" {
+
+emin_status emin_profile_enable(int enable) {
+  std::lock_guard<std::mutex> g(emin::prof::mu);
+  emin::prof::on = enable != 0;
+  return EMIN_OK;
+}
+
+emin_status emin_profile_collect(emin_kstat_t* out, int32_t nkinds) {
+  if (!out || nkinds <= 0) return EMIN_ERR_ARG;
+  using namespace emin::prof;
+  std::lock_guard<std::mutex> g(mu);
+  for (int k = 0; k < nkinds; k++) out[k] = emin_kstat_t{0, 0.0, 0.0, 0.0};
+  for (Rec& r : recs) {
+    if (hipEventSynchronize(r.e1) != hipSuccess) return EMIN_ERR_DEVICE;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.e0, r.e1) != hipSuccess) return EMIN_ERR_DEVICE;
+    if (r.kind >= 0 && r.kind < nkinds) {
+      out[r.kind].launches += 1;
+      out[r.kind].total_ms += ms;
+      out[r.kind].bytes += r.bytes;
+      out[r.kind].flops += r.flops;
+    }
+    pool.push_back(r.e0);
+    pool.push_back(r.e1);
+  }
+  recs.clear();
+  return EMIN_OK;
+}
+
+}  // extern "C"

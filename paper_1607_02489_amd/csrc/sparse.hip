@@ -1,6 +1,7 @@
 // Sparse building blocks: scans, transposes, the ordered row-wise SpGEMM,
 // and the drop/lump filter of eq. (e:filtering) with its symmetrisation.
 #include "common.h"
+#include "prof.h"
 
 namespace emin {
 
@@ -406,6 +407,9 @@ static void launch_num(const CsrView& A, const CsrView& B, const Csr& C, int cap
 void spgemm_numeric(const CsrView& A, const CsrView& B, const Csr& C, const SpgemmPlan& plan,
                     hipStream_t s) {
   if (A.nrows == 0 || C.nnz == 0) return;
+  prof::Scope ps(s, EMIN_PROF_SPGEMM,
+                 12.0 * (double)A.nnz + 12.0 * (double)B.nnz + 12.0 * (double)C.nnz +
+                     16.0 * (double)A.nrows);
   const int g = plan.g_num;
   const int NG = 256 / g;
   // LDS budget ~96 KiB per block

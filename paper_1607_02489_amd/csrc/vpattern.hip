@@ -8,6 +8,7 @@
 // show.  Extra C^(v) points (non-Dirichlet F nodes with no C^(v) within
 // distance 3) are taken in ascending order by a single workgroup.
 #include "coarsen.h"
+#include "prof.h"
 
 namespace emin {
 
@@ -229,6 +230,7 @@ void velocity_pattern(const Csr& G, const uint8_t* dir, uint8_t* cv, VPatternOut
   if (ballcap * 4 + 64 > lds_max) ballcap = (lds_max - 64) / 4;
   HIP_OK(hipFuncSetAttribute((const void*)k_vextras, hipFuncAttributeMaxDynamicSharedMemorySize,
                              ballcap * 4));
+  prof::Scope ps(s, EMIN_PROF_VPAT, 0.0);
   k_vextras<<<1, 1024, (size_t)ballcap * 4, s>>>(G.rowptr, G.col, n, dir, cv, cov, vis, extra,
                                                   nextra, ballcap, deg_cap, err);
   HIP_OK(hipGetLastError());

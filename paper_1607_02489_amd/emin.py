@@ -24,7 +24,8 @@ STATUS = ["OK", "ERR_ARG", "ERR_SHAPE", "ERR_PATTERN", "ERR_VALUE", "ERR_INFEASI
           "ERR_BREAKDOWN", "ERR_BUDGET", "ERR_DEVICE", "ERR_OOM", "ERR_CAPACITY", "ERR_COLOCATE"]
 SYMBOLS = ["emin_pattern", "emin_pattern_info", "emin_pattern_view", "emin_setup", "emin_rap",
            "emin_sync_report", "emin_memcpy_d2h", "emin_pattern_destroy", "emin_status_string",
-           "emin_version", "emin_fp_probe"]
+           "emin_version", "emin_fp_probe", "emin_profile_enable", "emin_profile_collect"]
+PROF_KINDS = ["spmm", "update", "spgemm", "alg3", "alg4", "vpattern", "r6", "r7"]
 
 
 class EminError(RuntimeError):
@@ -66,6 +67,11 @@ class c_report(C.Structure):
                 ("gamma_v", C.c_double * MAX_ITERS), ("gamma_p", C.c_double * MAX_ITERS)]
 
 
+class c_kstat(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double), ("bytes", C.c_double),
+                ("flops", C.c_double)]
+
+
 class c_view(C.Structure):
     _fields_ = [("n", C.c_int64), ("ncols", C.c_int64), ("nnz", C.c_int64),
                 ("rowptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p),
@@ -98,6 +104,8 @@ def lib():
         L.emin_status_string.restype = C.c_char_p
         L.emin_version.restype = C.c_char_p
         L.emin_fp_probe.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+        L.emin_profile_enable.argtypes = [C.c_int]
+        L.emin_profile_collect.argtypes = [P(c_kstat), C.c_int32]
         _lib = L
     return _lib
 
@@ -222,6 +230,17 @@ class Pattern:
             self.close()
         except Exception:
             pass
+
+
+def profile_enable(on=True):
+    _check(lib().emin_profile_enable(1 if on else 0), "emin_profile_enable")
+
+
+def profile_collect() -> dict:
+    arr = (c_kstat * len(PROF_KINDS))()
+    _check(lib().emin_profile_collect(arr, len(PROF_KINDS)), "emin_profile_collect")
+    return {k: dict(launches=int(a.launches), ms=float(a.total_ms), bytes=float(a.bytes),
+                    flops=float(a.flops)) for k, a in zip(PROF_KINDS, arr) if a.launches}
 
 
 def sync_report(rep_tensor, stream=None, raise_on_error=True) -> c_report:
