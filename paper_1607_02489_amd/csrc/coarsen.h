@@ -16,17 +16,18 @@ struct CoarsenArgs {
   uint8_t* st = nullptr;          // ST_*
   int32_t* cnt = nullptr;         // C points within distance 4
   double* rs = nullptr;           // sum of 1/|x_j - x_c| over those C points
-  int32_t* vis = nullptr;         // BFS stamps
   int32_t* s_cnt = nullptr;       // |S_j|
   int32_t* s_c = nullptr;         // S_j entries (n*scap), insertion order until sorted
   uint8_t* s_d = nullptr;         // their graph distances
   int scap = 32;
   int32_t* order = nullptr;       // C points in selection order
-  int32_t* meta = nullptr;        // [0] |C|, [1] |C| of Alg. 3, [2] error bits, [3] stamp
-  int deg_cap = 8;
+  int32_t* meta = nullptr;        // [0] |C|, [1] |C| of Alg. 3, [2] error bits
+  const int32_t* balls = nullptr; // distance-4 balls (vertex | dist << 29), n*bmax
+  const int32_t* bsize = nullptr; // ball sizes
+  const int32_t* b3 = nullptr;    // entries at distance <= 3 (a prefix of the ball)
+  int bmax = 0;
   int vb = 64;                    // vertices per argmin block
   int nblk = 1;
-  int ballcap = 4096;
   int dcap = 1024;
 };
 

@@ -31,52 +31,92 @@ __device__ __forceinline__ bool lex_less(double ka, int32_t ia, double kb, int32
   return ka < kb || (ka == kb && ia < ib);
 }
 
-// Breadth-first search of the whole workgroup from src to `depth`.  Visited
-// vertices carry the stamp in vis[] (stamps increase, so no clearing).  The
-// ball is listed level by level; lvl_end[L] ends level L.
-__device__ int wg_bfs(const CoarsenArgs& D, int32_t src, int depth, int32_t stamp, int32_t* ball,
-                      int* lvl_end, int* nb_sh, int* err_sh) {
-  const int tid = threadIdx.x;
-  if (tid == 0) {
-    ball[0] = src;
-    atomicMax(&D.vis[src], stamp);
-    *nb_sh = 1;
-    lvl_end[0] = 1;
+// Every vertex's distance-4 ball, listed in BFS level order as
+// (vertex | distance << 29), computed once in parallel (one wave per vertex,
+// LDS hash set).  Each greedy step then reads the ball of its new C point in
+// one coalesced sweep instead of walking the graph.
+constexpr int BW = 4;          // waves per block
+constexpr int BHASH = 4096;    // LDS hash slots per wave
+constexpr int BLIST = 2048;    // ball capacity per wave
+constexpr int DSHIFT = 29;
+constexpr int32_t VMASK = (1 << DSHIFT) - 1;
+
+__device__ __forceinline__ uint32_t bhash(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+__global__ __launch_bounds__(64 * BW) void k_balls(const int64_t* grp, const int32_t* gcol,
+                                                   int64_t n, int depth, int32_t* bsize,
+                                                   int32_t* b3, int32_t* balls, int bmax,
+                                                   int* err) {
+  extern __shared__ int32_t lds_b[];
+  __shared__ int nb_all[BW];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t v0 = (int64_t)blockIdx.x * BW + w;
+  if (v0 >= n) return;
+  int32_t* hs = lds_b + w * (BHASH + BLIST);
+  int32_t* ball = hs + BHASH;
+  for (int t = lane; t < BHASH; t += 64) hs[t] = -1;
+  if (lane == 0) {
+    ball[0] = (int32_t)v0;
+    hs[bhash((uint32_t)v0) & (BHASH - 1)] = (int32_t)v0;
+    nb_all[w] = 1;
   }
-  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   int ls = 0, le = 1;
-  const int per = A3_BS / D.deg_cap;
+  int ends[5] = {1, 1, 1, 1, 1};
+  bool bad = false;
   for (int L = 0; L < depth; L++) {
-    for (int base = ls; base < le; base += per) {
-      const int f = base + tid / D.deg_cap;
-      const int slot = tid % D.deg_cap;
-      if (f < le) {
-        const int32_t v = ball[f];
-        const int64_t b = D.grp[v + 1];
-        for (int64_t e = D.grp[v] + slot; e < b; e += D.deg_cap) {
-          const int32_t w = D.gcol[e];
-          if (w == v) continue;
-          if (atomicMax(&D.vis[w], stamp) < stamp) {
-            const int p = atomicAdd(nb_sh, 1);
-            if (p < D.ballcap) ball[p] = w;
-            else atomicOr(err_sh, DERR_CAPACITY);
+    for (int f = ls + lane; f < le; f += 64) {
+      const int32_t v = ball[f];
+      for (int64_t e = grp[v]; e < grp[v + 1]; e++) {
+        const int32_t u = gcol[e];
+        if (u == v) continue;
+        uint32_t h = bhash((uint32_t)u) & (BHASH - 1);
+        int probes = 0;
+        while (true) {
+          const int32_t old = atomicCAS(&hs[h], -1, u);
+          if (old == -1) {
+            const int p = atomicAdd(&nb_all[w], 1);
+            if (p < BLIST) ball[p] = u; else bad = true;
+            break;
           }
+          if (old == u) break;
+          h = (h + 1) & (BHASH - 1);
+          if (++probes >= BHASH / 2) { bad = true; break; }
         }
       }
     }
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     ls = le;
-    le = min(*nb_sh, D.ballcap);
-    if (tid == 0) lvl_end[L + 1] = le;
-    __syncthreads();
+    le = min(nb_all[w], BLIST);
+    ends[L + 1] = le;
   }
-  return le;
-}
-
-__device__ __forceinline__ int level_of(int t, const int* lvl_end) {
-  int d = 0;
-  while (t >= lvl_end[d]) d++;
-  return d;
+  for (int L = depth + 1; L < 5; L++) ends[L] = le;
+  if (bad || le > bmax) {
+    if (lane == 0) atomicOr(err, DERR_CAPACITY);
+    return;
+  }
+  if (lane == 0) {
+    bsize[v0] = le;
+    b3[v0] = ends[3];
+  }
+  if (!balls) return;
+  int32_t* out = balls + v0 * (int64_t)bmax;
+  for (int t = lane; t < le; t += 64) {
+    int d = 0;
+    while (d < 4 && t >= ends[d]) d++;
+    out[t] = (int32_t)((uint32_t)ball[t] | ((uint32_t)d << DSHIFT));
+  }
 }
 
 __device__ __forceinline__ void s_append(const CoarsenArgs& D, int32_t v, int32_t c, int d,
@@ -103,13 +143,11 @@ __device__ __forceinline__ void mark_dirty(int b, uint32_t* dbits, int32_t* dlis
 
 __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
   extern __shared__ unsigned char lds_raw[];
-  int32_t* ball = reinterpret_cast<int32_t*>(lds_raw);
-  double* bkey = reinterpret_cast<double*>(ball + D.ballcap);
+  double* bkey = reinterpret_cast<double*>(lds_raw);
   int32_t* bidx = reinterpret_cast<int32_t*>(bkey + D.nblk);
   uint32_t* dbits = reinterpret_cast<uint32_t*>(bidx + D.nblk);
   int32_t* dlist = reinterpret_cast<int32_t*>(dbits + ((D.nblk + 31) / 32));
-  __shared__ int lvl_end[8];
-  __shared__ int nb_sh, err_sh, dn_sh, dall_sh, nc_sh, stamp_sh, cursor_sh, found_sh;
+  __shared__ int err_sh, dn_sh, dall_sh, nc_sh, cursor_sh, found_sh;
   __shared__ int32_t k_sh;
   __shared__ double wkey[A3_WAVES];
   __shared__ int32_t widx[A3_WAVES];
@@ -120,7 +158,7 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
   for (int b = tid; b < D.nblk; b += A3_BS) { bkey[b] = INF; bidx[b] = INT32_MAX; }
   for (int b = tid; b < (D.nblk + 31) / 32; b += A3_BS) dbits[b] = 0u;
   if (tid == 0) {
-    nb_sh = 0; err_sh = 0; dn_sh = 0; dall_sh = 0; nc_sh = 0; stamp_sh = 0; cursor_sh = 0;
+    err_sh = 0; dn_sh = 0; dall_sh = 0; nc_sh = 0; cursor_sh = 0;
     k_sh = n > 0 ? 0 : -1;   // Alg. 3's "arbitrary vertex": vertex 0
   }
   __syncthreads();
@@ -128,12 +166,13 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
   while (true) {
     const int32_t k = k_sh;
     if (k < 0) break;
-    const int32_t stamp = stamp_sh;
-    const int nb = wg_bfs(D, k, 4, stamp, ball, lvl_end, &nb_sh, &err_sh);
+    const int nb = D.bsize[k];
+    const int32_t* bl = D.balls + (int64_t)k * D.bmax;
     // S_j += {k} for dist <= 3; C/F/Cand update; update_heuristics
     for (int t = tid; t < nb; t += A3_BS) {
-      const int32_t v = ball[t];
-      const int d = level_of(t, lvl_end);
+      const int32_t e = bl[t];
+      const int32_t v = e & VMASK;
+      const int d = (int)((uint32_t)e >> DSHIFT);
       if (d <= 3) s_append(D, v, k, d, &err_sh);
       if (d >= 1) {
         const uint8_t s = D.st[v];
@@ -142,14 +181,12 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
         D.cnt[v] += 1;
         D.rs[v] = D.rs[v] + 1.0 / euclid(D.x, D.dim, v, k);
         mark_dirty(v / D.vb, dbits, dlist, D.dcap, &dn_sh, &dall_sh);
+      } else {
+        D.st[k] = ST_C;
+        D.order[nc_sh] = k;
+        nc_sh++;
+        mark_dirty(k / D.vb, dbits, dlist, D.dcap, &dn_sh, &dall_sh);
       }
-    }
-    if (tid == 0) {
-      D.st[k] = ST_C;
-      D.order[nc_sh] = k;
-      nc_sh++;
-      stamp_sh = stamp + 1;
-      mark_dirty(k / D.vb, dbits, dlist, D.dcap, &dn_sh, &dall_sh);
     }
     __syncthreads();
     // refresh the minima of the touched blocks
@@ -185,7 +222,8 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
       int32_t ii = INT32_MAX;
       for (int w = 0; w < A3_WAVES; w++)
         if (lex_less(wkey[w], widx[w], kk, ii)) { kk = wkey[w]; ii = widx[w]; }
-      k_sh = (ii == INT32_MAX) ? -2 : ii;
+      // an error ends the loop for every thread at the same point
+      k_sh = err_sh ? -1 : ((ii == INT32_MAX) ? -2 : ii);
       found_sh = INT32_MAX;
     }
     __syncthreads();
@@ -206,14 +244,12 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
       }
       __syncthreads();
     }
-    if (err_sh) break;
   }
   __syncthreads();
   if (tid == 0) {
     D.meta[0] = nc_sh;
     D.meta[1] = nc_sh;
     D.meta[2] |= err_sh;
-    D.meta[3] = stamp_sh;
   }
 }
 
@@ -273,15 +309,11 @@ __device__ bool extra_pred(const CoarsenArgs& D, const double* ebar, int pass, i
 // converted, so the next conversion is the smallest vertex at or after the
 // cursor whose predicate holds now; the workgroup finds it 1024 at a time.
 __global__ __launch_bounds__(A3_BS) void k_extras(CoarsenArgs D, const double* ebar) {
-  extern __shared__ unsigned char lds_raw[];
-  int32_t* ball = reinterpret_cast<int32_t*>(lds_raw);
-  __shared__ int lvl_end[8];
-  __shared__ int nb_sh, err_sh, found_sh, nc_sh, stamp_sh;
+  __shared__ int err_sh, found_sh, nc_sh;
   const int tid = threadIdx.x;
   if (tid == 0) {
     err_sh = 0;
     nc_sh = D.meta[0];
-    stamp_sh = D.meta[3];
   }
   __syncthreads();
   for (int pass = 1; pass <= 2; pass++) {
@@ -299,15 +331,18 @@ __global__ __launch_bounds__(A3_BS) void k_extras(CoarsenArgs D, const double* e
       }
       const int j = found_sh;
       if (j == INT32_MAX) break;
+      // j becomes C and joins the S set of every vertex within distance 3
+      const int n3 = D.b3[j];
+      const int32_t* bl = D.balls + (int64_t)j * D.bmax;
+      for (int t = tid; t < n3; t += A3_BS) {
+        const int32_t e = bl[t];
+        s_append(D, e & VMASK, j, (int)((uint32_t)e >> DSHIFT), &err_sh);
+      }
       if (tid == 0) {
         D.st[j] = ST_C;
         D.order[nc_sh] = j;
         nc_sh++;
       }
-      const int32_t stamp = stamp_sh;
-      const int nb = wg_bfs(D, j, 3, stamp, ball, lvl_end, &nb_sh, &err_sh);
-      for (int t = tid; t < nb; t += A3_BS) s_append(D, ball[t], j, level_of(t, lvl_end), &err_sh);
-      if (tid == 0) stamp_sh = stamp + 1;
       __syncthreads();
       cursor = (int64_t)j + 1;
       if (err_sh) break;
@@ -318,7 +353,6 @@ __global__ __launch_bounds__(A3_BS) void k_extras(CoarsenArgs D, const double* e
   if (tid == 0) {
     D.meta[0] = nc_sh;
     D.meta[2] |= err_sh;
-    D.meta[3] = stamp_sh;
   }
 }
 
@@ -390,7 +424,6 @@ void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar,
   D.st = ar.alloc<uint8_t>(n);
   D.cnt = ar.alloc<int32_t>(n);
   D.rs = ar.alloc<double>(n);
-  D.vis = ar.alloc<int32_t>(n);
   D.s_cnt = ar.alloc<int32_t>(n);
   D.s_c = ar.alloc<int32_t>((size_t)n * D.scap);
   D.s_d = ar.alloc<uint8_t>((size_t)n * D.scap);
@@ -399,24 +432,37 @@ void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar,
   HIP_OK(hipMemsetAsync(D.st, 0, n, s));
   HIP_OK(hipMemsetAsync(D.cnt, 0, sizeof(int32_t) * n, s));
   HIP_OK(hipMemsetAsync(D.rs, 0, sizeof(double) * n, s));
-  HIP_OK(hipMemsetAsync(D.vis, 0xFF, sizeof(int32_t) * n, s));
   HIP_OK(hipMemsetAsync(D.s_cnt, 0, sizeof(int32_t) * n, s));
   HIP_OK(hipMemsetAsync(D.meta, 0, sizeof(int32_t) * 4, s));
-  int64_t maxdeg = max_row_len(D.grp, n, s, ar);
-  D.deg_cap = 1;
-  while (D.deg_cap < maxdeg && D.deg_cap < A3_BS) D.deg_cap <<= 1;
-  // LDS layout: ball | block keys | block idx | dirty bits | dirty list
-  D.ballcap = 4096;
-  D.dcap = 1024;
-  const int fixed = D.ballcap * 4 + D.dcap * 4 + 64;
+  // distance-4 balls of every vertex: sizes first, then the lists
+  int32_t* bsize = ar.alloc<int32_t>(n);
+  int32_t* b3 = ar.alloc<int32_t>(n);
+  const size_t blds = (size_t)BW * (BHASH + BLIST) * sizeof(int32_t);
+  HIP_OK(hipFuncSetAttribute((const void*)k_balls, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)blds));
+  if (n)
+    k_balls<<<nblocks(n, BW), 64 * BW, blds, s>>>(D.grp, D.gcol, n, 4, bsize, b3, nullptr, BLIST,
+                                                  D.meta + 2);
+  if (d2h(D.meta + 2, s) & DERR_CAPACITY) throw Error(EMIN_ERR_CAPACITY, "alg3: ball capacity");
+  const int64_t bmax = n ? max_row_len_i32(bsize, n, s, ar) : 1;
+  int32_t* balls = ar.alloc<int32_t>((size_t)n * bmax);
+  if (n)
+    k_balls<<<nblocks(n, BW), 64 * BW, blds, s>>>(D.grp, D.gcol, n, 4, bsize, b3, balls,
+                                                  (int)bmax, D.meta + 2);
+  D.balls = balls;
+  D.bsize = bsize;
+  D.b3 = b3;
+  D.bmax = (int)bmax;
+  // LDS layout: block keys | block idx | dirty bits | dirty list
+  D.dcap = 2048;
+  const int fixed = D.dcap * 4 + 64;
   int max_blocks = (lds_max - fixed) / 13;
   if (max_blocks < 64) throw Error(EMIN_ERR_CAPACITY, "alg3: LDS too small");
   D.vb = 64;
   while ((n + D.vb - 1) / D.vb > max_blocks) D.vb <<= 1;
   D.nblk = (int)((n + D.vb - 1) / D.vb);
   if (D.nblk < 1) D.nblk = 1;
-  size_t lds = (size_t)D.ballcap * 4 + (size_t)D.nblk * 12 + (size_t)((D.nblk + 31) / 32) * 4 +
-               (size_t)D.dcap * 4;
+  size_t lds = (size_t)D.nblk * 12 + (size_t)((D.nblk + 31) / 32) * 4 + (size_t)D.dcap * 4;
   HIP_OK(hipFuncSetAttribute((const void*)k_alg3, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)lds));
   {
@@ -425,8 +471,7 @@ void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar,
   HIP_OK(hipGetLastError());
   double* ebar = ar.alloc<double>(n);
   if (n) k_ebar<<<nblocks(n, 256), 256, 0, s>>>(D, ebar);
-  size_t lds2 = (size_t)D.ballcap * 4;
-  k_extras<<<1, A3_BS, lds2, s>>>(D, ebar);
+  k_extras<<<1, A3_BS, 0, s>>>(D, ebar);
   HIP_OK(hipGetLastError());
   }
   if (n) k_sort_s<<<nblocks(n, 256), 256, 0, s>>>(D);

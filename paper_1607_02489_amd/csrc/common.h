@@ -45,26 +45,40 @@ class Arena {
   Arena(const Arena&) = delete;
   Arena& operator=(const Arena&) = delete;
   ~Arena() { release(); }
+  // bump allocation from 64 MiB chunks (few hipMalloc calls per handle)
   template <class T>
   T* alloc(size_t n) {
-    void* p = nullptr;
     size_t b = (n ? n : 1) * sizeof(T);
     b = (b + 255) & ~size_t(255);
-    if (hipMalloc(&p, b) != hipSuccess) throw Error(EMIN_ERR_OOM, "hipMalloc failed");
-    ptrs_.push_back(p);
-    bytes_ += b;
-    return static_cast<T*>(p);
+    if (b > left_) {
+      const size_t chunk = b > kChunk ? b : kChunk;
+      void* p = nullptr;
+      if (hipMalloc(&p, chunk) != hipSuccess) throw Error(EMIN_ERR_OOM, "hipMalloc failed");
+      ptrs_.push_back(p);
+      bytes_ += chunk;
+      cur_ = static_cast<char*>(p);
+      left_ = chunk;
+    }
+    void* r = cur_;
+    cur_ += b;
+    left_ -= b;
+    return static_cast<T*>(r);
   }
   void release() {
     for (void* p : ptrs_) (void)hipFree(p);
     ptrs_.clear();
     bytes_ = 0;
+    cur_ = nullptr;
+    left_ = 0;
   }
   size_t bytes() const { return bytes_; }
 
  private:
+  static constexpr size_t kChunk = size_t(64) << 20;
   std::vector<void*> ptrs_;
   size_t bytes_ = 0;
+  char* cur_ = nullptr;
+  size_t left_ = 0;
 };
 
 // a CSR matrix in device memory (rowptr int64, col int32, val double/float)
@@ -99,6 +113,8 @@ inline T d2h(const T* p, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // longest row of a CSR (synchronises the stream)
 int64_t max_row_len(const int64_t* rp, int64_t n, hipStream_t s, Arena& ar);
+// largest value of a non-negative int32 array (synchronises the stream)
+int64_t max_row_len_i32(const int32_t* a, int64_t n, hipStream_t s, Arena& ar);
 // in-place inclusive scan of a[0..n)
 void scan_inclusive(int64_t* a, int64_t n, hipStream_t s, Arena& ar);
 // counts written to rowptr[1..n]; rowptr[0] = 0 set here; returns total

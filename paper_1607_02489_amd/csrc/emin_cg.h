@@ -26,7 +26,12 @@ struct EminWork {
   float *Zf = nullptr, *Qf = nullptr;
   double *part = nullptr, *part_e = nullptr;
   CgScalars* sc = nullptr;
+  // row bins of the masked product by pattern-row length: (0,4], (4,8], ..., (32,64]
+  static constexpr int NBIN = 5;
+  int32_t* bin_rows[NBIN] = {};
+  int64_t bin_n[NBIN] = {};
   void allocate(int64_t n, int64_t nnz, int64_t nc, Arena& ar, bool mixed);
+  void make_bins(const int64_t* nrp, hipStream_t s, Arena& ar);
 };
 
 // Y = mask_N(M X) with <D, Y> block partials (D may be NULL); returns the

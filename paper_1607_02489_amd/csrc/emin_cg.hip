@@ -61,60 +61,100 @@ __global__ void k_default_modes(const uint8_t* dir, int64_t n, double* W) {
   if (i < n) W[i] = dir ? (dir[i] ? 0.0 : 1.0) : 1.0;
 }
 
-// Y = mask_N(M X); optional dot partial of <D, Y> per block
-template <int G, int SMAX, class TM, class TX, class TY>
-__global__ __launch_bounds__(256) void k_spmm(const int64_t* mrp, const int32_t* mcol,
-                                              const TM* mval, const int64_t* nrp,
-                                              const int32_t* ncol, const TX* X, TY* Y,
-                                              int64_t n, const double* D, double* part) {
-  using TA = TM;  // accumulate in the operator's precision
+// XCD-aware block order: the hardware deals consecutive blocks round-robin to
+// the 8 XCDs; remapping gives every XCD one contiguous range of rows, so the
+// neighbour rows a block gathers are likely already in that XCD's L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+  const int64_t q = nb / 8, r = nb % 8, x = b % 8, j = b / 8;
+  return x * q + (x < r ? x : r) + j;
+}
+
+// Row-binned masked product: G lanes own one row i whose pattern has at most G
+// entries, lane s computing slot s (column j_s).  The group first stages M's
+// row i and the pattern-row bounds of its columns k across its lanes (two
+// coalesced loads), then walks the k's four at a time: the four pattern rows
+// (columns and X values, G entries each) are loaded together, and each lane
+// finds j_s among them by a binary search over the lanes.  Every slot sums
+// over k in ascending order, so results are deterministic.
+template <int G, class TX>
+__device__ __forceinline__ TX find_in_group(int32_t js, int32_t c, TX z, bool& hit) {
+  int pos = 0;
+#pragma unroll
+  for (int step = G / 2; step >= 1; step >>= 1) {
+    const int32_t cp = __shfl(c, pos + step - 1, G);
+    if (cp < js) pos += step;
+  }
+  const int32_t cf = __shfl(c, pos, G);
+  const TX zf = __shfl(z, pos, G);
+  hit = (cf == js);
+  return zf;
+}
+
+template <int G, class TM, class TX, class TY>
+__global__ __launch_bounds__(256) void k_spmm_bin(const int32_t* rows, int64_t nrows,
+                                                  const int64_t* mrp, const int32_t* mcol,
+                                                  const TM* mval, const int64_t* nrp,
+                                                  const int32_t* ncol, const TX* X, TY* Y,
+                                                  const double* D, double* part) {
+  using TA = TM;
   constexpr int NG = 256 / G;
+  constexpr int U = 4;
   __shared__ double lds[4];
+  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
   const int g = threadIdx.x / G, lane = threadIdx.x % G;
-  const int64_t i = (int64_t)blockIdx.x * NG + g;
+  const int64_t r = lb * NG + g;
   double dot = 0.0;
-  if (i < n) {
+  if (r < nrows) {
+    const int32_t i = rows[r];
     const int64_t na = nrp[i];
     const int ni = (int)(nrp[i + 1] - na);
-    int32_t my = (lane < ni) ? ncol[na + lane] : INT32_MAX;
-    int32_t cols[SMAX];
+    const int32_t js = lane < ni ? ncol[na + lane] : INT32_MAX;
+    const int64_t ma = mrp[i], mb = mrp[i + 1];
+    TA acc = TA(0);
+    for (int64_t e0 = ma; e0 < mb; e0 += G) {
+      const int64_t e = e0 + lane;
+      const bool ev = e < mb;
+      const int32_t kk = ev ? mcol[e] : 0;
+      const TA mvv = ev ? (TA)mval[e] : TA(0);
+      const int64_t ka = ev ? nrp[kk] : 0;
+      const int len = ev ? (int)(nrp[kk + 1] - ka) : 0;
+      const int cnt = (int)((mb - e0) < G ? (mb - e0) : G);
+      for (int q0 = 0; q0 < cnt; q0 += U) {
+        int32_t c[U];
+        TX z[U];
+        TA m[U];
+        int64_t a[U];
+        int l[U];
 #pragma unroll
-    for (int s = 0; s < SMAX; s++) cols[s] = __shfl(my, s % G, G);
-    if (SMAX > G) {
-      // rows longer than G: lanes hold slot s mod G; gather the rest directly
+        for (int u = 0; u < U; u++) {
+          const int q = q0 + u;
+          const bool qv = q < cnt;
+          a[u] = __shfl(ka, q, G);
+          l[u] = qv ? __shfl(len, q, G) : 0;
+          m[u] = __shfl(mvv, q, G);
+          const int64_t t = a[u] + lane;
+          c[u] = lane < l[u] ? ncol[t] : INT32_MAX;
+          z[u] = lane < l[u] ? X[t] : TX(0);
+        }
 #pragma unroll
-      for (int s = G; s < SMAX; s++) cols[s] = (s < ni) ? ncol[na + s] : INT32_MAX;
-    }
-    TA acc[SMAX];
-#pragma unroll
-    for (int s = 0; s < SMAX; s++) acc[s] = TA(0);
-    for (int64_t e = mrp[i] + lane; e < mrp[i + 1]; e += G) {
-      const int32_t k = mcol[e];
-      const TA mv = (TA)mval[e];
-      int64_t t = nrp[k];
-      const int64_t te = nrp[k + 1];
-#pragma unroll
-      for (int s = 0; s < SMAX; s++) {
-        if (s < ni) {
-          while (t < te && ncol[t] < cols[s]) t++;
-          if (t < te && ncol[t] == cols[s]) {
-            acc[s] = fma(mv, (TA)X[t], acc[s]);
-            t++;
+        for (int u = 0; u < U; u++) {
+          bool hit;
+          TX zf = find_in_group<G, TX>(js, c[u], z[u], hit);
+          for (int off = G; off < l[u]; off += G) {   // pattern row k longer than G (uniform)
+            const int64_t t = a[u] + off + lane;
+            const int32_t cc = off + lane < l[u] ? ncol[t] : INT32_MAX;
+            const TX zz = off + lane < l[u] ? X[t] : TX(0);
+            bool h2;
+            const TX z2 = find_in_group<G, TX>(js, cc, zz, h2);
+            if (h2 && !hit) { zf = z2; hit = true; }
           }
+          if (hit) acc = fma(m[u], (TA)zf, acc);
         }
       }
     }
-#pragma unroll
-    for (int s = 0; s < SMAX; s++) {
-#pragma unroll
-      for (int m = G / 2; m >= 1; m >>= 1) acc[s] += __shfl_xor(acc[s], m, G);
-    }
-#pragma unroll
-    for (int s = 0; s < SMAX; s++) {
-      if (s < ni && (s % G) == lane) {
-        Y[na + s] = (TY)acc[s];
-        if (D) dot += D[na + s] * (double)acc[s];
-      }
+    if (lane < ni) {
+      Y[na + lane] = (TY)acc;
+      if (D) dot = D[na + lane] * (double)acc;
     }
   }
   if (part) {
@@ -295,37 +335,62 @@ void EminWork::allocate(int64_t n_, int64_t nnz_, int64_t nc_, Arena& ar, bool m
   sc = ar.alloc<CgScalars>(1);
 }
 
-template <int G, int SMAX, class TM, class TX, class TY>
-static void spmm_launch(const Csr& M, const TM* mval, const int64_t* nrp, const int32_t* ncol,
-                        const TX* X, TY* Y, int64_t n, const double* D, double* part,
-                        hipStream_t s) {
-  constexpr int NG = 256 / G;
-  k_spmm<G, SMAX, TM, TX, TY><<<nblocks(n, NG), 256, 0, s>>>(M.rowptr, M.col, mval, nrp, ncol, X,
-                                                            Y, n, D, part);
+__global__ void k_bin_flags(const int64_t* nrp, int64_t n, int lo, int hi, int64_t* f) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t c = nrp[i + 1] - nrp[i];
+  f[i] = (c > lo && c <= hi) ? 1 : 0;
+}
+
+__global__ void k_bin_place(const int64_t* f, int64_t n, int32_t* rows) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t prev = i ? f[i - 1] : 0;
+  if (f[i] != prev) rows[prev] = (int32_t)i;
+}
+
+void EminWork::make_bins(const int64_t* nrp, hipStream_t s, Arena& ar) {
+  int64_t* f = ar.alloc<int64_t>(n);
+  int lo = 0;
+  for (int b = 0; b < NBIN; b++) {
+    const int hi = 4 << b;
+    bin_n[b] = 0;
+    bin_rows[b] = nullptr;
+    if (n) {
+      k_bin_flags<<<nblocks(n, 256), 256, 0, s>>>(nrp, n, lo, hi, f);
+      scan_inclusive(f, n, s, ar);
+      bin_n[b] = d2h(f + n - 1, s);
+      bin_rows[b] = ar.alloc<int32_t>(bin_n[b]);
+      if (bin_n[b]) k_bin_place<<<nblocks(n, 256), 256, 0, s>>>(f, n, bin_rows[b]);
+    }
+    lo = hi;
+  }
 }
 
 template <int G, class TM, class TX, class TY>
-static void spmm_smax(int smax, const Csr& M, const TM* mval, const int64_t* nrp,
-                      const int32_t* ncol, const TX* X, TY* Y, int64_t n, const double* D,
-                      double* part, hipStream_t s) {
-  if (smax <= 4) spmm_launch<G, 4>(M, mval, nrp, ncol, X, Y, n, D, part, s);
-  else if (smax <= 8) spmm_launch<G, 8>(M, mval, nrp, ncol, X, Y, n, D, part, s);
-  else if (smax <= 16) spmm_launch<G, 16>(M, mval, nrp, ncol, X, Y, n, D, part, s);
-  else if (smax <= 32) spmm_launch<G, 32>(M, mval, nrp, ncol, X, Y, n, D, part, s);
-  else spmm_launch<G, 64>(M, mval, nrp, ncol, X, Y, n, D, part, s);
+static int64_t bin_launch(const EminWork& w, int b, const Csr& M, const TM* mval,
+                          const int64_t* nrp, const int32_t* ncol, const TX* X, TY* Y,
+                          const double* D, double* part, hipStream_t s) {
+  constexpr int NG = 256 / G;
+  const int64_t nr = w.bin_n[b];
+  if (nr == 0) return 0;
+  const unsigned nb = nblocks(nr, NG);
+  k_spmm_bin<G, TM, TX, TY><<<nb, 256, 0, s>>>(w.bin_rows[b], nr, M.rowptr, M.col, mval, nrp,
+                                               ncol, X, Y, D, part);
+  return nb;
 }
 
 template <class TM, class TX, class TY>
-static int64_t spmm_any(int g, int smax, const Csr& M, const TM* mval, const int64_t* nrp,
-                        const int32_t* ncol, const TX* X, TY* Y, int64_t n, const double* D,
-                        double* part, hipStream_t s) {
-  switch (g) {
-    case 4: spmm_smax<4>(smax, M, mval, nrp, ncol, X, Y, n, D, part, s); return nblocks(n, 64);
-    case 8: spmm_smax<8>(smax, M, mval, nrp, ncol, X, Y, n, D, part, s); return nblocks(n, 32);
-    case 16: spmm_smax<16>(smax, M, mval, nrp, ncol, X, Y, n, D, part, s); return nblocks(n, 16);
-    case 32: spmm_smax<32>(smax, M, mval, nrp, ncol, X, Y, n, D, part, s); return nblocks(n, 8);
-    default: spmm_smax<64>(smax, M, mval, nrp, ncol, X, Y, n, D, part, s); return nblocks(n, 4);
-  }
+static int64_t spmm_any(const EminWork& w, const Csr& M, const TM* mval, const int64_t* nrp,
+                        const int32_t* ncol, const TX* X, TY* Y, const double* D, double* part,
+                        hipStream_t s) {
+  int64_t np = 0;
+  np += bin_launch<4>(w, 0, M, mval, nrp, ncol, X, Y, D, part ? part + np : nullptr, s);
+  np += bin_launch<8>(w, 1, M, mval, nrp, ncol, X, Y, D, part ? part + np : nullptr, s);
+  np += bin_launch<16>(w, 2, M, mval, nrp, ncol, X, Y, D, part ? part + np : nullptr, s);
+  np += bin_launch<32>(w, 3, M, mval, nrp, ncol, X, Y, D, part ? part + np : nullptr, s);
+  np += bin_launch<64>(w, 4, M, mval, nrp, ncol, X, Y, D, part ? part + np : nullptr, s);
+  return np;
 }
 
 // algorithmic bytes of one masked product: M (col + val) and row pointers,
@@ -338,8 +403,7 @@ static double spmm_bytes(const EminWork& w, const Csr& M, bool mixed) {
 int64_t masked_spmm(const EminWork& w, const Csr& M, const int64_t* nrp, const int32_t* ncol,
                     const double* X, double* Y, const double* D, double* part, hipStream_t s) {
   prof::Scope ps(s, EMIN_PROF_SPMM, spmm_bytes(w, M, false));
-  return spmm_any<double, double, double>(w.g, w.smax, M, M.val, nrp, ncol, X, Y, w.n, D, part,
-                                          s);
+  return spmm_any<double, double, double>(w, M, M.val, nrp, ncol, X, Y, D, part, s);
 }
 
 void run_emin(EminWork& w, const Csr& M, const float* Mf, const int64_t* nrp, const int32_t* ncol,
@@ -360,8 +424,7 @@ void run_emin(EminWork& w, const Csr& M, const float* Mf, const int64_t* nrp, co
   for (int it = 0; it < iters; it++) {
     if (mixed) {
       prof::Scope ps(s, EMIN_PROF_SPMM, spmm_bytes(w, M, true));
-      np = spmm_any<float, float, float>(w.g, w.smax, M, Mf, nrp, ncol, w.Zf, w.Qf, n, w.Z,
-                                         w.part, s);
+      np = spmm_any<float, float, float>(w, M, Mf, nrp, ncol, w.Zf, w.Qf, w.Z, w.part, s);
     } else {
       np = masked_spmm(w, M, nrp, ncol, w.Z, w.Q, w.Z, w.part, s);
     }

@@ -104,10 +104,45 @@ __global__ void k_place(const int32_t* key, const int64_t* incl, int64_t n, int3
   if (i < n && key[i] == val) order[base + incl[i] - 1] = (int32_t)i;
 }
 
-__global__ __launch_bounds__(64) void k_mid_decide(const int32_t* order, int64_t norder,
-                                                   const int32_t* m, const int32_t* tcnt,
-                                                   const int32_t* tlist, const uint8_t* st,
-                                                   int64_t n, uint8_t* cbar) {
+// per position p of the visiting order: m, T (padded with -1) and the mask
+// of earlier entries of the same 64-chunk whose m lies in T
+__global__ void k_mid_pack(const int32_t* order, int64_t norder, const int32_t* m,
+                           const int32_t* tcnt, const int32_t* tlist, int32_t* mo, int32_t* to,
+                           unsigned long long* dep) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= norder) return;
+  const int32_t i = order[p];
+  mo[p] = m[i];
+  const int tc = tcnt[i];
+  for (int t = 0; t < TCAP; t++) to[p * TCAP + t] = t < tc ? tlist[(int64_t)i * TCAP + t] : -1;
+  (void)dep;
+}
+
+__global__ void k_mid_dep(const int32_t* mo, const int32_t* to, int64_t norder,
+                          unsigned long long* dep) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= norder) return;
+  const int64_t base = p & ~int64_t(63);
+  int32_t T[TCAP];
+#pragma unroll
+  for (int t = 0; t < TCAP; t++) T[t] = to[p * TCAP + t];
+  unsigned long long d = 0ull;
+  for (int64_t q = base; q < p; q++) {
+    const int32_t mq = mo[q];
+#pragma unroll
+    for (int t = 0; t < TCAP; t++)
+      if (T[t] == mq) d |= 1ull << (q - base);
+  }
+  dep[p] = d;
+}
+
+// The ordered pass of Alg. 4 in one wave, 64 entries per chunk.  An entry is
+// rejected when some vertex of its T is in C-bar from an earlier chunk (LDS
+// bitmap) or is the m of an earlier accepted entry of its own chunk (its
+// dependence mask); the chunk is resolved in lane order with scalar code.
+__global__ __launch_bounds__(64) void k_mid_decide(const int32_t* mo, const int32_t* to,
+                                                   const unsigned long long* dep, int64_t norder,
+                                                   const uint8_t* st, int64_t n, uint8_t* cbar) {
   extern __shared__ uint32_t bits[];
   const int lane = threadIdx.x;
   const int64_t nw = (n + 31) / 32;
@@ -120,38 +155,44 @@ __global__ __launch_bounds__(64) void k_mid_decide(const int32_t* order, int64_t
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-  for (int64_t base = 0; base < norder; base += 64) {
-    const bool valid = base + lane < norder;
-    const int32_t i = valid ? order[base + lane] : 0;
-    const int32_t mi = valid ? m[i] : -1;
-    const int tc = valid ? tcnt[i] : 0;
-    int32_t T[TCAP];
+  // software pipeline: chunk c+1's entries load while chunk c resolves
+  int32_t T[TCAP], Tn[TCAP];
+  int32_t mi = -1, mn = -1;
+  unsigned long long dp = 0ull, dn = 0ull;
+  auto load = [&](int64_t base, int32_t* Tx, int32_t& mx, unsigned long long& dx) {
+    const int64_t p = base + lane;
+    const bool ok = p < norder;
 #pragma unroll
-    for (int t = 0; t < TCAP; t++) T[t] = (t < tc) ? tlist[(int64_t)i * TCAP + t] : -1;
-    bool pre = false;
+    for (int t = 0; t < TCAP; t++) Tx[t] = ok ? to[p * TCAP + t] : -1;
+    mx = ok ? mo[p] : -1;
+    dx = ok ? dep[p] : 0ull;
+  };
+  if (norder > 0) load(0, T, mi, dp);
+  for (int64_t base = 0; base < norder; base += 64) {
+    if (base + 64 < norder) load(base + 64, Tn, mn, dn);
+    const bool valid = base + lane < norder;
+    bool pre = !valid;
 #pragma unroll
     for (int t = 0; t < TCAP; t++)
-      if (T[t] >= 0 && (bits[T[t] >> 5] >> (T[t] & 31)) & 1u) pre = true;
-    uint64_t dep = 0ull;
+      if (T[t] >= 0 && ((bits[T[t] >> 5] >> (T[t] & 31)) & 1u)) pre = true;
+    const unsigned long long rejected = __ballot(pre);
+    const uint32_t dlo = (uint32_t)dp, dhi = (uint32_t)(dp >> 32);
+    unsigned long long accepted = 0ull;
     for (int l = 0; l < 64; l++) {
-      const int32_t ml = __shfl(mi, l, 64);
-      if (l < lane) {
-#pragma unroll
-        for (int t = 0; t < TCAP; t++)
-          if (T[t] >= 0 && T[t] == ml) dep |= 1ull << l;
-      }
-    }
-    uint64_t accepted = 0ull;
-    for (int l = 0; l < 64; l++) {
-      const int v = __shfl((int)valid, l, 64);
-      const int p = __shfl((int)pre, l, 64);
-      const uint64_t dl = __shfl(dep, l, 64);
-      if (v && !p && (dl & accepted) == 0ull) accepted |= 1ull << l;
+      if ((rejected >> l) & 1ull) continue;
+      const unsigned long long dl =
+          ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)dhi, l) << 32) |
+          (uint32_t)__builtin_amdgcn_readlane((int)dlo, l);
+      if ((dl & accepted) == 0ull) accepted |= 1ull << l;
     }
     if ((accepted >> lane) & 1ull) atomicOr(&bits[mi >> 5], 1u << (mi & 31));
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll
+    for (int t = 0; t < TCAP; t++) T[t] = Tn[t];
+    mi = mn;
+    dp = dn;
   }
   for (int64_t i = lane; i < n; i += 64) cbar[i] = (bits[i >> 5] >> (i & 31)) & 1u;
 }
@@ -191,9 +232,16 @@ int64_t midpoints(const Csr& S, const uint8_t* st, const double* x, int dim, dou
   if ((int64_t)lds > lds_max) throw Error(EMIN_ERR_CAPACITY, "alg4: C-bar bitmap exceeds LDS");
   HIP_OK(hipFuncSetAttribute((const void*)k_mid_decide,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  int32_t* mo = ar.alloc<int32_t>(norder);
+  int32_t* to = ar.alloc<int32_t>((size_t)norder * TCAP);
+  unsigned long long* dep = ar.alloc<unsigned long long>(norder);
+  if (norder) {
+    k_mid_pack<<<nblocks(norder, 256), 256, 0, s>>>(order, norder, m, tcnt, tlist, mo, to, dep);
+    k_mid_dep<<<nblocks(norder, 256), 256, 0, s>>>(mo, to, norder, dep);
+  }
   {
     prof::Scope ps(s, EMIN_PROF_ALG4, 0.0);
-    k_mid_decide<<<1, 64, lds, s>>>(order, norder, m, tcnt, tlist, st, n, cbar);
+    k_mid_decide<<<1, 64, lds, s>>>(mo, to, dep, norder, st, n, cbar);
   }
   HIP_OK(hipGetLastError());
   unsigned long long* c = ar.alloc<unsigned long long>(2);

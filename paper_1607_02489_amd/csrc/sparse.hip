@@ -125,21 +125,74 @@ __global__ void k_transpose_fill(const int64_t* rp, const int32_t* col, int64_t 
   }
 }
 
-// rows of the transpose are short: insertion sort restores ascending order
-__global__ void k_sort_segments(const int64_t* rp, int64_t n, int32_t* key, int32_t* src) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int64_t a = rp[i], b = rp[i + 1];
-  for (int64_t p = a + 1; p < b; p++) {
-    int32_t k = key[p], s = src[p];
-    int64_t q = p;
-    while (q > a && key[q - 1] > k) {
-      key[q] = key[q - 1];
-      src[q] = src[q - 1];
-      q--;
+// Restores ascending order inside each row of the transpose (the atomic fill
+// leaves it arbitrary).  A wave owns 64 consecutive rows: short rows are
+// insertion-sorted by their own lane; each long row is then rank-sorted by
+// the whole wave through LDS (keys are distinct within a row).
+constexpr int SORT_W = 4;
+constexpr int SORT_LDS = 1024;
+
+__global__ __launch_bounds__(64 * SORT_W) void k_sort_segments(const int64_t* rp, int64_t n,
+                                                               int32_t* key, int32_t* src) {
+  __shared__ int32_t tk_all[SORT_W][SORT_LDS];
+  __shared__ int32_t ts_all[SORT_W][SORT_LDS];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t base = ((int64_t)blockIdx.x * SORT_W + w) * 64;
+  const int64_t i = base + lane;
+  int64_t len = 0;
+  if (i < n) len = rp[i + 1] - rp[i];
+  const bool shortrow = len <= 16;
+  if (i < n && shortrow) {
+    const int64_t a = rp[i], b = rp[i + 1];
+    for (int64_t p = a + 1; p < b; p++) {
+      const int32_t k = key[p], s = src[p];
+      int64_t q = p;
+      while (q > a && key[q - 1] > k) {
+        key[q] = key[q - 1];
+        src[q] = src[q - 1];
+        q--;
+      }
+      key[q] = k;
+      src[q] = s;
     }
-    key[q] = k;
-    src[q] = s;
+  }
+  unsigned long long longs = __ballot(i < n && !shortrow);
+  int32_t* tk = tk_all[w];
+  int32_t* ts = ts_all[w];
+  while (longs) {
+    const int l = __builtin_ctzll(longs);
+    longs &= longs - 1;
+    const int64_t r = base + l;
+    const int64_t a = rp[r];
+    const int L = (int)(rp[r + 1] - a);
+    if (L <= SORT_LDS) {
+      for (int t = lane; t < L; t += 64) { tk[t] = key[a + t]; ts[t] = src[a + t]; }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      for (int t = lane; t < L; t += 64) {
+        const int32_t k = tk[t];
+        int rank = 0;
+        for (int u = 0; u < L; u++) rank += tk[u] < k;
+        key[a + rank] = k;
+        src[a + rank] = ts[t];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    } else if (lane == 0) {
+      for (int64_t p = a + 1; p < a + L; p++) {
+        const int32_t k = key[p], s = src[p];
+        int64_t q = p;
+        while (q > a && key[q - 1] > k) {
+          key[q] = key[q - 1];
+          src[q] = src[q - 1];
+          q--;
+        }
+        key[q] = k;
+        src[q] = s;
+      }
+    }
   }
 }
 
@@ -160,7 +213,8 @@ void transpose_pattern(const CsrView& A, Csr& At, int32_t*& src, hipStream_t s, 
     k_transpose_fill<<<nblocks(A.nrows, 256), 256, 0, s>>>(A.rowptr, A.col, A.nrows, cursor,
                                                             At.col, src);
   if (At.nrows)
-    k_sort_segments<<<nblocks(At.nrows, 256), 256, 0, s>>>(At.rowptr, At.nrows, At.col, src);
+    k_sort_segments<<<nblocks(At.nrows, 64 * SORT_W), 64 * SORT_W, 0, s>>>(At.rowptr, At.nrows,
+                                                                           At.col, src);
 }
 
 __global__ void k_gather(const double* in, const int32_t* src, double* out, int64_t n) {
@@ -185,73 +239,105 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
   return x;
 }
 
-template <int G>
-__global__ void k_spgemm_sym(const int64_t* arp, const int32_t* acol, const int64_t* brp,
-                             const int32_t* bcol, int64_t n, int hcap, int64_t* out_cnt,
-                             const int64_t* crp, int32_t* ccol, int* derr) {
+// Symbolic pass: a group of G lanes per output row inserts the columns
+// reached through A's row into an LDS open-addressing table.  Count mode
+// writes the row length; rows whose table would be more than half full are
+// appended to ovf (processed again with a larger table).  Fill mode compacts
+// the keys and writes them in ascending order (rank of each distinct key).
+template <int G, int BS>
+__global__ __launch_bounds__(BS) void k_spgemm_sym(const int32_t* rows, int64_t nrows,
+                                                   const int64_t* arp, const int32_t* acol,
+                                                   const int64_t* brp, const int32_t* bcol,
+                                                   int hcap, int64_t* out_cnt, const int64_t* crp,
+                                                   int32_t* ccol, int32_t* ovf, int* novf,
+                                                   int* derr) {
   extern __shared__ int32_t lds_keys[];
-  constexpr int NG = 256 / G;
-  __shared__ int32_t cnt[NG];
+  constexpr int NG = BS / G;
+  __shared__ int32_t cnt[NG], cnt2[NG], ovf_g[NG];
   const int g = threadIdx.x / G, lane = threadIdx.x % G;
-  int32_t* keys = lds_keys + (size_t)g * hcap;
-  const int64_t row = (int64_t)blockIdx.x * NG + g;
+  int32_t* keys = lds_keys + (size_t)g * (hcap + hcap / 2);
+  int32_t* dense = keys + hcap;
+  const int64_t r = (int64_t)blockIdx.x * NG + g;
+  const int64_t row = r < nrows ? (rows ? (int64_t)rows[r] : r) : -1;
   for (int t = lane; t < hcap; t += G) keys[t] = -1;
-  if (lane == 0) cnt[g] = 0;
+  if (lane == 0) { cnt[g] = 0; cnt2[g] = 0; ovf_g[g] = 0; }
   __syncthreads();
   const uint32_t mask = (uint32_t)hcap - 1u;
   bool overflow = false;
-  if (row < n) {
-    for (int64_t e = arp[row] + lane; e < arp[row + 1]; e += G) {
-      int32_t k = acol[e];
+  if (row >= 0) {
+    for (int64_t e = arp[row] + lane; e < arp[row + 1] && !overflow; e += G) {
+      const int32_t k = acol[e];
       for (int64_t f = brp[k]; f < brp[k + 1]; f++) {
-        int32_t j = bcol[f];
+        const int32_t j = bcol[f];
         uint32_t h = hash32((uint32_t)j) & mask;
         int probes = 0;
         while (true) {
-          int32_t old = atomicCAS(&keys[h], -1, j);
-          if (old == -1) { atomicAdd(&cnt[g], 1); break; }
+          const int32_t old = atomicCAS(&keys[h], -1, j);
+          if (old == -1) {
+            if (atomicAdd(&cnt[g], 1) >= hcap / 2) overflow = true;
+            break;
+          }
           if (old == j) break;
           h = (h + 1u) & mask;
           if (++probes >= hcap) { overflow = true; break; }
         }
         if (overflow) break;
       }
-      if (overflow) break;
     }
   }
+  if (overflow) atomicOr(&ovf_g[g], 1);
   __syncthreads();
-  if (overflow || (row < n && cnt[g] * 2 > hcap)) {
-    if (lane == 0) atomicOr(derr, DERR_CAPACITY);
-    return;
-  }
-  if (row >= n) return;
+  if (row < 0) return;
+  const bool over = ovf_g[g] != 0 || cnt[g] > hcap / 2;
   if (ccol == nullptr) {
-    if (lane == 0) out_cnt[row + 1] = cnt[g];
+    if (lane == 0) {
+      if (over) {
+        if (ovf) ovf[atomicAdd(novf, 1)] = (int32_t)row;
+        else atomicOr(derr, DERR_CAPACITY);
+      } else {
+        out_cnt[row + 1] = cnt[g];
+      }
+    }
     return;
   }
-  const int64_t base = crp[row];
+  if (over) {
+    // the caller redoes overflowed rows with a larger table; without that
+    // second pass (ovf == nullptr only there) this is an error
+    if (lane == 0 && ovf == nullptr && rows != nullptr) atomicOr(derr, DERR_CAPACITY);
+    return;
+  }
   for (int t = lane; t < hcap; t += G) {
-    int32_t key = keys[t];
-    if (key < 0) continue;
-    int32_t rank = 0;
-    for (int u = 0; u < hcap; u++) {
-      int32_t o = keys[u];
-      rank += (o >= 0 && o < key);
-    }
+    const int32_t key = keys[t];
+    if (key >= 0) dense[atomicAdd(&cnt2[g], 1)] = key;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  const int u = cnt[g];
+  const int64_t base = crp[row];
+  for (int t = lane; t < u; t += G) {
+    const int32_t key = dense[t];
+    int rank = 0;
+    for (int v = 0; v < u; v++) rank += dense[v] < key;
     ccol[base + rank] = key;
   }
 }
 
-// SpGEMM, numeric: G lanes per row; for each k of A's row in ascending order
-// the lanes take B's row k (distinct columns, so no two lanes meet), find
-// each column in the row's sorted output list held in LDS and accumulate.
+// Numeric pass: G lanes per output row.  A's row is staged across the lanes
+// (columns, values, and the bounds of the B rows they select), then the B
+// rows are taken four at a time with their loads in flight together.  Within
+// one B row the columns are distinct, so lanes never meet; across B rows the
+// order is ascending k.  Each product and each sum is rounded separately, so
+// c_ij is exactly sum_k a_ik*b_kj accumulated in ascending k.
 template <int G>
-__global__ void k_spgemm_num(const int64_t* arp, const int32_t* acol, const double* aval,
-                             const int64_t* brp, const int32_t* bcol, const double* bval,
-                             const int64_t* crp, const int32_t* ccol, double* cval, int64_t n,
-                             int cap) {
+__global__ __launch_bounds__(256) void k_spgemm_num(const int64_t* arp, const int32_t* acol,
+                                                   const double* aval, const int64_t* brp,
+                                                   const int32_t* bcol, const double* bval,
+                                                   const int64_t* crp, const int32_t* ccol,
+                                                   double* cval, int64_t n, int cap) {
   extern __shared__ unsigned char lds_raw[];
   constexpr int NG = 256 / G;
+  constexpr int U = 4;
   const int g = threadIdx.x / G, lane = threadIdx.x % G;
   double* acc = reinterpret_cast<double*>(lds_raw) + (size_t)g * cap;
   int32_t* cols = reinterpret_cast<int32_t*>(reinterpret_cast<double*>(lds_raw) + (size_t)NG * cap) +
@@ -268,22 +354,53 @@ __global__ void k_spgemm_num(const int64_t* arp, const int32_t* acol, const doub
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-  for (int64_t e = arp[row]; e < arp[row + 1]; e++) {
-    const int32_t k = acol[e];
-    const double a = aval[e];
-    for (int64_t f = brp[k] + lane; f < brp[k + 1]; f += G) {
-      const int32_t j = bcol[f];
-      int lo = 0, hi = nc;
-      while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (cols[mid] < j) lo = mid + 1; else hi = mid;
+  const int64_t ea = arp[row], eb = arp[row + 1];
+  for (int64_t e0 = ea; e0 < eb; e0 += G) {
+    const int64_t e = e0 + lane;
+    const bool ev = e < eb;
+    const int32_t kk = ev ? acol[e] : 0;
+    const double av = ev ? aval[e] : 0.0;
+    const int64_t kb0 = ev ? brp[kk] : 0;
+    const int kl = ev ? (int)(brp[kk + 1] - kb0) : 0;
+    const int cnt = (int)((eb - e0) < G ? (eb - e0) : G);
+    for (int q0 = 0; q0 < cnt; q0 += U) {
+      int32_t jj[U];
+      double bv[U], am[U];
+      int64_t b0[U];
+      int bl[U];
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        const int q = q0 + u;
+        b0[u] = __shfl(kb0, q, G);
+        bl[u] = q < cnt ? __shfl(kl, q, G) : 0;
+        am[u] = __shfl(av, q, G);
+        jj[u] = lane < bl[u] ? bcol[b0[u] + lane] : -1;
+        bv[u] = lane < bl[u] ? bval[b0[u] + lane] : 0.0;
       }
-      const double prod = a * bval[f];
-      acc[lo] = acc[lo] + prod;
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        for (int off = 0; off < bl[u]; off += G) {
+          int32_t j = jj[u];
+          double b = bv[u];
+          if (off > 0) {
+            j = off + lane < bl[u] ? bcol[b0[u] + off + lane] : -1;
+            b = off + lane < bl[u] ? bval[b0[u] + off + lane] : 0.0;
+          }
+          if (j >= 0) {
+            int lo = 0, hi = nc;
+            while (lo < hi) {
+              const int mid = (lo + hi) >> 1;
+              if (cols[mid] < j) lo = mid + 1; else hi = mid;
+            }
+            const double prod = am[u] * b;
+            acc[lo] = acc[lo] + prod;
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        }
+      }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   }
   for (int t = lane; t < nc; t += G) cval[c0 + t] = acc[t];
 }
@@ -335,30 +452,62 @@ int64_t max_row_len(const int64_t* rp, int64_t n, hipStream_t s, Arena& ar) {
   return (int64_t)d2h(mx, s);
 }
 
+__global__ void k_max_i32(const int32_t* a, int64_t n, unsigned long long* mx) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long v = (i < n) ? (unsigned long long)a[i] : 0ull;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    unsigned long long o = __shfl_xor(v, m, 64);
+    v = o > v ? o : v;
+  }
+  if ((threadIdx.x & 63) == 0) atomicMax(mx, v);
+}
+
+int64_t max_row_len_i32(const int32_t* a, int64_t n, hipStream_t s, Arena& ar) {
+  if (n <= 0) return 0;
+  unsigned long long* mx = ar.alloc<unsigned long long>(1);
+  HIP_OK(hipMemsetAsync(mx, 0, sizeof(unsigned long long), s));
+  k_max_i32<<<nblocks(n, 256), 256, 0, s>>>(a, n, mx);
+  return (int64_t)d2h(mx, s);
+}
+
 static int pick_g(double avg) {
   int g = 4;
   while (g < 64 && g < avg) g <<= 1;
   return g;
 }
 
-template <int G>
-static void launch_sym(const CsrView& A, const CsrView& B, int hcap, int64_t* cnt,
-                       const int64_t* crp, int32_t* ccol, int* derr, hipStream_t s) {
-  constexpr int NG = 256 / G;
-  size_t lds = (size_t)NG * hcap * sizeof(int32_t);
-  k_spgemm_sym<G><<<nblocks(A.nrows, NG), 256, lds, s>>>(A.rowptr, A.col, B.rowptr, B.col,
-                                                         A.nrows, hcap, cnt, crp, ccol, derr);
+template <int G, int BS>
+static void launch_sym(const int32_t* rows, int64_t nrows, const CsrView& A, const CsrView& B,
+                       int hcap, int64_t* cnt, const int64_t* crp, int32_t* ccol, int32_t* ovf,
+                       int* novf, int* derr, hipStream_t s) {
+  constexpr int NG = BS / G;
+  const size_t lds = (size_t)NG * (hcap + hcap / 2) * sizeof(int32_t);
+  HIP_OK(hipFuncSetAttribute((const void*)k_spgemm_sym<G, BS>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  k_spgemm_sym<G, BS><<<nblocks(nrows, NG), BS, lds, s>>>(rows, nrows, A.rowptr, A.col, B.rowptr,
+                                                          B.col, hcap, cnt, crp, ccol, ovf, novf,
+                                                          derr);
 }
 
-static void sym_dispatch(int g, const CsrView& A, const CsrView& B, int hcap, int64_t* cnt,
-                         const int64_t* crp, int32_t* ccol, int* derr, hipStream_t s) {
+static void sym_dispatch(int g, int64_t nrows, const CsrView& A, const CsrView& B, int hcap,
+                         int64_t* cnt, const int64_t* crp, int32_t* ccol, int32_t* ovf, int* novf,
+                         int* derr, hipStream_t s) {
   switch (g) {
-    case 4: launch_sym<4>(A, B, hcap, cnt, crp, ccol, derr, s); break;
-    case 8: launch_sym<8>(A, B, hcap, cnt, crp, ccol, derr, s); break;
-    case 16: launch_sym<16>(A, B, hcap, cnt, crp, ccol, derr, s); break;
-    case 32: launch_sym<32>(A, B, hcap, cnt, crp, ccol, derr, s); break;
-    default: launch_sym<64>(A, B, hcap, cnt, crp, ccol, derr, s); break;
+    case 4: launch_sym<4, 256>(nullptr, nrows, A, B, hcap, cnt, crp, ccol, ovf, novf, derr, s); break;
+    case 8: launch_sym<8, 256>(nullptr, nrows, A, B, hcap, cnt, crp, ccol, ovf, novf, derr, s); break;
+    case 16: launch_sym<16, 256>(nullptr, nrows, A, B, hcap, cnt, crp, ccol, ovf, novf, derr, s); break;
+    case 32: launch_sym<32, 256>(nullptr, nrows, A, B, hcap, cnt, crp, ccol, ovf, novf, derr, s); break;
+    default: launch_sym<64, 256>(nullptr, nrows, A, B, hcap, cnt, crp, ccol, ovf, novf, derr, s); break;
   }
+}
+
+// rows whose table overflowed: one 64-lane group per block, a large table
+static void sym_big(const int32_t* rows, int64_t nrows, const CsrView& A, const CsrView& B,
+                    int hcap, int64_t* cnt, const int64_t* crp, int32_t* ccol, int* derr,
+                    hipStream_t s) {
+  if (nrows)
+    launch_sym<64, 64>(rows, nrows, A, B, hcap, cnt, crp, ccol, nullptr, nullptr, derr, s);
 }
 
 void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& plan,
@@ -370,29 +519,36 @@ void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& pla
   HIP_OK(hipMemsetAsync(C.rowptr, 0, sizeof(int64_t) * (C.nrows + 1), s));
   const double avg_a = A.nrows ? (double)A.nnz / (double)A.nrows : 1.0;
   const int g = pick_g(avg_a);
-  const int64_t maxb = max_row_len(B.rowptr, B.nrows, s, ar);
-  int hcap = 32;
-  while (hcap < 2 * maxb && hcap < 1024) hcap <<= 1;
-  const int max_hcap = 65536 / (256 / g) / 4 * 2;  // per-group share of ~128 KiB
-  int* lerr = ar.alloc<int>(1);
-  while (true) {
-    HIP_OK(hipMemsetAsync(lerr, 0, sizeof(int), s));
-    if (A.nrows) sym_dispatch(g, A, B, hcap, C.rowptr, nullptr, nullptr, lerr, s);
-    int e = d2h(lerr, s);
-    if (!(e & DERR_CAPACITY)) break;
-    if (hcap >= max_hcap || hcap >= 16384)
-      throw Error(EMIN_ERR_CAPACITY, "spgemm: output row exceeds the LDS hash capacity");
-    hcap <<= 1;
-  }
+  const int NG = 256 / g;
+  // table per group within ~48 KiB per block (keys + compacted copy)
+  int hcap = 64;
+  while ((size_t)NG * 3 * hcap * sizeof(int32_t) <= 48 * 1024 && hcap < 4096) hcap <<= 1;
+  const int big = 16384;  // one 64-lane group, 96 KiB of LDS
+  int* lerr = ar.alloc<int>(2);
+  int32_t* ovf = ar.alloc<int32_t>(A.nrows);
+  HIP_OK(hipMemsetAsync(lerr, 0, 2 * sizeof(int), s));
+  if (A.nrows)
+    sym_dispatch(g, A.nrows, A, B, hcap, C.rowptr, nullptr, nullptr, ovf, lerr + 1, lerr, s);
+  int hl[2];
+  HIP_OK(hipMemcpyAsync(hl, lerr, sizeof(hl), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  const int nov = hl[1];
+  if (nov) sym_big(ovf, nov, A, B, big, C.rowptr, nullptr, nullptr, lerr, s);
   C.nnz = rowptr_from_counts(C.rowptr, C.nrows, s, ar);
+  if (d2h(lerr, s)) throw Error(EMIN_ERR_CAPACITY, "spgemm: output row exceeds the LDS table");
   C.col = ar.alloc<int32_t>(C.nnz);
   C.val = ar.alloc<double>(C.nnz);
-  HIP_OK(hipMemsetAsync(lerr, 0, sizeof(int), s));
-  if (A.nrows) sym_dispatch(g, A, B, hcap, nullptr, C.rowptr, C.col, lerr, s);
+  // the first fill skips the rows that overflowed; the big table redoes them
+  if (A.nrows)
+    sym_dispatch(g, A.nrows, A, B, hcap, nullptr, C.rowptr, C.col, ovf, lerr + 1, lerr, s);
+  if (nov) sym_big(ovf, nov, A, B, big, nullptr, C.rowptr, C.col, lerr, s);
   if (d2h(lerr, s)) throw Error(EMIN_ERR_CAPACITY, "spgemm: fill pass overflow");
   plan.max_row = max_row_len(C.rowptr, C.nrows, s, ar);
   const double avg_b = B.nrows ? (double)B.nnz / (double)B.nrows : 1.0;
-  plan.g_num = pick_g(avg_b);
+  int gn = pick_g(avg_b);
+  // enough lanes per row that the longest output row fits the LDS budget
+  while (gn < 64 && (size_t)(256 / gn) * plan.max_row * 12 > 96 * 1024) gn <<= 1;
+  plan.g_num = gn;
   (void)derr;
 }
 
