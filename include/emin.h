@@ -173,9 +173,12 @@ emin_status emin_setup(emin_pattern_t *h, const emin_system_t *sys, const emin_p
 /* Alg. 1 Galerkin product with R = P^T on the unfiltered operator:
  * Ac = Pv^T Ahat Pv (nnz_Ac values) and Bc = Pp^T Bdiv (I_d (x) Pv)
  * (nnz_Bc values), written into caller buffers on the handle's coarse
- * patterns.  Asynchronous on stream. */
+ * patterns.  precision EMIN_PREC_MIXED computes the products from FP32
+ * copies with FP32 accumulation (results stored as FP64).  Asynchronous on
+ * stream (the first mixed call on a handle allocates its FP32 buffers). */
 emin_status emin_rap(emin_pattern_t *h, const emin_system_t *sys, const double *Pv_vals,
-                     const double *Pp_vals, double *Ac_vals, double *Bc_vals, void *stream);
+                     const double *Pp_vals, double *Ac_vals, double *Bc_vals, int32_t precision,
+                     void *stream);
 
 /* Synchronises stream, copies the report to host memory and returns its status. */
 emin_status emin_sync_report(const emin_report_t *report, void *stream, emin_report_t *host);

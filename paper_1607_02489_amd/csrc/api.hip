@@ -39,6 +39,9 @@ struct emin_pattern_s {
   Csr PvT, T, Ac, X, U, PpT, Bc;
   int32_t *pvt_src = nullptr, *x_src = nullptr, *ppt_src = nullptr;
   SpgemmPlan tplan, acplan, uplan, bcplan;
+  // FP32 copies for the mixed-precision Galerkin product (allocated on first use)
+  float *Af = nullptr, *Bf = nullptr, *Pvf = nullptr, *Ppf = nullptr, *PvTf = nullptr,
+        *Xf = nullptr, *PpTf = nullptr, *Tf = nullptr, *Uf = nullptr;
   // coarse descriptors
   double* xv_c = nullptr;
   int32_t* p2v_c = nullptr;
@@ -319,13 +322,42 @@ void run_setup(emin_pattern_t* h, const emin_system_t* sys, const emin_params_t*
 }
 
 void run_rap(emin_pattern_t* h, const emin_system_t* sys, const double* Pv, const double* Pp,
-             double* Acv, double* Bcv, hipStream_t s) {
+             double* Acv, double* Bcv, int precision, hipStream_t s) {
   check_same_structure(h, sys);
+  if (precision != EMIN_PREC_F64 && precision != EMIN_PREC_MIXED)
+    throw Error(EMIN_ERR_ARG, "unknown precision");
   if ((h->sizes.nnz_Pv && !Pv) || (h->sizes.nnz_Pp && !Pp) || (h->Ac.nnz && !Acv) ||
       (h->Bc.nnz && !Bcv))
     throw Error(EMIN_ERR_ARG, "NULL value array");
   const CsrView A = in_view(sys->Ahat), B = in_view(sys->Bdiv);
   CsrView PvV{h->vp.N.nrows, h->vp.N.ncols, h->vp.N.nnz, h->vp.N.rowptr, h->vp.N.col, Pv};
+  if (precision == EMIN_PREC_MIXED) {
+    Arena& ar = h->ar;
+    if (!h->Af) {
+      h->Af = ar.alloc<float>(A.nnz);
+      h->Bf = ar.alloc<float>(B.nnz);
+      h->Pvf = ar.alloc<float>(h->vp.N.nnz);
+      h->Ppf = ar.alloc<float>(h->cp.N.nnz);
+      h->PvTf = ar.alloc<float>(h->PvT.nnz);
+      h->Xf = ar.alloc<float>(h->X.nnz);
+      h->PpTf = ar.alloc<float>(h->PpT.nnz);
+      h->Tf = ar.alloc<float>(h->T.nnz);
+      h->Uf = ar.alloc<float>(h->U.nnz);
+    }
+    to_float(A.val, h->Af, A.nnz, s);
+    to_float(B.val, h->Bf, B.nnz, s);
+    to_float(Pv, h->Pvf, h->vp.N.nnz, s);
+    to_float(Pp, h->Ppf, h->cp.N.nnz, s);
+    gather_values_f(h->Pvf, h->pvt_src, h->PvTf, h->PvT.nnz, s);
+    gather_values_f(h->Pvf, h->x_src, h->Xf, h->X.nnz, s);
+    gather_values_f(h->Ppf, h->ppt_src, h->PpTf, h->PpT.nnz, s);
+    spgemm_numeric_f32(A, h->Af, PvV, h->Pvf, h->T, h->Tf, nullptr, h->tplan, s);
+    spgemm_numeric_f32(view(h->PvT), h->PvTf, view(h->T), h->Tf, h->Ac, nullptr, Acv, h->acplan, s);
+    spgemm_numeric_f32(B, h->Bf, view(h->X), h->Xf, h->U, h->Uf, nullptr, h->uplan, s);
+    spgemm_numeric_f32(view(h->PpT), h->PpTf, view(h->U), h->Uf, h->Bc, nullptr, Bcv, h->bcplan, s);
+    HIP_OK(hipGetLastError());
+    return;
+  }
   gather_values(Pv, h->pvt_src, h->PvT.val, h->PvT.nnz, s);
   spgemm_numeric(A, PvV, h->T, h->tplan, s);
   Csr Ac = h->Ac;
@@ -430,9 +462,12 @@ emin_status emin_setup(emin_pattern_t* h, const emin_system_t* sys, const emin_p
 }
 
 emin_status emin_rap(emin_pattern_t* h, const emin_system_t* sys, const double* Pv_vals,
-                     const double* Pp_vals, double* Ac_vals, double* Bc_vals, void* stream) {
+                     const double* Pp_vals, double* Ac_vals, double* Bc_vals, int32_t precision,
+                     void* stream) {
   if (!h) return EMIN_ERR_ARG;
-  return guarded([&] { run_rap(h, sys, Pv_vals, Pp_vals, Ac_vals, Bc_vals, as_stream(stream)); });
+  return guarded([&] {
+    run_rap(h, sys, Pv_vals, Pp_vals, Ac_vals, Bc_vals, precision, as_stream(stream));
+  });
 }
 
 emin_status emin_sync_report(const emin_report_t* report, void* stream, emin_report_t* host) {

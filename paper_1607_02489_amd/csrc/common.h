@@ -136,6 +136,12 @@ void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& pla
                      hipStream_t s, Arena& ar, int* derr);
 void spgemm_numeric(const CsrView& A, const CsrView& B, const Csr& C, const SpgemmPlan& plan,
                     hipStream_t s);
+// FP32 values and accumulation (mixed-precision RAP); result to cval32, or
+// converted to FP64 into cval64 when that is non-null
+void spgemm_numeric_f32(const CsrView& A, const float* aval, const CsrView& B, const float* bval,
+                        const Csr& C, float* cval32, double* cval64, const SpgemmPlan& plan,
+                        hipStream_t s);
+void gather_values_f(const float* in, const int32_t* src, float* out, int64_t n, hipStream_t s);
 
 // filter of eq. (e:filtering) with lumping; keep mask per entry of A
 void diag_of(const CsrView& A, double* d, hipStream_t s);

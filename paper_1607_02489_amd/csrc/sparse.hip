@@ -329,18 +329,18 @@ __global__ __launch_bounds__(BS) void k_spgemm_sym(const int32_t* rows, int64_t 
 // one B row the columns are distinct, so lanes never meet; across B rows the
 // order is ascending k.  Each product and each sum is rounded separately, so
 // c_ij is exactly sum_k a_ik*b_kj accumulated in ascending k.
-template <int G>
+template <int G, class TV, class TO>
 __global__ __launch_bounds__(256) void k_spgemm_num(const int64_t* arp, const int32_t* acol,
-                                                   const double* aval, const int64_t* brp,
-                                                   const int32_t* bcol, const double* bval,
+                                                   const TV* aval, const int64_t* brp,
+                                                   const int32_t* bcol, const TV* bval,
                                                    const int64_t* crp, const int32_t* ccol,
-                                                   double* cval, int64_t n, int cap) {
+                                                   TO* cval, int64_t n, int cap) {
   extern __shared__ unsigned char lds_raw[];
   constexpr int NG = 256 / G;
   constexpr int U = 4;
   const int g = threadIdx.x / G, lane = threadIdx.x % G;
-  double* acc = reinterpret_cast<double*>(lds_raw) + (size_t)g * cap;
-  int32_t* cols = reinterpret_cast<int32_t*>(reinterpret_cast<double*>(lds_raw) + (size_t)NG * cap) +
+  TV* acc = reinterpret_cast<TV*>(lds_raw) + (size_t)g * cap;
+  int32_t* cols = reinterpret_cast<int32_t*>(reinterpret_cast<TV*>(lds_raw) + (size_t)NG * cap) +
                   (size_t)g * cap;
   const int64_t row = (int64_t)blockIdx.x * NG + g;
   if (row >= n) return;
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(256) void k_spgemm_num(const int64_t* arp, const in
   if (nc > cap) return;  // handled by k_spgemm_num_long
   for (int t = lane; t < nc; t += G) {
     cols[t] = ccol[c0 + t];
-    acc[t] = 0.0;
+    acc[t] = TV(0);
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
@@ -359,13 +359,13 @@ __global__ __launch_bounds__(256) void k_spgemm_num(const int64_t* arp, const in
     const int64_t e = e0 + lane;
     const bool ev = e < eb;
     const int32_t kk = ev ? acol[e] : 0;
-    const double av = ev ? aval[e] : 0.0;
+    const TV av = ev ? aval[e] : TV(0);
     const int64_t kb0 = ev ? brp[kk] : 0;
     const int kl = ev ? (int)(brp[kk + 1] - kb0) : 0;
     const int cnt = (int)((eb - e0) < G ? (eb - e0) : G);
     for (int q0 = 0; q0 < cnt; q0 += U) {
       int32_t jj[U];
-      double bv[U], am[U];
+      TV bv[U], am[U];
       int64_t b0[U];
       int bl[U];
 #pragma unroll
@@ -375,16 +375,16 @@ __global__ __launch_bounds__(256) void k_spgemm_num(const int64_t* arp, const in
         bl[u] = q < cnt ? __shfl(kl, q, G) : 0;
         am[u] = __shfl(av, q, G);
         jj[u] = lane < bl[u] ? bcol[b0[u] + lane] : -1;
-        bv[u] = lane < bl[u] ? bval[b0[u] + lane] : 0.0;
+        bv[u] = lane < bl[u] ? bval[b0[u] + lane] : TV(0);
       }
 #pragma unroll
       for (int u = 0; u < U; u++) {
         for (int off = 0; off < bl[u]; off += G) {
           int32_t j = jj[u];
-          double b = bv[u];
+          TV b = bv[u];
           if (off > 0) {
             j = off + lane < bl[u] ? bcol[b0[u] + off + lane] : -1;
-            b = off + lane < bl[u] ? bval[b0[u] + off + lane] : 0.0;
+            b = off + lane < bl[u] ? bval[b0[u] + off + lane] : TV(0);
           }
           if (j >= 0) {
             int lo = 0, hi = nc;
@@ -392,7 +392,7 @@ __global__ __launch_bounds__(256) void k_spgemm_num(const int64_t* arp, const in
               const int mid = (lo + hi) >> 1;
               if (cols[mid] < j) lo = mid + 1; else hi = mid;
             }
-            const double prod = am[u] * b;
+            const TV prod = am[u] * b;
             acc[lo] = acc[lo] + prod;
           }
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -402,24 +402,27 @@ __global__ __launch_bounds__(256) void k_spgemm_num(const int64_t* arp, const in
       }
     }
   }
-  for (int t = lane; t < nc; t += G) cval[c0 + t] = acc[t];
+  for (int t = lane; t < nc; t += G) cval[c0 + t] = (TO)acc[t];
 }
 
 // fallback for rows longer than the LDS capacity: one lane per row, the
 // accumulators live in the output array itself (same summation order)
-__global__ void k_spgemm_num_long(const int64_t* arp, const int32_t* acol, const double* aval,
-                                  const int64_t* brp, const int32_t* bcol, const double* bval,
-                                  const int64_t* crp, const int32_t* ccol, double* cval,
+template <class TV, class TO>
+__global__ void k_spgemm_num_long(const int64_t* arp, const int32_t* acol, const TV* aval,
+                                  const int64_t* brp, const int32_t* bcol, const TV* bval,
+                                  const int64_t* crp, const int32_t* ccol, TO* cval,
                                   int64_t n, int cap) {
   int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= n) return;
   const int64_t c0 = crp[row];
   const int nc = (int)(crp[row + 1] - c0);
   if (nc <= cap) return;
-  for (int t = 0; t < nc; t++) cval[c0 + t] = 0.0;
+  TV accv = TV(0);
+  (void)accv;
+  for (int t = 0; t < nc; t++) cval[c0 + t] = TO(0);
   for (int64_t e = arp[row]; e < arp[row + 1]; e++) {
     const int32_t k = acol[e];
-    const double a = aval[e];
+    const TV a = aval[e];
     for (int64_t f = brp[k]; f < brp[k + 1]; f++) {
       const int32_t j = bcol[f];
       int lo = 0, hi = nc;
@@ -427,8 +430,8 @@ __global__ void k_spgemm_num_long(const int64_t* arp, const int32_t* acol, const
         int mid = (lo + hi) >> 1;
         if (ccol[c0 + mid] < j) lo = mid + 1; else hi = mid;
       }
-      const double prod = a * bval[f];
-      cval[c0 + lo] = cval[c0 + lo] + prod;
+      const TV prod = a * bval[f];
+      cval[c0 + lo] = (TO)((TV)cval[c0 + lo] + prod);
     }
   }
 }
@@ -552,37 +555,58 @@ void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& pla
   (void)derr;
 }
 
-template <int G>
-static void launch_num(const CsrView& A, const CsrView& B, const Csr& C, int cap, hipStream_t s) {
+template <int G, class TV, class TO>
+static void launch_num(const CsrView& A, const TV* aval, const CsrView& B, const TV* bval,
+                       const Csr& C, TO* cval, int cap, hipStream_t s) {
   constexpr int NG = 256 / G;
-  size_t lds = (size_t)NG * cap * (sizeof(double) + sizeof(int32_t));
-  k_spgemm_num<G><<<nblocks(A.nrows, NG), 256, lds, s>>>(
-      A.rowptr, A.col, A.val, B.rowptr, B.col, B.val, C.rowptr, C.col, C.val, A.nrows, cap);
+  const size_t lds = (size_t)NG * cap * (sizeof(TV) + sizeof(int32_t));
+  k_spgemm_num<G, TV, TO><<<nblocks(A.nrows, NG), 256, lds, s>>>(
+      A.rowptr, A.col, aval, B.rowptr, B.col, bval, C.rowptr, C.col, cval, A.nrows, cap);
+}
+
+template <class TV, class TO>
+static void numeric_any(const CsrView& A, const TV* aval, const CsrView& B, const TV* bval,
+                        const Csr& C, TO* cval, const SpgemmPlan& plan, hipStream_t s) {
+  if (A.nrows == 0 || C.nnz == 0) return;
+  prof::Scope ps(s, EMIN_PROF_SPGEMM,
+                 (4.0 + sizeof(TV)) * (double)(A.nnz + B.nnz + C.nnz) + 16.0 * (double)A.nrows);
+  const int g = plan.g_num;
+  const int NG = 256 / g;
+  // LDS budget ~96 KiB per block
+  int cap = (int)((96 * 1024) / (NG * (sizeof(TV) + sizeof(int32_t))));
+  if (cap > plan.max_row) cap = (int)plan.max_row;
+  if (cap < 1) cap = 1;
+  switch (g) {
+    case 4: launch_num<4>(A, aval, B, bval, C, cval, cap, s); break;
+    case 8: launch_num<8>(A, aval, B, bval, C, cval, cap, s); break;
+    case 16: launch_num<16>(A, aval, B, bval, C, cval, cap, s); break;
+    case 32: launch_num<32>(A, aval, B, bval, C, cval, cap, s); break;
+    default: launch_num<64>(A, aval, B, bval, C, cval, cap, s); break;
+  }
+  if (plan.max_row > cap)
+    k_spgemm_num_long<TV, TO><<<nblocks(A.nrows, 64), 64, 0, s>>>(
+        A.rowptr, A.col, aval, B.rowptr, B.col, bval, C.rowptr, C.col, cval, A.nrows, cap);
 }
 
 void spgemm_numeric(const CsrView& A, const CsrView& B, const Csr& C, const SpgemmPlan& plan,
                     hipStream_t s) {
-  if (A.nrows == 0 || C.nnz == 0) return;
-  prof::Scope ps(s, EMIN_PROF_SPGEMM,
-                 12.0 * (double)A.nnz + 12.0 * (double)B.nnz + 12.0 * (double)C.nnz +
-                     16.0 * (double)A.nrows);
-  const int g = plan.g_num;
-  const int NG = 256 / g;
-  // LDS budget ~96 KiB per block
-  int cap = (int)((96 * 1024) / (NG * (sizeof(double) + sizeof(int32_t))));
-  if (cap > plan.max_row) cap = (int)plan.max_row;
-  if (cap < 1) cap = 1;
-  switch (g) {
-    case 4: launch_num<4>(A, B, C, cap, s); break;
-    case 8: launch_num<8>(A, B, C, cap, s); break;
-    case 16: launch_num<16>(A, B, C, cap, s); break;
-    case 32: launch_num<32>(A, B, C, cap, s); break;
-    default: launch_num<64>(A, B, C, cap, s); break;
-  }
-  if (plan.max_row > cap)
-    k_spgemm_num_long<<<nblocks(A.nrows, 64), 64, 0, s>>>(A.rowptr, A.col, A.val, B.rowptr,
-                                                          B.col, B.val, C.rowptr, C.col, C.val,
-                                                          A.nrows, cap);
+  numeric_any<double, double>(A, A.val, B, B.val, C, C.val, plan, s);
+}
+
+void spgemm_numeric_f32(const CsrView& A, const float* aval, const CsrView& B, const float* bval,
+                        const Csr& C, float* cval32, double* cval64, const SpgemmPlan& plan,
+                        hipStream_t s) {
+  if (cval64) numeric_any<float, double>(A, aval, B, bval, C, cval64, plan, s);
+  else numeric_any<float, float>(A, aval, B, bval, C, cval32, plan, s);
+}
+
+__global__ void k_gather_f(const float* in, const int32_t* src, float* out, int64_t n) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) out[p] = in[src[p]];
+}
+
+void gather_values_f(const float* in, const int32_t* src, float* out, int64_t n, hipStream_t s) {
+  if (n) k_gather_f<<<nblocks(n, 256), 256, 0, s>>>(in, src, out, n);
 }
 
 // ---------------------------------------------------------------------------

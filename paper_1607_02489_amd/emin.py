@@ -95,7 +95,7 @@ def lib():
         L.emin_setup.argtypes = [C.c_void_p, P(c_system), P(c_params), C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_void_p]
         L.emin_rap.argtypes = [C.c_void_p, P(c_system), C.c_void_p, C.c_void_p, C.c_void_p,
-                               C.c_void_p, C.c_void_p]
+                               C.c_void_p, C.c_int32, C.c_void_p]
         L.emin_sync_report.argtypes = [C.c_void_p, C.c_void_p, P(c_report)]
         L.emin_memcpy_d2h.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
         L.emin_pattern_destroy.argtypes = [C.c_void_p]
@@ -207,9 +207,11 @@ class Pattern:
                                 C.c_void_p(Pp), _stream(stream),
                                 C.c_void_p(report) if report else None), "emin_setup")
 
-    def rap(self, Pv, Pp, Ac, Bc, stream=None):
+    def rap(self, Pv, Pp, Ac, Bc, stream=None, mixed=False):
         _check(lib().emin_rap(self.h, C.byref(self._c), C.c_void_p(Pv), C.c_void_p(Pp),
-                              C.c_void_p(Ac), C.c_void_p(Bc), _stream(stream)), "emin_rap")
+                              C.c_void_p(Ac), C.c_void_p(Bc),
+                              EMIN_PREC_MIXED if mixed else EMIN_PREC_F64, _stream(stream)),
+               "emin_rap")
 
     def coarse_system(self, Ac, Bc) -> DeviceSystem:
         a, b = self.view(VIEW_AC), self.view(VIEW_BC)
@@ -297,7 +299,8 @@ class Hierarchy:
                       torch.empty(max(s["nnz_Ac"], 1), **f64),
                       torch.empty(max(s["nnz_Bc"], 1), **f64), new_report(self.device))
             pat.setup(self.prm, L.Pv.data_ptr(), L.Pp.data_ptr(), L.report.data_ptr(), stream)
-            pat.rap(L.Pv.data_ptr(), L.Pp.data_ptr(), L.Ac.data_ptr(), L.Bc.data_ptr(), stream)
+            pat.rap(L.Pv.data_ptr(), L.Pp.data_ptr(), L.Ac.data_ptr(), L.Bc.data_ptr(), stream,
+                    mixed=self.prm.precision == EMIN_PREC_MIXED)
             self.levels.append(L)
             cur = pat.coarse_system(L.Ac, L.Bc)
         self.coarsest = cur
@@ -307,7 +310,7 @@ class Hierarchy:
         for L in self.levels:
             L.pattern.setup(self.prm, L.Pv.data_ptr(), L.Pp.data_ptr(), L.report.data_ptr(), stream)
             L.pattern.rap(L.Pv.data_ptr(), L.Pp.data_ptr(), L.Ac.data_ptr(), L.Bc.data_ptr(),
-                          stream)
+                          stream, mixed=self.prm.precision == EMIN_PREC_MIXED)
 
     def p_nnz(self):
         return sum(L.pattern.sizes["nnz_Pv"] + L.pattern.sizes["nnz_Pp"] for L in self.levels)

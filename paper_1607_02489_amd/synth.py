@@ -230,27 +230,36 @@ def _assemble(dim, n, V, nu, wind_fn, chunk=4096):
         pn = pnodes[e0:e1]
         Xc = V[pn]                                             # [E, nbp, d]
         xv[vn.reshape(-1)] = _velocity_coords(dim, n, V, pn).reshape(-1, dim)
-        J = np.einsum("qad,eak->eqkd", Gg, Xc)                 # dx_k/ds_d
+        J = np.einsum("qad,eak->eqkd", Gg, Xc, optimize=True)  # dx_k/ds_d
         detJ = np.linalg.det(J)
         Jinv = np.linalg.inv(J)                                # ds/dx : [e,q,d,k]
-        gphys = np.einsum("qbd,eqdk->eqbk", Gq, Jinv)          # [E,nq,nbv,d]
+        # physical gradients [E,nq,nbv,d] as batched matmuls over (e,q)
+        gphys = np.matmul(Gq[None], Jinv)
         wdet = wq[None, :] * np.abs(detJ)                      # [E,nq]
-        Ke = nu * np.einsum("eq,eqik,eqjk->eij", wdet, gphys, gphys)
+        E_ = gphys.shape[0]
+        nq = gphys.shape[1]
+        # Ke_ij = sum_{q,k} w_q |J| g_qik g_qjk  ->  (E, nbv, nq*d) @ (E, nq*d, nbv)
+        gw = gphys * wdet[:, :, None, None]
+        Gt = gw.transpose(0, 2, 1, 3).reshape(E_, nbv, nq * dim)
+        Gm = gphys.transpose(0, 1, 3, 2).reshape(E_, nq * dim, nbv)
+        Ke = nu * np.matmul(Gt, Gm)
         if wind_fn is not None:
             xn = xv[vn]                                        # node coords [E,nbv,d]
             Wn = wind_fn(xn)                                   # nodal wind [E,nbv,d]
-            wqv = np.einsum("qb,ebd->eqd", Vq, Wn)             # wind at qp
-            adv = np.einsum("eqd,eqjd->eqj", wqv, gphys)       # w . grad(phi_j)
-            Ke = Ke + np.einsum("eq,qi,eqj->eij", wdet, Vq, adv)
+            wqv = np.matmul(Vq[None], Wn)                      # wind at qp [E,nq,d]
+            adv = np.matmul(gphys, wqv[:, :, :, None])[..., 0]  # w . grad(phi_j) [E,nq,nbv]
+            # Ke_ij += sum_q w_q |J| phi_i(q) adv_qj
+            Ke = Ke + np.matmul((Vq[None] * wdet[:, :, None]).transpose(0, 2, 1), adv)
         rowsA.append(np.repeat(vn, nbv, axis=1).reshape(-1))
         colsA.append(np.tile(vn, (1, nbv)).reshape(-1))
         valsA.append(Ke.reshape(-1))
-        # b_{c,k,i} = int psi_k dphi_i/dx_c
-        Be = np.einsum("eq,qk,eqic->ecki", wdet, Pq, gphys)    # [E,d,nbp,nbv]
+        # b_{c,k,i} = int psi_k dphi_i/dx_c  ->  (E, nbp, nq) @ (E, nq, nbv) per c
+        Pw = (Pq[None] * wdet[:, :, None]).transpose(0, 2, 1)  # [E,nbp,nq]
         for c in range(dim):
+            Bc = np.matmul(Pw, gphys[:, :, :, c])               # [E,nbp,nbv]
             rowsB.append(np.repeat(pn, nbv, axis=1).reshape(-1))
             colsB.append((np.tile(vn, (1, nbp)) + c * n_v).reshape(-1))
-            valsB.append(Be[:, c].reshape(-1))
+            valsB.append(Bc.reshape(-1))
     A = sp.coo_matrix((np.concatenate(valsA), (np.concatenate(rowsA), np.concatenate(colsA))),
                       shape=(n_v, n_v)).tocsr()
     B = sp.coo_matrix((np.concatenate(valsB), (np.concatenate(rowsB), np.concatenate(colsB))),

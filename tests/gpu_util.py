@@ -30,7 +30,7 @@ def gpu_level(sys_: System, tau1_v=0.06, tau1_p=0.06, tau2_sq=1.5e-3, iters=5, m
     Bc = torch.empty(max(s["nnz_Bc"], 1), **f64)
     rep = E.new_report()
     pat.setup(prm, Pv.data_ptr(), Pp.data_ptr(), rep.data_ptr())
-    pat.rap(Pv.data_ptr(), Pp.data_ptr(), Ac.data_ptr(), Bc.data_ptr())
+    pat.rap(Pv.data_ptr(), Pp.data_ptr(), Ac.data_ptr(), Bc.data_ptr(), mixed=mixed)
     torch.cuda.synchronize()
     r = E.sync_report(rep, raise_on_error=False)
     out = dict(sizes=s, status=r.status, its_v=r.its_v, its_p=r.its_p)

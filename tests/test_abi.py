@@ -42,5 +42,5 @@ def test_null_arguments_rejected_without_device():
     s = E.c_sizes()
     assert L.emin_pattern_info(None, C.byref(s)) == 1
     assert L.emin_setup(None, None, None, None, None, None, None) == 1
-    assert L.emin_rap(None, None, None, None, None, None, None) == 1
+    assert L.emin_rap(None, None, None, None, None, None, 0, None) == 1
     L.emin_pattern_destroy(None)                                   # NULL-safe

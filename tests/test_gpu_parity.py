@@ -108,3 +108,149 @@ def test_hierarchy_cfg2_small_per_level():
         keep.append(g)
         compare_level(g, L)
         cur = host_coarse(g, s.dim)
+
+
+MIXED_CASES = {
+    "cfg1_stokes2d_8": lambda: (synth.stokes2d_small(), {}),
+    "oseen2d_40_jitter": CASES["oseen2d_40_jitter"],
+    "stokes3d_5": CASES["stokes3d_5"],
+}
+
+
+@pytest.mark.parametrize("case", list(MIXED_CASES))
+def test_mixed_precision_level(case):
+    """FP32 masked products and RAP, FP64 projection and scalars: patterns
+    unchanged, P and RAP within 1e-5 of the FP64 oracle, and the constraint
+    still met to FP64 accuracy (the projection runs in FP64)."""
+    from tests.gpu_util import same_pattern
+    s, kw = MIXED_CASES[case]()
+    say(f"[gpu] mixed precision {case}: dofs={s.dofs}")
+    L = O.level(s, iters=5, **kw)
+    g = gpu_level(s, iters=5, mixed=True, **kw)
+    assert g["status"] == 0
+    for k in ("Pv", "Pp", "Ac", "Bc"):
+        assert same_pattern(g[k], getattr(L, k)), k
+        assert relfro(g[k].val, getattr(L, k).val) <= 1e-5, k
+    Pv, Pp = g["Pv"].to_scipy(), g["Pp"].to_scipy()
+    Wv = (~L.dir).astype(np.float64)
+    assert np.linalg.norm(Pv @ Wv[L.is_cv] - Wv) / np.linalg.norm(Wv) <= 1e-12
+    assert np.linalg.norm(Pp @ np.ones(Pp.shape[1]) - 1.0) / np.sqrt(s.n_p) <= 1e-12
+
+
+def test_cfg2_full_hierarchy_per_level():
+    """Config 2 at full size (2-D Oseen 256x256, 592,387 dofs), all four
+    levels, each against the oracle on the GPU's own input for that level."""
+    s = synth.oseen2d(256)
+    cur = s
+    keep = []
+    for lev in range(3):
+        say(f"[gpu] cfg2 level {lev}: dofs={cur.dofs}")
+        L = O.level(cur, iters=5)
+        g = gpu_level(cur, iters=5)
+        keep.append(g)
+        compare_level(g, L)
+        cur = host_coarse(g, s.dim)
+    assert cur.dofs < 1000
+
+
+def test_stokes3d_16_bitexact():
+    s = synth.make_system(3, 16, jitter=0.05, seed=3)
+    say(f"[gpu] stokes3d 16^3: dofs={s.dofs}")
+    kw = dict(tau1_v=0.038, tau1_p=0.04)
+    compare_level(gpu_level(s, iters=5, **kw), O.level(s, iters=5, **kw))
+
+
+def _bfs_dist(rp, col, src, maxd):
+    dist = {int(src): 0}
+    front = [int(src)]
+    for d in range(1, maxd + 1):
+        nxt = []
+        for v in front:
+            for w in col[rp[v]:rp[v + 1]]:
+                w = int(w)
+                if w not in dist:
+                    dist[w] = d
+                    nxt.append(w)
+        front = nxt
+    return dist
+
+
+def test_cfg3_full_size_properties():
+    """Config 3 at full size (3-D Stokes 48^3, 2.86M dofs), in the launch
+    configuration the benchmark times: properties that hold at any size --
+    constraint, symmetric coarse velocity block, B_c^T 1 = 0, and on sampled
+    vertices the distance invariants of Alg. 3 and the S sets."""
+    s = synth.stokes3d(48)
+    say(f"[gpu] cfg3 full size: dofs={s.dofs}")
+    kw = dict(tau1_v=0.038, tau1_p=0.04)
+    g = gpu_level(s, iters=5, energy=True, **kw)
+    assert g["status"] == 0
+    Pv, Pp = g["Pv"].to_scipy(), g["Pp"].to_scipy()
+    Wv = (~g["dir"]).astype(np.float64)
+    assert np.linalg.norm(Pv @ Wv[g["Cv"]] - Wv) / np.linalg.norm(Wv) <= 1e-12
+    assert np.linalg.norm(Pp @ np.ones(Pp.shape[1]) - 1.0) / np.sqrt(s.n_p) <= 1e-12
+    assert (np.diff(g["energy_v"]) <= 1e-13 * abs(g["energy_v"][0])).all()
+    Ac = g["Ac"].to_scipy()
+    assert abs(Ac - Ac.T).max() <= 1e-13 * abs(Ac).max()
+    Bc = g["Bc"].to_scipy()
+    assert np.abs(np.asarray(Bc.sum(axis=0))).max() <= 1e-12 * np.abs(Bc.data).max()
+    # sampled Alg. 3 invariants on the pressure graph (structure of M_p)
+    Mp = g["Mp"]
+    rp, col = Mp.rowptr, Mp.col
+    Cset = set(g["Cp"].tolist())
+    alg3 = g["order"][:g["sizes"]["n_cp_alg3"]]
+    rng = np.random.default_rng(0)
+    for c in rng.choice(alg3, size=min(40, alg3.size), replace=False):
+        ball = _bfs_dist(rp, col, c, 3)
+        assert not (set(ball) & set(alg3.tolist())) - {int(c)}
+    S = g["S"]
+    for v in rng.choice(s.n_p, size=300, replace=False):
+        ball = _bfs_dist(rp, col, v, 3)
+        want = sorted(u for u in ball if u in Cset)
+        assert S.col[S.rowptr[v]:S.rowptr[v + 1]].tolist() == want
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_degenerate_small_meshes(n):
+    """Tiny meshes: one element (a single interior velocity node), two and
+    three elements per side."""
+    s = synth.make_system(2, n, jitter=0.1 if n > 1 else 0.0, seed=n)
+    say(f"[gpu] degenerate n={n}: dofs={s.dofs}")
+    compare_level(gpu_level(s, iters=5), O.level(s, iters=5))
+
+
+def test_error_paths_reported():
+    """Malformed inputs come back as status codes (host and kernel checks),
+    never as faults."""
+    import torch
+    from paper_1607_02489_amd import emin as E
+    s = synth.make_system(2, 4)
+    d = E.DeviceSystem.upload(s)
+    bad = E.params(iters=E.MAX_ITERS + 1)
+    with pytest.raises(E.EminError) as ei:
+        E.Pattern(d, bad)
+    assert ei.value.status == 1                      # ERR_ARG
+    # unsorted columns in one row of Ahat
+    col = s.Ahat.col.copy()
+    a, b = s.Ahat.rowptr[20], s.Ahat.rowptr[21]
+    col[a:b] = col[a:b][::-1]
+    s2 = synth.System(2, synth.CSR(s.Ahat.nrows, s.Ahat.ncols, s.Ahat.rowptr, col, s.Ahat.val),
+                      s.Bdiv, s.xv, s.p2v)
+    with pytest.raises(E.EminError) as ei:
+        E.Pattern(E.DeviceSystem.upload(s2), E.params())
+    assert ei.value.status == 3                      # ERR_PATTERN
+    # co-location index out of range
+    p2v = s.p2v.copy()
+    p2v[3] = s.n_v + 5
+    s3 = synth.System(2, s.Ahat, s.Bdiv, s.xv, p2v)
+    with pytest.raises(E.EminError) as ei:
+        E.Pattern(E.DeviceSystem.upload(s3), E.params())
+    assert ei.value.status == 3
+    # setup on a system whose structure differs from the pattern's
+    pat = E.Pattern(d, E.params())
+    other = E.DeviceSystem.upload(synth.make_system(2, 5))
+    pat._c = other.c()
+    P = torch.empty(max(pat.sizes["nnz_Pv"], 1), dtype=torch.float64, device="cuda")
+    with pytest.raises(E.EminError) as ei:
+        pat.setup(E.params(), P.data_ptr(), P.data_ptr())
+    assert ei.value.status == 2                      # ERR_SHAPE
