@@ -73,16 +73,202 @@ def cpu_baseline(system, wl, seconds, p_nnz_iters):
                 ms_per_setup=mean * 1e3)
 
 
+def batch_systems(synth, count=64, seed=1):
+    """64 2-D Oseen systems: n ~ U{16..128}, Re log-uniform in [1, 500], wind
+    seeds 1000+i (the stream-function recipe of the 2-D Oseen workload)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(16, 129, size=count)
+    res = np.exp(rng.uniform(np.log(1.0), np.log(500.0), size=count))
+    return [synth.make_system(2, int(n), nu=1.0 / float(re), wind="stream", seed=1000 + i)
+            for i, (n, re) in enumerate(zip(ns, res))], ns, res
+
+
+def run_batch(args, E, synth, torch):
+    """Config 4: 64 uneven hierarchies built concurrently (one stream per
+    build), then every numeric re-setup replayed as one hipGraph launch;
+    compared with plain FP64 built one after another."""
+    t0 = time.perf_counter()
+    systems, ns, res = batch_systems(synth)
+    log(f"[bench] generated 64 systems ({sum(s.dofs for s in systems)} dofs) in "
+        f"{time.perf_counter() - t0:.1f}s")
+    ds = [E.DeviceSystem.upload(s) for s in systems]
+    iters, nlev, mind = 5, 4, 200
+    mixed = E.params(iters=iters, mixed=True)
+    fp64 = E.params(iters=iters)
+    torch.cuda.synchronize()
+
+    def pnnz(hs):
+        return sum(z["nnz_Pv"] + z["nnz_Pp"] for h in hs for z in h.sizes())
+
+    for _ in range(args.warmup):
+        for h in E.build_batch(ds, mixed, nlev, mind, max_parallel=16):
+            h.close()
+    build_ms, seq_ms = [], []
+    for k in range(args.steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        hs = E.build_batch(ds, mixed, nlev, mind, max_parallel=16)
+        torch.cuda.synchronize()
+        build_ms.append((time.perf_counter() - t) * 1e3)
+        if k < args.steps - 1:
+            for h in hs:
+                h.close()
+        log(f"[bench] batch build {k + 1}/{args.steps}: {build_ms[-1]:.1f} ms")
+    p_nnz_iters = pnnz(hs) * iters
+    B = E.Batch(hs)
+    stream = torch.cuda.current_stream()
+    rep_ms = []
+    for _ in range(max(5, args.steps)):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        B.run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        rep_ms.append(e0.elapsed_time(e1))
+    # plain FP64, one system after another (same GPU)
+    for k in range(max(1, args.steps // 2)):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        seq = [E.NativeHierarchy(d, fp64, nlev, mind) for d in ds]
+        torch.cuda.synchronize()
+        seq_ms.append((time.perf_counter() - t) * 1e3)
+        seq_pnnz = pnnz(seq) * iters
+        seq_inc = []
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for h in seq:
+                h.resetup()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            seq_inc.append(e0.elapsed_time(e1))
+        for h in seq:
+            h.close()
+    B.close()
+    for h in hs:
+        h.close()
+    bm = sorted(build_ms)[len(build_ms) // 2]
+    rm = sorted(rep_ms)[len(rep_ms) // 2]
+    sm = sorted(seq_ms)[len(seq_ms) // 2]
+    si = sorted(seq_inc)[len(seq_inc) // 2]
+    return {
+        "metric": "EMIN setup P-nnz*iters/s",
+        "value": p_nnz_iters / (bm * 1e-3),
+        "unit": "P-nnz*iters/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": bm, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "batch64_oseen2d", "systems": 64,
+                   "n_range": [int(ns.min()), int(ns.max())],
+                   "re_range": [float(res.min()), float(res.max())],
+                   "dofs_total": int(sum(s.dofs for s in systems)), "iters": iters,
+                   "max_levels": nlev, "precision": "mixed"},
+        "roofline": None, "cpu_baseline": None,
+        "p_nnz_iters": p_nnz_iters,
+        "graph_replay": {"ms": rm, "value": p_nnz_iters / (rm * 1e-3),
+                         "what": "numeric phases of all 64 hierarchies as one hipGraph launch"},
+        "fp64_sequential": {"build_ms": sm, "value": seq_pnnz / (sm * 1e-3),
+                            "incremental_ms": si, "incremental_value": seq_pnnz / (si * 1e-3)},
+    }
+
+
+def serve_pool(synth, sizes, seed=0):
+    """Pool of 3-D Oseen channel systems, one per mesh size m: the Laplacian
+    and convection parts on one structure, so a request with its own
+    Reynolds number forms nu*A_S + K on the device."""
+    return {m: synth.make_split_system(3, m, seed=seed, wind="channel", domain="channel")
+            for m in sizes}
+
+
+def run_serve(args, E, synth, torch):
+    """Config 5: Poisson arrivals of 3-D Oseen channel setup requests admitted
+    by a device-memory budget; latency from arrival to a finished hierarchy."""
+    import threading
+    import numpy as np
+    rng = np.random.default_rng(5)
+    sizes = list(range(16, 41, 4))
+    t0 = time.perf_counter()
+    pool = serve_pool(synth, sizes)
+    log(f"[bench] serve pool of {len(pool)} channel systems in {time.perf_counter() - t0:.1f}s")
+    # device copies of structure + the two value arrays per pool entry
+    dev = {}
+    for m, sysm in pool.items():
+        d = E.DeviceSystem.upload(sysm)
+        dev[m] = (d, torch.from_numpy(sysm.meta["S_val"]).cuda(),
+                  torch.from_numpy(sysm.meta["K_val"]).cuda())
+    lam, dur = 20.0, args.serve_seconds
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=int(lam * dur * 2)))
+    arrivals = arrivals[arrivals < dur]
+    ms = rng.integers(16, 41, size=arrivals.size)
+    res = np.exp(rng.uniform(np.log(10.0), np.log(500.0), size=arrivals.size))
+    prm = E.params(0.038, 0.04, 1.5e-3, 5, mixed=True)
+    srv = E.Server(budget_bytes=200 << 30, slots=args.serve_slots)
+    lat, qms, done_at, tickets = [], [], [], []
+    pnnz_total = [0]
+    lock = threading.Lock()
+
+    def waiter(ticket, t_arr, req_tensors):
+        view, q, r = srv.wait(ticket)
+        t_done = time.perf_counter() - t_start
+        pn = sum(z["nnz_Pv"] + z["nnz_Pp"] for z in view.sizes()) * 5
+        srv.release(ticket)
+        with lock:
+            lat.append((t_done - t_arr) * 1e3)
+            qms.append(q)
+            done_at.append(t_done)
+            pnnz_total[0] += pn
+
+    threads = []
+    sub = torch.cuda.Stream()     # forms each request's values; never a device-wide sync
+    t_start = time.perf_counter()
+    for a, m, re in zip(arrivals, ms, res):
+        now = time.perf_counter() - t_start
+        if a > now:
+            time.sleep(a - now)
+        key = sizes[int(np.argmin([abs(m - z) for z in sizes]))]
+        d, sv, kv = dev[key]
+        with torch.cuda.stream(sub):
+            vals = (sv * (1.0 / re) + kv).contiguous()
+        sub.synchronize()
+        req = E.DeviceSystem(3, d.n_v, d.n_p, (d.A[0], d.A[1], d.A[2], vals.data_ptr()), d.B,
+                             d.xv, d.p2v, [d, vals])
+        t = srv.submit(req, prm, 4, 1000)
+        th = threading.Thread(target=waiter, args=(t, a, req))
+        th.start()
+        threads.append(th)
+    for th in threads:
+        th.join()
+    wall = max(done_at) if done_at else 0.0
+    srv.close()
+    return {
+        "metric": "EMIN setup P-nnz*iters/s", "value": pnnz_total[0] / wall if wall else 0.0,
+        "unit": "P-nnz*iters/s", "n_gpus": 1, "steps": len(lat), "warmup": 0,
+        "ms_per_step": float(np.mean(lat)) if lat else None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "serve_oseen3d_channel", "arrival_rate_per_s": lam,
+                   "duration_s": dur, "requests": int(arrivals.size),
+                   "m_range": [16, 40], "pool_sizes": sizes, "re_range": [10, 500],
+                   "budget_gb": 200, "slots": args.serve_slots, "precision": "mixed"},
+        "roofline": None, "cpu_baseline": None,
+        "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+        "queue_p50_ms": pct(qms, 50), "queue_p99_ms": pct(qms, 99),
+        "requests_per_s": len(lat) / wall if wall else 0.0,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="oseen2d_256", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="oseen2d_256",
+                    choices=sorted(WORKLOADS) + ["batch64_oseen2d", "serve_oseen3d_channel"])
     ap.add_argument("--mixed", action="store_true", help="FP32 masked products, FP64 projection/scalars")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--serve-slots", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -93,6 +279,14 @@ def main():
     from paper_1607_02489_amd import emin as E
     from paper_1607_02489_amd import synth
 
+    if args.workload == "batch64_oseen2d":
+        torch.cuda.init()
+        print(json.dumps(run_batch(args, E, synth, torch)), flush=True)
+        return
+    if args.workload == "serve_oseen3d_channel":
+        torch.cuda.init()
+        print(json.dumps(run_serve(args, E, synth, torch)), flush=True)
+        return
     wl = WORKLOADS[args.workload]
     mixed = args.mixed or wl["mixed"]
     t0 = time.perf_counter()

@@ -186,11 +186,84 @@ emin_status emin_sync_report(const emin_report_t *report, void *stream, emin_rep
 /* Copies bytes from device to host memory (synchronous on stream). */
 emin_status emin_memcpy_d2h(void *dst_host, const void *src_dev, size_t bytes, void *stream);
 
-/* Releases the handle and its device memory.  NULL-safe. */
+/* Releases the handle.  Its device memory returns to a process-wide cache of
+ * chunks that later handles reuse (no hipFree, so no device-wide wait); the
+ * caller must make sure no queued work still uses the handle (synchronise
+ * the streams it was used on).  NULL-safe. */
 void emin_pattern_destroy(emin_pattern_t *h);
+/* Frees the cached device chunks; returns the bytes released. */
+int64_t emin_release_cached(void);
 
 const char *emin_status_string(emin_status s);
 const char *emin_version(void);
+/* Human-readable detail of the last error returned on the calling thread. */
+const char *emin_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Whole hierarchies (Alg. 1 without relaxation)
+ * ------------------------------------------------------------------------ */
+typedef struct emin_hierarchy_s emin_hierarchy_t;
+
+/* Builds levels 0..nlevels-1 (at most nlevels-1 transfers) by emin_pattern,
+ * emin_setup and emin_rap per level, stopping before a level with at most
+ * min_dofs dofs.  Level 0's arrays are borrowed (they must stay valid while
+ * the hierarchy is re-set up); coarse levels are owned.  Synchronises the
+ * stream between levels (emin_pattern reads sizes back). */
+emin_status emin_hierarchy_build(const emin_system_t *sys, const emin_params_t *prm,
+                                 int32_t nlevels, int64_t min_dofs, void *stream,
+                                 emin_hierarchy_t **out);
+/* Numeric phases only (emin_setup + emin_rap on every level) for new values
+ * of the level-0 system with unchanged structure; asynchronous. */
+emin_status emin_hierarchy_resetup(emin_hierarchy_t *h, const emin_system_t *sys, void *stream);
+/* Number of transfers built; per_level (host, cap entries) gets the sizes. */
+emin_status emin_hierarchy_info(const emin_hierarchy_t *h, int32_t *ntransfers,
+                                emin_sizes_t *per_level, int32_t cap);
+/* Borrowed device pointers of one transfer level (any output may be NULL). */
+emin_status emin_hierarchy_level(const emin_hierarchy_t *h, int32_t level, emin_pattern_t **pat,
+                                 const double **Pv, const double **Pp, const double **Ac,
+                                 const double **Bc, const emin_report_t **report);
+/* Device memory held by the hierarchy and its pattern handles (bytes). */
+int64_t emin_hierarchy_device_bytes(const emin_hierarchy_t *h);
+/* Same contract as emin_pattern_destroy (no queued work may use it). */
+void emin_hierarchy_destroy(emin_hierarchy_t *h);
+
+/* Batched form: builds count hierarchies concurrently, one host thread and
+ * one default-priority HIP stream per concurrent build (at most
+ * max_parallel).  out receives count handles; on error all are released. */
+emin_status emin_hierarchy_build_batch(const emin_system_t *const *systems, int32_t count,
+                                       const emin_params_t *prm, int32_t nlevels,
+                                       int64_t min_dofs, int32_t max_parallel,
+                                       emin_hierarchy_t **out);
+/* Captures the numeric phases of every level of every hierarchy (one
+ * branch per hierarchy, forked from and joined to stream) into one hipGraph;
+ * emin_batch_run replays it as a single launch.  systems[i] is hierarchy i's
+ * level-0 system (borrowed).  The capture contains kernels only. */
+typedef struct emin_batch_s emin_batch_t;
+emin_status emin_batch_create(emin_hierarchy_t *const *hs, const emin_system_t *const *systems,
+                              int32_t count, void *stream, emin_batch_t **out);
+emin_status emin_batch_run(emin_batch_t *b, void *stream);
+void emin_batch_destroy(emin_batch_t *b);
+
+/* Serving: requests are admitted in arrival order when one of max_slots
+ * workers is free and their device-memory estimate fits budget_bytes; each
+ * worker builds on its own stream, so admitted requests overlap on the GPU.
+ * A request's arrays are borrowed until it completes; its hierarchy stays on
+ * the device until released.  submit returns EMIN_ERR_BUDGET for a request
+ * larger than the whole budget. */
+typedef struct emin_server_s emin_server_t;
+emin_status emin_server_create(int64_t budget_bytes, int32_t max_slots, emin_server_t **out);
+emin_status emin_server_submit(emin_server_t *srv, const emin_system_t *sys,
+                               const emin_params_t *prm, int32_t nlevels, int64_t min_dofs,
+                               int64_t *ticket);
+emin_status emin_server_poll(emin_server_t *srv, int64_t ticket, int32_t *done);
+/* Blocks until the request completes; returns its build status. queue_ms =
+ * submit to start, run_ms = start to completion (host clock). */
+emin_status emin_server_wait(emin_server_t *srv, int64_t ticket, emin_hierarchy_t **result,
+                             double *queue_ms, double *run_ms);
+emin_status emin_server_release(emin_server_t *srv, int64_t ticket);
+emin_status emin_server_stats(emin_server_t *srv, int64_t *in_use, int32_t *queued,
+                              int32_t *running);
+void emin_server_destroy(emin_server_t *srv);
 
 /* Kernel-class profiling with HIP events recorded on the launch stream
  * around each instrumented kernel.  Disabled by default.  collect

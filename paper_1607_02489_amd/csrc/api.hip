@@ -49,6 +49,20 @@ struct emin_pattern_s {
   emin_sizes_t sizes{};
 };
 
+static thread_local std::string g_last_error;
+
+void emin::set_last_error(const char* msg) { g_last_error = msg ? msg : ""; }
+
+__global__ void k_zero_words(uint32_t* p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+void emin::zero_bytes(void* p, size_t bytes, hipStream_t s) {
+  const int64_t n = (int64_t)(bytes / 4);
+  if (n) k_zero_words<<<nblocks(n, 256), 256, 0, s>>>(static_cast<uint32_t*>(p), n);
+}
+
 namespace {
 
 __global__ void k_fp_probe(const double* x, double* sq, double* rc, int64_t n) {
@@ -294,7 +308,8 @@ void run_setup(emin_pattern_t* h, const emin_system_t* sys, const emin_params_t*
   if ((h->sizes.nnz_Pv && !Pv) || (h->sizes.nnz_Pp && !Pp)) throw Error(EMIN_ERR_ARG, "NULL P");
   const CsrView A = in_view(sys->Ahat), B = in_view(sys->Bdiv);
   emin_report_t* r = rep ? rep : h->rep_internal;
-  HIP_OK(hipMemsetAsync(r, 0, sizeof(emin_report_t), s));
+  // a kernel, not a memset node: this path may be captured into a graph
+  zero_bytes(r, sizeof(emin_report_t), s);
   // energy operators on the stored drop masks
   gather_values(B.val, h->bt_src, h->BT.val, h->BT.nnz, s);
   spgemm_numeric(B, view(h->BT), h->Z, h->zplan, s);
@@ -378,6 +393,7 @@ emin_status guarded(F&& f) {
     f();
     return EMIN_OK;
   } catch (const Error& e) {
+    set_last_error(e.what());
     return e.code;
   } catch (const std::bad_alloc&) {
     return EMIN_ERR_OOM;
@@ -408,6 +424,7 @@ emin_status emin_pattern(const emin_system_t* sys, const emin_params_t* prm, voi
     }
     return st;
   }
+  set_last_error("");
   *out = h;
   return EMIN_OK;
 }
@@ -491,7 +508,6 @@ emin_status emin_memcpy_d2h(void* dst, const void* src, size_t bytes, void* stre
 
 void emin_pattern_destroy(emin_pattern_t* h) {
   if (!h) return;
-  (void)hipDeviceSynchronize();
   delete h;
 }
 
@@ -514,6 +530,8 @@ const char* emin_status_string(emin_status s) {
 }
 
 const char* emin_version(void) { return "emin-mi355x 0.1.0 (gfx950)"; }
+
+const char* emin_last_error(void) { return g_last_error.c_str(); }
 
 emin_status emin_fp_probe(const double* x, double* out_sqrt, double* out_rcp, int64_t n,
                           void* stream) {

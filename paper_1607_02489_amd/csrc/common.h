@@ -39,22 +39,28 @@ enum DevErr : int {
 // ---------------------------------------------------------------------------
 // device memory owned by a handle
 // ---------------------------------------------------------------------------
+// Process-wide cache of device chunks: handles return their chunks here
+// instead of calling hipFree (which would wait for the whole device), and new
+// handles take cached chunks first.  emin_release_cached() frees the cache.
+void* chunk_get(size_t bytes);
+void chunk_put(void* p, size_t bytes);
+
 class Arena {
  public:
   Arena() = default;
   Arena(const Arena&) = delete;
   Arena& operator=(const Arena&) = delete;
   ~Arena() { release(); }
-  // bump allocation from 64 MiB chunks (few hipMalloc calls per handle)
+  // bump allocation from 64 MiB chunks (few allocations per handle)
   template <class T>
   T* alloc(size_t n) {
     size_t b = (n ? n : 1) * sizeof(T);
     b = (b + 255) & ~size_t(255);
     if (b > left_) {
       const size_t chunk = b > kChunk ? b : kChunk;
-      void* p = nullptr;
-      if (hipMalloc(&p, chunk) != hipSuccess) throw Error(EMIN_ERR_OOM, "hipMalloc failed");
-      ptrs_.push_back(p);
+      void* p = chunk_get(chunk);
+      if (!p) throw Error(EMIN_ERR_OOM, "device allocation failed");
+      chunks_.push_back({p, chunk});
       bytes_ += chunk;
       cur_ = static_cast<char*>(p);
       left_ = chunk;
@@ -64,9 +70,10 @@ class Arena {
     left_ -= b;
     return static_cast<T*>(r);
   }
+  // the caller guarantees that no queued work still uses the memory
   void release() {
-    for (void* p : ptrs_) (void)hipFree(p);
-    ptrs_.clear();
+    for (auto& c : chunks_) chunk_put(c.first, c.second);
+    chunks_.clear();
     bytes_ = 0;
     cur_ = nullptr;
     left_ = 0;
@@ -75,7 +82,7 @@ class Arena {
 
  private:
   static constexpr size_t kChunk = size_t(64) << 20;
-  std::vector<void*> ptrs_;
+  std::vector<std::pair<void*, size_t>> chunks_;
   size_t bytes_ = 0;
   char* cur_ = nullptr;
   size_t left_ = 0;
@@ -107,6 +114,12 @@ inline T d2h(const T* p, hipStream_t s) {
   HIP_OK(hipStreamSynchronize(s));
   return v;
 }
+
+// message of the last error raised on this thread (emin_last_error)
+void set_last_error(const char* msg);
+
+// zero a device buffer with a kernel (graph-capturable; bytes % 4 == 0)
+void zero_bytes(void* p, size_t bytes, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // sparse building blocks (sparse.hip)

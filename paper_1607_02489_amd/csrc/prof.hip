@@ -1,6 +1,7 @@
 // HIP-event profiler of kernel classes (see prof.h).
 #include "prof.h"
 
+#include <map>
 #include <mutex>
 
 namespace emin {
@@ -34,6 +35,8 @@ hipEvent_t get_event() {
 bool enabled() { return on; }
 
 int begin(hipStream_t s, int kind, double bytes, double flops) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return -1;
   std::lock_guard<std::mutex> g(mu);
   Rec r{kind, bytes, flops, get_event(), get_event()};
   HIP_OK(hipEventRecord(r.e0, s));
@@ -49,7 +52,45 @@ void end(int token, hipStream_t s) {
 }  // namespace prof
 }  // namespace emin
 
+namespace emin {
+namespace {
+std::mutex cache_mu;
+std::multimap<size_t, void*> cache;
+}  // namespace
+
+void* chunk_get(size_t bytes) {
+  {
+    std::lock_guard<std::mutex> g(cache_mu);
+    auto it = cache.find(bytes);
+    if (it != cache.end()) {
+      void* p = it->second;
+      cache.erase(it);
+      return p;
+    }
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  return p;
+}
+
+void chunk_put(void* p, size_t bytes) {
+  std::lock_guard<std::mutex> g(cache_mu);
+  cache.emplace(bytes, p);
+}
+}  // namespace emin
+
 extern "C" {
+
+int64_t emin_release_cached(void) {
+  std::lock_guard<std::mutex> g(emin::cache_mu);
+  int64_t freed = 0;
+  for (auto& kv : emin::cache) {
+    (void)hipFree(kv.second);
+    freed += (int64_t)kv.first;
+  }
+  emin::cache.clear();
+  return freed;
+}
 
 emin_status emin_profile_enable(int enable) {
   std::lock_guard<std::mutex> g(emin::prof::mu);

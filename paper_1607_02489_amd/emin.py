@@ -24,14 +24,24 @@ STATUS = ["OK", "ERR_ARG", "ERR_SHAPE", "ERR_PATTERN", "ERR_VALUE", "ERR_INFEASI
           "ERR_BREAKDOWN", "ERR_BUDGET", "ERR_DEVICE", "ERR_OOM", "ERR_CAPACITY", "ERR_COLOCATE"]
 SYMBOLS = ["emin_pattern", "emin_pattern_info", "emin_pattern_view", "emin_setup", "emin_rap",
            "emin_sync_report", "emin_memcpy_d2h", "emin_pattern_destroy", "emin_status_string",
-           "emin_version", "emin_fp_probe", "emin_profile_enable", "emin_profile_collect"]
+           "emin_version", "emin_last_error", "emin_fp_probe", "emin_release_cached", "emin_profile_enable", "emin_profile_collect",
+           "emin_hierarchy_build", "emin_hierarchy_resetup", "emin_hierarchy_info",
+           "emin_hierarchy_level", "emin_hierarchy_device_bytes", "emin_hierarchy_destroy",
+           "emin_hierarchy_build_batch", "emin_batch_create", "emin_batch_run",
+           "emin_batch_destroy", "emin_server_create", "emin_server_submit", "emin_server_poll",
+           "emin_server_wait", "emin_server_release", "emin_server_stats", "emin_server_destroy"]
 PROF_KINDS = ["spmm", "update", "spgemm", "alg3", "alg4", "vpattern", "r6", "r7"]
 
 
 class EminError(RuntimeError):
     def __init__(self, status, where=""):
         name = STATUS[status] if 0 <= status < len(STATUS) else str(status)
-        super().__init__(f"{where}: {name}")
+        detail = ""
+        try:
+            detail = lib().emin_last_error().decode(errors="replace")
+        except Exception:
+            pass
+        super().__init__(f"{where}: {name}" + (f" ({detail})" if detail else ""))
         self.status = status
 
 
@@ -103,7 +113,37 @@ def lib():
         L.emin_status_string.argtypes = [C.c_int]
         L.emin_status_string.restype = C.c_char_p
         L.emin_version.restype = C.c_char_p
+        L.emin_last_error.restype = C.c_char_p
+        L.emin_release_cached.restype = C.c_int64
         L.emin_fp_probe.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+        L.emin_hierarchy_build.argtypes = [P(c_system), P(c_params), C.c_int32, C.c_int64,
+                                           C.c_void_p, P(C.c_void_p)]
+        L.emin_hierarchy_resetup.argtypes = [C.c_void_p, P(c_system), C.c_void_p]
+        L.emin_hierarchy_info.argtypes = [C.c_void_p, P(C.c_int32), P(c_sizes), C.c_int32]
+        L.emin_hierarchy_level.argtypes = [C.c_void_p, C.c_int32, P(C.c_void_p), P(C.c_void_p),
+                                           P(C.c_void_p), P(C.c_void_p), P(C.c_void_p),
+                                           P(C.c_void_p)]
+        L.emin_hierarchy_device_bytes.argtypes = [C.c_void_p]
+        L.emin_hierarchy_device_bytes.restype = C.c_int64
+        L.emin_hierarchy_destroy.argtypes = [C.c_void_p]
+        L.emin_hierarchy_destroy.restype = None
+        L.emin_hierarchy_build_batch.argtypes = [P(P(c_system)), C.c_int32, P(c_params), C.c_int32,
+                                                 C.c_int64, C.c_int32, P(C.c_void_p)]
+        L.emin_batch_create.argtypes = [P(C.c_void_p), P(P(c_system)), C.c_int32, C.c_void_p,
+                                        P(C.c_void_p)]
+        L.emin_batch_run.argtypes = [C.c_void_p, C.c_void_p]
+        L.emin_batch_destroy.argtypes = [C.c_void_p]
+        L.emin_batch_destroy.restype = None
+        L.emin_server_create.argtypes = [C.c_int64, C.c_int32, P(C.c_void_p)]
+        L.emin_server_submit.argtypes = [C.c_void_p, P(c_system), P(c_params), C.c_int32,
+                                         C.c_int64, P(C.c_int64)]
+        L.emin_server_poll.argtypes = [C.c_void_p, C.c_int64, P(C.c_int32)]
+        L.emin_server_wait.argtypes = [C.c_void_p, C.c_int64, P(C.c_void_p), P(C.c_double),
+                                       P(C.c_double)]
+        L.emin_server_release.argtypes = [C.c_void_p, C.c_int64]
+        L.emin_server_stats.argtypes = [C.c_void_p, P(C.c_int64), P(C.c_int32), P(C.c_int32)]
+        L.emin_server_destroy.argtypes = [C.c_void_p]
+        L.emin_server_destroy.restype = None
         L.emin_profile_enable.argtypes = [C.c_int]
         L.emin_profile_collect.argtypes = [P(c_kstat), C.c_int32]
         _lib = L
@@ -126,6 +166,13 @@ def _stream(stream):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return C.c_void_p(s.cuda_stream)
+
+
+def _sync():
+    """Waits for all queued device work (before a handle's memory is reused)."""
+    import torch
+    if torch.cuda.is_available():
+        torch.cuda.synchronize()
 
 
 def d2h(ptr, n, dtype, stream=None) -> np.ndarray:
@@ -224,6 +271,7 @@ class Pattern:
 
     def close(self):
         if self.h:
+            _sync()
             lib().emin_pattern_destroy(self.h)
             self.h = None
 
@@ -319,3 +367,166 @@ class Hierarchy:
         for L in reversed(self.levels):
             L.pattern.close()
         self.levels = []
+
+
+# ----------------------------------------------------------------------------
+# native hierarchies, batches and the serving loop
+# ----------------------------------------------------------------------------
+class HierarchyView:
+    """Read access to a native hierarchy's levels (borrowed device pointers)."""
+
+    def __init__(self, h):
+        self.h = h
+
+    def ntransfers(self) -> int:
+        n = C.c_int32()
+        _check(lib().emin_hierarchy_info(self.h, C.byref(n), None, 0), "emin_hierarchy_info")
+        return n.value
+
+    def sizes(self):
+        n = self.ntransfers()
+        arr = (c_sizes * max(n, 1))()
+        k = C.c_int32()
+        _check(lib().emin_hierarchy_info(self.h, C.byref(k), arr, n), "emin_hierarchy_info")
+        return [arr[i].as_dict() for i in range(n)]
+
+    def level_host(self, level):
+        """Host copies (Pv, Pp, Ac, Bc values) of one transfer level."""
+        p, pv, pp, ac, bc, rep = (C.c_void_p() for _ in range(6))
+        _check(lib().emin_hierarchy_level(self.h, level, C.byref(p), C.byref(pv), C.byref(pp),
+                                          C.byref(ac), C.byref(bc), C.byref(rep)),
+               "emin_hierarchy_level")
+        z = self.sizes()[level]
+        return dict(Pv=d2h(pv.value, z["nnz_Pv"], np.float64),
+                    Pp=d2h(pp.value, z["nnz_Pp"], np.float64),
+                    Ac=d2h(ac.value, z["nnz_Ac"], np.float64),
+                    Bc=d2h(bc.value, z["nnz_Bc"], np.float64), pattern=p.value,
+                    report=rep.value)
+
+    def device_bytes(self) -> int:
+        return int(lib().emin_hierarchy_device_bytes(self.h))
+
+
+class NativeHierarchy(HierarchyView):
+    """emin_hierarchy_build: every level built by the library's C++ driver."""
+
+    def __init__(self, dsys: DeviceSystem, prm: c_params, nlevels: int, min_dofs: int = 0,
+                 stream=None, handle=None):
+        self.dsys = dsys
+        self._c = dsys.c()
+        if handle is None:
+            h = C.c_void_p()
+            _check(lib().emin_hierarchy_build(C.byref(self._c), C.byref(prm), nlevels, min_dofs,
+                                              _stream(stream), C.byref(h)),
+                   "emin_hierarchy_build")
+            handle = h
+        super().__init__(handle)
+
+    def resetup(self, stream=None, dsys: DeviceSystem = None):
+        if dsys is not None:
+            self.dsys, self._c = dsys, dsys.c()
+        _check(lib().emin_hierarchy_resetup(self.h, C.byref(self._c), _stream(stream)),
+               "emin_hierarchy_resetup")
+
+    def close(self):
+        if self.h:
+            _sync()
+            lib().emin_hierarchy_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_batch(dsystems, prm: c_params, nlevels: int, min_dofs: int = 0, max_parallel: int = 16):
+    n = len(dsystems)
+    cs = [d.c() for d in dsystems]
+    ptrs = (C.POINTER(c_system) * n)(*[C.pointer(c) for c in cs])
+    out = (C.c_void_p * n)()
+    _check(lib().emin_hierarchy_build_batch(ptrs, n, C.byref(prm), nlevels, min_dofs,
+                                            max_parallel, out), "emin_hierarchy_build_batch")
+    return [NativeHierarchy(d, prm, nlevels, min_dofs, handle=C.c_void_p(out[i]))
+            for i, d in enumerate(dsystems)]
+
+
+class Batch:
+    """All numeric phases of several hierarchies captured as one hipGraph."""
+
+    def __init__(self, hierarchies, stream=None):
+        self.hs = hierarchies
+        n = len(hierarchies)
+        self._cs = [h._c for h in hierarchies]
+        hp = (C.c_void_p * n)(*[h.h for h in hierarchies])
+        sp = (C.POINTER(c_system) * n)(*[C.pointer(c) for c in self._cs])
+        b = C.c_void_p()
+        _check(lib().emin_batch_create(hp, sp, n, _stream(stream), C.byref(b)), "emin_batch_create")
+        self.b = b
+
+    def run(self, stream=None):
+        _check(lib().emin_batch_run(self.b, _stream(stream)), "emin_batch_run")
+
+    def close(self):
+        if self.b:
+            lib().emin_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """The serving loop: admission by device-memory budget, worker streams."""
+
+    def __init__(self, budget_bytes: int, slots: int):
+        s = C.c_void_p()
+        _check(lib().emin_server_create(int(budget_bytes), slots, C.byref(s)), "emin_server_create")
+        self.s = s
+        self._borrowed = {}
+
+    def submit(self, dsys: DeviceSystem, prm: c_params, nlevels: int, min_dofs: int = 0) -> int:
+        c = dsys.c()
+        t = C.c_int64()
+        _check(lib().emin_server_submit(self.s, C.byref(c), C.byref(prm), nlevels, min_dofs,
+                                        C.byref(t)), "emin_server_submit")
+        self._borrowed[t.value] = (dsys, c)
+        return t.value
+
+    def done(self, ticket) -> bool:
+        d = C.c_int32()
+        _check(lib().emin_server_poll(self.s, ticket, C.byref(d)), "emin_server_poll")
+        return bool(d.value)
+
+    def wait(self, ticket):
+        h = C.c_void_p()
+        q, r = C.c_double(), C.c_double()
+        _check(lib().emin_server_wait(self.s, ticket, C.byref(h), C.byref(q), C.byref(r)),
+               "emin_server_wait")
+        return HierarchyView(h), q.value, r.value
+
+    def release(self, ticket):
+        _check(lib().emin_server_release(self.s, ticket), "emin_server_release")
+        self._borrowed.pop(ticket, None)
+
+    def stats(self):
+        m, q, r = C.c_int64(), C.c_int32(), C.c_int32()
+        _check(lib().emin_server_stats(self.s, C.byref(m), C.byref(q), C.byref(r)),
+               "emin_server_stats")
+        return dict(in_use=m.value, queued=q.value, running=r.value)
+
+    def close(self):
+        if self.s:
+            lib().emin_server_destroy(self.s)
+            self.s = None
+            self._borrowed.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

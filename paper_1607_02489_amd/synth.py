@@ -207,7 +207,7 @@ def _velocity_coords(dim, n, V, pnodes_vertices):
 # ---------------------------------------------------------------------------
 # assembly
 # ---------------------------------------------------------------------------
-def _assemble(dim, n, V, nu, wind_fn, chunk=4096):
+def _assemble(dim, n, V, nu, wind_fn, chunk=4096, split=False):
     nv1 = 2 * n + 1
     n_v = nv1 ** dim
     n_p = (n + 1) ** dim
@@ -222,7 +222,7 @@ def _assemble(dim, n, V, nu, wind_fn, chunk=4096):
     wq = _quad_weights(dim)
 
     xv = np.zeros((n_v, dim))
-    rowsA, colsA, valsA = [], [], []
+    rowsA, colsA, valsA, valsK = [], [], [], []
     rowsB, colsB, valsB = [], [], []
     for e0 in range(0, ne, chunk):
         e1 = min(ne, e0 + chunk)
@@ -243,16 +243,21 @@ def _assemble(dim, n, V, nu, wind_fn, chunk=4096):
         Gt = gw.transpose(0, 2, 1, 3).reshape(E_, nbv, nq * dim)
         Gm = gphys.transpose(0, 1, 3, 2).reshape(E_, nq * dim, nbv)
         Ke = nu * np.matmul(Gt, Gm)
+        Kc = None
         if wind_fn is not None:
             xn = xv[vn]                                        # node coords [E,nbv,d]
             Wn = wind_fn(xn)                                   # nodal wind [E,nbv,d]
             wqv = np.matmul(Vq[None], Wn)                      # wind at qp [E,nq,d]
             adv = np.matmul(gphys, wqv[:, :, :, None])[..., 0]  # w . grad(phi_j) [E,nq,nbv]
             # Ke_ij += sum_q w_q |J| phi_i(q) adv_qj
-            Ke = Ke + np.matmul((Vq[None] * wdet[:, :, None]).transpose(0, 2, 1), adv)
+            Kc = np.matmul((Vq[None] * wdet[:, :, None]).transpose(0, 2, 1), adv)
+            if not split:
+                Ke = Ke + Kc
         rowsA.append(np.repeat(vn, nbv, axis=1).reshape(-1))
         colsA.append(np.tile(vn, (1, nbv)).reshape(-1))
         valsA.append(Ke.reshape(-1))
+        if split:
+            valsK.append((Kc if Kc is not None else np.zeros_like(Ke)).reshape(-1))
         # b_{c,k,i} = int psi_k dphi_i/dx_c  ->  (E, nbp, nq) @ (E, nq, nbv) per c
         Pw = (Pq[None] * wdet[:, :, None]).transpose(0, 2, 1)  # [E,nbp,nq]
         for c in range(dim):
@@ -265,6 +270,14 @@ def _assemble(dim, n, V, nu, wind_fn, chunk=4096):
     B = sp.coo_matrix((np.concatenate(valsB), (np.concatenate(rowsB), np.concatenate(colsB))),
                       shape=(n_p, dim * n_v)).tocsr()
     A.sum_duplicates(); B.sum_duplicates()
+    if split:
+        # same COO indices -> same CSR structure, convection values aligned
+        K = sp.coo_matrix((np.concatenate(valsK), (np.concatenate(rowsA), np.concatenate(colsA))),
+                          shape=(n_v, n_v)).tocsr()
+        K.sum_duplicates()
+        A.sort_indices(); K.sort_indices()
+        assert np.array_equal(A.indptr, K.indptr) and np.array_equal(A.indices, K.indices)
+        return A, B, xv, K
     return A, B, xv
 
 
@@ -409,6 +422,65 @@ def make_system(dim: int, n: int, *, jitter: float = 0.0, seed: int = 0,
                   meta=dict(n=n, jitter=jitter, seed=seed, nu=nu, wind=wind,
                             wind_seed=wind_seed, domain=domain,
                             dirichlet=int(dmask.sum())))
+
+
+def make_split_system(dim: int, n: int, *, jitter: float = 0.0, seed: int = 0,
+                      wind: str = "channel", wind_seed: int | None = None,
+                      domain: str = "channel") -> System:
+    """An Oseen system whose velocity block is kept as two value arrays on one
+    structure: the Laplacian part A_S and the convection part K, so that
+    nu*A_S + K can be formed for any viscosity without re-assembly.  Ahat
+    holds A_S + K; meta['S_val'] and meta['K_val'] hold the parts."""
+    rng = np.random.default_rng(seed)
+    V = _vertices(dim, n, jitter, rng)
+    wrng = np.random.default_rng(seed if wind_seed is None else wind_seed)
+    pert = stream_wind_3d(wrng) if dim == 3 else stream_wind_2d(wrng)
+    if wind == "channel":
+        def raw(x, pert=pert):
+            out = 0.25 * pert(x)
+            if dim == 3:
+                prof = 16.0 * x[..., 1] * (1 - x[..., 1]) * x[..., 2] * (1 - x[..., 2])
+            else:
+                prof = 4.0 * x[..., 1] * (1 - x[..., 1])
+            out[..., 0] += prof
+            return out
+    elif wind == "stream":
+        raw = pert
+    else:
+        raise ValueError(wind)
+    A, B, xv, K = _assemble(dim, n, V, 1.0, _scaled(raw, dim, n), split=True)
+    m = 2 * n + 1
+    lat = _lattice_index(dim, m)
+    if domain == "cavity":
+        dmask = np.any((lat == 0) | (lat == m - 1), axis=1)
+    else:
+        side = np.any((lat[:, 1:] == 0) | (lat[:, 1:] == m - 1), axis=1)
+        dmask = side | (lat[:, 0] == 0)
+    rows = np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
+    cols = A.indices
+    elim = dmask[rows] | dmask[cols]
+    diag = rows == cols
+    Sv = np.where(elim, 0.0, A.data)
+    Kv = np.where(elim, 0.0, K.data)
+    Sv = np.where(elim & diag, 1.0, Sv)
+    # joint pruning keeps one structure for both parts
+    mag = np.abs(Sv) + np.abs(Kv)
+    rmax = np.zeros(A.shape[0])
+    np.maximum.at(rmax, rows, mag)
+    keep = mag > 1e-14 * rmax[rows]
+    rp = np.concatenate([[0], np.cumsum(np.bincount(rows[keep], minlength=A.shape[0]))])
+    Ahat = CSR(A.shape[0], A.shape[1], rp.astype(np.int64), cols[keep].astype(np.int32),
+               (Sv + Kv)[keep])
+    keepB = sp.diags(np.tile((~dmask).astype(np.float64), dim))
+    Bd = _prune((B @ keepB).tocsr())
+    plat = _lattice_index(dim, n + 1)
+    if dim == 2:
+        p2v = 2 * plat[:, 0] + m * (2 * plat[:, 1])
+    else:
+        p2v = 2 * plat[:, 0] + m * (2 * plat[:, 1]) + m * m * (2 * plat[:, 2])
+    return System(dim, Ahat, CSR.from_scipy(Bd), np.ascontiguousarray(xv), p2v.astype(np.int32),
+                  meta=dict(n=n, seed=seed, wind=wind, domain=domain, S_val=Sv[keep],
+                            K_val=Kv[keep], dirichlet=int(dmask.sum())))
 
 
 # ---------------------------------------------------------------------------

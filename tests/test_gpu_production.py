@@ -1,0 +1,136 @@
+"""GPU tests of the production forms: the native hierarchy driver, batched
+builds with a graph-captured numeric phase, and the serving loop.  Every
+result must equal the same request built alone (the kernels are
+deterministic, so bit for bit)."""
+import numpy as np
+import pytest
+
+from paper_1607_02489_amd import synth
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _levels(view):
+    return [view.level_host(l) for l in range(view.ntransfers())]
+
+
+def _same(la, lb):
+    assert len(la) == len(lb)
+    for a, b in zip(la, lb):
+        for k in ("Pv", "Pp", "Ac", "Bc"):
+            assert np.array_equal(a[k], b[k]), k
+
+
+def _systems():
+    out = []
+    for i, (n, re_) in enumerate([(12, 10.0), (16, 100.0), (20, 1.0), (9, 300.0), (24, 50.0),
+                                  (14, 500.0)]):
+        out.append(synth.make_system(2, n, nu=1.0 / re_, wind="stream", seed=1000 + i))
+    return out
+
+
+def test_native_hierarchy_matches_level_calls():
+    import torch
+    from paper_1607_02489_amd import emin as E
+    s = synth.oseen2d(32)
+    prm = E.params(iters=5)
+    H = E.Hierarchy(s, 4, prm).build()
+    torch.cuda.synchronize()
+    N = E.NativeHierarchy(H.fine, prm, 4)
+    torch.cuda.synchronize()
+    assert N.ntransfers() == len(H.levels)
+    for l, L in enumerate(H.levels):
+        got = N.level_host(l)
+        assert np.array_equal(got["Pv"], L.Pv.cpu().numpy()[:L.pattern.sizes["nnz_Pv"]])
+        assert np.array_equal(got["Ac"], L.Ac.cpu().numpy()[:L.pattern.sizes["nnz_Ac"]])
+    N.close()
+    H.close()
+
+
+def test_batch_build_equals_alone():
+    import torch
+    from paper_1607_02489_amd import emin as E
+    systems = _systems()
+    prm = E.params(iters=5, mixed=True)
+    ds = [E.DeviceSystem.upload(s) for s in systems]
+    say(f"[gpu] batch build of {len(ds)} systems")
+    hs = E.build_batch(ds, prm, 4, min_dofs=200, max_parallel=len(ds))
+    torch.cuda.synchronize()
+    for d, h in zip(ds, hs):
+        alone = E.NativeHierarchy(d, prm, 4, min_dofs=200)
+        torch.cuda.synchronize()
+        _same(_levels(h), _levels(alone))
+        alone.close()
+    for h in hs:
+        h.close()
+
+
+def test_batch_graph_replays_match_eager():
+    """The captured numeric phase of several hierarchies, replayed after the
+    level-0 values change (new Picard linearisations), equals an eager
+    re-setup of twin hierarchies; replays alternate with other eager work."""
+    import torch
+    from paper_1607_02489_amd import emin as E
+    systems = _systems()[:4]
+    prm = E.params(iters=5)
+    ds = [E.DeviceSystem.upload(s) for s in systems]
+    hs = E.build_batch(ds, prm, 3, max_parallel=4)
+    twins = [E.NativeHierarchy(d, prm, 3) for d in ds]
+    torch.cuda.synchronize()
+    B = E.Batch(hs)
+    for rep in range(3):
+        for d in ds:
+            d.keep[2].mul_(1.0 + 0.01 * (rep + 1))       # Ahat values, in place
+        torch.cuda.synchronize()
+        B.run()
+        for t in twins:
+            t.resetup()
+        torch.cuda.synchronize()
+        for h, t in zip(hs, twins):
+            _same(_levels(h), _levels(t))
+    B.close()
+    for h in hs + twins:
+        h.close()
+
+
+def test_server_mix_equals_alone_and_fifo_admission():
+    import time
+    import torch
+    from paper_1607_02489_amd import emin as E
+    systems = _systems()
+    prm = E.params(iters=5, mixed=True)
+    ds = [E.DeviceSystem.upload(s) for s in systems]
+    alone = []
+    for d in ds:
+        h = E.NativeHierarchy(d, prm, 4, min_dofs=200)
+        torch.cuda.synchronize()
+        alone.append(_levels(h))
+        h.close()
+    # a budget that fits about two requests at a time forces queueing
+    srv = E.Server(budget_bytes=3 * (64 << 20) * 5, slots=3)
+    t0 = time.perf_counter()
+    tickets, submitted = [], []
+    for d in ds + ds:
+        tickets.append(srv.submit(d, prm, 4, min_dofs=200))
+        submitted.append(time.perf_counter() - t0)
+    starts = []
+    for i, t in enumerate(tickets):
+        view, q_ms, r_ms = srv.wait(t)
+        starts.append(submitted[i] + q_ms * 1e-3)
+        _same(_levels(view), alone[i % len(ds)])
+        srv.release(t)
+    # admission in arrival order (start times follow ticket order up to clock noise)
+    assert all(b >= a - 5e-3 for a, b in zip(starts, starts[1:]))
+    assert srv.stats()["in_use"] == 0
+    srv.close()
+
+
+def test_server_rejects_over_budget():
+    from paper_1607_02489_amd import emin as E
+    srv = E.Server(budget_bytes=1 << 20, slots=1)
+    d = E.DeviceSystem.upload(synth.make_system(2, 8))
+    with pytest.raises(E.EminError) as ei:
+        srv.submit(d, E.params(), 2)
+    assert ei.value.status == 7                      # ERR_BUDGET
+    srv.close()
