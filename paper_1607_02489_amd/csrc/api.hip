@@ -230,8 +230,8 @@ void build_pattern(emin_pattern_t* h, const emin_system_t* sys, const emin_param
   h->ev.smax = (int)max_row_len(h->vp.N.rowptr, nv, s, ar);
   h->ep.smax = (int)max_row_len(h->cp.N.rowptr, np, s, ar);
   if (h->ev.smax > 64 || h->ep.smax > 64) throw Error(EMIN_ERR_CAPACITY, "pattern row > 64");
-  h->ev.make_bins(h->vp.N.rowptr, s, ar);
-  h->ep.make_bins(h->cp.N.rowptr, s, ar);
+  h->ev.make_bins(h->Mv, h->vp.N.rowptr, h->vp.N.col, s, ar);
+  h->ep.make_bins(h->Mp, h->cp.N.rowptr, h->cp.N.col, s, ar);
   h->Mvf = ar.alloc<float>(h->Mv.nnz);
   h->Mpf = ar.alloc<float>(h->Mp.nnz);
   h->Wv_def = ar.alloc<double>(nv);

@@ -16,6 +16,7 @@ struct CoarsenArgs {
   uint8_t* st = nullptr;          // ST_*
   int32_t* cnt = nullptr;         // C points within distance 4
   double* rs = nullptr;           // sum of 1/|x_j - x_c| over those C points
+  double* hkey = nullptr;         // h1 = cnt/rs of a candidate, +inf otherwise
   int32_t* s_cnt = nullptr;       // |S_j|
   int32_t* s_c = nullptr;         // S_j entries (n*scap), insertion order until sorted
   uint8_t* s_d = nullptr;         // their graph distances

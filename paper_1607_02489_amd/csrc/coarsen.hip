@@ -141,6 +141,17 @@ __device__ __forceinline__ void mark_dirty(int b, uint32_t* dbits, int32_t* dlis
   }
 }
 
+__global__ void k_fill_inf(double* a, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = __builtin_inf();
+}
+
+// One greedy step costs a few dependent memory round trips, so the loop is
+// arranged to keep that chain short: the new C point's ball is fetched
+// together with its size, every per-vertex field a ball entry needs is loaded
+// before any is stored, and the heuristic key of each candidate (h1 = cnt/rs,
+// +inf for a non-candidate) is kept in its own array so that refreshing a
+// block's minimum is a single coalesced read.
 __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
   extern __shared__ unsigned char lds_raw[];
   double* bkey = reinterpret_cast<double*>(lds_raw);
@@ -148,47 +159,74 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
   uint32_t* dbits = reinterpret_cast<uint32_t*>(bidx + D.nblk);
   int32_t* dlist = reinterpret_cast<int32_t*>(dbits + ((D.nblk + 31) / 32));
   __shared__ int err_sh, dn_sh, dall_sh, nc_sh, cursor_sh, found_sh;
-  __shared__ int32_t k_sh;
   __shared__ double wkey[A3_WAVES];
   __shared__ int32_t widx[A3_WAVES];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const double INF = __builtin_inf();
   const int64_t n = D.n;
+  const int dim = D.dim;
 
   for (int b = tid; b < D.nblk; b += A3_BS) { bkey[b] = INF; bidx[b] = INT32_MAX; }
   for (int b = tid; b < (D.nblk + 31) / 32; b += A3_BS) dbits[b] = 0u;
-  if (tid == 0) {
-    err_sh = 0; dn_sh = 0; dall_sh = 0; nc_sh = 0; cursor_sh = 0;
-    k_sh = n > 0 ? 0 : -1;   // Alg. 3's "arbitrary vertex": vertex 0
-  }
+  if (tid == 0) { err_sh = 0; dn_sh = 0; dall_sh = 0; nc_sh = 0; cursor_sh = 0; }
   __syncthreads();
 
-  while (true) {
-    const int32_t k = k_sh;
-    if (k < 0) break;
-    const int nb = D.bsize[k];
+  int32_t k = n > 0 ? 0 : -1;   // Alg. 3's "arbitrary vertex": vertex 0
+  while (k >= 0) {
     const int32_t* bl = D.balls + (int64_t)k * D.bmax;
+    const int32_t e0 = tid < D.bmax ? bl[tid] : 0;
+    const int nb = D.bsize[k];
+    double xk[3] = {0.0, 0.0, 0.0};
+    for (int d = 0; d < dim; d++) xk[d] = D.x[(int64_t)k * dim + d];
+    const int nc0 = nc_sh;
     // S_j += {k} for dist <= 3; C/F/Cand update; update_heuristics
     for (int t = tid; t < nb; t += A3_BS) {
-      const int32_t e = bl[t];
+      const int32_t e = t == tid ? e0 : bl[t];
       const int32_t v = e & VMASK;
       const int d = (int)((uint32_t)e >> DSHIFT);
-      if (d <= 3) s_append(D, v, k, d, &err_sh);
-      if (d >= 1) {
-        const uint8_t s = D.st[v];
-        if (d <= 3 && (s == ST_U || s == ST_CAND)) D.st[v] = ST_F;
-        if (d == 4 && s == ST_U) D.st[v] = ST_CAND;
-        D.cnt[v] += 1;
-        D.rs[v] = D.rs[v] + 1.0 / euclid(D.x, D.dim, v, k);
+      if (d == 0) {
+        s_append(D, v, k, 0, &err_sh);   // S_k holds k itself
+        D.st[v] = ST_C;
+        D.hkey[v] = INF;
+        D.order[nc0] = v;
         mark_dirty(v / D.vb, dbits, dlist, D.dcap, &dn_sh, &dall_sh);
-      } else {
-        D.st[k] = ST_C;
-        D.order[nc_sh] = k;
-        nc_sh++;
-        mark_dirty(k / D.vb, dbits, dlist, D.dcap, &dn_sh, &dall_sh);
+        continue;
       }
+      // all loads of this entry first
+      const uint8_t s = D.st[v];
+      const int32_t c = D.cnt[v];
+      const double r = D.rs[v];
+      const int32_t sl = D.s_cnt[v];
+      double xv[3] = {0.0, 0.0, 0.0};
+      for (int q = 0; q < dim; q++) xv[q] = D.x[(int64_t)v * dim + q];
+      double ss = 0.0;
+      for (int q = 0; q < dim; q++) {
+        const double tq = xv[q] - xk[q];
+        ss = ss + tq * tq;
+      }
+      const double r1 = r + 1.0 / sqrt(ss);
+      const int32_t c1 = c + 1;
+      uint8_t s1 = s;
+      if (d <= 3 && (s == ST_U || s == ST_CAND)) s1 = ST_F;
+      if (d == 4 && s == ST_U) s1 = ST_CAND;
+      if (d <= 3) {
+        if (sl < D.scap) {
+          D.s_c[(int64_t)v * D.scap + sl] = k;
+          D.s_d[(int64_t)v * D.scap + sl] = (uint8_t)d;
+          D.s_cnt[v] = sl + 1;
+        } else {
+          atomicOr(&err_sh, DERR_CAPACITY);
+        }
+      }
+      if (s1 != s) D.st[v] = s1;
+      D.cnt[v] = c1;
+      D.rs[v] = r1;
+      if (s1 == ST_CAND) D.hkey[v] = (double)c1 / r1;
+      else if (s == ST_CAND) D.hkey[v] = INF;
+      mark_dirty(v / D.vb, dbits, dlist, D.dcap, &dn_sh, &dall_sh);
     }
     __syncthreads();
+    if (tid == 0) nc_sh = nc0 + 1;
     // refresh the minima of the touched blocks
     const bool all = dall_sh != 0;
     const int todo = all ? D.nblk : dn_sh;
@@ -198,9 +236,9 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
       int32_t idx = INT32_MAX;
       for (int u = lane; u < D.vb; u += 64) {
         const int64_t v = (int64_t)b * D.vb + u;
-        if (v < n && D.st[v] == ST_CAND) {
-          const double h1 = (double)D.cnt[v] / D.rs[v];
-          if (lex_less(h1, (int32_t)v, key, idx)) { key = h1; idx = (int32_t)v; }
+        if (v < n) {
+          const double h1 = D.hkey[v];
+          if (h1 < INF && lex_less(h1, (int32_t)v, key, idx)) { key = h1; idx = (int32_t)v; }
         }
       }
       wave_argmin(key, idx);
@@ -209,7 +247,8 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
     __syncthreads();
     for (int b = tid; b < (D.nblk + 31) / 32; b += A3_BS) dbits[b] = 0u;
     if (tid == 0) { dn_sh = 0; dall_sh = 0; }
-    // next k = argmin over Cand of (h1, index)
+    // next k = argmin over Cand of (h1, index); every wave reduces the wave
+    // minima itself, so no further barrier is needed before the next step
     double key = INF;
     int32_t idx = INT32_MAX;
     for (int b = tid; b < D.nblk; b += A3_BS)
@@ -217,19 +256,17 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
     wave_argmin(key, idx);
     if (lane == 0) { wkey[wave] = key; widx[wave] = idx; }
     __syncthreads();
-    if (tid == 0) {
-      double kk = INF;
-      int32_t ii = INT32_MAX;
-      for (int w = 0; w < A3_WAVES; w++)
-        if (lex_less(wkey[w], widx[w], kk, ii)) { kk = wkey[w]; ii = widx[w]; }
-      // an error ends the loop for every thread at the same point
-      k_sh = err_sh ? -1 : ((ii == INT32_MAX) ? -2 : ii);
-      found_sh = INT32_MAX;
-    }
-    __syncthreads();
-    if (k_sh == -2) {
+    key = lane < A3_WAVES ? wkey[lane] : INF;
+    idx = lane < A3_WAVES ? widx[lane] : INT32_MAX;
+    wave_argmin(key, idx);
+    // an error ends the loop for every thread at the same point
+    if (err_sh) break;
+    k = idx;
+    if (k == INT32_MAX) {
       // Cand is empty: the smallest-index unmarked vertex (the cursor only
       // moves forward: marks are permanent)
+      if (tid == 0) found_sh = INT32_MAX;
+      __syncthreads();
       for (int64_t base = cursor_sh; base < n; base += A3_BS) {
         const int64_t v = base + tid;
         if (v < n && D.st[v] == ST_U) atomicMin(&found_sh, (int)v);
@@ -238,11 +275,9 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
         __syncthreads();
         if (f != INT32_MAX) break;
       }
-      if (tid == 0) {
-        k_sh = found_sh == INT32_MAX ? -1 : found_sh;
-        if (found_sh != INT32_MAX) cursor_sh = found_sh;
-      }
+      k = found_sh == INT32_MAX ? -1 : found_sh;
       __syncthreads();
+      if (tid == 0 && k >= 0) cursor_sh = k;
     }
   }
   __syncthreads();
@@ -424,6 +459,7 @@ void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar,
   D.st = ar.alloc<uint8_t>(n);
   D.cnt = ar.alloc<int32_t>(n);
   D.rs = ar.alloc<double>(n);
+  D.hkey = ar.alloc<double>(n);
   D.s_cnt = ar.alloc<int32_t>(n);
   D.s_c = ar.alloc<int32_t>((size_t)n * D.scap);
   D.s_d = ar.alloc<uint8_t>((size_t)n * D.scap);
@@ -432,6 +468,7 @@ void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar,
   HIP_OK(hipMemsetAsync(D.st, 0, n, s));
   HIP_OK(hipMemsetAsync(D.cnt, 0, sizeof(int32_t) * n, s));
   HIP_OK(hipMemsetAsync(D.rs, 0, sizeof(double) * n, s));
+  if (n) k_fill_inf<<<nblocks(n, 256), 256, 0, s>>>(D.hkey, n);
   HIP_OK(hipMemsetAsync(D.s_cnt, 0, sizeof(int32_t) * n, s));
   HIP_OK(hipMemsetAsync(D.meta, 0, sizeof(int32_t) * 4, s));
   // distance-4 balls of every vertex: sizes first, then the lists

@@ -179,13 +179,55 @@ __device__ __forceinline__ double shfl_xor_d(double v, int m) {
 }
 
 // lexicographic (key, index) minimum across a full 64-lane wave
+// Wave-wide reductions on the DPP network (row shifts, then the two row
+// broadcasts), which leave the result in lane 63; it is then read out as a
+// wave-uniform value.  Every lane of the wave must be active.  Lanes whose
+// DPP source lies outside the row (or whose row is masked off) keep the
+// identity passed as "old".
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double ident, double v) {
+  const unsigned long long o = (unsigned long long)__double_as_longlong(ident);
+  const unsigned long long x = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)x, CTRL, ROWS, 0xF,
+                                             false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(x >> 32),
+                                             CTRL, ROWS, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+__device__ __forceinline__ double wave_min_f64(double v) {
+  const double I = __builtin_inf();
+  double t;
+  t = dpp_f64<0x111, 0xF>(I, v); v = t < v ? t : v;   // row_shr:1
+  t = dpp_f64<0x112, 0xF>(I, v); v = t < v ? t : v;   // row_shr:2
+  t = dpp_f64<0x114, 0xF>(I, v); v = t < v ? t : v;   // row_shr:4
+  t = dpp_f64<0x118, 0xF>(I, v); v = t < v ? t : v;   // row_shr:8
+  t = dpp_f64<0x142, 0xA>(I, v); v = t < v ? t : v;   // row_bcast:15
+  t = dpp_f64<0x143, 0xC>(I, v); v = t < v ? t : v;   // row_bcast:31
+  const unsigned long long x = (unsigned long long)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), 63);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ int32_t wave_min_i32(int32_t v) {
+  const int I = INT32_MAX;
+  int t;
+  t = __builtin_amdgcn_update_dpp(I, v, 0x111, 0xF, 0xF, false); v = t < v ? t : v;
+  t = __builtin_amdgcn_update_dpp(I, v, 0x112, 0xF, 0xF, false); v = t < v ? t : v;
+  t = __builtin_amdgcn_update_dpp(I, v, 0x114, 0xF, 0xF, false); v = t < v ? t : v;
+  t = __builtin_amdgcn_update_dpp(I, v, 0x118, 0xF, 0xF, false); v = t < v ? t : v;
+  t = __builtin_amdgcn_update_dpp(I, v, 0x142, 0xA, 0xF, false); v = t < v ? t : v;
+  t = __builtin_amdgcn_update_dpp(I, v, 0x143, 0xC, 0xF, false); v = t < v ? t : v;
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
+// lexicographic (key, index) minimum over the wave, wave-uniform result:
+// the smallest key first, then the smallest index among the lanes holding it
 __device__ __forceinline__ void wave_argmin(double& k, int32_t& i) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    double ok = __shfl_xor(k, m, 64);
-    int32_t oi = __shfl_xor(i, m, 64);
-    if (ok < k || (ok == k && oi < i)) { k = ok; i = oi; }
-  }
+  const double km = wave_min_f64(k);
+  i = wave_min_i32(k == km ? i : INT32_MAX);
+  k = km;
 }
 
 }  // namespace emin

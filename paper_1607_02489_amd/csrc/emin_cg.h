@@ -26,12 +26,22 @@ struct EminWork {
   float *Zf = nullptr, *Qf = nullptr;
   double *part = nullptr, *part_e = nullptr;
   CgScalars* sc = nullptr;
-  // row bins of the masked product by pattern-row length: (0,4], (4,8], ..., (32,64]
+  // row bins of the masked product by pattern-row length: (0,4], (4,8], ..., (32,64];
+  // mbin_*: rows served from precomputed intersection maps (length <= 32),
+  // bin_*: the rest, served by the searching kernel
   static constexpr int NBIN = 5;
   int32_t* bin_rows[NBIN] = {};
   int64_t bin_n[NBIN] = {};
+  int32_t* mbin_rows[NBIN] = {};
+  int64_t mbin_n[NBIN] = {};
+  // intersection maps per M entry: base offset and 4-bit slot fields
+  // (nplanes words of eight fields, plane-major)
+  int32_t* kofs = nullptr;
+  uint32_t* nib = nullptr;
+  int64_t nnzm = 0;
+  int nplanes = 1;
   void allocate(int64_t n, int64_t nnz, int64_t nc, Arena& ar, bool mixed);
-  void make_bins(const int64_t* nrp, hipStream_t s, Arena& ar);
+  void make_bins(const Csr& M, const int64_t* nrp, const int32_t* ncol, hipStream_t s, Arena& ar);
 };
 
 // Y = mask_N(M X) with <D, Y> block partials (D may be NULL); returns the

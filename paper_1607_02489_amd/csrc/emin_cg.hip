@@ -163,6 +163,142 @@ __global__ __launch_bounds__(256) void k_spmm_bin(const int32_t* rows, int64_t n
   }
 }
 
+// Precomputed intersection maps.  For an M entry (i,k), slot s of N_i meets
+// column N_i[s] in row k at position pos(s) (or nowhere).  When row i has at
+// most 32 slots and, over all its M entries, the offsets pos(s) - s of each
+// entry span at most 14, the map of entry e is stored as one base offset into
+// the pattern values, kofs[e] = nrp[k] + min(pos(s) - s), and one 4-bit field
+// per slot, pos(s) - s - min or 15 for "no match", packed eight to a 32-bit
+// word (plane q of the word array holds slots 8q..8q+7).  Rows that do not
+// fit are marked ineligible and keep the searching kernel.
+__global__ void k_spmm_maps(const int64_t* mrp, const int32_t* mcol, const int64_t* nrp,
+                            const int32_t* ncol, int64_t n, int64_t nnzm, int nplanes,
+                            int32_t* kofs, uint32_t* nib, uint8_t* elig) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t na = nrp[i], nb = nrp[i + 1];
+  const int ni = (int)(nb - na);
+  const int planes = ni <= 8 ? 1 : (ni <= 16 ? 2 : 4);
+  bool ok = ni <= 32 && planes <= nplanes;
+  for (int64_t e = mrp[i]; e < mrp[i + 1]; e++) {
+    const int32_t k = mcol[e];
+    const int64_t ka = nrp[k], kb = nrp[k + 1];
+    uint32_t w[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+    int64_t base = 0;
+    if (ok) {
+      // pass 1: range of pos(s) - s
+      int64_t lo = INT64_MAX, hi = INT64_MIN;
+      for (int pass = 0; pass < 2 && ok; pass++) {
+        int64_t a = na, b = ka;
+        while (a < nb && b < kb) {
+          const int32_t ca = ncol[a], cb = ncol[b];
+          if (ca < cb) a++;
+          else if (cb < ca) b++;
+          else {
+            const int64_t off = (b - ka) - (a - na);
+            if (pass == 0) {
+              lo = off < lo ? off : lo;
+              hi = off > hi ? off : hi;
+            } else {
+              const int sl = (int)(a - na);
+              const uint32_t f = (uint32_t)(off - lo);
+              w[sl >> 3] &= ~(0xFu << (4 * (sl & 7)));
+              w[sl >> 3] |= f << (4 * (sl & 7));
+            }
+            a++;
+            b++;
+          }
+        }
+        if (pass == 0) {
+          if (lo == INT64_MAX) break;          // no common column: all fields 15
+          if (hi - lo > 14) ok = false;
+        }
+      }
+      base = lo == INT64_MAX ? 0 : lo;
+    }
+    const int64_t ko = ka + base;
+    if (ko < INT32_MIN + 64 || ko > INT32_MAX - 64) ok = false;
+    kofs[e] = (int32_t)(ok ? ko : 0);
+    for (int q = 0; q < nplanes; q++) nib[(int64_t)q * nnzm + e] = w[q];
+  }
+  elig[i] = ok ? 1 : 0;
+}
+
+// Masked product on the intersection maps: G lanes (G >= |N_i|) own row i,
+// lane s computing slot s.  The group copies M's row (values, base offsets,
+// map words) through a small LDS window with coalesced loads; then for each
+// entry lane s reads its 4-bit field and, on a match, gathers exactly one
+// pattern value, X[kofs + s + field].  No searching and no cross-lane
+// traffic; per-slot sums run over k in order (deterministic).
+template <int G, class TM, class TX, class TY>
+__global__ __launch_bounds__(256) void k_spmm_map(const int32_t* rows, int64_t nrows,
+                                                  const int64_t* mrp, const TM* mval,
+                                                  const int32_t* kofs, const uint32_t* nib,
+                                                  int64_t nnzm, const int64_t* nrp, const TX* X,
+                                                  TY* Y, const double* D, double* part) {
+  using TA = TM;
+  constexpr int NG = 256 / G;
+  constexpr int NP = G <= 8 ? 1 : G / 8;     // map planes of a row
+  constexpr int CH = G < 16 ? 16 : G;        // LDS window (entries) per group
+  constexpr int U = 4;
+  __shared__ TM s_m[NG * CH];
+  __shared__ int32_t s_k[NG * CH];
+  __shared__ uint32_t s_w[NP][NG * CH];
+  __shared__ double lds[4];
+  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const int g = threadIdx.x / G, lane = threadIdx.x % G;
+  const int64_t r = lb * NG + g;
+  const int q = lane >> 3, sh = 4 * (lane & 7);
+  TM* gm = s_m + g * CH;
+  int32_t* gk = s_k + g * CH;
+  double dot = 0.0;
+  if (r < nrows) {
+    const int32_t i = rows[r];
+    const int64_t na = nrp[i];
+    const int ni = (int)(nrp[i + 1] - na);
+    const int64_t ma = mrp[i], mb = mrp[i + 1];
+    TA acc = TA(0);
+    for (int64_t c0 = ma; c0 < mb; c0 += CH) {
+      const int cn = (int)((mb - c0) < CH ? (mb - c0) : CH);
+      for (int t = lane; t < cn; t += G) {
+        gm[t] = mval[c0 + t];
+        gk[t] = kofs[c0 + t];
+#pragma unroll
+        for (int p = 0; p < NP; p++) s_w[p][g * CH + t] = nib[(int64_t)p * nnzm + c0 + t];
+      }
+      // the group lies inside one wave: order its LDS writes before the reads
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const uint32_t* gw = s_w[q] + g * CH;
+      for (int t = 0; t < cn; t += U) {
+        TX x[U];
+        uint32_t f[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          f[u] = t + u < cn ? (gw[t + u] >> sh) & 0xFu : 0xFu;
+          x[u] = f[u] != 0xFu ? X[(int64_t)gk[t + u] + lane + (int)f[u]] : TX(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++)
+          if (f[u] != 0xFu) acc = fma(gm[t + u], (TA)x[u], acc);
+      }
+      // every lane is done with the window before the next pass refills it
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (lane < ni) {
+      Y[na + lane] = (TY)acc;
+      if (D) dot = D[na + lane] * (double)acc;
+    }
+  }
+  if (part) {
+    const double t = block_sum(dot, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+  }
+}
+
 // R = -Pi(MP), Z = R, partial <R,R>
 __global__ void k_init_r(const int64_t* rp, const int32_t* col, int64_t n, const int32_t* cid,
                          const double* Wc, const double* G, const double* MP, double* R,
@@ -329,17 +465,10 @@ void EminWork::allocate(int64_t n_, int64_t nnz_, int64_t nc_, Arena& ar, bool m
   Zf = ar.alloc<float>(nnz);
   Qf = ar.alloc<float>(nnz);
   (void)mixed;
-  const int64_t np = (int64_t)nblocks(n, 4) + 8;  // enough for every grid used
+  const int64_t np = 2 * (int64_t)nblocks(n, 4) + 16;  // enough for every grid used
   part = ar.alloc<double>(np);
   part_e = ar.alloc<double>(np);
   sc = ar.alloc<CgScalars>(1);
-}
-
-__global__ void k_bin_flags(const int64_t* nrp, int64_t n, int lo, int hi, int64_t* f) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int64_t c = nrp[i + 1] - nrp[i];
-  f[i] = (c > lo && c <= hi) ? 1 : 0;
 }
 
 __global__ void k_bin_place(const int64_t* f, int64_t n, int32_t* rows) {
@@ -349,22 +478,56 @@ __global__ void k_bin_place(const int64_t* f, int64_t n, int32_t* rows) {
   if (f[i] != prev) rows[prev] = (int32_t)i;
 }
 
-void EminWork::make_bins(const int64_t* nrp, hipStream_t s, Arena& ar) {
+__global__ void k_bin_flags2(const int64_t* nrp, const uint8_t* elig, int want, int64_t n, int lo,
+                             int hi, int64_t* f) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t c = nrp[i + 1] - nrp[i];
+  f[i] = (c > lo && c <= hi && (int)elig[i] == want) ? 1 : 0;
+}
+
+void EminWork::make_bins(const Csr& M, const int64_t* nrp, const int32_t* ncol, hipStream_t s,
+                         Arena& ar) {
+  nnzm = M.nnz;
+  nplanes = smax <= 8 ? 1 : (smax <= 16 ? 2 : 4);
+  kofs = ar.alloc<int32_t>(M.nnz);
+  nib = ar.alloc<uint32_t>((size_t)M.nnz * nplanes);
+  uint8_t* elig = ar.alloc<uint8_t>(n);
+  if (n)
+    k_spmm_maps<<<nblocks(n, 256), 256, 0, s>>>(M.rowptr, M.col, nrp, ncol, n, M.nnz, nplanes,
+                                                kofs, nib, elig);
   int64_t* f = ar.alloc<int64_t>(n);
-  int lo = 0;
-  for (int b = 0; b < NBIN; b++) {
-    const int hi = 4 << b;
-    bin_n[b] = 0;
-    bin_rows[b] = nullptr;
-    if (n) {
-      k_bin_flags<<<nblocks(n, 256), 256, 0, s>>>(nrp, n, lo, hi, f);
-      scan_inclusive(f, n, s, ar);
-      bin_n[b] = d2h(f + n - 1, s);
-      bin_rows[b] = ar.alloc<int32_t>(bin_n[b]);
-      if (bin_n[b]) k_bin_place<<<nblocks(n, 256), 256, 0, s>>>(f, n, bin_rows[b]);
+  for (int kind = 0; kind < 2; kind++) {          // 0: searched rows, 1: intersection maps
+    int lo = 0;
+    for (int b = 0; b < NBIN; b++) {
+      const int hi = 4 << b;
+      int64_t& cnt = kind ? mbin_n[b] : bin_n[b];
+      int32_t*& rows = kind ? mbin_rows[b] : bin_rows[b];
+      cnt = 0;
+      rows = nullptr;
+      if (n && !(kind == 1 && b == NBIN - 1)) {
+        k_bin_flags2<<<nblocks(n, 256), 256, 0, s>>>(nrp, elig, kind, n, lo, hi, f);
+        scan_inclusive(f, n, s, ar);
+        cnt = d2h(f + n - 1, s);
+        rows = ar.alloc<int32_t>(cnt);
+        if (cnt) k_bin_place<<<nblocks(n, 256), 256, 0, s>>>(f, n, rows);
+      }
+      lo = hi;
     }
-    lo = hi;
   }
+}
+
+template <int G, class TM, class TX, class TY>
+static int64_t map_launch(const EminWork& w, int b, const Csr& M, const TM* mval,
+                          const int64_t* nrp, const TX* X, TY* Y, const double* D, double* part,
+                          hipStream_t s) {
+  constexpr int NG = 256 / G;
+  const int64_t nr = w.mbin_n[b];
+  if (nr == 0) return 0;
+  const unsigned nb = nblocks(nr, NG);
+  k_spmm_map<G, TM, TX, TY><<<nb, 256, 0, s>>>(w.mbin_rows[b], nr, M.rowptr, mval, w.kofs, w.nib,
+                                               w.nnzm, nrp, X, Y, D, part);
+  return nb;
 }
 
 template <int G, class TM, class TX, class TY>
@@ -385,6 +548,10 @@ static int64_t spmm_any(const EminWork& w, const Csr& M, const TM* mval, const i
                         const int32_t* ncol, const TX* X, TY* Y, const double* D, double* part,
                         hipStream_t s) {
   int64_t np = 0;
+  np += map_launch<4>(w, 0, M, mval, nrp, X, Y, D, part ? part + np : nullptr, s);
+  np += map_launch<8>(w, 1, M, mval, nrp, X, Y, D, part ? part + np : nullptr, s);
+  np += map_launch<16>(w, 2, M, mval, nrp, X, Y, D, part ? part + np : nullptr, s);
+  np += map_launch<32>(w, 3, M, mval, nrp, X, Y, D, part ? part + np : nullptr, s);
   np += bin_launch<4>(w, 0, M, mval, nrp, ncol, X, Y, D, part ? part + np : nullptr, s);
   np += bin_launch<8>(w, 1, M, mval, nrp, ncol, X, Y, D, part ? part + np : nullptr, s);
   np += bin_launch<16>(w, 2, M, mval, nrp, ncol, X, Y, D, part ? part + np : nullptr, s);
