@@ -172,44 +172,36 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
   __syncthreads();
 
   int32_t k = n > 0 ? 0 : -1;   // Alg. 3's "arbitrary vertex": vertex 0
+  // Almost always the next C point lies on the distance-4 ring of the current
+  // one, so the ball rows of the ring's candidates are fetched ahead (while
+  // the argmin runs); the results are only retired once the next step's own
+  // ball load has arrived.  Done for short rows only (a few cache lines).
+  const bool prefetch = D.bmax <= 96;
+  int32_t pf0 = 0, pf1 = 0, pf2 = 0, pf3 = 0, pf4 = 0, pf5 = 0;
   while (k >= 0) {
     const int32_t* bl = D.balls + (int64_t)k * D.bmax;
     const int32_t e0 = tid < D.bmax ? bl[tid] : 0;
     const int nb = D.bsize[k];
-    double xk[3] = {0.0, 0.0, 0.0};
-    for (int d = 0; d < dim; d++) xk[d] = D.x[(int64_t)k * dim + d];
+    const double* xkp = D.x + (int64_t)k * dim;
+    const double xk0 = xkp[0], xk1 = xkp[1], xk2 = dim == 3 ? xkp[2] : 0.0;
+    asm volatile("" ::"v"(e0), "v"(pf0), "v"(pf1), "v"(pf2), "v"(pf3), "v"(pf4), "v"(pf5)
+                 : "memory");
     const int nc0 = nc_sh;
+    int32_t pv = -1;   // a candidate on the ring
     // S_j += {k} for dist <= 3; C/F/Cand update; update_heuristics
     for (int t = tid; t < nb; t += A3_BS) {
       const int32_t e = t == tid ? e0 : bl[t];
       const int32_t v = e & VMASK;
       const int d = (int)((uint32_t)e >> DSHIFT);
-      if (d == 0) {
-        s_append(D, v, k, 0, &err_sh);   // S_k holds k itself
-        D.st[v] = ST_C;
-        D.hkey[v] = INF;
-        D.order[nc0] = v;
-        mark_dirty(v / D.vb, dbits, dlist, D.dcap, &dn_sh, &dall_sh);
-        continue;
-      }
-      // all loads of this entry first
+      // every entry (k itself included) loads the same fields before any
+      // store, so the wave issues them together
       const uint8_t s = D.st[v];
       const int32_t c = D.cnt[v];
       const double r = D.rs[v];
       const int32_t sl = D.s_cnt[v];
-      double xv[3] = {0.0, 0.0, 0.0};
-      for (int q = 0; q < dim; q++) xv[q] = D.x[(int64_t)v * dim + q];
-      double ss = 0.0;
-      for (int q = 0; q < dim; q++) {
-        const double tq = xv[q] - xk[q];
-        ss = ss + tq * tq;
-      }
-      const double r1 = r + 1.0 / sqrt(ss);
-      const int32_t c1 = c + 1;
-      uint8_t s1 = s;
-      if (d <= 3 && (s == ST_U || s == ST_CAND)) s1 = ST_F;
-      if (d == 4 && s == ST_U) s1 = ST_CAND;
-      if (d <= 3) {
+      const double* xvp = D.x + (int64_t)v * dim;
+      const double xv0 = xvp[0], xv1 = xvp[1], xv2 = dim == 3 ? xvp[2] : 0.0;
+      if (d <= 3) {   // S_v += {k}; S_k holds k itself
         if (sl < D.scap) {
           D.s_c[(int64_t)v * D.scap + sl] = k;
           D.s_d[(int64_t)v * D.scap + sl] = (uint8_t)d;
@@ -218,11 +210,29 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
           atomicOr(&err_sh, DERR_CAPACITY);
         }
       }
-      if (s1 != s) D.st[v] = s1;
-      D.cnt[v] = c1;
-      D.rs[v] = r1;
-      if (s1 == ST_CAND) D.hkey[v] = (double)c1 / r1;
-      else if (s == ST_CAND) D.hkey[v] = INF;
+      if (d == 0) {
+        D.st[v] = ST_C;
+        D.hkey[v] = INF;
+        D.order[nc0] = v;
+      } else {
+        // |x_v - x_k| summed in coordinate order, as in the definition
+        const double t0 = xv0 - xk0, t1 = xv1 - xk1, t2 = xv2 - xk2;
+        double ss = 0.0;
+        ss = ss + t0 * t0;
+        ss = ss + t1 * t1;
+        if (dim == 3) ss = ss + t2 * t2;
+        const double r1 = r + 1.0 / sqrt(ss);
+        const int32_t c1 = c + 1;
+        uint8_t s1 = s;
+        if (d <= 3 && (s == ST_U || s == ST_CAND)) s1 = ST_F;
+        if (d == 4 && s == ST_U) s1 = ST_CAND;
+        if (s1 != s) D.st[v] = s1;
+        D.cnt[v] = c1;
+        D.rs[v] = r1;
+        if (s1 == ST_CAND) D.hkey[v] = (double)c1 / r1;
+        else if (s == ST_CAND) D.hkey[v] = INF;
+        if (s1 == ST_CAND) pv = v;
+      }
       mark_dirty(v / D.vb, dbits, dlist, D.dcap, &dn_sh, &dall_sh);
     }
     __syncthreads();
@@ -247,6 +257,15 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
     __syncthreads();
     for (int b = tid; b < (D.nblk + 31) / 32; b += A3_BS) dbits[b] = 0u;
     if (tid == 0) { dn_sh = 0; dall_sh = 0; }
+    if (prefetch && pv >= 0) {
+      const int32_t* pb = D.balls + (int64_t)pv * D.bmax;
+      pf0 = pb[0];
+      pf1 = pb[D.bmax > 32 ? 32 : 0];
+      pf2 = pb[D.bmax > 64 ? 64 : 0];
+      pf3 = pb[D.bmax - 1];
+      pf4 = D.bsize[pv];
+      pf5 = reinterpret_cast<const int32_t*>(D.x)[(int64_t)pv * dim * 2];
+    }
     // next k = argmin over Cand of (h1, index); every wave reduces the wave
     // minima itself, so no further barrier is needed before the next step
     double key = INF;
