@@ -43,8 +43,8 @@ struct CoarsenOut {
 
 void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar, int lds_max);
 
-// Alg. 4: C-bar^(p) flags (n_p) from the S sets; returns the number of
-// mid-points added
+// Alg. 4: C-bar^(p) flags (n_p) from the S sets; returns |C-bar^(p)| (the C
+// points and the mid-points added)
 int64_t midpoints(const Csr& S, const uint8_t* st, const double* x, int dim, double tau2_sq,
                   uint8_t* cbar, hipStream_t s, Arena& ar, int lds_max);
 

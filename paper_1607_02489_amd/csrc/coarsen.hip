@@ -156,9 +156,13 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
   extern __shared__ unsigned char lds_raw[];
   double* bkey = reinterpret_cast<double*>(lds_raw);
   int32_t* bidx = reinterpret_cast<int32_t*>(bkey + D.nblk);
-  uint32_t* dbits = reinterpret_cast<uint32_t*>(bidx + D.nblk);
-  int32_t* dlist = reinterpret_cast<int32_t*>(dbits + ((D.nblk + 31) / 32));
-  __shared__ int err_sh, dn_sh, dall_sh, nc_sh, cursor_sh, found_sh;
+  // dirty-block sets are double-buffered by step parity, so a set can be
+  // cleared right after its refresh
+  const int nw = (D.nblk + 31) / 32;
+  uint32_t* dbits0 = reinterpret_cast<uint32_t*>(bidx + D.nblk);
+  int32_t* dlist0 = reinterpret_cast<int32_t*>(dbits0 + 2 * nw);
+  __shared__ int err_sh, nc_sh, cursor_sh, found_sh;
+  __shared__ int dn_sh[2], dall_sh[2];
   __shared__ double wkey[A3_WAVES];
   __shared__ int32_t widx[A3_WAVES];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -167,9 +171,14 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
   const int dim = D.dim;
 
   for (int b = tid; b < D.nblk; b += A3_BS) { bkey[b] = INF; bidx[b] = INT32_MAX; }
-  for (int b = tid; b < (D.nblk + 31) / 32; b += A3_BS) dbits[b] = 0u;
-  if (tid == 0) { err_sh = 0; dn_sh = 0; dall_sh = 0; nc_sh = 0; cursor_sh = 0; }
+  for (int b = tid; b < 2 * nw; b += A3_BS) dbits0[b] = 0u;
+  if (tid == 0) {
+    err_sh = 0; nc_sh = 0; cursor_sh = 0;
+    dn_sh[0] = dn_sh[1] = 0;
+    dall_sh[0] = dall_sh[1] = 0;
+  }
   __syncthreads();
+  int par = 0;
 
   int32_t k = n > 0 ? 0 : -1;   // Alg. 3's "arbitrary vertex": vertex 0
   // Almost always the next C point lies on the distance-4 ring of the current
@@ -179,6 +188,8 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
   const bool prefetch = D.bmax <= 96;
   int32_t pf0 = 0, pf1 = 0, pf2 = 0, pf3 = 0, pf4 = 0, pf5 = 0;
   while (k >= 0) {
+    uint32_t* dbits = dbits0 + par * nw;
+    int32_t* dlist = dlist0 + par * D.dcap;
     const int32_t* bl = D.balls + (int64_t)k * D.bmax;
     const int32_t e0 = tid < D.bmax ? bl[tid] : 0;
     const int nb = D.bsize[k];
@@ -233,30 +244,43 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
         else if (s == ST_CAND) D.hkey[v] = INF;
         if (s1 == ST_CAND) pv = v;
       }
-      mark_dirty(v / D.vb, dbits, dlist, D.dcap, &dn_sh, &dall_sh);
+      mark_dirty(v / D.vb, dbits, dlist, D.dcap, &dn_sh[par], &dall_sh[par]);
     }
     __syncthreads();
     if (tid == 0) nc_sh = nc0 + 1;
-    // refresh the minima of the touched blocks
-    const bool all = dall_sh != 0;
-    const int todo = all ? D.nblk : dn_sh;
+    // refresh the minima of the touched blocks (each lane keeps four loads
+    // in flight per pass over the block)
+    const bool all = dall_sh[par] != 0;
+    const int todo = all ? D.nblk : dn_sh[par];
     for (int t = wave; t < todo; t += A3_WAVES) {
       const int b = all ? t : dlist[t];
       double key = INF;
       int32_t idx = INT32_MAX;
-      for (int u = lane; u < D.vb; u += 64) {
-        const int64_t v = (int64_t)b * D.vb + u;
-        if (v < n) {
-          const double h1 = D.hkey[v];
-          if (h1 < INF && lex_less(h1, (int32_t)v, key, idx)) { key = h1; idx = (int32_t)v; }
+      if (D.vb == 64) {
+        const int64_t v = (int64_t)b * 64 + lane;
+        const double h1 = v < n ? D.hkey[v] : INF;
+        if (h1 < INF) { key = h1; idx = (int32_t)v; }
+      } else for (int u0 = 0; u0 < D.vb; u0 += 256) {
+        double h[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int64_t v = (int64_t)b * D.vb + u0 + lane + 64 * j;
+          h[j] = (u0 + lane + 64 * j < D.vb && v < n) ? D.hkey[v] : INF;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int32_t v = (int32_t)((int64_t)b * D.vb + u0 + lane + 64 * j);
+          if (h[j] < INF && lex_less(h[j], v, key, idx)) { key = h[j]; idx = v; }
         }
       }
       wave_argmin(key, idx);
       if (lane == 0) { bkey[b] = key; bidx[b] = idx; }
     }
     __syncthreads();
-    for (int b = tid; b < (D.nblk + 31) / 32; b += A3_BS) dbits[b] = 0u;
-    if (tid == 0) { dn_sh = 0; dall_sh = 0; }
+    // this step's dirty set is next used two steps on, after two barriers
+    for (int b = tid; b < nw; b += A3_BS) dbits[b] = 0u;
+    if (tid == 0) { dn_sh[par] = 0; dall_sh[par] = 0; }
+    par ^= 1;
     if (prefetch && pv >= 0) {
       const int32_t* pb = D.balls + (int64_t)pv * D.bmax;
       pf0 = pb[0];
@@ -266,8 +290,8 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
       pf4 = D.bsize[pv];
       pf5 = reinterpret_cast<const int32_t*>(D.x)[(int64_t)pv * dim * 2];
     }
-    // next k = argmin over Cand of (h1, index); every wave reduces the wave
-    // minima itself, so no further barrier is needed before the next step
+    // next k = argmin over Cand of (h1, index): block minima reduced per
+    // wave, then every wave reduces the wave minima itself
     double key = INF;
     int32_t idx = INT32_MAX;
     for (int b = tid; b < D.nblk; b += A3_BS)
@@ -510,15 +534,15 @@ void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar,
   D.b3 = b3;
   D.bmax = (int)bmax;
   // LDS layout: block keys | block idx | dirty bits | dirty list
-  D.dcap = 2048;
-  const int fixed = D.dcap * 4 + 64;
-  int max_blocks = (lds_max - fixed) / 13;
-  if (max_blocks < 64) throw Error(EMIN_ERR_CAPACITY, "alg3: LDS too small");
-  D.vb = 64;
-  while ((n + D.vb - 1) / D.vb > max_blocks) D.vb <<= 1;
+  // argmin blocks: 64 vertices where balls are small (few blocks touched per
+  // step), 256 where they are large; at most two blocks per thread
+  D.dcap = 1024;
+  D.vb = D.bmax <= 128 ? 64 : 256;
+  while ((n + D.vb - 1) / D.vb > 2 * A3_BS) D.vb <<= 1;
   D.nblk = (int)((n + D.vb - 1) / D.vb);
   if (D.nblk < 1) D.nblk = 1;
-  size_t lds = (size_t)D.nblk * 12 + (size_t)((D.nblk + 31) / 32) * 4 + (size_t)D.dcap * 4;
+  size_t lds = (size_t)D.nblk * 12 + 2 * (size_t)((D.nblk + 31) / 32) * 4 + 2 * (size_t)D.dcap * 4;
+  if (lds > (size_t)lds_max) throw Error(EMIN_ERR_CAPACITY, "alg3: LDS too small");
   HIP_OK(hipFuncSetAttribute((const void*)k_alg3, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)lds));
   {

@@ -136,22 +136,53 @@ __global__ void k_mid_dep(const int32_t* mo, const int32_t* to, int64_t norder,
   dep[p] = d;
 }
 
+// C-bar as a bitmap of 32-bit words: built from the C points in parallel,
+// carried through the ordered pass in LDS, expanded to flags afterwards.
+__global__ void k_cbits_init(const uint8_t* st, int64_t n, uint32_t* gb) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w * 32 >= n) return;
+  uint32_t m = 0u;
+  for (int b = 0; b < 32; b++) {
+    const int64_t i = w * 32 + b;
+    if (i < n && st[i] == ST_C) m |= 1u << b;
+  }
+  gb[w] = m;
+}
+
+__global__ void k_cbits_expand(const uint32_t* gb, int64_t n, uint8_t* cbar,
+                               unsigned long long* count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint8_t f = (uint8_t)((gb[i >> 5] >> (i & 31)) & 1u);
+  cbar[i] = f;
+  const unsigned long long c = __ballot(f != 0);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, (unsigned long long)__popcll(c));
+}
+
 // The ordered pass of Alg. 4 in one wave, 64 entries per chunk.  An entry is
 // rejected when some vertex of its T is in C-bar from an earlier chunk (LDS
 // bitmap) or is the m of an earlier accepted entry of its own chunk (its
-// dependence mask); the chunk is resolved in lane order with scalar code.
+// dependence mask).  Entries without a dependence are decided at once; only
+// those with one are resolved in lane order, with scalar code.
 __global__ __launch_bounds__(64) void k_mid_decide(const int32_t* mo, const int32_t* to,
                                                    const unsigned long long* dep, int64_t norder,
-                                                   const uint8_t* st, int64_t n, uint8_t* cbar) {
+                                                   int64_t n, uint32_t* gb) {
   extern __shared__ uint32_t bits[];
   const int lane = threadIdx.x;
   const int64_t nw = (n + 31) / 32;
-  for (int64_t w = lane; w < nw; w += 64) bits[w] = 0u;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-  for (int64_t i = lane; i < n; i += 64)
-    if (st[i] == ST_C) atomicOr(&bits[i >> 5], 1u << (i & 31));
+  for (int64_t w0 = 0; w0 < nw; w0 += 8 * 64) {
+    uint32_t v[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      const int64_t w = w0 + j * 64 + lane;
+      v[j] = w < nw ? gb[w] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      const int64_t w = w0 + j * 64 + lane;
+      if (w < nw) bits[w] = v[j];
+    }
+  }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
@@ -171,19 +202,28 @@ __global__ __launch_bounds__(64) void k_mid_decide(const int32_t* mo, const int3
   for (int64_t base = 0; base < norder; base += 64) {
     if (base + 64 < norder) load(base + 64, Tn, mn, dn);
     const bool valid = base + lane < norder;
+    // all TCAP bitmap words read together
+    uint32_t wd[TCAP];
+#pragma unroll
+    for (int t = 0; t < TCAP; t++) wd[t] = bits[(T[t] >= 0 ? T[t] : 0) >> 5];
     bool pre = !valid;
 #pragma unroll
     for (int t = 0; t < TCAP; t++)
-      if (T[t] >= 0 && ((bits[T[t] >> 5] >> (T[t] & 31)) & 1u)) pre = true;
+      if (T[t] >= 0 && ((wd[t] >> (T[t] & 31)) & 1u)) pre = true;
     const unsigned long long rejected = __ballot(pre);
-    const uint32_t dlo = (uint32_t)dp, dhi = (uint32_t)(dp >> 32);
-    unsigned long long accepted = 0ull;
-    for (int l = 0; l < 64; l++) {
-      if ((rejected >> l) & 1ull) continue;
-      const unsigned long long dl =
-          ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)dhi, l) << 32) |
-          (uint32_t)__builtin_amdgcn_readlane((int)dlo, l);
-      if ((dl & accepted) == 0ull) accepted |= 1ull << l;
+    const unsigned long long depend = __ballot(!pre && dp != 0ull);
+    unsigned long long accepted = ~rejected & ~depend;
+    unsigned long long todo = depend;
+    if (todo) {
+      const uint32_t dlo = (uint32_t)dp, dhi = (uint32_t)(dp >> 32);
+      while (todo) {
+        const int l = __builtin_ctzll(todo);
+        todo &= todo - 1ull;
+        const unsigned long long dl =
+            ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)dhi, l) << 32) |
+            (uint32_t)__builtin_amdgcn_readlane((int)dlo, l);
+        if ((dl & accepted) == 0ull) accepted |= 1ull << l;
+      }
     }
     if ((accepted >> lane) & 1ull) atomicOr(&bits[mi >> 5], 1u << (mi & 31));
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -194,12 +234,7 @@ __global__ __launch_bounds__(64) void k_mid_decide(const int32_t* mo, const int3
     mi = mn;
     dp = dn;
   }
-  for (int64_t i = lane; i < n; i += 64) cbar[i] = (bits[i >> 5] >> (i & 31)) & 1u;
-}
-
-__global__ void k_count_set(const uint8_t* f, int64_t n, unsigned long long* c) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && f[i]) atomicAdd(c, 1ull);
+  for (int64_t w = lane; w < nw; w += 64) gb[w] = bits[w];
 }
 
 int64_t midpoints(const Csr& S, const uint8_t* st, const double* x, int dim, double tau2_sq,
@@ -239,14 +274,17 @@ int64_t midpoints(const Csr& S, const uint8_t* st, const double* x, int dim, dou
     k_mid_pack<<<nblocks(norder, 256), 256, 0, s>>>(order, norder, m, tcnt, tlist, mo, to, dep);
     k_mid_dep<<<nblocks(norder, 256), 256, 0, s>>>(mo, to, norder, dep);
   }
+  const int64_t nw = (n + 31) / 32;
+  uint32_t* gb = ar.alloc<uint32_t>(nw);
+  k_cbits_init<<<nblocks(nw, 256), 256, 0, s>>>(st, n, gb);
   {
     prof::Scope ps(s, EMIN_PROF_ALG4, 0.0);
-    k_mid_decide<<<1, 64, lds, s>>>(mo, to, dep, norder, st, n, cbar);
+    k_mid_decide<<<1, 64, lds, s>>>(mo, to, dep, norder, n, gb);
   }
   HIP_OK(hipGetLastError());
   unsigned long long* c = ar.alloc<unsigned long long>(2);
   HIP_OK(hipMemsetAsync(c, 0, 2 * sizeof(unsigned long long), s));
-  k_count_set<<<nblocks(n, 256), 256, 0, s>>>(cbar, n, c);
+  k_cbits_expand<<<nblocks(n, 256), 256, 0, s>>>(gb, n, cbar, c);
   return (int64_t)d2h(c, s);
 }
 

@@ -126,74 +126,187 @@ __global__ void k_transpose_fill(const int64_t* rp, const int32_t* col, int64_t 
 }
 
 // Restores ascending order inside each row of the transpose (the atomic fill
-// leaves it arbitrary).  A wave owns 64 consecutive rows: short rows are
-// insertion-sorted by their own lane; each long row is then rank-sorted by
-// the whole wave through LDS (keys are distinct within a row).
-constexpr int SORT_W = 4;
-constexpr int SORT_LDS = 1024;
+// leaves it arbitrary; keys are distinct within a row).  Rows are binned by
+// length without a host round trip (device-side lists), then
+//  - rows of at most 64 entries: G lanes per row, each lane ranks its key
+//    against the row's others through wave shuffles and writes it in place;
+//  - longer rows: one block per row, bitonic sort of the padded row in LDS
+//    (rows beyond the largest LDS size: the same network in global memory).
+// The network is the variant in which every comparator puts the smaller key
+// at the lower index (the first stage of each merge compares mirrored
+// positions), so padding keys (+inf) beyond the row's end never move into it.
+// Every bin kernel walks its list grid-stride and reads the list length on
+// the device, so the launches do not wait for the classification.
+constexpr int SORT_NBIN = 9;   // G = 4, 8, 16, 32, 64; P = 512, 2048, 16384; longer
+constexpr int SORT_PMAX = 16384;
 
-__global__ __launch_bounds__(64 * SORT_W) void k_sort_segments(const int64_t* rp, int64_t n,
-                                                               int32_t* key, int32_t* src) {
-  __shared__ int32_t tk_all[SORT_W][SORT_LDS];
-  __shared__ int32_t ts_all[SORT_W][SORT_LDS];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t base = ((int64_t)blockIdx.x * SORT_W + w) * 64;
-  const int64_t i = base + lane;
-  int64_t len = 0;
-  if (i < n) len = rp[i + 1] - rp[i];
-  const bool shortrow = len <= 16;
-  if (i < n && shortrow) {
-    const int64_t a = rp[i], b = rp[i + 1];
-    for (int64_t p = a + 1; p < b; p++) {
-      const int32_t k = key[p], s = src[p];
-      int64_t q = p;
-      while (q > a && key[q - 1] > k) {
-        key[q] = key[q - 1];
-        src[q] = src[q - 1];
-        q--;
-      }
-      key[q] = k;
-      src[q] = s;
+__device__ __forceinline__ int sort_bin(int64_t L) {
+  if (L <= 4) return 0;
+  if (L <= 8) return 1;
+  if (L <= 16) return 2;
+  if (L <= 32) return 3;
+  if (L <= 64) return 4;
+  if (L <= 512) return 5;
+  if (L <= 2048) return 6;
+  if (L <= SORT_PMAX) return 7;
+  return 8;
+}
+
+// one atomic per bin per wave (ballot-aggregated)
+__global__ void k_sort_classify(const int64_t* rp, int64_t n, int32_t* lists, int32_t* counts) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int b = -1;
+  if (i < n) {
+    const int64_t L = rp[i + 1] - rp[i];
+    if (L > 1) b = sort_bin(L);
+  }
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  for (int q = 0; q < SORT_NBIN; q++) {
+    const unsigned long long m = __ballot(b == q);
+    if (m == 0ull) continue;
+    const int leader = __builtin_ctzll(m);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&counts[q], __popcll(m));
+    base = __shfl(base, leader, 64);
+    if (b == q) lists[(int64_t)q * n + base + __popcll(m & below)] = (int32_t)i;
+  }
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_sort_group(const int64_t* rp, const int32_t* rows,
+                                                    const int32_t* count, int32_t* key,
+                                                    int32_t* src) {
+  constexpr int NG = 256 / G;
+  const int g = threadIdx.x / G, lane = threadIdx.x % G;
+  const int64_t nr = *count;
+  for (int64_t r0 = (int64_t)blockIdx.x * NG; r0 < nr; r0 += (int64_t)gridDim.x * NG) {
+    const int64_t r = r0 + g;
+    int64_t a = 0;
+    int L = 0;
+    if (r < nr) {
+      const int32_t i = rows[r];
+      a = rp[i];
+      L = (int)(rp[i + 1] - a);
+    }
+    const bool mine = lane < L;
+    const int32_t k = mine ? key[a + lane] : INT32_MAX;
+    const int32_t sv = mine ? src[a + lane] : 0;
+    int rank = 0;
+#pragma unroll
+    for (int u = 0; u < G; u++) {
+      const int32_t ku = __shfl(k, u, G);
+      rank += (ku < k) ? 1 : 0;
+    }
+    if (mine) {
+      key[a + rank] = k;
+      src[a + rank] = sv;
     }
   }
-  unsigned long long longs = __ballot(i < n && !shortrow);
-  int32_t* tk = tk_all[w];
-  int32_t* ts = ts_all[w];
-  while (longs) {
-    const int l = __builtin_ctzll(longs);
-    longs &= longs - 1;
-    const int64_t r = base + l;
-    const int64_t a = rp[r];
-    const int L = (int)(rp[r + 1] - a);
-    if (L <= SORT_LDS) {
-      for (int t = lane; t < L; t += 64) { tk[t] = key[a + t]; ts[t] = src[a + t]; }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-      for (int t = lane; t < L; t += 64) {
-        const int32_t k = tk[t];
-        int rank = 0;
-        for (int u = 0; u < L; u++) rank += tk[u] < k;
-        key[a + rank] = k;
-        src[a + rank] = ts[t];
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    } else if (lane == 0) {
-      for (int64_t p = a + 1; p < a + L; p++) {
-        const int32_t k = key[p], s = src[p];
-        int64_t q = p;
-        while (q > a && key[q - 1] > k) {
-          key[q] = key[q - 1];
-          src[q] = src[q - 1];
-          q--;
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_sort_block(const int64_t* rp, const int32_t* rows,
+                                                    const int32_t* count, int32_t* key,
+                                                    int32_t* src) {
+  extern __shared__ int32_t sb[];
+  int32_t* tk = sb;
+  int32_t* ts = sb + P;
+  const int64_t nr = *count;
+  for (int64_t r = blockIdx.x; r < nr; r += gridDim.x) {
+    const int32_t i = rows[r];
+    const int64_t a = rp[i];
+    const int L = (int)(rp[i + 1] - a);
+    for (int t = threadIdx.x; t < P; t += 256) {
+      tk[t] = t < L ? key[a + t] : INT32_MAX;
+      ts[t] = t < L ? src[a + t] : 0;
+    }
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int t = threadIdx.x; t < P / 2; t += 256) {
+          const int lo = 2 * t - (t & (j - 1));   // index with bit j clear
+          const int hi = j == (k >> 1) ? (lo | (k - 1)) - (lo & (k - 1)) : lo + j;
+          const int32_t x = tk[lo], y = tk[hi];
+          if (x > y) {
+            tk[lo] = y;
+            tk[hi] = x;
+            const int32_t sx = ts[lo];
+            ts[lo] = ts[hi];
+            ts[hi] = sx;
+          }
         }
-        key[q] = k;
-        src[q] = s;
+        __syncthreads();
+      }
+    }
+    for (int t = threadIdx.x; t < L; t += 256) {
+      key[a + t] = tk[t];
+      src[a + t] = ts[t];
+    }
+    __syncthreads();
+  }
+}
+
+// rows longer than the LDS network: the same comparators on the row in place
+__global__ __launch_bounds__(256) void k_sort_global(const int64_t* rp, const int32_t* rows,
+                                                     const int32_t* count, int32_t* key,
+                                                     int32_t* src) {
+  const int64_t nr = *count;
+  for (int64_t r = blockIdx.x; r < nr; r += gridDim.x) {
+    const int32_t i = rows[r];
+    int32_t* tk = key + rp[i];
+    int32_t* ts = src + rp[i];
+    const int64_t L = rp[i + 1] - rp[i];
+    int64_t P = 1;
+    while (P < L) P <<= 1;
+    for (int64_t k = 2; k <= P; k <<= 1) {
+      for (int64_t j = k >> 1; j > 0; j >>= 1) {
+        for (int64_t t = threadIdx.x; t < P / 2; t += 256) {
+          const int64_t lo = 2 * t - (t & (j - 1));
+          const int64_t hi = j == (k >> 1) ? (lo | (k - 1)) - (lo & (k - 1)) : lo + j;
+          if (hi < L) {
+            const int32_t x = tk[lo], y = tk[hi];
+            if (x > y) {
+              tk[lo] = y;
+              tk[hi] = x;
+              const int32_t sx = ts[lo];
+              ts[lo] = ts[hi];
+              ts[hi] = sx;
+            }
+          }
+        }
+        __syncthreads();
       }
     }
   }
+}
+
+void sort_rows(const int64_t* rp, int64_t n, int32_t* key, int32_t* src, hipStream_t s,
+               Arena& ar) {
+  if (n == 0) return;
+  int32_t* lists = ar.alloc<int32_t>((size_t)SORT_NBIN * n);
+  int32_t* counts = ar.alloc<int32_t>(SORT_NBIN);
+  HIP_OK(hipMemsetAsync(counts, 0, sizeof(int32_t) * SORT_NBIN, s));
+  k_sort_classify<<<nblocks(n, 256), 256, 0, s>>>(rp, n, lists, counts);
+  // grids sized for the worst case, capped (the kernels walk grid-stride)
+  auto grid = [&](int64_t per) { return (unsigned)std::min<int64_t>(nblocks(n, per), 4096); };
+  k_sort_group<4><<<grid(64), 256, 0, s>>>(rp, lists + 0 * n, counts + 0, key, src);
+  k_sort_group<8><<<grid(32), 256, 0, s>>>(rp, lists + 1 * n, counts + 1, key, src);
+  k_sort_group<16><<<grid(16), 256, 0, s>>>(rp, lists + 2 * n, counts + 2, key, src);
+  k_sort_group<32><<<grid(8), 256, 0, s>>>(rp, lists + 3 * n, counts + 3, key, src);
+  k_sort_group<64><<<grid(4), 256, 0, s>>>(rp, lists + 4 * n, counts + 4, key, src);
+  HIP_OK(hipFuncSetAttribute((const void*)k_sort_block<SORT_PMAX>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             2 * SORT_PMAX * (int)sizeof(int32_t)));
+  const unsigned gb = (unsigned)std::min<int64_t>(n, 2048);
+  k_sort_block<512><<<gb, 256, 2 * 512 * sizeof(int32_t), s>>>(rp, lists + 5 * n, counts + 5,
+                                                                key, src);
+  k_sort_block<2048><<<gb, 256, 2 * 2048 * sizeof(int32_t), s>>>(rp, lists + 6 * n, counts + 6,
+                                                                  key, src);
+  k_sort_block<SORT_PMAX><<<std::min(gb, 512u), 256, 2 * SORT_PMAX * sizeof(int32_t), s>>>(
+      rp, lists + 7 * n, counts + 7, key, src);
+  k_sort_global<<<std::min(gb, 64u), 256, 0, s>>>(rp, lists + 8 * n, counts + 8, key, src);
+  HIP_OK(hipGetLastError());
 }
 
 void transpose_pattern(const CsrView& A, Csr& At, int32_t*& src, hipStream_t s, Arena& ar) {
@@ -212,9 +325,7 @@ void transpose_pattern(const CsrView& A, Csr& At, int32_t*& src, hipStream_t s, 
   if (A.nrows)
     k_transpose_fill<<<nblocks(A.nrows, 256), 256, 0, s>>>(A.rowptr, A.col, A.nrows, cursor,
                                                             At.col, src);
-  if (At.nrows)
-    k_sort_segments<<<nblocks(At.nrows, 64 * SORT_W), 64 * SORT_W, 0, s>>>(At.rowptr, At.nrows,
-                                                                           At.col, src);
+  sort_rows(At.rowptr, At.nrows, At.col, src, s, ar);
 }
 
 __global__ void k_gather(const double* in, const int32_t* src, double* out, int64_t n) {

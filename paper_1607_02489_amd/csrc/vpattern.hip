@@ -106,13 +106,26 @@ __global__ __launch_bounds__(1024) void k_vextras(const int64_t* grp, const int3
   while (true) {
     if (tid == 0) found_sh = INT32_MAX;
     __syncthreads();
-    for (int64_t base = cursor; base < n; base += 1024) {
-      const int64_t v = base + tid;
-      if (v < n && !cv[v] && !dir[v] && !cov[v]) atomicMin(&found_sh, (int)v);
+    // eight flags per thread per pass (vertices before the cursor are never
+    // eligible again, so the pass may start at the aligned position below it)
+    for (int64_t base = cursor & ~(int64_t)7; base < n; base += 8 * 1024) {
+      const int64_t v0 = base + (int64_t)tid * 8;
+      int f = INT32_MAX;
+      if (v0 + 8 <= n) {
+        const uint64_t bad = *reinterpret_cast<const uint64_t*>(cv + v0) |
+                             *reinterpret_cast<const uint64_t*>(dir + v0) |
+                             *reinterpret_cast<const uint64_t*>(cov + v0);
+        for (int q = 0; q < 8; q++)
+          if (((bad >> (8 * q)) & 0xFFu) == 0u) { f = (int)(v0 + q); break; }
+      } else {
+        for (int64_t v = v0; v < n; v++)
+          if (!cv[v] && !dir[v] && !cov[v]) { f = (int)v; break; }
+      }
+      if (f != INT32_MAX) atomicMin(&found_sh, f);
       __syncthreads();
-      const int f = found_sh;
+      const int ff = found_sh;
       __syncthreads();
-      if (f != INT32_MAX) break;
+      if (ff != INT32_MAX) break;
     }
     const int j = found_sh;
     if (j == INT32_MAX) break;
