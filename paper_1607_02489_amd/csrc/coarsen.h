@@ -26,7 +26,8 @@ struct CoarsenArgs {
   const int32_t* balls = nullptr; // distance-4 balls (vertex | dist << 29), n*bmax
   const int32_t* bsize = nullptr; // ball sizes
   const int32_t* b3 = nullptr;    // entries at distance <= 3 (a prefix of the ball)
-  int bmax = 0;
+  int bmax = 0;                   // largest ball
+  int64_t bstride = 0;            // row stride of balls (>= bmax)
   int vb = 64;                    // vertices per argmin block
   int nblk = 1;
   int dcap = 1024;

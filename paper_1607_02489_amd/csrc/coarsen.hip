@@ -119,6 +119,113 @@ __global__ __launch_bounds__(64 * BW) void k_balls(const int64_t* grp, const int
   }
 }
 
+// Index bandwidth of the graph, max |i - j| over its edges: every vertex of
+// the distance-4 ball of v lies in [v - 4 bw, v + 4 bw].
+__global__ void k_bandwidth(const int64_t* grp, const int32_t* gcol, int64_t n,
+                            unsigned long long* bw) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long m = 0ull;
+  if (i < n)
+    for (int64_t e = grp[i]; e < grp[i + 1]; e++) {
+      const int64_t d = (int64_t)gcol[e] - i;
+      const unsigned long long a = (unsigned long long)(d < 0 ? -d : d);
+      m = a > m ? a : m;
+    }
+  for (int o = 32; o >= 1; o >>= 1) {
+    const unsigned long long t = __shfl_xor(m, o, 64);
+    m = t > m ? t : m;
+  }
+  if ((threadIdx.x & 63) == 0 && m) atomicMax(bw, m);
+}
+
+// Distance-4 balls with a visited bitmap over the index window of the ball
+// (8 bw + 1 bits) instead of a hash set: one atomic OR per edge, no probing,
+// little LDS, so many waves per CU.  One wave per vertex, BFS level by level;
+// entries (vertex | distance << 29) in level order, at most lcap per ball
+// (a longer ball sets the overflow flag and leaves its row unwritten).
+constexpr int BWIN_W = 4;   // waves per block
+
+__global__ __launch_bounds__(64 * BWIN_W) void k_balls_win(const int64_t* grp,
+                                                           const int32_t* gcol, int64_t n,
+                                                           const int32_t* verts, int64_t bw,
+                                                           int nwords, int lcap, int32_t* bsize,
+                                                           int32_t* b3, int32_t* balls,
+                                                           int64_t stride, int* flags) {
+  extern __shared__ uint32_t lds_w[];
+  __shared__ int cnt[BWIN_W];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * BWIN_W + w;
+  if (r >= n) return;   // whole wave; the block never synchronises
+  const int64_t v0 = verts ? verts[r] : r;
+  uint32_t* bits = lds_w + (size_t)w * (nwords + lcap);
+  int32_t* list = reinterpret_cast<int32_t*>(bits + nwords);
+  const int64_t lo = v0 - 4 * bw > 0 ? v0 - 4 * bw : 0;
+  for (int t = lane; t < nwords; t += 64) bits[t] = 0u;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  if (lane == 0) {
+    const int64_t o = v0 - lo;
+    bits[o >> 5] |= 1u << (o & 31);
+    list[0] = (int32_t)v0;
+    cnt[w] = 1;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  int ls = 0, le = 1;
+  int ends[5] = {1, 1, 1, 1, 1};
+  for (int L = 0; L < 4; L++) {
+    for (int f = ls + lane; f < le; f += 64) {
+      const int32_t v = list[f];
+      const int64_t ea = grp[v], eb = grp[v + 1];
+      for (int64_t e = ea; e < eb; e += 4) {
+        int32_t u[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) u[q] = e + q < eb ? gcol[e + q] : v;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          if (u[q] == v) continue;
+          const int64_t o = (int64_t)u[q] - lo;
+          const uint32_t bit = 1u << (o & 31);
+          if ((atomicOr(&bits[o >> 5], bit) & bit) == 0u) {
+            const int p = atomicAdd(&cnt[w], 1);
+            if (p < lcap) list[p] = u[q];
+          }
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const int c = cnt[w];
+    if (c > lcap) {
+      if (lane == 0) atomicOr(flags, 1);
+      return;
+    }
+    ls = le;
+    le = c;
+    ends[L + 1] = le;
+  }
+  if (lane == 0) {
+    bsize[v0] = le;
+    b3[v0] = ends[3];
+    atomicMax(flags + 1, le);
+  }
+  if (!balls) return;
+  int32_t* out = balls + v0 * stride;
+  for (int t = lane; t < le; t += 64) {
+    int d = 0;
+    while (d < 4 && t >= ends[d]) d++;
+    out[t] = (int32_t)((uint32_t)list[t] | ((uint32_t)d << DSHIFT));
+  }
+}
+
+__global__ void k_sample_verts(int64_t n, int32_t m, int32_t* verts) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) verts[i] = (int32_t)(((int64_t)i * n) / m);
+}
+
 __device__ __forceinline__ void s_append(const CoarsenArgs& D, int32_t v, int32_t c, int d,
                                          int* err_sh) {
   const int sl = D.s_cnt[v];
@@ -190,7 +297,7 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
   while (k >= 0) {
     uint32_t* dbits = dbits0 + par * nw;
     int32_t* dlist = dlist0 + par * D.dcap;
-    const int32_t* bl = D.balls + (int64_t)k * D.bmax;
+    const int32_t* bl = D.balls + (int64_t)k * D.bstride;
     const int32_t e0 = tid < D.bmax ? bl[tid] : 0;
     const int nb = D.bsize[k];
     const double* xkp = D.x + (int64_t)k * dim;
@@ -282,7 +389,7 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
     if (tid == 0) { dn_sh[par] = 0; dall_sh[par] = 0; }
     par ^= 1;
     if (prefetch && pv >= 0) {
-      const int32_t* pb = D.balls + (int64_t)pv * D.bmax;
+      const int32_t* pb = D.balls + (int64_t)pv * D.bstride;
       pf0 = pb[0];
       pf1 = pb[D.bmax > 32 ? 32 : 0];
       pf2 = pb[D.bmax > 64 ? 64 : 0];
@@ -411,7 +518,7 @@ __global__ __launch_bounds__(A3_BS) void k_extras(CoarsenArgs D, const double* e
       if (j == INT32_MAX) break;
       // j becomes C and joins the S set of every vertex within distance 3
       const int n3 = D.b3[j];
-      const int32_t* bl = D.balls + (int64_t)j * D.bmax;
+      const int32_t* bl = D.balls + (int64_t)j * D.bstride;
       for (int t = tid; t < n3; t += A3_BS) {
         const int32_t e = bl[t];
         s_append(D, e & VMASK, j, (int)((uint32_t)e >> DSHIFT), &err_sh);
@@ -514,25 +621,77 @@ void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar,
   if (n) k_fill_inf<<<nblocks(n, 256), 256, 0, s>>>(D.hkey, n);
   HIP_OK(hipMemsetAsync(D.s_cnt, 0, sizeof(int32_t) * n, s));
   HIP_OK(hipMemsetAsync(D.meta, 0, sizeof(int32_t) * 4, s));
-  // distance-4 balls of every vertex: sizes first, then the lists
+  // distance-4 balls of every vertex
   int32_t* bsize = ar.alloc<int32_t>(n);
   int32_t* b3 = ar.alloc<int32_t>(n);
-  const size_t blds = (size_t)BW * (BHASH + BLIST) * sizeof(int32_t);
-  HIP_OK(hipFuncSetAttribute((const void*)k_balls, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)blds));
-  if (n)
+  int32_t* balls = nullptr;
+  int64_t bmax = 1, stride = 1;
+  bool done = false;
+  if (n) {
+    // windowed bitmap kernel when the index bandwidth keeps the window small:
+    // ball sizes of a sample of vertices pick the row capacity, then one pass
+    // fills every row (a ball above the capacity repeats the pass, larger)
+    unsigned long long* bwp = ar.alloc<unsigned long long>(1);
+    int* flags = ar.alloc<int>(2);
+    HIP_OK(hipMemsetAsync(bwp, 0, sizeof(unsigned long long), s));
+    k_bandwidth<<<nblocks(n, 256), 256, 0, s>>>(D.grp, D.gcol, n, bwp);
+    const int64_t bw = (int64_t)d2h(bwp, s);
+    const int64_t nwords = (8 * bw + 1 + 31) / 32;
+    int lcap = BLIST;
+    auto lds_for = [&](int cap) { return (size_t)BWIN_W * (nwords + cap) * sizeof(uint32_t); };
+    if (lds_for(BLIST) <= (size_t)lds_max) {
+      HIP_OK(hipFuncSetAttribute((const void*)k_balls_win,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_for(BLIST)));
+      const int32_t m = (int32_t)std::min<int64_t>(n, 512);
+      int32_t* sv = ar.alloc<int32_t>(m);
+      k_sample_verts<<<nblocks(m, 256), 256, 0, s>>>(n, m, sv);
+      HIP_OK(hipMemsetAsync(flags, 0, 2 * sizeof(int), s));
+      k_balls_win<<<nblocks(m, BWIN_W), 64 * BWIN_W, lds_for(BLIST), s>>>(
+          D.grp, D.gcol, m, sv, bw, (int)nwords, BLIST, bsize, b3, nullptr, 0, flags);
+      int fl[2];
+      HIP_OK(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
+      HIP_OK(hipStreamSynchronize(s));
+      if (fl[0] == 0) {
+        lcap = 64;
+        while (lcap < BLIST && lcap < fl[1] + fl[1] / 4) lcap <<= 1;
+        for (int attempt = 0; attempt < 2 && !done; attempt++) {
+          stride = lcap;
+          balls = ar.alloc<int32_t>((size_t)n * stride);
+          HIP_OK(hipMemsetAsync(flags, 0, 2 * sizeof(int), s));
+          k_balls_win<<<nblocks(n, BWIN_W), 64 * BWIN_W, lds_for(lcap), s>>>(
+              D.grp, D.gcol, n, nullptr, bw, (int)nwords, lcap, bsize, b3, balls, stride, flags);
+          HIP_OK(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
+          HIP_OK(hipStreamSynchronize(s));
+          if (fl[0] == 0) {
+            done = true;
+            bmax = fl[1];
+          } else {
+            lcap = BLIST;
+          }
+        }
+      }
+    }
+  }
+  if (n && !done) {
+    // hash-set kernel: sizes first, then the lists
+    const size_t blds = (size_t)BW * (BHASH + BLIST) * sizeof(int32_t);
+    HIP_OK(hipFuncSetAttribute((const void*)k_balls, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)blds));
     k_balls<<<nblocks(n, BW), 64 * BW, blds, s>>>(D.grp, D.gcol, n, 4, bsize, b3, nullptr, BLIST,
                                                   D.meta + 2);
-  if (d2h(D.meta + 2, s) & DERR_CAPACITY) throw Error(EMIN_ERR_CAPACITY, "alg3: ball capacity");
-  const int64_t bmax = n ? max_row_len_i32(bsize, n, s, ar) : 1;
-  int32_t* balls = ar.alloc<int32_t>((size_t)n * bmax);
-  if (n)
+    if (d2h(D.meta + 2, s) & DERR_CAPACITY) throw Error(EMIN_ERR_CAPACITY, "alg3: ball capacity");
+    bmax = max_row_len_i32(bsize, n, s, ar);
+    stride = bmax;
+    balls = ar.alloc<int32_t>((size_t)n * stride);
     k_balls<<<nblocks(n, BW), 64 * BW, blds, s>>>(D.grp, D.gcol, n, 4, bsize, b3, balls,
-                                                  (int)bmax, D.meta + 2);
+                                                  (int)stride, D.meta + 2);
+  }
+  if (!n) balls = ar.alloc<int32_t>(1);
   D.balls = balls;
   D.bsize = bsize;
   D.b3 = b3;
   D.bmax = (int)bmax;
+  D.bstride = stride;
   // LDS layout: block keys | block idx | dirty bits | dirty list
   // argmin blocks: 64 vertices where balls are small (few blocks touched per
   // step), 256 where they are large; at most two blocks per thread
