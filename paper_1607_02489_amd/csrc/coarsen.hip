@@ -239,14 +239,21 @@ __device__ __forceinline__ void s_append(const CoarsenArgs& D, int32_t v, int32_
 }
 
 __device__ __forceinline__ void mark_dirty(int b, uint32_t* dbits, int32_t* dlist, int dcap,
-                                           int* dn, int* dall) {
+                                           int* dn, int* dall, int32_t* bslot = nullptr) {
   const uint32_t bit = 1u << (b & 31);
   if ((atomicOr(&dbits[b >> 5], bit) & bit) == 0) {
     const int p = atomicAdd(dn, 1);
     if (p < dcap) dlist[p] = b;
     else *dall = 1;
+    if (bslot) bslot[b] = p;
   }
 }
+
+// Alg. 3 keeps, for at most A3_OVL touched blocks of 64 vertices, an LDS
+// overlay of the keys the step has just written, so the refresh can combine
+// them with keys loaded before the update (those of untouched vertices are
+// unchanged) instead of reloading the block after its stores.
+constexpr int A3_OVL = 64;
 
 __global__ void k_fill_inf(double* a, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -259,6 +266,14 @@ __global__ void k_fill_inf(double* a, int64_t n) {
 // before any is stored, and the heuristic key of each candidate (h1 = cnt/rs,
 // +inf for a non-candidate) is kept in its own array so that refreshing a
 // block's minimum is a single coalesced read.
+// per-thread copy of one ball entry's vertex state (set only in waves that
+// hold entries, and read only there)
+struct A3Entry {
+  int32_t v, d, s, c, sl;
+  double r, x0, x1, x2;
+};
+
+template <bool OVL>
 __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
   extern __shared__ unsigned char lds_raw[];
   double* bkey = reinterpret_cast<double*>(lds_raw);
@@ -268,6 +283,13 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
   const int nw = (D.nblk + 31) / 32;
   uint32_t* dbits0 = reinterpret_cast<uint32_t*>(bidx + D.nblk);
   int32_t* dlist0 = reinterpret_cast<int32_t*>(dbits0 + 2 * nw);
+  // overlay (64-vertex blocks only): slot of each touched block, and keys
+  int32_t* bslot = dlist0 + 2 * D.dcap;
+  const size_t ovl_off =
+      ((size_t)D.nblk * 12 + (size_t)nw * 8 + (size_t)D.dcap * 8 + ((size_t)D.nblk + 1) * 4 + 7) &
+      ~(size_t)7;
+  double* ovl = reinterpret_cast<double*>(lds_raw + ovl_off);
+  constexpr bool ovl_ok = OVL;   // 64-vertex blocks
   __shared__ int err_sh, nc_sh, cursor_sh, found_sh;
   __shared__ int dn_sh[2], dall_sh[2];
   __shared__ double wkey[A3_WAVES];
@@ -279,6 +301,8 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
 
   for (int b = tid; b < D.nblk; b += A3_BS) { bkey[b] = INF; bidx[b] = INT32_MAX; }
   for (int b = tid; b < 2 * nw; b += A3_BS) dbits0[b] = 0u;
+  if (ovl_ok)
+    for (int t = tid; t < A3_OVL * 64; t += A3_BS) ovl[t] = -1.0;
   if (tid == 0) {
     err_sh = 0; nc_sh = 0; cursor_sh = 0;
     dn_sh[0] = dn_sh[1] = 0;
@@ -297,69 +321,136 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
   while (k >= 0) {
     uint32_t* dbits = dbits0 + par * nw;
     int32_t* dlist = dlist0 + par * D.dcap;
+    // (1) the ball of k (at most two entries per thread), dirty marks, and
+    // the loads of every per-vertex field the entries need
     const int32_t* bl = D.balls + (int64_t)k * D.bstride;
-    const int32_t e0 = tid < D.bmax ? bl[tid] : 0;
+    const int32_t ea = tid < D.bmax ? bl[tid] : 0;
+    const int32_t eb = tid + A3_BS < D.bmax ? bl[tid + A3_BS] : 0;
     const int nb = D.bsize[k];
     const double* xkp = D.x + (int64_t)k * dim;
     const double xk0 = xkp[0], xk1 = xkp[1], xk2 = dim == 3 ? xkp[2] : 0.0;
-    asm volatile("" ::"v"(e0), "v"(pf0), "v"(pf1), "v"(pf2), "v"(pf3), "v"(pf4), "v"(pf5)
+    asm volatile("" ::"v"(ea), "v"(pf0), "v"(pf1), "v"(pf2), "v"(pf3), "v"(pf4), "v"(pf5)
                  : "memory");
     const int nc0 = nc_sh;
+    A3Entry E[2];
+    const bool has[2] = {tid < nb, tid + A3_BS < nb};
+    const bool wh[2] = {wave * 64 < nb, A3_BS + wave * 64 < nb};   // wave-uniform
+    // (inside a wave that holds entries the loads are unconditional, from k
+    // itself for a lane without one, so that no register merge waits for them)
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+      if (!wh[q]) continue;
+      const int32_t e = q ? eb : ea;
+      A3Entry& x = E[q];
+      x.v = has[q] ? (e & VMASK) : k;
+      x.d = (int)((uint32_t)e >> DSHIFT);
+      if (has[q])
+        mark_dirty(x.v / D.vb, dbits, dlist, D.dcap, &dn_sh[par], &dall_sh[par],
+                   ovl_ok ? bslot : nullptr);
+      x.s = D.st[x.v];
+      x.c = D.cnt[x.v];
+      x.r = D.rs[x.v];
+      x.sl = D.s_cnt[x.v];
+      const double* xvp = D.x + (int64_t)x.v * dim;
+      x.x0 = xvp[0];
+      x.x1 = xvp[1];
+      x.x2 = xvp[dim == 3 ? 2 : 1];
+    }
+    __syncthreads();
+    // (2) while those loads are in flight: the pre-update keys of the touched
+    // blocks (overlay mode), and the minimum over the blocks this step leaves
+    // untouched (their stored minima are current)
+    const bool all = dall_sh[par] != 0;
+    const int todo = all ? D.nblk : dn_sh[par];
+    const bool use_ovl = ovl_ok && !all && todo <= A3_OVL;   // uniform
+    // (issued unconditionally, from clamped addresses, so that the number of
+    // loads in flight is the same on every path and later waits stay exact)
+    double oldk[A3_OVL / A3_WAVES];
+    if (ovl_ok) {
+#pragma unroll
+      for (int i = 0; i < A3_OVL / A3_WAVES; i++) {
+        const int t = wave + A3_WAVES * i;
+        const int64_t v = (int64_t)dlist[t < todo ? t : 0] * 64 + lane;
+        const double h = D.hkey[v < n ? v : n - 1];
+        oldk[i] = (use_ovl && t < todo && v < n) ? h : INF;
+      }
+    }
+    double ck = INF;
+    int32_t ci = INT32_MAX;
+    for (int b = tid; b < D.nblk; b += A3_BS)
+      if (!((dbits[b >> 5] >> (b & 31)) & 1u) && lex_less(bkey[b], bidx[b], ck, ci)) {
+        ck = bkey[b];
+        ci = bidx[b];
+      }
+    wave_argmin(ck, ci);
+    // the loaded fields are first used here (an empty asm that "modifies"
+    // them keeps the compiler from consuming them before the scan)
+#pragma unroll
+    for (int q = 0; q < 2; q++)
+      if (wh[q])
+        asm volatile("" : "+v"(E[q].s), "+v"(E[q].c), "+v"(E[q].r), "+v"(E[q].sl),
+                     "+v"(E[q].x0), "+v"(E[q].x1), "+v"(E[q].x2));
+    // (3) S_j += {k} for dist <= 3; C/F/Cand update; update_heuristics
     int32_t pv = -1;   // a candidate on the ring
-    // S_j += {k} for dist <= 3; C/F/Cand update; update_heuristics
-    for (int t = tid; t < nb; t += A3_BS) {
-      const int32_t e = t == tid ? e0 : bl[t];
-      const int32_t v = e & VMASK;
-      const int d = (int)((uint32_t)e >> DSHIFT);
-      // every entry (k itself included) loads the same fields before any
-      // store, so the wave issues them together
-      const uint8_t s = D.st[v];
-      const int32_t c = D.cnt[v];
-      const double r = D.rs[v];
-      const int32_t sl = D.s_cnt[v];
-      const double* xvp = D.x + (int64_t)v * dim;
-      const double xv0 = xvp[0], xv1 = xvp[1], xv2 = dim == 3 ? xvp[2] : 0.0;
-      if (d <= 3) {   // S_v += {k}; S_k holds k itself
-        if (sl < D.scap) {
-          D.s_c[(int64_t)v * D.scap + sl] = k;
-          D.s_d[(int64_t)v * D.scap + sl] = (uint8_t)d;
-          D.s_cnt[v] = sl + 1;
+#pragma unroll
+    for (int q = 0; q < 2; q++) {
+      if (!has[q]) continue;
+      const A3Entry& x = E[q];
+      if (x.d <= 3) {   // S_v += {k}; S_k holds k itself
+        if (x.sl < D.scap) {
+          D.s_c[(int64_t)x.v * D.scap + x.sl] = k;
+          D.s_d[(int64_t)x.v * D.scap + x.sl] = (uint8_t)x.d;
+          D.s_cnt[x.v] = x.sl + 1;
         } else {
           atomicOr(&err_sh, DERR_CAPACITY);
         }
       }
-      if (d == 0) {
-        D.st[v] = ST_C;
-        D.hkey[v] = INF;
-        D.order[nc0] = v;
+      if (x.d == 0) {
+        D.st[x.v] = ST_C;
+        D.hkey[x.v] = INF;
+        D.order[nc0] = x.v;
+        if (use_ovl) ovl[bslot[x.v >> 6] * 64 + (x.v & 63)] = INF;
       } else {
         // |x_v - x_k| summed in coordinate order, as in the definition
-        const double t0 = xv0 - xk0, t1 = xv1 - xk1, t2 = xv2 - xk2;
+        const double t0 = x.x0 - xk0, t1 = x.x1 - xk1, t2 = (dim == 3 ? x.x2 : 0.0) - xk2;
         double ss = 0.0;
         ss = ss + t0 * t0;
         ss = ss + t1 * t1;
         if (dim == 3) ss = ss + t2 * t2;
-        const double r1 = r + 1.0 / sqrt(ss);
-        const int32_t c1 = c + 1;
-        uint8_t s1 = s;
-        if (d <= 3 && (s == ST_U || s == ST_CAND)) s1 = ST_F;
-        if (d == 4 && s == ST_U) s1 = ST_CAND;
-        if (s1 != s) D.st[v] = s1;
-        D.cnt[v] = c1;
-        D.rs[v] = r1;
-        if (s1 == ST_CAND) D.hkey[v] = (double)c1 / r1;
-        else if (s == ST_CAND) D.hkey[v] = INF;
-        if (s1 == ST_CAND) pv = v;
+        const double r1 = x.r + 1.0 / sqrt(ss);
+        const int32_t c1 = x.c + 1;
+        int32_t s1 = x.s;
+        if (x.d <= 3 && (x.s == ST_U || x.s == ST_CAND)) s1 = ST_F;
+        if (x.d == 4 && x.s == ST_U) s1 = ST_CAND;
+        if (s1 != x.s) D.st[x.v] = (uint8_t)s1;
+        D.cnt[x.v] = c1;
+        D.rs[x.v] = r1;
+        const double nk = s1 == ST_CAND ? (double)c1 / r1 : INF;
+        if (s1 == ST_CAND || x.s == ST_CAND) D.hkey[x.v] = nk;
+        if (use_ovl) ovl[bslot[x.v >> 6] * 64 + (x.v & 63)] = nk;
+        if (s1 == ST_CAND) pv = x.v;
       }
-      mark_dirty(v / D.vb, dbits, dlist, D.dcap, &dn_sh[par], &dall_sh[par]);
     }
     __syncthreads();
     if (tid == 0) nc_sh = nc0 + 1;
-    // refresh the minima of the touched blocks (each lane keeps four loads
-    // in flight per pass over the block)
-    const bool all = dall_sh[par] != 0;
-    const int todo = all ? D.nblk : dn_sh[par];
-    for (int t = wave; t < todo; t += A3_WAVES) {
+    // (4) new minima of the touched blocks, folded into the wave's minimum
+    if (use_ovl) {
+#pragma unroll
+      for (int i = 0; i < A3_OVL / A3_WAVES; i++) {
+        const int t = wave + A3_WAVES * i;
+        if (t >= todo) break;   // wave-uniform
+        const int b = dlist[t];
+        const double o = ovl[t * 64 + lane];
+        ovl[t * 64 + lane] = -1.0;
+        const double h1 = o != -1.0 ? o : oldk[i];
+        double key = INF;
+        int32_t idx = INT32_MAX;
+        if (h1 < INF) { key = h1; idx = b * 64 + lane; }
+        wave_argmin(key, idx);
+        if (lane == 0) { bkey[b] = key; bidx[b] = idx; }
+        if (lex_less(key, idx, ck, ci)) { ck = key; ci = idx; }
+      }
+    } else for (int t = wave; t < todo; t += A3_WAVES) {
       const int b = all ? t : dlist[t];
       double key = INF;
       int32_t idx = INT32_MAX;
@@ -382,9 +473,11 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
       }
       wave_argmin(key, idx);
       if (lane == 0) { bkey[b] = key; bidx[b] = idx; }
+      if (lex_less(key, idx, ck, ci)) { ck = key; ci = idx; }
     }
+    if (lane == 0) { wkey[wave] = ck; widx[wave] = ci; }
     __syncthreads();
-    // this step's dirty set is next used two steps on, after two barriers
+    // this step's dirty set is next used two steps on, after three barriers
     for (int b = tid; b < nw; b += A3_BS) dbits[b] = 0u;
     if (tid == 0) { dn_sh[par] = 0; dall_sh[par] = 0; }
     par ^= 1;
@@ -397,17 +490,10 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
       pf4 = D.bsize[pv];
       pf5 = reinterpret_cast<const int32_t*>(D.x)[(int64_t)pv * dim * 2];
     }
-    // next k = argmin over Cand of (h1, index): block minima reduced per
-    // wave, then every wave reduces the wave minima itself
-    double key = INF;
-    int32_t idx = INT32_MAX;
-    for (int b = tid; b < D.nblk; b += A3_BS)
-      if (lex_less(bkey[b], bidx[b], key, idx)) { key = bkey[b]; idx = bidx[b]; }
-    wave_argmin(key, idx);
-    if (lane == 0) { wkey[wave] = key; widx[wave] = idx; }
-    __syncthreads();
-    key = lane < A3_WAVES ? wkey[lane] : INF;
-    idx = lane < A3_WAVES ? widx[lane] : INT32_MAX;
+    // (5) next k = argmin over Cand of (h1, index): every wave reduces the
+    // wave minima itself
+    double key = lane < A3_WAVES ? wkey[lane] : INF;
+    int32_t idx = lane < A3_WAVES ? widx[lane] : INT32_MAX;
     wave_argmin(key, idx);
     // an error ends the loop for every thread at the same point
     if (err_sh) break;
@@ -700,13 +786,15 @@ void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar,
   while ((n + D.vb - 1) / D.vb > 2 * A3_BS) D.vb <<= 1;
   D.nblk = (int)((n + D.vb - 1) / D.vb);
   if (D.nblk < 1) D.nblk = 1;
-  size_t lds = (size_t)D.nblk * 12 + 2 * (size_t)((D.nblk + 31) / 32) * 4 + 2 * (size_t)D.dcap * 4;
+  size_t lds = (size_t)D.nblk * 12 + 2 * (size_t)((D.nblk + 31) / 32) * 4 + 2 * (size_t)D.dcap * 4 +
+               ((size_t)D.nblk + 1) * 4 + 8 + (D.vb == 64 ? (size_t)A3_OVL * 64 * 8 : 0);
   if (lds > (size_t)lds_max) throw Error(EMIN_ERR_CAPACITY, "alg3: LDS too small");
-  HIP_OK(hipFuncSetAttribute((const void*)k_alg3, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)lds));
+  const void* kfun = D.vb == 64 ? (const void*)k_alg3<true> : (const void*)k_alg3<false>;
+  HIP_OK(hipFuncSetAttribute(kfun, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   {
   prof::Scope ps(s, EMIN_PROF_ALG3, 0.0);
-  k_alg3<<<1, A3_BS, lds, s>>>(D);
+  if (D.vb == 64) k_alg3<true><<<1, A3_BS, lds, s>>>(D);
+  else k_alg3<false><<<1, A3_BS, lds, s>>>(D);
   HIP_OK(hipGetLastError());
   double* ebar = ar.alloc<double>(n);
   if (n) k_ebar<<<nblocks(n, 256), 256, 0, s>>>(D, ebar);
