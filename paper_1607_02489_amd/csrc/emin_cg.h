@@ -17,6 +17,15 @@ struct EminReportPtrs {
   int32_t* status = nullptr;
 };
 
+// one masked-product launch: row lists of every class back to back, with the
+// row and block ranges of each class
+constexpr int SPMM_NT = 9;
+struct SpmmSched {
+  const int32_t* rows = nullptr;
+  int64_t row_off[SPMM_NT + 1] = {};
+  int64_t blk_off[SPMM_NT + 1] = {};
+};
+
 struct EminWork {
   int64_t n = 0, nnz = 0, nc = 0;
   int g = 8;       // lanes per row of the masked product
@@ -26,14 +35,10 @@ struct EminWork {
   float *Zf = nullptr, *Qf = nullptr;
   double *part = nullptr, *part_e = nullptr;
   CgScalars* sc = nullptr;
-  // row bins of the masked product by pattern-row length: (0,4], (4,8], ..., (32,64];
-  // mbin_*: rows served from precomputed intersection maps (length <= 32),
-  // bin_*: the rest, served by the searching kernel
-  static constexpr int NBIN = 5;
-  int32_t* bin_rows[NBIN] = {};
-  int64_t bin_n[NBIN] = {};
-  int32_t* mbin_rows[NBIN] = {};
-  int64_t mbin_n[NBIN] = {};
+  // row classes of the masked product by pattern-row length: rows served
+  // from precomputed intersection maps (length <= 32, G = 4..32) and the rest,
+  // served by the searching kernel (G = 4..64)
+  SpmmSched sched;
   // intersection maps per M entry: base offset and 4-bit slot fields
   // (nplanes words of eight fields, plane-major)
   int32_t* kofs = nullptr;

@@ -91,16 +91,14 @@ __device__ __forceinline__ TX find_in_group(int32_t js, int32_t c, TX z, bool& h
 }
 
 template <int G, class TM, class TX, class TY>
-__global__ __launch_bounds__(256) void k_spmm_bin(const int32_t* rows, int64_t nrows,
-                                                  const int64_t* mrp, const int32_t* mcol,
-                                                  const TM* mval, const int64_t* nrp,
-                                                  const int32_t* ncol, const TX* X, TY* Y,
-                                                  const double* D, double* part) {
+__device__ __forceinline__ double spmm_search_rows(int64_t lb, const int32_t* rows, int64_t nrows,
+                                                   const int64_t* mrp, const int32_t* mcol,
+                                                   const TM* mval, const int64_t* nrp,
+                                                   const int32_t* ncol, const TX* X, TY* Y,
+                                                   const double* D) {
   using TA = TM;
   constexpr int NG = 256 / G;
   constexpr int U = 4;
-  __shared__ double lds[4];
-  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
   const int g = threadIdx.x / G, lane = threadIdx.x % G;
   const int64_t r = lb * NG + g;
   double dot = 0.0;
@@ -157,10 +155,7 @@ __global__ __launch_bounds__(256) void k_spmm_bin(const int32_t* rows, int64_t n
       if (D) dot = D[na + lane] * (double)acc;
     }
   }
-  if (part) {
-    const double t = block_sum(dot, lds);
-    if (threadIdx.x == 0) part[blockIdx.x] = t;
-  }
+  return dot;
 }
 
 // Precomputed intersection maps.  For an M entry (i,k), slot s of N_i meets
@@ -226,31 +221,37 @@ __global__ void k_spmm_maps(const int64_t* mrp, const int32_t* mcol, const int64
 
 // Masked product on the intersection maps: G lanes (G >= |N_i|) own row i,
 // lane s computing slot s.  The group copies M's row (values, base offsets,
-// map words) through a small LDS window with coalesced loads; then for each
-// entry lane s reads its 4-bit field and, on a match, gathers exactly one
-// pattern value, X[kofs + s + field].  No searching and no cross-lane
-// traffic; per-slot sums run over k in order (deterministic).
+// map words) through a small LDS window with coalesced loads, padding the
+// window to a multiple of four entries with empty maps; then for each entry
+// lane s reads its 4-bit field and, on a match, gathers exactly one pattern
+// value, X[kofs + s + field].  No searching and no cross-lane traffic;
+// per-slot sums run over k in order (deterministic).
+template <int G>
+struct MapWin {
+  static constexpr int NG = 256 / G;
+  static constexpr int NP = G <= 8 ? 1 : G / 8;     // map planes of a row
+  static constexpr int CH = G <= 4 ? 8 : (G < 16 ? 16 : G);   // window entries per group
+};
+
 template <int G, class TM, class TX, class TY>
-__global__ __launch_bounds__(256) void k_spmm_map(const int32_t* rows, int64_t nrows,
-                                                  const int64_t* mrp, const TM* mval,
-                                                  const int32_t* kofs, const uint32_t* nib,
-                                                  int64_t nnzm, const int64_t* nrp, const TX* X,
-                                                  TY* Y, const double* D, double* part) {
+__device__ __forceinline__ double spmm_map_rows(int64_t lb, const int32_t* rows, int64_t nrows,
+                                                const int64_t* mrp, const TM* mval,
+                                                const int32_t* kofs, const uint32_t* nib,
+                                                int64_t nnzm, const int64_t* nrp, const TX* X,
+                                                TY* Y, const double* D, unsigned char* smem) {
   using TA = TM;
-  constexpr int NG = 256 / G;
-  constexpr int NP = G <= 8 ? 1 : G / 8;     // map planes of a row
-  constexpr int CH = G < 16 ? 16 : G;        // LDS window (entries) per group
+  using W = MapWin<G>;
+  constexpr int NG = W::NG, NP = W::NP, CH = W::CH;
   constexpr int U = 4;
-  __shared__ TM s_m[NG * CH];
-  __shared__ int32_t s_k[NG * CH];
-  __shared__ uint32_t s_w[NP][NG * CH];
-  __shared__ double lds[4];
-  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+  TM* s_m = reinterpret_cast<TM*>(smem);
+  int32_t* s_k = reinterpret_cast<int32_t*>(s_m + NG * CH);
+  uint32_t* s_w = reinterpret_cast<uint32_t*>(s_k + NG * CH);   // [NP][NG*CH]
   const int g = threadIdx.x / G, lane = threadIdx.x % G;
   const int64_t r = lb * NG + g;
   const int q = lane >> 3, sh = 4 * (lane & 7);
   TM* gm = s_m + g * CH;
   int32_t* gk = s_k + g * CH;
+  const uint32_t* gw = s_w + q * (NG * CH) + g * CH;
   double dot = 0.0;
   if (r < nrows) {
     const int32_t i = rows[r];
@@ -260,24 +261,26 @@ __global__ __launch_bounds__(256) void k_spmm_map(const int32_t* rows, int64_t n
     TA acc = TA(0);
     for (int64_t c0 = ma; c0 < mb; c0 += CH) {
       const int cn = (int)((mb - c0) < CH ? (mb - c0) : CH);
-      for (int t = lane; t < cn; t += G) {
-        gm[t] = mval[c0 + t];
-        gk[t] = kofs[c0 + t];
+      const int cnp = (cn + U - 1) & ~(U - 1);
+      for (int t = lane; t < cnp; t += G) {
+        const bool v = t < cn;
+        gm[t] = v ? mval[c0 + t] : TM(0);
+        gk[t] = v ? kofs[c0 + t] : 0;
 #pragma unroll
-        for (int p = 0; p < NP; p++) s_w[p][g * CH + t] = nib[(int64_t)p * nnzm + c0 + t];
+        for (int p = 0; p < NP; p++)
+          s_w[p * (NG * CH) + g * CH + t] = v ? nib[(int64_t)p * nnzm + c0 + t] : 0xFFFFFFFFu;
       }
       // the group lies inside one wave: order its LDS writes before the reads
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      const uint32_t* gw = s_w[q] + g * CH;
-      for (int t = 0; t < cn; t += U) {
+      for (int t = 0; t < cnp; t += U) {
         TX x[U];
         uint32_t f[U];
 #pragma unroll
         for (int u = 0; u < U; u++) {
-          f[u] = t + u < cn ? (gw[t + u] >> sh) & 0xFu : 0xFu;
-          x[u] = f[u] != 0xFu ? X[(int64_t)gk[t + u] + lane + (int)f[u]] : TX(0);
+          f[u] = (gw[t + u] >> sh) & 0xFu;
+          x[u] = f[u] != 0xFu ? X[(int64_t)(gk[t + u] + lane + (int)f[u])] : TX(0);
         }
 #pragma unroll
         for (int u = 0; u < U; u++)
@@ -292,6 +295,56 @@ __global__ __launch_bounds__(256) void k_spmm_map(const int32_t* rows, int64_t n
       Y[na + lane] = (TY)acc;
       if (D) dot = D[na + lane] * (double)acc;
     }
+  }
+  return dot;
+}
+
+template <int G, class TM>
+constexpr int map_smem() {
+  return MapWin<G>::NG * MapWin<G>::CH * (int)(sizeof(TM) + 4 + 4 * MapWin<G>::NP);
+}
+
+template <class TM>
+constexpr int spmm_smem() {
+  constexpr int a = map_smem<4, TM>(), b = map_smem<8, TM>(), c = map_smem<16, TM>(),
+                d = map_smem<32, TM>();
+  constexpr int ab = a > b ? a : b, cd = c > d ? c : d;
+  return ab > cd ? ab : cd;
+}
+
+// The whole masked product in one launch: block ranges serve the row classes
+// (map rows with G = 4, 8, 16, 32 lanes, then searched rows with G = 4 ...
+// 64).  Every class has a multiple of 8 blocks and each XCD (which receives
+// the hardware blocks x, x+8, ...) takes the x-th eighth of every class: the
+// load is balanced across XCDs and each XCD works on contiguous rows.
+template <class TM, class TX, class TY>
+__global__ __launch_bounds__(256) void k_spmm(SpmmSched S, const int64_t* mrp,
+                                              const int32_t* mcol, const TM* mval,
+                                              const int32_t* kofs, const uint32_t* nib,
+                                              int64_t nnzm, const int64_t* nrp,
+                                              const int32_t* ncol, const TX* X, TY* Y,
+                                              const double* D, double* part) {
+  __shared__ __align__(16) unsigned char smem[spmm_smem<TM>()];
+  __shared__ double lds[4];
+  const int64_t x = blockIdx.x & 7, j = blockIdx.x >> 3;
+  int ty = 0;
+#pragma unroll
+  for (int t = 1; t < SPMM_NT; t++) ty += j >= (S.blk_off[t] >> 3) ? 1 : 0;
+  const int64_t q = (S.blk_off[ty + 1] - S.blk_off[ty]) >> 3;
+  const int64_t lb = x * q + (j - (S.blk_off[ty] >> 3));
+  const int32_t* rows = S.rows + S.row_off[ty];
+  const int64_t nr = S.row_off[ty + 1] - S.row_off[ty];
+  double dot = 0.0;
+  switch (ty) {
+    case 0: dot = spmm_map_rows<4>(lb, rows, nr, mrp, mval, kofs, nib, nnzm, nrp, X, Y, D, smem); break;
+    case 1: dot = spmm_map_rows<8>(lb, rows, nr, mrp, mval, kofs, nib, nnzm, nrp, X, Y, D, smem); break;
+    case 2: dot = spmm_map_rows<16>(lb, rows, nr, mrp, mval, kofs, nib, nnzm, nrp, X, Y, D, smem); break;
+    case 3: dot = spmm_map_rows<32>(lb, rows, nr, mrp, mval, kofs, nib, nnzm, nrp, X, Y, D, smem); break;
+    case 4: dot = spmm_search_rows<4>(lb, rows, nr, mrp, mcol, mval, nrp, ncol, X, Y, D); break;
+    case 5: dot = spmm_search_rows<8>(lb, rows, nr, mrp, mcol, mval, nrp, ncol, X, Y, D); break;
+    case 6: dot = spmm_search_rows<16>(lb, rows, nr, mrp, mcol, mval, nrp, ncol, X, Y, D); break;
+    case 7: dot = spmm_search_rows<32>(lb, rows, nr, mrp, mcol, mval, nrp, ncol, X, Y, D); break;
+    default: dot = spmm_search_rows<64>(lb, rows, nr, mrp, mcol, mval, nrp, ncol, X, Y, D); break;
   }
   if (part) {
     const double t = block_sum(dot, lds);
@@ -465,7 +518,9 @@ void EminWork::allocate(int64_t n_, int64_t nnz_, int64_t nc_, Arena& ar, bool m
   Zf = ar.alloc<float>(nnz);
   Qf = ar.alloc<float>(nnz);
   (void)mixed;
-  const int64_t np = 2 * (int64_t)nblocks(n, 4) + 16;  // enough for every grid used
+  // enough for every grid used (the masked product pads each row class to a
+  // multiple of 8 blocks)
+  const int64_t np = 2 * (int64_t)nblocks(n, 4) + 16 + 8 * SPMM_NT;
   part = ar.alloc<double>(np);
   part_e = ar.alloc<double>(np);
   sc = ar.alloc<CgScalars>(1);
@@ -496,68 +551,40 @@ void EminWork::make_bins(const Csr& M, const int64_t* nrp, const int32_t* ncol, 
   if (n)
     k_spmm_maps<<<nblocks(n, 256), 256, 0, s>>>(M.rowptr, M.col, nrp, ncol, n, M.nnz, nplanes,
                                                 kofs, nib, elig);
+  // classes: map rows with G = 4, 8, 16, 32; searched rows with G = 4 ... 64
   int64_t* f = ar.alloc<int64_t>(n);
-  for (int kind = 0; kind < 2; kind++) {          // 0: searched rows, 1: intersection maps
-    int lo = 0;
-    for (int b = 0; b < NBIN; b++) {
-      const int hi = 4 << b;
-      int64_t& cnt = kind ? mbin_n[b] : bin_n[b];
-      int32_t*& rows = kind ? mbin_rows[b] : bin_rows[b];
-      cnt = 0;
-      rows = nullptr;
-      if (n && !(kind == 1 && b == NBIN - 1)) {
-        k_bin_flags2<<<nblocks(n, 256), 256, 0, s>>>(nrp, elig, kind, n, lo, hi, f);
-        scan_inclusive(f, n, s, ar);
-        cnt = d2h(f + n - 1, s);
-        rows = ar.alloc<int32_t>(cnt);
-        if (cnt) k_bin_place<<<nblocks(n, 256), 256, 0, s>>>(f, n, rows);
-      }
-      lo = hi;
+  int32_t* all = ar.alloc<int32_t>(n);
+  int64_t off = 0, blocks = 0;
+  for (int ty = 0; ty < SPMM_NT; ty++) {
+    const int kind = ty < 4 ? 1 : 0;
+    const int b = ty < 4 ? ty : ty - 4;
+    const int lo = b == 0 ? 0 : (4 << (b - 1)), hi = 4 << b;
+    sched.row_off[ty] = off;
+    sched.blk_off[ty] = blocks;
+    int64_t cnt = 0;
+    if (n) {
+      k_bin_flags2<<<nblocks(n, 256), 256, 0, s>>>(nrp, elig, kind, n, lo, hi, f);
+      scan_inclusive(f, n, s, ar);
+      cnt = d2h(f + n - 1, s);
+      if (cnt) k_bin_place<<<nblocks(n, 256), 256, 0, s>>>(f, n, all + off);
     }
+    off += cnt;
+    blocks += ((cnt + (256 / hi) - 1) / (256 / hi) + 7) & ~(int64_t)7;
   }
-}
-
-template <int G, class TM, class TX, class TY>
-static int64_t map_launch(const EminWork& w, int b, const Csr& M, const TM* mval,
-                          const int64_t* nrp, const TX* X, TY* Y, const double* D, double* part,
-                          hipStream_t s) {
-  constexpr int NG = 256 / G;
-  const int64_t nr = w.mbin_n[b];
-  if (nr == 0) return 0;
-  const unsigned nb = nblocks(nr, NG);
-  k_spmm_map<G, TM, TX, TY><<<nb, 256, 0, s>>>(w.mbin_rows[b], nr, M.rowptr, mval, w.kofs, w.nib,
-                                               w.nnzm, nrp, X, Y, D, part);
-  return nb;
-}
-
-template <int G, class TM, class TX, class TY>
-static int64_t bin_launch(const EminWork& w, int b, const Csr& M, const TM* mval,
-                          const int64_t* nrp, const int32_t* ncol, const TX* X, TY* Y,
-                          const double* D, double* part, hipStream_t s) {
-  constexpr int NG = 256 / G;
-  const int64_t nr = w.bin_n[b];
-  if (nr == 0) return 0;
-  const unsigned nb = nblocks(nr, NG);
-  k_spmm_bin<G, TM, TX, TY><<<nb, 256, 0, s>>>(w.bin_rows[b], nr, M.rowptr, M.col, mval, nrp,
-                                               ncol, X, Y, D, part);
-  return nb;
+  sched.row_off[SPMM_NT] = off;
+  sched.blk_off[SPMM_NT] = blocks;
+  sched.rows = all;
 }
 
 template <class TM, class TX, class TY>
 static int64_t spmm_any(const EminWork& w, const Csr& M, const TM* mval, const int64_t* nrp,
                         const int32_t* ncol, const TX* X, TY* Y, const double* D, double* part,
                         hipStream_t s) {
-  int64_t np = 0;
-  np += map_launch<4>(w, 0, M, mval, nrp, X, Y, D, part ? part + np : nullptr, s);
-  np += map_launch<8>(w, 1, M, mval, nrp, X, Y, D, part ? part + np : nullptr, s);
-  np += map_launch<16>(w, 2, M, mval, nrp, X, Y, D, part ? part + np : nullptr, s);
-  np += map_launch<32>(w, 3, M, mval, nrp, X, Y, D, part ? part + np : nullptr, s);
-  np += bin_launch<4>(w, 0, M, mval, nrp, ncol, X, Y, D, part ? part + np : nullptr, s);
-  np += bin_launch<8>(w, 1, M, mval, nrp, ncol, X, Y, D, part ? part + np : nullptr, s);
-  np += bin_launch<16>(w, 2, M, mval, nrp, ncol, X, Y, D, part ? part + np : nullptr, s);
-  np += bin_launch<32>(w, 3, M, mval, nrp, ncol, X, Y, D, part ? part + np : nullptr, s);
-  np += bin_launch<64>(w, 4, M, mval, nrp, ncol, X, Y, D, part ? part + np : nullptr, s);
-  return np;
+  const int64_t nb = w.sched.blk_off[SPMM_NT];
+  if (nb == 0) return 0;
+  k_spmm<TM, TX, TY><<<(unsigned)nb, 256, 0, s>>>(w.sched, M.rowptr, M.col, mval, w.kofs, w.nib,
+                                                   w.nnzm, nrp, ncol, X, Y, D, part);
+  return nb;
 }
 
 // algorithmic bytes of one masked product: M (col + val) and row pointers,
