@@ -55,22 +55,135 @@ def pct(xs, q):
 
 def cpu_baseline(system, wl, seconds, p_nnz_iters):
     """The oracle (single-threaded C, FP64) on the same workload, repeated
-    until `seconds` of CPU work have been spent."""
+    until `seconds` of CPU work have been spent.  Returns the rate and the
+    last oracle hierarchy (the accuracy reference)."""
     from oracle import oracle as O
     times = []
+    levels = None
     t_end = time.perf_counter() + seconds
     while True:
         t0 = time.perf_counter()
-        O.hierarchy(system, wl["nlevels"], tau1_v=wl["tau1_v"], tau1_p=wl["tau1_p"],
-                    iters=wl["iters"], min_dofs=wl["min_dofs"])
+        levels, _ = O.hierarchy(system, wl["nlevels"], tau1_v=wl["tau1_v"], tau1_p=wl["tau1_p"],
+                                iters=wl["iters"], min_dofs=wl["min_dofs"])
         times.append(time.perf_counter() - t0)
         if time.perf_counter() >= t_end:
             break
     mean = sum(times) / len(times)
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return dict(value=p_nnz_iters / mean, unit="P-nnz*iters/s", cores=1, kind="oracle",
                 sample=f"{len(times)} full hierarchy setups of the same workload "
                        f"({sum(times):.1f} s of CPU work, mean {mean * 1e3:.0f} ms)",
-                ms_per_setup=mean * 1e3)
+                ms_per_setup=mean * 1e3, host_cpus=os.cpu_count(), cpu_model=cpu_model), levels
+
+
+def _relfro(a, b):
+    import numpy as np
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(np.asarray(a, np.float64) - np.asarray(b, np.float64)) /
+                 (nb if nb > 0 else 1.0))
+
+
+def accuracy(H, ref_levels, label):
+    """Relative Frobenius errors of P and of the Galerkin blocks, level by level,
+    against a reference hierarchy with the same patterns, and the constraint
+    residual ||P W_c - W|| / ||W|| of every computed P (default modes)."""
+    import numpy as np
+    import scipy.sparse as sp
+    out = []
+    for L, R in zip(H.levels, ref_levels):
+        s = L.pattern.sizes
+        d = {}
+        for name, nnz in (("Pv", "nnz_Pv"), ("Pp", "nnz_Pp"), ("Ac", "nnz_Ac"), ("Bc", "nnz_Bc")):
+            g = getattr(L, name)[:s[nnz]].double().cpu().numpy()
+            r = R[name]
+            d[name] = _relfro(g, r.val) if len(r.val) == len(g) else float("nan")
+        for blk, Pr in (("v", R["Pv"]), ("p", R["Pp"])):
+            g = getattr(L, "P" + blk)[:Pr.nnz].double().cpu().numpy()
+            P = sp.csr_matrix((g, Pr.col, Pr.rowptr), shape=(Pr.nrows, Pr.ncols))
+            W = R["W" + blk]
+            Wc = R["Wc" + blk]
+            nw = float(np.linalg.norm(W))
+            d["constraint_" + blk] = float(np.linalg.norm(P @ Wc - W) / (nw if nw > 0 else 1.0))
+        out.append({k: (float("%.3g" % v) if v == v else None) for k, v in d.items()})
+    worst = lambda keys: max((lv[k] for lv in out for k in keys if lv[k] is not None), default=None)
+    return dict(reference=label, levels=out, max_P=worst(("Pv", "Pp")),
+                max_RAP=worst(("Ac", "Bc")), max_constraint=worst(("constraint_v", "constraint_p")))
+
+
+def oracle_reference(levels):
+    """Reference values and default modes from oracle levels."""
+    import numpy as np
+    out = []
+    for L in levels:
+        Wv = (~L.dir).astype(np.float64)
+        out.append(dict(Pv=L.Pv, Pp=L.Pp, Ac=L.Ac, Bc=L.Bc, Wv=Wv, Wcv=Wv[np.nonzero(L.is_cv)[0]],
+                        Wp=np.ones(L.Pp.nrows), Wcp=np.ones(L.Pp.ncols)))
+    return out
+
+
+def gpu_reference(H, E):
+    """Reference values from a GPU hierarchy (patterns and modes from its views)."""
+    import numpy as np
+    from paper_1607_02489_amd.synth import CSR
+    out = []
+    for L in H.levels:
+        pat = L.pattern
+        Wv = (~pat.array_host(E.VIEW_DIR, np.uint8).astype(bool)).astype(np.float64)
+        cv = pat.array_host(E.VIEW_CV, np.int32)
+        ref = dict(Wv=Wv, Wcv=Wv[cv])
+        for name, what in (("Pv", E.VIEW_PV), ("Pp", E.VIEW_PP), ("Ac", E.VIEW_AC),
+                           ("Bc", E.VIEW_BC)):
+            n, nc, rp, col, val = pat.csr_host(what, getattr(L, name).data_ptr())
+            ref[name] = CSR(int(n), int(nc), rp, col, val)
+        ref["Wp"] = np.ones(ref["Pp"].nrows)
+        ref["Wcp"] = np.ones(ref["Pp"].ncols)
+        out.append(ref)
+    return out
+
+
+def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
+    """Achievable HBM rate of a streaming device copy (torch's copy kernel):
+    bytes read plus bytes written per copy, median of `reps`."""
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    ts = []
+    for _ in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ts = sorted(ts[1:])
+    ms = ts[len(ts) // 2]
+    del a, b
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+def load_traffic(kernel, workload, precision):
+    """HBM bytes per launch measured by rocprofv3 counters (FETCH_SIZE and
+    WRITE_SIZE, scaled by the same counters on a copy kernel of known size),
+    as recorded in profiles/; None when the record is missing or was taken on
+    another version of the kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{precision}_traffic.json")
+    src = os.path.join(ROOT, "paper_1607_02489_amd", "csrc", "emin_cg.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def batch_systems(synth, count=64, seed=1):
@@ -262,7 +375,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="oseen2d_256",
-                    choices=sorted(WORKLOADS) + ["batch64_oseen2d", "serve_oseen3d_channel"])
+                    choices=sorted(WORKLOADS) + ["batch64_oseen2d", "serve_oseen3d_channel",
+                                                 "copy_probe"])
     ap.add_argument("--mixed", action="store_true", help="FP32 masked products, FP64 projection/scalars")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -279,6 +393,15 @@ def main():
     from paper_1607_02489_amd import emin as E
     from paper_1607_02489_amd import synth
 
+    if args.workload == "copy_probe":
+        # streaming copy of a 1 GiB buffer: the achievable rate, and the known
+        # byte counts that scale the HBM counters
+        torch.cuda.init()
+        gbs = copy_bandwidth(torch)
+        print(json.dumps({"workload": "copy_probe", "bytes_read_per_copy": 1 << 30,
+                          "bytes_written_per_copy": 1 << 30, "copies": 6, "copy_gbs": gbs}),
+              flush=True)
+        return
     if args.workload == "batch64_oseen2d":
         torch.cuda.init()
         print(json.dumps(run_batch(args, E, synth, torch)), flush=True)
@@ -349,7 +472,8 @@ def main():
         avg_ms = sp["ms"] / sp["launches"]
         bytes_per = sp["bytes"] / sp["launches"]
         achieved = bytes_per / (avg_ms * 1e-3) / 1e9
-        roof = dict(kernel="masked_spmm (k_spmm)", bound="hbm", achieved=round(achieved, 1),
+        roof = dict(kernel="k_spmm (masked product M*Z on the pattern of P)", bound="hbm",
+                    achieved=round(achieved, 1),
                     peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=None, launches=sp["launches"], avg_us=round(avg_ms * 1e3, 2),
                     algorithmic_bytes_per_launch=round(bytes_per),
@@ -357,10 +481,43 @@ def main():
     breakdown = {k: dict(launches=v["launches"], ms_per_step=round(v["ms"] / args.steps, 3))
                  for k, v in prof.items()}
 
+    # the same hierarchy in plain FP64 on this GPU, for the mixed form
+    fp64_plain = None
+    H64 = None
+    if mixed:
+        prm64 = E.params(wl["tau1_v"], wl["tau1_p"], 1.5e-3, wl["iters"], mixed=False)
+        H64 = E.Hierarchy(system, wl["nlevels"], prm64, min_dofs=wl["min_dofs"])
+        H64.build()
+        torch.cuda.synchronize()
+        t64 = []
+        for _ in range(max(1, min(args.steps, 3))):
+            H64.close()
+            ts = time.perf_counter()
+            H64.build()
+            torch.cuda.synchronize()
+            t64.append(time.perf_counter() - ts)
+        ms64 = sorted(t64)[len(t64) // 2] * 1e3
+        fp64_plain = dict(ms_per_step=ms64, value=p_nnz_iters / (ms64 * 1e-3),
+                          speedup_of_mixed=ms64 / ms_per_step)
+
+    copy_gbs = copy_bandwidth(torch)
+    if roof is not None:
+        roof["copy_gbs"] = round(copy_gbs, 1)
+        roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
+        roof["traffic"] = load_traffic("k_spmm", args.workload, "mixed" if mixed else "fp64")
+
     cpu = None
+    oracle_levels = None
     if not args.no_cpu_baseline:
         log(f"[bench] CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
-        cpu = cpu_baseline(system, wl, args.cpu_seconds, p_nnz_iters)
+        cpu, oracle_levels = cpu_baseline(system, wl, args.cpu_seconds, p_nnz_iters)
+    acc = None
+    if H64 is not None:
+        acc = accuracy(H, gpu_reference(H64, E), "GPU FP64 hierarchy (matches the oracle to 1e-10)")
+    elif oracle_levels is not None:
+        acc = accuracy(H, oracle_reference(oracle_levels), "FP64 oracle")
+    if H64 is not None:
+        H64.close()
 
     H.close()
     out = {
@@ -382,6 +539,8 @@ def main():
                    "precision": "mixed" if mixed else "fp64"},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "accuracy": acc,
+        "fp64_plain": fp64_plain,
         "p50_ms": pct(lat, 50) * 1e3,
         "p99_ms": pct(lat, 99) * 1e3,
         "p_nnz_iters": p_nnz_iters,
