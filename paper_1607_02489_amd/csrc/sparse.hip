@@ -624,6 +624,131 @@ static void sym_big(const int32_t* rows, int64_t nrows, const CsrView& A, const 
     launch_sym<64, 64>(rows, nrows, A, B, hcap, cnt, crp, ccol, nullptr, nullptr, derr, s);
 }
 
+// Symbolic pass over a column window: a row's output columns all lie between
+// the smallest first column and the largest last column of the B rows its
+// A entries select (B rows are sorted).  When that window is at most
+// 32 * wcap columns wide, a visited bitmap over it replaces the hash table:
+// one atomic OR per product, no probing, and the set bits read out in order
+// give the sorted row directly.  Rows with a wider window are listed in ovf
+// (count mode) or skipped (fill mode) and go to the hash kernels.
+template <int G>
+__global__ __launch_bounds__(256) void k_spgemm_win(int64_t n, const int64_t* arp,
+                                                   const int32_t* acol, const int64_t* brp,
+                                                   const int32_t* bcol, int wcap,
+                                                   int64_t* out_cnt, const int64_t* crp,
+                                                   int32_t* ccol, int32_t* ovf, int* novf) {
+  extern __shared__ uint32_t sbits[];
+  constexpr int NG = 256 / G;
+  const int g = threadIdx.x / G, lane = threadIdx.x % G;
+  uint32_t* words = sbits + (size_t)g * wcap;
+  const int64_t row = (int64_t)blockIdx.x * NG + g;
+  if (row >= n) return;   // whole group; the block never synchronises
+  const int64_t ea = arp[row], eb = arp[row + 1];
+  // window bounds
+  int32_t lo = INT32_MAX, hi = -1;
+  for (int64_t e = ea + lane; e < eb; e += G) {
+    const int32_t k = acol[e];
+    const int64_t b0 = brp[k], b1 = brp[k + 1];
+    if (b1 > b0) {
+      const int32_t f = bcol[b0], l = bcol[b1 - 1];
+      lo = f < lo ? f : lo;
+      hi = l > hi ? l : hi;
+    }
+  }
+#pragma unroll
+  for (int m = G / 2; m >= 1; m >>= 1) {
+    const int32_t ol = __shfl_xor(lo, m, G), oh = __shfl_xor(hi, m, G);
+    lo = ol < lo ? ol : lo;
+    hi = oh > hi ? oh : hi;
+  }
+  if (hi < 0) {   // empty output row
+    if (out_cnt && lane == 0) out_cnt[row + 1] = 0;
+    return;
+  }
+  const int64_t width = (int64_t)hi - lo + 1;
+  if (width > 32 * (int64_t)wcap) {
+    if (out_cnt && lane == 0) ovf[atomicAdd(novf, 1)] = (int32_t)row;
+    return;
+  }
+  const int nw = (int)((width + 31) >> 5);
+  for (int t = lane; t < nw; t += G) words[t] = 0u;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  for (int64_t e = ea + lane; e < eb; e += G) {
+    const int32_t k = acol[e];
+    const int64_t b0 = brp[k], b1 = brp[k + 1];
+    for (int64_t f = b0; f < b1; f += 4) {
+      int32_t j[4];
+#pragma unroll
+      for (int q = 0; q < 4; q++) j[q] = f + q < b1 ? bcol[f + q] - lo : -1;
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+        if (j[q] >= 0) atomicOr(&words[j[q] >> 5], 1u << (j[q] & 31));
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  // lane l owns words [l*wpl, (l+1)*wpl)
+  const int wpl = (nw + G - 1) / G;
+  const int w0 = lane * wpl, w1 = (w0 + wpl) < nw ? (w0 + wpl) : nw;
+  int c = 0;
+  for (int t = w0; t < w1; t++) c += __popc(words[t]);
+  int incl = c;   // inclusive scan over the group
+#pragma unroll
+  for (int m = 1; m < G; m <<= 1) {
+    const int o = __shfl_up(incl, m, G);
+    if (lane >= m) incl += o;
+  }
+  const int total = __shfl(incl, G - 1, G);
+  if (out_cnt) {
+    if (lane == 0) out_cnt[row + 1] = total;
+    return;
+  }
+  int32_t* out = ccol + crp[row] + (incl - c);
+  for (int t = w0; t < w1; t++) {
+    uint32_t m = words[t];
+    while (m) {
+      const int b = __builtin_ctz(m);
+      m &= m - 1u;
+      *out++ = lo + 32 * t + b;
+    }
+  }
+}
+
+template <int G>
+static void launch_win(int64_t n, const CsrView& A, const CsrView& B, int wcap, int64_t* cnt,
+                       const int64_t* crp, int32_t* ccol, int32_t* ovf, int* novf,
+                       hipStream_t s) {
+  constexpr int NG = 256 / G;
+  const size_t lds = (size_t)NG * wcap * sizeof(uint32_t);
+  HIP_OK(hipFuncSetAttribute((const void*)k_spgemm_win<G>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  k_spgemm_win<G><<<nblocks(n, NG), 256, lds, s>>>(n, A.rowptr, A.col, B.rowptr, B.col, wcap,
+                                                   cnt, crp, ccol, ovf, novf);
+}
+
+static void win_dispatch(int g, int64_t n, const CsrView& A, const CsrView& B, int wcap,
+                         int64_t* cnt, const int64_t* crp, int32_t* ccol, int32_t* ovf, int* novf,
+                         hipStream_t s) {
+  switch (g) {
+    case 4: launch_win<4>(n, A, B, wcap, cnt, crp, ccol, ovf, novf, s); break;
+    case 8: launch_win<8>(n, A, B, wcap, cnt, crp, ccol, ovf, novf, s); break;
+    case 16: launch_win<16>(n, A, B, wcap, cnt, crp, ccol, ovf, novf, s); break;
+    case 32: launch_win<32>(n, A, B, wcap, cnt, crp, ccol, ovf, novf, s); break;
+    default: launch_win<64>(n, A, B, wcap, cnt, crp, ccol, ovf, novf, s); break;
+  }
+}
+
+// hash kernels for a list of rows (those outside the window kernel's reach)
+template <int G>
+static void launch_sym_rows(const int32_t* rows, int64_t nrows, const CsrView& A,
+                            const CsrView& B, int hcap, int64_t* cnt, const int64_t* crp,
+                            int32_t* ccol, int32_t* ovf, int* novf, int* derr, hipStream_t s) {
+  if (nrows) launch_sym<G, 256>(rows, nrows, A, B, hcap, cnt, crp, ccol, ovf, novf, derr, s);
+}
+
 void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& plan,
                      hipStream_t s, Arena& ar, int* derr) {
   if (A.ncols != B.nrows) throw Error(EMIN_ERR_SHAPE, "spgemm: inner dimensions differ");
@@ -634,28 +759,53 @@ void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& pla
   const double avg_a = A.nrows ? (double)A.nnz / (double)A.nrows : 1.0;
   const int g = pick_g(avg_a);
   const int NG = 256 / g;
+  // window bitmap per group: up to 32 KiB per block
+  const int wcap = (int)std::min<int64_t>(4096, (32 * 1024 / 4) / NG);
+  const int big = 16384;  // hash table of one 64-lane group, 96 KiB of LDS
+  int* lerr = ar.alloc<int>(4);
+  int32_t* ovf = ar.alloc<int32_t>(A.nrows);    // rows wider than the window
+  int32_t* ovf2 = ar.alloc<int32_t>(A.nrows);   // of those, rows the hash table cannot hold
+  HIP_OK(hipMemsetAsync(lerr, 0, 4 * sizeof(int), s));
+  if (A.nrows) win_dispatch(g, A.nrows, A, B, wcap, C.rowptr, nullptr, nullptr, ovf, lerr + 1, s);
+  int hl[4];
+  HIP_OK(hipMemcpyAsync(hl, lerr, sizeof(hl), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  const int nwide = hl[1];
   // table per group within ~48 KiB per block (keys + compacted copy)
   int hcap = 64;
   while ((size_t)NG * 3 * hcap * sizeof(int32_t) <= 48 * 1024 && hcap < 4096) hcap <<= 1;
-  const int big = 16384;  // one 64-lane group, 96 KiB of LDS
-  int* lerr = ar.alloc<int>(2);
-  int32_t* ovf = ar.alloc<int32_t>(A.nrows);
-  HIP_OK(hipMemsetAsync(lerr, 0, 2 * sizeof(int), s));
-  if (A.nrows)
-    sym_dispatch(g, A.nrows, A, B, hcap, C.rowptr, nullptr, nullptr, ovf, lerr + 1, lerr, s);
-  int hl[2];
-  HIP_OK(hipMemcpyAsync(hl, lerr, sizeof(hl), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipStreamSynchronize(s));
-  const int nov = hl[1];
-  if (nov) sym_big(ovf, nov, A, B, big, C.rowptr, nullptr, nullptr, lerr, s);
+  int nov = 0;
+  if (nwide) {
+    switch (g) {
+      case 4: launch_sym_rows<4>(ovf, nwide, A, B, hcap, C.rowptr, nullptr, nullptr, ovf2, lerr + 2, lerr, s); break;
+      case 8: launch_sym_rows<8>(ovf, nwide, A, B, hcap, C.rowptr, nullptr, nullptr, ovf2, lerr + 2, lerr, s); break;
+      case 16: launch_sym_rows<16>(ovf, nwide, A, B, hcap, C.rowptr, nullptr, nullptr, ovf2, lerr + 2, lerr, s); break;
+      case 32: launch_sym_rows<32>(ovf, nwide, A, B, hcap, C.rowptr, nullptr, nullptr, ovf2, lerr + 2, lerr, s); break;
+      default: launch_sym_rows<64>(ovf, nwide, A, B, hcap, C.rowptr, nullptr, nullptr, ovf2, lerr + 2, lerr, s); break;
+    }
+    HIP_OK(hipMemcpyAsync(hl, lerr, sizeof(hl), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    nov = hl[2];
+    if (nov) sym_big(ovf2, nov, A, B, big, C.rowptr, nullptr, nullptr, lerr, s);
+  }
   C.nnz = rowptr_from_counts(C.rowptr, C.nrows, s, ar);
   if (d2h(lerr, s)) throw Error(EMIN_ERR_CAPACITY, "spgemm: output row exceeds the LDS table");
   C.col = ar.alloc<int32_t>(C.nnz);
   C.val = ar.alloc<double>(C.nnz);
-  // the first fill skips the rows that overflowed; the big table redoes them
-  if (A.nrows)
-    sym_dispatch(g, A.nrows, A, B, hcap, nullptr, C.rowptr, C.col, ovf, lerr + 1, lerr, s);
-  if (nov) sym_big(ovf, nov, A, B, big, nullptr, C.rowptr, C.col, lerr, s);
+  // the window fill skips the wide rows; the hash kernels fill those (the
+  // first hash fill skips the rows its table could not hold; the big table
+  // does them)
+  if (A.nrows) win_dispatch(g, A.nrows, A, B, wcap, nullptr, C.rowptr, C.col, nullptr, nullptr, s);
+  if (nwide) {
+    switch (g) {
+      case 4: launch_sym_rows<4>(ovf, nwide, A, B, hcap, nullptr, C.rowptr, C.col, ovf2, lerr + 3, lerr, s); break;
+      case 8: launch_sym_rows<8>(ovf, nwide, A, B, hcap, nullptr, C.rowptr, C.col, ovf2, lerr + 3, lerr, s); break;
+      case 16: launch_sym_rows<16>(ovf, nwide, A, B, hcap, nullptr, C.rowptr, C.col, ovf2, lerr + 3, lerr, s); break;
+      case 32: launch_sym_rows<32>(ovf, nwide, A, B, hcap, nullptr, C.rowptr, C.col, ovf2, lerr + 3, lerr, s); break;
+      default: launch_sym_rows<64>(ovf, nwide, A, B, hcap, nullptr, C.rowptr, C.col, ovf2, lerr + 3, lerr, s); break;
+    }
+    if (nov) sym_big(ovf2, nov, A, B, big, nullptr, C.rowptr, C.col, lerr, s);
+  }
   if (d2h(lerr, s)) throw Error(EMIN_ERR_CAPACITY, "spgemm: fill pass overflow");
   plan.max_row = max_row_len(C.rowptr, C.nrows, s, ar);
   const double avg_b = B.nrows ? (double)B.nnz / (double)B.nrows : 1.0;
