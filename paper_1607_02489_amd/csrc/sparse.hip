@@ -85,25 +85,168 @@ int64_t rowptr_from_counts(int64_t* rowptr, int64_t n, hipStream_t s, Arena& ar)
 // ---------------------------------------------------------------------------
 // validation
 // ---------------------------------------------------------------------------
-__global__ void k_validate(const int64_t* rp, const int32_t* col, const double* val, int64_t n,
-                           int64_t ncols, int64_t nnz, int* derr) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// ---------------------------------------------------------------------------
+// Row kernels with G lanes per row (G a power of two, at most 64, so a group
+// never spans two waves): loads of a row are coalesced and its entries are
+// processed in parallel.  Control flow is uniform within a group.
+// ---------------------------------------------------------------------------
+static int lanes_for(const CsrView& A) {
+  const double avg = A.nrows ? (double)A.nnz / (double)A.nrows : 1.0;
+  int g = 4;
+  while (g < 64 && g < avg) g <<= 1;
+  return g;
+}
+
+template <int G>
+__device__ __forceinline__ uint64_t group_ballot(bool p) {
+  const uint64_t b = __ballot(p);
+  if (G == 64) return b;
+  const int base = (int)(threadIdx.x & 63) & ~(G - 1);
+  return (b >> base) & ((1ull << G) - 1ull);
+}
+
+#define ROWS_DISPATCH(g, KERNEL, n, s, ...)                                              \
+  do {                                                                                   \
+    switch (g) {                                                                         \
+      case 4: KERNEL<4><<<nblocks(n, 64), 256, 0, s>>>(__VA_ARGS__); break;              \
+      case 8: KERNEL<8><<<nblocks(n, 32), 256, 0, s>>>(__VA_ARGS__); break;              \
+      case 16: KERNEL<16><<<nblocks(n, 16), 256, 0, s>>>(__VA_ARGS__); break;            \
+      case 32: KERNEL<32><<<nblocks(n, 8), 256, 0, s>>>(__VA_ARGS__); break;             \
+      default: KERNEL<64><<<nblocks(n, 4), 256, 0, s>>>(__VA_ARGS__); break;             \
+    }                                                                                    \
+  } while (0)
+
+template <int G>
+__global__ __launch_bounds__(256) void k_validate_g(const int64_t* rp, const int32_t* col,
+                                                   const double* val, int64_t n, int64_t ncols,
+                                                   int64_t nnz, int* derr) {
+  const int64_t i = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
+  const int lane = threadIdx.x % G;
   if (i >= n) return;
-  int64_t a = rp[i], b = rp[i + 1];
-  if (a < 0 || b < a || b > nnz) { atomicOr(derr, DERR_PATTERN); return; }
-  int32_t prev = -1;
-  for (int64_t e = a; e < b; e++) {
-    int32_t c = col[e];
-    if (c <= prev || c >= ncols) { atomicOr(derr, DERR_PATTERN); return; }
-    prev = c;
-    if (val && !isfinite(val[e])) atomicOr(derr, DERR_VALUE);
+  const int64_t a = rp[i], b = rp[i + 1];
+  if (a < 0 || b < a || b > nnz) {
+    if (lane == 0) atomicOr(derr, DERR_PATTERN);
+    return;
+  }
+  bool badp = false, badv = false;
+  for (int64_t e = a + lane; e < b; e += G) {
+    const int32_t c = col[e];
+    const int32_t prev = e > a ? col[e - 1] : -1;
+    if (c <= prev || c >= ncols) badp = true;
+    if (val && !isfinite(val[e])) badv = true;
+  }
+  if (badp) atomicOr(derr, DERR_PATTERN);
+  if (badv) atomicOr(derr, DERR_VALUE);
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_transpose_fill_g(const int64_t* rp, const int32_t* col,
+                                                         int64_t n, int64_t* cursor,
+                                                         int32_t* colT, int32_t* src) {
+  const int64_t i = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
+  const int lane = threadIdx.x % G;
+  if (i >= n) return;
+  for (int64_t e = rp[i] + lane; e < rp[i + 1]; e += G) {
+    const int64_t p = (int64_t)atomicAdd((unsigned long long*)&cursor[col[e]], 1ull);
+    colT[p] = (int32_t)i;
+    src[p] = (int32_t)e;
   }
 }
 
+template <int G>
+__global__ __launch_bounds__(256) void k_dirichlet_g(const int64_t* rp, const int32_t* col,
+                                                    const double* val, int64_t n, uint8_t* dir) {
+  const int64_t i = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
+  const int lane = threadIdx.x % G;
+  if (i >= n) return;
+  bool nz = false;
+  for (int64_t e = rp[i] + lane; e < rp[i + 1]; e += G)
+    if (col[e] != i && val[e] != 0.0) nz = true;
+  const uint64_t m = group_ballot<G>(nz);
+  if (lane == 0) dir[i] = m ? 0 : 1;
+}
+
+// eq. (e:filtering), squared form, per entry; the row count adds the diagonal
+template <int G>
+__global__ __launch_bounds__(256) void k_filter_count_g(const int64_t* rp, const int32_t* col,
+                                                       const double* val, int64_t n, double t2,
+                                                       const double* d, uint8_t* keep,
+                                                       int64_t* cnt) {
+  const int64_t i = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
+  const int lane = threadIdx.x % G;
+  if (i >= n) return;
+  const double di = d[i];
+  int64_t c = 1;
+  for (int64_t e0 = rp[i]; e0 < rp[i + 1]; e0 += G) {
+    const int64_t e = e0 + lane;
+    bool kept_off = false;
+    if (e < rp[i + 1]) {
+      const int32_t j = col[e];
+      uint8_t k = 1;
+      if (j != i) {
+        const double v = val[e];
+        const double lhs = v * v;
+        const double rhs = t2 * fabs(di * d[j]);
+        k = lhs > rhs;
+        kept_off = k;
+      }
+      keep[e] = k;
+    }
+    c += __popcll(group_ballot<G>(kept_off));
+  }
+  if (lane == 0) cnt[i + 1] = c;
+}
+
+// Filtered row: kept off-diagonals in column order with the diagonal at its
+// sorted place; the diagonal is a_ii plus the dropped entries added one by
+// one in ascending column order (the same sums, in the same order, as a
+// sequential pass over the row).
+template <int G>
+__global__ __launch_bounds__(256) void k_filter_fill_g(const int64_t* rp, const int32_t* col,
+                                                      const double* val, int64_t n,
+                                                      const uint8_t* keep, const double* d,
+                                                      const int64_t* orp, int32_t* ocol,
+                                                      double* oval) {
+  const int64_t i = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
+  const int lane = threadIdx.x % G;
+  if (i >= n) return;
+  const int64_t a = rp[i], b = rp[i + 1], base = orp[i];
+  const uint64_t below = (1ull << lane) - 1ull;
+  double lump = d[i];
+  int64_t kept = 0, kept_lt = 0;
+  for (int64_t e0 = a; e0 < b; e0 += G) {
+    const int64_t e = e0 + lane;
+    const bool ok = e < b;
+    const int32_t j = ok ? col[e] : (int32_t)i;
+    const double v = ok ? val[e] : 0.0;
+    const bool k = ok && j != i && keep[e];
+    const bool dropped = ok && j != i && !keep[e];
+    uint64_t md = group_ballot<G>(dropped);
+    while (md) {
+      const int t = __builtin_ctzll(md);
+      md &= md - 1ull;
+      lump = lump + __shfl(v, t, G);
+    }
+    const uint64_t mk = group_ballot<G>(k);
+    if (k) {
+      const int64_t p = base + kept + __popcll(mk & below) + (j > i ? 1 : 0);
+      if (ocol) ocol[p] = j;
+      oval[p] = v;
+    }
+    kept += __popcll(mk);
+    kept_lt += __popcll(group_ballot<G>(k && j < i));
+  }
+  if (lane == 0) {
+    if (ocol) ocol[base + kept_lt] = (int32_t)i;
+    oval[base + kept_lt] = lump;
+  }
+}
+
+
 void validate_csr(const CsrView& A, bool values, int* derr, hipStream_t s) {
   if (A.nrows == 0) return;
-  k_validate<<<nblocks(A.nrows, 256), 256, 0, s>>>(A.rowptr, A.col, values ? A.val : nullptr,
-                                                    A.nrows, A.ncols, A.nnz, derr);
+  ROWS_DISPATCH(lanes_for(A), k_validate_g, A.nrows, s, A.rowptr, A.col,
+                values ? A.val : nullptr, A.nrows, A.ncols, A.nnz, derr);
 }
 
 // ---------------------------------------------------------------------------
@@ -114,16 +257,6 @@ __global__ void k_count_cols(const int32_t* col, int64_t nnz, int64_t* cnt) {
   if (e < nnz) atomicAdd((unsigned long long*)&cnt[col[e] + 1], 1ull);
 }
 
-__global__ void k_transpose_fill(const int64_t* rp, const int32_t* col, int64_t n,
-                                 int64_t* cursor, int32_t* colT, int32_t* src) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  for (int64_t e = rp[i]; e < rp[i + 1]; e++) {
-    int64_t p = (int64_t)atomicAdd((unsigned long long*)&cursor[col[e]], 1ull);
-    colT[p] = (int32_t)i;
-    src[p] = (int32_t)e;
-  }
-}
 
 // Restores ascending order inside each row of the transpose (the atomic fill
 // leaves it arbitrary; keys are distinct within a row).  Rows are binned by
@@ -152,25 +285,24 @@ __device__ __forceinline__ int sort_bin(int64_t L) {
   return 8;
 }
 
-// one atomic per bin per wave (ballot-aggregated)
-__global__ void k_sort_classify(const int64_t* rp, int64_t n, int32_t* lists, int32_t* counts) {
+// one global atomic per bin per block (LDS counters first)
+__global__ __launch_bounds__(1024) void k_sort_classify(const int64_t* rp, int64_t n,
+                                                       int32_t* lists, int32_t* counts) {
+  __shared__ int lcnt[SORT_NBIN], lbase[SORT_NBIN];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (threadIdx.x < SORT_NBIN) lcnt[threadIdx.x] = 0;
+  __syncthreads();
   int b = -1;
   if (i < n) {
     const int64_t L = rp[i + 1] - rp[i];
     if (L > 1) b = sort_bin(L);
   }
-  const int lane = threadIdx.x & 63;
-  const unsigned long long below = (1ull << lane) - 1ull;
-  for (int q = 0; q < SORT_NBIN; q++) {
-    const unsigned long long m = __ballot(b == q);
-    if (m == 0ull) continue;
-    const int leader = __builtin_ctzll(m);
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&counts[q], __popcll(m));
-    base = __shfl(base, leader, 64);
-    if (b == q) lists[(int64_t)q * n + base + __popcll(m & below)] = (int32_t)i;
-  }
+  const int lpos = b >= 0 ? atomicAdd(&lcnt[b], 1) : 0;
+  __syncthreads();
+  if (threadIdx.x < SORT_NBIN && lcnt[threadIdx.x])
+    lbase[threadIdx.x] = atomicAdd(&counts[threadIdx.x], lcnt[threadIdx.x]);
+  __syncthreads();
+  if (b >= 0) lists[(int64_t)b * n + lbase[b] + lpos] = (int32_t)i;
 }
 
 template <int G>
@@ -287,7 +419,7 @@ void sort_rows(const int64_t* rp, int64_t n, int32_t* key, int32_t* src, hipStre
   int32_t* lists = ar.alloc<int32_t>((size_t)SORT_NBIN * n);
   int32_t* counts = ar.alloc<int32_t>(SORT_NBIN);
   HIP_OK(hipMemsetAsync(counts, 0, sizeof(int32_t) * SORT_NBIN, s));
-  k_sort_classify<<<nblocks(n, 256), 256, 0, s>>>(rp, n, lists, counts);
+  k_sort_classify<<<nblocks(n, 1024), 1024, 0, s>>>(rp, n, lists, counts);
   // grids sized for the worst case, capped (the kernels walk grid-stride)
   auto grid = [&](int64_t per) { return (unsigned)std::min<int64_t>(nblocks(n, per), 4096); };
   k_sort_group<4><<<grid(64), 256, 0, s>>>(rp, lists + 0 * n, counts + 0, key, src);
@@ -323,8 +455,8 @@ void transpose_pattern(const CsrView& A, Csr& At, int32_t*& src, hipStream_t s, 
   HIP_OK(hipMemcpyAsync(cursor, At.rowptr, sizeof(int64_t) * (At.nrows + 1),
                         hipMemcpyDeviceToDevice, s));
   if (A.nrows)
-    k_transpose_fill<<<nblocks(A.nrows, 256), 256, 0, s>>>(A.rowptr, A.col, A.nrows, cursor,
-                                                            At.col, src);
+    ROWS_DISPATCH(lanes_for(A), k_transpose_fill_g, A.nrows, s, A.rowptr, A.col, A.nrows, cursor,
+                  At.col, src);
   sort_rows(At.rowptr, At.nrows, At.col, src, s, ar);
 }
 
@@ -892,56 +1024,7 @@ void diag_of(const CsrView& A, double* d, hipStream_t s) {
   if (A.nrows) k_diag<<<nblocks(A.nrows, 256), 256, 0, s>>>(A.rowptr, A.col, A.val, A.nrows, d);
 }
 
-__global__ void k_filter_count(const int64_t* rp, const int32_t* col, const double* val,
-                               int64_t n, double t2, const double* d, uint8_t* keep,
-                               int64_t* cnt) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int64_t c = 1;
-  const double di = d[i];
-  for (int64_t e = rp[i]; e < rp[i + 1]; e++) {
-    const int32_t j = col[e];
-    if (j == i) { keep[e] = 1; continue; }
-    const double v = val[e];
-    const double lhs = v * v;
-    const double rhs = t2 * fabs(di * d[j]);
-    const uint8_t k = lhs > rhs;
-    keep[e] = k;
-    c += k;
-  }
-  cnt[i + 1] = c;
-}
 
-__global__ void k_filter_fill(const int64_t* rp, const int32_t* col, const double* val, int64_t n,
-                              const uint8_t* keep, const double* d, const int64_t* orp,
-                              int32_t* ocol, double* oval) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double lump = d[i];
-  for (int64_t e = rp[i]; e < rp[i + 1]; e++)
-    if (col[e] != i && !keep[e]) lump = lump + val[e];
-  int64_t p = orp[i];
-  bool placed = false;
-  for (int64_t e = rp[i]; e < rp[i + 1]; e++) {
-    const int32_t j = col[e];
-    if (!placed && j > i) {
-      if (ocol) ocol[p] = (int32_t)i;
-      oval[p] = lump;
-      p++;
-      placed = true;
-    }
-    if (j == i) continue;
-    if (keep[e]) {
-      if (ocol) ocol[p] = j;
-      oval[p] = val[e];
-      p++;
-    }
-  }
-  if (!placed) {
-    if (ocol) ocol[p] = (int32_t)i;
-    oval[p] = lump;
-  }
-}
 
 void filter_symbolic(const CsrView& A, double tau1, const double* d, uint8_t* keep, Csr& At,
                      hipStream_t s, Arena& ar) {
@@ -949,21 +1032,21 @@ void filter_symbolic(const CsrView& A, double tau1, const double* d, uint8_t* ke
   At.rowptr = ar.alloc<int64_t>(A.nrows + 1);
   const double t2 = tau1 * tau1;
   if (A.nrows)
-    k_filter_count<<<nblocks(A.nrows, 256), 256, 0, s>>>(A.rowptr, A.col, A.val, A.nrows, t2, d,
-                                                          keep, At.rowptr);
+    ROWS_DISPATCH(lanes_for(A), k_filter_count_g, A.nrows, s, A.rowptr, A.col, A.val, A.nrows, t2,
+                  d, keep, At.rowptr);
   At.nnz = rowptr_from_counts(At.rowptr, A.nrows, s, ar);
   At.col = ar.alloc<int32_t>(At.nnz);
   At.val = ar.alloc<double>(At.nnz);
   if (A.nrows)
-    k_filter_fill<<<nblocks(A.nrows, 256), 256, 0, s>>>(A.rowptr, A.col, A.val, A.nrows, keep, d,
-                                                         At.rowptr, At.col, At.val);
+    ROWS_DISPATCH(lanes_for(A), k_filter_fill_g, A.nrows, s, A.rowptr, A.col, A.val, A.nrows, keep,
+                  d, At.rowptr, At.col, At.val);
 }
 
 void filter_numeric(const CsrView& A, const uint8_t* keep, const double* d, const Csr& At,
                     hipStream_t s) {
   if (A.nrows)
-    k_filter_fill<<<nblocks(A.nrows, 256), 256, 0, s>>>(A.rowptr, A.col, A.val, A.nrows, keep, d,
-                                                         At.rowptr, nullptr, At.val);
+    ROWS_DISPATCH(lanes_for(A), k_filter_fill_g, A.nrows, s, A.rowptr, A.col, A.val, A.nrows, keep,
+                  d, At.rowptr, (int32_t*)nullptr, At.val);
 }
 
 // ---------------------------------------------------------------------------
@@ -1024,19 +1107,10 @@ void symmetrize_numeric(const double* aval, const int32_t* ia, const int32_t* ib
 }
 
 // a Dirichlet row has no nonzero off-diagonal value
-__global__ void k_dirichlet(const int64_t* rp, const int32_t* col, const double* val, int64_t n,
-                            uint8_t* dir) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  uint8_t d = 1;
-  for (int64_t e = rp[i]; e < rp[i + 1]; e++)
-    if (col[e] != i && val[e] != 0.0) d = 0;
-  dir[i] = d;
-}
 
 void dirichlet_rows(const CsrView& A, uint8_t* dir, hipStream_t s) {
   if (A.nrows)
-    k_dirichlet<<<nblocks(A.nrows, 256), 256, 0, s>>>(A.rowptr, A.col, A.val, A.nrows, dir);
+    ROWS_DISPATCH(lanes_for(A), k_dirichlet_g, A.nrows, s, A.rowptr, A.col, A.val, A.nrows, dir);
 }
 
 }  // namespace emin
