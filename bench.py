@@ -207,7 +207,11 @@ def run_batch(args, E, synth, torch):
         f"{time.perf_counter() - t0:.1f}s")
     ds = [E.DeviceSystem.upload(s) for s in systems]
     iters, nlev, mind = 5, 4, 200
-    mixed = E.params(iters=iters, mixed=True)
+    # masked-product schedules autotuned per problem shape (the first build of
+    # a shape times the candidates, later ones reuse the choice)
+    E.autotune_reset()
+    mixed = E.params(iters=iters, mixed=True, autotune=True)
+    mixed_default = E.params(iters=iters, mixed=True)
     fp64 = E.params(iters=iters)
     torch.cuda.synchronize()
 
@@ -229,16 +233,36 @@ def run_batch(args, E, synth, torch):
                 h.close()
         log(f"[bench] batch build {k + 1}/{args.steps}: {build_ms[-1]:.1f} ms")
     p_nnz_iters = pnnz(hs) * iters
-    B = E.Batch(hs)
+    tune = E.autotune_stats()
+    codes = {}
+    for h in hs:
+        for z in h.sizes():
+            for k in ("sched_v", "sched_p"):
+                name = E.sched_name(z[k] & 0xF)
+                codes[name] = codes.get(name, 0) + 1
     stream = torch.cuda.current_stream()
-    rep_ms = []
-    for _ in range(max(5, args.steps)):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        B.run()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        rep_ms.append(e0.elapsed_time(e1))
+
+    def replay_ms(batch):
+        ts = []
+        for _ in range(max(5, args.steps)):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            batch.run()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return sorted(ts)[len(ts) // 2]
+
+    B = E.Batch(hs)
+    rm = replay_ms(B)
+    # the same batch with the default schedules, for comparison
+    hd = E.build_batch(ds, mixed_default, nlev, mind, max_parallel=16)
+    torch.cuda.synchronize()
+    Bd = E.Batch(hd)
+    rmd = replay_ms(Bd)
+    Bd.close()
+    for h in hd:
+        h.close()
     # plain FP64, one system after another (same GPU)
     for k in range(max(1, args.steps // 2)):
         torch.cuda.synchronize()
@@ -262,7 +286,6 @@ def run_batch(args, E, synth, torch):
     for h in hs:
         h.close()
     bm = sorted(build_ms)[len(build_ms) // 2]
-    rm = sorted(rep_ms)[len(rep_ms) // 2]
     sm = sorted(seq_ms)[len(seq_ms) // 2]
     si = sorted(seq_inc)[len(seq_inc) // 2]
     return {
@@ -279,7 +302,9 @@ def run_batch(args, E, synth, torch):
         "roofline": None, "cpu_baseline": None,
         "p_nnz_iters": p_nnz_iters,
         "graph_replay": {"ms": rm, "value": p_nnz_iters / (rm * 1e-3),
-                         "what": "numeric phases of all 64 hierarchies as one hipGraph launch"},
+                         "what": "numeric phases of all 64 hierarchies as one hipGraph launch",
+                         "default_schedule_ms": rmd},
+        "autotune": {"stats": tune, "schedules": codes},
         "fp64_sequential": {"build_ms": sm, "value": seq_pnnz / (sm * 1e-3),
                             "incremental_ms": si, "incremental_value": seq_pnnz / (si * 1e-3)},
     }

@@ -60,7 +60,10 @@ typedef enum {
 enum { EMIN_PREC_F64 = 0, EMIN_PREC_MIXED = 1 };
 enum {
   EMIN_FLAG_ENERGY = 1u,    /* emin_setup: record the energy trace(P^T M P) per step */
-  EMIN_FLAG_VALIDATE = 2u   /* check values for NaN/Inf */
+  EMIN_FLAG_VALIDATE = 2u,  /* check values for NaN/Inf */
+  EMIN_FLAG_AUTOTUNE = 4u   /* emin_pattern: time candidate schedules of the masked
+                               product on this pattern (or reuse the choice made for
+                               the same problem shape) and keep the fastest */
 };
 #define EMIN_MAX_ITERS 32
 
@@ -105,6 +108,10 @@ typedef struct {
   int64_t nnz_Mv, nnz_Mp;   /* energy operators */
   int64_t nnz_Ac, nnz_Bc;   /* coarse scalar velocity block and coarse divergence */
   int64_t device_bytes;     /* device memory held by the handle */
+  int64_t sched_v, sched_p; /* masked-product schedule of each block: bit 0 intersection
+                               maps used, bit 1 lanes per row doubled, bit 2 XCD split by
+                               row class; bits 4-5: 0 default, 1 autotuned on this
+                               pattern, 2 reused from an earlier tuning of the same shape */
 } emin_sizes_t;
 
 /* Device-resident report of emin_setup (read it with emin_sync_report). */
@@ -193,6 +200,12 @@ emin_status emin_memcpy_d2h(void *dst_host, const void *src_dev, size_t bytes, v
 void emin_pattern_destroy(emin_pattern_t *h);
 /* Frees the cached device chunks; returns the bytes released. */
 int64_t emin_release_cached(void);
+
+/* Autotuner bookkeeping (process-wide): out[0] shapes tuned by timing,
+ * out[1] patterns that reused a tuned shape, out[2] candidate schedules timed,
+ * out[3] entries in the table.  emin_autotune_reset() empties the table. */
+emin_status emin_autotune_stats(int64_t *out4);
+emin_status emin_autotune_reset(void);
 
 const char *emin_status_string(emin_status s);
 const char *emin_version(void);

@@ -230,8 +230,9 @@ void build_pattern(emin_pattern_t* h, const emin_system_t* sys, const emin_param
   h->ev.smax = (int)max_row_len(h->vp.N.rowptr, nv, s, ar);
   h->ep.smax = (int)max_row_len(h->cp.N.rowptr, np, s, ar);
   if (h->ev.smax > 64 || h->ep.smax > 64) throw Error(EMIN_ERR_CAPACITY, "pattern row > 64");
-  h->ev.make_bins(h->Mv, h->vp.N.rowptr, h->vp.N.col, s, ar);
-  h->ep.make_bins(h->Mp, h->cp.N.rowptr, h->cp.N.col, s, ar);
+  const bool tune = (prm->flags & EMIN_FLAG_AUTOTUNE) != 0;
+  h->ev.make_bins(h->Mv, h->vp.N.rowptr, h->vp.N.col, s, ar, tune);
+  h->ep.make_bins(h->Mp, h->cp.N.rowptr, h->cp.N.col, s, ar, tune);
   h->Mvf = ar.alloc<float>(h->Mv.nnz);
   h->Mpf = ar.alloc<float>(h->Mp.nnz);
   h->Wv_def = ar.alloc<double>(nv);
@@ -292,6 +293,8 @@ void build_pattern(emin_pattern_t* h, const emin_system_t* sys, const emin_param
   z.nnz_Ac = h->Ac.nnz;
   z.nnz_Bc = h->Bc.nnz;
   z.device_bytes = (int64_t)ar.bytes();
+  z.sched_v = h->ev.sched_code();
+  z.sched_p = h->ep.sched_code();
 }
 
 void check_same_structure(const emin_pattern_t* h, const emin_system_t* sys) {
@@ -426,6 +429,17 @@ emin_status emin_pattern(const emin_system_t* sys, const emin_params_t* prm, voi
   }
   set_last_error("");
   *out = h;
+  return EMIN_OK;
+}
+
+emin_status emin_autotune_stats(int64_t* out4) {
+  if (!out4) return EMIN_ERR_ARG;
+  emin::autotune_stats(out4);
+  return EMIN_OK;
+}
+
+emin_status emin_autotune_reset(void) {
+  emin::autotune_clear();
   return EMIN_OK;
 }
 

@@ -11,6 +11,12 @@
 #include "emin_cg.h"
 #include "prof.h"
 
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <map>
+#include <mutex>
+
 namespace emin {
 
 constexpr int RB = 256;  // block size of row-wise kernels
@@ -91,17 +97,16 @@ __device__ __forceinline__ TX find_in_group(int32_t js, int32_t c, TX z, bool& h
 }
 
 template <int G, class TM, class TX, class TY>
-__device__ __forceinline__ double spmm_search_rows(int64_t lb, const int32_t* rows, int64_t nrows,
-                                                   const int64_t* mrp, const int32_t* mcol,
-                                                   const TM* mval, const int64_t* nrp,
-                                                   const int32_t* ncol, const TX* X, TY* Y,
-                                                   const double* D) {
+__device__ __forceinline__ void spmm_search_rows(int64_t lb, const int32_t* rows, int64_t nrows,
+                                                 const int64_t* mrp, const int32_t* mcol,
+                                                 const TM* mval, const int64_t* nrp,
+                                                 const int32_t* ncol, const TX* X, TY* Y,
+                                                 const double* D, double* rowdot) {
   using TA = TM;
   constexpr int NG = 256 / G;
   constexpr int U = 4;
   const int g = threadIdx.x / G, lane = threadIdx.x % G;
   const int64_t r = lb * NG + g;
-  double dot = 0.0;
   if (r < nrows) {
     const int32_t i = rows[r];
     const int64_t na = nrp[i];
@@ -150,12 +155,15 @@ __device__ __forceinline__ double spmm_search_rows(int64_t lb, const int32_t* ro
         }
       }
     }
-    if (lane < ni) {
-      Y[na + lane] = (TY)acc;
-      if (D) dot = D[na + lane] * (double)acc;
+    if (lane < ni) Y[na + lane] = (TY)acc;
+    if (rowdot) {
+      // <D, Y> of the row, summed in slot order by lane 0
+      const double pr = lane < ni ? D[na + lane] * (double)acc : 0.0;
+      double sum = 0.0;
+      for (int t = 0; t < ni; t++) sum = sum + __shfl(pr, t, G);
+      if (lane == 0) rowdot[i] = sum;
     }
   }
-  return dot;
 }
 
 // Precomputed intersection maps.  For an M entry (i,k), slot s of N_i meets
@@ -234,11 +242,12 @@ struct MapWin {
 };
 
 template <int G, class TM, class TX, class TY>
-__device__ __forceinline__ double spmm_map_rows(int64_t lb, const int32_t* rows, int64_t nrows,
-                                                const int64_t* mrp, const TM* mval,
-                                                const int32_t* kofs, const uint32_t* nib,
-                                                int64_t nnzm, const int64_t* nrp, const TX* X,
-                                                TY* Y, const double* D, unsigned char* smem) {
+__device__ __forceinline__ void spmm_map_rows(int64_t lb, const int32_t* rows, int64_t nrows,
+                                              const int64_t* mrp, const TM* mval,
+                                              const int32_t* kofs, const uint32_t* nib,
+                                              int64_t nnzm, const int64_t* nrp, const TX* X,
+                                              TY* Y, const double* D, double* rowdot,
+                                              unsigned char* smem) {
   using TA = TM;
   using W = MapWin<G>;
   constexpr int NG = W::NG, NP = W::NP, CH = W::CH;
@@ -252,7 +261,6 @@ __device__ __forceinline__ double spmm_map_rows(int64_t lb, const int32_t* rows,
   TM* gm = s_m + g * CH;
   int32_t* gk = s_k + g * CH;
   const uint32_t* gw = s_w + q * (NG * CH) + g * CH;
-  double dot = 0.0;
   if (r < nrows) {
     const int32_t i = rows[r];
     const int64_t na = nrp[i];
@@ -291,12 +299,15 @@ __device__ __forceinline__ double spmm_map_rows(int64_t lb, const int32_t* rows,
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    if (lane < ni) {
-      Y[na + lane] = (TY)acc;
-      if (D) dot = D[na + lane] * (double)acc;
+    if (lane < ni) Y[na + lane] = (TY)acc;
+    if (rowdot) {
+      // <D, Y> of the row, summed in slot order by lane 0
+      const double pr = lane < ni ? D[na + lane] * (double)acc : 0.0;
+      double sum = 0.0;
+      for (int t = 0; t < ni; t++) sum = sum + __shfl(pr, t, G);
+      if (lane == 0) rowdot[i] = sum;
     }
   }
-  return dot;
 }
 
 template <int G, class TM>
@@ -314,42 +325,63 @@ constexpr int spmm_smem() {
 
 // The whole masked product in one launch: block ranges serve the row classes
 // (map rows with G = 4, 8, 16, 32 lanes, then searched rows with G = 4 ...
-// 64).  Every class has a multiple of 8 blocks and each XCD (which receives
-// the hardware blocks x, x+8, ...) takes the x-th eighth of every class: the
-// load is balanced across XCDs and each XCD works on contiguous rows.
+// 64).  Every class has a multiple of 8 blocks.  With xcd_split each XCD
+// (which receives the hardware blocks x, x+8, ...) takes the x-th eighth of
+// every class, so the load is balanced across XCDs and each XCD works on
+// contiguous rows; otherwise each XCD takes one contiguous eighth of the grid.
 template <class TM, class TX, class TY>
 __global__ __launch_bounds__(256) void k_spmm(SpmmSched S, const int64_t* mrp,
                                               const int32_t* mcol, const TM* mval,
                                               const int32_t* kofs, const uint32_t* nib,
                                               int64_t nnzm, const int64_t* nrp,
                                               const int32_t* ncol, const TX* X, TY* Y,
-                                              const double* D, double* part) {
+                                              const double* D, double* rowdot) {
   __shared__ __align__(16) unsigned char smem[spmm_smem<TM>()];
-  __shared__ double lds[4];
-  const int64_t x = blockIdx.x & 7, j = blockIdx.x >> 3;
   int ty = 0;
+  int64_t lb;
+  if (S.xcd_split) {
+    const int64_t x = blockIdx.x & 7, j = blockIdx.x >> 3;
 #pragma unroll
-  for (int t = 1; t < SPMM_NT; t++) ty += j >= (S.blk_off[t] >> 3) ? 1 : 0;
-  const int64_t q = (S.blk_off[ty + 1] - S.blk_off[ty]) >> 3;
-  const int64_t lb = x * q + (j - (S.blk_off[ty] >> 3));
+    for (int t = 1; t < SPMM_NT; t++) ty += j >= (S.blk_off[t] >> 3) ? 1 : 0;
+    const int64_t q = (S.blk_off[ty + 1] - S.blk_off[ty]) >> 3;
+    lb = x * q + (j - (S.blk_off[ty] >> 3));
+  } else {
+    // one contiguous eighth of the whole grid per XCD
+    const int64_t gb = xcd_block(blockIdx.x, gridDim.x);
+#pragma unroll
+    for (int t = 1; t < SPMM_NT; t++) ty += gb >= S.blk_off[t] ? 1 : 0;
+    lb = gb - S.blk_off[ty];
+  }
   const int32_t* rows = S.rows + S.row_off[ty];
   const int64_t nr = S.row_off[ty + 1] - S.row_off[ty];
-  double dot = 0.0;
+  double* rd = D ? rowdot : nullptr;
   switch (ty) {
-    case 0: dot = spmm_map_rows<4>(lb, rows, nr, mrp, mval, kofs, nib, nnzm, nrp, X, Y, D, smem); break;
-    case 1: dot = spmm_map_rows<8>(lb, rows, nr, mrp, mval, kofs, nib, nnzm, nrp, X, Y, D, smem); break;
-    case 2: dot = spmm_map_rows<16>(lb, rows, nr, mrp, mval, kofs, nib, nnzm, nrp, X, Y, D, smem); break;
-    case 3: dot = spmm_map_rows<32>(lb, rows, nr, mrp, mval, kofs, nib, nnzm, nrp, X, Y, D, smem); break;
-    case 4: dot = spmm_search_rows<4>(lb, rows, nr, mrp, mcol, mval, nrp, ncol, X, Y, D); break;
-    case 5: dot = spmm_search_rows<8>(lb, rows, nr, mrp, mcol, mval, nrp, ncol, X, Y, D); break;
-    case 6: dot = spmm_search_rows<16>(lb, rows, nr, mrp, mcol, mval, nrp, ncol, X, Y, D); break;
-    case 7: dot = spmm_search_rows<32>(lb, rows, nr, mrp, mcol, mval, nrp, ncol, X, Y, D); break;
-    default: dot = spmm_search_rows<64>(lb, rows, nr, mrp, mcol, mval, nrp, ncol, X, Y, D); break;
+    case 0: spmm_map_rows<4>(lb, rows, nr, mrp, mval, kofs, nib, nnzm, nrp, X, Y, D, rd, smem); break;
+    case 1: spmm_map_rows<8>(lb, rows, nr, mrp, mval, kofs, nib, nnzm, nrp, X, Y, D, rd, smem); break;
+    case 2: spmm_map_rows<16>(lb, rows, nr, mrp, mval, kofs, nib, nnzm, nrp, X, Y, D, rd, smem); break;
+    case 3: spmm_map_rows<32>(lb, rows, nr, mrp, mval, kofs, nib, nnzm, nrp, X, Y, D, rd, smem); break;
+    case 4: spmm_search_rows<4>(lb, rows, nr, mrp, mcol, mval, nrp, ncol, X, Y, D, rd); break;
+    case 5: spmm_search_rows<8>(lb, rows, nr, mrp, mcol, mval, nrp, ncol, X, Y, D, rd); break;
+    case 6: spmm_search_rows<16>(lb, rows, nr, mrp, mcol, mval, nrp, ncol, X, Y, D, rd); break;
+    case 7: spmm_search_rows<32>(lb, rows, nr, mrp, mcol, mval, nrp, ncol, X, Y, D, rd); break;
+    default: spmm_search_rows<64>(lb, rows, nr, mrp, mcol, mval, nrp, ncol, X, Y, D, rd); break;
   }
-  if (part) {
-    const double t = block_sum(dot, lds);
-    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// <D, Y> over all rows from the per-row values, in a fixed tree: block b sums
+// rows [1024 b, 1024 b + 1024) (four per thread in order, then the block
+// tree); the result does not depend on how the product was scheduled.
+__global__ __launch_bounds__(256) void k_rowsum(const double* rowdot, int64_t n, double* part) {
+  __shared__ double lds[4];
+  const int64_t b0 = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  double v = 0.0;
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    const int64_t i = b0 + 256 * j;
+    if (i < n) v = v + rowdot[i];
   }
+  const double t = block_sum(v, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
 // R = -Pi(MP), Z = R, partial <R,R>
@@ -523,27 +555,122 @@ void EminWork::allocate(int64_t n_, int64_t nnz_, int64_t nc_, Arena& ar, bool m
   const int64_t np = 2 * (int64_t)nblocks(n, 4) + 16 + 8 * SPMM_NT;
   part = ar.alloc<double>(np);
   part_e = ar.alloc<double>(np);
+  rowdot = ar.alloc<double>(n);
   sc = ar.alloc<CgScalars>(1);
 }
 
-__global__ void k_bin_place(const int64_t* f, int64_t n, int32_t* rows) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int64_t prev = i ? f[i - 1] : 0;
-  if (f[i] != prev) rows[prev] = (int32_t)i;
+// Row classes: -1 for an empty pattern row, 0..3 for map rows with
+// G = 4..32 lanes, 4..8 for searched rows with G = 4..64.  gshift moves a
+// row to a class with 2^gshift times more lanes than its length needs.
+__device__ __forceinline__ int spmm_class(int64_t len, bool map, int gshift) {
+  if (len <= 0) return -1;
+  int b = len <= 4 ? 0 : (len <= 8 ? 1 : (len <= 16 ? 2 : (len <= 32 ? 3 : 4)));
+  b += gshift;
+  if (b > 4) b = 4;
+  return (map && b <= 3) ? b : 4 + b;
 }
 
-__global__ void k_bin_flags2(const int64_t* nrp, const uint8_t* elig, int want, int64_t n, int lo,
-                             int hi, int64_t* f) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int64_t c = nrp[i + 1] - nrp[i];
-  f[i] = (c > lo && c <= hi && (int)elig[i] == want) ? 1 : 0;
+// per block (256 rows) and class, the number of rows; class-major
+__global__ __launch_bounds__(256) void k_sched_count(const int64_t* nrp, const uint8_t* elig,
+                                                    int64_t n, int maps, int gshift,
+                                                    int64_t* bc, int64_t nb) {
+  __shared__ int cnt[SPMM_NT];
+  if (threadIdx.x < SPMM_NT) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int c = i < n ? spmm_class(nrp[i + 1] - nrp[i], maps && elig[i], gshift) : -1;
+  if (c >= 0) atomicAdd(&cnt[c], 1);
+  __syncthreads();
+  if (threadIdx.x < SPMM_NT) bc[(int64_t)threadIdx.x * nb + blockIdx.x] = cnt[threadIdx.x];
 }
+
+// stable placement: class-major, ascending row index within a class
+// (inclusive scan of the class-major block counts gives each block's start)
+__global__ __launch_bounds__(256) void k_sched_place(const int64_t* nrp, const uint8_t* elig,
+                                                    int64_t n, int maps, int gshift,
+                                                    const int64_t* incl, int64_t nb,
+                                                    int32_t* rows) {
+  __shared__ int wc[4][SPMM_NT];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int c = i < n ? spmm_class(nrp[i + 1] - nrp[i], maps && elig[i], gshift) : -1;
+  const uint64_t below = (1ull << lane) - 1ull;
+  uint64_t mine = 0;
+  for (int q = 0; q < SPMM_NT; q++) {
+    const uint64_t m = __ballot(c == q);
+    if (lane == 0) wc[w][q] = __popcll(m);
+    if (c == q) mine = m;
+  }
+  __syncthreads();
+  if (c < 0) return;
+  const int64_t k = (int64_t)c * nb + blockIdx.x;
+  int64_t pos = k ? incl[k - 1] : 0;   // where this block's rows of class c start
+  for (int v = 0; v < w; v++) pos += wc[v][c];
+  rows[pos + __popcll(mine & below)] = (int32_t)i;
+}
+
+__global__ void k_sched_totals(const int64_t* incl, int64_t nb, int64_t* tot) {
+  const int c = threadIdx.x;
+  if (c < SPMM_NT) tot[c] = incl[(int64_t)(c + 1) * nb - 1];
+}
+
+// Schedule of the masked product under one set of options: one counting
+// kernel, one scan, one placement kernel, one read-back of the class ends.
+static void build_sched(const EminWork& w, const int64_t* nrp, const uint8_t* elig, SchedOpts o,
+                        SpmmSched& S, hipStream_t s, Arena& ar) {
+  const int64_t n = w.n;
+  const int64_t nb = n ? (int64_t)nblocks(n, 256) : 0;
+  int64_t tot[SPMM_NT] = {};
+  int32_t* rows = ar.alloc<int32_t>(n);
+  if (n) {
+    int64_t* bc = ar.alloc<int64_t>((size_t)SPMM_NT * nb);
+    int64_t* dtot = ar.alloc<int64_t>(SPMM_NT);
+    k_sched_count<<<(unsigned)nb, 256, 0, s>>>(nrp, elig, n, o.maps, o.gshift, bc, nb);
+    scan_inclusive(bc, SPMM_NT * nb, s, ar);
+    k_sched_place<<<(unsigned)nb, 256, 0, s>>>(nrp, elig, n, o.maps, o.gshift, bc, nb, rows);
+    k_sched_totals<<<1, 64, 0, s>>>(bc, nb, dtot);
+    HIP_OK(hipMemcpyAsync(tot, dtot, sizeof(tot), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+  }
+  int64_t prev = 0, blocks = 0;
+  for (int ty = 0; ty < SPMM_NT; ty++) {
+    const int G = 4 << (ty < 4 ? ty : ty - 4);
+    const int64_t cnt = tot[ty] - prev;
+    S.row_off[ty] = prev;
+    S.blk_off[ty] = blocks;
+    blocks += ((cnt + (256 / G) - 1) / (256 / G) + 7) & ~(int64_t)7;
+    prev = tot[ty];
+  }
+  S.row_off[SPMM_NT] = prev;
+  S.blk_off[SPMM_NT] = blocks;
+  S.rows = rows;
+  S.xcd_split = o.xcd_split;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner of the masked product's schedule.  The candidates (maps on/off,
+// lanes per row tight or doubled, XCD split by class or contiguous) are timed
+// on the pattern itself (median of three products, HIP events); the winner is
+// kept in a process-wide table keyed by the shape of the problem (row count,
+// mean row lengths of M and of the pattern, longest pattern row, bucketed),
+// so later patterns of the same shape reuse it without timing.
+// ---------------------------------------------------------------------------
+namespace {
+std::mutex g_tune_mu;
+std::map<std::array<int64_t, 4>, SchedOpts> g_tune;
+int64_t g_tune_stats[3] = {0, 0, 0};   // timed, reused, candidates timed
+
+std::array<int64_t, 4> shape_key(const EminWork& w, const Csr& M) {
+  auto lg = [](double v) { return (int64_t)std::llround(2.0 * std::log2(v > 1.0 ? v : 1.0)); };
+  return {lg((double)w.n), lg(w.n ? (double)M.nnz / w.n : 1.0),
+          lg(w.n ? (double)w.nnz / w.n : 1.0), (int64_t)w.smax};
+}
+}  // namespace
 
 void EminWork::make_bins(const Csr& M, const int64_t* nrp, const int32_t* ncol, hipStream_t s,
-                         Arena& ar) {
+                         Arena& ar, bool tune) {
   nnzm = M.nnz;
+  if (n) HIP_OK(hipMemsetAsync(rowdot, 0, sizeof(double) * n, s));   // empty rows stay 0
   nplanes = smax <= 8 ? 1 : (smax <= 16 ? 2 : 4);
   kofs = ar.alloc<int32_t>(M.nnz);
   nib = ar.alloc<uint32_t>((size_t)M.nnz * nplanes);
@@ -551,39 +678,109 @@ void EminWork::make_bins(const Csr& M, const int64_t* nrp, const int32_t* ncol, 
   if (n)
     k_spmm_maps<<<nblocks(n, 256), 256, 0, s>>>(M.rowptr, M.col, nrp, ncol, n, M.nnz, nplanes,
                                                 kofs, nib, elig);
-  // classes: map rows with G = 4, 8, 16, 32; searched rows with G = 4 ... 64
-  int64_t* f = ar.alloc<int64_t>(n);
-  int32_t* all = ar.alloc<int32_t>(n);
-  int64_t off = 0, blocks = 0;
-  for (int ty = 0; ty < SPMM_NT; ty++) {
-    const int kind = ty < 4 ? 1 : 0;
-    const int b = ty < 4 ? ty : ty - 4;
-    const int lo = b == 0 ? 0 : (4 << (b - 1)), hi = 4 << b;
-    sched.row_off[ty] = off;
-    sched.blk_off[ty] = blocks;
-    int64_t cnt = 0;
-    if (n) {
-      k_bin_flags2<<<nblocks(n, 256), 256, 0, s>>>(nrp, elig, kind, n, lo, hi, f);
-      scan_inclusive(f, n, s, ar);
-      cnt = d2h(f + n - 1, s);
-      if (cnt) k_bin_place<<<nblocks(n, 256), 256, 0, s>>>(f, n, all + off);
-    }
-    off += cnt;
-    blocks += ((cnt + (256 / hi) - 1) / (256 / hi) + 7) & ~(int64_t)7;
+  tuned = 0;
+  opts = SchedOpts{};
+  if (!tune || n == 0) {
+    build_sched(*this, nrp, elig, opts, sched, s, ar);
+    return;
   }
-  sched.row_off[SPMM_NT] = off;
-  sched.blk_off[SPMM_NT] = blocks;
-  sched.rows = all;
+  const auto key = shape_key(*this, M);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      g_tune_stats[1]++;
+      opts = it->second;
+      tuned = 2;
+      build_sched(*this, nrp, elig, opts, sched, s, ar);
+      return;
+    }
+  }
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  float best = 1e30f;
+  SchedOpts bo{};
+  SpmmSched bs{};
+  int ncand = 0;
+  for (int maps = 1; maps >= 0; maps--)
+    for (int gshift = 0; gshift <= 1; gshift++)
+      for (int xs = 1; xs >= 0; xs--) {
+        const SchedOpts o{maps != 0, gshift, xs != 0};
+        SpmmSched S{};
+        build_sched(*this, nrp, elig, o, S, s, ar);
+        const SpmmSched keep = sched;
+        sched = S;
+        float t[3];
+        for (int r = 0; r < 3; r++) {
+          HIP_OK(hipEventRecord(e0, s));
+          masked_spmm(*this, M, nrp, ncol, Z, Q, nullptr, part, nullptr, s);
+          HIP_OK(hipEventRecord(e1, s));
+          HIP_OK(hipEventSynchronize(e1));
+          HIP_OK(hipEventElapsedTime(&t[r], e0, e1));
+        }
+        sched = keep;
+        std::sort(t, t + 3);
+        ncand++;
+        if (t[1] < best) {
+          best = t[1];
+          bo = o;
+          bs = S;
+        }
+      }
+  HIP_OK(hipEventDestroy(e0));
+  HIP_OK(hipEventDestroy(e1));
+  sched = bs;
+  opts = bo;
+  tuned = 1;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = bo;
+  g_tune_stats[0]++;
+  g_tune_stats[2] += ncand;
+}
+
+int32_t EminWork::sched_code() const {
+  return (int32_t)((opts.maps ? 1 : 0) | (opts.gshift ? 2 : 0) | (opts.xcd_split ? 4 : 0) |
+                   (tuned << 4));
+}
+
+void autotune_stats(int64_t* out) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  out[0] = g_tune_stats[0];
+  out[1] = g_tune_stats[1];
+  out[2] = g_tune_stats[2];
+  out[3] = (int64_t)g_tune.size();
+}
+
+void autotune_clear() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+  g_tune_stats[0] = g_tune_stats[1] = g_tune_stats[2] = 0;
 }
 
 template <class TM, class TX, class TY>
-static int64_t spmm_any(const EminWork& w, const Csr& M, const TM* mval, const int64_t* nrp,
-                        const int32_t* ncol, const TX* X, TY* Y, const double* D, double* part,
-                        hipStream_t s) {
+static void spmm_any(const EminWork& w, const Csr& M, const TM* mval, const int64_t* nrp,
+                     const int32_t* ncol, const TX* X, TY* Y, const double* D, hipStream_t s) {
   const int64_t nb = w.sched.blk_off[SPMM_NT];
-  if (nb == 0) return 0;
+  if (nb == 0) return;
   k_spmm<TM, TX, TY><<<(unsigned)nb, 256, 0, s>>>(w.sched, M.rowptr, M.col, mval, w.kofs, w.nib,
-                                                   w.nnzm, nrp, ncol, X, Y, D, part);
+                                                   w.nnzm, nrp, ncol, X, Y, D, w.rowdot);
+}
+
+// The values the finaliser sums for <D, Y> (rows with an empty pattern keep
+// rowdot = 0): up to 16K rows the per-row values themselves, above that the
+// block sums of k_rowsum.  The choice depends on n only, so every schedule of
+// the product gives the same scalar.
+constexpr int64_t ROWDOT_DIRECT = 16384;
+static int64_t rowdot_partials(const EminWork& w, double* part, const double** src,
+                               hipStream_t s) {
+  if (w.n <= ROWDOT_DIRECT) {
+    *src = w.rowdot;
+    return w.n;
+  }
+  const int64_t nb = (int64_t)nblocks(w.n, 1024);
+  k_rowsum<<<(unsigned)nb, 256, 0, s>>>(w.rowdot, w.n, part);
+  *src = part;
   return nb;
 }
 
@@ -595,9 +792,13 @@ static double spmm_bytes(const EminWork& w, const Csr& M, bool mixed) {
 }
 
 int64_t masked_spmm(const EminWork& w, const Csr& M, const int64_t* nrp, const int32_t* ncol,
-                    const double* X, double* Y, const double* D, double* part, hipStream_t s) {
-  prof::Scope ps(s, EMIN_PROF_SPMM, spmm_bytes(w, M, false));
-  return spmm_any<double, double, double>(w, M, M.val, nrp, ncol, X, Y, D, part, s);
+                    const double* X, double* Y, const double* D, double* part,
+                    const double** dots, hipStream_t s) {
+  {
+    prof::Scope ps(s, EMIN_PROF_SPMM, spmm_bytes(w, M, false));
+    spmm_any<double, double, double>(w, M, M.val, nrp, ncol, X, Y, D, s);
+  }
+  return D ? rowdot_partials(w, part, dots, s) : 0;
 }
 
 void run_emin(EminWork& w, const Csr& M, const float* Mf, const int64_t* nrp, const int32_t* ncol,
@@ -608,8 +809,9 @@ void run_emin(EminWork& w, const Csr& M, const float* Mf, const int64_t* nrp, co
   if (w.nc) k_gather_modes<<<nblocks(w.nc, 256), 256, 0, s>>>(W, clist, w.nc, w.Wc);
   k_emin_init<<<nblocks(n, RB), RB, 0, s>>>(nrp, ncol, n, cid, W, w.Wc, w.G, P, rp.status);
   // E0 = <P0, mask(M P0)> and R = -Pi(mask(M P0))
-  int64_t np = masked_spmm(w, M, nrp, ncol, P, w.MP, P, w.part, s);
-  k_finalize<<<1, 1024, 0, s>>>(w.part, (int)np, w.sc, FIN_E0, 0, rp.energy, nullptr, nullptr,
+  const double* dots = nullptr;
+  int64_t np = masked_spmm(w, M, nrp, ncol, P, w.MP, P, w.part, &dots, s);
+  k_finalize<<<1, 1024, 0, s>>>(dots, (int)np, w.sc, FIN_E0, 0, rp.energy, nullptr, nullptr,
                                 nullptr, nullptr);
   k_init_r<<<nblocks(n, RB), RB, 0, s>>>(nrp, ncol, n, cid, w.Wc, w.G, w.MP, w.R, w.Z, w.part);
   k_finalize<<<1, 1024, 0, s>>>(w.part, (int)nblocks(n, RB), w.sc, FIN_RHO0, 0, nullptr, rp.rho,
@@ -617,12 +819,15 @@ void run_emin(EminWork& w, const Csr& M, const float* Mf, const int64_t* nrp, co
   if (mixed) k_to_float<<<nblocks(nnz, 256), 256, 0, s>>>(w.Z, w.Zf, nnz);
   for (int it = 0; it < iters; it++) {
     if (mixed) {
-      prof::Scope ps(s, EMIN_PROF_SPMM, spmm_bytes(w, M, true));
-      np = spmm_any<float, float, float>(w, M, Mf, nrp, ncol, w.Zf, w.Qf, w.Z, w.part, s);
+      {
+        prof::Scope ps(s, EMIN_PROF_SPMM, spmm_bytes(w, M, true));
+        spmm_any<float, float, float>(w, M, Mf, nrp, ncol, w.Zf, w.Qf, w.Z, s);
+      }
+      np = rowdot_partials(w, w.part, &dots, s);
     } else {
-      np = masked_spmm(w, M, nrp, ncol, w.Z, w.Q, w.Z, w.part, s);
+      np = masked_spmm(w, M, nrp, ncol, w.Z, w.Q, w.Z, w.part, &dots, s);
     }
-    k_finalize<<<1, 1024, 0, s>>>(w.part, (int)np, w.sc, FIN_GAMMA, it, nullptr, nullptr,
+    k_finalize<<<1, 1024, 0, s>>>(dots, (int)np, w.sc, FIN_GAMMA, it, nullptr, nullptr,
                                   rp.gamma, rp.its, rp.status);
     {
     const double ub = (mixed ? 40.0 : 44.0) * (double)nnz + 20.0 * (double)n +

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libemin.so")
 
 EMIN_PREC_F64, EMIN_PREC_MIXED = 0, 1
-EMIN_FLAG_ENERGY, EMIN_FLAG_VALIDATE = 1, 2
+EMIN_FLAG_ENERGY, EMIN_FLAG_VALIDATE, EMIN_FLAG_AUTOTUNE = 1, 2, 4
 MAX_ITERS = 32
 (VIEW_PV, VIEW_PP, VIEW_AC, VIEW_BC, VIEW_MV, VIEW_MP, VIEW_S, VIEW_ORDER, VIEW_CP, VIEW_CBAR,
  VIEW_CV, VIEW_XVC, VIEW_P2VC, VIEW_KEEPV, VIEW_KEEPP, VIEW_DIR) = range(16)
@@ -63,7 +63,8 @@ class c_params(C.Structure):
 class c_sizes(C.Structure):
     _fields_ = [(k, C.c_int64) for k in
                 ["n_v", "n_p", "n_vc", "n_pc", "n_cp_alg3", "n_cp_extra", "n_mid", "n_cv_extra",
-                 "nnz_Pv", "nnz_Pp", "nnz_Mv", "nnz_Mp", "nnz_Ac", "nnz_Bc", "device_bytes"]]
+                 "nnz_Pv", "nnz_Pp", "nnz_Mv", "nnz_Mp", "nnz_Ac", "nnz_Bc", "device_bytes",
+                 "sched_v", "sched_p"]]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -145,6 +146,7 @@ def lib():
         L.emin_server_destroy.argtypes = [C.c_void_p]
         L.emin_server_destroy.restype = None
         L.emin_profile_enable.argtypes = [C.c_int]
+        L.emin_autotune_stats.argtypes = [P(C.c_int64)]
         L.emin_profile_collect.argtypes = [P(c_kstat), C.c_int32]
         _lib = L
     return _lib
@@ -156,8 +158,9 @@ def _check(st, where):
 
 
 def params(tau1_v=0.06, tau1_p=0.06, tau2_sq=1.5e-3, iters=5, mixed=False, energy=False,
-           validate=False) -> c_params:
-    flags = (EMIN_FLAG_ENERGY if energy else 0) | (EMIN_FLAG_VALIDATE if validate else 0)
+           validate=False, autotune=False) -> c_params:
+    flags = ((EMIN_FLAG_ENERGY if energy else 0) | (EMIN_FLAG_VALIDATE if validate else 0) |
+             (EMIN_FLAG_AUTOTUNE if autotune else 0))
     return c_params(tau1_v, tau1_p, tau2_sq, iters, EMIN_PREC_MIXED if mixed else EMIN_PREC_F64,
                     flags)
 
@@ -280,6 +283,25 @@ class Pattern:
             self.close()
         except Exception:
             pass
+
+
+def autotune_stats() -> dict:
+    """Process-wide autotuner counters of the masked-product schedule."""
+    out = (C.c_int64 * 4)()
+    _check(lib().emin_autotune_stats(out), "emin_autotune_stats")
+    return dict(tuned=int(out[0]), reused=int(out[1]), candidates_timed=int(out[2]),
+                table=int(out[3]))
+
+
+def autotune_reset():
+    _check(lib().emin_autotune_reset(), "emin_autotune_reset")
+
+
+def sched_name(code: int) -> str:
+    """Readable form of a schedule code from the level sizes."""
+    parts = ["maps" if code & 1 else "search-only", "2x-lanes" if code & 2 else "tight-lanes",
+             "xcd-by-class" if code & 4 else "xcd-contiguous"]
+    return "+".join(parts) + ["", " (tuned)", " (reused)", ""][(code >> 4) & 3]
 
 
 def profile_enable(on=True):

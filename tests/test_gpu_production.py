@@ -134,3 +134,31 @@ def test_server_rejects_over_budget():
         srv.submit(d, E.params(), 2)
     assert ei.value.status == 7                      # ERR_BUDGET
     srv.close()
+
+
+def test_autotuned_schedule_same_results_and_reuse():
+    """Every candidate schedule of the masked product sums the same products
+    in the same order, so the autotuned level equals the default one bitwise;
+    a second pattern of the same shape reuses the tuned choice."""
+    import torch
+    from paper_1607_02489_amd import emin as E
+    s = synth.oseen2d(48)
+    E.autotune_reset()
+    base = E.NativeHierarchy(E.DeviceSystem.upload(s), E.params(iters=5), 3)
+    torch.cuda.synchronize()
+    tuned = E.NativeHierarchy(E.DeviceSystem.upload(s), E.params(iters=5, autotune=True), 3)
+    torch.cuda.synchronize()
+    st = E.autotune_stats()
+    say(f"[gpu] autotune stats {st}")
+    assert st["tuned"] >= 1 and st["candidates_timed"] >= 8 * st["tuned"]
+    _same(_levels(tuned), _levels(base))
+    for z in tuned.sizes():
+        assert (z["sched_v"] >> 4) & 3 in (1, 2) and (z["sched_p"] >> 4) & 3 in (1, 2)
+    again = E.NativeHierarchy(E.DeviceSystem.upload(s), E.params(iters=5, autotune=True), 3)
+    torch.cuda.synchronize()
+    assert E.autotune_stats()["reused"] > st["reused"]
+    assert all((z["sched_v"] >> 4) & 3 == 2 for z in again.sizes())
+    _same(_levels(again), _levels(base))
+    for h in (base, tuned, again):
+        h.close()
+    E.autotune_reset()
