@@ -119,25 +119,6 @@ __global__ __launch_bounds__(64 * BW) void k_balls(const int64_t* grp, const int
   }
 }
 
-// Index bandwidth of the graph, max |i - j| over its edges: every vertex of
-// the distance-4 ball of v lies in [v - 4 bw, v + 4 bw].
-__global__ void k_bandwidth(const int64_t* grp, const int32_t* gcol, int64_t n,
-                            unsigned long long* bw) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned long long m = 0ull;
-  if (i < n)
-    for (int64_t e = grp[i]; e < grp[i + 1]; e++) {
-      const int64_t d = (int64_t)gcol[e] - i;
-      const unsigned long long a = (unsigned long long)(d < 0 ? -d : d);
-      m = a > m ? a : m;
-    }
-  for (int o = 32; o >= 1; o >>= 1) {
-    const unsigned long long t = __shfl_xor(m, o, 64);
-    m = t > m ? t : m;
-  }
-  if ((threadIdx.x & 63) == 0 && m) atomicMax(bw, m);
-}
-
 // Distance-4 balls with a visited bitmap over the index window of the ball
 // (8 bw + 1 bits) instead of a hash set: one atomic OR per edge, no probing,
 // little LDS, so many waves per CU.  One wave per vertex, BFS level by level;
@@ -717,11 +698,8 @@ void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar,
     // windowed bitmap kernel when the index bandwidth keeps the window small:
     // ball sizes of a sample of vertices pick the row capacity, then one pass
     // fills every row (a ball above the capacity repeats the pass, larger)
-    unsigned long long* bwp = ar.alloc<unsigned long long>(1);
     int* flags = ar.alloc<int>(2);
-    HIP_OK(hipMemsetAsync(bwp, 0, sizeof(unsigned long long), s));
-    k_bandwidth<<<nblocks(n, 256), 256, 0, s>>>(D.grp, D.gcol, n, bwp);
-    const int64_t bw = (int64_t)d2h(bwp, s);
+    const int64_t bw = index_bandwidth(D.grp, D.gcol, n, s, ar);
     const int64_t nwords = (8 * bw + 1 + 31) / 32;
     int lcap = BLIST;
     auto lds_for = [&](int cap) { return (size_t)BWIN_W * (nwords + cap) * sizeof(uint32_t); };

@@ -125,6 +125,9 @@ void zero_bytes(void* p, size_t bytes, hipStream_t s);
 // sparse building blocks (sparse.hip)
 // ---------------------------------------------------------------------------
 // longest row of a CSR (synchronises the stream)
+// max |i - j| over the entries of a square pattern (a graph's index bandwidth)
+int64_t index_bandwidth(const int64_t* rp, const int32_t* col, int64_t n, hipStream_t s,
+                        Arena& ar);
 int64_t max_row_len(const int64_t* rp, int64_t n, hipStream_t s, Arena& ar);
 // largest value of a non-negative int32 array (synchronises the stream)
 int64_t max_row_len_i32(const int32_t* a, int64_t n, hipStream_t s, Arena& ar);

@@ -26,18 +26,27 @@ __device__ __forceinline__ bool subset_sorted(const int32_t* a, int na, const in
   return true;
 }
 
-__global__ void k_mid_prep(const int64_t* srp, const int32_t* scol, const int64_t* trp,
-                           const int32_t* tcol, const uint8_t* st, const double* x, int dim,
-                           double tau2_sq, int64_t n, int32_t* m_out, int32_t* size_key,
-                           int32_t* tcnt, int32_t* tlist, int* err) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// One wave per F vertex i: X_i (mean of S_i's coordinates, summed in S
+// order), B_i = {j in F : S_i within S_j} (candidates j: the F vertices whose
+// S contains S_i's first C point), m = argmin over B_i of (|x_j - X_i|^2, j),
+// w2 = squared diagonal of B_i's bounding box, and T_i = {j in B_i :
+// |x_j - x_m|^2 < tau2^2 w2} (at most TCAP, in candidate order).  The lanes
+// share the candidates; minima and box by wave reductions (exact).
+__global__ __launch_bounds__(256) void k_mid_prep(const int64_t* srp, const int32_t* scol,
+                                                  const int64_t* trp, const int32_t* tcol,
+                                                  const uint8_t* st, const double* x, int dim,
+                                                  double tau2_sq, int64_t n, int32_t* m_out,
+                                                  int32_t* size_key, int32_t* tcnt,
+                                                  int32_t* tlist, int* err) {
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;   // whole wave
   const int64_t s0 = srp[i], s1 = srp[i + 1];
   const int si = (int)(s1 - s0);
-  m_out[i] = -1;
-  size_key[i] = 0;
-  tcnt[i] = 0;
-  if (st[i] == ST_C || si < 2) return;
+  if (st[i] == ST_C || si < 2) {
+    if (lane == 0) { m_out[i] = -1; size_key[i] = 0; tcnt[i] = 0; }
+    return;
+  }
   double X[3] = {0.0, 0.0, 0.0};
   for (int d = 0; d < dim; d++) {
     double acc = 0.0;
@@ -45,11 +54,12 @@ __global__ void k_mid_prep(const int64_t* srp, const int32_t* scol, const int64_
     X[d] = acc / (double)si;
   }
   const int32_t c0 = scol[s0];
-  int32_t m = -1;
-  double md = 0.0;
-  double lo[3] = {0.0, 0.0, 0.0}, hi[3] = {0.0, 0.0, 0.0};
-  bool first = true;
-  for (int64_t e = trp[c0]; e < trp[c0 + 1]; e++) {
+  const int64_t t0 = trp[c0], t1 = trp[c0 + 1];
+  const double INF = __builtin_inf();
+  double mk = INF;
+  int32_t mi = INT32_MAX;
+  double lo[3] = {INF, INF, INF}, hi[3] = {-INF, -INF, -INF};
+  for (int64_t e = t0 + lane; e < t1; e += 64) {
     const int32_t j = tcol[e];
     if (st[j] == ST_C) continue;
     if (!subset_sorted(scol + s0, si, scol + srp[j], (int)(srp[j + 1] - srp[j]))) continue;
@@ -58,39 +68,55 @@ __global__ void k_mid_prep(const int64_t* srp, const int32_t* scol, const int64_
       const double r = x[(int64_t)j * dim + d] - X[d];
       d2 = d2 + r * r;
     }
-    if (m < 0 || d2 < md || (d2 == md && j < m)) { m = j; md = d2; }
+    if (d2 < mk || (d2 == mk && j < mi)) { mk = d2; mi = j; }
     for (int d = 0; d < dim; d++) {
       const double v = x[(int64_t)j * dim + d];
-      if (first || v < lo[d]) lo[d] = v;
-      if (first || v > hi[d]) hi[d] = v;
+      lo[d] = v < lo[d] ? v : lo[d];
+      hi[d] = v > hi[d] ? v : hi[d];
     }
-    first = false;
   }
+  wave_argmin(mk, mi);
+  for (int d = 0; d < dim; d++) {
+    lo[d] = wave_min_f64(lo[d]);
+    hi[d] = -wave_min_f64(-hi[d]);
+  }
+  const int32_t m = mi == INT32_MAX ? -1 : mi;   // i itself is in B_i, so m exists
   double w2 = 0.0;
   for (int d = 0; d < dim; d++) {
     const double w = hi[d] - lo[d];
     w2 = w2 + w * w;
   }
   const double thr = tau2_sq * w2;
-  int tc = 0;
-  for (int64_t e = trp[c0]; e < trp[c0 + 1]; e++) {
-    const int32_t j = tcol[e];
-    if (st[j] == ST_C) continue;
-    if (!subset_sorted(scol + s0, si, scol + srp[j], (int)(srp[j + 1] - srp[j]))) continue;
-    double d2 = 0.0;
-    for (int d = 0; d < dim; d++) {
-      const double r = x[(int64_t)j * dim + d] - x[(int64_t)m * dim + d];
-      d2 = d2 + r * r;
+  int tc = 0;   // wave-uniform running count
+  for (int64_t e0 = t0; e0 < t1; e0 += 64) {
+    const int64_t e = e0 + lane;
+    bool in_t = false;
+    int32_t j = -1;
+    if (e < t1 && m >= 0) {
+      j = tcol[e];
+      if (st[j] != ST_C &&
+          subset_sorted(scol + s0, si, scol + srp[j], (int)(srp[j + 1] - srp[j]))) {
+        double d2 = 0.0;
+        for (int d = 0; d < dim; d++) {
+          const double r = x[(int64_t)j * dim + d] - x[(int64_t)m * dim + d];
+          d2 = d2 + r * r;
+        }
+        in_t = d2 < thr;
+      }
     }
-    if (d2 < thr) {
-      if (tc < TCAP) tlist[i * TCAP + tc] = j;
+    const unsigned long long bal = __ballot(in_t);
+    if (in_t) {
+      const int p = tc + __popcll(bal & ((1ull << lane) - 1ull));
+      if (p < TCAP) tlist[i * TCAP + p] = j;
       else atomicOr(err, DERR_CAPACITY);
-      tc++;
     }
+    tc += __popcll(bal);
   }
-  m_out[i] = m;
-  size_key[i] = si;
-  tcnt[i] = tc < TCAP ? tc : TCAP;
+  if (lane == 0) {
+    m_out[i] = m;
+    size_key[i] = si;
+    tcnt[i] = tc < TCAP ? tc : TCAP;
+  }
 }
 
 __global__ void k_flag_eq(const int32_t* key, int64_t n, int32_t val, int64_t* flags) {
@@ -250,8 +276,8 @@ int64_t midpoints(const Csr& S, const uint8_t* st, const double* x, int dim, dou
   int32_t* tlist = ar.alloc<int32_t>((size_t)n * TCAP);
   int* err = ar.alloc<int>(1);
   HIP_OK(hipMemsetAsync(err, 0, sizeof(int), s));
-  k_mid_prep<<<nblocks(n, 256), 256, 0, s>>>(S.rowptr, S.col, ST.rowptr, ST.col, st, x, dim,
-                                              tau2_sq, n, m, key, tcnt, tlist, err);
+  k_mid_prep<<<nblocks(n, 4), 256, 0, s>>>(S.rowptr, S.col, ST.rowptr, ST.col, st, x, dim,
+                                            tau2_sq, n, m, key, tcnt, tlist, err);
   if (d2h(err, s)) throw Error(EMIN_ERR_CAPACITY, "alg4: closeness set capacity");
   const int64_t maxs = max_row_len(S.rowptr, n, s, ar);
   int32_t* order = ar.alloc<int32_t>(n);

@@ -76,6 +76,34 @@ void scan_inclusive(int64_t* a, int64_t n, hipStream_t s, Arena& ar) {
   k_tile_scan<<<nb, SCAN_BS, 0, s>>>(a, n, bs);
 }
 
+// Index bandwidth of a graph, max |i - j| over its edges: every vertex within
+// distance d of v lies in [v - d bw, v + d bw].
+__global__ void k_bandwidth(const int64_t* grp, const int32_t* gcol, int64_t n,
+                            unsigned long long* bw) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long m = 0ull;
+  if (i < n)
+    for (int64_t e = grp[i]; e < grp[i + 1]; e++) {
+      const int64_t d = (int64_t)gcol[e] - i;
+      const unsigned long long a = (unsigned long long)(d < 0 ? -d : d);
+      m = a > m ? a : m;
+    }
+  for (int o = 32; o >= 1; o >>= 1) {
+    const unsigned long long t = __shfl_xor(m, o, 64);
+    m = t > m ? t : m;
+  }
+  if ((threadIdx.x & 63) == 0 && m) atomicMax(bw, m);
+}
+
+int64_t index_bandwidth(const int64_t* rp, const int32_t* col, int64_t n, hipStream_t s,
+                        Arena& ar) {
+  if (n <= 0) return 0;
+  unsigned long long* bw = ar.alloc<unsigned long long>(1);
+  HIP_OK(hipMemsetAsync(bw, 0, sizeof(unsigned long long), s));
+  k_bandwidth<<<nblocks(n, 256), 256, 0, s>>>(rp, col, n, bw);
+  return (int64_t)d2h(bw, s);
+}
+
 int64_t rowptr_from_counts(int64_t* rowptr, int64_t n, hipStream_t s, Arena& ar) {
   HIP_OK(hipMemsetAsync(rowptr, 0, sizeof(int64_t), s));
   scan_inclusive(rowptr + 1, n, s, ar);

@@ -92,12 +92,16 @@ __global__ __launch_bounds__(64 * VB_WAVES) void k_vbfs(const int64_t* grp, cons
 
 // Extra C^(v), ascending: the smallest non-Dirichlet, uncovered, non-C node
 // at or after the cursor is converted, then its distance-3 ball is covered.
+// Visited marks: with nwin > 0, a bitmap in LDS over the index window
+// j ± 3·bw of the ball (bw = the graph's index bandwidth), cleared per ball;
+// otherwise per-vertex stamps in global memory.
 __global__ __launch_bounds__(1024) void k_vextras(const int64_t* grp, const int32_t* gcol,
                                                   int64_t n, const uint8_t* dir, uint8_t* cv,
                                                   uint8_t* cov, int32_t* vis, int32_t* extra,
                                                   int32_t* nextra, int ballcap, int deg_cap,
-                                                  int* err) {
+                                                  int64_t bw, int nwin, int* err) {
   extern __shared__ int32_t ball[];
+  uint32_t* win = reinterpret_cast<uint32_t*>(ball + ballcap);
   __shared__ int found_sh, nb_sh, ne_sh, bad_sh;
   const int tid = threadIdx.x;
   if (tid == 0) { ne_sh = 0; bad_sh = 0; }
@@ -129,12 +133,22 @@ __global__ __launch_bounds__(1024) void k_vextras(const int64_t* grp, const int3
     }
     const int j = found_sh;
     if (j == INT32_MAX) break;
+    const int64_t lo = (int64_t)j - 3 * bw > 0 ? (int64_t)j - 3 * bw : 0;
+    if (nwin) {
+      for (int t = tid; t < nwin; t += 1024) win[t] = 0u;
+      __syncthreads();
+    }
     if (tid == 0) {
       cv[j] = 1;
       extra[ne_sh] = j;
       ne_sh++;
       ball[0] = j;
-      atomicMax(&vis[j], stamp);
+      if (nwin) {
+        const int64_t o = j - lo;
+        win[o >> 5] |= 1u << (o & 31);
+      } else {
+        atomicMax(&vis[j], stamp);
+      }
       nb_sh = 1;
     }
     __syncthreads();
@@ -149,7 +163,15 @@ __global__ __launch_bounds__(1024) void k_vextras(const int64_t* grp, const int3
           for (int64_t e = grp[v] + slot; e < grp[v + 1]; e += deg_cap) {
             const int32_t u = gcol[e];
             if (u == v) continue;
-            if (atomicMax(&vis[u], stamp) < stamp) {
+            bool fresh;
+            if (nwin) {
+              const int64_t o = (int64_t)u - lo;
+              const uint32_t bit = 1u << (o & 31);
+              fresh = (atomicOr(&win[o >> 5], bit) & bit) == 0u;
+            } else {
+              fresh = atomicMax(&vis[u], stamp) < stamp;
+            }
+            if (fresh) {
               const int p = atomicAdd(&nb_sh, 1);
               if (p < ballcap) ball[p] = u; else atomicOr(&bad_sh, 1);
             }
@@ -241,11 +263,16 @@ void velocity_pattern(const Csr& G, const uint8_t* dir, uint8_t* cv, VPatternOut
   int32_t* nextra = ar.alloc<int32_t>(1);
   int ballcap = 8192;
   if (ballcap * 4 + 64 > lds_max) ballcap = (lds_max - 64) / 4;
+  // visited bitmap over the ball's index window when it fits beside the list
+  const int64_t bw = index_bandwidth(G.rowptr, G.col, n, s, ar);
+  const int64_t words = (6 * bw + 1 + 31) / 32;
+  const int nwin = (int64_t)ballcap * 4 + words * 4 + 64 <= lds_max ? (int)words : 0;
+  const size_t lds = (size_t)ballcap * 4 + (size_t)nwin * 4;
   HIP_OK(hipFuncSetAttribute((const void*)k_vextras, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             ballcap * 4));
+                             (int)lds));
   prof::Scope ps(s, EMIN_PROF_VPAT, 0.0);
-  k_vextras<<<1, 1024, (size_t)ballcap * 4, s>>>(G.rowptr, G.col, n, dir, cv, cov, vis, extra,
-                                                  nextra, ballcap, deg_cap, err);
+  k_vextras<<<1, 1024, lds, s>>>(G.rowptr, G.col, n, dir, cv, cov, vis, extra, nextra, ballcap,
+                                  deg_cap, bw, nwin, err);
   HIP_OK(hipGetLastError());
   out.n_extra = d2h(nextra, s);
   if (out.n_extra)
