@@ -237,9 +237,30 @@ __global__ void k_spmm_maps(const int64_t* mrp, const int32_t* mcol, const int64
 template <int G>
 struct MapWin {
   static constexpr int NG = 256 / G;
+  static constexpr int WG = 64 / G;                 // groups per wave
   static constexpr int NP = G <= 8 ? 1 : G / 8;     // map planes of a row
   static constexpr int CH = G <= 4 ? 8 : (G < 16 ? 16 : G);   // window entries per group
 };
+
+template <int G, class TM>
+constexpr int map_wave_smem() {
+  return MapWin<G>::WG * MapWin<G>::CH * (int)(sizeof(TM) + 4 + 4 * MapWin<G>::NP);
+}
+
+// LDS of one wave's windows (the largest over the map classes) and of a block
+template <class TM>
+constexpr int spmm_wave_smem() {
+  constexpr int a = map_wave_smem<4, TM>(), b = map_wave_smem<8, TM>(),
+                c = map_wave_smem<16, TM>(), d = map_wave_smem<32, TM>();
+  constexpr int ab = a > b ? a : b, cd = c > d ? c : d;
+  return ((ab > cd ? ab : cd) + 15) & ~15;
+}
+
+template <class TM>
+constexpr int spmm_smem() {
+  return 4 * spmm_wave_smem<TM>();
+}
+
 
 template <int G, class TM, class TX, class TY>
 __device__ __forceinline__ void spmm_map_rows(int64_t lb, const int32_t* rows, int64_t nrows,
@@ -252,15 +273,20 @@ __device__ __forceinline__ void spmm_map_rows(int64_t lb, const int32_t* rows, i
   using W = MapWin<G>;
   constexpr int NG = W::NG, NP = W::NP, CH = W::CH;
   constexpr int U = 4;
-  TM* s_m = reinterpret_cast<TM*>(smem);
-  int32_t* s_k = reinterpret_cast<int32_t*>(s_m + NG * CH);
-  uint32_t* s_w = reinterpret_cast<uint32_t*>(s_k + NG * CH);   // [NP][NG*CH]
+  // each wave owns its own LDS region (its groups' windows): the layout of
+  // one wave never depends on another wave's row class
+  constexpr int WG = W::WG;
+  unsigned char* wbase = smem + (threadIdx.x >> 6) * spmm_wave_smem<TM>();
+  TM* s_m = reinterpret_cast<TM*>(wbase);
+  int32_t* s_k = reinterpret_cast<int32_t*>(s_m + WG * CH);
+  uint32_t* s_w = reinterpret_cast<uint32_t*>(s_k + WG * CH);   // [NP][WG*CH]
   const int g = threadIdx.x / G, lane = threadIdx.x % G;
+  const int gi = (threadIdx.x & 63) / G;   // group within the wave
   const int64_t r = lb * NG + g;
   const int q = lane >> 3, sh = 4 * (lane & 7);
-  TM* gm = s_m + g * CH;
-  int32_t* gk = s_k + g * CH;
-  const uint32_t* gw = s_w + q * (NG * CH) + g * CH;
+  TM* gm = s_m + gi * CH;
+  int32_t* gk = s_k + gi * CH;
+  const uint32_t* gw = s_w + q * (WG * CH) + gi * CH;
   if (r < nrows) {
     const int32_t i = rows[r];
     const int64_t na = nrp[i];
@@ -276,7 +302,7 @@ __device__ __forceinline__ void spmm_map_rows(int64_t lb, const int32_t* rows, i
         gk[t] = v ? kofs[c0 + t] : 0;
 #pragma unroll
         for (int p = 0; p < NP; p++)
-          s_w[p * (NG * CH) + g * CH + t] = v ? nib[(int64_t)p * nnzm + c0 + t] : 0xFFFFFFFFu;
+          s_w[p * (WG * CH) + gi * CH + t] = v ? nib[(int64_t)p * nnzm + c0 + t] : 0xFFFFFFFFu;
       }
       // the group lies inside one wave: order its LDS writes before the reads
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -308,19 +334,6 @@ __device__ __forceinline__ void spmm_map_rows(int64_t lb, const int32_t* rows, i
       if (lane == 0) rowdot[i] = sum;
     }
   }
-}
-
-template <int G, class TM>
-constexpr int map_smem() {
-  return MapWin<G>::NG * MapWin<G>::CH * (int)(sizeof(TM) + 4 + 4 * MapWin<G>::NP);
-}
-
-template <class TM>
-constexpr int spmm_smem() {
-  constexpr int a = map_smem<4, TM>(), b = map_smem<8, TM>(), c = map_smem<16, TM>(),
-                d = map_smem<32, TM>();
-  constexpr int ab = a > b ? a : b, cd = c > d ? c : d;
-  return ab > cd ? ab : cd;
 }
 
 // The whole masked product in one launch: block ranges serve the row classes
