@@ -124,10 +124,10 @@ void zero_bytes(void* p, size_t bytes, hipStream_t s);
 // ---------------------------------------------------------------------------
 // sparse building blocks (sparse.hip)
 // ---------------------------------------------------------------------------
-// longest row of a CSR (synchronises the stream)
 // max |i - j| over the entries of a square pattern (a graph's index bandwidth)
 int64_t index_bandwidth(const int64_t* rp, const int32_t* col, int64_t n, hipStream_t s,
                         Arena& ar);
+// longest row of a CSR (synchronises the stream)
 int64_t max_row_len(const int64_t* rp, int64_t n, hipStream_t s, Arena& ar);
 // largest value of a non-negative int32 array (synchronises the stream)
 int64_t max_row_len_i32(const int32_t* a, int64_t n, hipStream_t s, Arena& ar);
@@ -143,7 +143,10 @@ void gather_values(const double* in, const int32_t* src, double* out, int64_t n,
 
 // C = A*B: symbolic (pattern) once, numeric any number of times.  For every
 // (i,j), c_ij accumulates a_ik*b_kj over k in ascending order of A's row,
-// each product and sum rounded separately (bit-reproducible).
+// each product and sum rounded separately (bit-reproducible).  The symbolic
+// pass reads back once (twice when rows exceed the window bitmap); an overflow
+// seen only by its fill pass is ORed into *derr (DERR_CAPACITY) for the caller
+// to check, or thrown at once when derr is null.
 struct SpgemmPlan {
   int64_t max_row = 0;  // longest output row
   int g_num = 16;       // lanes per row in the numeric kernel

@@ -119,15 +119,53 @@ __global__ __launch_bounds__(256) void k_mid_prep(const int64_t* srp, const int3
   }
 }
 
-__global__ void k_flag_eq(const int32_t* key, int64_t n, int32_t val, int64_t* flags) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) flags[i] = key[i] == val;
+// Visiting order of Alg. 4 as one stable counting sort: class c = KMAX - |S|
+// (|S| from KMAX down to 2), ascending index within a class.  Per block (256
+// vertices) and class the count (class-major), one inclusive scan gives each
+// block's start, and per-wave ballots rank the vertices inside the block.
+constexpr int KMAX = 32;             // S sets hold at most 32 entries
+constexpr int NCLS = KMAX - 1;       // |S| = 32 ... 2
+
+__global__ __launch_bounds__(256) void k_order_count(const int32_t* key, int64_t n, int64_t nb,
+                                                    int64_t* bc, int* err) {
+  __shared__ int cnt[NCLS];
+  if (threadIdx.x < NCLS) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int k = i < n ? key[i] : 0;
+  if (k >= 2 && k <= KMAX) atomicAdd(&cnt[KMAX - k], 1);
+  else if (k > KMAX) atomicOr(err, DERR_CAPACITY);
+  __syncthreads();
+  if (threadIdx.x < NCLS) bc[(int64_t)threadIdx.x * nb + blockIdx.x] = cnt[threadIdx.x];
 }
 
-__global__ void k_place(const int32_t* key, const int64_t* incl, int64_t n, int32_t val,
-                        int64_t base, int32_t* order) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && key[i] == val) order[base + incl[i] - 1] = (int32_t)i;
+__global__ __launch_bounds__(256) void k_order_place(const int32_t* key, int64_t n,
+                                                    const int64_t* incl, int64_t nb,
+                                                    int32_t* order) {
+  __shared__ int wc[4][NCLS];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int k = i < n ? key[i] : 0;
+  const int c = (k >= 2 && k <= KMAX) ? KMAX - k : -1;
+  uint64_t mine = 0;
+  for (int q = 0; q < NCLS; q++) {
+    const uint64_t m = __ballot(c == q);
+    if (lane == 0) wc[w][q] = __popcll(m);
+    if (c == q) mine = m;
+  }
+  __syncthreads();
+  if (c < 0) return;
+  const int64_t kk = (int64_t)c * nb + blockIdx.x;
+  int64_t pos = kk ? incl[kk - 1] : 0;
+  for (int v = 0; v < w; v++) pos += wc[v][c];
+  order[pos + __popcll(mine & ((1ull << lane) - 1ull))] = (int32_t)i;
+}
+
+__global__ void k_order_total(const int64_t* incl, int64_t len, const int* err, int64_t* out) {
+  if (threadIdx.x == 0) {
+    out[0] = len ? incl[len - 1] : 0;
+    out[1] = *err;
+  }
 }
 
 // per position p of the visiting order: m, T (padded with -1) and the mask
@@ -278,17 +316,21 @@ int64_t midpoints(const Csr& S, const uint8_t* st, const double* x, int dim, dou
   HIP_OK(hipMemsetAsync(err, 0, sizeof(int), s));
   k_mid_prep<<<nblocks(n, 4), 256, 0, s>>>(S.rowptr, S.col, ST.rowptr, ST.col, st, x, dim,
                                             tau2_sq, n, m, key, tcnt, tlist, err);
-  if (d2h(err, s)) throw Error(EMIN_ERR_CAPACITY, "alg4: closeness set capacity");
-  const int64_t maxs = max_row_len(S.rowptr, n, s, ar);
+  // visiting order: |S| descending, index ascending (one read-back with the
+  // capacity flag)
   int32_t* order = ar.alloc<int32_t>(n);
-  int64_t* flags = ar.alloc<int64_t>(n);
-  int64_t norder = 0;
-  for (int64_t sz = maxs; sz >= 2; sz--) {
-    k_flag_eq<<<nblocks(n, 256), 256, 0, s>>>(key, n, (int32_t)sz, flags);
-    scan_inclusive(flags, n, s, ar);
-    k_place<<<nblocks(n, 256), 256, 0, s>>>(key, flags, n, (int32_t)sz, norder, order);
-    norder += d2h(flags + n - 1, s);
-  }
+  const int64_t nb = (int64_t)nblocks(n, 256);
+  int64_t* bc = ar.alloc<int64_t>((size_t)NCLS * nb);
+  int64_t* tot = ar.alloc<int64_t>(2);
+  k_order_count<<<(unsigned)nb, 256, 0, s>>>(key, n, nb, bc, err);
+  scan_inclusive(bc, NCLS * nb, s, ar);
+  k_order_place<<<(unsigned)nb, 256, 0, s>>>(key, n, bc, nb, order);
+  k_order_total<<<1, 64, 0, s>>>(bc, NCLS * nb, err, tot);
+  int64_t th[2];
+  HIP_OK(hipMemcpyAsync(th, tot, sizeof(th), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  if (th[1]) throw Error(EMIN_ERR_CAPACITY, "alg4: closeness set capacity");
+  const int64_t norder = th[0];
   const size_t lds = (size_t)((n + 31) / 32) * 4;
   if ((int64_t)lds > lds_max) throw Error(EMIN_ERR_CAPACITY, "alg4: C-bar bitmap exceeds LDS");
   HIP_OK(hipFuncSetAttribute((const void*)k_mid_decide,

@@ -718,6 +718,21 @@ __global__ void k_row_len_max(const int64_t* rp, int64_t n, unsigned long long* 
   if ((threadIdx.x & 63) == 0) atomicMax(mx, v);
 }
 
+// output size, count-pass overflow flag and longest row of a symbolic product
+__global__ void k_sym_summary(const int64_t* rp, int64_t n, const int* lerr,
+                              const unsigned long long* mx, int64_t* out) {
+  if (threadIdx.x == 0) {
+    out[0] = rp[n];
+    out[1] = lerr[0];
+    out[2] = (int64_t)*mx;
+  }
+}
+
+// a fill-pass overflow is reported with the handle's other deferred errors
+__global__ void k_defer_err(const int* lerr, int* derr) {
+  if (threadIdx.x == 0 && lerr[0]) atomicOr(derr, DERR_CAPACITY);
+}
+
 int64_t max_row_len(const int64_t* rp, int64_t n, hipStream_t s, Arena& ar) {
   if (n <= 0) return 0;
   unsigned long long* mx = ar.alloc<unsigned long long>(1);
@@ -948,8 +963,20 @@ void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& pla
     nov = hl[2];
     if (nov) sym_big(ovf2, nov, A, B, big, C.rowptr, nullptr, nullptr, lerr, s);
   }
-  C.nnz = rowptr_from_counts(C.rowptr, C.nrows, s, ar);
-  if (d2h(lerr, s)) throw Error(EMIN_ERR_CAPACITY, "spgemm: output row exceeds the LDS table");
+  // one read-back: output size, count-pass overflow, longest output row
+  HIP_OK(hipMemsetAsync(C.rowptr, 0, sizeof(int64_t), s));
+  scan_inclusive(C.rowptr + 1, C.nrows, s, ar);
+  unsigned long long* mx = ar.alloc<unsigned long long>(1);
+  int64_t* sm = ar.alloc<int64_t>(3);
+  HIP_OK(hipMemsetAsync(mx, 0, sizeof(unsigned long long), s));
+  if (C.nrows) k_row_len_max<<<nblocks(C.nrows, 256), 256, 0, s>>>(C.rowptr, C.nrows, mx);
+  k_sym_summary<<<1, 64, 0, s>>>(C.rowptr, C.nrows, lerr, mx, sm);
+  int64_t hs[3];
+  HIP_OK(hipMemcpyAsync(hs, sm, sizeof(hs), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  C.nnz = hs[0];
+  if (hs[1]) throw Error(EMIN_ERR_CAPACITY, "spgemm: output row exceeds the LDS table");
+  plan.max_row = hs[2];
   C.col = ar.alloc<int32_t>(C.nnz);
   C.val = ar.alloc<double>(C.nnz);
   // the window fill skips the wide rows; the hash kernels fill those (the
@@ -966,14 +993,13 @@ void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& pla
     }
     if (nov) sym_big(ovf2, nov, A, B, big, nullptr, C.rowptr, C.col, lerr, s);
   }
-  if (d2h(lerr, s)) throw Error(EMIN_ERR_CAPACITY, "spgemm: fill pass overflow");
-  plan.max_row = max_row_len(C.rowptr, C.nrows, s, ar);
+  if (derr) k_defer_err<<<1, 64, 0, s>>>(lerr, derr);
+  else if (d2h(lerr, s)) throw Error(EMIN_ERR_CAPACITY, "spgemm: fill pass overflow");
   const double avg_b = B.nrows ? (double)B.nnz / (double)B.nrows : 1.0;
   int gn = pick_g(avg_b);
   // enough lanes per row that the longest output row fits the LDS budget
   while (gn < 64 && (size_t)(256 / gn) * plan.max_row * 12 > 96 * 1024) gn <<= 1;
   plan.g_num = gn;
-  (void)derr;
 }
 
 template <int G, class TV, class TO>
