@@ -61,9 +61,14 @@ enum { EMIN_PREC_F64 = 0, EMIN_PREC_MIXED = 1 };
 enum {
   EMIN_FLAG_ENERGY = 1u,    /* emin_setup: record the energy trace(P^T M P) per step */
   EMIN_FLAG_VALIDATE = 2u,  /* check values for NaN/Inf */
-  EMIN_FLAG_AUTOTUNE = 4u   /* emin_pattern: time candidate schedules of the masked
+  EMIN_FLAG_AUTOTUNE = 4u,  /* emin_pattern: time candidate schedules of the masked
                                product on this pattern (or reuse the choice made for
                                the same problem shape) and keep the fastest */
+  EMIN_FLAG_PATTERN_VALUES = 8u  /* emin_setup: the system's values are still those the
+                                    handle's emin_pattern call was given, so the
+                                    filtered operators that call formed are reused
+                                    instead of being formed again (the caller vouches
+                                    for it; nothing checks the values) */
 };
 #define EMIN_MAX_ITERS 32
 

@@ -313,15 +313,18 @@ void run_setup(emin_pattern_t* h, const emin_system_t* sys, const emin_params_t*
   emin_report_t* r = rep ? rep : h->rep_internal;
   // a kernel, not a memset node: this path may be captured into a graph
   zero_bytes(r, sizeof(emin_report_t), s);
-  // energy operators on the stored drop masks
-  gather_values(B.val, h->bt_src, h->BT.val, h->BT.nnz, s);
-  spgemm_numeric(B, view(h->BT), h->Z, h->zplan, s);
-  diag_of(view(h->Z), h->dZ, s);
-  filter_numeric(view(h->Z), h->keep_p, h->dZ, h->Atp, s);
-  symmetrize_numeric(h->Atp.val, h->mp_ia, h->mp_ib, h->Mp, s);
-  diag_of(A, h->dA, s);
-  filter_numeric(A, h->keep_v, h->dA, h->Atv, s);
-  symmetrize_numeric(h->Atv.val, h->mv_ia, h->mv_ib, h->Mv, s);
+  // energy operators on the stored drop masks (emin_pattern formed them
+  // already from values the caller vouches are unchanged)
+  if ((prm->flags & EMIN_FLAG_PATTERN_VALUES) == 0) {
+    gather_values(B.val, h->bt_src, h->BT.val, h->BT.nnz, s);
+    spgemm_numeric(B, view(h->BT), h->Z, h->zplan, s);
+    diag_of(view(h->Z), h->dZ, s);
+    filter_numeric(view(h->Z), h->keep_p, h->dZ, h->Atp, s);
+    symmetrize_numeric(h->Atp.val, h->mp_ia, h->mp_ib, h->Mp, s);
+    diag_of(A, h->dA, s);
+    filter_numeric(A, h->keep_v, h->dA, h->Atv, s);
+    symmetrize_numeric(h->Atv.val, h->mv_ia, h->mv_ib, h->Mv, s);
+  }
   const bool mixed = prm->precision == EMIN_PREC_MIXED;
   if (mixed) {
     to_float(h->Mv.val, h->Mvf, h->Mv.nnz, s);

@@ -191,7 +191,10 @@ __global__ __launch_bounds__(64 * BWIN_W) void k_balls_win(const int64_t* grp,
   if (lane == 0) {
     bsize[v0] = le;
     b3[v0] = ends[3];
-    atomicMax(flags + 1, le);
+    // a relaxed read first: most balls are not larger than one already seen,
+    // and same-address atomics from every vertex would serialise
+    if (le > __hip_atomic_load(flags + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(flags + 1, le);
   }
   if (!balls) return;
   int32_t* out = balls + v0 * stride;

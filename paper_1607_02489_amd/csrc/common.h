@@ -149,6 +149,7 @@ void gather_values(const double* in, const int32_t* src, double* out, int64_t n,
 // to check, or thrown at once when derr is null.
 struct SpgemmPlan {
   int64_t max_row = 0;  // longest output row
+  int64_t max_words = 0;  // widest column span of an output row, in 32-bit words
   int g_num = 16;       // lanes per row in the numeric kernel
 };
 void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& plan,
@@ -180,6 +181,14 @@ void validate_csr(const CsrView& A, bool values, int* derr, hipStream_t s);
 // ---------------------------------------------------------------------------
 // device helpers
 // ---------------------------------------------------------------------------
+// XCD-aware block order: the hardware deals consecutive blocks round-robin to
+// the 8 XCDs; remapping gives every XCD one contiguous range of rows, so the
+// neighbour rows a block gathers are likely already in that XCD's L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+  const int64_t q = nb / 8, r = nb % 8, x = b % 8, j = b / 8;
+  return x * q + (x < r ? x : r) + j;
+}
+
 __device__ __forceinline__ double shfl_xor_d(double v, int m) {
   return __shfl_xor(v, m, 64);
 }

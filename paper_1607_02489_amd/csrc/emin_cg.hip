@@ -67,14 +67,6 @@ __global__ void k_default_modes(const uint8_t* dir, int64_t n, double* W) {
   if (i < n) W[i] = dir ? (dir[i] ? 0.0 : 1.0) : 1.0;
 }
 
-// XCD-aware block order: the hardware deals consecutive blocks round-robin to
-// the 8 XCDs; remapping gives every XCD one contiguous range of rows, so the
-// neighbour rows a block gathers are likely already in that XCD's L2.
-__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
-  const int64_t q = nb / 8, r = nb % 8, x = b % 8, j = b / 8;
-  return x * q + (x < r ? x : r) + j;
-}
-
 // Row-binned masked product: G lanes own one row i whose pattern has at most G
 // entries, lane s computing slot s (column j_s).  The group first stages M's
 // row i and the pattern-row bounds of its columns k across its lanes (two

@@ -94,6 +94,10 @@ emin_status emin_hierarchy_build(const emin_system_t* sys, const emin_params_t* 
     return EMIN_ERR_OOM;
   }
   h->prm = *prm;
+  h->prm.flags &= ~(uint32_t)EMIN_FLAG_PATTERN_VALUES;   // re-setups take new values
+  // each level's setup follows its pattern on the same values
+  emin_params_t first = h->prm;
+  first.flags |= EMIN_FLAG_PATTERN_VALUES;
   emin_system_t cur = *sys;
   emin_status st = EMIN_OK;
   try {
@@ -111,8 +115,8 @@ emin_status emin_hierarchy_build(const emin_system_t* sys, const emin_params_t* 
       h->Ac.push_back(h->ar.alloc<double>(z.nnz_Ac));
       h->Bc.push_back(h->ar.alloc<double>(z.nnz_Bc));
       h->rep.push_back(h->ar.alloc<emin_report_t>(1));
-      if ((st = emin_setup(p, &cur, prm, h->Pv.back(), h->Pp.back(), stream, h->rep.back())) !=
-          EMIN_OK)
+      if ((st = emin_setup(p, &cur, &first, h->Pv.back(), h->Pp.back(), stream,
+                           h->rep.back())) != EMIN_OK)
         break;
       if ((st = emin_rap(p, &cur, h->Pv.back(), h->Pp.back(), h->Ac.back(), h->Bc.back(),
                          prm->precision, stream)) != EMIN_OK)

@@ -92,7 +92,8 @@ __global__ void k_bandwidth(const int64_t* grp, const int32_t* gcol, int64_t n,
     const unsigned long long t = __shfl_xor(m, o, 64);
     m = t > m ? t : m;
   }
-  if ((threadIdx.x & 63) == 0 && m) atomicMax(bw, m);
+  if ((threadIdx.x & 63) == 0 && m > __hip_atomic_load(bw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    atomicMax(bw, m);
 }
 
 int64_t index_bandwidth(const int64_t* rp, const int32_t* col, int64_t n, hipStream_t s,
@@ -594,85 +595,202 @@ __global__ __launch_bounds__(BS) void k_spgemm_sym(const int32_t* rows, int64_t 
   }
 }
 
-// Numeric pass: G lanes per output row.  A's row is staged across the lanes
-// (columns, values, and the bounds of the B rows they select), then the B
-// rows are taken four at a time with their loads in flight together.  Within
-// one B row the columns are distinct, so lanes never meet; across B rows the
-// order is ascending k.  Each product and each sum is rounded separately, so
-// c_ij is exactly sum_k a_ik*b_kj accumulated in ascending k.
+// Numeric product, G lanes per output row (a group never spans two waves).
+// The row's accumulators sit in LDS together with an index of its sorted
+// columns that maps a column j to its slot:
+//   flat window (span of nw words fits): word w holds the row's column bits
+//     and the slot of its first column, slot = first + popc(bits below j);
+//   two-level (nw1 = nw/32 super-words plus one pair per non-empty word
+//     fit): super-word s holds the bits of its non-empty words and the rank
+//     of the first one, which picks the word's pair as above;
+//   otherwise a binary search over the sorted columns.
+// The slots of a batch of consecutive A entries are found first (independent
+// lookups), then their products are added with LDS atomics.  The entries of
+// one B row land in distinct slots, and a wave's LDS operations complete in
+// issue order, so every c_ij still receives its products in ascending order
+// of A's row, each product and each sum rounded separately.
+template <int G>
+__device__ __forceinline__ void group_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 template <int G, class TV, class TO>
 __global__ __launch_bounds__(256) void k_spgemm_num(const int64_t* arp, const int32_t* acol,
                                                    const TV* aval, const int64_t* brp,
                                                    const int32_t* bcol, const TV* bval,
                                                    const int64_t* crp, const int32_t* ccol,
-                                                   TO* cval, int64_t n, int cap) {
-  extern __shared__ unsigned char lds_raw[];
+                                                   TO* cval, int64_t n, int cap, int iw) {
+  extern __shared__ uint32_t lds_words[];
   constexpr int NG = 256 / G;
-  constexpr int U = 4;
+  constexpr int UF = G < 16 ? G : 16;   // A entries per batch when B rows fit the group
+  constexpr int US = 4;                 // ... when some B row is longer than the group
   const int g = threadIdx.x / G, lane = threadIdx.x % G;
-  TV* acc = reinterpret_cast<TV*>(lds_raw) + (size_t)g * cap;
-  int32_t* cols = reinterpret_cast<int32_t*>(reinterpret_cast<TV*>(lds_raw) + (size_t)NG * cap) +
-                  (size_t)g * cap;
+  uint32_t* idx = lds_words + (size_t)g * iw;   // iw even: pairs stay 8-byte aligned
+  TV* acc = reinterpret_cast<TV*>(lds_words + (size_t)NG * iw) + (size_t)g * cap;
+  // (measured: the dispatch order beats the XCD-contiguous one here, although
+  // the latter raises the L2 hit rate)
   const int64_t row = (int64_t)blockIdx.x * NG + g;
   if (row >= n) return;
   const int64_t c0 = crp[row];
   const int nc = (int)(crp[row + 1] - c0);
-  if (nc > cap) return;  // handled by k_spgemm_num_long
-  for (int t = lane; t < nc; t += G) {
-    cols[t] = ccol[c0 + t];
-    acc[t] = TV(0);
+  if (nc > cap || nc == 0) return;  // long rows: k_spgemm_num_long
+  const int32_t jlo = ccol[c0];
+  const int64_t span = (int64_t)ccol[c0 + nc - 1] - jlo;
+  const int64_t nw = (span >> 5) + 1, nw1 = (nw + 31) >> 5;
+  // 1: flat window, 2: two-level, 0: binary search (uniform over the group)
+  const int mode = 2 * nw <= iw ? 1 : (2 * (nw1 + nc) <= iw ? 2 : 0);
+  uint32_t* cw = idx + 2 * nw1;   // two-level: pairs of the non-empty words
+  for (int t = lane; t < nc; t += G) acc[t] = TV(0);
+  if (mode == 1) {
+    for (int t = lane; t < nw; t += G) idx[2 * t] = 0u;
+  } else if (mode == 2) {
+    for (int t = lane; t < nw1; t += G) idx[2 * t] = 0u;
+    for (int t = lane; t < nc; t += G) cw[2 * t] = 0u;
+  } else {
+    for (int t = lane; t < nc; t += G) idx[t] = (uint32_t)ccol[c0 + t];
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-  const int64_t ea = arp[row], eb = arp[row + 1];
-  for (int64_t e0 = ea; e0 < eb; e0 += G) {
-    const int64_t e = e0 + lane;
-    const bool ev = e < eb;
-    const int32_t kk = ev ? acol[e] : 0;
-    const TV av = ev ? aval[e] : TV(0);
-    const int64_t kb0 = ev ? brp[kk] : 0;
-    const int kl = ev ? (int)(brp[kk + 1] - kb0) : 0;
-    const int cnt = (int)((eb - e0) < G ? (eb - e0) : G);
-    for (int q0 = 0; q0 < cnt; q0 += U) {
-      int32_t jj[U];
-      TV bv[U], am[U];
-      int64_t b0[U];
-      int bl[U];
+  group_sync_lds<G>();
+  if (mode == 1) {
+    for (int t = lane; t < nc; t += G) {
+      const int r = ccol[c0 + t] - jlo;
+      const int w = r >> 5;
+      atomicOr(&idx[2 * w], 1u << (r & 31));
+      if (t == 0 || ((ccol[c0 + t - 1] - jlo) >> 5) != w) idx[2 * w + 1] = (uint32_t)t;
+    }
+    group_sync_lds<G>();
+  } else if (mode == 2) {
+    for (int t = lane; t < nc; t += G) {
+      const int w = (ccol[c0 + t] - jlo) >> 5;
+      atomicOr(&idx[2 * (w >> 5)], 1u << (w & 31));
+    }
+    group_sync_lds<G>();
+    // rank of each super-word's first non-empty word (exclusive scan)
+    int run = 0;
+    for (int s0 = 0; s0 < nw1; s0 += G) {
+      const int sw = s0 + lane;
+      const int c = sw < nw1 ? __popc(idx[2 * sw]) : 0;
+      int incl = c;
 #pragma unroll
-      for (int u = 0; u < U; u++) {
-        const int q = q0 + u;
-        b0[u] = __shfl(kb0, q, G);
-        bl[u] = q < cnt ? __shfl(kl, q, G) : 0;
-        am[u] = __shfl(av, q, G);
-        jj[u] = lane < bl[u] ? bcol[b0[u] + lane] : -1;
-        bv[u] = lane < bl[u] ? bval[b0[u] + lane] : TV(0);
+      for (int m = 1; m < G; m <<= 1) {
+        const int o = __shfl_up(incl, m, G);
+        if (lane >= m) incl += o;
       }
+      if (sw < nw1) idx[2 * sw + 1] = (uint32_t)(run + incl - c);
+      run += __shfl(incl, G - 1, G);
+    }
+    group_sync_lds<G>();
+    for (int t = lane; t < nc; t += G) {
+      const int r = ccol[c0 + t] - jlo;
+      const int w = r >> 5, sw = w >> 5;
+      const int d = (int)idx[2 * sw + 1] + __popc(idx[2 * sw] & ((1u << (w & 31)) - 1u));
+      atomicOr(&cw[2 * d], 1u << (r & 31));
+      if (t == 0 || ((ccol[c0 + t - 1] - jlo) >> 5) != w) cw[2 * d + 1] = (uint32_t)t;
+    }
+    group_sync_lds<G>();
+  }
+  auto slot_of = [&](int32_t j) -> int {
+    const int r = j - jlo;
+    if (mode == 1) {
+      const uint2 e = *reinterpret_cast<const uint2*>(idx + 2 * (r >> 5));
+      return (int)e.y + __popc(e.x & ((1u << (r & 31)) - 1u));
+    }
+    if (mode == 2) {
+      const int w = r >> 5;
+      const uint2 e1 = *reinterpret_cast<const uint2*>(idx + 2 * (w >> 5));
+      const int d = (int)e1.y + __popc(e1.x & ((1u << (w & 31)) - 1u));
+      const uint2 e2 = *reinterpret_cast<const uint2*>(cw + 2 * d);
+      return (int)e2.y + __popc(e2.x & ((1u << (r & 31)) - 1u));
+    }
+    int lo = 0, hi = nc;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if ((int32_t)idx[mid] < j) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+  };
+  const int64_t ea = arp[row], eb = arp[row + 1];
+  // A entries of the next chunk are loaded while the current one is summed
+  int32_t kk_n = 0;
+  TV av_n = TV(0);
+  int64_t kb0_n = 0;
+  int kl_n = 0;
+  if (ea + lane < eb) {
+    kk_n = acol[ea + lane];
+    av_n = aval[ea + lane];
+    kb0_n = brp[kk_n];
+    kl_n = (int)(brp[kk_n + 1] - kb0_n);
+  }
+  for (int64_t e0 = ea; e0 < eb; e0 += G) {
+    const TV av = av_n;
+    const int64_t kb0 = kb0_n;
+    const int kl = kl_n;
+    const int cnt = (int)((eb - e0) < G ? (eb - e0) : G);
+    {
+      const int64_t e = e0 + G + lane;
+      kl_n = 0;
+      if (e < eb) {
+        kk_n = acol[e];
+        av_n = aval[e];
+        kb0_n = brp[kk_n];
+        kl_n = (int)(brp[kk_n + 1] - kb0_n);
+      }
+    }
+    if (group_ballot<G>(kl > G) == 0ull) {
+      // every B row of the chunk fits the group: one entry per lane
+      for (int q0 = 0; q0 < cnt; q0 += UF) {
+        int32_t jj[UF];
+        TV pr[UF];
 #pragma unroll
-      for (int u = 0; u < U; u++) {
-        for (int off = 0; off < bl[u]; off += G) {
-          int32_t j = jj[u];
-          TV b = bv[u];
-          if (off > 0) {
-            j = off + lane < bl[u] ? bcol[b0[u] + off + lane] : -1;
-            b = off + lane < bl[u] ? bval[b0[u] + off + lane] : TV(0);
-          }
-          if (j >= 0) {
-            int lo = 0, hi = nc;
-            while (lo < hi) {
-              const int mid = (lo + hi) >> 1;
-              if (cols[mid] < j) lo = mid + 1; else hi = mid;
+        for (int u = 0; u < UF; u++) {
+          const int q = q0 + u;
+          const int64_t b0 = __shfl(kb0, q, G);
+          const int bl = q < cnt ? __shfl(kl, q, G) : 0;
+          const TV am = __shfl(av, q, G);
+          jj[u] = lane < bl ? bcol[b0 + lane] : -1;
+          pr[u] = am * (lane < bl ? bval[b0 + lane] : TV(0));
+        }
+        int sl[UF];
+#pragma unroll
+        for (int u = 0; u < UF; u++) sl[u] = jj[u] >= 0 ? slot_of(jj[u]) : -1;
+#pragma unroll
+        for (int u = 0; u < UF; u++)
+          if (sl[u] >= 0) atomicAdd(&acc[sl[u]], pr[u]);
+      }
+    } else {
+      for (int q0 = 0; q0 < cnt; q0 += US) {
+        int32_t jj[US];
+        TV bv[US], am[US];
+        int64_t b0[US];
+        int bl[US], sl[US];
+#pragma unroll
+        for (int u = 0; u < US; u++) {
+          const int q = q0 + u;
+          b0[u] = __shfl(kb0, q, G);
+          bl[u] = q < cnt ? __shfl(kl, q, G) : 0;
+          am[u] = __shfl(av, q, G);
+          jj[u] = lane < bl[u] ? bcol[b0[u] + lane] : -1;
+          bv[u] = lane < bl[u] ? bval[b0[u] + lane] : TV(0);
+        }
+#pragma unroll
+        for (int u = 0; u < US; u++) sl[u] = jj[u] >= 0 ? slot_of(jj[u]) : 0;
+#pragma unroll
+        for (int u = 0; u < US; u++) {
+          if (jj[u] >= 0) atomicAdd(&acc[sl[u]], am[u] * bv[u]);
+          // the rest of a B row longer than the group, before the next entry
+          for (int off = G; off < bl[u]; off += G) {
+            if (off + lane < bl[u]) {
+              const int32_t j = bcol[b0[u] + off + lane];
+              const TV b = bval[b0[u] + off + lane];
+              atomicAdd(&acc[slot_of(j)], am[u] * b);
             }
-            const TV prod = am[u] * b;
-            acc[lo] = acc[lo] + prod;
           }
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         }
       }
     }
   }
+  group_sync_lds<G>();
   for (int t = lane; t < nc; t += G) cval[c0 + t] = (TO)acc[t];
 }
 
@@ -707,24 +825,62 @@ __global__ void k_spgemm_num_long(const int64_t* arp, const int32_t* acol, const
   }
 }
 
-__global__ void k_row_len_max(const int64_t* rp, int64_t n, unsigned long long* mx) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned long long v = (i < n) ? (unsigned long long)(rp[i + 1] - rp[i]) : 0ull;
+// maximum over a 256-thread block, then one atomic per block
+__device__ __forceinline__ void block_max_to(unsigned long long v, unsigned long long* mx) {
+  __shared__ unsigned long long part[4];
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) {
-    unsigned long long o = __shfl_xor(v, m, 64);
+    const unsigned long long o = __shfl_xor(v, m, 64);
     v = o > v ? o : v;
   }
-  if ((threadIdx.x & 63) == 0) atomicMax(mx, v);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; w++) v = part[w] > v ? part[w] : v;
+    atomicMax(mx, v);
+  }
 }
 
-// output size, count-pass overflow flag and longest row of a symbolic product
+__global__ __launch_bounds__(256) void k_row_len_max(const int64_t* rp, int64_t n,
+                                                    unsigned long long* mx) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  block_max_to(i < n ? (unsigned long long)(rp[i + 1] - rp[i]) : 0ull, mx);
+}
+
+// longest row and widest window of a symbolic product: block maxima, one
+// atomic pair per block
+__global__ __launch_bounds__(256) void k_sym_maxima(const int64_t* rp, const int32_t* rwords,
+                                                   int64_t n, unsigned long long* mx) {
+  __shared__ unsigned long long part[2][4];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  unsigned long long a = i < n ? (unsigned long long)(rp[i + 1] - rp[i]) : 0ull;
+  unsigned long long b = i < n ? (unsigned long long)rwords[i] : 0ull;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const unsigned long long oa = __shfl_xor(a, m, 64), ob = __shfl_xor(b, m, 64);
+    a = oa > a ? oa : a;
+    b = ob > b ? ob : b;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    part[0][threadIdx.x >> 6] = a;
+    part[1][threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    unsigned long long v = part[threadIdx.x][0];
+    for (int w = 1; w < 4; w++) v = part[threadIdx.x][w] > v ? part[threadIdx.x][w] : v;
+    atomicMax(&mx[threadIdx.x], v);
+  }
+}
+
+// output size, count-pass overflow flag, longest row and widest window
 __global__ void k_sym_summary(const int64_t* rp, int64_t n, const int* lerr,
                               const unsigned long long* mx, int64_t* out) {
   if (threadIdx.x == 0) {
     out[0] = rp[n];
     out[1] = lerr[0];
-    out[2] = (int64_t)*mx;
+    out[2] = (int64_t)mx[0];
+    out[3] = (int64_t)mx[1];
   }
 }
 
@@ -741,15 +897,10 @@ int64_t max_row_len(const int64_t* rp, int64_t n, hipStream_t s, Arena& ar) {
   return (int64_t)d2h(mx, s);
 }
 
-__global__ void k_max_i32(const int32_t* a, int64_t n, unsigned long long* mx) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  unsigned long long v = (i < n) ? (unsigned long long)a[i] : 0ull;
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    unsigned long long o = __shfl_xor(v, m, 64);
-    v = o > v ? o : v;
-  }
-  if ((threadIdx.x & 63) == 0) atomicMax(mx, v);
+__global__ __launch_bounds__(256) void k_max_i32(const int32_t* a, int64_t n,
+                                                unsigned long long* mx) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  block_max_to(i < n ? (unsigned long long)a[i] : 0ull, mx);
 }
 
 int64_t max_row_len_i32(const int32_t* a, int64_t n, hipStream_t s, Arena& ar) {
@@ -811,12 +962,13 @@ __global__ __launch_bounds__(256) void k_spgemm_win(int64_t n, const int64_t* ar
                                                    const int32_t* acol, const int64_t* brp,
                                                    const int32_t* bcol, int wcap,
                                                    int64_t* out_cnt, const int64_t* crp,
-                                                   int32_t* ccol, int32_t* ovf, int* novf) {
+                                                   int32_t* ccol, int32_t* ovf, int* novf,
+                                                   int32_t* rwords) {
   extern __shared__ uint32_t sbits[];
   constexpr int NG = 256 / G;
   const int g = threadIdx.x / G, lane = threadIdx.x % G;
   uint32_t* words = sbits + (size_t)g * wcap;
-  const int64_t row = (int64_t)blockIdx.x * NG + g;
+  const int64_t row = xcd_block(blockIdx.x, gridDim.x) * NG + g;
   if (row >= n) return;   // whole group; the block never synchronises
   const int64_t ea = arp[row], eb = arp[row + 1];
   // window bounds
@@ -837,15 +989,21 @@ __global__ __launch_bounds__(256) void k_spgemm_win(int64_t n, const int64_t* ar
     hi = oh > hi ? oh : hi;
   }
   if (hi < 0) {   // empty output row
-    if (out_cnt && lane == 0) out_cnt[row + 1] = 0;
+    if (out_cnt && lane == 0) {
+      out_cnt[row + 1] = 0;
+      rwords[row] = 0;
+    }
     return;
   }
   const int64_t width = (int64_t)hi - lo + 1;
-  if (width > 32 * (int64_t)wcap) {
+  // lo and hi are columns of the output row, so nw is also the word count of
+  // the numeric pass's window over that row
+  const int nw = (int)((width + 31) >> 5);
+  if (out_cnt && lane == 0) rwords[row] = nw;
+  if (nw > wcap) {
     if (out_cnt && lane == 0) ovf[atomicAdd(novf, 1)] = (int32_t)row;
     return;
   }
-  const int nw = (int)((width + 31) >> 5);
   for (int t = lane; t < nw; t += G) words[t] = 0u;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
@@ -895,24 +1053,24 @@ __global__ __launch_bounds__(256) void k_spgemm_win(int64_t n, const int64_t* ar
 template <int G>
 static void launch_win(int64_t n, const CsrView& A, const CsrView& B, int wcap, int64_t* cnt,
                        const int64_t* crp, int32_t* ccol, int32_t* ovf, int* novf,
-                       hipStream_t s) {
+                       int32_t* rwords, hipStream_t s) {
   constexpr int NG = 256 / G;
   const size_t lds = (size_t)NG * wcap * sizeof(uint32_t);
   HIP_OK(hipFuncSetAttribute((const void*)k_spgemm_win<G>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   k_spgemm_win<G><<<nblocks(n, NG), 256, lds, s>>>(n, A.rowptr, A.col, B.rowptr, B.col, wcap,
-                                                   cnt, crp, ccol, ovf, novf);
+                                                   cnt, crp, ccol, ovf, novf, rwords);
 }
 
 static void win_dispatch(int g, int64_t n, const CsrView& A, const CsrView& B, int wcap,
                          int64_t* cnt, const int64_t* crp, int32_t* ccol, int32_t* ovf, int* novf,
-                         hipStream_t s) {
+                         int32_t* rwords, hipStream_t s) {
   switch (g) {
-    case 4: launch_win<4>(n, A, B, wcap, cnt, crp, ccol, ovf, novf, s); break;
-    case 8: launch_win<8>(n, A, B, wcap, cnt, crp, ccol, ovf, novf, s); break;
-    case 16: launch_win<16>(n, A, B, wcap, cnt, crp, ccol, ovf, novf, s); break;
-    case 32: launch_win<32>(n, A, B, wcap, cnt, crp, ccol, ovf, novf, s); break;
-    default: launch_win<64>(n, A, B, wcap, cnt, crp, ccol, ovf, novf, s); break;
+    case 4: launch_win<4>(n, A, B, wcap, cnt, crp, ccol, ovf, novf, rwords, s); break;
+    case 8: launch_win<8>(n, A, B, wcap, cnt, crp, ccol, ovf, novf, rwords, s); break;
+    case 16: launch_win<16>(n, A, B, wcap, cnt, crp, ccol, ovf, novf, rwords, s); break;
+    case 32: launch_win<32>(n, A, B, wcap, cnt, crp, ccol, ovf, novf, rwords, s); break;
+    default: launch_win<64>(n, A, B, wcap, cnt, crp, ccol, ovf, novf, rwords, s); break;
   }
 }
 
@@ -937,11 +1095,13 @@ void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& pla
   // window bitmap per group: up to 32 KiB per block
   const int wcap = (int)std::min<int64_t>(4096, (32 * 1024 / 4) / NG);
   const int big = 16384;  // hash table of one 64-lane group, 96 KiB of LDS
-  int* lerr = ar.alloc<int>(4);
+  int* lerr = ar.alloc<int>(4);   // error, wide rows, hash overflow, fill overflow
+  int32_t* rwords = ar.alloc<int32_t>(A.nrows);   // words spanned by each output row
   int32_t* ovf = ar.alloc<int32_t>(A.nrows);    // rows wider than the window
   int32_t* ovf2 = ar.alloc<int32_t>(A.nrows);   // of those, rows the hash table cannot hold
   HIP_OK(hipMemsetAsync(lerr, 0, 4 * sizeof(int), s));
-  if (A.nrows) win_dispatch(g, A.nrows, A, B, wcap, C.rowptr, nullptr, nullptr, ovf, lerr + 1, s);
+  if (A.nrows)
+    win_dispatch(g, A.nrows, A, B, wcap, C.rowptr, nullptr, nullptr, ovf, lerr + 1, rwords, s);
   int hl[4];
   HIP_OK(hipMemcpyAsync(hl, lerr, sizeof(hl), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
@@ -966,23 +1126,25 @@ void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& pla
   // one read-back: output size, count-pass overflow, longest output row
   HIP_OK(hipMemsetAsync(C.rowptr, 0, sizeof(int64_t), s));
   scan_inclusive(C.rowptr + 1, C.nrows, s, ar);
-  unsigned long long* mx = ar.alloc<unsigned long long>(1);
-  int64_t* sm = ar.alloc<int64_t>(3);
-  HIP_OK(hipMemsetAsync(mx, 0, sizeof(unsigned long long), s));
-  if (C.nrows) k_row_len_max<<<nblocks(C.nrows, 256), 256, 0, s>>>(C.rowptr, C.nrows, mx);
+  unsigned long long* mx = ar.alloc<unsigned long long>(2);
+  int64_t* sm = ar.alloc<int64_t>(4);
+  HIP_OK(hipMemsetAsync(mx, 0, 2 * sizeof(unsigned long long), s));
+  if (C.nrows) k_sym_maxima<<<nblocks(C.nrows, 256), 256, 0, s>>>(C.rowptr, rwords, C.nrows, mx);
   k_sym_summary<<<1, 64, 0, s>>>(C.rowptr, C.nrows, lerr, mx, sm);
-  int64_t hs[3];
+  int64_t hs[4];
   HIP_OK(hipMemcpyAsync(hs, sm, sizeof(hs), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
   C.nnz = hs[0];
   if (hs[1]) throw Error(EMIN_ERR_CAPACITY, "spgemm: output row exceeds the LDS table");
   plan.max_row = hs[2];
+  plan.max_words = hs[3];
   C.col = ar.alloc<int32_t>(C.nnz);
   C.val = ar.alloc<double>(C.nnz);
   // the window fill skips the wide rows; the hash kernels fill those (the
   // first hash fill skips the rows its table could not hold; the big table
   // does them)
-  if (A.nrows) win_dispatch(g, A.nrows, A, B, wcap, nullptr, C.rowptr, C.col, nullptr, nullptr, s);
+  if (A.nrows)
+    win_dispatch(g, A.nrows, A, B, wcap, nullptr, C.rowptr, C.col, nullptr, nullptr, nullptr, s);
   if (nwide) {
     switch (g) {
       case 4: launch_sym_rows<4>(ovf, nwide, A, B, hcap, nullptr, C.rowptr, C.col, ovf2, lerr + 3, lerr, s); break;
@@ -1004,11 +1166,13 @@ void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& pla
 
 template <int G, class TV, class TO>
 static void launch_num(const CsrView& A, const TV* aval, const CsrView& B, const TV* bval,
-                       const Csr& C, TO* cval, int cap, hipStream_t s) {
+                       const Csr& C, TO* cval, int cap, int iw, hipStream_t s) {
   constexpr int NG = 256 / G;
-  const size_t lds = (size_t)NG * cap * (sizeof(TV) + sizeof(int32_t));
+  const size_t lds = (size_t)NG * ((size_t)iw * sizeof(uint32_t) + cap * sizeof(TV));
+  HIP_OK(hipFuncSetAttribute((const void*)k_spgemm_num<G, TV, TO>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   k_spgemm_num<G, TV, TO><<<nblocks(A.nrows, NG), 256, lds, s>>>(
-      A.rowptr, A.col, aval, B.rowptr, B.col, bval, C.rowptr, C.col, cval, A.nrows, cap);
+      A.rowptr, A.col, aval, B.rowptr, B.col, bval, C.rowptr, C.col, cval, A.nrows, cap, iw);
 }
 
 template <class TV, class TO>
@@ -1019,16 +1183,27 @@ static void numeric_any(const CsrView& A, const TV* aval, const CsrView& B, cons
                  (4.0 + sizeof(TV)) * (double)(A.nnz + B.nnz + C.nnz) + 16.0 * (double)A.nrows);
   const int g = plan.g_num;
   const int NG = 256 / g;
-  // LDS budget ~96 KiB per block
+  // LDS: accumulators of the longest row (within ~96 KiB per block), and an
+  // index of iw words per row: enough for the two-level index of every window
+  // row, the flat window where ~40 KiB per block allow it, never less than
+  // the sorted columns, and within 152 KiB per block in all
   int cap = (int)((96 * 1024) / (NG * (sizeof(TV) + sizeof(int32_t))));
   if (cap > plan.max_row) cap = (int)plan.max_row;
   if (cap < 1) cap = 1;
+  const int64_t mw = plan.max_words;
+  const int64_t two_level = 2 * ((mw + 31) / 32 + cap);
+  const int64_t flat = std::min<int64_t>(2 * mw, (40 * 1024 / NG - (int64_t)cap * sizeof(TV)) / 4);
+  const int64_t most = (152 * 1024 / NG - (int64_t)cap * sizeof(TV)) / 4;
+  // (the two-level room only where some window row misses the flat one)
+  int64_t iw = std::min(flat >= 2 * mw ? flat : std::max(two_level, flat), most);
+  iw = std::max<int64_t>(iw, cap);
+  iw = (iw + 1) & ~int64_t(1);
   switch (g) {
-    case 4: launch_num<4>(A, aval, B, bval, C, cval, cap, s); break;
-    case 8: launch_num<8>(A, aval, B, bval, C, cval, cap, s); break;
-    case 16: launch_num<16>(A, aval, B, bval, C, cval, cap, s); break;
-    case 32: launch_num<32>(A, aval, B, bval, C, cval, cap, s); break;
-    default: launch_num<64>(A, aval, B, bval, C, cval, cap, s); break;
+    case 4: launch_num<4>(A, aval, B, bval, C, cval, cap, (int)iw, s); break;
+    case 8: launch_num<8>(A, aval, B, bval, C, cval, cap, (int)iw, s); break;
+    case 16: launch_num<16>(A, aval, B, bval, C, cval, cap, (int)iw, s); break;
+    case 32: launch_num<32>(A, aval, B, bval, C, cval, cap, (int)iw, s); break;
+    default: launch_num<64>(A, aval, B, bval, C, cval, cap, (int)iw, s); break;
   }
   if (plan.max_row > cap)
     k_spgemm_num_long<TV, TO><<<nblocks(A.nrows, 64), 64, 0, s>>>(

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libemin.so")
 
 EMIN_PREC_F64, EMIN_PREC_MIXED = 0, 1
-EMIN_FLAG_ENERGY, EMIN_FLAG_VALIDATE, EMIN_FLAG_AUTOTUNE = 1, 2, 4
+EMIN_FLAG_ENERGY, EMIN_FLAG_VALIDATE, EMIN_FLAG_AUTOTUNE, EMIN_FLAG_PATTERN_VALUES = 1, 2, 4, 8
 MAX_ITERS = 32
 (VIEW_PV, VIEW_PP, VIEW_AC, VIEW_BC, VIEW_MV, VIEW_MP, VIEW_S, VIEW_ORDER, VIEW_CP, VIEW_CBAR,
  VIEW_CV, VIEW_XVC, VIEW_P2VC, VIEW_KEEPV, VIEW_KEEPP, VIEW_DIR) = range(16)
@@ -349,7 +349,8 @@ class Hierarchy:
     def __init__(self, sys, nlevels, prm: c_params, min_dofs=0, device="cuda"):
         self.fine = DeviceSystem.upload(sys, device)
         self.nlevels = nlevels
-        self.prm = prm
+        self.prm = c_params.from_buffer_copy(prm)
+        self.prm.flags &= ~EMIN_FLAG_PATTERN_VALUES   # re-setups take new values
         self.min_dofs = min_dofs
         self.device = device
         self.levels: list[Level] = []
@@ -357,6 +358,9 @@ class Hierarchy:
     def build(self, stream=None):
         import torch
         self.levels = []
+        # each level's setup follows its pattern on the same values
+        first = c_params.from_buffer_copy(self.prm)
+        first.flags |= EMIN_FLAG_PATTERN_VALUES
         cur = self.fine
         for _ in range(self.nlevels - 1):
             if cur.dim * cur.n_v + cur.n_p <= self.min_dofs:
@@ -368,7 +372,7 @@ class Hierarchy:
                       torch.empty(max(s["nnz_Pp"], 1), **f64),
                       torch.empty(max(s["nnz_Ac"], 1), **f64),
                       torch.empty(max(s["nnz_Bc"], 1), **f64), new_report(self.device))
-            pat.setup(self.prm, L.Pv.data_ptr(), L.Pp.data_ptr(), L.report.data_ptr(), stream)
+            pat.setup(first, L.Pv.data_ptr(), L.Pp.data_ptr(), L.report.data_ptr(), stream)
             pat.rap(L.Pv.data_ptr(), L.Pp.data_ptr(), L.Ac.data_ptr(), L.Bc.data_ptr(), stream,
                     mixed=self.prm.precision == EMIN_PREC_MIXED)
             self.levels.append(L)

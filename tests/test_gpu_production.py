@@ -162,3 +162,25 @@ def test_autotuned_schedule_same_results_and_reuse():
     for h in (base, tuned, again):
         h.close()
     E.autotune_reset()
+
+
+def test_pattern_values_flag_equals_full_setup():
+    """emin_setup with EMIN_FLAG_PATTERN_VALUES right after emin_pattern reuses
+    the pattern's filtered operators: P must equal a setup that forms them
+    again, bit for bit; a hierarchy re-setup on the same values too."""
+    import torch
+    from paper_1607_02489_amd import emin as E
+    s = synth.oseen2d(24)
+    prm = E.params(iters=5)
+    H = E.Hierarchy(s, 3, prm).build()     # first setups use the flag
+    torch.cuda.synchronize()
+    first = [(L.Pv.cpu().numpy().copy(), L.Pp.cpu().numpy().copy(), L.Ac.cpu().numpy().copy())
+             for L in H.levels]
+    assert H.prm.flags & E.EMIN_FLAG_PATTERN_VALUES == 0
+    H.resetup()                            # forms the operators again
+    torch.cuda.synchronize()
+    for (pv, pp, ac), L in zip(first, H.levels):
+        assert np.array_equal(pv, L.Pv.cpu().numpy())
+        assert np.array_equal(pp, L.Pp.cpu().numpy())
+        assert np.array_equal(ac, L.Ac.cpu().numpy())
+    H.close()
