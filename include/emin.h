@@ -115,8 +115,11 @@ typedef struct {
   int64_t device_bytes;     /* device memory held by the handle */
   int64_t sched_v, sched_p; /* masked-product schedule of each block: bit 0 intersection
                                maps used, bit 1 lanes per row doubled, bit 2 XCD split by
-                               row class; bits 4-5: 0 default, 1 autotuned on this
-                               pattern, 2 reused from an earlier tuning of the same shape */
+                               row class, bit 3 blocks of all classes in row order with
+                               one contiguous eighth per XCD (neither: one contiguous
+                               eighth of the class-major grid per XCD); bits 4-5: 0
+                               default, 1 autotuned on this pattern, 2 reused from an
+                               earlier tuning of the same shape */
 } emin_sizes_t;
 
 /* Device-resident report of emin_setup (read it with emin_sync_report). */

@@ -20,18 +20,27 @@ struct EminReportPtrs {
 // one masked-product launch: row lists of every class back to back, with the
 // row and block ranges of each class
 constexpr int SPMM_NT = 9;
+// block order of the masked product over the XCDs
+enum : int32_t {
+  XCD_CONTIGUOUS = 0,   // each XCD takes one contiguous eighth of the grid
+  XCD_BY_CLASS = 1,     // each XCD takes an eighth of every row class
+  XCD_MERGED = 2        // blocks of all classes in order of their first row, then
+                        // one contiguous eighth of that order per XCD
+};
+
 struct SpmmSched {
   const int32_t* rows = nullptr;
   int64_t row_off[SPMM_NT + 1] = {};
   int64_t blk_off[SPMM_NT + 1] = {};
-  int32_t xcd_split = 1;
+  int32_t xcd_split = XCD_BY_CLASS;
+  const int32_t* bmap = nullptr;   // XCD_MERGED: (class << 27) | block in class, per slot
 };
 
 // options of a masked-product schedule (the autotuner's search space)
 struct SchedOpts {
   bool maps = true;      // rows that fit the intersection maps use them
   int gshift = 0;        // lanes per row: the tight power of two, times 2^gshift
-  bool xcd_split = true; // each XCD takes an eighth of every class
+  int xcd_split = XCD_MERGED;   // XCD_*
 };
 
 struct EminWork {

@@ -221,17 +221,19 @@ __global__ void k_spmm_maps(const int64_t* mrp, const int32_t* mcol, const int64
 
 // Masked product on the intersection maps: G lanes (G >= |N_i|) own row i,
 // lane s computing slot s.  The group copies M's row (values, base offsets,
-// map words) through a small LDS window with coalesced loads, padding the
-// window to a multiple of four entries with empty maps; then for each entry
+// map words) through an LDS window with coalesced loads; then for each entry
 // lane s reads its 4-bit field and, on a match, gathers exactly one pattern
 // value, X[kofs + s + field].  No searching and no cross-lane traffic;
-// per-slot sums run over k in order (deterministic).
+// per-slot sums run over k in order (deterministic).  The inner loop has no
+// branches: the trip count is the longest row of the wave (shorter rows are
+// padded with empty maps), a missing match gathers X[0] and adds m * 0, and
+// four entries are read from the window with one 16-byte LDS load per array.
 template <int G>
 struct MapWin {
   static constexpr int NG = 256 / G;
   static constexpr int WG = 64 / G;                 // groups per wave
   static constexpr int NP = G <= 8 ? 1 : G / 8;     // map planes of a row
-  static constexpr int CH = G <= 4 ? 8 : (G < 16 ? 16 : G);   // window entries per group
+  static constexpr int CH = G <= 4 ? 16 : 32;       // window entries per group
 };
 
 template <int G, class TM>
@@ -253,6 +255,22 @@ constexpr int spmm_smem() {
   return 4 * spmm_wave_smem<TM>();
 }
 
+template <class T> struct Vec4;
+template <> struct Vec4<double> {
+  double v[4];
+  __device__ __forceinline__ void load(const double* p) {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    const double2 b = *reinterpret_cast<const double2*>(p + 2);
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+  }
+};
+template <> struct Vec4<float> {
+  float v[4];
+  __device__ __forceinline__ void load(const float* p) {
+    const float4 a = *reinterpret_cast<const float4*>(p);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  }
+};
 
 template <int G, class TM, class TX, class TY>
 __device__ __forceinline__ void spmm_map_rows(int64_t lb, const int32_t* rows, int64_t nrows,
@@ -264,7 +282,6 @@ __device__ __forceinline__ void spmm_map_rows(int64_t lb, const int32_t* rows, i
   using TA = TM;
   using W = MapWin<G>;
   constexpr int NG = W::NG, NP = W::NP, CH = W::CH;
-  constexpr int U = 4;
   // each wave owns its own LDS region (its groups' windows): the layout of
   // one wave never depends on another wave's row class
   constexpr int WG = W::WG;
@@ -279,48 +296,62 @@ __device__ __forceinline__ void spmm_map_rows(int64_t lb, const int32_t* rows, i
   TM* gm = s_m + gi * CH;
   int32_t* gk = s_k + gi * CH;
   const uint32_t* gw = s_w + q * (WG * CH) + gi * CH;
-  if (r < nrows) {
-    const int32_t i = rows[r];
-    const int64_t na = nrp[i];
-    const int ni = (int)(nrp[i + 1] - na);
-    const int64_t ma = mrp[i], mb = mrp[i + 1];
-    TA acc = TA(0);
-    for (int64_t c0 = ma; c0 < mb; c0 += CH) {
-      const int cn = (int)((mb - c0) < CH ? (mb - c0) : CH);
-      const int cnp = (cn + U - 1) & ~(U - 1);
-      for (int t = lane; t < cnp; t += G) {
-        const bool v = t < cn;
-        gm[t] = v ? mval[c0 + t] : TM(0);
-        gk[t] = v ? kofs[c0 + t] : 0;
+  // rows past the class end join the wave's loops as empty rows
+  const bool valid = r < nrows;
+  const int32_t i = valid ? rows[r] : 0;
+  const int64_t na = valid ? nrp[i] : 0;
+  const int ni = valid ? (int)(nrp[i + 1] - na) : 0;
+  const int64_t ma = valid ? mrp[i] : 0;
+  const int len = valid ? (int)(mrp[i + 1] - ma) : 0;
+  const int wl = -wave_min_i32(-len);   // longest row of the wave (uniform)
+  const double dv = (rowdot && lane < ni) ? D[na + lane] : 0.0;
+  TA acc = TA(0);
+  for (int c0 = 0; c0 < wl; c0 += CH) {
+    const int cw = ((wl - c0 < CH ? wl - c0 : CH) + 3) & ~3;   // uniform
+    for (int t = lane; t < cw; t += G) {
+      const bool v = c0 + t < len;
+      const int64_t e = ma + c0 + t;
+      gm[t] = v ? mval[e] : TM(0);
+      gk[t] = v ? kofs[e] : 0;
 #pragma unroll
-        for (int p = 0; p < NP; p++)
-          s_w[p * (WG * CH) + gi * CH + t] = v ? nib[(int64_t)p * nnzm + c0 + t] : 0xFFFFFFFFu;
-      }
-      // the group lies inside one wave: order its LDS writes before the reads
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      for (int t = 0; t < cnp; t += U) {
-        TX x[U];
-        uint32_t f[U];
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-          f[u] = (gw[t + u] >> sh) & 0xFu;
-          x[u] = f[u] != 0xFu ? X[(int64_t)(gk[t + u] + lane + (int)f[u])] : TX(0);
-        }
-#pragma unroll
-        for (int u = 0; u < U; u++)
-          if (f[u] != 0xFu) acc = fma(gm[t + u], (TA)x[u], acc);
-      }
-      // every lane is done with the window before the next pass refills it
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int p = 0; p < NP; p++)
+        s_w[p * (WG * CH) + gi * CH + t] = v ? nib[(int64_t)p * nnzm + e] : 0xFFFFFFFFu;
     }
+    // the group lies inside one wave: order its LDS writes before the reads
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int t = 0; t < cw; t += 4) {
+      const uint4 w4 = *reinterpret_cast<const uint4*>(gw + t);
+      const int4 k4 = *reinterpret_cast<const int4*>(gk + t);
+      Vec4<TM> m4;
+      m4.load(gm + t);
+      const uint32_t wv[4] = {w4.x, w4.y, w4.z, w4.w};
+      const int32_t kv[4] = {k4.x, k4.y, k4.z, k4.w};
+      TX x[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const uint32_t f = (wv[u] >> sh) & 0xFu;
+        const bool hit = f != 0xFu;
+        // 32-bit byte offset (a pattern of fewer than 2^29 entries): the load
+        // takes X as a scalar base plus one vector offset
+        const uint32_t off = (uint32_t)(hit ? kv[u] + lane + (int)f : 0) * (uint32_t)sizeof(TX);
+        const TX xl = *reinterpret_cast<const TX*>(reinterpret_cast<const char*>(X) + off);
+        x[u] = hit ? xl : TX(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; u++) acc = fma(m4.v[u], (TA)x[u], acc);
+    }
+    // every lane is done with the window before the next pass refills it
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  if (valid) {
     if (lane < ni) Y[na + lane] = (TY)acc;
     if (rowdot) {
       // <D, Y> of the row, summed in slot order by lane 0
-      const double pr = lane < ni ? D[na + lane] * (double)acc : 0.0;
+      const double pr = lane < ni ? dv * (double)acc : 0.0;
       double sum = 0.0;
       for (int t = 0; t < ni; t++) sum = sum + __shfl(pr, t, G);
       if (lane == 0) rowdot[i] = sum;
@@ -344,7 +375,11 @@ __global__ __launch_bounds__(256) void k_spmm(SpmmSched S, const int64_t* mrp,
   __shared__ __align__(16) unsigned char smem[spmm_smem<TM>()];
   int ty = 0;
   int64_t lb;
-  if (S.xcd_split) {
+  if (S.xcd_split == XCD_MERGED) {
+    const int32_t m = S.bmap[xcd_block(blockIdx.x, gridDim.x)];
+    ty = m >> 27;
+    lb = m & ((1 << 27) - 1);
+  } else if (S.xcd_split == XCD_BY_CLASS) {
     const int64_t x = blockIdx.x & 7, j = blockIdx.x >> 3;
 #pragma unroll
     for (int t = 1; t < SPMM_NT; t++) ty += j >= (S.blk_off[t] >> 3) ? 1 : 0;
@@ -614,6 +649,44 @@ __global__ __launch_bounds__(256) void k_sched_place(const int64_t* nrp, const u
   rows[pos + __popcll(mine & below)] = (int32_t)i;
 }
 
+// XCD_MERGED order: block lb of class c goes to slot lb + the number of
+// blocks of the other classes whose first row comes before its own (ties by
+// class); padding blocks (no rows) sort last.  The first rows of a class's
+// blocks ascend, so each count is a binary search.
+struct MergeArgs {
+  const int32_t* rows;
+  int64_t row_off[SPMM_NT + 1];
+  int64_t blk_off[SPMM_NT + 1];
+};
+
+__device__ __forceinline__ int64_t first_row(const MergeArgs& A, int c, int64_t lb) {
+  const int G = 4 << (c < 4 ? c : c - 4);
+  const int64_t r = A.row_off[c] + lb * (256 / G);
+  return r < A.row_off[c + 1] ? (int64_t)A.rows[r] : INT64_MAX;
+}
+
+__global__ void k_sched_merge(MergeArgs A, int32_t* bmap) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= A.blk_off[SPMM_NT]) return;
+  int c = 0;
+  while (c + 1 < SPMM_NT && b >= A.blk_off[c + 1]) c++;
+  const int64_t lb = b - A.blk_off[c];
+  const int64_t key = first_row(A, c, lb);
+  int64_t pos = lb;
+  for (int c2 = 0; c2 < SPMM_NT; c2++) {
+    if (c2 == c) continue;
+    // blocks of c2 before (key, c): first row < key, or == key with c2 < c
+    int64_t lo = 0, hi = A.blk_off[c2 + 1] - A.blk_off[c2];
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      const int64_t k2 = first_row(A, c2, mid);
+      if (k2 < key || (k2 == key && c2 < c)) lo = mid + 1; else hi = mid;
+    }
+    pos += lo;
+  }
+  bmap[pos] = (int32_t)((c << 27) | (int32_t)lb);
+}
+
 __global__ void k_sched_totals(const int64_t* incl, int64_t nb, int64_t* tot) {
   const int c = threadIdx.x;
   if (c < SPMM_NT) tot[c] = incl[(int64_t)(c + 1) * nb - 1];
@@ -650,6 +723,19 @@ static void build_sched(const EminWork& w, const int64_t* nrp, const uint8_t* el
   S.blk_off[SPMM_NT] = blocks;
   S.rows = rows;
   S.xcd_split = o.xcd_split;
+  S.bmap = nullptr;
+  if (o.xcd_split == XCD_MERGED && blocks) {
+    if (blocks >= (int64_t(1) << 27)) throw Error(EMIN_ERR_CAPACITY, "masked product: too many blocks");
+    int32_t* bmap = ar.alloc<int32_t>(blocks);
+    MergeArgs A;
+    A.rows = rows;
+    for (int t = 0; t <= SPMM_NT; t++) {
+      A.row_off[t] = S.row_off[t];
+      A.blk_off[t] = S.blk_off[t];
+    }
+    k_sched_merge<<<nblocks(blocks, 256), 256, 0, s>>>(A, bmap);
+    S.bmap = bmap;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -710,8 +796,8 @@ void EminWork::make_bins(const Csr& M, const int64_t* nrp, const int32_t* ncol, 
   int ncand = 0;
   for (int maps = 1; maps >= 0; maps--)
     for (int gshift = 0; gshift <= 1; gshift++)
-      for (int xs = 1; xs >= 0; xs--) {
-        const SchedOpts o{maps != 0, gshift, xs != 0};
+      for (int xs = XCD_MERGED; xs >= XCD_CONTIGUOUS; xs--) {
+        const SchedOpts o{maps != 0, gshift, xs};
         SpmmSched S{};
         build_sched(*this, nrp, elig, o, S, s, ar);
         const SpmmSched keep = sched;
@@ -745,8 +831,9 @@ void EminWork::make_bins(const Csr& M, const int64_t* nrp, const int32_t* ncol, 
 }
 
 int32_t EminWork::sched_code() const {
-  return (int32_t)((opts.maps ? 1 : 0) | (opts.gshift ? 2 : 0) | (opts.xcd_split ? 4 : 0) |
-                   (tuned << 4));
+  return (int32_t)((opts.maps ? 1 : 0) | (opts.gshift ? 2 : 0) |
+                   (opts.xcd_split == XCD_BY_CLASS ? 4 : 0) |
+                   (opts.xcd_split == XCD_MERGED ? 8 : 0) | (tuned << 4));
 }
 
 void autotune_stats(int64_t* out) {

@@ -300,7 +300,7 @@ def autotune_reset():
 def sched_name(code: int) -> str:
     """Readable form of a schedule code from the level sizes."""
     parts = ["maps" if code & 1 else "search-only", "2x-lanes" if code & 2 else "tight-lanes",
-             "xcd-by-class" if code & 4 else "xcd-contiguous"]
+             "xcd-by-class" if code & 4 else ("xcd-merged" if code & 8 else "xcd-contiguous")]
     return "+".join(parts) + ["", " (tuned)", " (reused)", ""][(code >> 4) & 3]
 
 
