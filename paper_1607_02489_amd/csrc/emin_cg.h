@@ -20,6 +20,9 @@ struct EminReportPtrs {
 // one masked-product launch: row lists of every class back to back, with the
 // row and block ranges of each class
 constexpr int SPMM_NT = 9;
+// threads per block of the masked product (a multiple of 64)
+constexpr int SPMM_BS = 64;
+
 // block order of the masked product over the XCDs
 enum : int32_t {
   XCD_CONTIGUOUS = 0,   // each XCD takes one contiguous eighth of the grid

@@ -95,7 +95,7 @@ __device__ __forceinline__ void spmm_search_rows(int64_t lb, const int32_t* rows
                                                  const int32_t* ncol, const TX* X, TY* Y,
                                                  const double* D, double* rowdot) {
   using TA = TM;
-  constexpr int NG = 256 / G;
+  constexpr int NG = SPMM_BS / G;
   constexpr int U = 4;
   const int g = threadIdx.x / G, lane = threadIdx.x % G;
   const int64_t r = lb * NG + g;
@@ -230,7 +230,7 @@ __global__ void k_spmm_maps(const int64_t* mrp, const int32_t* mcol, const int64
 // four entries are read from the window with one 16-byte LDS load per array.
 template <int G>
 struct MapWin {
-  static constexpr int NG = 256 / G;
+  static constexpr int NG = SPMM_BS / G;
   static constexpr int WG = 64 / G;                 // groups per wave
   static constexpr int NP = G <= 8 ? 1 : G / 8;     // map planes of a row
   static constexpr int CH = G <= 4 ? 16 : 32;       // window entries per group
@@ -252,7 +252,7 @@ constexpr int spmm_wave_smem() {
 
 template <class TM>
 constexpr int spmm_smem() {
-  return 4 * spmm_wave_smem<TM>();
+  return (SPMM_BS / 64) * spmm_wave_smem<TM>();
 }
 
 template <class T> struct Vec4;
@@ -366,7 +366,7 @@ __device__ __forceinline__ void spmm_map_rows(int64_t lb, const int32_t* rows, i
 // every class, so the load is balanced across XCDs and each XCD works on
 // contiguous rows; otherwise each XCD takes one contiguous eighth of the grid.
 template <class TM, class TX, class TY>
-__global__ __launch_bounds__(256) void k_spmm(SpmmSched S, const int64_t* mrp,
+__global__ __launch_bounds__(SPMM_BS) void k_spmm(SpmmSched S, const int64_t* mrp,
                                               const int32_t* mcol, const TM* mval,
                                               const int32_t* kofs, const uint32_t* nib,
                                               int64_t nnzm, const int64_t* nrp,
@@ -661,7 +661,7 @@ struct MergeArgs {
 
 __device__ __forceinline__ int64_t first_row(const MergeArgs& A, int c, int64_t lb) {
   const int G = 4 << (c < 4 ? c : c - 4);
-  const int64_t r = A.row_off[c] + lb * (256 / G);
+  const int64_t r = A.row_off[c] + lb * (SPMM_BS / G);
   return r < A.row_off[c + 1] ? (int64_t)A.rows[r] : INT64_MAX;
 }
 
@@ -716,7 +716,7 @@ static void build_sched(const EminWork& w, const int64_t* nrp, const uint8_t* el
     const int64_t cnt = tot[ty] - prev;
     S.row_off[ty] = prev;
     S.blk_off[ty] = blocks;
-    blocks += ((cnt + (256 / G) - 1) / (256 / G) + 7) & ~(int64_t)7;
+    blocks += ((cnt + (SPMM_BS / G) - 1) / (SPMM_BS / G) + 7) & ~(int64_t)7;
     prev = tot[ty];
   }
   S.row_off[SPMM_NT] = prev;
@@ -855,7 +855,7 @@ static void spmm_any(const EminWork& w, const Csr& M, const TM* mval, const int6
                      const int32_t* ncol, const TX* X, TY* Y, const double* D, hipStream_t s) {
   const int64_t nb = w.sched.blk_off[SPMM_NT];
   if (nb == 0) return;
-  k_spmm<TM, TX, TY><<<(unsigned)nb, 256, 0, s>>>(w.sched, M.rowptr, M.col, mval, w.kofs, w.nib,
+  k_spmm<TM, TX, TY><<<(unsigned)nb, SPMM_BS, 0, s>>>(w.sched, M.rowptr, M.col, mval, w.kofs, w.nib,
                                                    w.nnzm, nrp, ncol, X, Y, D, w.rowdot);
 }
 
