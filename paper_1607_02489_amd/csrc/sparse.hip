@@ -605,15 +605,36 @@ __global__ __launch_bounds__(BS) void k_spgemm_sym(const int32_t* rows, int64_t 
 //     of the first one, which picks the word's pair as above;
 //   otherwise a binary search over the sorted columns.
 // The slots of a batch of consecutive A entries are found first (independent
-// lookups), then their products are added with LDS atomics.  The entries of
-// one B row land in distinct slots, and a wave's LDS operations complete in
-// issue order, so every c_ij still receives its products in ascending order
-// of A's row, each product and each sum rounded separately.
+// lookups), then their products are added (acc_add).  The entries of one B
+// row land in distinct slots, and a wave's LDS operations complete in issue
+// order, so every c_ij still receives its products in ascending order of A's
+// row, each product and each sum rounded separately.
 template <int G>
 __device__ __forceinline__ void group_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// acc[slot] += v, in the wave's issue order.  FP64: an LDS atomic add (no
+// return, so consecutive adds do not wait for each other).  FP32: a plain
+// read-add-write (measured faster than the LDS float atomic here); a wave's
+// LDS operations complete in order, and acc_order(), called by every lane
+// after each entry's adds, keeps the compiler from moving the next entry's
+// reads above these writes.
+template <class TV>
+__device__ __forceinline__ void acc_add(TV* acc, int slot, TV v) {
+  if constexpr (sizeof(TV) == 8) atomicAdd(&acc[slot], v);
+  else acc[slot] = acc[slot] + v;
+}
+
+template <class TV>
+__device__ __forceinline__ void acc_order() {
+  if constexpr (sizeof(TV) == 4) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
 }
 
 template <int G, class TV, class TO>
@@ -755,8 +776,10 @@ __global__ __launch_bounds__(256) void k_spgemm_num(const int64_t* arp, const in
 #pragma unroll
         for (int u = 0; u < UF; u++) sl[u] = jj[u] >= 0 ? slot_of(jj[u]) : -1;
 #pragma unroll
-        for (int u = 0; u < UF; u++)
-          if (sl[u] >= 0) atomicAdd(&acc[sl[u]], pr[u]);
+        for (int u = 0; u < UF; u++) {
+          if (sl[u] >= 0) acc_add(acc, sl[u], pr[u]);
+          acc_order<TV>();
+        }
       }
     } else {
       for (int q0 = 0; q0 < cnt; q0 += US) {
@@ -777,15 +800,16 @@ __global__ __launch_bounds__(256) void k_spgemm_num(const int64_t* arp, const in
         for (int u = 0; u < US; u++) sl[u] = jj[u] >= 0 ? slot_of(jj[u]) : 0;
 #pragma unroll
         for (int u = 0; u < US; u++) {
-          if (jj[u] >= 0) atomicAdd(&acc[sl[u]], am[u] * bv[u]);
+          if (jj[u] >= 0) acc_add(acc, sl[u], am[u] * bv[u]);
           // the rest of a B row longer than the group, before the next entry
           for (int off = G; off < bl[u]; off += G) {
             if (off + lane < bl[u]) {
               const int32_t j = bcol[b0[u] + off + lane];
               const TV b = bval[b0[u] + off + lane];
-              atomicAdd(&acc[slot_of(j)], am[u] * b);
+              acc_add(acc, slot_of(j), am[u] * b);
             }
           }
+          acc_order<TV>();
         }
       }
     }
