@@ -250,36 +250,37 @@ __global__ __launch_bounds__(64) void k_mid_decide(const int32_t* mo, const int3
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-  // software pipeline: chunk c+1's entries load while chunk c resolves
-  int32_t T[TCAP], Tn[TCAP];
-  int32_t mi = -1, mn = -1;
-  unsigned long long dp = 0ull, dn = 0ull;
-  auto load = [&](int64_t base, int32_t* Tx, int32_t& mx, unsigned long long& dx) {
+  // software pipeline: each chunk's entries are loaded DEPTH chunks ahead
+  // (a chunk's work is far shorter than a memory round trip)
+  struct Chunk {
+    int32_t T[TCAP];
+    int32_t m;
+    unsigned long long d;
+  };
+  auto load = [&](int64_t base, Chunk& c) {
     const int64_t p = base + lane;
     const bool ok = p < norder;
 #pragma unroll
-    for (int t = 0; t < TCAP; t++) Tx[t] = ok ? to[p * TCAP + t] : -1;
-    mx = ok ? mo[p] : -1;
-    dx = ok ? dep[p] : 0ull;
+    for (int t = 0; t < TCAP; t++) c.T[t] = ok ? to[p * TCAP + t] : -1;
+    c.m = ok ? mo[p] : -1;
+    c.d = ok ? dep[p] : 0ull;
   };
-  if (norder > 0) load(0, T, mi, dp);
-  for (int64_t base = 0; base < norder; base += 64) {
-    if (base + 64 < norder) load(base + 64, Tn, mn, dn);
+  auto decide = [&](int64_t base, const Chunk& c) {
     const bool valid = base + lane < norder;
     // all TCAP bitmap words read together
     uint32_t wd[TCAP];
 #pragma unroll
-    for (int t = 0; t < TCAP; t++) wd[t] = bits[(T[t] >= 0 ? T[t] : 0) >> 5];
+    for (int t = 0; t < TCAP; t++) wd[t] = bits[(c.T[t] >= 0 ? c.T[t] : 0) >> 5];
     bool pre = !valid;
 #pragma unroll
     for (int t = 0; t < TCAP; t++)
-      if (T[t] >= 0 && ((wd[t] >> (T[t] & 31)) & 1u)) pre = true;
+      if (c.T[t] >= 0 && ((wd[t] >> (c.T[t] & 31)) & 1u)) pre = true;
     const unsigned long long rejected = __ballot(pre);
-    const unsigned long long depend = __ballot(!pre && dp != 0ull);
+    const unsigned long long depend = __ballot(!pre && c.d != 0ull);
     unsigned long long accepted = ~rejected & ~depend;
     unsigned long long todo = depend;
     if (todo) {
-      const uint32_t dlo = (uint32_t)dp, dhi = (uint32_t)(dp >> 32);
+      const uint32_t dlo = (uint32_t)c.d, dhi = (uint32_t)(c.d >> 32);
       while (todo) {
         const int l = __builtin_ctzll(todo);
         todo &= todo - 1ull;
@@ -289,14 +290,23 @@ __global__ __launch_bounds__(64) void k_mid_decide(const int32_t* mo, const int3
         if ((dl & accepted) == 0ull) accepted |= 1ull << l;
       }
     }
-    if ((accepted >> lane) & 1ull) atomicOr(&bits[mi >> 5], 1u << (mi & 31));
+    if ((accepted >> lane) & 1ull) atomicOr(&bits[c.m >> 5], 1u << (c.m & 31));
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  };
+  constexpr int DEPTH = 8;
+  Chunk c[DEPTH];
 #pragma unroll
-    for (int t = 0; t < TCAP; t++) T[t] = Tn[t];
-    mi = mn;
-    dp = dn;
+  for (int k = 0; k < DEPTH; k++) load(64 * k, c[k]);
+  for (int64_t base = 0; base < norder; base += 64 * DEPTH) {
+#pragma unroll
+    for (int k = 0; k < DEPTH; k++) {   // unrolled: every c[k] stays in registers
+      if (base + 64 * k < norder) {
+        decide(base + 64 * k, c[k]);
+        load(base + 64 * (k + DEPTH), c[k]);
+      }
+    }
   }
   for (int64_t w = lane; w < nw; w += 64) gb[w] = bits[w];
 }
