@@ -298,7 +298,10 @@ enum {
   EMIN_PROF_ALG3 = 3,       /* Alg. 3 greedy + extra points */
   EMIN_PROF_ALG4 = 4,       /* Alg. 4 mid-points */
   EMIN_PROF_VPAT = 5,       /* velocity pattern */
-  EMIN_PROF_N = 8
+  EMIN_PROF_N = 8,
+  EMIN_PROF_ONLY = 1 << 30  /* emin_profile_enable(EMIN_PROF_ONLY | (1 << kind) | ...):
+                               time only the kinds named; any other nonzero value times
+                               all kinds, 0 none */
 };
 typedef struct {
   int64_t launches;

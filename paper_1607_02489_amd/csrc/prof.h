@@ -6,7 +6,7 @@
 namespace emin {
 namespace prof {
 
-bool enabled();
+bool enabled(int kind);
 // records a start event on s; returns a token (or -1 when disabled)
 int begin(hipStream_t s, int kind, double bytes, double flops);
 void end(int token, hipStream_t s);
@@ -15,7 +15,7 @@ struct Scope {
   int tok;
   hipStream_t s;
   Scope(hipStream_t s_, int kind, double bytes, double flops = 0.0)
-      : tok(enabled() ? begin(s_, kind, bytes, flops) : -1), s(s_) {}
+      : tok(enabled(kind) ? begin(s_, kind, bytes, flops) : -1), s(s_) {}
   ~Scope() {
     if (tok >= 0) end(tok, s);
   }

@@ -15,7 +15,7 @@ struct Rec {
 };
 
 std::mutex mu;
-bool on = false;
+uint32_t kinds = 0;   // bit k: time kind k
 std::vector<Rec> recs;
 std::vector<hipEvent_t> pool;
 
@@ -32,7 +32,7 @@ hipEvent_t get_event() {
 
 }  // namespace
 
-bool enabled() { return on; }
+bool enabled(int kind) { return (kinds >> kind) & 1u; }
 
 int begin(hipStream_t s, int kind, double bytes, double flops) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -94,7 +94,9 @@ int64_t emin_release_cached(void) {
 
 emin_status emin_profile_enable(int enable) {
   std::lock_guard<std::mutex> g(emin::prof::mu);
-  emin::prof::on = enable != 0;
+  if (enable == 0) emin::prof::kinds = 0u;
+  else if (enable & EMIN_PROF_ONLY) emin::prof::kinds = (uint32_t)enable & ((1u << EMIN_PROF_N) - 1u);
+  else emin::prof::kinds = (1u << EMIN_PROF_N) - 1u;
   return EMIN_OK;
 }
 

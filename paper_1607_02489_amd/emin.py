@@ -31,6 +31,7 @@ SYMBOLS = ["emin_pattern", "emin_pattern_info", "emin_pattern_view", "emin_setup
            "emin_batch_destroy", "emin_server_create", "emin_server_submit", "emin_server_poll",
            "emin_server_wait", "emin_server_release", "emin_server_stats", "emin_server_destroy"]
 PROF_KINDS = ["spmm", "update", "spgemm", "alg3", "alg4", "vpattern", "r6", "r7"]
+EMIN_PROF_ONLY = 1 << 30
 
 
 class EminError(RuntimeError):
@@ -304,8 +305,18 @@ def sched_name(code: int) -> str:
     return "+".join(parts) + ["", " (tuned)", " (reused)", ""][(code >> 4) & 3]
 
 
-def profile_enable(on=True):
-    _check(lib().emin_profile_enable(1 if on else 0), "emin_profile_enable")
+def profile_enable(on=True, kinds=None):
+    """Time kernel classes with HIP events: all of them, or only `kinds`
+    (names of profile_collect's keys)."""
+    if not on:
+        v = 0
+    elif kinds is None:
+        v = 1
+    else:
+        v = EMIN_PROF_ONLY
+        for k in kinds:
+            v |= 1 << PROF_KINDS.index(k)
+    _check(lib().emin_profile_enable(v), "emin_profile_enable")
 
 
 def profile_collect() -> dict:
