@@ -187,7 +187,7 @@ void build_pattern(emin_pattern_t* h, const emin_system_t* sys, const emin_param
   h->BT.val = ar.alloc<double>(h->BT.nnz);
   gather_values(B.val, h->bt_src, h->BT.val, h->BT.nnz, s);
   spgemm_symbolic(B, view(h->BT), h->Z, h->zplan, s, ar, h->derr);
-  spgemm_numeric(B, view(h->BT), h->Z, h->zplan, s);
+  spgemm_numeric_aat(B, view(h->BT), h->Z, h->zplan, s);
   h->dZ = ar.alloc<double>(np);
   diag_of(view(h->Z), h->dZ, s);
   h->keep_p = ar.alloc<uint8_t>(h->Z.nnz);
@@ -245,8 +245,8 @@ void build_pattern(emin_pattern_t* h, const emin_system_t* sys, const emin_param
   Csr Pv = h->vp.N, Pp = h->cp.N;
   transpose_pattern(view(Pv), h->PvT, h->pvt_src, s, ar);
   h->PvT.val = ar.alloc<double>(h->PvT.nnz);
-  spgemm_symbolic(A, view(Pv), h->T, h->tplan, s, ar, h->derr);
-  spgemm_symbolic(view(h->PvT), view(h->T), h->Ac, h->acplan, s, ar, h->derr);
+  spgemm_symbolic(A, view(Pv), h->T, h->tplan, s, ar, h->derr, true);
+  spgemm_symbolic(view(h->PvT), view(h->T), h->Ac, h->acplan, s, ar, h->derr, true);
   h->X.nrows = (int64_t)dim * nv;
   h->X.ncols = (int64_t)dim * h->vp.n_c;
   h->X.nnz = (int64_t)dim * Pv.nnz;
@@ -260,10 +260,10 @@ void build_pattern(emin_pattern_t* h, const emin_system_t* sys, const emin_param
                                                              h->X.col, h->x_src);
   else
     HIP_OK(hipMemsetAsync(h->X.rowptr, 0, sizeof(int64_t), s));
-  spgemm_symbolic(B, view(h->X), h->U, h->uplan, s, ar, h->derr);
+  spgemm_symbolic(B, view(h->X), h->U, h->uplan, s, ar, h->derr, true);
   transpose_pattern(view(Pp), h->PpT, h->ppt_src, s, ar);
   h->PpT.val = ar.alloc<double>(h->PpT.nnz);
-  spgemm_symbolic(view(h->PpT), view(h->U), h->Bc, h->bcplan, s, ar, h->derr);
+  spgemm_symbolic(view(h->PpT), view(h->U), h->Bc, h->bcplan, s, ar, h->derr, true);
 
   // coarse descriptors: coordinates by injection, co-location map
   h->xv_c = ar.alloc<double>((size_t)h->vp.n_c * dim);
@@ -317,7 +317,7 @@ void run_setup(emin_pattern_t* h, const emin_system_t* sys, const emin_params_t*
   // already from values the caller vouches are unchanged)
   if ((prm->flags & EMIN_FLAG_PATTERN_VALUES) == 0) {
     gather_values(B.val, h->bt_src, h->BT.val, h->BT.nnz, s);
-    spgemm_numeric(B, view(h->BT), h->Z, h->zplan, s);
+    spgemm_numeric_aat(B, view(h->BT), h->Z, h->zplan, s);
     diag_of(view(h->Z), h->dZ, s);
     filter_numeric(view(h->Z), h->keep_p, h->dZ, h->Atp, s);
     symmetrize_numeric(h->Atp.val, h->mp_ia, h->mp_ib, h->Mp, s);

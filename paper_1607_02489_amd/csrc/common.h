@@ -143,7 +143,9 @@ void gather_values(const double* in, const int32_t* src, double* out, int64_t n,
 
 // C = A*B: symbolic (pattern) once, numeric any number of times.  For every
 // (i,j), c_ij accumulates a_ik*b_kj over k in ascending order of A's row,
-// each product and sum rounded separately (bit-reproducible).  The symbolic
+// each product and sum rounded separately (bit-reproducible); in a row of
+// more than SPGEMM_SPLIT entries of A, over each chunk of SPGEMM_SPLIT
+// entries so, then the chunk sums in chunk order.  The symbolic
 // pass reads back once (twice when rows exceed the window bitmap); an overflow
 // seen only by its fill pass is ORed into *derr (DERR_CAPACITY) for the caller
 // to check, or thrown at once when derr is null.
@@ -151,11 +153,32 @@ struct SpgemmPlan {
   int64_t max_row = 0;  // longest output row
   int64_t max_words = 0;  // widest column span of an output row, in 32-bit words
   int g_num = 16;       // lanes per row in the numeric kernel
+  // rows with more than SPGEMM_SPLIT entries of A (and at most SPGEMM_SPLIT_NC
+  // outputs) are summed in chunks of SPGEMM_SPLIT entries, one work item per
+  // chunk, then the chunk sums are added in chunk order
+  int64_t ntasks = 0;               // (row, chunk) work items
+  const int32_t* task_row = nullptr;
+  const int32_t* task_chunk = nullptr;
+  const int64_t* poff = nullptr;    // per row: offset of its chunk sums, -1 when not split
+  double* part = nullptr;           // chunk sums (8 bytes per value; FP32 uses the low half)
+  int64_t max_arow = 0;             // longest row of A
 };
+constexpr int SPGEMM_SPLIT = 512;
+constexpr int SPGEMM_SPLIT_NC = 1024;
+// split: rows of more than SPGEMM_SPLIT entries of A may be summed in chunks
+// (only for products whose values need not equal the single ascending chain
+// bit for bit)
 void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& plan,
-                     hipStream_t s, Arena& ar, int* derr);
+                     hipStream_t s, Arena& ar, int* derr, bool split = false);
 void spgemm_numeric(const CsrView& A, const CsrView& B, const Csr& C, const SpgemmPlan& plan,
                     hipStream_t s);
+// C = A A^T (B of the symbolic pass was A^T): when A has at most 256 rows,
+// some longer than SPGEMM_SPLIT, c_ij as the dot product of rows i and j of A
+// over their common columns in ascending order -- the same products summed in
+// the same order as spgemm_numeric, so the same bits -- with one lane per
+// output entry; otherwise spgemm_numeric
+void spgemm_numeric_aat(const CsrView& A, const CsrView& At, const Csr& C, const SpgemmPlan& plan,
+                        hipStream_t s);
 // FP32 values and accumulation (mixed-precision RAP); result to cval32, or
 // converted to FP64 into cval64 when that is non-null
 void spgemm_numeric_f32(const CsrView& A, const float* aval, const CsrView& B, const float* bval,
@@ -191,6 +214,16 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
 
 __device__ __forceinline__ double shfl_xor_d(double v, int m) {
   return __shfl_xor(v, m, 64);
+}
+
+// ballot restricted to the caller's aligned group of G lanes (bit t = lane t
+// of the group); lanes outside the group do not count
+template <int G>
+__device__ __forceinline__ uint64_t group_ballot(bool p) {
+  const uint64_t b = __ballot(p);
+  if (G == 64) return b;
+  const int base = (int)(threadIdx.x & 63) & ~(G - 1);
+  return (b >> base) & ((1ull << G) - 1ull);
 }
 
 // lexicographic (key, index) minimum across a full 64-lane wave

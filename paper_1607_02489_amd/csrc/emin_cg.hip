@@ -166,16 +166,20 @@ __device__ __forceinline__ void spmm_search_rows(int64_t lb, const int32_t* rows
 // per slot, pos(s) - s - min or 15 for "no match", packed eight to a 32-bit
 // word (plane q of the word array holds slots 8q..8q+7).  Rows that do not
 // fit are marked ineligible and keep the searching kernel.
-__global__ void k_spmm_maps(const int64_t* mrp, const int32_t* mcol, const int64_t* nrp,
-                            const int32_t* ncol, int64_t n, int64_t nnzm, int nplanes,
-                            int32_t* kofs, uint32_t* nib, uint8_t* elig) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+template <int G>
+__global__ __launch_bounds__(256) void k_spmm_maps(const int64_t* mrp, const int32_t* mcol,
+                                                  const int64_t* nrp, const int32_t* ncol,
+                                                  int64_t n, int64_t nnzm, int nplanes,
+                                                  int32_t* kofs, uint32_t* nib, uint8_t* elig) {
+  // G lanes per row i, lane t taking M entries t, t + G, ...
+  const int g = threadIdx.x / G, lane = threadIdx.x % G;
+  const int64_t i = (int64_t)blockIdx.x * (256 / G) + g;
+  if (i >= n) return;   // whole group
   const int64_t na = nrp[i], nb = nrp[i + 1];
   const int ni = (int)(nb - na);
   const int planes = ni <= 8 ? 1 : (ni <= 16 ? 2 : 4);
-  bool ok = ni <= 32 && planes <= nplanes;
-  for (int64_t e = mrp[i]; e < mrp[i + 1]; e++) {
+  bool ok = ni <= 32 && planes <= nplanes;   // this lane's entries all fit
+  for (int64_t e = mrp[i] + lane; e < mrp[i + 1]; e += G) {
     const int32_t k = mcol[e];
     const int64_t ka = nrp[k], kb = nrp[k + 1];
     uint32_t w[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
@@ -216,7 +220,8 @@ __global__ void k_spmm_maps(const int64_t* mrp, const int32_t* mcol, const int64
     kofs[e] = (int32_t)(ok ? ko : 0);
     for (int q = 0; q < nplanes; q++) nib[(int64_t)q * nnzm + e] = w[q];
   }
-  elig[i] = ok ? 1 : 0;
+  const bool all = group_ballot<G>(!ok) == 0ull;
+  if (lane == 0) elig[i] = all ? 1 : 0;
 }
 
 // Masked product on the intersection maps: G lanes (G >= |N_i|) own row i,
@@ -766,9 +771,18 @@ void EminWork::make_bins(const Csr& M, const int64_t* nrp, const int32_t* ncol, 
   kofs = ar.alloc<int32_t>(M.nnz);
   nib = ar.alloc<uint32_t>((size_t)M.nnz * nplanes);
   uint8_t* elig = ar.alloc<uint8_t>(n);
-  if (n)
-    k_spmm_maps<<<nblocks(n, 256), 256, 0, s>>>(M.rowptr, M.col, nrp, ncol, n, M.nnz, nplanes,
-                                                kofs, nib, elig);
+  if (n) {
+    const double avg = (double)M.nnz / (double)n;
+    int g = 4;
+    while (g < 64 && g < avg) g <<= 1;
+    switch (g) {
+      case 4: k_spmm_maps<4><<<nblocks(n, 64), 256, 0, s>>>(M.rowptr, M.col, nrp, ncol, n, M.nnz, nplanes, kofs, nib, elig); break;
+      case 8: k_spmm_maps<8><<<nblocks(n, 32), 256, 0, s>>>(M.rowptr, M.col, nrp, ncol, n, M.nnz, nplanes, kofs, nib, elig); break;
+      case 16: k_spmm_maps<16><<<nblocks(n, 16), 256, 0, s>>>(M.rowptr, M.col, nrp, ncol, n, M.nnz, nplanes, kofs, nib, elig); break;
+      case 32: k_spmm_maps<32><<<nblocks(n, 8), 256, 0, s>>>(M.rowptr, M.col, nrp, ncol, n, M.nnz, nplanes, kofs, nib, elig); break;
+      default: k_spmm_maps<64><<<nblocks(n, 4), 256, 0, s>>>(M.rowptr, M.col, nrp, ncol, n, M.nnz, nplanes, kofs, nib, elig); break;
+    }
+  }
   tuned = 0;
   opts = SchedOpts{};
   if (!tune || n == 0) {

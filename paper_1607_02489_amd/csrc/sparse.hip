@@ -126,13 +126,6 @@ static int lanes_for(const CsrView& A) {
   return g;
 }
 
-template <int G>
-__device__ __forceinline__ uint64_t group_ballot(bool p) {
-  const uint64_t b = __ballot(p);
-  if (G == 64) return b;
-  const int base = (int)(threadIdx.x & 63) & ~(G - 1);
-  return (b >> base) & ((1ull << G) - 1ull);
-}
 
 #define ROWS_DISPATCH(g, KERNEL, n, s, ...)                                              \
   do {                                                                                   \
@@ -616,6 +609,16 @@ __device__ __forceinline__ void group_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// split rows of a numeric product (see SpgemmPlan)
+template <class TV>
+struct SplitArgsT {
+  const int32_t* trow = nullptr;
+  const int32_t* tchunk = nullptr;
+  const int64_t* poff = nullptr;
+  TV* part = nullptr;
+  int64_t ntasks = 0;
+};
+
 // acc[slot] += v, in the wave's issue order.  FP64: an LDS atomic add (no
 // return, so consecutive adds do not wait for each other).  FP32: a plain
 // read-add-write (measured faster than the LDS float atomic here); a wave's
@@ -642,7 +645,8 @@ __global__ __launch_bounds__(256) void k_spgemm_num(const int64_t* arp, const in
                                                    const TV* aval, const int64_t* brp,
                                                    const int32_t* bcol, const TV* bval,
                                                    const int64_t* crp, const int32_t* ccol,
-                                                   TO* cval, int64_t n, int cap, int iw) {
+                                                   TO* cval, int64_t n, int cap, int iw,
+                                                   SplitArgsT<TV> sp) {
   extern __shared__ uint32_t lds_words[];
   constexpr int NG = 256 / G;
   constexpr int UF = G < 16 ? G : 16;   // A entries per batch when B rows fit the group
@@ -652,8 +656,26 @@ __global__ __launch_bounds__(256) void k_spgemm_num(const int64_t* arp, const in
   TV* acc = reinterpret_cast<TV*>(lds_words + (size_t)NG * iw) + (size_t)g * cap;
   // (measured: the dispatch order beats the XCD-contiguous one here, although
   // the latter raises the L2 hit rate)
-  const int64_t row = (int64_t)blockIdx.x * NG + g;
-  if (row >= n) return;
+  // row mode: one output row per group (split rows are left to the chunk
+  // items); chunk mode (sp.trow set): one chunk of a split row per group,
+  // its sums written to sp.part
+  int64_t row, ea, eb;
+  TV* pout = nullptr;
+  if (sp.trow) {
+    const int64_t w = (int64_t)blockIdx.x * NG + g;
+    if (w >= sp.ntasks) return;
+    row = sp.trow[w];
+    const int64_t ch = sp.tchunk[w];
+    ea = arp[row] + ch * SPGEMM_SPLIT;
+    eb = ea + SPGEMM_SPLIT < arp[row + 1] ? ea + SPGEMM_SPLIT : arp[row + 1];
+    pout = sp.part + sp.poff[row] + ch * (crp[row + 1] - crp[row]);
+  } else {
+    row = (int64_t)blockIdx.x * NG + g;
+    if (row >= n) return;
+    if (sp.poff && sp.poff[row] >= 0) return;
+    ea = arp[row];
+    eb = arp[row + 1];
+  }
   const int64_t c0 = crp[row];
   const int nc = (int)(crp[row + 1] - c0);
   if (nc > cap || nc == 0) return;  // long rows: k_spgemm_num_long
@@ -731,7 +753,6 @@ __global__ __launch_bounds__(256) void k_spgemm_num(const int64_t* arp, const in
     }
     return lo;
   };
-  const int64_t ea = arp[row], eb = arp[row + 1];
   // A entries of the next chunk are loaded while the current one is summed
   int32_t kk_n = 0;
   TV av_n = TV(0);
@@ -815,7 +836,30 @@ __global__ __launch_bounds__(256) void k_spgemm_num(const int64_t* arp, const in
     }
   }
   group_sync_lds<G>();
-  for (int t = lane; t < nc; t += G) cval[c0 + t] = (TO)acc[t];
+  if (pout) {
+    for (int t = lane; t < nc; t += G) pout[t] = acc[t];
+  } else {
+    for (int t = lane; t < nc; t += G) cval[c0 + t] = (TO)acc[t];
+  }
+}
+
+// split rows: c_it = the chunk sums of slot t added in chunk order (one
+// group of 64 lanes per split row, found as its chunk-0 work item)
+template <class TV, class TO>
+__global__ __launch_bounds__(256) void k_spgemm_combine(const int64_t* arp, const int64_t* crp,
+                                                       SplitArgsT<TV> sp, TO* cval) {
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (w >= sp.ntasks || sp.tchunk[w] != 0) return;
+  const int64_t row = sp.trow[w];
+  const int64_t c0 = crp[row], nc = crp[row + 1] - c0;
+  const int64_t nch = (arp[row + 1] - arp[row] + SPGEMM_SPLIT - 1) / SPGEMM_SPLIT;
+  const TV* p = sp.part + sp.poff[row];
+  for (int64_t t = lane; t < nc; t += 64) {
+    TV v = p[t];
+    for (int64_t c = 1; c < nch; c++) v = v + p[c * nc + t];
+    cval[c0 + t] = (TO)v;
+  }
 }
 
 // fallback for rows longer than the LDS capacity: one lane per row, the
@@ -873,31 +917,88 @@ __global__ __launch_bounds__(256) void k_row_len_max(const int64_t* rp, int64_t 
 
 // longest row and widest window of a symbolic product: block maxima, one
 // atomic pair per block
+// chunks of a row summed apart (0: the row is not split)
+__device__ __forceinline__ int64_t split_chunks(int64_t lena, int64_t nc) {
+  return (lena > SPGEMM_SPLIT && nc > 0 && nc <= SPGEMM_SPLIT_NC)
+             ? (lena + SPGEMM_SPLIT - 1) / SPGEMM_SPLIT : 0;
+}
+
+// mx[0] longest row, mx[1] widest window, mx[4] longest row of A (block
+// maxima, one atomic each per block); mx[2] split work items and mx[3]
+// chunk-sum values (block sums; arp null: no split)
 __global__ __launch_bounds__(256) void k_sym_maxima(const int64_t* rp, const int32_t* rwords,
+                                                   const int64_t* arp, const int64_t* aall,
                                                    int64_t n, unsigned long long* mx) {
-  __shared__ unsigned long long part[2][4];
+  __shared__ unsigned long long part[5][4];
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  unsigned long long a = i < n ? (unsigned long long)(rp[i + 1] - rp[i]) : 0ull;
+  const int64_t nc = i < n ? rp[i + 1] - rp[i] : 0;
+  unsigned long long la = i < n ? (unsigned long long)(aall[i + 1] - aall[i]) : 0ull;
+  unsigned long long a = (unsigned long long)nc;
   unsigned long long b = i < n ? (unsigned long long)rwords[i] : 0ull;
+  const int64_t ch = (i < n && arp) ? split_chunks(arp[i + 1] - arp[i], nc) : 0;
+  unsigned long long c = (unsigned long long)ch, d = (unsigned long long)(ch * nc);
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) {
     const unsigned long long oa = __shfl_xor(a, m, 64), ob = __shfl_xor(b, m, 64);
     a = oa > a ? oa : a;
     b = ob > b ? ob : b;
+    c += __shfl_xor(c, m, 64);
+    d += __shfl_xor(d, m, 64);
+    const unsigned long long ol = __shfl_xor(la, m, 64);
+    la = ol > la ? ol : la;
   }
   if ((threadIdx.x & 63) == 0) {
     part[0][threadIdx.x >> 6] = a;
     part[1][threadIdx.x >> 6] = b;
+    part[2][threadIdx.x >> 6] = c;
+    part[3][threadIdx.x >> 6] = d;
+    part[4][threadIdx.x >> 6] = la;
   }
   __syncthreads();
   if (threadIdx.x < 2) {
     unsigned long long v = part[threadIdx.x][0];
     for (int w = 1; w < 4; w++) v = part[threadIdx.x][w] > v ? part[threadIdx.x][w] : v;
     atomicMax(&mx[threadIdx.x], v);
+  } else if (threadIdx.x < 4) {
+    const unsigned long long v = part[threadIdx.x][0] + part[threadIdx.x][1] +
+                                 part[threadIdx.x][2] + part[threadIdx.x][3];
+    if (v) atomicAdd(&mx[threadIdx.x], v);
+  } else if (threadIdx.x == 4) {
+    unsigned long long v = part[4][0];
+    for (int w = 1; w < 4; w++) v = part[4][w] > v ? part[4][w] : v;
+    atomicMax(&mx[4], v);
   }
 }
 
-// output size, count-pass overflow flag, longest row and widest window
+// per row: its chunk count and chunk-sum values (scanned afterwards)
+__global__ void k_split_counts(const int64_t* rp, const int64_t* arp, int64_t n, int64_t* ch,
+                               int64_t* vals) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t nc = rp[i + 1] - rp[i];
+  const int64_t c = split_chunks(arp[i + 1] - arp[i], nc);
+  ch[i] = c;
+  vals[i] = c * nc;
+}
+
+__global__ void k_split_fill(const int64_t* rp, const int64_t* ch_incl, const int64_t* val_incl,
+                             int64_t n, int32_t* trow, int32_t* tchunk, int64_t* poff) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t c1 = ch_incl[i], c0 = i ? ch_incl[i - 1] : 0;
+  if (c1 == c0) {
+    poff[i] = -1;
+    return;
+  }
+  poff[i] = val_incl[i] - (c1 - c0) * (rp[i + 1] - rp[i]);
+  for (int64_t c = c0; c < c1; c++) {
+    trow[c] = (int32_t)i;
+    tchunk[c] = (int32_t)(c - c0);
+  }
+}
+
+// output size, count-pass overflow flag, longest row, widest window, split
+// work items and chunk-sum values
 __global__ void k_sym_summary(const int64_t* rp, int64_t n, const int* lerr,
                               const unsigned long long* mx, int64_t* out) {
   if (threadIdx.x == 0) {
@@ -905,6 +1006,9 @@ __global__ void k_sym_summary(const int64_t* rp, int64_t n, const int* lerr,
     out[1] = lerr[0];
     out[2] = (int64_t)mx[0];
     out[3] = (int64_t)mx[1];
+    out[4] = (int64_t)mx[2];
+    out[5] = (int64_t)mx[3];
+    out[6] = (int64_t)mx[4];
   }
 }
 
@@ -1107,7 +1211,7 @@ static void launch_sym_rows(const int32_t* rows, int64_t nrows, const CsrView& A
 }
 
 void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& plan,
-                     hipStream_t s, Arena& ar, int* derr) {
+                     hipStream_t s, Arena& ar, int* derr, bool split) {
   if (A.ncols != B.nrows) throw Error(EMIN_ERR_SHAPE, "spgemm: inner dimensions differ");
   C.nrows = A.nrows;
   C.ncols = B.ncols;
@@ -1150,18 +1254,39 @@ void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& pla
   // one read-back: output size, count-pass overflow, longest output row
   HIP_OK(hipMemsetAsync(C.rowptr, 0, sizeof(int64_t), s));
   scan_inclusive(C.rowptr + 1, C.nrows, s, ar);
-  unsigned long long* mx = ar.alloc<unsigned long long>(2);
-  int64_t* sm = ar.alloc<int64_t>(4);
-  HIP_OK(hipMemsetAsync(mx, 0, 2 * sizeof(unsigned long long), s));
-  if (C.nrows) k_sym_maxima<<<nblocks(C.nrows, 256), 256, 0, s>>>(C.rowptr, rwords, C.nrows, mx);
+  unsigned long long* mx = ar.alloc<unsigned long long>(5);
+  int64_t* sm = ar.alloc<int64_t>(7);
+  HIP_OK(hipMemsetAsync(mx, 0, 5 * sizeof(unsigned long long), s));
+  if (C.nrows)
+    k_sym_maxima<<<nblocks(C.nrows, 256), 256, 0, s>>>(
+        C.rowptr, rwords, split ? A.rowptr : nullptr, A.rowptr, C.nrows, mx);
   k_sym_summary<<<1, 64, 0, s>>>(C.rowptr, C.nrows, lerr, mx, sm);
-  int64_t hs[4];
+  int64_t hs[7];
   HIP_OK(hipMemcpyAsync(hs, sm, sizeof(hs), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
   C.nnz = hs[0];
   if (hs[1]) throw Error(EMIN_ERR_CAPACITY, "spgemm: output row exceeds the LDS table");
   plan.max_row = hs[2];
   plan.max_words = hs[3];
+  plan.ntasks = hs[4];
+  plan.max_arow = hs[6];
+  if (plan.ntasks) {
+    // long rows: work items (row, chunk) and the offsets of their chunk sums
+    const int64_t n = C.nrows;
+    int64_t* ch = ar.alloc<int64_t>(n);
+    int64_t* vals = ar.alloc<int64_t>(n);
+    int32_t* trow = ar.alloc<int32_t>(plan.ntasks);
+    int32_t* tchunk = ar.alloc<int32_t>(plan.ntasks);
+    int64_t* poff = ar.alloc<int64_t>(n);
+    k_split_counts<<<nblocks(n, 256), 256, 0, s>>>(C.rowptr, A.rowptr, n, ch, vals);
+    scan_inclusive(ch, n, s, ar);
+    scan_inclusive(vals, n, s, ar);
+    k_split_fill<<<nblocks(n, 256), 256, 0, s>>>(C.rowptr, ch, vals, n, trow, tchunk, poff);
+    plan.task_row = trow;
+    plan.task_chunk = tchunk;
+    plan.poff = poff;
+    plan.part = ar.alloc<double>(hs[5]);
+  }
   C.col = ar.alloc<int32_t>(C.nnz);
   C.val = ar.alloc<double>(C.nnz);
   // the window fill skips the wide rows; the hash kernels fill those (the
@@ -1190,13 +1315,29 @@ void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& pla
 
 template <int G, class TV, class TO>
 static void launch_num(const CsrView& A, const TV* aval, const CsrView& B, const TV* bval,
-                       const Csr& C, TO* cval, int cap, int iw, hipStream_t s) {
+                       const Csr& C, TO* cval, int cap, int iw, const SpgemmPlan& plan,
+                       hipStream_t s) {
   constexpr int NG = 256 / G;
   const size_t lds = (size_t)NG * ((size_t)iw * sizeof(uint32_t) + cap * sizeof(TV));
   HIP_OK(hipFuncSetAttribute((const void*)k_spgemm_num<G, TV, TO>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  SplitArgsT<TV> rows_only;
+  rows_only.poff = plan.ntasks ? plan.poff : nullptr;
   k_spgemm_num<G, TV, TO><<<nblocks(A.nrows, NG), 256, lds, s>>>(
-      A.rowptr, A.col, aval, B.rowptr, B.col, bval, C.rowptr, C.col, cval, A.nrows, cap, iw);
+      A.rowptr, A.col, aval, B.rowptr, B.col, bval, C.rowptr, C.col, cval, A.nrows, cap, iw,
+      rows_only);
+  if (plan.ntasks) {
+    SplitArgsT<TV> sp;
+    sp.trow = plan.task_row;
+    sp.tchunk = plan.task_chunk;
+    sp.poff = plan.poff;
+    sp.part = reinterpret_cast<TV*>(plan.part);
+    sp.ntasks = plan.ntasks;
+    k_spgemm_num<G, TV, TO><<<nblocks(plan.ntasks, NG), 256, lds, s>>>(
+        A.rowptr, A.col, aval, B.rowptr, B.col, bval, C.rowptr, C.col, cval, A.nrows, cap, iw,
+        sp);
+    k_spgemm_combine<TV, TO><<<nblocks(plan.ntasks, 4), 256, 0, s>>>(A.rowptr, C.rowptr, sp, cval);
+  }
 }
 
 template <class TV, class TO>
@@ -1223,15 +1364,154 @@ static void numeric_any(const CsrView& A, const TV* aval, const CsrView& B, cons
   iw = std::max<int64_t>(iw, cap);
   iw = (iw + 1) & ~int64_t(1);
   switch (g) {
-    case 4: launch_num<4>(A, aval, B, bval, C, cval, cap, (int)iw, s); break;
-    case 8: launch_num<8>(A, aval, B, bval, C, cval, cap, (int)iw, s); break;
-    case 16: launch_num<16>(A, aval, B, bval, C, cval, cap, (int)iw, s); break;
-    case 32: launch_num<32>(A, aval, B, bval, C, cval, cap, (int)iw, s); break;
-    default: launch_num<64>(A, aval, B, bval, C, cval, cap, (int)iw, s); break;
+    case 4: launch_num<4>(A, aval, B, bval, C, cval, cap, (int)iw, plan, s); break;
+    case 8: launch_num<8>(A, aval, B, bval, C, cval, cap, (int)iw, plan, s); break;
+    case 16: launch_num<16>(A, aval, B, bval, C, cval, cap, (int)iw, plan, s); break;
+    case 32: launch_num<32>(A, aval, B, bval, C, cval, cap, (int)iw, plan, s); break;
+    default: launch_num<64>(A, aval, B, bval, C, cval, cap, (int)iw, plan, s); break;
   }
   if (plan.max_row > cap)
     k_spgemm_num_long<TV, TO><<<nblocks(A.nrows, 64), 64, 0, s>>>(
         A.rowptr, A.col, aval, B.rowptr, B.col, bval, C.rowptr, C.col, cval, A.nrows, cap);
+}
+
+// C = A A^T by dot products (see spgemm_numeric_aat): one wave per output row
+// i; row i of A staged in LDS (its values, and a flat or two-level bitmap of
+// its columns giving the position of column k, as in k_spgemm_num); lane t
+// takes the output entries t, t + 64, ...: c_ij walks row j of A in column
+// order and adds a_ik * a_jk for the columns present in row i.
+__global__ __launch_bounds__(64) void k_spgemm_aat(const int64_t* arp, const int32_t* acol,
+                                                  const double* aval, const int64_t* crp,
+                                                  const int32_t* ccol, double* cval, int64_t n,
+                                                  int iw) {
+  extern __shared__ uint32_t lds_words[];
+  uint32_t* idx = lds_words;                                  // iw words (iw even)
+  double* av = reinterpret_cast<double*>(lds_words + iw);     // row i's values
+  const int lane = threadIdx.x;
+  const int64_t row = blockIdx.x;
+  if (row >= n) return;
+  const int64_t c0 = crp[row];
+  const int nc = (int)(crp[row + 1] - c0);
+  const int64_t a0 = arp[row];
+  const int la = (int)(arp[row + 1] - a0);
+  if (nc == 0) return;
+  if (la == 0) {
+    for (int t = lane; t < nc; t += 64) cval[c0 + t] = 0.0;
+    return;
+  }
+  const int32_t klo = acol[a0], khi = acol[a0 + la - 1];
+  const int64_t nw = (((int64_t)khi - klo) >> 5) + 1, nw1 = (nw + 31) >> 5;
+  const bool flat = 2 * nw <= iw;   // else two-level (sized to fit by the host)
+  uint32_t* cw = idx + 2 * nw1;
+  for (int t = lane; t < la; t += 64) av[t] = aval[a0 + t];
+  if (flat) {
+    for (int64_t t = lane; t < nw; t += 64) idx[2 * t] = 0u;
+  } else {
+    for (int64_t t = lane; t < nw1; t += 64) idx[2 * t] = 0u;
+    for (int t = lane; t < la; t += 64) cw[2 * t] = 0u;
+  }
+  group_sync_lds<64>();
+  if (flat) {
+    for (int t = lane; t < la; t += 64) {
+      const int r = acol[a0 + t] - klo;
+      const int w = r >> 5;
+      atomicOr(&idx[2 * w], 1u << (r & 31));
+      if (t == 0 || ((acol[a0 + t - 1] - klo) >> 5) != w) idx[2 * w + 1] = (uint32_t)t;
+    }
+  } else {
+    for (int t = lane; t < la; t += 64) {
+      const int w = (acol[a0 + t] - klo) >> 5;
+      atomicOr(&idx[2 * (w >> 5)], 1u << (w & 31));
+    }
+    group_sync_lds<64>();
+    int run = 0;
+    for (int64_t s0 = 0; s0 < nw1; s0 += 64) {
+      const int64_t sw = s0 + lane;
+      const int c = sw < nw1 ? __popc(idx[2 * sw]) : 0;
+      int incl = c;
+#pragma unroll
+      for (int m = 1; m < 64; m <<= 1) {
+        const int o = __shfl_up(incl, m, 64);
+        if (lane >= m) incl += o;
+      }
+      if (sw < nw1) idx[2 * sw + 1] = (uint32_t)(run + incl - c);
+      run += __shfl(incl, 63, 64);
+    }
+    group_sync_lds<64>();
+    for (int t = lane; t < la; t += 64) {
+      const int r = acol[a0 + t] - klo;
+      const int w = r >> 5, sw = w >> 5;
+      const int d = (int)idx[2 * sw + 1] + __popc(idx[2 * sw] & ((1u << (w & 31)) - 1u));
+      atomicOr(&cw[2 * d], 1u << (r & 31));
+      if (t == 0 || ((acol[a0 + t - 1] - klo) >> 5) != w) cw[2 * d + 1] = (uint32_t)t;
+    }
+  }
+  group_sync_lds<64>();
+  // position of column k in row i, or -1
+  auto pos_of = [&](int32_t k) -> int {
+    if (k < klo || k > khi) return -1;
+    const int r = k - klo, w = r >> 5;
+    const uint32_t bit = 1u << (r & 31);
+    uint2 e;
+    if (flat) {
+      e = *reinterpret_cast<const uint2*>(idx + 2 * w);
+    } else {
+      const uint2 e1 = *reinterpret_cast<const uint2*>(idx + 2 * (w >> 5));
+      const uint32_t wb = 1u << (w & 31);
+      if (!(e1.x & wb)) return -1;
+      const int d = (int)e1.y + __popc(e1.x & (wb - 1u));
+      e = *reinterpret_cast<const uint2*>(cw + 2 * d);
+    }
+    if (!(e.x & bit)) return -1;
+    return (int)e.y + __popc(e.x & (bit - 1u));
+  };
+  for (int t = lane; t < nc; t += 64) {
+    const int32_t j = ccol[c0 + t];
+    const int64_t b0 = arp[j], b1 = arp[j + 1];
+    double acc = 0.0;
+    int64_t e = b0;
+    for (; e + 4 <= b1; e += 4) {
+      int32_t k[4];
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        k[u] = acol[e + u];
+        v[u] = aval[e + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const int p = pos_of(k[u]);
+        if (p >= 0) acc = acc + av[p] * v[u];
+      }
+    }
+    for (; e < b1; e++) {
+      const int p = pos_of(acol[e]);
+      if (p >= 0) acc = acc + av[p] * aval[e];
+    }
+    cval[c0 + t] = acc;
+  }
+}
+
+void spgemm_numeric_aat(const CsrView& A, const CsrView& At, const Csr& C, const SpgemmPlan& plan,
+                        hipStream_t s) {
+  // index words for the two-level form of the longest row, the flat one
+  // where it fits in the same room; with the values, within ~150 KiB
+  const int64_t nw1 = ((A.ncols + 31) / 32 + 31) / 32;
+  int64_t iw = 2 * (nw1 + plan.max_arow);
+  iw = (iw + 1) & ~int64_t(1);
+  const size_t lds = (size_t)iw * 4 + (size_t)plan.max_arow * 8;
+  // (measured: with more than a few hundred rows the row-parallel kernel is
+  // faster; the dot products pay off where few long rows leave it idle)
+  if (plan.max_arow <= SPGEMM_SPLIT || A.nrows > 256 || lds > 150 * 1024 || A.nrows == 0 ||
+      C.nnz == 0) {
+    spgemm_numeric(A, At, C, plan, s);
+    return;
+  }
+  prof::Scope ps(s, EMIN_PROF_SPGEMM, 12.0 * (double)(A.nnz + At.nnz + C.nnz));
+  HIP_OK(hipFuncSetAttribute((const void*)k_spgemm_aat,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  k_spgemm_aat<<<(unsigned)A.nrows, 64, lds, s>>>(A.rowptr, A.col, A.val, C.rowptr, C.col, C.val,
+                                                  A.nrows, (int)iw);
 }
 
 void spgemm_numeric(const CsrView& A, const CsrView& B, const Csr& C, const SpgemmPlan& plan,

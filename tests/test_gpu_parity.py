@@ -160,6 +160,22 @@ def test_stokes3d_16_bitexact():
     compare_level(gpu_level(s, iters=5, **kw), O.level(s, iters=5, **kw))
 
 
+def test_stokes3d_level1_long_rows():
+    """Level 1 of a 3-D Stokes hierarchy: its divergence rows are longer than
+    the chunk length of the sparse products (512 entries of A), so the
+    Galerkin products sum those rows in chunks and add the chunk sums in
+    order; the level must still match the oracle run on its own input."""
+    s = synth.make_system(3, 24, jitter=0.05, seed=3)
+    kw = dict(tau1_v=0.038, tau1_p=0.04)
+    say(f"[gpu] stokes3d 24^3 level 0: dofs={s.dofs}")
+    g0 = gpu_level(s, iters=5, **kw)
+    c = host_coarse(g0, 3)
+    lens = np.diff(c.Bdiv.rowptr)
+    say(f"[gpu] level 1: dofs={c.dofs}, longest divergence row {int(lens.max())}")
+    assert lens.max() > 512   # the chunked path is taken
+    compare_level(gpu_level(c, iters=5, **kw), O.level(c, iters=5, **kw))
+
+
 def _bfs_dist(rp, col, src, maxd):
     dist = {int(src): 0}
     front = [int(src)]
