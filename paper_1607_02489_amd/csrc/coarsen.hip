@@ -67,9 +67,9 @@ __global__ __launch_bounds__(64 * BW) void k_balls(const int64_t* grp, const int
     hs[bhash((uint32_t)v0) & (BHASH - 1)] = (int32_t)v0;
     nb_all[w] = 1;
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   int ls = 0, le = 1;
   int ends[5] = {1, 1, 1, 1, 1};
   bool bad = false;
@@ -94,9 +94,9 @@ __global__ __launch_bounds__(64 * BW) void k_balls(const int64_t* grp, const int
         }
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     ls = le;
     le = min(nb_all[w], BLIST);
     ends[L + 1] = le;
@@ -142,18 +142,18 @@ __global__ __launch_bounds__(64 * BWIN_W) void k_balls_win(const int64_t* grp,
   int32_t* list = reinterpret_cast<int32_t*>(bits + nwords);
   const int64_t lo = v0 - 4 * bw > 0 ? v0 - 4 * bw : 0;
   for (int t = lane; t < nwords; t += 64) bits[t] = 0u;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   if (lane == 0) {
     const int64_t o = v0 - lo;
     bits[o >> 5] |= 1u << (o & 31);
     list[0] = (int32_t)v0;
     cnt[w] = 1;
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   int ls = 0, le = 1;
   int ends[5] = {1, 1, 1, 1, 1};
   for (int L = 0; L < 4; L++) {
@@ -176,9 +176,9 @@ __global__ __launch_bounds__(64 * BWIN_W) void k_balls_win(const int64_t* grp,
         }
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const int c = cnt[w];
     if (c > lcap) {
       if (lane == 0) atomicOr(flags, 1);

@@ -226,8 +226,8 @@ __global__ void k_cbits_expand(const uint32_t* gb, int64_t n, uint8_t* cbar,
 // The ordered pass of Alg. 4 in one wave, 64 entries per chunk.  An entry is
 // rejected when some vertex of its T is in C-bar from an earlier chunk (LDS
 // bitmap) or is the m of an earlier accepted entry of its own chunk (its
-// dependence mask).  Entries without a dependence are decided at once; only
-// those with one are resolved in lane order, with scalar code.
+// dependence mask).  Entries without a dependence are decided at once; those
+// with one are resolved in rounds along their dependence chains.
 __global__ __launch_bounds__(64) void k_mid_decide(const int32_t* mo, const int32_t* to,
                                                    const unsigned long long* dep, int64_t norder,
                                                    int64_t n, uint32_t* gb) {
@@ -247,9 +247,9 @@ __global__ __launch_bounds__(64) void k_mid_decide(const int32_t* mo, const int3
       if (w < nw) bits[w] = v[j];
     }
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   // software pipeline: each chunk's entries are loaded DEPTH chunks ahead
   // (a chunk's work is far shorter than a memory round trip)
   struct Chunk {
@@ -278,22 +278,22 @@ __global__ __launch_bounds__(64) void k_mid_decide(const int32_t* mo, const int3
     const unsigned long long rejected = __ballot(pre);
     const unsigned long long depend = __ballot(!pre && c.d != 0ull);
     unsigned long long accepted = ~rejected & ~depend;
-    unsigned long long todo = depend;
-    if (todo) {
-      const uint32_t dlo = (uint32_t)c.d, dhi = (uint32_t)(c.d >> 32);
-      while (todo) {
-        const int l = __builtin_ctzll(todo);
-        todo &= todo - 1ull;
-        const unsigned long long dl =
-            ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)dhi, l) << 32) |
-            (uint32_t)__builtin_amdgcn_readlane((int)dlo, l);
-        if ((dl & accepted) == 0ull) accepted |= 1ull << l;
-      }
+    // entries with a dependence (only on earlier lanes) decide in rounds: an
+    // entry whose dependences are all decided is accepted iff none of them
+    // was; the lowest undecided entry can always decide, and each decision
+    // is the one the lane-order pass would make
+    unsigned long long decided = ~depend;
+    while (decided != ~0ull) {
+      const bool mine = !((decided >> lane) & 1ull);
+      const bool can = mine && (c.d & ~decided) == 0ull;
+      const bool acc = can && (c.d & accepted) == 0ull;
+      accepted |= __ballot(acc);
+      decided |= __ballot(can);
     }
     if ((accepted >> lane) & 1ull) atomicOr(&bits[c.m >> 5], 1u << (c.m & 31));
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   };
   constexpr int DEPTH = 8;
   Chunk c[DEPTH];

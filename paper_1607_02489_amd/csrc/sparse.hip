@@ -575,9 +575,9 @@ __global__ __launch_bounds__(BS) void k_spgemm_sym(const int32_t* rows, int64_t 
     const int32_t key = keys[t];
     if (key >= 0) dense[atomicAdd(&cnt2[g], 1)] = key;
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const int u = cnt[g];
   const int64_t base = crp[row];
   for (int t = lane; t < u; t += G) {
@@ -602,11 +602,14 @@ __global__ __launch_bounds__(BS) void k_spgemm_sym(const int32_t* rows, int64_t 
 // row land in distinct slots, and a wave's LDS operations complete in issue
 // order, so every c_ij still receives its products in ascending order of A's
 // row, each product and each sum rounded separately.
+// orders a group's LDS writes before its later reads: the group lies inside
+// one wave, whose LDS operations complete in issue order, so a wave-scope
+// fence (a compiler barrier, no wait on outstanding global loads) suffices
 template <int G>
 __device__ __forceinline__ void group_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // split rows of a numeric product (see SpgemmPlan)
@@ -1133,9 +1136,9 @@ __global__ __launch_bounds__(256) void k_spgemm_win(int64_t n, const int64_t* ar
     return;
   }
   for (int t = lane; t < nw; t += G) words[t] = 0u;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   for (int64_t e = ea + lane; e < eb; e += G) {
     const int32_t k = acol[e];
     const int64_t b0 = brp[k], b1 = brp[k + 1];
@@ -1148,9 +1151,9 @@ __global__ __launch_bounds__(256) void k_spgemm_win(int64_t n, const int64_t* ar
         if (j[q] >= 0) atomicOr(&words[j[q] >> 5], 1u << (j[q] & 31));
     }
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   // lane l owns words [l*wpl, (l+1)*wpl)
   const int wpl = (nw + G - 1) / G;
   const int w0 = lane * wpl, w1 = (w0 + wpl) < nw ? (w0 + wpl) : nw;

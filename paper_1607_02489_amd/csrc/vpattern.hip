@@ -46,9 +46,9 @@ __global__ __launch_bounds__(64 * VB_WAVES) void k_vbfs(const int64_t* grp, cons
     hs[vhash((uint32_t)c) & (VHASH - 1)] = c;
     nb_all[w] = 1;
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   int ls = 0, le = 1;
   bool bad = false;
   for (int L = 0; L < 3; L++) {
@@ -72,9 +72,9 @@ __global__ __launch_bounds__(64 * VB_WAVES) void k_vbfs(const int64_t* grp, cons
         }
       }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     ls = le;
     le = min(nb_all[w], VBALL);
   }
