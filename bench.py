@@ -30,7 +30,8 @@ WORKLOADS = {
     "oseen2d_256": dict(make=lambda s: s.oseen2d(256), nlevels=4, iters=5, tau1_v=0.06,
                         tau1_p=0.06, mixed=False, min_dofs=0,
                         desc="2-D Oseen Q2-Q1 256x256, Re=100, 4-level FP64 hierarchy, 5 EMIN CG steps per level"),
-    # 3-D Stokes 48^3 Q2-Q1, jitter 0.05h; 3-D drop tolerances
+    # 3-D Stokes 48^3 Q2-Q1, jitter 0.05h; drop tolerances for the 27-point 3-D
+    # stencils (tau1_v = 0.038 sits in the gap of the velocity entry ratios)
     "stokes3d_48": dict(make=lambda s: s.stokes3d(48), nlevels=4, iters=5, tau1_v=0.038,
                         tau1_p=0.04, mixed=False, min_dofs=1000,
                         desc="3-D Stokes Q2-Q1 48^3, jitter 0.05h, hierarchy to <=1000 dofs, 5 EMIN CG steps per level"),
@@ -410,8 +411,9 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU only: the setup has no multi-GPU path (its numeric "
+              "phase would shard by row slabs with halo exchanges; the greedy coarsening does "
+              "not shard without changing the result).", file=sys.stderr)
         sys.exit(2)
 
     import torch

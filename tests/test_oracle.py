@@ -283,7 +283,7 @@ def test_emin_constraint_and_monotone(oracle_lib, case):
     Wv = (~L.dir).astype(np.float64)
     Pv = L.Pv.to_scipy()
     Pp = L.Pp.to_scipy()
-    # the benchmark spec: |P W_c - W| / |W| <= 1e-12
+    # constraint P W_c = W holds exactly: |P W_c - W| / |W| <= 1e-12
     assert np.linalg.norm(Pv @ Wv[L.is_cv] - Wv) / np.linalg.norm(Wv) <= 1e-12
     assert np.linalg.norm(Pp @ np.ones(Pp.shape[1]) - 1) / np.sqrt(s.n_p) <= 1e-12
     # energy decreases at every CG step
