@@ -650,6 +650,18 @@ __global__ void k_compact(const int64_t* incl, const uint8_t* st, int64_t n, int
   if (c) list[id] = (int32_t)i;
 }
 
+// meta[0..2] (|C|, |C| of Alg. 3, error bits) and the sizes of N^(p) and S
+__global__ void k_coarse_summary(const int32_t* meta, const int64_t* nn, const int64_t* sn,
+                                 int64_t* out) {
+  if (threadIdx.x == 0) {
+    out[0] = meta[0];
+    out[1] = meta[1];
+    out[2] = meta[2];
+    out[3] = *nn;
+    out[4] = *sn;
+  }
+}
+
 __global__ void k_p_counts(const uint8_t* st, const int32_t* s_cnt, int64_t n, int64_t* nrp,
                            int64_t* srp) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -783,28 +795,36 @@ void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar,
   HIP_OK(hipGetLastError());
   }
   if (n) k_sort_s<<<nblocks(n, 256), 256, 0, s>>>(D);
-  int32_t meta[4];
-  HIP_OK(hipMemcpyAsync(meta, D.meta, sizeof(meta), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipStreamSynchronize(s));
-  if (meta[2] & DERR_CAPACITY) throw Error(EMIN_ERR_CAPACITY, "alg3: S set or BFS ball capacity");
-  out.n_c = meta[0];
-  out.n_alg3 = meta[1];
-  // coarse numbering (ascending fine index), C list, S CSR, N^(p)
+  // coarse numbering (ascending fine index), C list, S CSR, N^(p); the
+  // counts of Alg. 3, its error bits and the two pattern sizes in one
+  // read-back
   int64_t* incl = ar.alloc<int64_t>(n + 1);
   if (n) k_flags_c<<<nblocks(n, 256), 256, 0, s>>>(D.st, n, incl);
   scan_inclusive(incl, n, s, ar);
-  out.cid = ar.alloc<int32_t>(n);
-  out.clist = ar.alloc<int32_t>(out.n_c);
-  if (n) k_compact<<<nblocks(n, 256), 256, 0, s>>>(incl, D.st, n, out.clist, out.cid);
   out.N.nrows = n;
-  out.N.ncols = out.n_c;
   out.N.rowptr = ar.alloc<int64_t>(n + 1);
   out.S.nrows = n;
   out.S.ncols = n;
   out.S.rowptr = ar.alloc<int64_t>(n + 1);
+  HIP_OK(hipMemsetAsync(out.N.rowptr, 0, sizeof(int64_t), s));
+  HIP_OK(hipMemsetAsync(out.S.rowptr, 0, sizeof(int64_t), s));
   if (n) k_p_counts<<<nblocks(n, 256), 256, 0, s>>>(D.st, D.s_cnt, n, out.N.rowptr, out.S.rowptr);
-  out.N.nnz = rowptr_from_counts(out.N.rowptr, n, s, ar);
-  out.S.nnz = rowptr_from_counts(out.S.rowptr, n, s, ar);
+  scan_inclusive(out.N.rowptr + 1, n, s, ar);
+  scan_inclusive(out.S.rowptr + 1, n, s, ar);
+  int64_t* q = ar.alloc<int64_t>(5);
+  k_coarse_summary<<<1, 64, 0, s>>>(D.meta, out.N.rowptr + n, out.S.rowptr + n, q);
+  int64_t hq[5];
+  HIP_OK(hipMemcpyAsync(hq, q, sizeof(hq), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  if (hq[2] & DERR_CAPACITY) throw Error(EMIN_ERR_CAPACITY, "alg3: S set or BFS ball capacity");
+  out.n_c = hq[0];
+  out.n_alg3 = hq[1];
+  out.N.nnz = hq[3];
+  out.S.nnz = hq[4];
+  out.N.ncols = out.n_c;
+  out.cid = ar.alloc<int32_t>(n);
+  out.clist = ar.alloc<int32_t>(out.n_c);
+  if (n) k_compact<<<nblocks(n, 256), 256, 0, s>>>(incl, D.st, n, out.clist, out.cid);
   out.N.col = ar.alloc<int32_t>(out.N.nnz);
   out.S.col = ar.alloc<int32_t>(out.S.nnz);
   out.sdist = ar.alloc<uint8_t>(out.S.nnz);

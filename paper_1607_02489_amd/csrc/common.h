@@ -127,6 +127,10 @@ void zero_bytes(void* p, size_t bytes, hipStream_t s);
 // max |i - j| over the entries of a square pattern (a graph's index bandwidth)
 int64_t index_bandwidth(const int64_t* rp, const int32_t* col, int64_t n, hipStream_t s,
                         Arena& ar);
+// the same two maxima left in device memory (*out, no read-back)
+void index_bandwidth_dev(const int64_t* rp, const int32_t* col, int64_t n,
+                         unsigned long long* out, hipStream_t s);
+void max_row_len_dev(const int64_t* rp, int64_t n, unsigned long long* out, hipStream_t s);
 // longest row of a CSR (synchronises the stream)
 int64_t max_row_len(const int64_t* rp, int64_t n, hipStream_t s, Arena& ar);
 // largest value of a non-negative int32 array (synchronises the stream)

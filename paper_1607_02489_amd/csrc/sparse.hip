@@ -96,12 +96,17 @@ __global__ void k_bandwidth(const int64_t* grp, const int32_t* gcol, int64_t n,
     atomicMax(bw, m);
 }
 
+void index_bandwidth_dev(const int64_t* rp, const int32_t* col, int64_t n,
+                         unsigned long long* out, hipStream_t s) {
+  HIP_OK(hipMemsetAsync(out, 0, sizeof(unsigned long long), s));
+  if (n > 0) k_bandwidth<<<nblocks(n, 256), 256, 0, s>>>(rp, col, n, out);
+}
+
 int64_t index_bandwidth(const int64_t* rp, const int32_t* col, int64_t n, hipStream_t s,
                         Arena& ar) {
   if (n <= 0) return 0;
   unsigned long long* bw = ar.alloc<unsigned long long>(1);
-  HIP_OK(hipMemsetAsync(bw, 0, sizeof(unsigned long long), s));
-  k_bandwidth<<<nblocks(n, 256), 256, 0, s>>>(rp, col, n, bw);
+  index_bandwidth_dev(rp, col, n, bw, s);
   return (int64_t)d2h(bw, s);
 }
 
@@ -1020,11 +1025,15 @@ __global__ void k_defer_err(const int* lerr, int* derr) {
   if (threadIdx.x == 0 && lerr[0]) atomicOr(derr, DERR_CAPACITY);
 }
 
+void max_row_len_dev(const int64_t* rp, int64_t n, unsigned long long* out, hipStream_t s) {
+  HIP_OK(hipMemsetAsync(out, 0, sizeof(unsigned long long), s));
+  if (n > 0) k_row_len_max<<<nblocks(n, 256), 256, 0, s>>>(rp, n, out);
+}
+
 int64_t max_row_len(const int64_t* rp, int64_t n, hipStream_t s, Arena& ar) {
   if (n <= 0) return 0;
   unsigned long long* mx = ar.alloc<unsigned long long>(1);
-  HIP_OK(hipMemsetAsync(mx, 0, sizeof(unsigned long long), s));
-  k_row_len_max<<<nblocks(n, 256), 256, 0, s>>>(rp, n, mx);
+  max_row_len_dev(rp, n, mx, s);
   return (int64_t)d2h(mx, s);
 }
 

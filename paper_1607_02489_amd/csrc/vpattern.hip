@@ -195,6 +195,18 @@ __global__ __launch_bounds__(1024) void k_vextras(const int64_t* grp, const int3
   }
 }
 
+// scalars gathered for one read-back into out[0..4] (a null source reads 0)
+__global__ void k_gather_scalars(const int64_t* a, const int64_t* b, const unsigned long long* c,
+                                 const unsigned long long* d, const int* e, int64_t* out) {
+  if (threadIdx.x == 0) {
+    out[0] = a ? *a : 0;
+    out[1] = b ? *b : 0;
+    out[2] = c ? (int64_t)*c : 0;
+    out[3] = d ? (int64_t)*d : 0;
+    out[4] = e ? *e : 0;
+  }
+}
+
 __global__ void k_flags_u8(const uint8_t* f, int64_t n, int64_t* out) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = f[i] != 0;
@@ -246,17 +258,26 @@ void velocity_pattern(const Csr& G, const uint8_t* dir, uint8_t* cv, VPatternOut
   HIP_OK(hipMemsetAsync(cov, 0, n, s));
   HIP_OK(hipMemsetAsync(vcnt, 0, sizeof(int32_t) * n, s));
   HIP_OK(hipMemsetAsync(vis, 0xFF, sizeof(int32_t) * n, s));
-  // initial C^(v) list
+  // initial C^(v) list; its size, the longest graph row and the index
+  // bandwidth in one read-back
   int64_t* incl = ar.alloc<int64_t>(n + 1);
+  unsigned long long* mx2 = ar.alloc<unsigned long long>(2);
+  int64_t* q = ar.alloc<int64_t>(5);
   if (n) k_flags_u8<<<nblocks(n, 256), 256, 0, s>>>(cv, n, incl);
   scan_inclusive(incl, n, s, ar);
-  const int64_t n0 = n ? d2h(incl + n - 1, s) : 0;
+  max_row_len_dev(G.rowptr, n, mx2, s);
+  index_bandwidth_dev(G.rowptr, G.col, n, mx2 + 1, s);
+  k_gather_scalars<<<1, 64, 0, s>>>(n ? incl + n - 1 : nullptr, nullptr, mx2, mx2 + 1, nullptr, q);
+  int64_t hq[5];
+  HIP_OK(hipMemcpyAsync(hq, q, sizeof(hq), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  const int64_t n0 = hq[0];
   int32_t* src0 = ar.alloc<int32_t>(n0);
   if (n) k_compact_u8<<<nblocks(n, 256), 256, 0, s>>>(incl, cv, n, src0, nullptr);
   if (n0) k_vbfs<<<nblocks(n0, VB_WAVES), 64 * VB_WAVES, 0, s>>>(G.rowptr, G.col, src0, n0, dir,
                                                                   cov, vcnt, vbuf, err);
   // extra points in ascending order
-  int64_t maxdeg = max_row_len(G.rowptr, n, s, ar);
+  const int64_t maxdeg = hq[2];
   int deg_cap = 1;
   while (deg_cap < maxdeg && deg_cap < 1024) deg_cap <<= 1;
   int32_t* extra = ar.alloc<int32_t>(n);
@@ -264,7 +285,7 @@ void velocity_pattern(const Csr& G, const uint8_t* dir, uint8_t* cv, VPatternOut
   int ballcap = 8192;
   if (ballcap * 4 + 64 > lds_max) ballcap = (lds_max - 64) / 4;
   // visited bitmap over the ball's index window when it fits beside the list
-  const int64_t bw = index_bandwidth(G.rowptr, G.col, n, s, ar);
+  const int64_t bw = hq[3];
   const int64_t words = (6 * bw + 1 + 31) / 32;
   const int nwin = (int64_t)ballcap * 4 + words * 4 + 64 <= lds_max ? (int)words : 0;
   const size_t lds = (size_t)ballcap * 4 + (size_t)nwin * 4;
@@ -278,19 +299,27 @@ void velocity_pattern(const Csr& G, const uint8_t* dir, uint8_t* cv, VPatternOut
   if (out.n_extra)
     k_vbfs<<<nblocks(out.n_extra, VB_WAVES), 64 * VB_WAVES, 0, s>>>(
         G.rowptr, G.col, extra, out.n_extra, dir, cov, vcnt, vbuf, err);
-  if (d2h(err, s)) throw Error(EMIN_ERR_CAPACITY, "velocity pattern: row or ball capacity");
-  // final numbering and the pattern
+  // final numbering and the pattern: C^(v) size, the error flag and the
+  // pattern size in one read-back
   if (n) k_flags_u8<<<nblocks(n, 256), 256, 0, s>>>(cv, n, incl);
   scan_inclusive(incl, n, s, ar);
-  out.n_c = n ? d2h(incl + n - 1, s) : 0;
+  out.N.nrows = n;
+  out.N.rowptr = ar.alloc<int64_t>(n + 1);
+  HIP_OK(hipMemsetAsync(out.N.rowptr, 0, sizeof(int64_t), s));
+  if (n) k_v_counts<<<nblocks(n, 256), 256, 0, s>>>(cv, dir, vcnt, n, out.N.rowptr);
+  scan_inclusive(out.N.rowptr + 1, n, s, ar);
+  k_gather_scalars<<<1, 64, 0, s>>>(n ? incl + n - 1 : nullptr, out.N.rowptr + n, nullptr,
+                                    nullptr, err, q);
+  int64_t hc[5];
+  HIP_OK(hipMemcpyAsync(hc, q, sizeof(hc), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  if (hc[4]) throw Error(EMIN_ERR_CAPACITY, "velocity pattern: row or ball capacity");
+  out.n_c = hc[0];
+  out.N.nnz = hc[1];
+  out.N.ncols = out.n_c;
   out.cid = ar.alloc<int32_t>(n);
   out.clist = ar.alloc<int32_t>(out.n_c);
   if (n) k_compact_u8<<<nblocks(n, 256), 256, 0, s>>>(incl, cv, n, out.clist, out.cid);
-  out.N.nrows = n;
-  out.N.ncols = out.n_c;
-  out.N.rowptr = ar.alloc<int64_t>(n + 1);
-  if (n) k_v_counts<<<nblocks(n, 256), 256, 0, s>>>(cv, dir, vcnt, n, out.N.rowptr);
-  out.N.nnz = rowptr_from_counts(out.N.rowptr, n, s, ar);
   out.N.col = ar.alloc<int32_t>(out.N.nnz);
   if (n)
     k_v_fill<<<nblocks(n, 256), 256, 0, s>>>(cv, dir, vcnt, vbuf, out.cid, n, out.N.rowptr,
