@@ -296,12 +296,6 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
   int par = 0;
 
   int32_t k = n > 0 ? 0 : -1;   // Alg. 3's "arbitrary vertex": vertex 0
-  // Almost always the next C point lies on the distance-4 ring of the current
-  // one, so the ball rows of the ring's candidates are fetched ahead (while
-  // the argmin runs); the results are only retired once the next step's own
-  // ball load has arrived.  Done for short rows only (a few cache lines).
-  const bool prefetch = D.bmax <= 96;
-  int32_t pf0 = 0, pf1 = 0, pf2 = 0, pf3 = 0, pf4 = 0, pf5 = 0;
   while (k >= 0) {
     uint32_t* dbits = dbits0 + par * nw;
     int32_t* dlist = dlist0 + par * D.dcap;
@@ -313,8 +307,10 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
     const int nb = D.bsize[k];
     const double* xkp = D.x + (int64_t)k * dim;
     const double xk0 = xkp[0], xk1 = xkp[1], xk2 = dim == 3 ? xkp[2] : 0.0;
-    asm volatile("" ::"v"(ea), "v"(pf0), "v"(pf1), "v"(pf2), "v"(pf3), "v"(pf4), "v"(pf5)
-                 : "memory");
+    // (k's coordinates arrive with the ball: retiring them here keeps their
+    // registers free of pending loads on every later path, where a wait for
+    // them would be a wait for the whole in-order load counter)
+    asm volatile("" ::"v"(ea), "v"(xk0), "v"(xk1), "v"(xk2) : "memory");
     const int nc0 = nc_sh;
     A3Entry E[2];
     const bool has[2] = {tid < nb, tid + A3_BS < nb};
@@ -375,7 +371,6 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
         asm volatile("" : "+v"(E[q].s), "+v"(E[q].c), "+v"(E[q].r), "+v"(E[q].sl),
                      "+v"(E[q].x0), "+v"(E[q].x1), "+v"(E[q].x2));
     // (3) S_j += {k} for dist <= 3; C/F/Cand update; update_heuristics
-    int32_t pv = -1;   // a candidate on the ring
 #pragma unroll
     for (int q = 0; q < 2; q++) {
       if (!has[q]) continue;
@@ -412,7 +407,6 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
         const double nk = s1 == ST_CAND ? (double)c1 / r1 : INF;
         if (s1 == ST_CAND || x.s == ST_CAND) D.hkey[x.v] = nk;
         if (use_ovl) ovl[bslot[x.v >> 6] * 64 + (x.v & 63)] = nk;
-        if (s1 == ST_CAND) pv = x.v;
       }
     }
     __syncthreads();
@@ -459,21 +453,19 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
       if (lane == 0) { bkey[b] = key; bidx[b] = idx; }
       if (lex_less(key, idx, ck, ci)) { ck = key; ci = idx; }
     }
+    // retire every pre-update key load on both refresh paths (they were
+    // issued long before): a load left pending here would make a later
+    // register reuse wait for the whole in-order load counter
+    if (ovl_ok) {
+#pragma unroll
+      for (int i = 0; i < A3_OVL / A3_WAVES; i++) asm volatile("" ::"v"(oldk[i]));
+    }
     if (lane == 0) { wkey[wave] = ck; widx[wave] = ci; }
     __syncthreads();
     // this step's dirty set is next used two steps on, after three barriers
     for (int b = tid; b < nw; b += A3_BS) dbits[b] = 0u;
     if (tid == 0) { dn_sh[par] = 0; dall_sh[par] = 0; }
     par ^= 1;
-    if (prefetch && pv >= 0) {
-      const int32_t* pb = D.balls + (int64_t)pv * D.bstride;
-      pf0 = pb[0];
-      pf1 = pb[D.bmax > 32 ? 32 : 0];
-      pf2 = pb[D.bmax > 64 ? 64 : 0];
-      pf3 = pb[D.bmax - 1];
-      pf4 = D.bsize[pv];
-      pf5 = reinterpret_cast<const int32_t*>(D.x)[(int64_t)pv * dim * 2];
-    }
     // (5) next k = argmin over Cand of (h1, index): every wave reduces the
     // wave minima itself
     double key = lane < A3_WAVES ? wkey[lane] : INF;
