@@ -481,7 +481,7 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
       __syncthreads();
       for (int64_t base = cursor_sh; base < n; base += A3_BS) {
         const int64_t v = base + tid;
-        if (v < n && D.st[v] == ST_U) atomicMin(&found_sh, (int)v);
+        first_lane_min(&found_sh, v < n && D.st[v] == ST_U, (int)v);
         __syncthreads();
         const int f = found_sh;
         __syncthreads();
@@ -570,7 +570,7 @@ __global__ __launch_bounds__(A3_BS) void k_extras(CoarsenArgs D, const double* e
       __syncthreads();
       for (int64_t base = cursor; base < D.n; base += A3_BS) {
         const int64_t v = base + tid;
-        if (v < D.n && extra_pred(D, ebar, pass, v)) atomicMin(&found_sh, (int)v);
+        first_lane_min(&found_sh, v < D.n && extra_pred(D, ebar, pass, v), (int)v);
         __syncthreads();
         const int f = found_sh;
         __syncthreads();

@@ -230,6 +230,15 @@ __device__ __forceinline__ uint64_t group_ballot(bool p) {
   return (b >> base) & ((1ull << G) - 1ull);
 }
 
+// atomicMin(dst, val) over the lanes with has set, for values that increase
+// with the lane index: only the wave's lowest such lane takes part (the
+// compiler would otherwise serialise a divergent atomic over the lanes).
+// Every lane of the wave must call it.
+__device__ __forceinline__ void first_lane_min(int* dst, bool has, int val) {
+  const uint64_t b = __ballot(has);
+  if (b && (int)(threadIdx.x & 63) == __builtin_ctzll(b)) atomicMin(dst, val);
+}
+
 // lexicographic (key, index) minimum across a full 64-lane wave
 // Wave-wide reductions on the DPP network (row shifts, then the two row
 // broadcasts), which leave the result in lane 63; it is then read out as a
