@@ -45,6 +45,41 @@ enum DevErr : int {
 void* chunk_get(size_t bytes);
 void chunk_put(void* p, size_t bytes);
 
+// A cached device chunk of a power-of-two size (at least 1 MiB, so later
+// calls reuse it), given back when the scope ends, after the stream's queued
+// work (errors are ignored there: the scope may be ending by one).
+struct ChunkLease {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipStream_t s = nullptr;
+  ChunkLease() = default;
+  ChunkLease(const ChunkLease&) = delete;
+  ChunkLease& operator=(const ChunkLease&) = delete;
+  void* take(size_t need, hipStream_t stream);
+  // gives the chunk back now (the caller has synchronised the stream)
+  void put_back() {
+    if (p) chunk_put(p, bytes);
+    p = nullptr;
+  }
+  ~ChunkLease() {
+    if (p) {
+      (void)hipStreamSynchronize(s);
+      chunk_put(p, bytes);
+    }
+  }
+};
+
+inline void* ChunkLease::take(size_t need, hipStream_t stream) {
+  size_t b = size_t(1) << 20;
+  while (b < need) b <<= 1;
+  void* q = chunk_get(b);
+  if (!q) throw Error(EMIN_ERR_OOM, "device allocation failed");
+  p = q;
+  bytes = b;
+  s = stream;
+  return q;
+}
+
 class Arena {
  public:
   Arena() = default;

@@ -1340,20 +1340,6 @@ static int64_t bitmap_budget() {
   return int64_t(1) << 30;
 }
 
-// a cached device chunk given back when the scope ends, after the stream's
-// queued work (errors are ignored there: the scope may be ending by one)
-struct ChunkLease {
-  void* p = nullptr;
-  size_t bytes = 0;
-  hipStream_t s = nullptr;
-  ~ChunkLease() {
-    if (p) {
-      (void)hipStreamSynchronize(s);
-      chunk_put(p, bytes);
-    }
-  }
-};
-
 // hash kernels for a list of rows (those outside the window kernel's reach)
 template <int G>
 static void launch_sym_rows(const int32_t* rows, int64_t nrows, const CsrView& A,
@@ -1400,21 +1386,14 @@ void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& pla
   const int nwide = (int)hw[1];
   // The union runs once and its bitmaps are kept for the fill pass when they
   // fit the budget; otherwise the fill pass recomputes them.  Large ones take
-  // a cached device chunk (power-of-two size, so later products reuse it),
-  // returned once the fill pass has finished.
+  // a cached device chunk, returned once the fill pass has finished.
   const size_t bbytes = (size_t)(twords > 0 ? twords : 1) * sizeof(uint32_t);
   const bool stored = (int64_t)bbytes <= bitmap_budget();
   const bool big_bits = stored && bbytes > (size_t(4) << 20);
-  size_t cbytes = size_t(1) << 20;
-  while (big_bits && cbytes < bbytes) cbytes <<= 1;
   uint32_t* bits = nullptr;
   ChunkLease lease;
   if (big_bits) {
-    bits = static_cast<uint32_t*>(chunk_get(cbytes));
-    if (!bits) throw Error(EMIN_ERR_OOM, "device allocation failed");
-    lease.p = bits;
-    lease.bytes = cbytes;
-    lease.s = s;
+    bits = static_cast<uint32_t*>(lease.take(bbytes, s));
   } else if (stored) {
     bits = ar.alloc<uint32_t>(bbytes / sizeof(uint32_t));
   }
