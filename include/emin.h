@@ -166,10 +166,6 @@ typedef struct emin_pattern_s emin_pattern_t;
 /* Alg. 2 up to the patterns, plus the symbolic RAP and the coarse
  * descriptors (coordinates by injection, co-location map).  Borrows sys for
  * the call; the handle owns its device memory (hipMalloc) until destroyed.
- * Each symbolic product keeps its rows' column bitmaps between its count and
- * fill passes, in a cached device chunk held only for the call, when they
- * take at most EMIN_SPGEMM_BITMAP_MAX bytes (environment, default 1 GiB);
- * beyond that the fill pass recomputes them.  The result is the same.
  * Errors: ARG/SHAPE/PATTERN on bad inputs, CAPACITY, COLOCATE, DEVICE, OOM. */
 emin_status emin_pattern(const emin_system_t *sys, const emin_params_t *prm, void *stream,
                          emin_pattern_t **out);

@@ -28,7 +28,6 @@ struct CoarsenArgs {
   const int32_t* b3 = nullptr;    // entries at distance <= 3 (a prefix of the ball)
   int bmax = 0;                   // largest ball
   int64_t bstride = 0;            // row stride of balls (>= bmax)
-  const double* binv = nullptr;   // small balls: each entry's 1/|x_v - x_centre| (same stride)
   int vb = 64;                    // vertices per argmin block
   int nblk = 1;
   int dcap = 1024;

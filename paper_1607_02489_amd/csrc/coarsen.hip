@@ -205,28 +205,6 @@ __global__ __launch_bounds__(64 * BWIN_W) void k_balls_win(const int64_t* grp,
   }
 }
 
-// 1/|x_u - x_v| of every ball entry u to its centre v, with the operations
-// of the greedy step in the same order (coordinate differences entry minus
-// centre, squares summed in coordinate order, no contraction), so the bits
-// are those the step would compute; the centre's own entry is unused
-__global__ void k_ball_invd(const int32_t* balls, const int32_t* bsize, int64_t stride,
-                            const double* x, int dim, int64_t n, double* binv) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n * stride) return;
-  const int64_t v = i / stride;
-  if (i - v * stride >= bsize[v]) return;
-  const int64_t u = balls[i] & VMASK;
-  const double t0 = x[u * dim] - x[v * dim], t1 = x[u * dim + 1] - x[v * dim + 1];
-  double ss = 0.0;
-  ss = ss + t0 * t0;
-  ss = ss + t1 * t1;
-  if (dim == 3) {
-    const double t2 = x[u * dim + 2] - x[v * dim + 2];
-    ss = ss + t2 * t2;
-  }
-  binv[i] = 1.0 / sqrt(ss);
-}
-
 __global__ void k_sample_verts(int64_t n, int32_t m, int32_t* verts) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) verts[i] = (int32_t)(((int64_t)i * n) / m);
@@ -327,10 +305,8 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
     const int32_t ea = tid < D.bmax ? bl[tid] : 0;
     const int32_t eb = tid + A3_BS < D.bmax ? bl[tid + A3_BS] : 0;
     const int nb = D.bsize[k];
-    // (k's coordinates only where the step computes the distances itself)
     const double* xkp = D.x + (int64_t)k * dim;
-    const double xk0 = OVL ? 0.0 : xkp[0], xk1 = OVL ? 0.0 : xkp[1],
-                 xk2 = !OVL && dim == 3 ? xkp[2] : 0.0;
+    const double xk0 = xkp[0], xk1 = xkp[1], xk2 = dim == 3 ? xkp[2] : 0.0;
     // (k's coordinates arrive with the ball: retiring them here keeps their
     // registers free of pending loads on every later path, where a wait for
     // them would be a wait for the whole in-order load counter)
@@ -355,18 +331,10 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
       x.c = D.cnt[x.v];
       x.r = D.rs[x.v];
       x.sl = D.s_cnt[x.v];
-      if constexpr (OVL) {
-        // small balls: the entry's inverse distance to k, computed with the
-        // balls (x0 holds it)
-        x.x0 = D.binv[(int64_t)k * D.bstride + (has[q] ? tid + q * A3_BS : 0)];
-        x.x1 = 0.0;
-        x.x2 = 0.0;
-      } else {
-        const double* xvp = D.x + (int64_t)x.v * dim;
-        x.x0 = xvp[0];
-        x.x1 = xvp[1];
-        x.x2 = xvp[dim == 3 ? 2 : 1];
-      }
+      const double* xvp = D.x + (int64_t)x.v * dim;
+      x.x0 = xvp[0];
+      x.x1 = xvp[1];
+      x.x2 = xvp[dim == 3 ? 2 : 1];
     }
     __syncthreads();
     // (2) while those loads are in flight: the pre-update keys of the touched
@@ -422,19 +390,13 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
         D.order[nc0] = x.v;
         if (use_ovl) ovl[bslot[x.v >> 6] * 64 + (x.v & 63)] = INF;
       } else {
-        double inv;
-        if constexpr (OVL) {
-          inv = x.x0;
-        } else {
-          // |x_v - x_k| summed in coordinate order, as in the definition
-          const double t0 = x.x0 - xk0, t1 = x.x1 - xk1, t2 = (dim == 3 ? x.x2 : 0.0) - xk2;
-          double ss = 0.0;
-          ss = ss + t0 * t0;
-          ss = ss + t1 * t1;
-          if (dim == 3) ss = ss + t2 * t2;
-          inv = 1.0 / sqrt(ss);
-        }
-        const double r1 = x.r + inv;
+        // |x_v - x_k| summed in coordinate order, as in the definition
+        const double t0 = x.x0 - xk0, t1 = x.x1 - xk1, t2 = (dim == 3 ? x.x2 : 0.0) - xk2;
+        double ss = 0.0;
+        ss = ss + t0 * t0;
+        ss = ss + t1 * t1;
+        if (dim == 3) ss = ss + t2 * t2;
+        const double r1 = x.r + 1.0 / sqrt(ss);
         const int32_t c1 = x.c + 1;
         int32_t s1 = x.s;
         if (x.d <= 3 && (x.s == ST_U || x.s == ST_CAND)) s1 = ST_F;
@@ -519,7 +481,7 @@ __global__ __launch_bounds__(A3_BS) void k_alg3(CoarsenArgs D) {
       __syncthreads();
       for (int64_t base = cursor_sh; base < n; base += A3_BS) {
         const int64_t v = base + tid;
-        first_lane_min(&found_sh, v < n && D.st[v] == ST_U, (int)v);
+        if (v < n && D.st[v] == ST_U) atomicMin(&found_sh, (int)v);
         __syncthreads();
         const int f = found_sh;
         __syncthreads();
@@ -608,7 +570,7 @@ __global__ __launch_bounds__(A3_BS) void k_extras(CoarsenArgs D, const double* e
       __syncthreads();
       for (int64_t base = cursor; base < D.n; base += A3_BS) {
         const int64_t v = base + tid;
-        first_lane_min(&found_sh, v < D.n && extra_pred(D, ebar, pass, v), (int)v);
+        if (v < D.n && extra_pred(D, ebar, pass, v)) atomicMin(&found_sh, (int)v);
         __syncthreads();
         const int f = found_sh;
         __syncthreads();
@@ -749,8 +711,7 @@ void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar,
     int lcap = BLIST;
     auto lds_for = [&](int cap) { return (size_t)BWIN_W * (nwords + cap) * sizeof(uint32_t); };
     if (lds_for(BLIST) <= (size_t)lds_max) {
-      HIP_OK(hipFuncSetAttribute((const void*)k_balls_win,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_for(BLIST)));
+      allow_lds((const void*)k_balls_win);
       const int32_t m = (int32_t)std::min<int64_t>(n, 512);
       int32_t* sv = ar.alloc<int32_t>(m);
       k_sample_verts<<<nblocks(m, 256), 256, 0, s>>>(n, m, sv);
@@ -784,8 +745,7 @@ void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar,
   if (n && !done) {
     // hash-set kernel: sizes first, then the lists
     const size_t blds = (size_t)BW * (BHASH + BLIST) * sizeof(int32_t);
-    HIP_OK(hipFuncSetAttribute((const void*)k_balls, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)blds));
+    allow_lds((const void*)k_balls);
     k_balls<<<nblocks(n, BW), 64 * BW, blds, s>>>(D.grp, D.gcol, n, 4, bsize, b3, nullptr, BLIST,
                                                   D.meta + 2);
     if (d2h(D.meta + 2, s) & DERR_CAPACITY) throw Error(EMIN_ERR_CAPACITY, "alg3: ball capacity");
@@ -813,18 +773,7 @@ void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar,
                ((size_t)D.nblk + 1) * 4 + 8 + (D.vb == 64 ? (size_t)A3_OVL * 64 * 8 : 0);
   if (lds > (size_t)lds_max) throw Error(EMIN_ERR_CAPACITY, "alg3: LDS too small");
   const void* kfun = D.vb == 64 ? (const void*)k_alg3<true> : (const void*)k_alg3<false>;
-  HIP_OK(hipFuncSetAttribute(kfun, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  // small balls (64-vertex blocks): every entry's inverse distance, computed
-  // in parallel here instead of in each greedy step; held for this call
-  ChunkLease binv_lease;
-  D.binv = nullptr;
-  if (D.vb == 64 && n) {
-    const size_t cnt = (size_t)n * (size_t)stride;
-    double* bi = static_cast<double*>(binv_lease.take(cnt * sizeof(double), s));
-    k_ball_invd<<<nblocks((int64_t)cnt, 256), 256, 0, s>>>(balls, bsize, stride, D.x, D.dim, n,
-                                                            bi);
-    D.binv = bi;
-  }
+  allow_lds(kfun);
   {
   prof::Scope ps(s, EMIN_PROF_ALG3, 0.0);
   if (D.vb == 64) k_alg3<true><<<1, A3_BS, lds, s>>>(D);
@@ -857,8 +806,6 @@ void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar,
   int64_t hq[5];
   HIP_OK(hipMemcpyAsync(hq, q, sizeof(hq), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
-  D.binv = nullptr;
-  binv_lease.put_back();
   if (hq[2] & DERR_CAPACITY) throw Error(EMIN_ERR_CAPACITY, "alg3: S set or BFS ball capacity");
   out.n_c = hq[0];
   out.n_alg3 = hq[1];

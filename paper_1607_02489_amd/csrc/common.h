@@ -45,40 +45,10 @@ enum DevErr : int {
 void* chunk_get(size_t bytes);
 void chunk_put(void* p, size_t bytes);
 
-// A cached device chunk of a power-of-two size (at least 1 MiB, so later
-// calls reuse it), given back when the scope ends, after the stream's queued
-// work (errors are ignored there: the scope may be ending by one).
-struct ChunkLease {
-  void* p = nullptr;
-  size_t bytes = 0;
-  hipStream_t s = nullptr;
-  ChunkLease() = default;
-  ChunkLease(const ChunkLease&) = delete;
-  ChunkLease& operator=(const ChunkLease&) = delete;
-  void* take(size_t need, hipStream_t stream);
-  // gives the chunk back now (the caller has synchronised the stream)
-  void put_back() {
-    if (p) chunk_put(p, bytes);
-    p = nullptr;
-  }
-  ~ChunkLease() {
-    if (p) {
-      (void)hipStreamSynchronize(s);
-      chunk_put(p, bytes);
-    }
-  }
-};
-
-inline void* ChunkLease::take(size_t need, hipStream_t stream) {
-  size_t b = size_t(1) << 20;
-  while (b < need) b <<= 1;
-  void* q = chunk_get(b);
-  if (!q) throw Error(EMIN_ERR_OOM, "device allocation failed");
-  p = q;
-  bytes = b;
-  s = stream;
-  return q;
-}
+// Lets kernel f take up to the device's LDS per block (less its static LDS)
+// as dynamic LDS.  Set once per kernel and device, under a lock, so host
+// threads launching f with different sizes never race on the limit.
+void allow_lds(const void* f);
 
 class Arena {
  public:
@@ -263,15 +233,6 @@ __device__ __forceinline__ uint64_t group_ballot(bool p) {
   if (G == 64) return b;
   const int base = (int)(threadIdx.x & 63) & ~(G - 1);
   return (b >> base) & ((1ull << G) - 1ull);
-}
-
-// atomicMin(dst, val) over the lanes with has set, for values that increase
-// with the lane index: only the wave's lowest such lane takes part (the
-// compiler would otherwise serialise a divergent atomic over the lanes).
-// Every lane of the wave must call it.
-__device__ __forceinline__ void first_lane_min(int* dst, bool has, int val) {
-  const uint64_t b = __ballot(has);
-  if (b && (int)(threadIdx.x & 63) == __builtin_ctzll(b)) atomicMin(dst, val);
 }
 
 // lexicographic (key, index) minimum across a full 64-lane wave

@@ -3,6 +3,8 @@
 // and replays all of their numeric phases as one captured hipGraph, and the
 // level-by-level device memory bookkeeping both need.
 #include <atomic>
+#include <mutex>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -124,8 +126,10 @@ emin_status emin_hierarchy_build(const emin_system_t* sys, const emin_params_t* 
       if ((st = coarse_of(p, h->Ac.back(), h->Bc.back(), cur.dim, &cur)) != EMIN_OK) break;
     }
   } catch (const Error& e) {
+    set_last_error(e.what());
     st = e.code;
   } catch (...) {
+    set_last_error("emin_hierarchy_build: unexpected exception");
     st = EMIN_ERR_DEVICE;
   }
   if (st != EMIN_OK) {
@@ -193,6 +197,8 @@ emin_status emin_hierarchy_build_batch(const emin_system_t* const* systems, int3
   for (int32_t i = 0; i < count; i++) out[i] = nullptr;
   std::atomic<int32_t> next{0};
   std::atomic<int> first_err{EMIN_OK};
+  std::mutex msg_mu;
+  std::string first_msg;   // the first failing build's message (worker threads')
   auto work = [&]() {
     hipStream_t s = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
@@ -204,10 +210,22 @@ emin_status emin_hierarchy_build_batch(const emin_system_t* const* systems, int3
       const int32_t i = next.fetch_add(1);
       if (i >= count) break;
       emin_status st = emin_hierarchy_build(systems[i], prm, nlevels, min_dofs, s, &out[i]);
-      if (st == EMIN_OK && hipStreamSynchronize(s) != hipSuccess) st = EMIN_ERR_DEVICE;
+      std::string why;
+      if (st != EMIN_OK) {
+        why = emin_last_error();
+      } else {
+        const hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+          st = EMIN_ERR_DEVICE;
+          why = std::string("hipStreamSynchronize: ") + hipGetErrorString(e);
+        }
+      }
       if (st != EMIN_OK) {
         int ok = EMIN_OK;
-        first_err.compare_exchange_strong(ok, st);
+        if (first_err.compare_exchange_strong(ok, st)) {
+          std::lock_guard<std::mutex> g(msg_mu);
+          first_msg = "system " + std::to_string(i) + ": " + why;
+        }
       }
     }
     (void)hipStreamDestroy(s);
@@ -221,6 +239,7 @@ emin_status emin_hierarchy_build_batch(const emin_system_t* const* systems, int3
       emin_hierarchy_destroy(out[i]);
       out[i] = nullptr;
     }
+    set_last_error(first_msg.c_str());
     return (emin_status)first_err.load();
   }
   return EMIN_OK;

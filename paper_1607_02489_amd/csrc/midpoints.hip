@@ -343,8 +343,7 @@ int64_t midpoints(const Csr& S, const uint8_t* st, const double* x, int dim, dou
   const int64_t norder = th[0];
   const size_t lds = (size_t)((n + 31) / 32) * 4;
   if ((int64_t)lds > lds_max) throw Error(EMIN_ERR_CAPACITY, "alg4: C-bar bitmap exceeds LDS");
-  HIP_OK(hipFuncSetAttribute((const void*)k_mid_decide,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  allow_lds((const void*)k_mid_decide);
   int32_t* mo = ar.alloc<int32_t>(norder);
   int32_t* to = ar.alloc<int32_t>((size_t)norder * TCAP);
   unsigned long long* dep = ar.alloc<unsigned long long>(norder);

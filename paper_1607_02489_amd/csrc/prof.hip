@@ -3,6 +3,7 @@
 
 #include <map>
 #include <mutex>
+#include <set>
 
 namespace emin {
 namespace prof {
@@ -57,6 +58,22 @@ namespace {
 std::mutex cache_mu;
 std::multimap<size_t, void*> cache;
 }  // namespace
+
+void allow_lds(const void* f) {
+  static std::mutex mu;
+  static std::set<std::pair<const void*, int>> done;
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(mu);
+  if (done.count({f, dev})) return;
+  int mx = 0;
+  HIP_OK(hipDeviceGetAttribute(&mx, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  hipFuncAttributes fa;
+  HIP_OK(hipFuncGetAttributes(&fa, f));
+  HIP_OK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             mx - (int)fa.sharedSizeBytes));
+  done.insert({f, dev});
+}
 
 void* chunk_get(size_t bytes) {
   {

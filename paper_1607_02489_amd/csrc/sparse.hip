@@ -454,9 +454,7 @@ void sort_rows(const int64_t* rp, int64_t n, int32_t* key, int32_t* src, hipStre
   k_sort_group<16><<<grid(16), 256, 0, s>>>(rp, lists + 2 * n, counts + 2, key, src);
   k_sort_group<32><<<grid(8), 256, 0, s>>>(rp, lists + 3 * n, counts + 3, key, src);
   k_sort_group<64><<<grid(4), 256, 0, s>>>(rp, lists + 4 * n, counts + 4, key, src);
-  HIP_OK(hipFuncSetAttribute((const void*)k_sort_block<SORT_PMAX>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                             2 * SORT_PMAX * (int)sizeof(int32_t)));
+  allow_lds((const void*)k_sort_block<SORT_PMAX>);
   const unsigned gb = (unsigned)std::min<int64_t>(n, 2048);
   k_sort_block<512><<<gb, 256, 2 * 512 * sizeof(int32_t), s>>>(rp, lists + 5 * n, counts + 5,
                                                                 key, src);
@@ -1063,8 +1061,7 @@ static void launch_sym(const int32_t* rows, int64_t nrows, const CsrView& A, con
                        int* novf, int* derr, hipStream_t s) {
   constexpr int NG = BS / G;
   const size_t lds = (size_t)NG * (hcap + hcap / 2) * sizeof(int32_t);
-  HIP_OK(hipFuncSetAttribute((const void*)k_spgemm_sym<G, BS>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  allow_lds((const void*)k_spgemm_sym<G, BS>);
   k_spgemm_sym<G, BS><<<nblocks(nrows, NG), BS, lds, s>>>(rows, nrows, A.rowptr, A.col, B.rowptr,
                                                           B.col, hcap, cnt, crp, ccol, ovf, novf,
                                                           derr);
@@ -1095,17 +1092,24 @@ static void sym_big(const int32_t* rows, int64_t nrows, const CsrView& A, const 
 // A entries select (B rows are sorted).  When that window is at most
 // 32 * wcap columns wide, a visited bitmap over it replaces the hash table:
 // one atomic OR per product, no probing, and the set bits read out in order
-// give the sorted row directly.  Rows with a wider window go to the hash
-// kernels.
-
-// the window [lo, hi] of a row's output columns (hi < 0: empty row), reduced
-// over the row's G lanes
+// give the sorted row directly.  Rows with a wider window are listed in ovf
+// (count mode) or skipped (fill mode) and go to the hash kernels.
 template <int G>
-__device__ __forceinline__ void win_bounds(int64_t ea, int64_t eb, int lane, const int32_t* acol,
-                                           const int64_t* brp, const int32_t* bcol, int32_t& lo,
-                                           int32_t& hi) {
-  lo = INT32_MAX;
-  hi = -1;
+__global__ __launch_bounds__(256) void k_spgemm_win(int64_t n, const int64_t* arp,
+                                                   const int32_t* acol, const int64_t* brp,
+                                                   const int32_t* bcol, int wcap,
+                                                   int64_t* out_cnt, const int64_t* crp,
+                                                   int32_t* ccol, int32_t* ovf, int* novf,
+                                                   int32_t* rwords) {
+  extern __shared__ uint32_t sbits[];
+  constexpr int NG = 256 / G;
+  const int g = threadIdx.x / G, lane = threadIdx.x % G;
+  uint32_t* words = sbits + (size_t)g * wcap;
+  const int64_t row = xcd_block(blockIdx.x, gridDim.x) * NG + g;
+  if (row >= n) return;   // whole group; the block never synchronises
+  const int64_t ea = arp[row], eb = arp[row + 1];
+  // window bounds
+  int32_t lo = INT32_MAX, hi = -1;
   for (int64_t e = ea + lane; e < eb; e += G) {
     const int32_t k = acol[e];
     const int64_t b0 = brp[k], b1 = brp[k + 1];
@@ -1121,13 +1125,22 @@ __device__ __forceinline__ void win_bounds(int64_t ea, int64_t eb, int lane, con
     lo = ol < lo ? ol : lo;
     hi = oh > hi ? oh : hi;
   }
-}
-
-// the group's LDS bitmap of the row's output columns over nw words from lo
-template <int G>
-__device__ __forceinline__ void win_union(uint32_t* words, int nw, int32_t lo, int64_t ea,
-                                          int64_t eb, int lane, const int32_t* acol,
-                                          const int64_t* brp, const int32_t* bcol) {
+  if (hi < 0) {   // empty output row
+    if (out_cnt && lane == 0) {
+      out_cnt[row + 1] = 0;
+      rwords[row] = 0;
+    }
+    return;
+  }
+  const int64_t width = (int64_t)hi - lo + 1;
+  // lo and hi are columns of the output row, so nw is also the word count of
+  // the numeric pass's window over that row
+  const int nw = (int)((width + 31) >> 5);
+  if (out_cnt && lane == 0) rwords[row] = nw;
+  if (nw > wcap) {
+    if (out_cnt && lane == 0) ovf[atomicAdd(novf, 1)] = (int32_t)row;
+    return;
+  }
   for (int t = lane; t < nw; t += G) words[t] = 0u;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -1147,16 +1160,11 @@ __device__ __forceinline__ void win_union(uint32_t* words, int nw, int32_t lo, i
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// the set bits of nw words (read through get(t)) written in order as
-// columns lo + bit index; lane l owns words [l*wpl, (l+1)*wpl)
-template <int G, class Get>
-__device__ __forceinline__ int win_emit(int nw, int32_t lo, int lane, Get get, int32_t* out_row) {
+  // lane l owns words [l*wpl, (l+1)*wpl)
   const int wpl = (nw + G - 1) / G;
   const int w0 = lane * wpl, w1 = (w0 + wpl) < nw ? (w0 + wpl) : nw;
   int c = 0;
-  for (int t = w0; t < w1; t++) c += __popc(get(t));
+  for (int t = w0; t < w1; t++) c += __popc(words[t]);
   int incl = c;   // inclusive scan over the group
 #pragma unroll
   for (int m = 1; m < G; m <<= 1) {
@@ -1164,135 +1172,18 @@ __device__ __forceinline__ int win_emit(int nw, int32_t lo, int lane, Get get, i
     if (lane >= m) incl += o;
   }
   const int total = __shfl(incl, G - 1, G);
-  if (out_row) {
-    int32_t* out = out_row + (incl - c);
-    for (int t = w0; t < w1; t++) {
-      uint32_t m = get(t);
-      while (m) {
-        const int b = __builtin_ctz(m);
-        m &= m - 1u;
-        *out++ = lo + 32 * t + b;
-      }
-    }
-  }
-  return total;
-}
-
-// Both passes in one kernel (used when the rows' bitmaps are too many to
-// keep): the count pass lists rows wider than the window in ovf (when ovf
-// is given) and writes their word counts; the fill pass skips them.
-template <int G>
-__global__ __launch_bounds__(256) void k_spgemm_win(int64_t n, const int64_t* arp,
-                                                   const int32_t* acol, const int64_t* brp,
-                                                   const int32_t* bcol, int wcap,
-                                                   int64_t* out_cnt, const int64_t* crp,
-                                                   int32_t* ccol, int32_t* ovf, int* novf,
-                                                   int32_t* rwords) {
-  extern __shared__ uint32_t sbits[];
-  constexpr int NG = 256 / G;
-  const int g = threadIdx.x / G, lane = threadIdx.x % G;
-  uint32_t* words = sbits + (size_t)g * wcap;
-  const int64_t row = xcd_block(blockIdx.x, gridDim.x) * NG + g;
-  if (row >= n) return;   // whole group; the block never synchronises
-  const int64_t ea = arp[row], eb = arp[row + 1];
-  int32_t lo, hi;
-  win_bounds<G>(ea, eb, lane, acol, brp, bcol, lo, hi);
-  if (hi < 0) {   // empty output row
-    if (out_cnt && lane == 0) {
-      out_cnt[row + 1] = 0;
-      rwords[row] = 0;
-    }
+  if (out_cnt) {
+    if (lane == 0) out_cnt[row + 1] = total;
     return;
   }
-  // lo and hi are columns of the output row, so nw is also the word count of
-  // the numeric pass's window over that row
-  const int nw = (int)((((int64_t)hi - lo + 1) + 31) >> 5);
-  if (out_cnt && lane == 0) rwords[row] = nw;
-  if (nw > wcap) {
-    if (out_cnt && ovf && lane == 0) ovf[atomicAdd(novf, 1)] = (int32_t)row;
-    return;
-  }
-  win_union<G>(words, nw, lo, ea, eb, lane, acol, brp, bcol);
-  const int total = win_emit<G>(nw, lo, lane, [&](int t) { return words[t]; },
-                                out_cnt ? nullptr : ccol + crp[row]);
-  if (out_cnt && lane == 0) out_cnt[row + 1] = total;
-}
-
-// Stored-bitmap form, step 1: every row's window (first column wlo, word
-// count rwords, 0 for an empty row) and the words its stored bitmap takes
-// (wcnt, 0 for an empty row and for one wider than the window, which is
-// listed in ovf for the hash kernels).
-template <int G>
-__global__ __launch_bounds__(256) void k_spgemm_bounds(int64_t n, const int64_t* arp,
-                                                      const int32_t* acol, const int64_t* brp,
-                                                      const int32_t* bcol, int wcap,
-                                                      int32_t* wlo, int32_t* rwords,
-                                                      int64_t* wcnt, int32_t* ovf, int* novf) {
-  constexpr int NG = 256 / G;
-  const int g = threadIdx.x / G, lane = threadIdx.x % G;
-  const int64_t row = xcd_block(blockIdx.x, gridDim.x) * NG + g;
-  if (row >= n) return;
-  int32_t lo, hi;
-  win_bounds<G>(arp[row], arp[row + 1], lane, acol, brp, bcol, lo, hi);
-  if (lane != 0) return;
-  const int nw = hi < 0 ? 0 : (int)((((int64_t)hi - lo + 1) + 31) >> 5);
-  wlo[row] = hi < 0 ? 0 : lo;
-  rwords[row] = nw;
-  wcnt[row] = nw <= wcap ? nw : 0;
-  if (nw > wcap) ovf[atomicAdd(novf, 1)] = (int32_t)row;
-}
-
-// step 2: the LDS bitmap of every row within reach, stored at woff[row],
-// and its bit count (the output row's length)
-template <int G>
-__global__ __launch_bounds__(256) void k_spgemm_union(int64_t n, const int64_t* arp,
-                                                     const int32_t* acol, const int64_t* brp,
-                                                     const int32_t* bcol, int wcap,
-                                                     const int32_t* wlo, const int32_t* rwords,
-                                                     const int64_t* woff, uint32_t* bits,
-                                                     int64_t* out_cnt) {
-  extern __shared__ uint32_t sbits[];
-  constexpr int NG = 256 / G;
-  const int g = threadIdx.x / G, lane = threadIdx.x % G;
-  uint32_t* words = sbits + (size_t)g * wcap;
-  const int64_t row = xcd_block(blockIdx.x, gridDim.x) * NG + g;
-  if (row >= n) return;
-  const int nw = rwords[row];
-  if (nw == 0 || nw > wcap) return;   // empty (count 0 already) or a hash row
-  win_union<G>(words, nw, wlo[row], arp[row], arp[row + 1], lane, acol, brp, bcol);
-  uint32_t* dst = bits + woff[row];
-  int c = 0;
-  for (int t = lane; t < nw; t += G) {
-    const uint32_t w = words[t];
-    dst[t] = w;
-    c += __popc(w);
-  }
-#pragma unroll
-  for (int m = G / 2; m >= 1; m >>= 1) c += __shfl_xor(c, m, G);
-  if (lane == 0) out_cnt[row + 1] = c;
-}
-
-// step 3: the stored bitmaps written out as sorted column lists
-template <int G>
-__global__ __launch_bounds__(256) void k_spgemm_emit(int64_t n, int wcap, const int32_t* wlo,
-                                                    const int32_t* rwords, const int64_t* woff,
-                                                    const uint32_t* bits, const int64_t* crp,
-                                                    int32_t* ccol) {
-  constexpr int NG = 256 / G;
-  const int g = threadIdx.x / G, lane = threadIdx.x % G;
-  const int64_t row = xcd_block(blockIdx.x, gridDim.x) * NG + g;
-  if (row >= n) return;
-  const int nw = rwords[row];
-  if (nw == 0 || nw > wcap) return;
-  const uint32_t* src = bits + woff[row];
-  win_emit<G>(nw, wlo[row], lane, [&](int t) { return src[t]; }, ccol + crp[row]);
-}
-
-// total stored words and the number of rows beyond the window's reach
-__global__ void k_win_summary(const int64_t* wtot, const int* lerr, int64_t* out) {
-  if (threadIdx.x == 0) {
-    out[0] = *wtot;
-    out[1] = lerr[1];
+  int32_t* out = ccol + crp[row] + (incl - c);
+  for (int t = w0; t < w1; t++) {
+    uint32_t m = words[t];
+    while (m) {
+      const int b = __builtin_ctz(m);
+      m &= m - 1u;
+      *out++ = lo + 32 * t + b;
+    }
   }
 }
 
@@ -1302,8 +1193,7 @@ static void launch_win(int64_t n, const CsrView& A, const CsrView& B, int wcap, 
                        int32_t* rwords, hipStream_t s) {
   constexpr int NG = 256 / G;
   const size_t lds = (size_t)NG * wcap * sizeof(uint32_t);
-  HIP_OK(hipFuncSetAttribute((const void*)k_spgemm_win<G>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  allow_lds((const void*)k_spgemm_win<G>);
   k_spgemm_win<G><<<nblocks(n, NG), 256, lds, s>>>(n, A.rowptr, A.col, B.rowptr, B.col, wcap,
                                                    cnt, crp, ccol, ovf, novf, rwords);
 }
@@ -1318,26 +1208,6 @@ static void win_dispatch(int g, int64_t n, const CsrView& A, const CsrView& B, i
     case 32: launch_win<32>(n, A, B, wcap, cnt, crp, ccol, ovf, novf, rwords, s); break;
     default: launch_win<64>(n, A, B, wcap, cnt, crp, ccol, ovf, novf, rwords, s); break;
   }
-}
-
-// lanes per row as a compile-time constant
-template <class F>
-static void with_g(int g, F f) {
-  switch (g) {
-    case 4: f(std::integral_constant<int, 4>()); break;
-    case 8: f(std::integral_constant<int, 8>()); break;
-    case 16: f(std::integral_constant<int, 16>()); break;
-    case 32: f(std::integral_constant<int, 32>()); break;
-    default: f(std::integral_constant<int, 64>()); break;
-  }
-}
-
-// Device bytes the stored bitmaps of one product may take (beyond that the
-// fill pass recomputes them); EMIN_SPGEMM_BITMAP_MAX overrides the default.
-static int64_t bitmap_budget() {
-  const char* e = getenv("EMIN_SPGEMM_BITMAP_MAX");
-  if (e && *e) return (int64_t)strtoll(e, nullptr, 10);
-  return int64_t(1) << 30;
 }
 
 // hash kernels for a list of rows (those outside the window kernel's reach)
@@ -1366,53 +1236,12 @@ void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& pla
   int32_t* ovf = ar.alloc<int32_t>(A.nrows);    // rows wider than the window
   int32_t* ovf2 = ar.alloc<int32_t>(A.nrows);   // of those, rows the hash table cannot hold
   HIP_OK(hipMemsetAsync(lerr, 0, 4 * sizeof(int), s));
-  // every row's window, and the offsets of the rows' bitmaps if stored
-  int32_t* wlo = ar.alloc<int32_t>(A.nrows);
-  int64_t* woff = ar.alloc<int64_t>(A.nrows + 1);
-  HIP_OK(hipMemsetAsync(woff, 0, sizeof(int64_t), s));
   if (A.nrows)
-    with_g(g, [&](auto gc) {
-      constexpr int G = decltype(gc)::value;
-      k_spgemm_bounds<G><<<nblocks(A.nrows, 256 / G), 256, 0, s>>>(
-          A.nrows, A.rowptr, A.col, B.rowptr, B.col, wcap, wlo, rwords, woff + 1, ovf, lerr + 1);
-    });
-  scan_inclusive(woff + 1, A.nrows, s, ar);
-  int64_t* wq = ar.alloc<int64_t>(2);
-  k_win_summary<<<1, 64, 0, s>>>(woff + A.nrows, lerr, wq);
-  int64_t hw[2];
-  HIP_OK(hipMemcpyAsync(hw, wq, sizeof(hw), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipStreamSynchronize(s));
-  const int64_t twords = hw[0];
-  const int nwide = (int)hw[1];
-  // The union runs once and its bitmaps are kept for the fill pass when they
-  // fit the budget; otherwise the fill pass recomputes them.  Large ones take
-  // a cached device chunk, returned once the fill pass has finished.
-  const size_t bbytes = (size_t)(twords > 0 ? twords : 1) * sizeof(uint32_t);
-  const bool stored = (int64_t)bbytes <= bitmap_budget();
-  const bool big_bits = stored && bbytes > (size_t(4) << 20);
-  uint32_t* bits = nullptr;
-  ChunkLease lease;
-  if (big_bits) {
-    bits = static_cast<uint32_t*>(lease.take(bbytes, s));
-  } else if (stored) {
-    bits = ar.alloc<uint32_t>(bbytes / sizeof(uint32_t));
-  }
-  if (A.nrows) {
-    if (stored)
-      with_g(g, [&](auto gc) {
-        constexpr int G = decltype(gc)::value;
-        const size_t lds = (size_t)(256 / G) * wcap * sizeof(uint32_t);
-        HIP_OK(hipFuncSetAttribute((const void*)k_spgemm_union<G>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        k_spgemm_union<G><<<nblocks(A.nrows, 256 / G), 256, lds, s>>>(
-            A.nrows, A.rowptr, A.col, B.rowptr, B.col, wcap, wlo, rwords, woff, bits,
-            C.rowptr);
-      });
-    else
-      win_dispatch(g, A.nrows, A, B, wcap, C.rowptr, nullptr, nullptr, nullptr, nullptr, rwords,
-                   s);
-  }
+    win_dispatch(g, A.nrows, A, B, wcap, C.rowptr, nullptr, nullptr, ovf, lerr + 1, rwords, s);
   int hl[4];
+  HIP_OK(hipMemcpyAsync(hl, lerr, sizeof(hl), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  const int nwide = hl[1];
   // table per group within ~48 KiB per block (keys + compacted copy)
   int hcap = 64;
   while ((size_t)NG * 3 * hcap * sizeof(int32_t) <= 48 * 1024 && hcap < 4096) hcap <<= 1;
@@ -1471,17 +1300,8 @@ void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& pla
   // the window fill skips the wide rows; the hash kernels fill those (the
   // first hash fill skips the rows its table could not hold; the big table
   // does them)
-  if (A.nrows) {
-    if (stored)
-      with_g(pick_g(A.nrows ? (double)twords / (double)A.nrows : 1.0), [&](auto gc) {
-        constexpr int G = decltype(gc)::value;
-        k_spgemm_emit<G><<<nblocks(A.nrows, 256 / G), 256, 0, s>>>(A.nrows, wcap, wlo, rwords,
-                                                                    woff, bits, C.rowptr, C.col);
-      });
-    else
-      win_dispatch(g, A.nrows, A, B, wcap, nullptr, C.rowptr, C.col, nullptr, nullptr, nullptr,
-                   s);
-  }
+  if (A.nrows)
+    win_dispatch(g, A.nrows, A, B, wcap, nullptr, C.rowptr, C.col, nullptr, nullptr, nullptr, s);
   if (nwide) {
     switch (g) {
       case 4: launch_sym_rows<4>(ovf, nwide, A, B, hcap, nullptr, C.rowptr, C.col, ovf2, lerr + 3, lerr, s); break;
@@ -1494,7 +1314,6 @@ void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& pla
   }
   if (derr) k_defer_err<<<1, 64, 0, s>>>(lerr, derr);
   else if (d2h(lerr, s)) throw Error(EMIN_ERR_CAPACITY, "spgemm: fill pass overflow");
-
   const double avg_b = B.nrows ? (double)B.nnz / (double)B.nrows : 1.0;
   int gn = pick_g(avg_b);
   // enough lanes per row that the longest output row fits the LDS budget
@@ -1508,8 +1327,7 @@ static void launch_num(const CsrView& A, const TV* aval, const CsrView& B, const
                        hipStream_t s) {
   constexpr int NG = 256 / G;
   const size_t lds = (size_t)NG * ((size_t)iw * sizeof(uint32_t) + cap * sizeof(TV));
-  HIP_OK(hipFuncSetAttribute((const void*)k_spgemm_num<G, TV, TO>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  allow_lds((const void*)k_spgemm_num<G, TV, TO>);
   SplitArgsT<TV> rows_only;
   rows_only.poff = plan.ntasks ? plan.poff : nullptr;
   k_spgemm_num<G, TV, TO><<<nblocks(A.nrows, NG), 256, lds, s>>>(
@@ -1697,8 +1515,7 @@ void spgemm_numeric_aat(const CsrView& A, const CsrView& At, const Csr& C, const
     return;
   }
   prof::Scope ps(s, EMIN_PROF_SPGEMM, 12.0 * (double)(A.nnz + At.nnz + C.nnz));
-  HIP_OK(hipFuncSetAttribute((const void*)k_spgemm_aat,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  allow_lds((const void*)k_spgemm_aat);
   k_spgemm_aat<<<(unsigned)A.nrows, 64, lds, s>>>(A.rowptr, A.col, A.val, C.rowptr, C.col, C.val,
                                                   A.nrows, (int)iw);
 }

@@ -94,61 +94,22 @@ __global__ __launch_bounds__(64 * VB_WAVES) void k_vbfs(const int64_t* grp, cons
 // at or after the cursor is converted, then its distance-3 ball is covered.
 // Visited marks: with nwin > 0, a bitmap in LDS over the index window
 // j ± 3·bw of the ball (bw = the graph's index bandwidth), cleared per ball;
-// otherwise per-vertex stamps in global memory.  With nel > 0 the nodes that
-// may still convert are kept as a bitmap in LDS (bits cleared as balls are
-// covered), so finding the next one is an LDS sweep from the cursor instead
-// of a pass over three flag arrays in memory.
+// otherwise per-vertex stamps in global memory.
 __global__ __launch_bounds__(1024) void k_vextras(const int64_t* grp, const int32_t* gcol,
                                                   int64_t n, const uint8_t* dir, uint8_t* cv,
                                                   uint8_t* cov, int32_t* vis, int32_t* extra,
                                                   int32_t* nextra, int ballcap, int deg_cap,
-                                                  int64_t bw, int nwin, int nel, int* err) {
+                                                  int64_t bw, int nwin, int* err) {
   extern __shared__ int32_t ball[];
   uint32_t* win = reinterpret_cast<uint32_t*>(ball + ballcap);
-  uint32_t* elig = win + nwin;   // nel > 0: bit v set while v may convert
   __shared__ int found_sh, nb_sh, ne_sh, bad_sh;
   const int tid = threadIdx.x;
   if (tid == 0) { ne_sh = 0; bad_sh = 0; }
-  for (int w = tid; w < nel; w += 1024) {
-    const int64_t v0 = (int64_t)w * 32;
-    uint32_t m = 0u;
-    if (v0 + 32 <= n) {   // (the flag arrays are 256-byte aligned)
-#pragma unroll
-      for (int h = 0; h < 4; h++) {
-        const uint64_t bad = reinterpret_cast<const uint64_t*>(cv + v0)[h] |
-                             reinterpret_cast<const uint64_t*>(dir + v0)[h] |
-                             reinterpret_cast<const uint64_t*>(cov + v0)[h];
-#pragma unroll
-        for (int q = 0; q < 8; q++)
-          if (((bad >> (8 * q)) & 0xFFu) == 0u) m |= 1u << (8 * h + q);
-      }
-    } else {
-      for (int64_t v = v0; v < n; v++)
-        if (!cv[v] && !dir[v] && !cov[v]) m |= 1u << (int)(v - v0);
-    }
-    elig[w] = m;
-  }
   int64_t cursor = 0;
   int32_t stamp = 0;
   while (true) {
     if (tid == 0) found_sh = INT32_MAX;
     __syncthreads();
-    if (nel) {
-      // the bitmap from the cursor's word on, 1024 words per pass
-      for (int64_t wb = cursor >> 5; wb < nel; wb += 1024) {
-        const int64_t w = wb + tid;
-        uint32_t m = 0u;
-        if (w < nel) {
-          m = elig[w];
-          if (w == (cursor >> 5)) m &= ~0u << (cursor & 31);
-        }
-        first_lane_min(&found_sh, m != 0u, (int)(w * 32 + (m ? __builtin_ctz(m) : 0)));
-        __syncthreads();
-        const int ff = found_sh;
-        __syncthreads();
-        if (ff != INT32_MAX) break;
-      }
-    } else
     // eight flags per thread per pass (vertices before the cursor are never
     // eligible again, so the pass may start at the aligned position below it)
     for (int64_t base = cursor & ~(int64_t)7; base < n; base += 8 * 1024) {
@@ -164,7 +125,7 @@ __global__ __launch_bounds__(1024) void k_vextras(const int64_t* grp, const int3
         for (int64_t v = v0; v < n; v++)
           if (!cv[v] && !dir[v] && !cov[v]) { f = (int)v; break; }
       }
-      first_lane_min(&found_sh, f != INT32_MAX, f);
+      if (f != INT32_MAX) atomicMin(&found_sh, f);
       __syncthreads();
       const int ff = found_sh;
       __syncthreads();
@@ -222,11 +183,7 @@ __global__ __launch_bounds__(1024) void k_vextras(const int64_t* grp, const int3
       le = min(nb_sh, ballcap);
       __syncthreads();
     }
-    for (int t = tid; t < le; t += 1024) {
-      const int32_t u = ball[t];
-      cov[u] = 1;
-      if (nel) atomicAnd(&elig[u >> 5], ~(1u << (u & 31)));
-    }
+    for (int t = tid; t < le; t += 1024) cov[ball[t]] = 1;
     __syncthreads();
     stamp++;
     cursor = (int64_t)j + 1;
@@ -331,16 +288,11 @@ void velocity_pattern(const Csr& G, const uint8_t* dir, uint8_t* cv, VPatternOut
   const int64_t bw = hq[3];
   const int64_t words = (6 * bw + 1 + 31) / 32;
   const int nwin = (int64_t)ballcap * 4 + words * 4 + 64 <= lds_max ? (int)words : 0;
-  // eligibility bitmap in LDS when it fits beside both (else the scan for
-  // the next point reads the flags from memory)
-  const int64_t ewords = (n + 31) / 32;
-  const int nel = (int64_t)ballcap * 4 + (int64_t)nwin * 4 + ewords * 4 + 64 <= lds_max ? (int)ewords : 0;
-  const size_t lds = (size_t)ballcap * 4 + (size_t)nwin * 4 + (size_t)nel * 4;
-  HIP_OK(hipFuncSetAttribute((const void*)k_vextras, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)lds));
+  const size_t lds = (size_t)ballcap * 4 + (size_t)nwin * 4;
+  allow_lds((const void*)k_vextras);
   prof::Scope ps(s, EMIN_PROF_VPAT, 0.0);
   k_vextras<<<1, 1024, lds, s>>>(G.rowptr, G.col, n, dir, cv, cov, vis, extra, nextra, ballcap,
-                                  deg_cap, bw, nwin, nel, err);
+                                  deg_cap, bw, nwin, err);
   HIP_OK(hipGetLastError());
   out.n_extra = d2h(nextra, s);
   if (out.n_extra)

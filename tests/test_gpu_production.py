@@ -185,48 +185,3 @@ def test_pattern_values_flag_equals_full_setup():
         assert np.array_equal(ac, L.Ac.cpu().numpy())
     H.close()
 
-
-def test_symbolic_bitmap_forms_agree():
-    """The symbolic products keep each row's column bitmap for the fill pass
-    (in the handle's arena when small, in a cached device chunk when large)
-    or, beyond a byte budget, recompute it.  Both forms must give the same
-    patterns, drop masks and values, bit for bit (3-D Stokes 32^3, whose
-    Galerkin products take the large form)."""
-    import os
-    import torch
-    from paper_1607_02489_amd import emin as E
-    s = synth.make_system(3, 32, jitter=0.05, seed=3)
-    prm = E.params(iters=3)
-    views = (E.VIEW_PV, E.VIEW_PP, E.VIEW_AC, E.VIEW_BC)
-
-    def run():
-        H = E.Hierarchy(s, 3, prm).build()
-        torch.cuda.synchronize()
-        out = []
-        for L in H.levels:
-            pats = [L.pattern.csr_host(v)[2:4] for v in views]
-            keep = L.pattern.array_host(E.VIEW_KEEPP, np.uint8)
-            vals = [t.cpu().numpy().copy() for t in (L.Pv, L.Pp, L.Ac, L.Bc)]
-            out.append((pats, keep, vals))
-        H.close()
-        return out
-
-    say("symbolic bitmaps: stored")
-    stored = run()
-    old = os.environ.get("EMIN_SPGEMM_BITMAP_MAX")
-    os.environ["EMIN_SPGEMM_BITMAP_MAX"] = "0"
-    try:
-        say("symbolic bitmaps: recomputed")
-        again = run()
-    finally:
-        if old is None:
-            del os.environ["EMIN_SPGEMM_BITMAP_MAX"]
-        else:
-            os.environ["EMIN_SPGEMM_BITMAP_MAX"] = old
-    assert len(stored) == len(again) >= 2
-    for (pa, ka, va), (pb, kb, vb) in zip(stored, again):
-        for (ra, ca), (rb, cb) in zip(pa, pb):
-            assert np.array_equal(ra, rb) and np.array_equal(ca, cb)
-        assert np.array_equal(ka, kb)
-        for a, b in zip(va, vb):
-            assert np.array_equal(a, b)
