@@ -11,6 +11,8 @@
 #include "emin_cg.h"
 #include "prof.h"
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -870,13 +872,25 @@ void autotune_clear() {
   g_tune_stats[0] = g_tune_stats[1] = g_tune_stats[2] = 0;
 }
 
+// (when the product is timed, the launch itself records the events at the
+// kernel's start and end, so the time excludes the gaps between launches)
 template <class TM, class TX, class TY>
 static void spmm_any(const EminWork& w, const Csr& M, const TM* mval, const int64_t* nrp,
-                     const int32_t* ncol, const TX* X, TY* Y, const double* D, hipStream_t s) {
+                     const int32_t* ncol, const TX* X, TY* Y, const double* D, double bytes,
+                     hipStream_t s) {
   const int64_t nb = w.sched.blk_off[SPMM_NT];
   if (nb == 0) return;
-  k_spmm<TM, TX, TY><<<(unsigned)nb, SPMM_BS, 0, s>>>(w.sched, M.rowptr, M.col, mval, w.kofs, w.nib,
-                                                   w.nnzm, nrp, ncol, X, Y, D, w.rowdot);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (prof::begin_launch(s, EMIN_PROF_SPMM, bytes, 0.0, &e0, &e1)) {
+    hipExtLaunchKernelGGL(k_spmm<TM, TX, TY>, dim3((unsigned)nb), dim3(SPMM_BS), 0, s, e0, e1, 0,
+                          w.sched, (const int64_t*)M.rowptr, (const int32_t*)M.col, mval,
+                          (const int32_t*)w.kofs, (const uint32_t*)w.nib, w.nnzm, nrp, ncol, X,
+                          Y, D, w.rowdot);
+    HIP_OK(hipGetLastError());
+  } else {
+    k_spmm<TM, TX, TY><<<(unsigned)nb, SPMM_BS, 0, s>>>(w.sched, M.rowptr, M.col, mval, w.kofs,
+                                                     w.nib, w.nnzm, nrp, ncol, X, Y, D, w.rowdot);
+  }
 }
 
 // The values the finaliser sums for <D, Y> (rows with an empty pattern keep
@@ -906,10 +920,7 @@ static double spmm_bytes(const EminWork& w, const Csr& M, bool mixed) {
 int64_t masked_spmm(const EminWork& w, const Csr& M, const int64_t* nrp, const int32_t* ncol,
                     const double* X, double* Y, const double* D, double* part,
                     const double** dots, hipStream_t s) {
-  {
-    prof::Scope ps(s, EMIN_PROF_SPMM, spmm_bytes(w, M, false));
-    spmm_any<double, double, double>(w, M, M.val, nrp, ncol, X, Y, D, s);
-  }
+  spmm_any<double, double, double>(w, M, M.val, nrp, ncol, X, Y, D, spmm_bytes(w, M, false), s);
   return D ? rowdot_partials(w, part, dots, s) : 0;
 }
 
@@ -931,10 +942,8 @@ void run_emin(EminWork& w, const Csr& M, const float* Mf, const int64_t* nrp, co
   if (mixed) k_to_float<<<nblocks(nnz, 256), 256, 0, s>>>(w.Z, w.Zf, nnz);
   for (int it = 0; it < iters; it++) {
     if (mixed) {
-      {
-        prof::Scope ps(s, EMIN_PROF_SPMM, spmm_bytes(w, M, true));
-        spmm_any<float, float, float>(w, M, Mf, nrp, ncol, w.Zf, w.Qf, w.Z, s);
-      }
+      spmm_any<float, float, float>(w, M, Mf, nrp, ncol, w.Zf, w.Qf, w.Z, spmm_bytes(w, M, true),
+                                    s);
       np = rowdot_partials(w, w.part, &dots, s);
     } else {
       np = masked_spmm(w, M, nrp, ncol, w.Z, w.Q, w.Z, w.part, &dots, s);

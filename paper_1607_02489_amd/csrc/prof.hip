@@ -45,6 +45,19 @@ int begin(hipStream_t s, int kind, double bytes, double flops) {
   return (int)recs.size() - 1;
 }
 
+bool begin_launch(hipStream_t s, int kind, double bytes, double flops, hipEvent_t* e0,
+                  hipEvent_t* e1) {
+  if (!enabled(kind)) return false;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return false;
+  std::lock_guard<std::mutex> g(mu);
+  Rec r{kind, bytes, flops, get_event(), get_event()};
+  recs.push_back(r);
+  *e0 = r.e0;
+  *e1 = r.e1;
+  return true;
+}
+
 void end(int token, hipStream_t s) {
   std::lock_guard<std::mutex> g(mu);
   if (token >= 0 && token < (int)recs.size()) (void)hipEventRecord(recs[token].e1, s);
