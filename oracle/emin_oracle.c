@@ -759,9 +759,15 @@ static int32_t *cidx_of(const uint8_t *flag, int64_t n, int64_t *nc) {
   return c;
 }
 
+/* One level of Alg. 1.  The EMIN energy of the velocity block (sec. 4.3, eq.
+ * (min_problem)) is the norm of the symmetrised filtered operator
+ * M = (A~ + A~^T)/2, or with energy_ata the A^T A-norm the section names for
+ * non-symmetric operators: M = A~^T A~.  Either way the distance-3 velocity
+ * pattern is grown on the symmetrised filtered graph, and L->Mv is the
+ * energy operator EMIN used. */
 int orc_level(int dim, const orc_csr *Ahat, const orc_csr *Bdiv,
               const double *xv, const int32_t *p2v,
-              double tau1_v, double tau1_p, double tau2_sq, int iters,
+              double tau1_v, double tau1_p, double tau2_sq, int iters, int energy_ata,
               orc_level_t *L) {
   memset(L, 0, sizeof(*L));
   L->dim = dim;
@@ -784,7 +790,14 @@ int orc_level(int dim, const orc_csr *Ahat, const orc_csr *Bdiv,
   orc_filter(&Z, tau1_p, &Atp, L->keep_p);
   orc_filter(Ahat, tau1_v, &Atv, L->keep_v);
   orc_symmetrize(&Atp, &L->Mp);
-  orc_symmetrize(&Atv, &L->Mv);
+  orc_csr Gv; /* velocity graph: the symmetrised filtered operator */
+  orc_symmetrize(&Atv, &Gv);
+  if (energy_ata) {
+    orc_csr AtvT;
+    orc_transpose(&Atv, &AtvT);
+    orc_spgemm(&AtvT, &Atv, &L->Mv);
+    orc_csr_free(&AtvT);
+  }
   orc_csr_free(&BT); orc_csr_free(&Z); orc_csr_free(&Atp); orc_csr_free(&Atv);
   L->dir = (uint8_t *)malloc((size_t)(nv > 0 ? nv : 1));
   orc_dirichlet(Ahat, L->dir);
@@ -803,7 +816,9 @@ int orc_level(int dim, const orc_csr *Ahat, const orc_csr *Bdiv,
   L->is_cv = (uint8_t *)calloc((size_t)(nv > 0 ? nv : 1), 1);
   for (int64_t i = 0; i < np; i++)
     if (L->cbar[i]) L->is_cv[p2v[i]] = 1;
-  orc_velocity_pattern(&L->Mv, L->dir, L->is_cv, &L->Pv, &L->n_extra_v);
+  orc_velocity_pattern(&Gv, L->dir, L->is_cv, &L->Pv, &L->n_extra_v);
+  if (energy_ata) orc_csr_free(&Gv);
+  else L->Mv = Gv;
   int64_t ncv, ncp;
   int32_t *cv_id = cidx_of(L->is_cv, nv, &ncv);
   int32_t *cp_id = cidx_of(L->is_cp, np, &ncp);

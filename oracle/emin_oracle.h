@@ -114,7 +114,7 @@ typedef struct {
 
 int orc_level(int dim, const orc_csr *Ahat, const orc_csr *Bdiv,
               const double *xv, const int32_t *p2v,
-              double tau1_v, double tau1_p, double tau2_sq, int iters,
+              double tau1_v, double tau1_p, double tau2_sq, int iters, int energy_ata,
               orc_level_t *out);
 void orc_level_free(orc_level_t *L);
 

@@ -81,7 +81,8 @@ def lib():
         L.orc_rap.argtypes = [P(c_csr), P(c_csr), C.c_int, P(c_csr), P(c_csr), P(c_csr),
                               P(c_csr)]
         L.orc_level.argtypes = [C.c_int, P(c_csr), P(c_csr), P(C.c_double), P(C.c_int32),
-                                C.c_double, C.c_double, C.c_double, C.c_int, P(c_level)]
+                                C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
+                                P(c_level)]
         L.orc_level_free.argtypes = [P(c_level)]
         _lib = L
     return _lib
@@ -298,13 +299,18 @@ class Level:
 
 
 def level(sys: System, tau1_v: float = TAU1, tau1_p: float = TAU1, tau2_sq: float = TAU2_SQ,
-          iters: int = 5) -> Level:
+          iters: int = 5, energy_ata: bool = False) -> Level:
+    """One level of Alg. 1 (orc_level).  energy_ata: the velocity block's EMIN
+    energy is the A^T A-norm of the filtered operator (sec. 4.3, eq.
+    (min_problem), for non-symmetric operators) instead of the norm of its
+    symmetric part; the velocity graph is the same either way."""
     a, b = _In(sys.Ahat), _In(sys.Bdiv)
     xv = np.ascontiguousarray(sys.xv, dtype=np.float64)
     p2v = np.ascontiguousarray(sys.p2v, dtype=np.int32)
     L = c_level()
     st = lib().orc_level(sys.dim, C.byref(a.c), C.byref(b.c), _ptr(xv, C.c_double),
-                         _ptr(p2v, C.c_int32), tau1_v, tau1_p, tau2_sq, iters, C.byref(L))
+                         _ptr(p2v, C.c_int32), tau1_v, tau1_p, tau2_sq, iters,
+                         1 if energy_ata else 0, C.byref(L))
     try:
         _check(st)
         nv, np_, d = sys.n_v, sys.n_p, sys.dim

@@ -436,3 +436,33 @@ def test_table2_first_coarse_size(oracle_lib):
     L = O.level(s, iters=1)
     n1 = 2 * int(L.is_cv.sum()) + int(L.is_cp.sum())
     assert 28088 <= n1 <= 74428
+
+
+def test_emin_ata_energy_operator_pattern_and_minimum(oracle_lib):
+    """Sec. 4.3, eq. (min_problem): the A^T A-norm for a non-symmetric block.
+    On an Oseen system (non-symmetric filtered operator A~): the energy
+    operator is dense(A~)^T dense(A~) (a transposed product would fail, as
+    A~ A~^T differs), the velocity pattern is the one the symmetrised graph
+    gives (the norm changes, the graph does not), CG run to convergence
+    reaches the dense KKT minimum of trace(P^T A~^T A~ P), and the energy
+    falls at every step."""
+    O = oracle_lib
+    s = synth.make_system(2, 4, jitter=0.1, nu=0.05, wind="stream", seed=11)
+    At, _ = O.filter_lump(s.Ahat, 0.06)
+    Ad = dense(At)
+    assert np.abs(Ad - Ad.T).max() > 1e-3 * np.abs(Ad).max()   # non-symmetric
+    Lsym = O.level(s, iters=0)
+    L = O.level(s, iters=0, energy_ata=True)
+    assert relfro(dense(L.Mv), Ad.T @ Ad) <= 1e-14
+    assert relfro(dense(L.Mv), Ad @ Ad.T) > 1e-3
+    assert np.array_equal(L.Pv.rowptr, Lsym.Pv.rowptr) and np.array_equal(L.Pv.col, Lsym.Pv.col)
+    assert np.array_equal(L.is_cv, Lsym.is_cv)
+    # the pressure block keeps the A-norm of its symmetric operator
+    assert np.array_equal(L.Mp.val, Lsym.Mp.val)
+    Wv, Wvc, cidv, _ = _modes(L, s)
+    ref = kkt_emin(Ad.T @ Ad, L.Pv, cidv, Wv, Wvc)
+    Lc = O.level(s, iters=300, energy_ata=True)
+    assert relfro(Lc.Pv.val, ref) <= 1e-10
+    Lk = O.level(s, iters=8, energy_ata=True)
+    e = Lk.energy_v[: Lk.its_v + 1]
+    assert len(e) > 2 and np.all(np.diff(e) <= 1e-13 * abs(e[0]))
