@@ -65,7 +65,8 @@ def cpu_baseline(system, wl, seconds, p_nnz_iters):
     while True:
         t0 = time.perf_counter()
         levels, _ = O.hierarchy(system, wl["nlevels"], tau1_v=wl["tau1_v"], tau1_p=wl["tau1_p"],
-                                iters=wl["iters"], min_dofs=wl["min_dofs"])
+                                iters=wl["iters"], min_dofs=wl["min_dofs"],
+                                energy_ata=wl.get("energy_ata", False))
         times.append(time.perf_counter() - t0)
         if time.perf_counter() >= t_end:
             break
@@ -404,6 +405,8 @@ def main():
                     choices=sorted(WORKLOADS) + ["batch64_oseen2d", "serve_oseen3d_channel",
                                                  "copy_probe"])
     ap.add_argument("--mixed", action="store_true", help="FP32 masked products, FP64 projection/scalars")
+    ap.add_argument("--energy-ata", action="store_true",
+                    help="velocity EMIN energy in the A^T A-norm of the filtered operator")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
@@ -443,7 +446,9 @@ def main():
     system = wl["make"](synth)
     log(f"[bench] generated {args.workload}: dofs={system.dofs} in {time.perf_counter() - t0:.1f}s")
     torch.cuda.init()
-    prm = E.params(wl["tau1_v"], wl["tau1_p"], 1.5e-3, wl["iters"], mixed=mixed)
+    ata = bool(args.energy_ata)
+    wl = dict(wl, energy_ata=ata)
+    prm = E.params(wl["tau1_v"], wl["tau1_p"], 1.5e-3, wl["iters"], mixed=mixed, energy_ata=ata)
     H = E.Hierarchy(system, wl["nlevels"], prm, min_dofs=wl["min_dofs"])
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
@@ -523,7 +528,8 @@ def main():
     fp64_plain = None
     H64 = None
     if mixed:
-        prm64 = E.params(wl["tau1_v"], wl["tau1_p"], 1.5e-3, wl["iters"], mixed=False)
+        prm64 = E.params(wl["tau1_v"], wl["tau1_p"], 1.5e-3, wl["iters"], mixed=False,
+                         energy_ata=ata)
         H64 = E.Hierarchy(system, wl["nlevels"], prm64, min_dofs=wl["min_dofs"])
         H64.build()
         torch.cuda.synchronize()
@@ -542,7 +548,8 @@ def main():
     if roof is not None:
         roof["copy_gbs"] = round(copy_gbs, 1)
         roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
-        roof["traffic"] = load_traffic("k_spmm", args.workload, "mixed" if mixed else "fp64")
+        roof["traffic"] = load_traffic("k_spmm", args.workload,
+                                       ("mixed" if mixed else "fp64") + ("_ata" if ata else ""))
 
     cpu = None
     oracle_levels = None
@@ -574,7 +581,8 @@ def main():
         "config": {"workload": args.workload, "description": wl["desc"], "dofs": system.dofs,
                    "levels": len(levels) + 1, "iters": wl["iters"], "tau1_v": wl["tau1_v"],
                    "tau1_p": wl["tau1_p"], "tau2_sq": 1.5e-3,
-                   "precision": "mixed" if mixed else "fp64"},
+                   "precision": "mixed" if mixed else "fp64",
+                   "energy_v": "A^T A" if ata else "(A + A^T)/2"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "accuracy": acc,

@@ -64,11 +64,19 @@ enum {
   EMIN_FLAG_AUTOTUNE = 4u,  /* emin_pattern: time candidate schedules of the masked
                                product on this pattern (or reuse the choice made for
                                the same problem shape) and keep the fastest */
-  EMIN_FLAG_PATTERN_VALUES = 8u  /* emin_setup: the system's values are still those the
+  EMIN_FLAG_PATTERN_VALUES = 8u, /* emin_setup: the system's values are still those the
                                     handle's emin_pattern call was given, so the
                                     filtered operators that call formed are reused
                                     instead of being formed again (the caller vouches
                                     for it; nothing checks the values) */
+  EMIN_FLAG_ENERGY_ATA = 16u     /* sec. 4.3, eq. (min_problem): the velocity block's
+                                    energy is the A^T A-norm of the filtered operator,
+                                    trace(P^T A~^T A~ P), the norm the section names for
+                                    non-symmetric operators, instead of the norm of its
+                                    symmetric part; the velocity graph and the pressure
+                                    block are unchanged.  emin_pattern forms A~^T A~;
+                                    emin_setup must pass the same flag (EMIN_ERR_ARG
+                                    otherwise).  EMIN_VIEW_MV is then A~^T A~. */
 };
 #define EMIN_MAX_ITERS 32
 

@@ -341,7 +341,8 @@ def level(sys: System, tau1_v: float = TAU1, tau1_p: float = TAU1, tau2_sq: floa
 
 
 def hierarchy(sys: System, nlevels: int, tau1_v: float = TAU1, tau1_p: float = TAU1,
-              tau2_sq: float = TAU2_SQ, iters: int = 5, min_dofs: int = 0):
+              tau2_sq: float = TAU2_SQ, iters: int = 5, min_dofs: int = 0,
+              energy_ata: bool = False):
     """Alg. 1 without relaxation: levels 0..nlevels-1 (nlevels-1 transfers),
     stopping early when a level has at most min_dofs dofs."""
     out = []
@@ -349,7 +350,7 @@ def hierarchy(sys: System, nlevels: int, tau1_v: float = TAU1, tau1_p: float = T
     for _ in range(nlevels - 1):
         if cur.dofs <= min_dofs:
             break
-        L = level(cur, tau1_v, tau1_p, tau2_sq, iters)
+        L = level(cur, tau1_v, tau1_p, tau2_sq, iters, energy_ata=energy_ata)
         out.append(L)
         cur = L.coarse_system()
     return out, cur

@@ -21,6 +21,12 @@ struct emin_pattern_s {
   uint8_t *keep_p = nullptr, *keep_v = nullptr;
   Csr Atp, Atv, Mp, Mv;
   int32_t *mp_ia = nullptr, *mp_ib = nullptr, *mv_ia = nullptr, *mv_ib = nullptr;
+  // EMIN_FLAG_ENERGY_ATA: the velocity energy operator A~^T A~ (Mv stays the
+  // velocity graph)
+  bool ata = false;
+  Csr AtvT, Ev;
+  int32_t* atvt_src = nullptr;
+  SpgemmPlan evplan;
   float *Mpf = nullptr, *Mvf = nullptr;
   uint8_t* dir = nullptr;
   double* xp = nullptr;
@@ -156,6 +162,15 @@ int pick_lanes(const Csr& M) {
   return g;
 }
 
+// the operator whose norm EMIN minimises on the velocity block
+static const Csr& energy_v(const emin_pattern_t* h) { return h->ata ? h->Ev : h->Mv; }
+
+// E = A~^T A~ from the filtered operator's current values
+static void ata_numeric(emin_pattern_t* h, hipStream_t s) {
+  gather_values(h->Atv.val, h->atvt_src, h->AtvT.val, h->AtvT.nnz, s);
+  spgemm_numeric(view(h->AtvT), view(h->Atv), h->Ev, h->evplan, s);
+}
+
 void build_pattern(emin_pattern_t* h, const emin_system_t* sys, const emin_params_t* prm,
                    hipStream_t s) {
   Arena& ar = h->ar;
@@ -200,6 +215,14 @@ void build_pattern(emin_pattern_t* h, const emin_system_t* sys, const emin_param
   filter_symbolic(A, prm->tau1_v, h->dA, h->keep_v, h->Atv, s, ar);
   symmetrize_symbolic(h->Atv, h->Mv, h->mv_ia, h->mv_ib, s, ar);
   symmetrize_numeric(h->Atv.val, h->mv_ia, h->mv_ib, h->Mv, s);
+  // sec. 4.3, eq. (min_problem): the A^T A-norm for a non-symmetric block
+  h->ata = (prm->flags & EMIN_FLAG_ENERGY_ATA) != 0;
+  if (h->ata) {
+    transpose_pattern(view(h->Atv), h->AtvT, h->atvt_src, s, ar);
+    h->AtvT.val = ar.alloc<double>(h->AtvT.nnz);
+    spgemm_symbolic(view(h->AtvT), view(h->Atv), h->Ev, h->evplan, s, ar, h->derr);
+    ata_numeric(h, s);
+  }
   h->dir = ar.alloc<uint8_t>(nv);
   dirichlet_rows(A, h->dir, s);
 
@@ -225,15 +248,15 @@ void build_pattern(emin_pattern_t* h, const emin_system_t* sys, const emin_param
   const bool mixed = true;  // FP32 copies are allocated so either mode can run
   h->ev.allocate(nv, h->vp.N.nnz, h->vp.n_c, ar, mixed);
   h->ep.allocate(np, h->cp.N.nnz, h->cp.n_c, ar, mixed);
-  h->ev.g = pick_lanes(h->Mv);
+  h->ev.g = pick_lanes(energy_v(h));
   h->ep.g = pick_lanes(h->Mp);
   h->ev.smax = (int)max_row_len(h->vp.N.rowptr, nv, s, ar);
   h->ep.smax = (int)max_row_len(h->cp.N.rowptr, np, s, ar);
   if (h->ev.smax > 64 || h->ep.smax > 64) throw Error(EMIN_ERR_CAPACITY, "pattern row > 64");
   const bool tune = (prm->flags & EMIN_FLAG_AUTOTUNE) != 0;
-  h->ev.make_bins(h->Mv, h->vp.N.rowptr, h->vp.N.col, s, ar, tune);
+  h->ev.make_bins(energy_v(h), h->vp.N.rowptr, h->vp.N.col, s, ar, tune);
   h->ep.make_bins(h->Mp, h->cp.N.rowptr, h->cp.N.col, s, ar, tune);
-  h->Mvf = ar.alloc<float>(h->Mv.nnz);
+  h->Mvf = ar.alloc<float>(energy_v(h).nnz);
   h->Mpf = ar.alloc<float>(h->Mp.nnz);
   h->Wv_def = ar.alloc<double>(nv);
   h->Wp_def = ar.alloc<double>(np);
@@ -288,7 +311,7 @@ void build_pattern(emin_pattern_t* h, const emin_system_t* sys, const emin_param
   z.n_cv_extra = h->vp.n_extra;
   z.nnz_Pv = h->vp.N.nnz;
   z.nnz_Pp = h->cp.N.nnz;
-  z.nnz_Mv = h->Mv.nnz;
+  z.nnz_Mv = energy_v(h).nnz;
   z.nnz_Mp = h->Mp.nnz;
   z.nnz_Ac = h->Ac.nnz;
   z.nnz_Bc = h->Bc.nnz;
@@ -308,6 +331,8 @@ void run_setup(emin_pattern_t* h, const emin_system_t* sys, const emin_params_t*
                double* Pp, hipStream_t s, emin_report_t* rep) {
   check_same_structure(h, sys);
   check_params(prm);
+  if (((prm->flags & EMIN_FLAG_ENERGY_ATA) != 0) != h->ata)
+    throw Error(EMIN_ERR_ARG, "energy norm differs from the pattern's (EMIN_FLAG_ENERGY_ATA)");
   if ((h->sizes.nnz_Pv && !Pv) || (h->sizes.nnz_Pp && !Pp)) throw Error(EMIN_ERR_ARG, "NULL P");
   const CsrView A = in_view(sys->Ahat), B = in_view(sys->Bdiv);
   emin_report_t* r = rep ? rep : h->rep_internal;
@@ -324,10 +349,11 @@ void run_setup(emin_pattern_t* h, const emin_system_t* sys, const emin_params_t*
     diag_of(A, h->dA, s);
     filter_numeric(A, h->keep_v, h->dA, h->Atv, s);
     symmetrize_numeric(h->Atv.val, h->mv_ia, h->mv_ib, h->Mv, s);
+    if (h->ata) ata_numeric(h, s);
   }
   const bool mixed = prm->precision == EMIN_PREC_MIXED;
   if (mixed) {
-    to_float(h->Mv.val, h->Mvf, h->Mv.nnz, s);
+    to_float(energy_v(h).val, h->Mvf, energy_v(h).nnz, s);
     to_float(h->Mp.val, h->Mpf, h->Mp.nnz, s);
   }
   const bool energy = (prm->flags & EMIN_FLAG_ENERGY) != 0;
@@ -335,7 +361,7 @@ void run_setup(emin_pattern_t* h, const emin_system_t* sys, const emin_params_t*
   EminReportPtrs rpp{r->energy_p, r->rho_p, r->gamma_p, &r->its_p, &r->status};
   const double* Wv = sys->Wv ? sys->Wv : h->Wv_def;
   const double* Wp = sys->Wp ? sys->Wp : h->Wp_def;
-  run_emin(h->ev, h->Mv, h->Mvf, h->vp.N.rowptr, h->vp.N.col, h->vp.cid, h->vp.clist, Wv, Pv,
+  run_emin(h->ev, energy_v(h), h->Mvf, h->vp.N.rowptr, h->vp.N.col, h->vp.cid, h->vp.clist, Wv, Pv,
            prm->iters, energy, mixed, rv, s);
   run_emin(h->ep, h->Mp, h->Mpf, h->cp.N.rowptr, h->cp.N.col, h->cp.cid, h->cp.clist, Wp, Pp,
            prm->iters, energy, mixed, rpp, s);
@@ -472,7 +498,7 @@ emin_status emin_pattern_view(const emin_pattern_t* h, int32_t what, emin_view_t
     case EMIN_VIEW_PP: csr(h->cp.N, false); break;
     case EMIN_VIEW_AC: csr(h->Ac, false); break;
     case EMIN_VIEW_BC: csr(h->Bc, false); break;
-    case EMIN_VIEW_MV: csr(h->Mv, true); break;
+    case EMIN_VIEW_MV: csr(energy_v(h), true); break;
     case EMIN_VIEW_MP: csr(h->Mp, true); break;
     case EMIN_VIEW_S: csr(h->cp.S, false); break;
     case EMIN_VIEW_ORDER: arr(h->cp.n_c, h->ca.order); break;

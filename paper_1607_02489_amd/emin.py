@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libemin.so")
 
 EMIN_PREC_F64, EMIN_PREC_MIXED = 0, 1
-EMIN_FLAG_ENERGY, EMIN_FLAG_VALIDATE, EMIN_FLAG_AUTOTUNE, EMIN_FLAG_PATTERN_VALUES = 1, 2, 4, 8
+(EMIN_FLAG_ENERGY, EMIN_FLAG_VALIDATE, EMIN_FLAG_AUTOTUNE, EMIN_FLAG_PATTERN_VALUES,
+ EMIN_FLAG_ENERGY_ATA) = 1, 2, 4, 8, 16
 MAX_ITERS = 32
 (VIEW_PV, VIEW_PP, VIEW_AC, VIEW_BC, VIEW_MV, VIEW_MP, VIEW_S, VIEW_ORDER, VIEW_CP, VIEW_CBAR,
  VIEW_CV, VIEW_XVC, VIEW_P2VC, VIEW_KEEPV, VIEW_KEEPP, VIEW_DIR) = range(16)
@@ -159,9 +160,11 @@ def _check(st, where):
 
 
 def params(tau1_v=0.06, tau1_p=0.06, tau2_sq=1.5e-3, iters=5, mixed=False, energy=False,
-           validate=False, autotune=False) -> c_params:
+           validate=False, autotune=False, energy_ata=False) -> c_params:
+    """energy_ata: the velocity block's EMIN energy is the A^T A-norm of the
+    filtered operator (sec. 4.3, eq. (min_problem), non-symmetric operators)."""
     flags = ((EMIN_FLAG_ENERGY if energy else 0) | (EMIN_FLAG_VALIDATE if validate else 0) |
-             (EMIN_FLAG_AUTOTUNE if autotune else 0))
+             (EMIN_FLAG_AUTOTUNE if autotune else 0) | (EMIN_FLAG_ENERGY_ATA if energy_ata else 0))
     return c_params(tau1_v, tau1_p, tau2_sq, iters, EMIN_PREC_MIXED if mixed else EMIN_PREC_F64,
                     flags)
 

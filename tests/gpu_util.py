@@ -16,11 +16,12 @@ def say(*a):
 
 
 def gpu_level(sys_: System, tau1_v=0.06, tau1_p=0.06, tau2_sq=1.5e-3, iters=5, mixed=False,
-              energy=True, dsys=None):
+              energy=True, dsys=None, energy_ata=False):
     import torch
     from paper_1607_02489_amd import emin as E
     d = dsys if dsys is not None else E.DeviceSystem.upload(sys_)
-    prm = E.params(tau1_v, tau1_p, tau2_sq, iters, mixed=mixed, energy=energy)
+    prm = E.params(tau1_v, tau1_p, tau2_sq, iters, mixed=mixed, energy=energy,
+                   energy_ata=energy_ata)
     pat = E.Pattern(d, prm)
     s = pat.sizes
     f64 = dict(dtype=torch.float64, device="cuda")

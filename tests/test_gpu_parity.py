@@ -35,6 +35,41 @@ def test_level_parity(case):
     compare_level(g, L)
 
 
+@pytest.mark.parametrize("case", ["oseen2d_16_uniform", "oseen2d_40_jitter", "oseen3d_6"])
+def test_level_parity_ata_energy(case):
+    """EMIN_FLAG_ENERGY_ATA (sec. 4.3, eq. (min_problem): the A^T A-norm for
+    the non-symmetric Oseen velocity block): the energy operator A~^T A~ is
+    bit-exact, the velocity graph and so every pattern are the same as the
+    symmetric-norm level's, and P, the energies and RAP agree with the
+    oracle's A^T A level to 1e-10."""
+    s, kw = CASES[case]()
+    say(f"[gpu] level parity, A^T A energy, {case}: dofs={s.dofs}")
+    L = O.level(s, iters=5, energy_ata=True, **kw)
+    g = gpu_level(s, iters=5, energy_ata=True, **kw)
+    compare_level(g, L)
+    assert g["sizes"]["nnz_Mv"] == L.Mv.nnz
+
+
+def test_energy_norm_must_match_pattern():
+    """emin_setup with a different energy norm than its emin_pattern call is
+    rejected (status, not a fault)."""
+    import torch
+    from paper_1607_02489_amd import emin as E
+    s = synth.make_system(2, 8, nu=0.05, wind="stream", seed=5)
+    d = E.DeviceSystem.upload(s)
+    pat = E.Pattern(d, E.params(iters=2, energy_ata=True))
+    z = pat.sizes
+    f64 = dict(dtype=torch.float64, device="cuda")
+    Pv = torch.empty(max(z["nnz_Pv"], 1), **f64)
+    Pp = torch.empty(max(z["nnz_Pp"], 1), **f64)
+    with pytest.raises(E.EminError) as ei:
+        pat.setup(E.params(iters=2), Pv.data_ptr(), Pp.data_ptr())
+    assert ei.value.status == 1   # EMIN_ERR_ARG
+    pat.setup(E.params(iters=2, energy_ata=True), Pv.data_ptr(), Pp.data_ptr())
+    torch.cuda.synchronize()
+    pat.close()
+
+
 def test_fp_div_sqrt_bitwise():
     """The integer decisions rely on IEEE-correct division and square root on
     the GPU (they are compared bitwise with the CPU's)."""
