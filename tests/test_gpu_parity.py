@@ -145,6 +145,39 @@ def test_hierarchy_cfg2_small_per_level():
         cur = host_coarse(g, s.dim)
 
 
+
+def test_hierarchy_ata_energy():
+    """EMIN_FLAG_ENERGY_ATA over three levels of an Oseen hierarchy: every
+    level matches the oracle's A^T A level run on the GPU's own input for that
+    level (patterns and the energy operator bit-exact, P and RAP to 1e-10),
+    and the library's multi-level driver, which passes the flag to every
+    level's pattern and setup calls, equals those level calls bit for bit."""
+    import torch
+    from paper_1607_02489_amd import emin as E
+    s = synth.make_system(2, 32, jitter=0.05, nu=0.01, wind="stream", seed=12)
+    cur = s
+    for lev in range(2):
+        say(f"[gpu] A^T A hierarchy level {lev}: dofs={cur.dofs}")
+        L = O.level(cur, iters=5, energy_ata=True)
+        g = gpu_level(cur, iters=5, energy_ata=True)
+        compare_level(g, L)
+        cur = host_coarse(g, s.dim)
+    prm = E.params(iters=5, energy_ata=True)
+    H = E.Hierarchy(s, 3, prm).build()
+    torch.cuda.synchronize()
+    N = E.NativeHierarchy(H.fine, prm, 3)
+    torch.cuda.synchronize()
+    assert N.ntransfers() == len(H.levels)
+    for l, Lh in enumerate(H.levels):
+        got = N.level_host(l)
+        z = Lh.pattern.sizes
+        assert np.array_equal(got["Pv"], Lh.Pv.cpu().numpy()[:z["nnz_Pv"]])
+        assert np.array_equal(got["Ac"], Lh.Ac.cpu().numpy()[:z["nnz_Ac"]])
+        assert np.array_equal(got["Bc"], Lh.Bc.cpu().numpy()[:z["nnz_Bc"]])
+    N.close()
+    H.close()
+
+
 MIXED_CASES = {
     "cfg1_stokes2d_8": lambda: (synth.stokes2d_small(), {}),
     "oseen2d_40_jitter": CASES["oseen2d_40_jitter"],
