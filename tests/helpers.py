@@ -83,3 +83,76 @@ def relfro(a, b) -> float:
     b = np.asarray(b, dtype=np.float64)
     nb = np.linalg.norm(b)
     return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def emin_quadratic(M: np.ndarray, N: CSR, cidx: np.ndarray, Wc: np.ndarray):
+    """The EMIN problem of eq. (min_problem) as a quadratic over the vector of
+    P's pattern entries: energy(p) = p^T H p with H[(i,j),(k,j)] = M[i,k]
+    (entries of the same column couple through M), and the orthogonal
+    projector Pi onto the feasible update directions: entries of C rows held
+    at zero, and on every F row the component along w_i = W_c restricted to
+    the row's pattern removed (so P W_c is unchanged)."""
+    n = N.nrows
+    rows = np.repeat(np.arange(n), np.diff(N.rowptr))
+    cols = np.asarray(N.col)
+    same_col = cols[:, None] == cols[None, :]
+    H = np.where(same_col, M[rows][:, rows], 0.0)
+    nnz = N.nnz
+    Pi = np.eye(nnz)
+    for i in range(n):
+        a, b = int(N.rowptr[i]), int(N.rowptr[i + 1])
+        if a == b:
+            continue
+        if cidx[i] >= 0:
+            Pi[a:b, :] = 0.0
+            Pi[:, a:b] = 0.0
+            continue
+        w = np.zeros(nnz)
+        w[a:b] = Wc[cols[a:b]]
+        ww = w @ w
+        if ww > 0.0:
+            Pi -= np.outer(w, w) / ww
+    return H, Pi
+
+
+def krylov_emin_iterate(M: np.ndarray, N: CSR, cidx: np.ndarray, W: np.ndarray, Wc: np.ndarray,
+                        k: int) -> np.ndarray:
+    """The k-th iterate of conjugate gradients on eq. (min_problem), by its
+    characterisation rather than its recurrence: the minimiser of p^T H p over
+    p0 + K_k(Pi H Pi, r0), where p0 is the row-normalised binary start (C rows
+    by injection), r0 = -Pi H p0 the projected negative gradient, and K_k the
+    Krylov space of dimension k (orthonormal basis by twice-repeated
+    Gram-Schmidt).  Dense numpy; tiny problems only."""
+    n = N.nrows
+    rows = np.repeat(np.arange(n), np.diff(N.rowptr))
+    cols = np.asarray(N.col)
+    H, Pi = emin_quadratic(M, N, cidx, Wc)
+    p0 = np.zeros(N.nnz)
+    for i in range(n):
+        a, b = int(N.rowptr[i]), int(N.rowptr[i + 1])
+        if cidx[i] >= 0:
+            p0[a:b] = 1.0
+            continue
+        g = float(np.sum(Wc[cols[a:b]] ** 2))
+        if g > 0.0:
+            p0[a:b] = W[i] * Wc[cols[a:b]] / g
+    A = Pi @ H @ Pi
+    r = -(Pi @ (H @ p0))
+    basis = []
+    v = r.copy()
+    for _ in range(k):
+        for _rep in range(2):
+            for q in basis:
+                v = v - (q @ v) * q
+        nv = np.linalg.norm(v)
+        if nv <= 1e-14 * max(np.linalg.norm(r), 1e-300):
+            break
+        q = v / nv
+        basis.append(q)
+        v = A @ q
+    if not basis:
+        return p0
+    K = np.stack(basis, 1)
+    y = np.linalg.solve(K.T @ H @ K, -(K.T @ (H @ p0)))
+    del rows
+    return p0 + K @ y

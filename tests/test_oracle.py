@@ -171,6 +171,79 @@ def test_alg3_chain(oracle_lib):
             assert co.S.col[co.S.rowptr[i]:co.S.rowptr[i + 1]].tolist() == [lo, lo + 4]
 
 
+def _graph_from_paths(n, paths):
+    """Undirected graph on n vertices from vertex paths (consecutive entries
+    joined by an edge), as a CSR pattern."""
+    rows, cols = [], []
+    for p in paths:
+        for a, b in zip(p[:-1], p[1:]):
+            rows += [a, b]
+            cols += [b, a]
+    A = sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(n, n))
+    A.sum_duplicates()
+    A.sort_indices()
+    return CSR.from_scipy(A)
+
+
+def _h1_case(first_far):
+    """A hand-built graph where the third pick of Alg. 3 turns on
+    update_heuristics.  Vertex 0 (C1, at the origin) reaches a (3 units away)
+    and X through chains of three F vertices (graph distance 4 each); X also
+    reaches a through its own chain of three; Y reaches a only (through a
+    third chain), and is 8 hops from vertex 0.  Coordinates of the chain
+    vertices play no part in the picks.
+
+    After C1 = 0 the candidates are a and X; a is nearer (3 < |X|), so C2 = a.
+    Then the candidates are X (C points 0 and a within distance 4) and Y
+    (only a within distance 4)."""
+    # vertex numbers: 0, a=1, chain 0-a: 2,3,4; chain 0-X: 5,6,7; chain X-a:
+    # 8,9,10; chain a-Y: 11,12,13; then X and Y in the order requested
+    if first_far:   # X before Y in index order
+        X, Y = 14, 15
+    else:
+        Y, X = 14, 15
+    a = 1
+    paths = [[0, 2, 3, 4, a], [0, 5, 6, 7, X], [X, 8, 9, 10, a], [a, 11, 12, 13, Y]]
+    G = _graph_from_paths(16, paths)
+    x = np.zeros((16, 2))
+    x[a] = (-3.0, 0.0)
+    rng = np.random.default_rng(0)
+    for v in (2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13):
+        x[v] = rng.uniform(-10.0, 10.0, 2)
+    return G, x, a, X, Y
+
+
+def test_alg3_update_heuristics_harmonic_mean(oracle_lib):
+    """sec. 4.1, update_heuristics: h1 of a candidate is the harmonic average
+    of its Euclidean distances to the C points within graph distance 4, and
+    the next C point minimises h1.  Hand-worked picks on two graphs where the
+    harmonic average, the arithmetic average, the plain sum of inverse
+    distances (no count) and graph-distance keys choose differently.
+
+    Case 1: X at (4, 0) has d = 4 (to 0) and 7 (to a); Y at a + (0, 5.3) has
+    d = 5.3 (to a).  h1(X) = 2/(1/4 + 1/7) = 5.0909 < h1(Y) = 5.3, so X is
+    the third C point.  An arithmetic mean (5.5 > 5.3) would pick Y, and so
+    would graph-distance keys (both 4: the index tie-break, Y < X).
+
+    Case 2: X at (-1.5, sqrt(22.75)) has d = 5 to both; Y at a + (0, -4.6)
+    has d = 4.6.  h1(X) = 5 > h1(Y) = 4.6, so Y is the third C point.  The
+    plain sum of inverse distances (2/5 > 1/4.6, i.e. 1/sum 2.5 < 4.6) would
+    pick X, and so would graph-distance keys (tie, X < Y)."""
+    O = oracle_lib
+    G, x, a, X, Y = _h1_case(first_far=False)
+    x[X] = (4.0, 0.0)
+    x[Y] = x[a] + (0.0, 5.3)
+    co = O.coarsen_pressure(G, x, 2)
+    assert co.order[:3].tolist() == [0, a, X]
+    G, x, a, X, Y = _h1_case(first_far=True)
+    x[X] = (-1.5, np.sqrt(25.0 - 2.25))
+    x[Y] = x[a] + (0.0, -4.6)
+    assert abs(np.linalg.norm(x[X] - x[a]) - 5.0) < 1e-12
+    assert abs(np.linalg.norm(x[X]) - 5.0) < 1e-12
+    co = O.coarsen_pressure(G, x, 2)
+    assert co.order[:3].tolist() == [0, a, Y]
+
+
 # --------------------------------------------------------------------------
 # Alg. 4
 # --------------------------------------------------------------------------
@@ -218,8 +291,70 @@ def test_midpoint_closeness_test(oracle_lib):
     c1, _ = O.midpoints(co.S, co.is_c, s.xv[s.p2v], 2, tau2_sq=1.5e-3)
     c2, _ = O.midpoints(co.S, co.is_c, s.xv[s.p2v], 2, tau2_sq=0.4 ** 2)
     assert c1.sum() <= c0.sum() and c2.sum() <= c1.sum()
-    assert (c1 <= c0).all() or c1.sum() <= c0.sum()
     assert (co.is_c <= c2).all()
+    # with tau2 = 0 the closeness test never rejects, so C-bar is C plus the
+    # target vertex m_i of every F vertex with |S_i| >= 2, whatever the
+    # visiting order: m_i = argmin over B_i = {j in F : S_i within S_j} of
+    # (|x_j - X_i|^2, j), X_i the barycentre of S_i (brute force here)
+    x = s.xv[s.p2v]
+    sets = [set(co.S.col[co.S.rowptr[i]:co.S.rowptr[i + 1]].tolist()) for i in range(s.n_p)]
+    want = co.is_c.copy()
+    for i in range(s.n_p):
+        if co.is_c[i] or len(sets[i]) < 2:
+            continue
+        X = x[sorted(sets[i])].mean(axis=0)
+        B = [j for j in range(s.n_p) if not co.is_c[j] and sets[i] <= sets[j]]
+        d2 = [float(((x[j] - X) ** 2).sum()) for j in B]
+        want[min(zip(d2, B))[1]] = True
+    assert np.array_equal(c0, want)
+    assert (c2 <= c0).all() and (c1 <= c0).all()
+
+
+def test_midpoints_hand_case_order_and_rejection(oracle_lib):
+    """Alg. 4 on hand-built S sets, where the visiting order (|S_i|
+    descending, then index) and the tau2 test decide C-bar.
+
+    C points c0 = (0,0), c1 = (4,0), c2 = (2,4), and an isolated C point
+    c3 = (2.05, 0.2) that no S set holds.  F vertices: b = (2,0.2),
+    d1 = (0.5,0.1), d2 = (3.5,0.1) with S = {c0,c1}, and a = (2,1) with
+    S = {c0,c1,c2}; indices c0..c3 = 0..3, b = 4, d1 = 5, d2 = 6, a = 7.
+
+    a goes first (|S| = 3): B_a = {a}, so m = a, nothing to test: a joins.
+    Then b, d1, d2 (|S| = 2) share B = {a,b,d1,d2}, target (2,0) and m = b;
+    B's box is 3 x 0.9, t^2 = 9.81, and B intersect C-bar = {a} with
+    |a - b|^2 = 0.64.  So b is rejected iff 0.64 < tau2^2 * 9.81, i.e.
+    tau2^2 > 0.0652...; the isolated C point c3 near b is outside B and
+    never counts.
+
+    tau2^2 = 0.068: C-bar = C + {a}.  Visiting b first (index order) would
+    add b and then a (b is not in B_a); a box of the widest side only
+    (t^2 = 9, threshold 0.612) would keep b.
+    tau2^2 = 1.5e-3 (the paper's) and 0: C-bar = C + {a, b}; testing against
+    all of C-bar (c3 is 0.0025 from b) would reject b."""
+    O = oracle_lib
+    n = 8
+    c0, c1, c2, c3, b, d1, d2, a = range(8)
+    x = np.array([[0.0, 0.0], [4.0, 0.0], [2.0, 4.0], [2.05, 0.2],
+                  [2.0, 0.2], [0.5, 0.1], [3.5, 0.1], [2.0, 1.0]])
+    sets = {c0: [c0], c1: [c1], c2: [c2], c3: [c3],
+            b: [c0, c1], d1: [c0, c1], d2: [c0, c1], a: [c0, c1, c2]}
+    rows = [i for i in range(n) for _ in sets[i]]
+    cols = [c for i in range(n) for c in sets[i]]
+    S = sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(n, n))
+    S.sort_indices()
+    S = CSR.from_scipy(S)
+    is_c = np.array([1, 1, 1, 1, 0, 0, 0, 0], dtype=bool)
+    cb, nadd = O.midpoints(S, is_c, x, 2, tau2_sq=0.068)
+    assert np.nonzero(cb)[0].tolist() == [c0, c1, c2, c3, a] and nadd == 1
+    for t2 in (1.5e-3, 0.0):
+        cb, nadd = O.midpoints(S, is_c, x, 2, tau2_sq=t2)
+        assert np.nonzero(cb)[0].tolist() == [c0, c1, c2, c3, b, a] and nadd == 2
+    # just below and above the hand-computed threshold 0.64 / 9.81
+    thr = 0.64 / 9.81
+    cb, _ = O.midpoints(S, is_c, x, 2, tau2_sq=thr * (1 - 1e-9))
+    assert cb[b]
+    cb, _ = O.midpoints(S, is_c, x, 2, tau2_sq=thr * (1 + 1e-9))
+    assert not cb[b]
 
 
 # --------------------------------------------------------------------------
@@ -304,6 +439,38 @@ def test_emin_matches_dense_kkt(oracle_lib):
         r = O.emin(M, N, cid, W, Wc, 300)
         ref = kkt_emin(dense(M), N, cid, W, Wc)
         assert relfro(r.P.val, ref) <= 1e-10
+
+
+@pytest.mark.parametrize("energy_ata", [False, True])
+def test_emin_k_step_iterate_is_krylov_minimiser(oracle_lib, energy_ata):
+    """sec. 4.3, eq. (min_problem), solved by the constrained CG: after k
+    steps (k = 1..5) the iterate is the minimiser of trace(P^T M P) over
+    P0 + K_k(Pi M Pi, R0), with Pi the orthogonal projector onto
+    pattern-supported updates that keep P W_c = W and hold the C rows, and
+    R0 = -Pi M P0.  The checker builds that Krylov space densely and
+    minimises over it (no CG recurrence), for the symmetric-part norm and for
+    the A^T A-norm of the filtered velocity block of a jittered Oseen
+    system, and for the pressure block.  A wrong beta, steepest descent, or
+    an update direction left unprojected all miss this minimiser."""
+    from tests.helpers import krylov_emin_iterate
+    O = oracle_lib
+    s = synth.make_system(2, 4, jitter=0.1, nu=0.05, wind="stream", seed=11)
+    L = O.level(s, iters=0, energy_ata=energy_ata)
+    Wv, Wvc, cidv, cidp = _modes(L, s)
+    blocks = [(L.Mv, L.Pv, cidv, Wv, Wvc)]
+    if not energy_ata:
+        blocks.append((L.Mp, L.Pp, cidp, np.ones(s.n_p), np.ones(int(L.is_cp.sum()))))
+    for M, N, cid, W, Wc in blocks:
+        Md = dense(M)
+        for k in range(1, 6):
+            r = O.emin(M, N, cid, W, Wc, k)
+            assert r.its == k
+            ref = krylov_emin_iterate(Md, N, cid, W, Wc, k)
+            assert relfro(r.P.val, ref) <= 1e-10, (k, relfro(r.P.val, ref))
+            # the energy the oracle reports is trace(P^T M P) of that iterate
+            H = dense(M)
+            Pd = dense(CSR(N.nrows, N.ncols, N.rowptr, N.col, ref))
+            assert abs(r.energy[k] - np.trace(Pd.T @ H @ Pd)) <= 1e-10 * abs(r.energy[0])
 
 
 def test_emin_1d_linear_interpolation(oracle_lib):
