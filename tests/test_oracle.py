@@ -280,6 +280,27 @@ def test_midpoints_perfect_coarsening(oracle_lib, n):
     assert 2 * n_vc + n_pc == 2 * (n // 2 + 1) ** 2 + (n // 4 + 1) ** 2
 
 
+@pytest.mark.parametrize("n", [8, 16])
+def test_level_with_given_cpoints_perfect_coarsening(oracle_lib, n):
+    """The level with C^(p) given (the spacing-4 pressure lattice of a uniform
+    mesh, a perfect distance-4 coarsening): its S sets are the C points within
+    graph distance 3 (scipy BFS), C-bar is the spacing-2 lattice (sec. 4.2
+    closed form), and the coarse level has 2(n/2+1)^2 + (n/4+1)^2 dofs."""
+    O = oracle_lib
+    s = synth.make_system(2, n)
+    m = n + 1
+    ij = np.stack(np.meshgrid(np.arange(m), np.arange(m), indexing="xy"), -1).reshape(-1, 2)
+    is_c = (ij[:, 0] % 4 == 0) & (ij[:, 1] % 4 == 0)
+    L = O.level(s, iters=3, cpoints=is_c)
+    assert np.array_equal(L.is_cp, is_c) and L.n_alg3 == int(is_c.sum())
+    assert L.order.tolist() == np.nonzero(is_c)[0].tolist()
+    G = graph_of(L.Mp)
+    want = _sets_from_c(G, is_c)
+    assert np.array_equal(L.S.rowptr, want.rowptr) and np.array_equal(L.S.col, want.col)
+    assert np.array_equal(L.cbar, (ij[:, 0] % 2 == 0) & (ij[:, 1] % 2 == 0))
+    assert 2 * int(L.is_cv.sum()) + int(L.is_cp.sum()) == 2 * (n // 2 + 1) ** 2 + (n // 4 + 1) ** 2
+
+
 def test_midpoint_closeness_test(oracle_lib):
     """Alg. 4's tau2 test: a candidate closer than tau2*t_i to an already
     chosen mid-point is rejected; tau2 = 0 accepts every target."""
