@@ -420,6 +420,46 @@ int orc_coarsen_pressure(const orc_csr *G, const double *x, int dim,
   return ORC_OK;
 }
 
+/* The S sets for a given C^(p) (the coarse pressures chosen elsewhere, e.g.
+ * a perfect distance-4 coarsening of a uniform mesh): S_i = every C point
+ * within graph distance 3 of i (sec. 4.1), sorted by fine index with its
+ * distance; order = the C points ascending. */
+int orc_sets_from_cpoints(const orc_csr *G, const uint8_t *is_c, orc_csr *S, int32_t **sdist,
+                          int32_t **order_out, int64_t *n_c) {
+  int64_t n = G->nrows;
+  int32_t *dist = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  int32_t *list = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  int32_t *order = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  slist *sl = (slist *)calloc((size_t)(n > 0 ? n : 1), sizeof(slist));
+  for (int64_t i = 0; i < n; i++) dist[i] = -1;
+  int64_t nc = 0;
+  for (int64_t c = 0; c < n; c++) {
+    if (!is_c[c]) continue;
+    order[nc++] = (int32_t)c;
+    int64_t nv = bfs(G, (int32_t)c, 3, dist, list);
+    for (int64_t t = 0; t < nv; t++) {
+      slist_push(&sl[list[t]], (int32_t)c, dist[list[t]]);
+      dist[list[t]] = -1;
+    }
+  }
+  int64_t tot = 0;
+  for (int64_t i = 0; i < n; i++) tot += sl[i].n;
+  csr_alloc(S, n, n, tot, 0);
+  int32_t *sd = (int32_t *)malloc((size_t)(tot > 0 ? tot : 1) * sizeof(int32_t));
+  for (int64_t i = 0; i < n; i++) {
+    int64_t b = S->rowptr[i];
+    S->rowptr[i + 1] = b + sl[i].n;
+    /* C points were visited in ascending order, so each list is sorted */
+    for (int32_t t = 0; t < sl[i].n; t++) { S->col[b + t] = sl[i].c[t]; sd[b + t] = sl[i].d[t]; }
+    free(sl[i].c); free(sl[i].d);
+  }
+  *sdist = sd;
+  *order_out = order;
+  *n_c = nc;
+  free(sl); free(dist); free(list);
+  return ORC_OK;
+}
+
 /* sec. 4.1: N^(p)_ij = 1 iff j in S_i, columns numbered by the position of
  * the C point in ascending fine order.  A C row interpolates by injection
  * from itself only (its pattern is {self}). */
@@ -769,6 +809,14 @@ int orc_level(int dim, const orc_csr *Ahat, const orc_csr *Bdiv,
               const double *xv, const int32_t *p2v,
               double tau1_v, double tau1_p, double tau2_sq, int iters, int energy_ata,
               orc_level_t *L) {
+  return orc_level_cp(dim, Ahat, Bdiv, xv, p2v, tau1_v, tau1_p, tau2_sq, iters, energy_ata,
+                      NULL, L);
+}
+
+int orc_level_cp(int dim, const orc_csr *Ahat, const orc_csr *Bdiv,
+                 const double *xv, const int32_t *p2v,
+                 double tau1_v, double tau1_p, double tau2_sq, int iters, int energy_ata,
+                 const uint8_t *cp_in, orc_level_t *L) {
   memset(L, 0, sizeof(*L));
   L->dim = dim;
   int64_t nv = Ahat->nrows, np = Bdiv->nrows;
@@ -808,7 +856,14 @@ int orc_level(int dim, const orc_csr *Ahat, const orc_csr *Bdiv,
     for (int d = 0; d < dim; d++) xp[i * dim + d] = xv[(int64_t)p2v[i] * dim + d];
 
   L->is_cp = (uint8_t *)malloc((size_t)(np > 0 ? np : 1));
-  orc_coarsen_pressure(&L->Mp, xp, dim, L->is_cp, &L->S, &L->sdist, &L->order, &L->n_cp, &L->n_alg3);
+  if (cp_in) {
+    memcpy(L->is_cp, cp_in, (size_t)np);
+    orc_sets_from_cpoints(&L->Mp, L->is_cp, &L->S, &L->sdist, &L->order, &L->n_cp);
+    L->n_alg3 = L->n_cp;
+  } else {
+    orc_coarsen_pressure(&L->Mp, xp, dim, L->is_cp, &L->S, &L->sdist, &L->order, &L->n_cp,
+                         &L->n_alg3);
+  }
   orc_pressure_pattern(&L->S, L->is_cp, &L->Pp);
   L->cbar = (uint8_t *)malloc((size_t)(np > 0 ? np : 1));
   memcpy(L->cbar, L->is_cp, (size_t)np);

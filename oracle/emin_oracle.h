@@ -58,6 +58,11 @@ int orc_coarsen_pressure(const orc_csr *G, const double *x, int dim,
                          uint8_t *is_c, orc_csr *S, int32_t **sdist,
                          int32_t **order, int64_t *n_c, int64_t *n_alg3);
 
+/* S sets (C within graph distance 3, sorted, with distances) for a given
+ * C^(p) flag array; order = the C points ascending. */
+int orc_sets_from_cpoints(const orc_csr *G, const uint8_t *is_c, orc_csr *S, int32_t **sdist,
+                          int32_t **order, int64_t *n_c);
+
 /* Alg. 4 (find_velocity_Cpoints) mid-point pass. cbar[n] in/out:
  * on entry the C^(p) flags, on exit C-bar^(p). */
 int orc_midpoints(const orc_csr *S, const uint8_t *is_c, const double *x,
@@ -116,6 +121,12 @@ int orc_level(int dim, const orc_csr *Ahat, const orc_csr *Bdiv,
               const double *xv, const int32_t *p2v,
               double tau1_v, double tau1_p, double tau2_sq, int iters, int energy_ata,
               orc_level_t *out);
+/* The same level with C^(p) given (cp_in, n_p flags) instead of chosen by
+ * Alg. 3; NULL cp_in is orc_level. */
+int orc_level_cp(int dim, const orc_csr *Ahat, const orc_csr *Bdiv,
+                 const double *xv, const int32_t *p2v,
+                 double tau1_v, double tau1_p, double tau2_sq, int iters, int energy_ata,
+                 const uint8_t *cp_in, orc_level_t *L);
 void orc_level_free(orc_level_t *L);
 
 #ifdef __cplusplus

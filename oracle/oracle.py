@@ -83,6 +83,9 @@ def lib():
         L.orc_level.argtypes = [C.c_int, P(c_csr), P(c_csr), P(C.c_double), P(C.c_int32),
                                 C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
                                 P(c_level)]
+        L.orc_level_cp.argtypes = [C.c_int, P(c_csr), P(c_csr), P(C.c_double), P(C.c_int32),
+                                   C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
+                                   P(C.c_uint8), P(c_level)]
         L.orc_level_free.argtypes = [P(c_level)]
         _lib = L
     return _lib
@@ -299,18 +302,26 @@ class Level:
 
 
 def level(sys: System, tau1_v: float = TAU1, tau1_p: float = TAU1, tau2_sq: float = TAU2_SQ,
-          iters: int = 5, energy_ata: bool = False) -> Level:
+          iters: int = 5, energy_ata: bool = False, cpoints=None) -> Level:
     """One level of Alg. 1 (orc_level).  energy_ata: the velocity block's EMIN
     energy is the A^T A-norm of the filtered operator (sec. 4.3, eq.
     (min_problem), for non-symmetric operators) instead of the norm of its
-    symmetric part; the velocity graph is the same either way."""
+    symmetric part; the velocity graph is the same either way.  cpoints: the
+    coarse pressures (bool[n_p]) given instead of chosen by Alg. 3
+    (orc_level_cp)."""
     a, b = _In(sys.Ahat), _In(sys.Bdiv)
     xv = np.ascontiguousarray(sys.xv, dtype=np.float64)
     p2v = np.ascontiguousarray(sys.p2v, dtype=np.int32)
     L = c_level()
-    st = lib().orc_level(sys.dim, C.byref(a.c), C.byref(b.c), _ptr(xv, C.c_double),
-                         _ptr(p2v, C.c_int32), tau1_v, tau1_p, tau2_sq, iters,
-                         1 if energy_ata else 0, C.byref(L))
+    if cpoints is None:
+        st = lib().orc_level(sys.dim, C.byref(a.c), C.byref(b.c), _ptr(xv, C.c_double),
+                             _ptr(p2v, C.c_int32), tau1_v, tau1_p, tau2_sq, iters,
+                             1 if energy_ata else 0, C.byref(L))
+    else:
+        cp = np.ascontiguousarray(np.asarray(cpoints, dtype=bool).astype(np.uint8))
+        st = lib().orc_level_cp(sys.dim, C.byref(a.c), C.byref(b.c), _ptr(xv, C.c_double),
+                                _ptr(p2v, C.c_int32), tau1_v, tau1_p, tau2_sq, iters,
+                                1 if energy_ata else 0, _ptr(cp, C.c_uint8), C.byref(L))
     try:
         _check(st)
         nv, np_, d = sys.n_v, sys.n_p, sys.dim

@@ -94,6 +94,16 @@ __global__ void k_check_idx(const int32_t* idx, int64_t n, int64_t bound, int* d
   if (i < n && (idx[i] < 0 || idx[i] >= bound)) atomicOr(derr, DERR_PATTERN);
 }
 
+// a C row (cid >= 0) holds exactly its own coarse column; cid < nc
+__global__ void k_check_cid(const int32_t* cid, const int64_t* nrp, const int32_t* ncol,
+                            int64_t n, int64_t nc, int* derr) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t c = cid[i];
+  if (c >= nc || (c >= 0 && (nrp[i + 1] - nrp[i] != 1 || ncol[nrp[i]] != c)))
+    atomicOr(derr, DERR_PATTERN);
+}
+
 __global__ void k_cv_from_cbar(const uint8_t* cbar, const int32_t* p2v, int64_t n_p, uint8_t* cv) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n_p && cbar[i]) cv[p2v[i]] = 1;
@@ -172,7 +182,7 @@ static void ata_numeric(emin_pattern_t* h, hipStream_t s) {
 }
 
 void build_pattern(emin_pattern_t* h, const emin_system_t* sys, const emin_params_t* prm,
-                   hipStream_t s) {
+                   hipStream_t s, const int32_t* cp_given = nullptr, int64_t ncp = 0) {
   Arena& ar = h->ar;
   const int dim = sys->dim;
   const int64_t nv = sys->Ahat.nrows, np = sys->Bdiv.nrows;
@@ -232,7 +242,7 @@ void build_pattern(emin_pattern_t* h, const emin_system_t* sys, const emin_param
   h->ca.n = np;
   h->ca.dim = dim;
   h->ca.x = h->xp;
-  coarsen_pressure(h->ca, h->cp, s, ar, h->lds_max);
+  coarsen_pressure(h->ca, h->cp, s, ar, h->lds_max, cp_given, ncp);
 
   // Alg. 4 mid-points, co-located velocities, velocity pattern
   h->cbar = ar.alloc<uint8_t>(np);
@@ -419,6 +429,61 @@ void run_rap(emin_pattern_t* h, const emin_system_t* sys, const double* Pv, cons
   HIP_OK(hipGetLastError());
 }
 
+// EMIN on one block with the energy operator, pattern, C rows and modes given
+// (sec. 4.3, eq. (min_problem)); synchronous, with its own workspace.
+void run_setup_with_pattern(const emin_csr_t* Min, const int64_t* nrp, const int32_t* ncol,
+                            int64_t nc, int64_t nnz, const int32_t* cid, const double* W,
+                            const double* Wc, int32_t iters, int32_t precision, uint32_t flags,
+                            double* P, hipStream_t s, emin_report_t* rep) {
+  if (!Min) throw Error(EMIN_ERR_ARG, "NULL operator");
+  const int64_t n = Min->nrows;
+  if (n < 0 || nc < 0 || nnz < 0 || Min->nnz < 0) throw Error(EMIN_ERR_ARG, "negative size");
+  if (Min->ncols != n) throw Error(EMIN_ERR_SHAPE, "operator must be square");
+  if (iters < 0 || iters > EMIN_MAX_ITERS) throw Error(EMIN_ERR_ARG, "iters out of range");
+  if (precision != EMIN_PREC_F64 && precision != EMIN_PREC_MIXED)
+    throw Error(EMIN_ERR_ARG, "unknown precision");
+  if (n && (!Min->rowptr || !nrp || !cid || !W || (Min->nnz && (!Min->col || !Min->val)) ||
+            (nnz && (!ncol || !P)) || (nc && !Wc)))
+    throw Error(EMIN_ERR_ARG, "NULL array");
+  if (Min->nnz >= INT32_MAX || nnz >= INT32_MAX) throw Error(EMIN_ERR_CAPACITY, "nnz >= 2^31");
+  Arena ar;
+  int* derr = ar.alloc<int>(1);
+  HIP_OK(hipMemsetAsync(derr, 0, sizeof(int), s));
+  const CsrView Mv = in_view(*Min);
+  const CsrView Nv{n, nc, nnz, nrp, ncol, nullptr};
+  validate_csr(Mv, (flags & EMIN_FLAG_VALIDATE) != 0, derr, s);
+  validate_csr(Nv, false, derr, s);
+  if (n) k_check_cid<<<nblocks(n, 256), 256, 0, s>>>(cid, nrp, ncol, n, nc, derr);
+  const int e = d2h(derr, s);
+  if (e & DERR_PATTERN) throw Error(EMIN_ERR_PATTERN, "malformed CSR or C rows");
+  if (e & DERR_VALUE) throw Error(EMIN_ERR_VALUE, "non-finite input value");
+  Csr M;
+  M.nrows = n;
+  M.ncols = n;
+  M.nnz = Min->nnz;
+  M.rowptr = const_cast<int64_t*>(Min->rowptr);
+  M.col = const_cast<int32_t*>(Min->col);
+  M.val = const_cast<double*>(Min->val);
+  EminWork w;
+  w.allocate(n, nnz, nc, ar, true);
+  w.g = pick_lanes(M);
+  w.smax = (int)max_row_len(nrp, n, s, ar);
+  if (w.smax > 64) throw Error(EMIN_ERR_CAPACITY, "pattern row > 64");
+  w.make_bins(M, nrp, ncol, s, ar, false);
+  if (nc) HIP_OK(hipMemcpyAsync(w.Wc, Wc, sizeof(double) * nc, hipMemcpyDeviceToDevice, s));
+  const bool mixed = precision == EMIN_PREC_MIXED;
+  float* Mf = ar.alloc<float>(M.nnz);
+  if (mixed) to_float(M.val, Mf, M.nnz, s);
+  emin_report_t* r = rep ? rep : ar.alloc<emin_report_t>(1);
+  zero_bytes(r, sizeof(emin_report_t), s);
+  EminReportPtrs rp{r->energy_v, r->rho_v, r->gamma_v, &r->its_v, &r->status};
+  run_emin(w, M, Mf, nrp, ncol, cid, nullptr, W, P, iters, (flags & EMIN_FLAG_ENERGY) != 0,
+           mixed, rp, s);
+  HIP_OK(hipGetLastError());
+  // the workspace is released on return: wait for the kernels that use it
+  HIP_OK(hipStreamSynchronize(s));
+}
+
 template <class F>
 emin_status guarded(F&& f) {
   try {
@@ -459,6 +524,49 @@ emin_status emin_pattern(const emin_system_t* sys, const emin_params_t* prm, voi
   set_last_error("");
   *out = h;
   return EMIN_OK;
+}
+
+emin_status emin_pattern_with_cpoints(const emin_system_t* sys, const emin_params_t* prm,
+                                      const int32_t* cp, int64_t ncp, void* stream,
+                                      emin_pattern_t** out) {
+  if (!out) return EMIN_ERR_ARG;
+  *out = nullptr;
+  emin_pattern_t* h = nullptr;
+  emin_status st = guarded([&] {
+    check_system(sys);
+    check_params(prm);
+    if (ncp < 0 || (ncp && !cp)) throw Error(EMIN_ERR_ARG, "C point list");
+    if (ncp > sys->Bdiv.nrows) throw Error(EMIN_ERR_SHAPE, "more C points than pressures");
+    h = new emin_pattern_s();
+    build_pattern(h, sys, prm, as_stream(stream), cp, ncp);
+  });
+  if (st != EMIN_OK) {
+    if (h) {
+      (void)hipStreamSynchronize(as_stream(stream));
+      delete h;
+    }
+    return st;
+  }
+  set_last_error("");
+  *out = h;
+  return EMIN_OK;
+}
+
+emin_status emin_setup_with_pattern(const emin_csr_t* M, const int64_t* N_rowptr,
+                                    const int32_t* N_col, int64_t ncoarse, int64_t nnz_N,
+                                    const int32_t* cid, const double* W, const double* Wc,
+                                    int32_t iters, int32_t precision, uint32_t flags,
+                                    double* P_vals, void* stream, emin_report_t* report) {
+  return guarded([&] {
+    try {
+      run_setup_with_pattern(M, N_rowptr, N_col, ncoarse, nnz_N, cid, W, Wc, iters, precision,
+                             flags, P_vals, as_stream(stream), report);
+    } catch (...) {
+      // the call's workspace is gone: let no queued kernel outlive it
+      (void)hipStreamSynchronize(as_stream(stream));
+      throw;
+    }
+  });
 }
 
 emin_status emin_autotune_stats(int64_t* out4) {

@@ -42,7 +42,10 @@ struct CoarsenOut {
   uint8_t* sdist = nullptr;
 };
 
-void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar, int lds_max);
+// Alg. 3 and the extra distance-3 points, or, with cp_given (ncp ascending
+// fine indices, device memory), that C^(p) taken as given
+void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar, int lds_max,
+                      const int32_t* cp_given = nullptr, int64_t ncp = 0);
 
 // Alg. 4: C-bar^(p) flags (n_p) from the S sets; returns |C-bar^(p)| (the C
 // points and the mid-points added)

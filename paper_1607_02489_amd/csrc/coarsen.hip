@@ -603,6 +603,48 @@ __global__ __launch_bounds__(A3_BS) void k_extras(CoarsenArgs D, const double* e
   }
 }
 
+// Given C^(p) (ascending fine indices, checked here) instead of Alg. 3:
+// the C flags and the selection order.
+__global__ void k_given_mark(CoarsenArgs D, const int32_t* cp, int64_t ncp) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) {
+    D.meta[0] = (int32_t)ncp;
+    D.meta[1] = (int32_t)ncp;
+  }
+  if (t >= ncp) return;
+  const int32_t c = cp[t];
+  if (c < 0 || c >= D.n || (t > 0 && cp[t - 1] >= c)) {
+    atomicOr(D.meta + 2, DERR_PATTERN);
+    return;
+  }
+  D.st[c] = ST_C;
+  D.order[t] = c;
+}
+
+// S_v = the C points within graph distance 3 of v, read off v's ball (its
+// entries at distance <= 3 are a prefix); a vertex not given as C is F.
+__global__ void k_given_sets(CoarsenArgs D) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= D.n) return;
+  if (D.st[v] != ST_C) D.st[v] = ST_F;
+  const int32_t* ball = D.balls + v * D.bstride;
+  const int m = D.b3[v];
+  int k = 0;
+  for (int t = 0; t < m; t++) {
+    const int32_t e = ball[t];
+    const int32_t u = e & ((1 << 29) - 1);
+    if (D.st[u] != ST_C) continue;
+    if (k < D.scap) {
+      D.s_c[v * D.scap + k] = u;
+      D.s_d[v * D.scap + k] = (uint8_t)((uint32_t)e >> 29);
+    } else {
+      atomicOr(D.meta + 2, DERR_CAPACITY);
+    }
+    k++;
+  }
+  D.s_cnt[v] = k < D.scap ? k : D.scap;
+}
+
 // sort every S list by fine index (distances follow)
 __global__ void k_sort_s(CoarsenArgs D) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -678,7 +720,8 @@ __global__ void k_p_fill(CoarsenArgs D, const int32_t* cid, const int64_t* nrp, 
   }
 }
 
-void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar, int lds_max) {
+void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar, int lds_max,
+                      const int32_t* cp_given, int64_t ncp) {
   const int64_t n = D.n;
   D.st = ar.alloc<uint8_t>(n);
   D.cnt = ar.alloc<int32_t>(n);
@@ -774,7 +817,12 @@ void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar,
   if (lds > (size_t)lds_max) throw Error(EMIN_ERR_CAPACITY, "alg3: LDS too small");
   const void* kfun = D.vb == 64 ? (const void*)k_alg3<true> : (const void*)k_alg3<false>;
   allow_lds(kfun);
-  {
+  if (cp_given) {
+    // C^(p) given: the flags, the order and the S sets from the balls
+    k_given_mark<<<nblocks(ncp > 0 ? ncp : 1, 256), 256, 0, s>>>(D, cp_given, ncp);
+    if (n) k_given_sets<<<nblocks(n, 256), 256, 0, s>>>(D);
+    HIP_OK(hipGetLastError());
+  } else {
   prof::Scope ps(s, EMIN_PROF_ALG3, 0.0);
   if (D.vb == 64) k_alg3<true><<<1, A3_BS, lds, s>>>(D);
   else k_alg3<false><<<1, A3_BS, lds, s>>>(D);
@@ -806,6 +854,7 @@ void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar,
   int64_t hq[5];
   HIP_OK(hipMemcpyAsync(hq, q, sizeof(hq), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
+  if (hq[2] & DERR_PATTERN) throw Error(EMIN_ERR_PATTERN, "given C points unsorted or out of range");
   if (hq[2] & DERR_CAPACITY) throw Error(EMIN_ERR_CAPACITY, "alg3: S set or BFS ball capacity");
   out.n_c = hq[0];
   out.n_alg3 = hq[1];

@@ -929,7 +929,8 @@ void run_emin(EminWork& w, const Csr& M, const float* Mf, const int64_t* nrp, co
               bool energy, bool mixed, EminReportPtrs rp, hipStream_t s) {
   const int64_t n = w.n, nnz = w.nnz;
   if (n == 0) return;
-  if (w.nc) k_gather_modes<<<nblocks(w.nc, 256), 256, 0, s>>>(W, clist, w.nc, w.Wc);
+  // W_c = W on the C points (without a C list, the caller has filled w.Wc)
+  if (w.nc && clist) k_gather_modes<<<nblocks(w.nc, 256), 256, 0, s>>>(W, clist, w.nc, w.Wc);
   k_emin_init<<<nblocks(n, RB), RB, 0, s>>>(nrp, ncol, n, cid, W, w.Wc, w.G, P, rp.status);
   // E0 = <P0, mask(M P0)> and R = -Pi(mask(M P0))
   const double* dots = nullptr;

@@ -50,17 +50,15 @@ def test_pattern_with_cpoints_perfect_coarsening(n):
 
 def test_pattern_with_cpoints_jittered_matches_oracle():
     """Given C^(p) on a jittered Oseen mesh (the oracle's own Alg. 3 choice
-    with every fifth point dropped, so S sets and mid-points differ from a
+    plus every seventh other pressure, so every vertex stays within distance
+    3 of a C point while the S sets, mid-points and patterns differ from a
     plain run): the level matches the oracle's level with that C^(p)."""
     import torch
     s = synth.make_system(2, 24, jitter=0.1, nu=0.01, wind="stream", seed=3)
     L0 = O.level(s, iters=1)
-    C = np.nonzero(L0.is_cp)[0]
-    keep = np.ones(C.size, bool)
-    keep[::5] = False
-    is_c = np.zeros(s.n_p, bool)
-    is_c[C[keep]] = True
+    is_c = L0.is_cp | (np.arange(s.n_p) % 7 == 3)
     L = O.level(s, iters=5, cpoints=is_c)
+    assert L.n_mid != L0.n_mid or not np.array_equal(L.cbar, L0.cbar)
     say(f"[gpu] pattern with given C points, jittered Oseen 24: dofs={s.dofs}")
     g = gpu_level(s, iters=5, cpoints=_t(np.nonzero(is_c)[0].astype(np.int32), torch.int32))
     compare_level(g, L)
