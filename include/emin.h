@@ -178,6 +178,22 @@ typedef struct emin_pattern_s emin_pattern_t;
 emin_status emin_pattern(const emin_system_t *sys, const emin_params_t *prm, void *stream,
                          emin_pattern_t **out);
 
+/* emin_pattern with the coarse pressures C^(p) given instead of chosen by
+ * Alg. 3 and the extra distance-3 pass (sec. 4.1): cp holds ncp ascending,
+ * distinct fine pressure indices (device memory, borrowed for the call).
+ * Everything after the coarse pressures is as in emin_pattern: the S sets
+ * (every given C point within graph distance 3 of a vertex, read off the
+ * distance-4 balls), Alg. 4's mid-points (sec. 4.2), the velocity pattern,
+ * the symbolic Galerkin product and the coarse descriptors.  For a perfect
+ * distance-4 coarsening of a uniform mesh, sec. 4.2 fixes C-bar as the
+ * spacing-2 pressure lattice, which this call lets a test check on the
+ * device.  EMIN_VIEW_ORDER lists the given points.  Errors: as emin_pattern,
+ * plus ARG for ncp < 0 or a NULL list, SHAPE for ncp > n_p, PATTERN for an
+ * unsorted, repeated or out-of-range list. */
+emin_status emin_pattern_with_cpoints(const emin_system_t *sys, const emin_params_t *prm,
+                                      const int32_t *cp, int64_t ncp, void *stream,
+                                      emin_pattern_t **out);
+
 /* Host copy of the level sizes. */
 emin_status emin_pattern_info(const emin_pattern_t *h, emin_sizes_t *out);
 
@@ -192,6 +208,33 @@ emin_status emin_pattern_view(const emin_pattern_t *h, int32_t what, emin_view_t
  * Asynchronous on stream; uses workspace held by the handle. */
 emin_status emin_setup(emin_pattern_t *h, const emin_system_t *sys, const emin_params_t *prm,
                        double *Pv_vals, double *Pp_vals, void *stream, emin_report_t *report);
+
+/* sec. 4.3, eq. (min_problem) on one block with every ingredient given:
+ * minimise trace(P^T M P) over P with the pattern N and P W_c = W, by
+ * `iters` constrained CG steps from P0 = W_i W_c / sum_{N_i} W_c^2 (the same
+ * kernels emin_setup runs on each block).
+ *   M        n x n CSR energy operator (symmetric positive semi-definite on
+ *            the feasible updates), borrowed;
+ *   N_rowptr int64[n+1], N_col int32[nnz_N]: the pattern, columns sorted in
+ *            [0, ncoarse), at most 64 per row;
+ *   cid      int32[n]: the coarse column of a C row (its pattern must be
+ *            exactly that column; the row is held at 1), -1 for other rows;
+ *   W        double[n], Wc double[ncoarse]: the near-nullspace mode and its
+ *            coarse restriction;
+ *   P_vals   double[nnz_N] out (caller-allocated);
+ *   precision EMIN_PREC_F64 or EMIN_PREC_MIXED; flags: EMIN_FLAG_ENERGY
+ *            records the energy, EMIN_FLAG_VALIDATE checks M's values;
+ *   report   device emin_report_t or NULL; the block's trace is in the _v
+ *            fields, INFEASIBLE (an F row with an empty pattern and W_i != 0)
+ *            and BREAKDOWN (<Z, M Z> <= 0 while <R, R> > 0) in status.
+ * Allocates its workspace for the call and synchronises the stream before
+ * returning.  Errors: ARG, SHAPE, PATTERN (malformed N, or a C row whose
+ * pattern is not its own column), VALUE, CAPACITY (a pattern row > 64). */
+emin_status emin_setup_with_pattern(const emin_csr_t *M, const int64_t *N_rowptr,
+                                    const int32_t *N_col, int64_t ncoarse, int64_t nnz_N,
+                                    const int32_t *cid, const double *W, const double *Wc,
+                                    int32_t iters, int32_t precision, uint32_t flags,
+                                    double *P_vals, void *stream, emin_report_t *report);
 
 /* Alg. 1 Galerkin product with R = P^T on the unfiltered operator:
  * Ac = Pv^T Ahat Pv (nnz_Ac values) and Bc = Pp^T Bdiv (I_d (x) Pv)
@@ -319,6 +362,17 @@ typedef struct {
 } emin_kstat_t;
 emin_status emin_profile_enable(int enable);
 emin_status emin_profile_collect(emin_kstat_t *out, int32_t nkinds);
+/* The same records one launch at a time, in launch order (kind, device time
+ * in ms, algorithmic bytes and flops): the first cap go to out (host array),
+ * *n receives the count; the records are cleared as by collect. */
+typedef struct {
+  int32_t kind;
+  int32_t reserved;
+  double ms;
+  double bytes;
+  double flops;
+} emin_klaunch_t;
+emin_status emin_profile_launches(emin_klaunch_t *out, int32_t cap, int32_t *n);
 
 /* Test hook: out_sqrt[i] = sqrt(x[i]), out_rcp[i] = 1/x[i] computed by the
  * device exactly as the coarsening kernels compute them (IEEE-rounded, no

@@ -130,6 +130,25 @@ emin_status emin_profile_enable(int enable) {
   return EMIN_OK;
 }
 
+emin_status emin_profile_launches(emin_klaunch_t* out, int32_t cap, int32_t* n) {
+  if (!n || cap < 0 || (cap && !out)) return EMIN_ERR_ARG;
+  using namespace emin::prof;
+  std::lock_guard<std::mutex> g(mu);
+  int32_t k = 0;
+  for (Rec& r : recs) {
+    if (hipEventSynchronize(r.e1) != hipSuccess) return EMIN_ERR_DEVICE;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.e0, r.e1) != hipSuccess) return EMIN_ERR_DEVICE;
+    if (k < cap) out[k] = emin_klaunch_t{r.kind, 0, (double)ms, r.bytes, r.flops};
+    k++;
+    pool.push_back(r.e0);
+    pool.push_back(r.e1);
+  }
+  recs.clear();
+  *n = k;
+  return EMIN_OK;
+}
+
 emin_status emin_profile_collect(emin_kstat_t* out, int32_t nkinds) {
   if (!out || nkinds <= 0) return EMIN_ERR_ARG;
   using namespace emin::prof;

@@ -30,7 +30,8 @@ SYMBOLS = ["emin_pattern", "emin_pattern_info", "emin_pattern_view", "emin_setup
            "emin_hierarchy_level", "emin_hierarchy_device_bytes", "emin_hierarchy_destroy",
            "emin_hierarchy_build_batch", "emin_batch_create", "emin_batch_run",
            "emin_batch_destroy", "emin_server_create", "emin_server_submit", "emin_server_poll",
-           "emin_server_wait", "emin_server_release", "emin_server_stats", "emin_server_destroy"]
+           "emin_server_wait", "emin_server_release", "emin_server_stats", "emin_server_destroy",
+           "emin_pattern_with_cpoints", "emin_setup_with_pattern", "emin_profile_launches"]
 PROF_KINDS = ["spmm", "update", "spgemm", "alg3", "alg4", "vpattern", "r6", "r7"]
 EMIN_PROF_ONLY = 1 << 30
 
@@ -85,6 +86,11 @@ class c_kstat(C.Structure):
                 ("flops", C.c_double)]
 
 
+class c_klaunch(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("ms", C.c_double),
+                ("bytes", C.c_double), ("flops", C.c_double)]
+
+
 class c_view(C.Structure):
     _fields_ = [("n", C.c_int64), ("ncols", C.c_int64), ("nnz", C.c_int64),
                 ("rowptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p),
@@ -103,6 +109,12 @@ def lib():
         L = C.CDLL(LIBPATH)
         P = C.POINTER
         L.emin_pattern.argtypes = [P(c_system), P(c_params), C.c_void_p, P(C.c_void_p)]
+        L.emin_pattern_with_cpoints.argtypes = [P(c_system), P(c_params), C.c_void_p, C.c_int64,
+                                                C.c_void_p, P(C.c_void_p)]
+        L.emin_setup_with_pattern.argtypes = [P(c_csr), C.c_void_p, C.c_void_p, C.c_int64,
+                                              C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                              C.c_int32, C.c_int32, C.c_uint32, C.c_void_p,
+                                              C.c_void_p, C.c_void_p]
         L.emin_pattern_info.argtypes = [C.c_void_p, P(c_sizes)]
         L.emin_pattern_view.argtypes = [C.c_void_p, C.c_int32, P(c_view)]
         L.emin_setup.argtypes = [C.c_void_p, P(c_system), P(c_params), C.c_void_p, C.c_void_p,
@@ -150,6 +162,7 @@ def lib():
         L.emin_profile_enable.argtypes = [C.c_int]
         L.emin_autotune_stats.argtypes = [P(C.c_int64)]
         L.emin_profile_collect.argtypes = [P(c_kstat), C.c_int32]
+        L.emin_profile_launches.argtypes = [P(c_klaunch), C.c_int32, P(C.c_int32)]
         _lib = L
     return _lib
 
@@ -225,14 +238,21 @@ class DeviceSystem:
 
 
 class Pattern:
-    """emin_pattern handle of one level."""
+    """emin_pattern handle of one level (emin_pattern_with_cpoints when
+    cpoints, a device int32 tensor of ascending coarse pressures, is given)."""
 
-    def __init__(self, dsys: DeviceSystem, prm: c_params, stream=None):
+    def __init__(self, dsys: DeviceSystem, prm: c_params, stream=None, cpoints=None):
         self.dsys = dsys
         self._c = dsys.c()
         h = C.c_void_p()
-        _check(lib().emin_pattern(C.byref(self._c), C.byref(prm), _stream(stream), C.byref(h)),
-               "emin_pattern")
+        if cpoints is None:
+            _check(lib().emin_pattern(C.byref(self._c), C.byref(prm), _stream(stream),
+                                      C.byref(h)), "emin_pattern")
+        else:
+            _check(lib().emin_pattern_with_cpoints(C.byref(self._c), C.byref(prm),
+                                                   C.c_void_p(cpoints.data_ptr()),
+                                                   int(cpoints.numel()), _stream(stream),
+                                                   C.byref(h)), "emin_pattern_with_cpoints")
         self.h = h
         s = c_sizes()
         _check(lib().emin_pattern_info(h, C.byref(s)), "emin_pattern_info")
@@ -289,6 +309,24 @@ class Pattern:
             pass
 
 
+def setup_with_pattern(M_dev, N_dev, ncoarse, cid, W, Wc, iters, P, mixed=False, energy=False,
+                       validate=False, report=None, stream=None):
+    """emin_setup_with_pattern.  M_dev = (n, nnz, rowptr, col, val) and
+    N_dev = (nnz, rowptr, col) device tensors; cid, W, Wc, P device tensors."""
+    n, mnnz, mrp, mcol, mval = M_dev
+    nnnz, nrp, ncol = N_dev
+    Mc = c_csr(n, n, mnnz, mrp.data_ptr(), mcol.data_ptr(), mval.data_ptr())
+    flags = (EMIN_FLAG_ENERGY if energy else 0) | (EMIN_FLAG_VALIDATE if validate else 0)
+    _check(lib().emin_setup_with_pattern(C.byref(Mc), C.c_void_p(nrp.data_ptr()),
+                                         C.c_void_p(ncol.data_ptr()), int(ncoarse), int(nnnz),
+                                         C.c_void_p(cid.data_ptr()), C.c_void_p(W.data_ptr()),
+                                         C.c_void_p(Wc.data_ptr()), iters,
+                                         EMIN_PREC_MIXED if mixed else EMIN_PREC_F64, flags,
+                                         C.c_void_p(P.data_ptr()), _stream(stream),
+                                         C.c_void_p(report.data_ptr()) if report is not None
+                                         else None), "emin_setup_with_pattern")
+
+
 def autotune_stats() -> dict:
     """Process-wide autotuner counters of the masked-product schedule."""
     out = (C.c_int64 * 4)()
@@ -327,6 +365,17 @@ def profile_collect() -> dict:
     _check(lib().emin_profile_collect(arr, len(PROF_KINDS)), "emin_profile_collect")
     return {k: dict(launches=int(a.launches), ms=float(a.total_ms), bytes=float(a.bytes),
                     flops=float(a.flops)) for k, a in zip(PROF_KINDS, arr) if a.launches}
+
+
+def profile_launches(cap=1 << 16) -> list:
+    """Per-launch records (kind name, ms, algorithmic bytes), in launch order;
+    clears the records as profile_collect does."""
+    arr = (c_klaunch * cap)()
+    n = C.c_int32()
+    _check(lib().emin_profile_launches(arr, cap, C.byref(n)), "emin_profile_launches")
+    return [dict(kind=PROF_KINDS[arr[i].kind] if 0 <= arr[i].kind < len(PROF_KINDS) else
+                 str(arr[i].kind), ms=float(arr[i].ms), bytes=float(arr[i].bytes),
+                 flops=float(arr[i].flops)) for i in range(min(n.value, cap))]
 
 
 def sync_report(rep_tensor, stream=None, raise_on_error=True) -> c_report:
@@ -394,11 +443,17 @@ class Hierarchy:
         self.coarsest = cur
         return self
 
-    def resetup(self, stream=None):
+    def resetup(self, stream=None, prm: c_params = None):
+        """Numeric phases of every level on the stored patterns and drop masks.
+        prm (default: the hierarchy's) may change the precision: a hierarchy
+        built in FP64 and re-set up in mixed precision runs the FP32 products
+        on the patterns of the FP64 pass."""
+        p = self.prm if prm is None else c_params.from_buffer_copy(prm)
+        p.flags &= ~EMIN_FLAG_PATTERN_VALUES
         for L in self.levels:
-            L.pattern.setup(self.prm, L.Pv.data_ptr(), L.Pp.data_ptr(), L.report.data_ptr(), stream)
+            L.pattern.setup(p, L.Pv.data_ptr(), L.Pp.data_ptr(), L.report.data_ptr(), stream)
             L.pattern.rap(L.Pv.data_ptr(), L.Pp.data_ptr(), L.Ac.data_ptr(), L.Bc.data_ptr(),
-                          stream, mixed=self.prm.precision == EMIN_PREC_MIXED)
+                          stream, mixed=p.precision == EMIN_PREC_MIXED)
 
     def p_nnz(self):
         return sum(L.pattern.sizes["nnz_Pv"] + L.pattern.sizes["nnz_Pp"] for L in self.levels)
