@@ -743,6 +743,104 @@ int orc_emin(const orc_csr *M, orc_csr *P, const int32_t *cidx,
   return status;
 }
 
+/* The GMRES form of the constrained minimisation (sec. 4.3 names a
+ * constrained version of CG or GMRES): for a non-symmetric operator K the
+ * update is sought in the same constrained subspace (pattern N, C rows held,
+ * row-wise P W_c fixed), and k steps of GMRES are taken on the projected
+ * masked system Pi mask_N(K P) = 0 from the same start P0: the iterate
+ * minimises ||Pi mask_N(K P)||_F over P0 + K_k(Pi mask_N(K .), R0) with
+ * R0 = -Pi mask_N(K P0).  Arnoldi with modified Gram-Schmidt, the small
+ * least-squares problem by Givens rotations; stops early when the residual
+ * vanishes.  res_out[j] (iters+1) receives the squared residual norm after j
+ * steps. */
+int orc_emin_gmres(const orc_csr *K, orc_csr *P, const int32_t *cidx,
+                   const double *W, const double *Wc, int iters, double *res_out,
+                   int *its_done) {
+  int64_t n = P->nrows, nnz = P->rowptr[n];
+  if (K->nrows != n || K->ncols != n || iters < 0) return ORC_ERR_SHAPE;
+  if (!P->val) P->val = (double *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(double));
+  double *G = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+  int status = ORC_OK;
+  for (int64_t i = 0; i < n; i++) {
+    int64_t a = P->rowptr[i], b = P->rowptr[i + 1];
+    double g = 0.0;
+    for (int64_t s = a; s < b; s++) g = g + Wc[P->col[s]] * Wc[P->col[s]];
+    G[i] = g;
+    if (cidx[i] >= 0) { for (int64_t s = a; s < b; s++) P->val[s] = 1.0; continue; }
+    if (g > 0.0) {
+      for (int64_t s = a; s < b; s++) P->val[s] = (W[i] * Wc[P->col[s]]) / g;
+    } else {
+      for (int64_t s = a; s < b; s++) P->val[s] = 0.0;
+      if (W[i] != 0.0) status = ORC_ERR_INFEASIBLE;
+    }
+  }
+  int m = iters;
+  size_t vb = (size_t)(nnz > 0 ? nnz : 1) * sizeof(double);
+  double *V = (double *)malloc(vb * (size_t)(m + 1));
+  double *w = (double *)malloc(vb);
+  double *H = (double *)calloc((size_t)(m + 1) * (size_t)(m > 0 ? m : 1), sizeof(double));
+  double *cs = (double *)calloc((size_t)(m > 0 ? m : 1), sizeof(double));
+  double *sn = (double *)calloc((size_t)(m > 0 ? m : 1), sizeof(double));
+  double *g = (double *)calloc((size_t)(m + 1), sizeof(double));
+  /* R0 = -Pi mask(K P0) */
+  masked_spmm(K, P, P->val, w);
+  for (int64_t e = 0; e < nnz; e++) w[e] = -w[e];
+  project(P, cidx, Wc, G, w);
+  double beta = sqrt(fdot(nnz, w, w));
+  if (res_out) res_out[0] = beta * beta;
+  int j = 0;
+  if (status == ORC_OK && beta > 0.0) {
+    for (int64_t e = 0; e < nnz; e++) V[e] = w[e] / beta;
+    g[0] = beta;
+    for (; j < m; j++) {
+      double *vj = V + (size_t)j * (size_t)nnz;
+      masked_spmm(K, P, vj, w);
+      project(P, cidx, Wc, G, w);
+      for (int i = 0; i <= j; i++) {
+        double *vi = V + (size_t)i * (size_t)nnz;
+        double h = fdot(nnz, vi, w);
+        H[(size_t)i * (size_t)m + j] = h;
+        for (int64_t e = 0; e < nnz; e++) w[e] = w[e] - h * vi[e];
+      }
+      double hn = sqrt(fdot(nnz, w, w));
+      H[(size_t)(j + 1) * (size_t)m + j] = hn;
+      /* earlier rotations on the new column, then a new one */
+      for (int i = 0; i < j; i++) {
+        double a = H[(size_t)i * (size_t)m + j], b = H[(size_t)(i + 1) * (size_t)m + j];
+        H[(size_t)i * (size_t)m + j] = cs[i] * a + sn[i] * b;
+        H[(size_t)(i + 1) * (size_t)m + j] = -sn[i] * a + cs[i] * b;
+      }
+      double a = H[(size_t)j * (size_t)m + j], b = hn;
+      double r = sqrt(a * a + b * b);
+      cs[j] = a / r;
+      sn[j] = b / r;
+      H[(size_t)j * (size_t)m + j] = r;
+      H[(size_t)(j + 1) * (size_t)m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      if (res_out) res_out[j + 1] = g[j + 1] * g[j + 1];
+      if (hn == 0.0) { j++; break; }
+      double *vn = V + (size_t)(j + 1) * (size_t)nnz;
+      for (int64_t e = 0; e < nnz; e++) vn[e] = w[e] / hn;
+    }
+    /* back substitution R y = g, then P += V y */
+    double *y = (double *)calloc((size_t)(j > 0 ? j : 1), sizeof(double));
+    for (int i = j - 1; i >= 0; i--) {
+      double t = g[i];
+      for (int c = i + 1; c < j; c++) t = t - H[(size_t)i * (size_t)m + c] * y[c];
+      y[i] = t / H[(size_t)i * (size_t)m + i];
+    }
+    for (int i = 0; i < j; i++) {
+      double *vi = V + (size_t)i * (size_t)nnz;
+      for (int64_t e = 0; e < nnz; e++) P->val[e] = P->val[e] + y[i] * vi[e];
+    }
+    free(y);
+  }
+  if (its_done) *its_done = j;
+  free(G); free(V); free(w); free(H); free(cs); free(sn); free(g);
+  return status;
+}
+
 /* Alg. 1: A_{l+1} = R A P with R = P^T (the symmetric choice of sec. 4.3).
  * The velocity prolongator is I_d (x) Pv (sec. 4: each component uses the
  * same pattern and P^(v) is block diagonal by component), so the coarse
@@ -776,6 +874,36 @@ int orc_rap(const orc_csr *Ahat, const orc_csr *Bdiv, int dim,
   return ORC_OK;
 }
 
+/* Petrov-Galerkin product (sec. 4.3, last paragraph): R_v = (Rvt)^T and
+ * R_p = Pp^T.  Ac = Rvt^T Ahat Pv, Bc = Pp^T Bdiv (I_d (x) Pv) as before, and
+ * the coarse gradient block, stored transposed on Bc's pattern:
+ * Gct = Pp^T Gt (I_d (x) Rvt), with Gt the fine gradient block's transpose
+ * on Bdiv's pattern (Gt_val NULL: the gradient is Bdiv^T, Gt = Bdiv). */
+int orc_rap_pg(const orc_csr *Ahat, const orc_csr *Bdiv, const double *Gt_val, int dim,
+               const orc_csr *Pv, const orc_csr *Rvt, const orc_csr *Pp, orc_csr *Ac,
+               orc_csr *Bc, orc_csr *Gct) {
+  int64_t nv = Ahat->nrows;
+  if (Pv->nrows != nv || Rvt->nrows != nv || Bdiv->ncols != dim * nv || Pp->nrows != Bdiv->nrows)
+    return ORC_ERR_SHAPE;
+  orc_csr T, RT;
+  orc_spgemm(Ahat, Pv, &T);
+  orc_transpose(Rvt, &RT);
+  orc_spgemm(&RT, &T, Ac);
+  orc_csr_free(&T); orc_csr_free(&RT);
+  orc_csr dummyA;
+  int st = orc_rap(Ahat, Bdiv, dim, Pv, Pp, &dummyA, Bc);
+  orc_csr_free(&dummyA);
+  if (st) return st;
+  orc_csr Gt = *Bdiv;
+  double *gv = NULL;
+  if (Gt_val) Gt.val = (double *)Gt_val;
+  orc_csr dummyB;
+  st = orc_rap(Ahat, &Gt, dim, Rvt, Pp, &dummyB, Gct);
+  orc_csr_free(&dummyB);
+  free(gv);
+  return st;
+}
+
 /* ------------------------------------------------------------------ */
 /* one level: Alg. 2 (form_interpolation) + EMIN + RAP + coordinates    */
 /* ------------------------------------------------------------------ */
@@ -799,28 +927,26 @@ static int32_t *cidx_of(const uint8_t *flag, int64_t n, int64_t *nc) {
   return c;
 }
 
-/* One level of Alg. 1.  The EMIN energy of the velocity block (sec. 4.3, eq.
- * (min_problem)) is the norm of the symmetrised filtered operator
+/* One level of Alg. 1.  The velocity block's EMIN (sec. 4.3, eq.
+ * (min_problem)) takes the norm of the symmetrised filtered operator
  * M = (A~ + A~^T)/2, or with energy_ata the A^T A-norm the section names for
- * non-symmetric operators: M = A~^T A~.  Either way the distance-3 velocity
- * pattern is grown on the symmetrised filtered graph, and L->Mv is the
- * energy operator EMIN used. */
-int orc_level(int dim, const orc_csr *Ahat, const orc_csr *Bdiv,
-              const double *xv, const int32_t *p2v,
-              double tau1_v, double tau1_p, double tau2_sq, int iters, int energy_ata,
-              orc_level_t *L) {
-  return orc_level_cp(dim, Ahat, Bdiv, xv, p2v, tau1_v, tau1_p, tau2_sq, iters, energy_ata,
-                      NULL, L);
-}
-
-int orc_level_cp(int dim, const orc_csr *Ahat, const orc_csr *Bdiv,
-                 const double *xv, const int32_t *p2v,
-                 double tau1_v, double tau1_p, double tau2_sq, int iters, int energy_ata,
-                 const uint8_t *cp_in, orc_level_t *L) {
+ * non-symmetric operators (M = A~^T A~), or with gmres the GMRES form on A~
+ * itself.  With pg the restriction is not P^T: following the section's last
+ * paragraph, R_v^T is a second energy minimisation on the same pattern with
+ * the A A^T-norm (M = A~ A~^T; with gmres, the GMRES form on A~^T), R_p stays
+ * P_p^T (its operator is symmetric), and the coarse gradient block differs
+ * from the transposed divergence: G_c^T = P_p^T G^T (I_d (x) R_v^T).  The
+ * distance-3 velocity pattern is grown on the symmetrised filtered graph
+ * either way, and L->Mv is the operator P's minimisation used. */
+int orc_level_ex(int dim, const orc_csr *Ahat, const orc_csr *Bdiv, const double *Gt_val,
+                 const double *xv, const int32_t *p2v, const orc_opts_t *o, orc_level_t *L) {
   memset(L, 0, sizeof(*L));
   L->dim = dim;
+  const double tau1_v = o->tau1_v, tau1_p = o->tau1_p, tau2_sq = o->tau2_sq;
+  const int iters = o->iters;
   int64_t nv = Ahat->nrows, np = Bdiv->nrows;
   if (dim < 1 || dim > 3 || iters < 0) return L->status = ORC_ERR_ARG;
+  if (o->energy_ata && o->gmres) return L->status = ORC_ERR_ARG;
   if (Ahat->ncols != nv || Bdiv->ncols != dim * nv) return L->status = ORC_ERR_SHAPE;
   int st = check_csr(Ahat);
   if (!st) st = check_csr(Bdiv);
@@ -840,13 +966,20 @@ int orc_level_cp(int dim, const orc_csr *Ahat, const orc_csr *Bdiv,
   orc_symmetrize(&Atp, &L->Mp);
   orc_csr Gv; /* velocity graph: the symmetrised filtered operator */
   orc_symmetrize(&Atv, &Gv);
-  if (energy_ata) {
-    orc_csr AtvT;
-    orc_transpose(&Atv, &AtvT);
-    orc_spgemm(&AtvT, &Atv, &L->Mv);
-    orc_csr_free(&AtvT);
+  orc_csr AtvT;
+  orc_transpose(&Atv, &AtvT);
+  orc_csr Rop = {0};   /* the restriction's operator (pg) */
+  if (o->energy_ata) orc_spgemm(&AtvT, &Atv, &L->Mv);
+  if (o->pg) {
+    if (o->gmres) {
+      Rop = AtvT;                     /* GMRES form on A~^T */
+      AtvT.rowptr = NULL; AtvT.col = NULL; AtvT.val = NULL;
+    } else {
+      orc_spgemm(&Atv, &AtvT, &Rop);  /* A A^T-norm */
+    }
   }
-  orc_csr_free(&BT); orc_csr_free(&Z); orc_csr_free(&Atp); orc_csr_free(&Atv);
+  orc_csr_free(&AtvT);
+  orc_csr_free(&BT); orc_csr_free(&Z); orc_csr_free(&Atp);
   L->dir = (uint8_t *)malloc((size_t)(nv > 0 ? nv : 1));
   orc_dirichlet(Ahat, L->dir);
 
@@ -856,8 +989,8 @@ int orc_level_cp(int dim, const orc_csr *Ahat, const orc_csr *Bdiv,
     for (int d = 0; d < dim; d++) xp[i * dim + d] = xv[(int64_t)p2v[i] * dim + d];
 
   L->is_cp = (uint8_t *)malloc((size_t)(np > 0 ? np : 1));
-  if (cp_in) {
-    memcpy(L->is_cp, cp_in, (size_t)np);
+  if (o->cp_in) {
+    memcpy(L->is_cp, o->cp_in, (size_t)np);
     orc_sets_from_cpoints(&L->Mp, L->is_cp, &L->S, &L->sdist, &L->order, &L->n_cp);
     L->n_alg3 = L->n_cp;
   } else {
@@ -872,8 +1005,10 @@ int orc_level_cp(int dim, const orc_csr *Ahat, const orc_csr *Bdiv,
   for (int64_t i = 0; i < np; i++)
     if (L->cbar[i]) L->is_cv[p2v[i]] = 1;
   orc_velocity_pattern(&Gv, L->dir, L->is_cv, &L->Pv, &L->n_extra_v);
-  if (energy_ata) orc_csr_free(&Gv);
+  if (o->energy_ata) orc_csr_free(&Gv);
+  else if (o->gmres) { orc_csr_free(&Gv); L->Mv = Atv; Atv.rowptr = NULL; Atv.col = NULL; Atv.val = NULL; }
   else L->Mv = Gv;
+  orc_csr_free(&Atv);
   int64_t ncv, ncp;
   int32_t *cv_id = cidx_of(L->is_cv, nv, &ncv);
   int32_t *cp_id = cidx_of(L->is_cp, np, &ncp);
@@ -896,10 +1031,34 @@ int orc_level_cp(int dim, const orc_csr *Ahat, const orc_csr *Bdiv,
   L->energy_p = (double *)calloc((size_t)iters + 1, sizeof(double));
   L->rho_v = (double *)calloc((size_t)iters + 1, sizeof(double));
   L->rho_p = (double *)calloc((size_t)iters + 1, sizeof(double));
-  st = orc_emin(&L->Mv, &L->Pv, cv_id, Wv, Wvc, iters, L->energy_v, L->rho_v, NULL, &L->its_v);
+  if (o->gmres)
+    st = orc_emin_gmres(&L->Mv, &L->Pv, cv_id, Wv, Wvc, iters, L->rho_v, &L->its_v);
+  else
+    st = orc_emin(&L->Mv, &L->Pv, cv_id, Wv, Wvc, iters, L->energy_v, L->rho_v, NULL, &L->its_v);
   if (!st) st = orc_emin(&L->Mp, &L->Pp, cp_id, Wp, Wpc, iters, L->energy_p, L->rho_p, NULL, &L->its_p);
+  if (!st && o->pg) {
+    /* R_v^T on the velocity pattern */
+    L->Rvt.nrows = L->Pv.nrows; L->Rvt.ncols = L->Pv.ncols;
+    L->Rvt.rowptr = (int64_t *)malloc((size_t)(nv + 1) * sizeof(int64_t));
+    memcpy(L->Rvt.rowptr, L->Pv.rowptr, (size_t)(nv + 1) * sizeof(int64_t));
+    int64_t pn = L->Pv.rowptr[nv];
+    L->Rvt.col = (int32_t *)malloc((size_t)(pn > 0 ? pn : 1) * sizeof(int32_t));
+    memcpy(L->Rvt.col, L->Pv.col, (size_t)(pn > 0 ? pn : 0) * sizeof(int32_t));
+    L->Rvt.val = NULL;
+    L->rho_r = (double *)calloc((size_t)iters + 1, sizeof(double));
+    L->energy_r = (double *)calloc((size_t)iters + 1, sizeof(double));
+    if (o->gmres)
+      st = orc_emin_gmres(&Rop, &L->Rvt, cv_id, Wv, Wvc, iters, L->rho_r, &L->its_r);
+    else
+      st = orc_emin(&Rop, &L->Rvt, cv_id, Wv, Wvc, iters, L->energy_r, L->rho_r, NULL, &L->its_r);
+  }
+  orc_csr_free(&Rop);
   free(Wv); free(Wp); free(Wvc); free(Wpc);
-  if (!st) st = orc_rap(Ahat, Bdiv, dim, &L->Pv, &L->Pp, &L->Ac, &L->Bc);
+  if (!st) {
+    if (o->pg) st = orc_rap_pg(Ahat, Bdiv, Gt_val, dim, &L->Pv, &L->Rvt, &L->Pp, &L->Ac, &L->Bc,
+                               &L->Gct);
+    else st = orc_rap(Ahat, Bdiv, dim, &L->Pv, &L->Pp, &L->Ac, &L->Bc);
+  }
   /* coarse descriptors: coordinates by injection, co-location map */
   if (!st) {
     L->xv_c = (double *)malloc((size_t)(ncv > 0 ? ncv : 1) * dim * sizeof(double));
@@ -918,8 +1077,29 @@ int orc_level_cp(int dim, const orc_csr *Ahat, const orc_csr *Bdiv,
   return L->status = st;
 }
 
+int orc_level(int dim, const orc_csr *Ahat, const orc_csr *Bdiv,
+              const double *xv, const int32_t *p2v,
+              double tau1_v, double tau1_p, double tau2_sq, int iters, int energy_ata,
+              orc_level_t *L) {
+  return orc_level_cp(dim, Ahat, Bdiv, xv, p2v, tau1_v, tau1_p, tau2_sq, iters, energy_ata,
+                      NULL, L);
+}
+
+int orc_level_cp(int dim, const orc_csr *Ahat, const orc_csr *Bdiv,
+                 const double *xv, const int32_t *p2v,
+                 double tau1_v, double tau1_p, double tau2_sq, int iters, int energy_ata,
+                 const uint8_t *cp_in, orc_level_t *L) {
+  orc_opts_t o;
+  memset(&o, 0, sizeof(o));
+  o.tau1_v = tau1_v; o.tau1_p = tau1_p; o.tau2_sq = tau2_sq; o.iters = iters;
+  o.energy_ata = energy_ata; o.cp_in = cp_in;
+  return orc_level_ex(dim, Ahat, Bdiv, NULL, xv, p2v, &o, L);
+}
+
 void orc_level_free(orc_level_t *L) {
   orc_csr_free(&L->Mv); orc_csr_free(&L->Mp);
+  orc_csr_free(&L->Rvt); orc_csr_free(&L->Gct);
+  free(L->rho_r); free(L->energy_r);
   free(L->keep_v); free(L->keep_p); free(L->dir);
   free(L->is_cp); orc_csr_free(&L->S); free(L->sdist); free(L->order);
   free(L->cbar); free(L->is_cv);

@@ -84,6 +84,12 @@ int orc_emin(const orc_csr *M, orc_csr *P, const int32_t *cidx,
              const double *W, const double *Wc, int iters,
              double *energy, double *rho, double *gamma, int *its_done);
 
+/* GMRES form of the same constrained problem for a non-symmetric operator
+ * K: k steps of GMRES on Pi mask_N(K P) = 0 from P0; res[iters+1] (may be
+ * NULL) receives the squared residual norms. */
+int orc_emin_gmres(const orc_csr *K, orc_csr *P, const int32_t *cidx,
+                   const double *W, const double *Wc, int iters, double *res, int *its_done);
+
 /* Galerkin product: Ac = Pv^T Ahat Pv, Bc = Pp^T Bdiv (I_d (x) Pv). */
 int orc_rap(const orc_csr *Ahat, const orc_csr *Bdiv, int dim,
             const orc_csr *Pv, const orc_csr *Pp, orc_csr *Ac, orc_csr *Bc);
@@ -115,7 +121,28 @@ typedef struct {
   orc_csr Ac, Bc;
   double *xv_c;                /* n_cv*dim */
   int32_t *p2v_c;              /* n_cp */
+  /* Petrov-Galerkin restriction (pg): R_v^T on Pv's pattern, its trace, and
+   * the coarse gradient block's transpose on Bc's pattern */
+  orc_csr Rvt, Gct;
+  double *energy_r, *rho_r;    /* iters+1 */
+  int its_r;
 } orc_level_t;
+
+/* options of orc_level_ex */
+typedef struct {
+  double tau1_v, tau1_p, tau2_sq;
+  int iters;
+  int energy_ata;              /* velocity P in the A^T A-norm */
+  int gmres;                   /* velocity P by the GMRES form on A~ */
+  int pg;                      /* Petrov-Galerkin restriction */
+  const uint8_t *cp_in;        /* C^(p) given (n_p flags) or NULL */
+} orc_opts_t;
+
+/* Petrov-Galerkin Galerkin product: Ac = Rvt^T Ahat Pv, Bc = Pp^T Bdiv (I_d (x) Pv),
+ * Gct = Pp^T Gt (I_d (x) Rvt) (Gt_val: values on Bdiv's pattern, NULL = Bdiv). */
+int orc_rap_pg(const orc_csr *Ahat, const orc_csr *Bdiv, const double *Gt_val, int dim,
+               const orc_csr *Pv, const orc_csr *Rvt, const orc_csr *Pp, orc_csr *Ac,
+               orc_csr *Bc, orc_csr *Gct);
 
 int orc_level(int dim, const orc_csr *Ahat, const orc_csr *Bdiv,
               const double *xv, const int32_t *p2v,
@@ -127,6 +154,10 @@ int orc_level_cp(int dim, const orc_csr *Ahat, const orc_csr *Bdiv,
                  const double *xv, const int32_t *p2v,
                  double tau1_v, double tau1_p, double tau2_sq, int iters, int energy_ata,
                  const uint8_t *cp_in, orc_level_t *L);
+/* The level under options; Gt_val: the fine gradient block's transpose on
+ * Bdiv's pattern (pg only; NULL = Bdiv). */
+int orc_level_ex(int dim, const orc_csr *Ahat, const orc_csr *Bdiv, const double *Gt_val,
+                 const double *xv, const int32_t *p2v, const orc_opts_t *o, orc_level_t *L);
 void orc_level_free(orc_level_t *L);
 
 #ifdef __cplusplus

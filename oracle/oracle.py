@@ -47,7 +47,16 @@ class c_level(C.Structure):
                 ("rho_v", C.POINTER(C.c_double)), ("rho_p", C.POINTER(C.c_double)),
                 ("its_v", C.c_int), ("its_p", C.c_int),
                 ("Ac", c_csr), ("Bc", c_csr),
-                ("xv_c", C.POINTER(C.c_double)), ("p2v_c", C.POINTER(C.c_int32))]
+                ("xv_c", C.POINTER(C.c_double)), ("p2v_c", C.POINTER(C.c_int32)),
+                ("Rvt", c_csr), ("Gct", c_csr),
+                ("energy_r", C.POINTER(C.c_double)), ("rho_r", C.POINTER(C.c_double)),
+                ("its_r", C.c_int)]
+
+
+class c_opts(C.Structure):
+    _fields_ = [("tau1_v", C.c_double), ("tau1_p", C.c_double), ("tau2_sq", C.c_double),
+                ("iters", C.c_int), ("energy_ata", C.c_int), ("gmres", C.c_int), ("pg", C.c_int),
+                ("cp_in", C.POINTER(C.c_uint8))]
 
 
 _lib = None
@@ -80,12 +89,16 @@ def lib():
                                C.c_int, P(C.c_double), P(C.c_double), P(C.c_double), P(C.c_int)]
         L.orc_rap.argtypes = [P(c_csr), P(c_csr), C.c_int, P(c_csr), P(c_csr), P(c_csr),
                               P(c_csr)]
+        L.orc_emin_gmres.argtypes = [P(c_csr), P(c_csr), P(C.c_int32), P(C.c_double),
+                                     P(C.c_double), C.c_int, P(C.c_double), P(C.c_int)]
         L.orc_level.argtypes = [C.c_int, P(c_csr), P(c_csr), P(C.c_double), P(C.c_int32),
                                 C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
                                 P(c_level)]
         L.orc_level_cp.argtypes = [C.c_int, P(c_csr), P(c_csr), P(C.c_double), P(C.c_int32),
                                    C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
                                    P(C.c_uint8), P(c_level)]
+        L.orc_level_ex.argtypes = [C.c_int, P(c_csr), P(c_csr), P(C.c_double), P(C.c_double),
+                                   P(C.c_int32), P(c_opts), P(c_level)]
         L.orc_level_free.argtypes = [P(c_level)]
         _lib = L
     return _lib
@@ -257,6 +270,25 @@ def emin(M: CSR, N: CSR, cidx: np.ndarray, W: np.ndarray, Wc: np.ndarray, iters:
     return EminResult(P, e, r, g[:iters], its.value, st)
 
 
+def emin_gmres(K: CSR, N: CSR, cidx: np.ndarray, W: np.ndarray, Wc: np.ndarray, iters: int,
+               raise_on_error: bool = True) -> EminResult:
+    """GMRES form of the constrained minimisation on a non-symmetric operator K
+    (orc_emin_gmres); rho holds the squared residual norms."""
+    m = _In(K)
+    p = _In(CSR(N.nrows, N.ncols, N.rowptr, N.col, np.zeros(N.nnz)))
+    ci = np.ascontiguousarray(cidx, dtype=np.int32)
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    Wc = np.ascontiguousarray(Wc, dtype=np.float64)
+    r = np.zeros(iters + 1)
+    its = C.c_int()
+    st = lib().orc_emin_gmres(C.byref(m.c), C.byref(p.c), _ptr(ci, C.c_int32), _ptr(W, C.c_double),
+                              _ptr(Wc, C.c_double), iters, _ptr(r, C.c_double), C.byref(its))
+    if st != 0 and raise_on_error:
+        raise OracleError(st)
+    P = CSR(N.nrows, N.ncols, N.rowptr.copy(), N.col.copy(), p.val.copy())
+    return EminResult(P, np.zeros(iters + 1), r, np.zeros(max(iters, 0)), its.value, st)
+
+
 def rap(Ahat: CSR, Bdiv: CSR, dim: int, Pv: CSR, Pp: CSR):
     a, b, pv, pp = _In(Ahat), _In(Bdiv), _In(Pv), _In(Pp)
     ac, bc = c_csr(), c_csr()
@@ -296,13 +328,21 @@ class Level:
     Bc: CSR
     xv_c: np.ndarray
     p2v_c: np.ndarray
+    Rvt: CSR = None          # Petrov-Galerkin: R_v^T on Pv's pattern
+    Gct: CSR = None          # coarse gradient block's transpose on Bc's pattern
+    rho_r: np.ndarray = None
+    its_r: int = 0
 
     def coarse_system(self, meta=None) -> System:
-        return System(self.dim, self.Ac, self.Bc, self.xv_c, self.p2v_c, meta=dict(meta or {}))
+        m = dict(meta or {})
+        if self.Gct is not None:
+            m["Gt"] = self.Gct.val
+        return System(self.dim, self.Ac, self.Bc, self.xv_c, self.p2v_c, meta=m)
 
 
 def level(sys: System, tau1_v: float = TAU1, tau1_p: float = TAU1, tau2_sq: float = TAU2_SQ,
-          iters: int = 5, energy_ata: bool = False, cpoints=None) -> Level:
+          iters: int = 5, energy_ata: bool = False, cpoints=None, gmres: bool = False,
+          pg: bool = False) -> Level:
     """One level of Alg. 1 (orc_level).  energy_ata: the velocity block's EMIN
     energy is the A^T A-norm of the filtered operator (sec. 4.3, eq.
     (min_problem), for non-symmetric operators) instead of the norm of its
@@ -313,15 +353,15 @@ def level(sys: System, tau1_v: float = TAU1, tau1_p: float = TAU1, tau2_sq: floa
     xv = np.ascontiguousarray(sys.xv, dtype=np.float64)
     p2v = np.ascontiguousarray(sys.p2v, dtype=np.int32)
     L = c_level()
-    if cpoints is None:
-        st = lib().orc_level(sys.dim, C.byref(a.c), C.byref(b.c), _ptr(xv, C.c_double),
-                             _ptr(p2v, C.c_int32), tau1_v, tau1_p, tau2_sq, iters,
-                             1 if energy_ata else 0, C.byref(L))
-    else:
-        cp = np.ascontiguousarray(np.asarray(cpoints, dtype=bool).astype(np.uint8))
-        st = lib().orc_level_cp(sys.dim, C.byref(a.c), C.byref(b.c), _ptr(xv, C.c_double),
-                                _ptr(p2v, C.c_int32), tau1_v, tau1_p, tau2_sq, iters,
-                                1 if energy_ata else 0, _ptr(cp, C.c_uint8), C.byref(L))
+    cp = (None if cpoints is None else
+          np.ascontiguousarray(np.asarray(cpoints, dtype=bool).astype(np.uint8)))
+    o = c_opts(tau1_v, tau1_p, tau2_sq, iters, 1 if energy_ata else 0, 1 if gmres else 0,
+               1 if pg else 0, _ptr(cp, C.c_uint8) if cp is not None else C.POINTER(C.c_uint8)())
+    gt = sys.meta.get("Gt") if getattr(sys, "meta", None) else None
+    gt = None if gt is None else np.ascontiguousarray(gt, dtype=np.float64)
+    st = lib().orc_level_ex(sys.dim, C.byref(a.c), C.byref(b.c),
+                            _ptr(gt, C.c_double) if gt is not None else C.POINTER(C.c_double)(),
+                            _ptr(xv, C.c_double), _ptr(p2v, C.c_int32), C.byref(o), C.byref(L))
     try:
         _check(st)
         nv, np_, d = sys.n_v, sys.n_p, sys.dim
@@ -346,6 +386,11 @@ def level(sys: System, tau1_v: float = TAU1, tau1_p: float = TAU1, tau2_sq: floa
             xv_c=_arr(L.xv_c, int(L.n_cv) * d, np.float64).reshape(-1, d),
             p2v_c=_arr(L.p2v_c, int(L.n_cp), np.int32))
         out.sdist = _arr(L.sdist, out.S.nnz, np.int32)
+        if pg:
+            out.Rvt = _out(L.Rvt, free=False)
+            out.Gct = _out(L.Gct, free=False)
+            out.rho_r = _arr(L.rho_r, iters + 1, np.float64)
+            out.its_r = int(L.its_r)
         return out
     finally:
         lib().orc_level_free(C.byref(L))
@@ -353,7 +398,7 @@ def level(sys: System, tau1_v: float = TAU1, tau1_p: float = TAU1, tau2_sq: floa
 
 def hierarchy(sys: System, nlevels: int, tau1_v: float = TAU1, tau1_p: float = TAU1,
               tau2_sq: float = TAU2_SQ, iters: int = 5, min_dofs: int = 0,
-              energy_ata: bool = False):
+              energy_ata: bool = False, gmres: bool = False, pg: bool = False):
     """Alg. 1 without relaxation: levels 0..nlevels-1 (nlevels-1 transfers),
     stopping early when a level has at most min_dofs dofs."""
     out = []
@@ -361,7 +406,7 @@ def hierarchy(sys: System, nlevels: int, tau1_v: float = TAU1, tau1_p: float = T
     for _ in range(nlevels - 1):
         if cur.dofs <= min_dofs:
             break
-        L = level(cur, tau1_v, tau1_p, tau2_sq, iters, energy_ata=energy_ata)
+        L = level(cur, tau1_v, tau1_p, tau2_sq, iters, energy_ata=energy_ata, gmres=gmres, pg=pg)
         out.append(L)
         cur = L.coarse_system()
     return out, cur

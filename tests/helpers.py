@@ -96,7 +96,7 @@ def emin_quadratic(M: np.ndarray, N: CSR, cidx: np.ndarray, Wc: np.ndarray):
     rows = np.repeat(np.arange(n), np.diff(N.rowptr))
     cols = np.asarray(N.col)
     same_col = cols[:, None] == cols[None, :]
-    H = np.where(same_col, M[rows][:, rows], 0.0)
+    H = np.where(same_col, M[rows][:, rows], 0.0)   # M need not be symmetric
     nnz = N.nnz
     Pi = np.eye(nnz)
     for i in range(n):
@@ -156,3 +156,45 @@ def krylov_emin_iterate(M: np.ndarray, N: CSR, cidx: np.ndarray, W: np.ndarray, 
     y = np.linalg.solve(K.T @ H @ K, -(K.T @ (H @ p0)))
     del rows
     return p0 + K @ y
+
+
+def gmres_krylov_iterate(K: np.ndarray, N: CSR, cidx: np.ndarray, W: np.ndarray, Wc: np.ndarray,
+                         k: int) -> np.ndarray:
+    """k-th iterate of GMRES on the constrained problem, by its
+    characterisation: with Kmask the masked operator over P's pattern entries
+    ((i,j),(l,j) -> K[i,l]) and Pi the projector of emin_quadratic, the
+    minimiser of ||Pi Kmask p|| over p0 + K_k(Pi Kmask Pi, r0), r0 = -Pi Kmask
+    p0 (dense least squares over an orthonormal Krylov basis)."""
+    n = N.nrows
+    rows = np.repeat(np.arange(n), np.diff(N.rowptr))
+    cols = np.asarray(N.col)
+    Km, Pi = emin_quadratic(K, N, cidx, Wc)   # Km = K restricted to same-column entries
+    p0 = np.zeros(N.nnz)
+    for i in range(n):
+        a, b = int(N.rowptr[i]), int(N.rowptr[i + 1])
+        if cidx[i] >= 0:
+            p0[a:b] = 1.0
+            continue
+        g = float(np.sum(Wc[cols[a:b]] ** 2))
+        if g > 0.0:
+            p0[a:b] = W[i] * Wc[cols[a:b]] / g
+    A = Pi @ Km
+    r = -(A @ p0)
+    basis = []
+    v = r.copy()
+    for _ in range(k):
+        for _rep in range(2):
+            for q in basis:
+                v = v - (q @ v) * q
+        nv = np.linalg.norm(v)
+        if nv <= 1e-14 * max(np.linalg.norm(r), 1e-300):
+            break
+        q = v / nv
+        basis.append(q)
+        v = A @ (Pi @ q)
+    if not basis:
+        return p0
+    Q = np.stack(basis, 1)
+    y = np.linalg.lstsq(A @ Q, r, rcond=None)[0]
+    del rows
+    return p0 + Q @ y

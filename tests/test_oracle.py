@@ -494,6 +494,109 @@ def test_emin_k_step_iterate_is_krylov_minimiser(oracle_lib, energy_ata):
             assert abs(r.energy[k] - np.trace(Pd.T @ H @ Pd)) <= 1e-10 * abs(r.energy[0])
 
 
+def test_emin_gmres_k_step_iterate(oracle_lib):
+    """The GMRES form of sec. 4.3's constrained minimisation on the
+    non-symmetric filtered Oseen velocity block: after k = 1..5 steps the
+    iterate minimises ||Pi mask_N(A~ P)||_F over P0 + K_k(Pi mask A~ Pi, R0),
+    the residual norms it reports are those of the iterates, the constraint
+    holds, and run long it solves the projected system (residual ~ 0)."""
+    from tests.helpers import emin_quadratic, gmres_krylov_iterate
+    O = oracle_lib
+    s = synth.make_system(2, 4, jitter=0.1, nu=0.02, wind="stream", seed=11)
+    At, _ = O.filter_lump(s.Ahat, 0.06)
+    Ad = dense(At)
+    assert np.abs(Ad - Ad.T).max() > 1e-3 * np.abs(Ad).max()
+    L = O.level(s, iters=0)
+    Wv, Wvc, cidv, _ = _modes(L, s)
+    Km, Pi = emin_quadratic(Ad, L.Pv, cidv, Wvc)
+    for k in range(1, 6):
+        r = O.emin_gmres(At, L.Pv, cidv, Wv, Wvc, k)
+        assert r.its == k
+        ref = gmres_krylov_iterate(Ad, L.Pv, cidv, Wv, Wvc, k)
+        assert relfro(r.P.val, ref) <= 1e-10, (k, relfro(r.P.val, ref))
+        res = Pi @ (Km @ r.P.val)
+        assert abs(r.rho[k] - res @ res) <= 1e-10 * r.rho[0]
+        assert np.all(np.diff(r.rho[:k + 1]) <= 1e-14 * r.rho[0])   # GMRES never increases it
+    Pv = CSR(L.Pv.nrows, L.Pv.ncols, L.Pv.rowptr, L.Pv.col, r.P.val).to_scipy()
+    assert np.linalg.norm(Pv @ Wvc - Wv) / np.linalg.norm(Wv) <= 1e-12
+    long = O.emin_gmres(At, L.Pv, cidv, Wv, Wvc, 32)
+    assert long.rho[long.its] <= 1e-20 * long.rho[0] or long.its < 32
+
+
+def test_level_gmres_form(oracle_lib):
+    """A level in the GMRES form: the velocity operator is the filtered,
+    non-symmetric A~ itself, the pattern and coarse points are those of the
+    A-norm level, and the velocity P is the GMRES iterate on A~."""
+    O = oracle_lib
+    s = synth.make_system(2, 6, jitter=0.1, nu=0.02, wind="stream", seed=7)
+    At, _ = O.filter_lump(s.Ahat, 0.06)
+    L0 = O.level(s, iters=3)
+    L = O.level(s, iters=3, gmres=True)
+    assert np.array_equal(dense(L.Mv), dense(At))
+    assert np.array_equal(L.Pv.col, L0.Pv.col) and np.array_equal(L.is_cv, L0.is_cv)
+    Wv, Wvc, cidv, _ = _modes(L, s)
+    r = O.emin_gmres(At, L.Pv, cidv, Wv, Wvc, 3)
+    assert np.array_equal(L.Pv.val, r.P.val) and np.array_equal(L.rho_v, r.rho)
+    assert np.array_equal(L.Pp.val, L0.Pp.val)
+    with pytest.raises(O.OracleError):
+        O.level(s, iters=3, gmres=True, energy_ata=True)
+
+
+@pytest.mark.parametrize("gmres", [False, True])
+def test_petrov_galerkin_restriction(oracle_lib, gmres):
+    """sec. 4.3, last paragraph: R != P^T for the non-symmetric block.  R_v^T
+    is a second minimisation on P's pattern in the A A^T-norm (or the GMRES
+    form on A~^T): run to convergence it reaches the dense KKT minimum of
+    trace(R A~ A~^T R^T) (CG form), or it is the k-step GMRES iterate on A~^T;
+    the coarse blocks are the dense products A_c = R_v A P_v,
+    B_c = P_p^T B (I (x) P_v), G_c^T = P_p^T B (I (x) R_v^T); and one more level
+    takes G_c^T as its gradient block."""
+    from tests.helpers import gmres_krylov_iterate
+    O = oracle_lib
+    s = synth.make_system(2, 4, jitter=0.1, nu=0.02, wind="stream", seed=11)
+    At, _ = O.filter_lump(s.Ahat, 0.06)
+    Ad = dense(At)
+    L = O.level(s, iters=4, pg=True, gmres=gmres)
+    Wv, Wvc, cidv, _ = _modes(L, s)
+    assert np.array_equal(L.Rvt.col, L.Pv.col)
+    if gmres:
+        ref = gmres_krylov_iterate(Ad.T, L.Rvt, cidv, Wv, Wvc, 4)
+        assert relfro(L.Rvt.val, ref) <= 1e-10
+    else:
+        Lc = O.level(s, iters=300, pg=True)
+        ref = kkt_emin(Ad @ Ad.T, Lc.Rvt, cidv, Wv, Wvc)
+        assert relfro(Lc.Rvt.val, ref) <= 1e-10
+        assert relfro(dense(L.Mv), 0.5 * (Ad + Ad.T)) <= 1e-15
+    Rv, Pv, Pp = dense(L.Rvt).T, dense(L.Pv), dense(L.Pp)
+    A, B = dense(s.Ahat), dense(s.Bdiv)
+    assert relfro(dense(L.Ac), Rv @ A @ Pv) <= 1e-13
+    assert relfro(dense(L.Bc), Pp.T @ B @ np.kron(np.eye(2), Pv)) <= 1e-13
+    assert np.array_equal(L.Gct.rowptr, L.Bc.rowptr) and np.array_equal(L.Gct.col, L.Bc.col)
+    Gct = Pp.T @ B @ np.kron(np.eye(2), Rv.T)
+    assert relfro(dense(L.Gct), Gct) <= 1e-13
+    # the constraint on R_v^T: rows sum to the mode
+    assert np.abs(dense(L.Rvt) @ Wvc - Wv).max() <= 1e-12
+    # next level: its gradient block is G_c (transposed, on B_c's pattern)
+    c = L.coarse_system()
+    if c.dofs > 30:
+        L1 = O.level(c, iters=2, pg=True, gmres=gmres)
+        Rv1, Pp1 = dense(L1.Rvt).T, dense(L1.Pp)
+        G1 = Pp1.T @ dense(CSR(c.Bdiv.nrows, c.Bdiv.ncols, c.Bdiv.rowptr, c.Bdiv.col,
+                                  c.meta["Gt"])) @ np.kron(np.eye(2), Rv1.T)
+        assert relfro(dense(L1.Gct), G1) <= 1e-13
+
+
+def test_petrov_galerkin_symmetric_block_equals_ata(oracle_lib):
+    """For a symmetric filtered block (Stokes) A A^T = A^T A, so the
+    restriction's minimisation is the A^T A-norm one: R_v^T equals the
+    prolongator of the A^T A-norm level."""
+    O = oracle_lib
+    s = synth.make_system(2, 6, jitter=0.1, seed=3)
+    L = O.level(s, iters=4, pg=True)
+    La = O.level(s, iters=4, energy_ata=True)
+    assert relfro(L.Rvt.val, La.Pv.val) <= 1e-13
+
+
 def test_emin_1d_linear_interpolation(oracle_lib):
     """1-D Laplacian, C every 4th node, distance-3 patterns: the constrained
     energy minimiser is piecewise-linear interpolation (hat functions)."""
