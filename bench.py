@@ -319,7 +319,7 @@ def run_batch(args, E, synth, torch):
     for h in hs:
         for z in h.sizes():
             for k in ("sched_v", "sched_p"):
-                name = E.sched_name(z[k] & 0xF)
+                name = E.sched_name(z[k] & 0x4F)
                 codes[name] = codes.get(name, 0) + 1
     stream = torch.cuda.current_stream()
 

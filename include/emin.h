@@ -69,7 +69,7 @@ enum {
                                     filtered operators that call formed are reused
                                     instead of being formed again (the caller vouches
                                     for it; nothing checks the values) */
-  EMIN_FLAG_ENERGY_ATA = 16u     /* sec. 4.3, eq. (min_problem): the velocity block's
+  EMIN_FLAG_ENERGY_ATA = 16u,    /* sec. 4.3, eq. (min_problem): the velocity block's
                                     energy is the A^T A-norm of the filtered operator,
                                     trace(P^T A~^T A~ P), the norm the section names for
                                     non-symmetric operators, instead of the norm of its
@@ -77,6 +77,28 @@ enum {
                                     block are unchanged.  emin_pattern forms A~^T A~;
                                     emin_setup must pass the same flag (EMIN_ERR_ARG
                                     otherwise).  EMIN_VIEW_MV is then A~^T A~. */
+  EMIN_FLAG_STAGED_PRODUCT = 32u, /* emin_pattern / emin_setup_with_pattern: the masked
+                                    product stages, per block of 16 rows that fits LDS,
+                                    the Z rows those rows reach (coalesced runs) and
+                                    sums from LDS, instead of gathering Z from device
+                                    memory row by row (the same sums in the same order,
+                                    so the same bits) */
+  EMIN_FLAG_GMRES = 64u,         /* sec. 4.3 names a constrained CG or GMRES: the velocity
+                                    block's EMIN runs `iters` steps of GMRES on the
+                                    projected masked system Pi mask_N(A~ P) = 0 of the
+                                    filtered, non-symmetric operator A~ itself, from the
+                                    same start P0 (the iterate minimises the projected
+                                    residual over the Krylov space); the report's rho_v
+                                    then holds the squared residual norms and energy_v
+                                    stays 0.  Not with EMIN_FLAG_ENERGY_ATA; emin_setup
+                                    must pass the same flag.  EMIN_VIEW_MV is then A~. */
+  EMIN_FLAG_PETROV_GALERKIN = 128u /* sec. 4.3, last paragraph: the restriction is not P^T.
+                                    emin_pattern also prepares a second minimisation for
+                                    R_v^T on the velocity pattern, in the A A^T-norm of
+                                    the filtered block (with EMIN_FLAG_GMRES: the GMRES
+                                    form on A~^T); emin_setup_pg computes it and
+                                    emin_rap_pg the Petrov-Galerkin coarse blocks.  R_p
+                                    stays P_p^T (its operator is symmetric). */
 };
 #define EMIN_MAX_ITERS 32
 
@@ -96,6 +118,9 @@ typedef struct {
   const int32_t *p2v;       /* n_p: velocity node co-located with each pressure */
   const double *Wv;         /* n_v near-nullspace mode or NULL: 1 off the Dirichlet set */
   const double *Wp;         /* n_p near-nullspace mode or NULL: all ones */
+  const double *Gt;         /* the gradient (1,2) block's transpose, its values on Bdiv's
+                               pattern, or NULL when it is Bdiv^T (a fine level; every
+                               level with R = P^T).  Read by emin_rap_pg only. */
 } emin_system_t;
 
 /* Parameters (sec. 6 uses tau1 = 0.06 and tau2 = sqrt(1.5e-3)). */
@@ -127,7 +152,9 @@ typedef struct {
                                one contiguous eighth per XCD (neither: one contiguous
                                eighth of the class-major grid per XCD); bits 4-5: 0
                                default, 1 autotuned on this pattern, 2 reused from an
-                               earlier tuning of the same shape */
+                               earlier tuning of the same shape; bit 6: blocks of rows
+                               staged in LDS (the other rows follow bits 0-3); bit 7:
+                               map rows gather 16 M entries per batch instead of 4 */
 } emin_sizes_t;
 
 /* Device-resident report of emin_setup (read it with emin_sync_report). */
@@ -138,6 +165,9 @@ typedef struct {
   double energy_v[EMIN_MAX_ITERS + 1], energy_p[EMIN_MAX_ITERS + 1];
   double rho_v[EMIN_MAX_ITERS + 1], rho_p[EMIN_MAX_ITERS + 1];
   double gamma_v[EMIN_MAX_ITERS], gamma_p[EMIN_MAX_ITERS];
+  /* the Petrov-Galerkin restriction's minimisation (emin_setup_pg) */
+  int32_t its_r, reserved2;
+  double energy_r[EMIN_MAX_ITERS + 1], rho_r[EMIN_MAX_ITERS + 1], gamma_r[EMIN_MAX_ITERS];
 } emin_report_t;
 
 /* Read-only device views held by a pattern handle (valid until destroy). */
@@ -246,6 +276,24 @@ emin_status emin_rap(emin_pattern_t *h, const emin_system_t *sys, const double *
                      const double *Pp_vals, double *Ac_vals, double *Bc_vals, int32_t precision,
                      void *stream);
 
+/* sec. 4.3, last paragraph (needs EMIN_FLAG_PETROV_GALERKIN at emin_pattern):
+ * emin_setup's work plus R_v^T (nnz_Pv values on the velocity pattern,
+ * caller-allocated) from the second minimisation, whose trace goes to the
+ * report's _r fields.  Asynchronous on stream. */
+emin_status emin_setup_pg(emin_pattern_t *h, const emin_system_t *sys, const emin_params_t *prm,
+                          double *Pv_vals, double *Pp_vals, double *Rvt_vals, void *stream,
+                          emin_report_t *report);
+
+/* Petrov-Galerkin coarse blocks with R_v = Rvt^T and R_p = P_p^T (FP64):
+ * Ac = R_v Ahat P_v (nnz_Ac), Bc = P_p^T Bdiv (I_d (x) P_v) (nnz_Bc, the
+ * divergence block), and the gradient block's transpose
+ * Gct = P_p^T G^T (I_d (x) Rvt) on Bc's pattern (nnz_Bc), G^T being sys->Gt
+ * (or Bdiv when NULL).  The next level takes Ac, Bc and Gct (as its Gt).
+ * Asynchronous on stream. */
+emin_status emin_rap_pg(emin_pattern_t *h, const emin_system_t *sys, const double *Pv_vals,
+                        const double *Pp_vals, const double *Rvt_vals, double *Ac_vals,
+                        double *Bc_vals, double *Gct_vals, void *stream);
+
 /* Synchronises stream, copies the report to host memory and returns its status. */
 emin_status emin_sync_report(const emin_report_t *report, void *stream, emin_report_t *host);
 
@@ -336,6 +384,34 @@ emin_status emin_server_release(emin_server_t *srv, int64_t ticket);
 emin_status emin_server_stats(emin_server_t *srv, int64_t *in_use, int32_t *queued,
                               int32_t *running);
 void emin_server_destroy(emin_server_t *srv);
+
+/* ------------------------------------------------------------------------
+ * Inf-sup diagnostic (sec. 6.1, Table 3)
+ * ------------------------------------------------------------------------ */
+typedef struct emin_matrix_s emin_matrix_t;
+
+/* C = P^T M P in device memory (the projection of a mass matrix to the next
+ * level with the level's transfer, sec. 6.1): M square n x n, P n x nc with
+ * values (e.g. the velocity pattern view with emin_setup's values).  The
+ * structural pattern; sums in ascending order.  Synchronous; *out owns C. */
+emin_status emin_galerkin(const emin_csr_t *M, const emin_csr_t *P, void *stream,
+                          emin_matrix_t **out);
+/* Borrowed device view of the matrix (valid until destroy). */
+emin_status emin_matrix_view(const emin_matrix_t *m, emin_csr_t *out);
+void emin_matrix_destroy(emin_matrix_t *m);
+
+/* sec. 6.1: the smallest non-zero singular value of
+ * B~ = lump(|M_p|)^(-1/2) B lump(|M_v|)^(-1/2), lump(|M|) being the diagonal
+ * of row sums of |M| and M_v acting on each of the dim velocity components
+ * (B is n_p x dim*n_v, component-blocked columns; M_v n_v x n_v; M_p
+ * n_p x n_p).  `steps` Lanczos steps with full re-orthogonalisation on
+ * B~ B~^T (at most n_p; n_p steps give its eigenvalues); singular values
+ * below rel * sigma_max count as zero (nzero of them, e.g. the hydrostatic
+ * pressure of an enclosed flow).  Synchronous; results in host memory.
+ * Errors: ARG, SHAPE, PATTERN, VALUE. */
+emin_status emin_infsup(const emin_csr_t *B, const emin_csr_t *Mv, const emin_csr_t *Mp,
+                        int32_t dim, int32_t steps, double rel, double *sigma_min,
+                        int32_t *nzero, int32_t *steps_done, void *stream);
 
 /* Kernel-class profiling with HIP events recorded on the launch stream
  * around each instrumented kernel.  Disabled by default.  collect

@@ -24,6 +24,18 @@ struct emin_pattern_s {
   // EMIN_FLAG_ENERGY_ATA: the velocity energy operator A~^T A~ (Mv stays the
   // velocity graph)
   bool ata = false;
+  // EMIN_FLAG_GMRES: the velocity block's operator is A~ itself, GMRES form
+  bool gmres = false;
+  GmresWork gv;
+  // EMIN_FLAG_PETROV_GALERKIN: the restriction's operator A~ A~^T (CG form) or
+  // A~^T (GMRES form), its workspace, and the Galerkin product's extra values
+  bool pg = false;
+  Csr Er;
+  SpgemmPlan erplan;
+  EminWork er;
+  GmresWork gr;
+  float* Mrf = nullptr;
+  double *X2val = nullptr, *U2val = nullptr;
   Csr AtvT, Ev;
   int32_t* atvt_src = nullptr;
   SpgemmPlan evplan;
@@ -172,13 +184,21 @@ int pick_lanes(const Csr& M) {
   return g;
 }
 
-// the operator whose norm EMIN minimises on the velocity block
-static const Csr& energy_v(const emin_pattern_t* h) { return h->ata ? h->Ev : h->Mv; }
+// the operator of the velocity block's EMIN: A~^T A~ (A^T A-norm), A~ itself
+// (GMRES form) or the symmetric part (A-norm)
+static const Csr& energy_v(const emin_pattern_t* h) {
+  return h->ata ? h->Ev : (h->gmres ? h->Atv : h->Mv);
+}
 
-// E = A~^T A~ from the filtered operator's current values
+// the restriction's operator (Petrov-Galerkin): A~ A~^T, or A~^T (GMRES form)
+static const Csr& energy_r(const emin_pattern_t* h) { return h->gmres ? h->AtvT : h->Er; }
+
+// A~^T's values, then E = A~^T A~ and the restriction's A~ A~^T from the
+// filtered operator's current values
 static void ata_numeric(emin_pattern_t* h, hipStream_t s) {
   gather_values(h->Atv.val, h->atvt_src, h->AtvT.val, h->AtvT.nnz, s);
-  spgemm_numeric(view(h->AtvT), view(h->Atv), h->Ev, h->evplan, s);
+  if (h->ata) spgemm_numeric(view(h->AtvT), view(h->Atv), h->Ev, h->evplan, s);
+  if (h->pg && !h->gmres) spgemm_numeric(view(h->Atv), view(h->AtvT), h->Er, h->erplan, s);
 }
 
 void build_pattern(emin_pattern_t* h, const emin_system_t* sys, const emin_params_t* prm,
@@ -227,10 +247,16 @@ void build_pattern(emin_pattern_t* h, const emin_system_t* sys, const emin_param
   symmetrize_numeric(h->Atv.val, h->mv_ia, h->mv_ib, h->Mv, s);
   // sec. 4.3, eq. (min_problem): the A^T A-norm for a non-symmetric block
   h->ata = (prm->flags & EMIN_FLAG_ENERGY_ATA) != 0;
-  if (h->ata) {
+  h->gmres = (prm->flags & EMIN_FLAG_GMRES) != 0;
+  if (h->ata && h->gmres)
+    throw Error(EMIN_ERR_ARG, "EMIN_FLAG_GMRES takes A~ itself, not the A^T A operator");
+  h->pg = (prm->flags & EMIN_FLAG_PETROV_GALERKIN) != 0;
+  if (h->ata || h->pg) {
     transpose_pattern(view(h->Atv), h->AtvT, h->atvt_src, s, ar);
     h->AtvT.val = ar.alloc<double>(h->AtvT.nnz);
-    spgemm_symbolic(view(h->AtvT), view(h->Atv), h->Ev, h->evplan, s, ar, h->derr);
+    if (h->ata) spgemm_symbolic(view(h->AtvT), view(h->Atv), h->Ev, h->evplan, s, ar, h->derr);
+    if (h->pg && !h->gmres)
+      spgemm_symbolic(view(h->Atv), view(h->AtvT), h->Er, h->erplan, s, ar, h->derr);
     ata_numeric(h, s);
   }
   h->dir = ar.alloc<uint8_t>(nv);
@@ -264,8 +290,16 @@ void build_pattern(emin_pattern_t* h, const emin_system_t* sys, const emin_param
   h->ep.smax = (int)max_row_len(h->cp.N.rowptr, np, s, ar);
   if (h->ev.smax > 64 || h->ep.smax > 64) throw Error(EMIN_ERR_CAPACITY, "pattern row > 64");
   const bool tune = (prm->flags & EMIN_FLAG_AUTOTUNE) != 0;
-  h->ev.make_bins(energy_v(h), h->vp.N.rowptr, h->vp.N.col, s, ar, tune);
-  h->ep.make_bins(h->Mp, h->cp.N.rowptr, h->cp.N.col, s, ar, tune);
+  const bool stage = (prm->flags & EMIN_FLAG_STAGED_PRODUCT) != 0;
+  h->ev.make_bins(energy_v(h), h->vp.N.rowptr, h->vp.N.col, s, ar, tune, stage);
+  h->ep.make_bins(h->Mp, h->cp.N.rowptr, h->cp.N.col, s, ar, tune, stage);
+  if (h->pg) {
+    h->er.allocate(nv, h->vp.N.nnz, h->vp.n_c, ar, mixed);
+    h->er.g = pick_lanes(energy_r(h));
+    h->er.smax = h->ev.smax;
+    h->er.make_bins(energy_r(h), h->vp.N.rowptr, h->vp.N.col, s, ar, tune, stage);
+    h->Mrf = ar.alloc<float>(energy_r(h).nnz);
+  }
   h->Mvf = ar.alloc<float>(energy_v(h).nnz);
   h->Mpf = ar.alloc<float>(h->Mp.nnz);
   h->Wv_def = ar.alloc<double>(nv);
@@ -338,11 +372,15 @@ void check_same_structure(const emin_pattern_t* h, const emin_system_t* sys) {
 }
 
 void run_setup(emin_pattern_t* h, const emin_system_t* sys, const emin_params_t* prm, double* Pv,
-               double* Pp, hipStream_t s, emin_report_t* rep) {
+               double* Pp, hipStream_t s, emin_report_t* rep, double* Rvt = nullptr) {
   check_same_structure(h, sys);
   check_params(prm);
   if (((prm->flags & EMIN_FLAG_ENERGY_ATA) != 0) != h->ata)
     throw Error(EMIN_ERR_ARG, "energy norm differs from the pattern's (EMIN_FLAG_ENERGY_ATA)");
+  if (((prm->flags & EMIN_FLAG_GMRES) != 0) != h->gmres)
+    throw Error(EMIN_ERR_ARG, "solver form differs from the pattern's (EMIN_FLAG_GMRES)");
+  if (((prm->flags & EMIN_FLAG_PETROV_GALERKIN) != 0) != h->pg)
+    throw Error(EMIN_ERR_ARG, "restriction differs from the pattern's (EMIN_FLAG_PETROV_GALERKIN)");
   if ((h->sizes.nnz_Pv && !Pv) || (h->sizes.nnz_Pp && !Pp)) throw Error(EMIN_ERR_ARG, "NULL P");
   const CsrView A = in_view(sys->Ahat), B = in_view(sys->Bdiv);
   emin_report_t* r = rep ? rep : h->rep_internal;
@@ -359,7 +397,7 @@ void run_setup(emin_pattern_t* h, const emin_system_t* sys, const emin_params_t*
     diag_of(A, h->dA, s);
     filter_numeric(A, h->keep_v, h->dA, h->Atv, s);
     symmetrize_numeric(h->Atv.val, h->mv_ia, h->mv_ib, h->Mv, s);
-    if (h->ata) ata_numeric(h, s);
+    if (h->ata || h->pg) ata_numeric(h, s);
   }
   const bool mixed = prm->precision == EMIN_PREC_MIXED;
   if (mixed) {
@@ -371,10 +409,29 @@ void run_setup(emin_pattern_t* h, const emin_system_t* sys, const emin_params_t*
   EminReportPtrs rpp{r->energy_p, r->rho_p, r->gamma_p, &r->its_p, &r->status};
   const double* Wv = sys->Wv ? sys->Wv : h->Wv_def;
   const double* Wp = sys->Wp ? sys->Wp : h->Wp_def;
-  run_emin(h->ev, energy_v(h), h->Mvf, h->vp.N.rowptr, h->vp.N.col, h->vp.cid, h->vp.clist, Wv, Pv,
-           prm->iters, energy, mixed, rv, s);
+  if (h->gmres) {
+    h->gv.reserve(prm->iters, h->vp.N.nnz, 0, h->ar);
+    run_emin_gmres(h->ev, energy_v(h), h->Mvf, h->vp.N.rowptr, h->vp.N.col, h->vp.cid,
+                   h->vp.clist, Wv, Pv, prm->iters, mixed, rv, h->gv, s);
+  } else {
+    run_emin(h->ev, energy_v(h), h->Mvf, h->vp.N.rowptr, h->vp.N.col, h->vp.cid, h->vp.clist, Wv,
+             Pv, prm->iters, energy, mixed, rv, s);
+  }
   run_emin(h->ep, h->Mp, h->Mpf, h->cp.N.rowptr, h->cp.N.col, h->cp.cid, h->cp.clist, Wp, Pp,
            prm->iters, energy, mixed, rpp, s);
+  if (Rvt) {
+    // the Petrov-Galerkin restriction: R_v^T on the velocity pattern
+    if (mixed) to_float(energy_r(h).val, h->Mrf, energy_r(h).nnz, s);
+    EminReportPtrs rr{r->energy_r, r->rho_r, r->gamma_r, &r->its_r, &r->status};
+    if (h->gmres) {
+      h->gr.reserve(prm->iters, h->vp.N.nnz, 0, h->ar);
+      run_emin_gmres(h->er, energy_r(h), h->Mrf, h->vp.N.rowptr, h->vp.N.col, h->vp.cid,
+                     h->vp.clist, Wv, Rvt, prm->iters, mixed, rr, h->gr, s);
+    } else {
+      run_emin(h->er, energy_r(h), h->Mrf, h->vp.N.rowptr, h->vp.N.col, h->vp.cid, h->vp.clist,
+               Wv, Rvt, prm->iters, energy, mixed, rr, s);
+    }
+  }
   HIP_OK(hipGetLastError());
 }
 
@@ -469,7 +526,7 @@ void run_setup_with_pattern(const emin_csr_t* Min, const int64_t* nrp, const int
   w.g = pick_lanes(M);
   w.smax = (int)max_row_len(nrp, n, s, ar);
   if (w.smax > 64) throw Error(EMIN_ERR_CAPACITY, "pattern row > 64");
-  w.make_bins(M, nrp, ncol, s, ar, false);
+  w.make_bins(M, nrp, ncol, s, ar, false, (flags & EMIN_FLAG_STAGED_PRODUCT) != 0);
   if (nc) HIP_OK(hipMemcpyAsync(w.Wc, Wc, sizeof(double) * nc, hipMemcpyDeviceToDevice, s));
   const bool mixed = precision == EMIN_PREC_MIXED;
   float* Mf = ar.alloc<float>(M.nnz);
@@ -482,6 +539,50 @@ void run_setup_with_pattern(const emin_csr_t* Min, const int64_t* nrp, const int
   HIP_OK(hipGetLastError());
   // the workspace is released on return: wait for the kernels that use it
   HIP_OK(hipStreamSynchronize(s));
+}
+
+// Petrov-Galerkin coarse blocks (FP64): Ac = Rvt^T Ahat Pv, Bc = Pp^T Bdiv
+// (I (x) Pv), Gct = Pp^T Gt (I (x) Rvt) on Bc's pattern (Gt: sys->Gt on Bdiv's
+// pattern, or Bdiv itself)
+void run_rap_pg(emin_pattern_t* h, const emin_system_t* sys, const double* Pv, const double* Pp,
+                const double* Rvt, double* Acv, double* Bcv, double* Gctv, hipStream_t s) {
+  check_same_structure(h, sys);
+  if (!h->pg) throw Error(EMIN_ERR_ARG, "pattern built without EMIN_FLAG_PETROV_GALERKIN");
+  if ((h->sizes.nnz_Pv && (!Pv || !Rvt)) || (h->sizes.nnz_Pp && !Pp) || (h->Ac.nnz && !Acv) ||
+      (h->Bc.nnz && (!Bcv || !Gctv)))
+    throw Error(EMIN_ERR_ARG, "NULL value array");
+  const CsrView A = in_view(sys->Ahat), B = in_view(sys->Bdiv);
+  CsrView PvV{h->vp.N.nrows, h->vp.N.ncols, h->vp.N.nnz, h->vp.N.rowptr, h->vp.N.col, Pv};
+  // Ac with R_v = Rvt^T: the transposed pattern carries Rvt's values
+  gather_values(Rvt, h->pvt_src, h->PvT.val, h->PvT.nnz, s);
+  spgemm_numeric(A, PvV, h->T, h->tplan, s);
+  Csr Ac = h->Ac;
+  Ac.val = Acv;
+  spgemm_numeric(view(h->PvT), view(h->T), Ac, h->acplan, s);
+  // Bc with P: the divergence block as in the Galerkin case
+  gather_values(Pv, h->x_src, h->X.val, h->X.nnz, s);
+  spgemm_numeric(B, view(h->X), h->U, h->uplan, s);
+  gather_values(Pp, h->ppt_src, h->PpT.val, h->PpT.nnz, s);
+  Csr Bc = h->Bc;
+  Bc.val = Bcv;
+  spgemm_numeric(view(h->PpT), view(h->U), Bc, h->bcplan, s);
+  // Gct: the same products with (Gt, Rvt) in place of (Bdiv, Pv)
+  if (!h->X2val) {
+    h->X2val = h->ar.alloc<double>(h->X.nnz);
+    h->U2val = h->ar.alloc<double>(h->U.nnz);
+  }
+  Csr X2 = h->X;
+  X2.val = h->X2val;
+  gather_values(Rvt, h->x_src, X2.val, X2.nnz, s);
+  CsrView G = B;
+  if (sys->Gt) G.val = sys->Gt;
+  Csr U2 = h->U;
+  U2.val = h->U2val;
+  spgemm_numeric(G, view(X2), U2, h->uplan, s);
+  Csr Gc = h->Bc;
+  Gc.val = Gctv;
+  spgemm_numeric(view(h->PpT), view(U2), Gc, h->bcplan, s);
+  HIP_OK(hipGetLastError());
 }
 
 template <class F>
@@ -627,6 +728,27 @@ emin_status emin_setup(emin_pattern_t* h, const emin_system_t* sys, const emin_p
                        double* Pv_vals, double* Pp_vals, void* stream, emin_report_t* report) {
   if (!h) return EMIN_ERR_ARG;
   return guarded([&] { run_setup(h, sys, prm, Pv_vals, Pp_vals, as_stream(stream), report); });
+}
+
+emin_status emin_setup_pg(emin_pattern_t* h, const emin_system_t* sys, const emin_params_t* prm,
+                          double* Pv_vals, double* Pp_vals, double* Rvt_vals, void* stream,
+                          emin_report_t* report) {
+  if (!h) return EMIN_ERR_ARG;
+  return guarded([&] {
+    if (!h->pg) throw Error(EMIN_ERR_ARG, "pattern built without EMIN_FLAG_PETROV_GALERKIN");
+    if (h->sizes.nnz_Pv && !Rvt_vals) throw Error(EMIN_ERR_ARG, "NULL Rvt");
+    run_setup(h, sys, prm, Pv_vals, Pp_vals, as_stream(stream), report,
+              Rvt_vals ? Rvt_vals : reinterpret_cast<double*>(h->ar.alloc<double>(1)));
+  });
+}
+
+emin_status emin_rap_pg(emin_pattern_t* h, const emin_system_t* sys, const double* Pv_vals,
+                        const double* Pp_vals, const double* Rvt_vals, double* Ac_vals,
+                        double* Bc_vals, double* Gct_vals, void* stream) {
+  if (!h) return EMIN_ERR_ARG;
+  return guarded([&] {
+    run_rap_pg(h, sys, Pv_vals, Pp_vals, Rvt_vals, Ac_vals, Bc_vals, Gct_vals, as_stream(stream));
+  });
 }
 
 emin_status emin_rap(emin_pattern_t* h, const emin_system_t* sys, const double* Pv_vals,

@@ -279,7 +279,7 @@ template <> struct Vec4<float> {
   }
 };
 
-template <int G, class TM, class TX, class TY>
+template <int G, int UB, class TM, class TX, class TY>
 __device__ __forceinline__ void spmm_map_rows(int64_t lb, const int32_t* rows, int64_t nrows,
                                               const int64_t* mrp, const TM* mval,
                                               const int32_t* kofs, const uint32_t* nib,
@@ -314,7 +314,7 @@ __device__ __forceinline__ void spmm_map_rows(int64_t lb, const int32_t* rows, i
   const double dv = (rowdot && lane < ni) ? D[na + lane] : 0.0;
   TA acc = TA(0);
   for (int c0 = 0; c0 < wl; c0 += CH) {
-    const int cw = ((wl - c0 < CH ? wl - c0 : CH) + 3) & ~3;   // uniform
+    const int cw = ((wl - c0 < CH ? wl - c0 : CH) + UB - 1) & ~(UB - 1);   // uniform
     for (int t = lane; t < cw; t += G) {
       const bool v = c0 + t < len;
       const int64_t e = ma + c0 + t;
@@ -328,26 +328,34 @@ __device__ __forceinline__ void spmm_map_rows(int64_t lb, const int32_t* rows, i
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int t = 0; t < cw; t += 4) {
-      const uint4 w4 = *reinterpret_cast<const uint4*>(gw + t);
-      const int4 k4 = *reinterpret_cast<const int4*>(gk + t);
-      Vec4<TM> m4;
-      m4.load(gm + t);
-      const uint32_t wv[4] = {w4.x, w4.y, w4.z, w4.w};
-      const int32_t kv[4] = {k4.x, k4.y, k4.z, k4.w};
-      TX x[4];
+    // UB entries per step: every gather of the step is issued before the
+    // first multiply-add, so a lane has UB loads in flight
+    for (int t = 0; t < cw; t += UB) {
+      TX x[UB];
 #pragma unroll
-      for (int u = 0; u < 4; u++) {
-        const uint32_t f = (wv[u] >> sh) & 0xFu;
-        const bool hit = f != 0xFu;
-        // 32-bit byte offset (a pattern of fewer than 2^29 entries): the load
-        // takes X as a scalar base plus one vector offset
-        const uint32_t off = (uint32_t)(hit ? kv[u] + lane + (int)f : 0) * (uint32_t)sizeof(TX);
-        const TX xl = *reinterpret_cast<const TX*>(reinterpret_cast<const char*>(X) + off);
-        x[u] = hit ? xl : TX(0);
+      for (int q = 0; q < UB; q += 4) {
+        const uint4 w4 = *reinterpret_cast<const uint4*>(gw + t + q);
+        const int4 k4 = *reinterpret_cast<const int4*>(gk + t + q);
+        const uint32_t wv[4] = {w4.x, w4.y, w4.z, w4.w};
+        const int32_t kv[4] = {k4.x, k4.y, k4.z, k4.w};
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          const uint32_t f = (wv[u] >> sh) & 0xFu;
+          const bool hit = f != 0xFu;
+          // 32-bit byte offset (a pattern of fewer than 2^29 entries): the
+          // load takes X as a scalar base plus one vector offset
+          const uint32_t off = (uint32_t)(hit ? kv[u] + lane + (int)f : 0) * (uint32_t)sizeof(TX);
+          const TX xl = *reinterpret_cast<const TX*>(reinterpret_cast<const char*>(X) + off);
+          x[q + u] = hit ? xl : TX(0);
+        }
       }
 #pragma unroll
-      for (int u = 0; u < 4; u++) acc = fma(m4.v[u], (TA)x[u], acc);
+      for (int q = 0; q < UB; q += 4) {
+        Vec4<TM> m4;
+        m4.load(gm + t + q);
+#pragma unroll
+        for (int u = 0; u < 4; u++) acc = fma(m4.v[u], (TA)x[q + u], acc);
+      }
     }
     // every lane is done with the window before the next pass refills it
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -402,11 +410,20 @@ __global__ __launch_bounds__(SPMM_BS) void k_spmm(SpmmSched S, const int64_t* mr
   const int32_t* rows = S.rows + S.row_off[ty];
   const int64_t nr = S.row_off[ty + 1] - S.row_off[ty];
   double* rd = D ? rowdot : nullptr;
+  if (S.unroll >= 16) {
+    switch (ty) {
+      case 0: spmm_map_rows<4, 16>(lb, rows, nr, mrp, mval, kofs, nib, nnzm, nrp, X, Y, D, rd, smem); return;
+      case 1: spmm_map_rows<8, 16>(lb, rows, nr, mrp, mval, kofs, nib, nnzm, nrp, X, Y, D, rd, smem); return;
+      case 2: spmm_map_rows<16, 16>(lb, rows, nr, mrp, mval, kofs, nib, nnzm, nrp, X, Y, D, rd, smem); return;
+      case 3: spmm_map_rows<32, 16>(lb, rows, nr, mrp, mval, kofs, nib, nnzm, nrp, X, Y, D, rd, smem); return;
+      default: break;
+    }
+  }
   switch (ty) {
-    case 0: spmm_map_rows<4>(lb, rows, nr, mrp, mval, kofs, nib, nnzm, nrp, X, Y, D, rd, smem); break;
-    case 1: spmm_map_rows<8>(lb, rows, nr, mrp, mval, kofs, nib, nnzm, nrp, X, Y, D, rd, smem); break;
-    case 2: spmm_map_rows<16>(lb, rows, nr, mrp, mval, kofs, nib, nnzm, nrp, X, Y, D, rd, smem); break;
-    case 3: spmm_map_rows<32>(lb, rows, nr, mrp, mval, kofs, nib, nnzm, nrp, X, Y, D, rd, smem); break;
+    case 0: spmm_map_rows<4, 4>(lb, rows, nr, mrp, mval, kofs, nib, nnzm, nrp, X, Y, D, rd, smem); break;
+    case 1: spmm_map_rows<8, 4>(lb, rows, nr, mrp, mval, kofs, nib, nnzm, nrp, X, Y, D, rd, smem); break;
+    case 2: spmm_map_rows<16, 4>(lb, rows, nr, mrp, mval, kofs, nib, nnzm, nrp, X, Y, D, rd, smem); break;
+    case 3: spmm_map_rows<32, 4>(lb, rows, nr, mrp, mval, kofs, nib, nnzm, nrp, X, Y, D, rd, smem); break;
     case 4: spmm_search_rows<4>(lb, rows, nr, mrp, mcol, mval, nrp, ncol, X, Y, D, rd); break;
     case 5: spmm_search_rows<8>(lb, rows, nr, mrp, mcol, mval, nrp, ncol, X, Y, D, rd); break;
     case 6: spmm_search_rows<16>(lb, rows, nr, mrp, mcol, mval, nrp, ncol, X, Y, D, rd); break;
@@ -619,13 +636,14 @@ __device__ __forceinline__ int spmm_class(int64_t len, bool map, int gshift) {
 
 // per block (256 rows) and class, the number of rows; class-major
 __global__ __launch_bounds__(256) void k_sched_count(const int64_t* nrp, const uint8_t* elig,
-                                                    int64_t n, int maps, int gshift,
-                                                    int64_t* bc, int64_t nb) {
+                                                    const uint8_t* skip, int64_t n, int maps,
+                                                    int gshift, int64_t* bc, int64_t nb) {
   __shared__ int cnt[SPMM_NT];
   if (threadIdx.x < SPMM_NT) cnt[threadIdx.x] = 0;
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int c = i < n ? spmm_class(nrp[i + 1] - nrp[i], maps && elig[i], gshift) : -1;
+  const int c = (i < n && !(skip && skip[i]))
+                    ? spmm_class(nrp[i + 1] - nrp[i], maps && elig[i], gshift) : -1;
   if (c >= 0) atomicAdd(&cnt[c], 1);
   __syncthreads();
   if (threadIdx.x < SPMM_NT) bc[(int64_t)threadIdx.x * nb + blockIdx.x] = cnt[threadIdx.x];
@@ -634,13 +652,14 @@ __global__ __launch_bounds__(256) void k_sched_count(const int64_t* nrp, const u
 // stable placement: class-major, ascending row index within a class
 // (inclusive scan of the class-major block counts gives each block's start)
 __global__ __launch_bounds__(256) void k_sched_place(const int64_t* nrp, const uint8_t* elig,
-                                                    int64_t n, int maps, int gshift,
-                                                    const int64_t* incl, int64_t nb,
+                                                    const uint8_t* skip, int64_t n, int maps,
+                                                    int gshift, const int64_t* incl, int64_t nb,
                                                     int32_t* rows) {
   __shared__ int wc[4][SPMM_NT];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int c = i < n ? spmm_class(nrp[i + 1] - nrp[i], maps && elig[i], gshift) : -1;
+  const int c = (i < n && !(skip && skip[i]))
+                    ? spmm_class(nrp[i + 1] - nrp[i], maps && elig[i], gshift) : -1;
   const uint64_t below = (1ull << lane) - 1ull;
   uint64_t mine = 0;
   for (int q = 0; q < SPMM_NT; q++) {
@@ -710,9 +729,11 @@ static void build_sched(const EminWork& w, const int64_t* nrp, const uint8_t* el
   if (n) {
     int64_t* bc = ar.alloc<int64_t>((size_t)SPMM_NT * nb);
     int64_t* dtot = ar.alloc<int64_t>(SPMM_NT);
-    k_sched_count<<<(unsigned)nb, 256, 0, s>>>(nrp, elig, n, o.maps, o.gshift, bc, nb);
+    // rows of staged blocks are the staged kernel's
+    const uint8_t* skip = (o.stage && w.stage.nblk) ? w.stage.row_staged : nullptr;
+    k_sched_count<<<(unsigned)nb, 256, 0, s>>>(nrp, elig, skip, n, o.maps, o.gshift, bc, nb);
     scan_inclusive(bc, SPMM_NT * nb, s, ar);
-    k_sched_place<<<(unsigned)nb, 256, 0, s>>>(nrp, elig, n, o.maps, o.gshift, bc, nb, rows);
+    k_sched_place<<<(unsigned)nb, 256, 0, s>>>(nrp, elig, skip, n, o.maps, o.gshift, bc, nb, rows);
     k_sched_totals<<<1, 64, 0, s>>>(bc, nb, dtot);
     HIP_OK(hipMemcpyAsync(tot, dtot, sizeof(tot), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
@@ -730,6 +751,7 @@ static void build_sched(const EminWork& w, const int64_t* nrp, const uint8_t* el
   S.blk_off[SPMM_NT] = blocks;
   S.rows = rows;
   S.xcd_split = o.xcd_split;
+  S.unroll = o.unroll;
   S.bmap = nullptr;
   if (o.xcd_split == XCD_MERGED && blocks) {
     if (blocks >= (int64_t(1) << 27)) throw Error(EMIN_ERR_CAPACITY, "masked product: too many blocks");
@@ -766,7 +788,7 @@ std::array<int64_t, 4> shape_key(const EminWork& w, const Csr& M) {
 }  // namespace
 
 void EminWork::make_bins(const Csr& M, const int64_t* nrp, const int32_t* ncol, hipStream_t s,
-                         Arena& ar, bool tune) {
+                         Arena& ar, bool tune, bool stage) {
   nnzm = M.nnz;
   if (n) HIP_OK(hipMemsetAsync(rowdot, 0, sizeof(double) * n, s));   // empty rows stay 0
   nplanes = smax <= 8 ? 1 : (smax <= 16 ? 2 : 4);
@@ -787,6 +809,9 @@ void EminWork::make_bins(const Csr& M, const int64_t* nrp, const int32_t* ncol, 
   }
   tuned = 0;
   opts = SchedOpts{};
+  opts.stage = stage;   // the LDS-staged product is chosen by the caller (off by default)
+  this->stage = StagePlan{};
+  if (n && stage) stage_plan(*this, M, nrp, elig, s, ar);
   if (!tune || n == 0) {
     build_sched(*this, nrp, elig, opts, sched, s, ar);
     return;
@@ -798,6 +823,7 @@ void EminWork::make_bins(const Csr& M, const int64_t* nrp, const int32_t* ncol, 
     if (it != g_tune.end()) {
       g_tune_stats[1]++;
       opts = it->second;
+      opts.stage = stage;
       tuned = 2;
       build_sched(*this, nrp, elig, opts, sched, s, ar);
       return;
@@ -812,8 +838,9 @@ void EminWork::make_bins(const Csr& M, const int64_t* nrp, const int32_t* ncol, 
   int ncand = 0;
   for (int maps = 1; maps >= 0; maps--)
     for (int gshift = 0; gshift <= 1; gshift++)
-      for (int xs = XCD_MERGED; xs >= XCD_CONTIGUOUS; xs--) {
-        const SchedOpts o{maps != 0, gshift, xs};
+      for (int xs = XCD_MERGED; xs >= XCD_CONTIGUOUS; xs--)
+        for (int un = 4; un <= (maps ? 16 : 4); un += 12) {
+        const SchedOpts o{maps != 0, gshift, xs, stage, un};
         SpmmSched S{};
         build_sched(*this, nrp, elig, o, S, s, ar);
         const SpmmSched keep = sched;
@@ -833,7 +860,8 @@ void EminWork::make_bins(const Csr& M, const int64_t* nrp, const int32_t* ncol, 
         // by 5 %: a product timed alone only roughly predicts one running
         // beside other work, as in batches
         const SchedOpts d{};
-        const bool is_def = o.maps == d.maps && o.gshift == d.gshift && o.xcd_split == d.xcd_split;
+        const bool is_def = o.maps == d.maps && o.gshift == d.gshift &&
+                            o.xcd_split == d.xcd_split && o.unroll == d.unroll;
         const float score = is_def ? t[1] : t[1] / 0.95f;
         if (score < best) {
           best = score;
@@ -855,7 +883,8 @@ void EminWork::make_bins(const Csr& M, const int64_t* nrp, const int32_t* ncol, 
 int32_t EminWork::sched_code() const {
   return (int32_t)((opts.maps ? 1 : 0) | (opts.gshift ? 2 : 0) |
                    (opts.xcd_split == XCD_BY_CLASS ? 4 : 0) |
-                   (opts.xcd_split == XCD_MERGED ? 8 : 0) | (tuned << 4));
+                   (opts.xcd_split == XCD_MERGED ? 8 : 0) | (tuned << 4) |
+                   ((opts.stage && stage.nblk) ? 64 : 0) | (opts.unroll >= 16 ? 128 : 0));
 }
 
 void autotune_stats(int64_t* out) {
@@ -878,6 +907,15 @@ template <class TM, class TX, class TY>
 static void spmm_any(const EminWork& w, const Csr& M, const TM* mval, const int64_t* nrp,
                      const int32_t* ncol, const TX* X, TY* Y, const double* D, double bytes,
                      hipStream_t s) {
+  // rows of staged blocks (their share of the algorithmic bytes), then the rest
+  if (w.opts.stage && w.stage.nblk) {
+    const StagePlan& P = w.stage;
+    const double vb = (double)sizeof(TX);
+    const double sb = (4.0 + (double)sizeof(TM)) * (double)P.m_entries +
+                      (4.0 + 2.0 * vb) * (double)P.p_entries + 16.0 * (double)P.rows;
+    spmm_stage<TM, TX, TY>(w, M.rowptr, mval, nrp, X, Y, D, sb, s);
+    bytes -= sb;
+  }
   const int64_t nb = w.sched.blk_off[SPMM_NT];
   if (nb == 0) return;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -971,6 +1009,34 @@ void run_emin(EminWork& w, const Csr& M, const float* Mf, const int64_t* nrp, co
                                     nullptr, nullptr, nullptr, nullptr);
     k_zupd<<<nblocks(nnz, 256), 256, 0, s>>>(w.R, w.Z, mixed ? w.Zf : nullptr, nnz, w.sc);
   }
+}
+
+void gather_modes(const double* W, const int32_t* clist, int64_t nc, double* Wc, hipStream_t s) {
+  if (nc) k_gather_modes<<<nblocks(nc, 256), 256, 0, s>>>(W, clist, nc, Wc);
+}
+
+void emin_init(const int64_t* rp, const int32_t* col, int64_t n, const int32_t* cid,
+               const double* W, const double* Wc, double* G, double* P, int32_t* status,
+               hipStream_t s) {
+  if (n) k_emin_init<<<nblocks(n, RB), RB, 0, s>>>(rp, col, n, cid, W, Wc, G, P, status);
+}
+
+__global__ void k_to_double(const float* a, double* b, int64_t n) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) b[e] = (double)a[e];
+}
+
+void masked_product(const EminWork& w, const Csr& M, const float* Mf, const int64_t* nrp,
+                    const int32_t* ncol, const double* X, double* Y, bool mixed, hipStream_t s) {
+  if (!mixed) {
+    spmm_any<double, double, double>(w, M, M.val, nrp, ncol, X, Y, nullptr,
+                                     spmm_bytes(w, M, false), s);
+    return;
+  }
+  if (w.nnz) k_to_float<<<nblocks(w.nnz, 256), 256, 0, s>>>(X, w.Zf, w.nnz);
+  spmm_any<float, float, float>(w, M, Mf, nrp, ncol, w.Zf, w.Qf, nullptr, spmm_bytes(w, M, true),
+                                s);
+  if (w.nnz) k_to_double<<<nblocks(w.nnz, 256), 256, 0, s>>>(w.Qf, Y, w.nnz);
 }
 
 void default_modes(const uint8_t* dir, int64_t n, double* W, hipStream_t s) {

@@ -17,7 +17,8 @@ LIBPATH = os.path.join(HERE, "libemin.so")
 
 EMIN_PREC_F64, EMIN_PREC_MIXED = 0, 1
 (EMIN_FLAG_ENERGY, EMIN_FLAG_VALIDATE, EMIN_FLAG_AUTOTUNE, EMIN_FLAG_PATTERN_VALUES,
- EMIN_FLAG_ENERGY_ATA) = 1, 2, 4, 8, 16
+ EMIN_FLAG_ENERGY_ATA, EMIN_FLAG_STAGED_PRODUCT, EMIN_FLAG_GMRES,
+ EMIN_FLAG_PETROV_GALERKIN) = 1, 2, 4, 8, 16, 32, 64, 128
 MAX_ITERS = 32
 (VIEW_PV, VIEW_PP, VIEW_AC, VIEW_BC, VIEW_MV, VIEW_MP, VIEW_S, VIEW_ORDER, VIEW_CP, VIEW_CBAR,
  VIEW_CV, VIEW_XVC, VIEW_P2VC, VIEW_KEEPV, VIEW_KEEPP, VIEW_DIR) = range(16)
@@ -31,7 +32,9 @@ SYMBOLS = ["emin_pattern", "emin_pattern_info", "emin_pattern_view", "emin_setup
            "emin_hierarchy_build_batch", "emin_batch_create", "emin_batch_run",
            "emin_batch_destroy", "emin_server_create", "emin_server_submit", "emin_server_poll",
            "emin_server_wait", "emin_server_release", "emin_server_stats", "emin_server_destroy",
-           "emin_pattern_with_cpoints", "emin_setup_with_pattern", "emin_profile_launches"]
+           "emin_pattern_with_cpoints", "emin_setup_with_pattern", "emin_profile_launches",
+           "emin_setup_pg", "emin_rap_pg", "emin_galerkin", "emin_matrix_view",
+           "emin_matrix_destroy", "emin_infsup"]
 PROF_KINDS = ["spmm", "update", "spgemm", "alg3", "alg4", "vpattern", "r6", "r7"]
 EMIN_PROF_ONLY = 1 << 30
 
@@ -55,7 +58,7 @@ class c_csr(C.Structure):
 
 class c_system(C.Structure):
     _fields_ = [("dim", C.c_int32), ("Ahat", c_csr), ("Bdiv", c_csr), ("xv", C.c_void_p),
-                ("p2v", C.c_void_p), ("Wv", C.c_void_p), ("Wp", C.c_void_p)]
+                ("p2v", C.c_void_p), ("Wv", C.c_void_p), ("Wp", C.c_void_p), ("Gt", C.c_void_p)]
 
 
 class c_params(C.Structure):
@@ -78,7 +81,10 @@ class c_report(C.Structure):
                 ("reserved", C.c_int32),
                 ("energy_v", C.c_double * (MAX_ITERS + 1)), ("energy_p", C.c_double * (MAX_ITERS + 1)),
                 ("rho_v", C.c_double * (MAX_ITERS + 1)), ("rho_p", C.c_double * (MAX_ITERS + 1)),
-                ("gamma_v", C.c_double * MAX_ITERS), ("gamma_p", C.c_double * MAX_ITERS)]
+                ("gamma_v", C.c_double * MAX_ITERS), ("gamma_p", C.c_double * MAX_ITERS),
+                ("its_r", C.c_int32), ("reserved2", C.c_int32),
+                ("energy_r", C.c_double * (MAX_ITERS + 1)), ("rho_r", C.c_double * (MAX_ITERS + 1)),
+                ("gamma_r", C.c_double * MAX_ITERS)]
 
 
 class c_kstat(C.Structure):
@@ -121,6 +127,10 @@ def lib():
                                  C.c_void_p, C.c_void_p]
         L.emin_rap.argtypes = [C.c_void_p, P(c_system), C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_int32, C.c_void_p]
+        L.emin_setup_pg.argtypes = [C.c_void_p, P(c_system), P(c_params), C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_void_p]
+        L.emin_rap_pg.argtypes = [C.c_void_p, P(c_system), C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.emin_sync_report.argtypes = [C.c_void_p, C.c_void_p, P(c_report)]
         L.emin_memcpy_d2h.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
         L.emin_pattern_destroy.argtypes = [C.c_void_p]
@@ -159,6 +169,12 @@ def lib():
         L.emin_server_stats.argtypes = [C.c_void_p, P(C.c_int64), P(C.c_int32), P(C.c_int32)]
         L.emin_server_destroy.argtypes = [C.c_void_p]
         L.emin_server_destroy.restype = None
+        L.emin_galerkin.argtypes = [P(c_csr), P(c_csr), C.c_void_p, P(C.c_void_p)]
+        L.emin_matrix_view.argtypes = [C.c_void_p, P(c_csr)]
+        L.emin_matrix_destroy.argtypes = [C.c_void_p]
+        L.emin_matrix_destroy.restype = None
+        L.emin_infsup.argtypes = [P(c_csr), P(c_csr), P(c_csr), C.c_int32, C.c_int32, C.c_double,
+                                  P(C.c_double), P(C.c_int32), P(C.c_int32), C.c_void_p]
         L.emin_profile_enable.argtypes = [C.c_int]
         L.emin_autotune_stats.argtypes = [P(C.c_int64)]
         L.emin_profile_collect.argtypes = [P(c_kstat), C.c_int32]
@@ -173,11 +189,16 @@ def _check(st, where):
 
 
 def params(tau1_v=0.06, tau1_p=0.06, tau2_sq=1.5e-3, iters=5, mixed=False, energy=False,
-           validate=False, autotune=False, energy_ata=False) -> c_params:
+           validate=False, autotune=False, energy_ata=False, staged=False,
+           gmres=False, pg=False) -> c_params:
     """energy_ata: the velocity block's EMIN energy is the A^T A-norm of the
-    filtered operator (sec. 4.3, eq. (min_problem), non-symmetric operators)."""
+    filtered operator (sec. 4.3, eq. (min_problem), non-symmetric operators).
+    staged: the masked product stages Z rows in LDS per block of rows (instead
+    of gathering them row by row from device memory)."""
     flags = ((EMIN_FLAG_ENERGY if energy else 0) | (EMIN_FLAG_VALIDATE if validate else 0) |
-             (EMIN_FLAG_AUTOTUNE if autotune else 0) | (EMIN_FLAG_ENERGY_ATA if energy_ata else 0))
+             (EMIN_FLAG_AUTOTUNE if autotune else 0) | (EMIN_FLAG_ENERGY_ATA if energy_ata else 0) |
+             (EMIN_FLAG_STAGED_PRODUCT if staged else 0) | (EMIN_FLAG_GMRES if gmres else 0) |
+             (EMIN_FLAG_PETROV_GALERKIN if pg else 0))
     return c_params(tau1_v, tau1_p, tau2_sq, iters, EMIN_PREC_MIXED if mixed else EMIN_PREC_F64,
                     flags)
 
@@ -215,6 +236,7 @@ class DeviceSystem:
     xv: int
     p2v: int
     keep: list = field(default_factory=list)   # keeps tensors / handles alive
+    Gt: int = 0         # gradient block's transpose on B's pattern (0: B itself)
 
     @staticmethod
     def upload(sys, device="cuda") -> "DeviceSystem":
@@ -226,15 +248,18 @@ class DeviceSystem:
                       t(sys.Bdiv.val, torch.float64))
         xv = t(sys.xv.reshape(-1), torch.float64)
         p2v = t(sys.p2v, torch.int32)
+        gt = (sys.meta or {}).get("Gt") if hasattr(sys, "meta") else None
+        Gt = t(gt, torch.float64) if gt is not None else None
         return DeviceSystem(sys.dim, sys.n_v, sys.n_p,
                             (sys.Ahat.nnz, Ar.data_ptr(), Ac.data_ptr(), Av.data_ptr()),
                             (sys.Bdiv.nnz, Br.data_ptr(), Bc.data_ptr(), Bv.data_ptr()),
-                            xv.data_ptr(), p2v.data_ptr(), [Ar, Ac, Av, Br, Bc, Bv, xv, p2v])
+                            xv.data_ptr(), p2v.data_ptr(), [Ar, Ac, Av, Br, Bc, Bv, xv, p2v, Gt],
+                            Gt.data_ptr() if Gt is not None else 0)
 
     def c(self) -> c_system:
         A = c_csr(self.n_v, self.n_v, self.A[0], self.A[1], self.A[2], self.A[3])
         B = c_csr(self.n_p, self.dim * self.n_v, self.B[0], self.B[1], self.B[2], self.B[3])
-        return c_system(self.dim, A, B, self.xv, self.p2v, None, None)
+        return c_system(self.dim, A, B, self.xv, self.p2v, None, None, self.Gt or None)
 
 
 class Pattern:
@@ -287,14 +312,26 @@ class Pattern:
                               EMIN_PREC_MIXED if mixed else EMIN_PREC_F64, _stream(stream)),
                "emin_rap")
 
-    def coarse_system(self, Ac, Bc) -> DeviceSystem:
+    def setup_pg(self, prm: c_params, Pv, Pp, Rvt, report=None, stream=None):
+        """emin_setup_pg: P and the Petrov-Galerkin restriction's R_v^T."""
+        _check(lib().emin_setup_pg(self.h, C.byref(self._c), C.byref(prm), C.c_void_p(Pv),
+                                   C.c_void_p(Pp), C.c_void_p(Rvt), _stream(stream),
+                                   C.c_void_p(report) if report else None), "emin_setup_pg")
+
+    def rap_pg(self, Pv, Pp, Rvt, Ac, Bc, Gct, stream=None):
+        _check(lib().emin_rap_pg(self.h, C.byref(self._c), C.c_void_p(Pv), C.c_void_p(Pp),
+                                 C.c_void_p(Rvt), C.c_void_p(Ac), C.c_void_p(Bc), C.c_void_p(Gct),
+                                 _stream(stream)), "emin_rap_pg")
+
+    def coarse_system(self, Ac, Bc, Gct=None) -> DeviceSystem:
         a, b = self.view(VIEW_AC), self.view(VIEW_BC)
         x, p = self.view(VIEW_XVC), self.view(VIEW_P2VC)
         s = self.sizes
         return DeviceSystem(self.dsys.dim, s["n_vc"], s["n_pc"],
                             (a.nnz, a.rowptr, a.col, Ac.data_ptr()),
                             (b.nnz, b.rowptr, b.col, Bc.data_ptr()),
-                            x.data, p.data, [self, Ac, Bc])
+                            x.data, p.data, [self, Ac, Bc, Gct],
+                            Gct.data_ptr() if Gct is not None else 0)
 
     def close(self):
         if self.h:
@@ -341,8 +378,9 @@ def autotune_reset():
 
 def sched_name(code: int) -> str:
     """Readable form of a schedule code from the level sizes."""
-    parts = ["maps" if code & 1 else "search-only", "2x-lanes" if code & 2 else "tight-lanes",
-             "xcd-by-class" if code & 4 else ("xcd-merged" if code & 8 else "xcd-contiguous")]
+    parts = (["staged"] if code & 64 else []) + (["batch16"] if code & 128 else []) + [
+        "maps" if code & 1 else "search-only", "2x-lanes" if code & 2 else "tight-lanes",
+        "xcd-by-class" if code & 4 else ("xcd-merged" if code & 8 else "xcd-contiguous")]
     return "+".join(parts) + ["", " (tuned)", " (reused)", ""][(code >> 4) & 3]
 
 
@@ -625,3 +663,66 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# ----------------------------------------------------------------------------
+# inf-sup diagnostic (sec. 6.1)
+# ----------------------------------------------------------------------------
+class DeviceMatrix:
+    """A square or rectangular CSR in device memory: torch tensors
+    (rowptr int64, col int32, val float64) or a library-owned matrix."""
+
+    def __init__(self, nrows, ncols, nnz, rowptr, col, val, keep=None, handle=None):
+        self.nrows, self.ncols, self.nnz = int(nrows), int(ncols), int(nnz)
+        self.rowptr, self.col, self.val = rowptr, col, val
+        self.keep = keep
+        self.handle = handle
+
+    @staticmethod
+    def upload(m, device="cuda") -> "DeviceMatrix":
+        import torch
+        t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt)
+        r, c, v = t(m.rowptr, torch.int64), t(m.col, torch.int32), t(m.val, torch.float64)
+        return DeviceMatrix(m.nrows, m.ncols, len(m.col), r.data_ptr(), c.data_ptr(),
+                            v.data_ptr(), keep=(r, c, v))
+
+    def c(self) -> c_csr:
+        return c_csr(self.nrows, self.ncols, self.nnz, self.rowptr, self.col, self.val)
+
+    def host(self):
+        rp = d2h(self.rowptr, self.nrows + 1, np.int64)
+        return rp, d2h(self.col, self.nnz, np.int32), d2h(self.val, self.nnz, np.float64)
+
+    def close(self):
+        if self.handle:
+            _sync()
+            lib().emin_matrix_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def galerkin(M: DeviceMatrix, P: DeviceMatrix, stream=None) -> DeviceMatrix:
+    """emin_galerkin: P^T M P on the device."""
+    h = C.c_void_p()
+    mc, pc = M.c(), P.c()
+    _check(lib().emin_galerkin(C.byref(mc), C.byref(pc), _stream(stream), C.byref(h)),
+           "emin_galerkin")
+    v = c_csr()
+    _check(lib().emin_matrix_view(h, C.byref(v)), "emin_matrix_view")
+    return DeviceMatrix(v.nrows, v.ncols, v.nnz, v.rowptr, v.col, v.val, keep=(M, P), handle=h)
+
+
+def infsup(B: DeviceMatrix, Mv: DeviceMatrix, Mp: DeviceMatrix, dim: int, steps: int,
+           rel: float = 1e-8, stream=None):
+    """emin_infsup: (sigma_min, zero singular values, Lanczos steps taken)."""
+    sig, nz, st = C.c_double(), C.c_int32(), C.c_int32()
+    bc, vc, pc = B.c(), Mv.c(), Mp.c()
+    _check(lib().emin_infsup(C.byref(bc), C.byref(vc), C.byref(pc), dim, steps, rel,
+                             C.byref(sig), C.byref(nz), C.byref(st), _stream(stream)),
+           "emin_infsup")
+    return sig.value, nz.value, st.value

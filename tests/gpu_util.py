@@ -16,12 +16,13 @@ def say(*a):
 
 
 def gpu_level(sys_: System, tau1_v=0.06, tau1_p=0.06, tau2_sq=1.5e-3, iters=5, mixed=False,
-              energy=True, dsys=None, energy_ata=False, cpoints=None):
+              energy=True, dsys=None, energy_ata=False, cpoints=None, staged=False,
+              gmres=False, pg=False):
     import torch
     from paper_1607_02489_amd import emin as E
     d = dsys if dsys is not None else E.DeviceSystem.upload(sys_)
     prm = E.params(tau1_v, tau1_p, tau2_sq, iters, mixed=mixed, energy=energy,
-                   energy_ata=energy_ata)
+                   energy_ata=energy_ata, staged=staged, gmres=gmres, pg=pg)
     pat = E.Pattern(d, prm, cpoints=cpoints)
     s = pat.sizes
     f64 = dict(dtype=torch.float64, device="cuda")
@@ -30,11 +31,22 @@ def gpu_level(sys_: System, tau1_v=0.06, tau1_p=0.06, tau2_sq=1.5e-3, iters=5, m
     Ac = torch.empty(max(s["nnz_Ac"], 1), **f64)
     Bc = torch.empty(max(s["nnz_Bc"], 1), **f64)
     rep = E.new_report()
-    pat.setup(prm, Pv.data_ptr(), Pp.data_ptr(), rep.data_ptr())
-    pat.rap(Pv.data_ptr(), Pp.data_ptr(), Ac.data_ptr(), Bc.data_ptr(), mixed=mixed)
+    Rvt = Gct = None
+    if pg:
+        Rvt = torch.empty(max(s["nnz_Pv"], 1), **f64)
+        Gct = torch.empty(max(s["nnz_Bc"], 1), **f64)
+        pat.setup_pg(prm, Pv.data_ptr(), Pp.data_ptr(), Rvt.data_ptr(), rep.data_ptr())
+        pat.rap_pg(Pv.data_ptr(), Pp.data_ptr(), Rvt.data_ptr(), Ac.data_ptr(), Bc.data_ptr(),
+                   Gct.data_ptr())
+    else:
+        pat.setup(prm, Pv.data_ptr(), Pp.data_ptr(), rep.data_ptr())
+        pat.rap(Pv.data_ptr(), Pp.data_ptr(), Ac.data_ptr(), Bc.data_ptr(), mixed=mixed)
     torch.cuda.synchronize()
     r = E.sync_report(rep, raise_on_error=False)
     out = dict(sizes=s, status=r.status, its_v=r.its_v, its_p=r.its_p)
+    if pg:
+        out["its_r"] = r.its_r
+        out["rho_r"] = np.array(r.rho_r[:iters + 1])
     out["energy_v"] = np.array(r.energy_v[:iters + 1])
     out["energy_p"] = np.array(r.energy_p[:iters + 1])
     out["rho_v"] = np.array(r.rho_v[:iters + 1])
@@ -60,7 +72,10 @@ def gpu_level(sys_: System, tau1_v=0.06, tau1_p=0.06, tau2_sq=1.5e-3, iters=5, m
     out["keep_v"] = pat.array_host(E.VIEW_KEEPV, np.uint8).astype(bool)
     out["keep_p"] = pat.array_host(E.VIEW_KEEPP, np.uint8).astype(bool)
     out["dir"] = pat.array_host(E.VIEW_DIR, np.uint8).astype(bool)
-    out["_keep"] = (pat, Pv, Pp, Ac, Bc, d)
+    if pg:
+        out["Rvt"] = csr(E.VIEW_PV, Rvt.data_ptr())
+        out["Gct"] = csr(E.VIEW_BC, Gct.data_ptr())
+    out["_keep"] = (pat, Pv, Pp, Ac, Bc, d, Rvt, Gct)
     return out
 
 
@@ -131,4 +146,5 @@ def compare_level(g, L, iters=5, tol=1e-10, values_exact=True):
 
 def host_coarse(g, dim) -> System:
     """The GPU's coarse system as host arrays (input of the next level)."""
-    return System(dim, g["Ac"], g["Bc"], g["xv_c"], g["p2v_c"])
+    meta = {"Gt": g["Gct"].val} if "Gct" in g else {}
+    return System(dim, g["Ac"], g["Bc"], g["xv_c"], g["p2v_c"], meta=meta)

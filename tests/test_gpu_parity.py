@@ -8,7 +8,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_1607_02489_amd import synth
-from tests.gpu_util import compare_level, gpu_level, host_coarse, say
+from tests.gpu_util import compare_level, gpu_level, host_coarse, rowmax_err, same_pattern, say
 from tests.helpers import relfro
 
 pytestmark = pytest.mark.gpu
@@ -90,6 +90,75 @@ def test_level_parity_ata_energy(case):
     g = gpu_level(s, iters=5, energy_ata=True, **kw)
     compare_level(g, L)
     assert g["sizes"]["nnz_Mv"] == L.Mv.nnz
+
+
+STAGE_CASES = {
+    "oseen2d_40_jitter": CASES["oseen2d_40_jitter"],
+    "stokes3d_16": lambda: (synth.make_system(3, 16, jitter=0.05, seed=3),
+                            dict(tau1_v=0.038, tau1_p=0.04)),
+    "oseen3d_6": CASES["oseen3d_6"],
+}
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("case", list(STAGE_CASES))
+def test_staged_product_equals_gathering_product(case, mixed):
+    """The masked product with Z rows staged in LDS per block of rows and the
+    one that gathers every row from device memory compute the same sums in
+    the same order: P, the CG traces and RAP are bitwise equal, in FP64 and in
+    mixed precision, and the staged plan covers the rows."""
+    s, kw = STAGE_CASES[case]()
+    say(f"[gpu] staged vs gathering product {case} mixed={mixed}: dofs={s.dofs}")
+    from paper_1607_02489_amd import emin as E
+    d = E.DeviceSystem.upload(s)
+    a = gpu_level(s, iters=5, mixed=mixed, dsys=d, staged=True, **kw)
+    b = gpu_level(s, iters=5, mixed=mixed, dsys=d, **kw)
+    assert a["sizes"]["sched_v"] & 64 and not b["sizes"]["sched_v"] & 64
+    for k in ("Pv", "Pp", "Ac", "Bc"):
+        assert np.array_equal(a[k].val, b[k].val), k
+    for k in ("energy_v", "energy_p", "rho_v", "rho_p"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("case", ["oseen2d_16_uniform", "oseen2d_40_jitter", "oseen3d_6"])
+def test_level_parity_gmres(case):
+    """EMIN_FLAG_GMRES (sec. 4.3's constrained GMRES on the non-symmetric
+    filtered velocity block A~): the operator A~ is bit-exact, the patterns are
+    the A-norm level's, and P, the residual trace and RAP match the oracle's
+    GMRES level to 1e-10."""
+    s, kw = CASES[case]()
+    say(f"[gpu] level parity, GMRES form, {case}: dofs={s.dofs}")
+    L = O.level(s, iters=5, gmres=True, **kw)
+    g = gpu_level(s, iters=5, gmres=True, **kw)
+    compare_level(g, L)
+    assert g["its_v"] == L.its_v
+    assert relfro(g["rho_v"], L.rho_v) <= 1e-10
+
+
+@pytest.mark.parametrize("gmres", [False, True])
+@pytest.mark.parametrize("case", ["oseen2d_16_uniform", "oseen2d_40_jitter", "oseen3d_6"])
+def test_level_parity_petrov_galerkin(case, gmres):
+    """EMIN_FLAG_PETROV_GALERKIN (sec. 4.3, last paragraph): R_v^T from the
+    A A^T-norm minimisation (or GMRES on A~^T), and the coarse blocks
+    A_c = R_v A P_v, B_c, G_c^T = P_p^T B (I (x) R_v^T): R_v^T, its residual trace
+    and the three coarse blocks match the oracle to 1e-10; one level down the
+    coarse gradient block is the input and the level matches again."""
+    s, kw = CASES[case]()
+    say(f"[gpu] level parity, Petrov-Galerkin, gmres={gmres}, {case}: dofs={s.dofs}")
+    cur = s
+    for lev in range(2):
+        L = O.level(cur, iters=5, pg=True, gmres=gmres, **kw)
+        g = gpu_level(cur, iters=5, pg=True, gmres=gmres, **kw)
+        compare_level(g, L)
+        assert g["its_r"] == L.its_r
+        assert relfro(g["rho_r"], L.rho_r) <= 1e-10
+        assert same_pattern(g["Rvt"], L.Rvt) and same_pattern(g["Gct"], L.Gct)
+        assert relfro(g["Rvt"].val, L.Rvt.val) <= 1e-10
+        assert relfro(g["Gct"].val, L.Gct.val) <= 1e-10
+        assert rowmax_err(g["Gct"], L.Gct) <= 1e-10
+        cur = host_coarse(g, s.dim)
+        if cur.dofs < 200:
+            break
 
 
 def test_energy_norm_must_match_pattern():
