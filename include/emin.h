@@ -407,11 +407,16 @@ void emin_matrix_destroy(emin_matrix_t *m);
  * n_p x n_p).  `steps` Lanczos steps with full re-orthogonalisation on
  * B~ B~^T (at most n_p; n_p steps give its eigenvalues); singular values
  * below rel * sigma_max count as zero (nzero of them, e.g. the hydrostatic
- * pressure of an enclosed flow).  Synchronous; results in host memory.
- * Errors: ARG, SHAPE, PATTERN, VALUE. */
+ * pressure of an enclosed flow).  A null vector D_p^(1/2) 1 (B^T 1 = 0) is
+ * locked first and counted in nzero, so Lanczos runs on its complement.
+ * resid (optional) receives the Lanczos residual norm of sigma_min^2's Ritz
+ * vector: some eigenvalue of B~ B~^T lies within resid of sigma_min^2, and a
+ * resid small against the gap to the next Ritz value says sigma_min has
+ * converged (the smallest Ritz value approaches from above as steps grow).
+ * Synchronous; results in host memory.  Errors: ARG, SHAPE, PATTERN, VALUE. */
 emin_status emin_infsup(const emin_csr_t *B, const emin_csr_t *Mv, const emin_csr_t *Mp,
                         int32_t dim, int32_t steps, double rel, double *sigma_min,
-                        int32_t *nzero, int32_t *steps_done, void *stream);
+                        double *resid, int32_t *nzero, int32_t *steps_done, void *stream);
 
 /* Kernel-class profiling with HIP events recorded on the launch stream
  * around each instrumented kernel.  Disabled by default.  collect

@@ -410,3 +410,43 @@ def hierarchy(sys: System, nlevels: int, tau1_v: float = TAU1, tau1_p: float = T
         out.append(L)
         cur = L.coarse_system()
     return out, cur
+
+
+# ----------------------------------------------------------------------------
+# inf-sup diagnostic (sec. 6.1, Table 3)
+# ----------------------------------------------------------------------------
+def galerkin(M: CSR, P: CSR) -> CSR:
+    """P^T M P with the oracle's sparse product and transpose (the projection
+    of a mass matrix to the next level, sec. 6.1)."""
+    return spgemm(transpose(P), spgemm(M, P))
+
+
+def lumped_abs(M: CSR) -> np.ndarray:
+    """lump(|M|): the diagonal of row sums of |m_ij|, as a vector."""
+    rows = np.repeat(np.arange(M.nrows), np.diff(M.rowptr))
+    out = np.zeros(M.nrows)
+    np.add.at(out, rows, np.abs(M.val))
+    return out
+
+
+def infsup_singular_values(B: CSR, Mv: CSR, Mp: CSR, dim: int):
+    """sec. 6.1: every singular value of the mass-scaled divergence
+    B~ = lump(|M_p|)^(-1/2) B lump(|M_v|)^(-1/2), M_v acting on each velocity
+    component (I_d (x) M_v), by dense SVD (small problems), descending."""
+    dp = lumped_abs(Mp)
+    dv = np.tile(lumped_abs(Mv), dim)
+    Bd = np.zeros((B.nrows, B.ncols))
+    rows = np.repeat(np.arange(B.nrows), np.diff(B.rowptr))
+    Bd[rows, B.col] = B.val
+    Bt = Bd / np.sqrt(dp)[:, None] / np.sqrt(dv)[None, :]
+    return np.linalg.svd(Bt, compute_uv=False)
+
+
+def infsup_sigma_min(B: CSR, Mv: CSR, Mp: CSR, dim: int, rel: float = 1e-8):
+    """sec. 6.1: the smallest non-zero singular value of B~ (as in
+    infsup_singular_values); singular values below rel * sigma_max count as
+    zero.  Returns (sigma_min, number of zero singular values, sigma_max)."""
+    sv = infsup_singular_values(B, Mv, Mp, dim)
+    smax = float(sv.max()) if sv.size else 0.0
+    nz = sv[sv > rel * smax]
+    return (float(nz.min()) if nz.size else 0.0), int(sv.size - nz.size), smax

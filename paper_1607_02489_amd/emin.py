@@ -174,7 +174,8 @@ def lib():
         L.emin_matrix_destroy.argtypes = [C.c_void_p]
         L.emin_matrix_destroy.restype = None
         L.emin_infsup.argtypes = [P(c_csr), P(c_csr), P(c_csr), C.c_int32, C.c_int32, C.c_double,
-                                  P(C.c_double), P(C.c_int32), P(C.c_int32), C.c_void_p]
+                                  P(C.c_double), P(C.c_double), P(C.c_int32), P(C.c_int32),
+                                  C.c_void_p]
         L.emin_profile_enable.argtypes = [C.c_int]
         L.emin_autotune_stats.argtypes = [P(C.c_int64)]
         L.emin_profile_collect.argtypes = [P(c_kstat), C.c_int32]
@@ -718,11 +719,15 @@ def galerkin(M: DeviceMatrix, P: DeviceMatrix, stream=None) -> DeviceMatrix:
 
 
 def infsup(B: DeviceMatrix, Mv: DeviceMatrix, Mp: DeviceMatrix, dim: int, steps: int,
-           rel: float = 1e-8, stream=None):
-    """emin_infsup: (sigma_min, zero singular values, Lanczos steps taken)."""
-    sig, nz, st = C.c_double(), C.c_int32(), C.c_int32()
+           rel: float = 1e-8, stream=None, resid: bool = False):
+    """emin_infsup: (sigma_min, zero singular values, Lanczos steps taken),
+    and the Ritz residual of sigma_min^2 last when resid is set."""
+    sig, res, nz, st = C.c_double(), C.c_double(), C.c_int32(), C.c_int32()
     bc, vc, pc = B.c(), Mv.c(), Mp.c()
     _check(lib().emin_infsup(C.byref(bc), C.byref(vc), C.byref(pc), dim, steps, rel,
-                             C.byref(sig), C.byref(nz), C.byref(st), _stream(stream)),
+                             C.byref(sig), C.byref(res), C.byref(nz), C.byref(st),
+                             _stream(stream)),
            "emin_infsup")
+    if resid:
+        return sig.value, nz.value, st.value, res.value
     return sig.value, nz.value, st.value

@@ -207,7 +207,7 @@ def _velocity_coords(dim, n, V, pnodes_vertices):
 # ---------------------------------------------------------------------------
 # assembly
 # ---------------------------------------------------------------------------
-def _assemble(dim, n, V, nu, wind_fn, chunk=4096, split=False):
+def _assemble(dim, n, V, nu, wind_fn, chunk=4096, split=False, mass=False):
     nv1 = 2 * n + 1
     n_v = nv1 ** dim
     n_p = (n + 1) ** dim
@@ -224,6 +224,7 @@ def _assemble(dim, n, V, nu, wind_fn, chunk=4096, split=False):
     xv = np.zeros((n_v, dim))
     rowsA, colsA, valsA, valsK = [], [], [], []
     rowsB, colsB, valsB = [], [], []
+    valsMv, rowsMp, colsMp, valsMp = [], [], [], []
     for e0 in range(0, ne, chunk):
         e1 = min(ne, e0 + chunk)
         vn = vnodes[e0:e1]
@@ -256,6 +257,15 @@ def _assemble(dim, n, V, nu, wind_fn, chunk=4096, split=False):
         rowsA.append(np.repeat(vn, nbv, axis=1).reshape(-1))
         colsA.append(np.tile(vn, (1, nbv)).reshape(-1))
         valsA.append(Ke.reshape(-1))
+        if mass:
+            # element mass matrices: sum_q w_q |J| phi_i(q) phi_j(q) (Q2 velocity,
+            # scalar) and psi_k(q) psi_l(q) (Q1 pressure)
+            Vw = (Vq[None] * wdet[:, :, None]).transpose(0, 2, 1)      # [E,nbv,nq]
+            valsMv.append(np.matmul(Vw, np.broadcast_to(Vq[None], (E_,) + Vq.shape)).reshape(-1))
+            Pw_ = (Pq[None] * wdet[:, :, None]).transpose(0, 2, 1)     # [E,nbp,nq]
+            valsMp.append(np.matmul(Pw_, np.broadcast_to(Pq[None], (E_,) + Pq.shape)).reshape(-1))
+            rowsMp.append(np.repeat(pn, nbp, axis=1).reshape(-1))
+            colsMp.append(np.tile(pn, (1, nbp)).reshape(-1))
         if split:
             valsK.append((Kc if Kc is not None else np.zeros_like(Ke)).reshape(-1))
         # b_{c,k,i} = int psi_k dphi_i/dx_c  ->  (E, nbp, nq) @ (E, nq, nbv) per c
@@ -270,6 +280,14 @@ def _assemble(dim, n, V, nu, wind_fn, chunk=4096, split=False):
     B = sp.coo_matrix((np.concatenate(valsB), (np.concatenate(rowsB), np.concatenate(colsB))),
                       shape=(n_p, dim * n_v)).tocsr()
     A.sum_duplicates(); B.sum_duplicates()
+    if mass:
+        Mv = sp.coo_matrix((np.concatenate(valsMv), (np.concatenate(rowsA), np.concatenate(colsA))),
+                           shape=(n_v, n_v)).tocsr()
+        Mp = sp.coo_matrix((np.concatenate(valsMp), (np.concatenate(rowsMp),
+                                                      np.concatenate(colsMp))),
+                           shape=(n_p, n_p)).tocsr()
+        Mv.sum_duplicates(); Mp.sum_duplicates()
+        return A, B, xv, (Mv, Mp)
     if split:
         # same COO indices -> same CSR structure, convection values aligned
         K = sp.coo_matrix((np.concatenate(valsK), (np.concatenate(rowsA), np.concatenate(colsA))),
@@ -366,7 +384,7 @@ def _scaled(raw, dim, n):
 
 def make_system(dim: int, n: int, *, jitter: float = 0.0, seed: int = 0,
                 nu: float = 1.0, wind: str | None = None, wind_seed: int | None = None,
-                domain: str = "cavity") -> System:
+                domain: str = "cavity", mass: bool = False) -> System:
     """Assemble a Q2-Q1 Stokes (wind=None) or Oseen system on the unit
     square/cube with n elements per side.
 
@@ -399,7 +417,10 @@ def make_system(dim: int, n: int, *, jitter: float = 0.0, seed: int = 0,
             wind_fn = _scaled(raw, dim, n)
         else:
             raise ValueError(f"unknown wind {wind!r}")
-    A, B, xv = _assemble(dim, n, V, nu, wind_fn)
+    if mass:
+        A, B, xv, (Mv, Mp) = _assemble(dim, n, V, nu, wind_fn, mass=True)
+    else:
+        A, B, xv = _assemble(dim, n, V, nu, wind_fn)
     m = 2 * n + 1
     lat = _lattice_index(dim, m)
     if domain == "cavity":
@@ -417,11 +438,18 @@ def make_system(dim: int, n: int, *, jitter: float = 0.0, seed: int = 0,
         p2v = 2 * plat[:, 0] + m * (2 * plat[:, 1])
     else:
         p2v = 2 * plat[:, 0] + m * (2 * plat[:, 1]) + m * m * (2 * plat[:, 2])
+    meta = dict(n=n, jitter=jitter, seed=seed, nu=nu, wind=wind, wind_seed=wind_seed,
+                domain=domain, dirichlet=int(dmask.sum()))
+    if mass:
+        # the velocity mass matrix on the space without the Dirichlet nodes
+        # (eliminated like the velocity block: zero row and column, unit
+        # diagonal), the pressure mass matrix as assembled
+        keep = sp.diags((~dmask).astype(np.float64))
+        Mv = _prune(keep @ Mv @ keep + sp.diags(dmask.astype(np.float64)))
+        meta["Mv"] = CSR.from_scipy(Mv)
+        meta["Mp"] = CSR.from_scipy(_prune(Mp))
     return System(dim, CSR.from_scipy(A), CSR.from_scipy(B), np.ascontiguousarray(xv),
-                  p2v.astype(np.int32),
-                  meta=dict(n=n, jitter=jitter, seed=seed, nu=nu, wind=wind,
-                            wind_seed=wind_seed, domain=domain,
-                            dirichlet=int(dmask.sum())))
+                  p2v.astype(np.int32), meta=meta)
 
 
 def make_split_system(dim: int, n: int, *, jitter: float = 0.0, seed: int = 0,

@@ -757,3 +757,63 @@ def test_emin_ata_energy_operator_pattern_and_minimum(oracle_lib):
     Lk = O.level(s, iters=8, energy_ata=True)
     e = Lk.energy_v[: Lk.its_v + 1]
     assert len(e) > 2 and np.all(np.diff(e) <= 1e-13 * abs(e[0]))
+
+
+# --------------------------------------------------------------------------
+# inf-sup diagnostic (sec. 6.1, Table 3)
+# --------------------------------------------------------------------------
+def test_mass_matrices_of_the_generator():
+    """The generator's mass matrices integrate exactly: 1^T M_p 1 is the
+    domain's area, and 1^T M_v 1 the area minus the part the Dirichlet nodes
+    carried (those rows are the identity)."""
+    s = synth.make_system(2, 8, jitter=0.1, seed=2, mass=True)
+    Mp, Mv = dense(s.meta["Mp"]), dense(s.meta["Mv"])
+    assert abs(Mp.sum() - 1.0) <= 1e-13
+    assert np.allclose(Mp, Mp.T, atol=0) and np.all(np.linalg.eigvalsh(Mp) > 0)
+    d = s.meta["dirichlet"]
+    assert 0.0 < Mv.sum() - d < 1.0
+
+
+def test_infsup_sigma_min_properties(oracle_lib):
+    """sec. 6.1: sigma_min of the mass-scaled divergence B~.  For the
+    enclosed (all-Dirichlet) cavity B^T 1 = 0, so exactly one singular value is
+    zero (the hydrostatic pressure) and sigma_min is the next one; B~ scales
+    as 1/length, so the unit square gives twice the value of the paper's
+    (-1,1)^2 domain; and as the mesh is refined sigma_min rises towards pi
+    (the root of the first Neumann eigenvalue of the Laplacian on the unit
+    square, pi^2), the paper's 1.54-1.56 at 592,387 dofs on (-1,1)^2 being
+    just below pi/2."""
+    O = oracle_lib
+    prev = 0.0
+    for n in (4, 8, 16):
+        s = synth.make_system(2, n, mass=True)
+        sig, nzero, smax = O.infsup_sigma_min(s.Bdiv, s.meta["Mv"], s.meta["Mp"], 2)
+        assert nzero == 1
+        assert prev < sig < np.pi
+        prev = sig
+        # the same mesh scaled by 2: every entry of B~ halves
+        t = synth.make_system(2, n, mass=True)
+        t.Bdiv.val = t.Bdiv.val * 2.0          # B ~ h^(d-1), lumped masses ~ h^d
+        Mv2 = CSR(t.meta["Mv"].nrows, t.meta["Mv"].ncols, t.meta["Mv"].rowptr,
+                  t.meta["Mv"].col, t.meta["Mv"].val * 4.0)
+        Mp2 = CSR(t.meta["Mp"].nrows, t.meta["Mp"].ncols, t.meta["Mp"].rowptr,
+                  t.meta["Mp"].col, t.meta["Mp"].val * 4.0)
+        sig2, _, _ = O.infsup_sigma_min(t.Bdiv, Mv2, Mp2, 2)
+        assert abs(sig2 - sig / 2.0) <= 1e-12 * sig
+    assert prev > 0.85 * np.pi
+
+
+def test_infsup_coarse_mass_matrices(oracle_lib):
+    """The coarse mass matrices of sec. 6.1 are P^T M P with the level's own
+    transfers (dense check), and the coarse levels of a cavity hierarchy keep
+    exactly one zero singular value and a sigma_min of the same size."""
+    O = oracle_lib
+    s = synth.make_system(2, 16, mass=True)
+    L = O.level(s, iters=5)
+    Mv1 = O.galerkin(s.meta["Mv"], L.Pv)
+    Mp1 = O.galerkin(s.meta["Mp"], L.Pp)
+    assert relfro(dense(Mv1), dense(L.Pv).T @ dense(s.meta["Mv"]) @ dense(L.Pv)) <= 1e-14
+    assert relfro(dense(Mp1), dense(L.Pp).T @ dense(s.meta["Mp"]) @ dense(L.Pp)) <= 1e-14
+    s0, _, _ = O.infsup_sigma_min(s.Bdiv, s.meta["Mv"], s.meta["Mp"], 2)
+    s1, z1, _ = O.infsup_sigma_min(L.Bc, Mv1, Mp1, 2)
+    assert z1 == 1 and 0.3 * s0 < s1 < 3.0 * s0
