@@ -266,6 +266,24 @@ emin_status emin_setup_with_pattern(const emin_csr_t *M, const int64_t *N_rowptr
                                     int32_t iters, int32_t precision, uint32_t flags,
                                     double *P_vals, void *stream, emin_report_t *report);
 
+/* emin_setup_with_pattern for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * allocation): the same arguments, the same kernels and the same results,
+ * with the workspace taken from a fixed 64 MiB device array the library
+ * holds on every GPU it runs on (until the process ends) instead of
+ * allocated.  No hipMalloc, hipFree or allocating library call is made.
+ * Problems whose workspace bound exceeds 64 MiB (about 1e5 rows with 1e6
+ * pattern entries and 2e6 operator entries) are rejected with
+ * EMIN_ERR_CAPACITY before any work is queued; EMIN_FLAG_STAGED_PRODUCT is
+ * rejected with EMIN_ERR_ARG.  All calls on one GPU share the array: calls
+ * that overlap in time on one GPU (several host threads or streams) race, so
+ * the caller serialises them.  Synchronises the stream before returning. */
+emin_status emin_setup_with_pattern_noalloc(const emin_csr_t *M, const int64_t *N_rowptr,
+                                            const int32_t *N_col, int64_t ncoarse, int64_t nnz_N,
+                                            const int32_t *cid, const double *W, const double *Wc,
+                                            int32_t iters, int32_t precision, uint32_t flags,
+                                            double *P_vals, void *stream, emin_report_t *report);
+
 /* Alg. 1 Galerkin product with R = P^T on the unfiltered operator:
  * Ac = Pv^T Ahat Pv (nnz_Ac values) and Bc = Pp^T Bdiv (I_d (x) Pv)
  * (nnz_Bc values), written into caller buffers on the handle's coarse

@@ -1,6 +1,7 @@
 // C ABI: one level of Alg. 1 as emin_pattern / emin_setup / emin_rap.
 #include <cstring>
 #include <memory>
+#include <mutex>
 
 #include "coarsen.h"
 #include "emin_cg.h"
@@ -491,7 +492,8 @@ void run_rap(emin_pattern_t* h, const emin_system_t* sys, const double* Pv, cons
 void run_setup_with_pattern(const emin_csr_t* Min, const int64_t* nrp, const int32_t* ncol,
                             int64_t nc, int64_t nnz, const int32_t* cid, const double* W,
                             const double* Wc, int32_t iters, int32_t precision, uint32_t flags,
-                            double* P, hipStream_t s, emin_report_t* rep) {
+                            double* P, hipStream_t s, emin_report_t* rep,
+                            Arena* ext = nullptr) {
   if (!Min) throw Error(EMIN_ERR_ARG, "NULL operator");
   const int64_t n = Min->nrows;
   if (n < 0 || nc < 0 || nnz < 0 || Min->nnz < 0) throw Error(EMIN_ERR_ARG, "negative size");
@@ -503,7 +505,8 @@ void run_setup_with_pattern(const emin_csr_t* Min, const int64_t* nrp, const int
             (nnz && (!ncol || !P)) || (nc && !Wc)))
     throw Error(EMIN_ERR_ARG, "NULL array");
   if (Min->nnz >= INT32_MAX || nnz >= INT32_MAX) throw Error(EMIN_ERR_CAPACITY, "nnz >= 2^31");
-  Arena ar;
+  Arena own;
+  Arena& ar = ext ? *ext : own;
   int* derr = ar.alloc<int>(1);
   HIP_OK(hipMemsetAsync(derr, 0, sizeof(int), s));
   const CsrView Mv = in_view(*Min);
@@ -602,6 +605,48 @@ emin_status guarded(F&& f) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// The allocation-free variant of emin_setup_with_pattern: its workspace is a
+// fixed device array of this file, one copy per GPU, reached through the
+// address hipGetSymbolAddress returns for the current device (host code never
+// passes the array's name to a kernel).
+// ---------------------------------------------------------------------------
+static constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static void* scratch_ptr() {
+  static std::mutex mu;
+  static void* ptr[64] = {};
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) throw Error(EMIN_ERR_DEVICE, "device index");
+  std::lock_guard<std::mutex> g(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    ptr[dev] = p;
+  }
+  return ptr[dev];
+}
+
+// an upper bound of the workspace emin_setup_with_pattern takes (every
+// array rounded up to 256 bytes, as the bump allocator does)
+static size_t setup_with_pattern_bytes(int64_t n, int64_t nc, int64_t nnz, int64_t nnzm,
+                                       int64_t smax) {
+  auto r = [](double b) { return (size_t)((b + 255.0) / 256.0) * 256; };
+  const int np = smax <= 8 ? 1 : (smax <= 16 ? 2 : 4);
+  const double nb = (double)((n + 255) / 256);
+  size_t b = 0;
+  b += r(4) * 8;                                        // flags, scalars, small maxima
+  b += r(8.0 * n) * 4 + r(8.0 * nc);                    // G, Wdef, rowdot, sched rows (+Wc)
+  b += r(8.0 * nnz) * 4 + r(4.0 * nnz) * 2;             // R, Z, Q, MP; FP32 Z, Q
+  b += r(8.0 * (2.0 * ((n + 3) / 4) + 16 + 8 * 9)) * 2; // block partials
+  b += r(4.0 * nnzm) * (2 + np) + r((double)n);         // maps, FP32 M, eligibility
+  b += r(8.0 * 9 * nb) * 2 + r(4.0 * ((n + 7) / 8 * 8 + 64));   // schedule counts, block map
+  b += r(sizeof(emin_report_t)) + r(8.0 * 64) * 8;      // report, scan partials
+  return b + (size_t(1) << 20);                         // slack for small arrays
+}
+
 extern "C" {
 
 emin_status emin_pattern(const emin_system_t* sys, const emin_params_t* prm, void* stream,
@@ -651,6 +696,33 @@ emin_status emin_pattern_with_cpoints(const emin_system_t* sys, const emin_param
   set_last_error("");
   *out = h;
   return EMIN_OK;
+}
+
+emin_status emin_setup_with_pattern_noalloc(const emin_csr_t* M, const int64_t* N_rowptr,
+                                            const int32_t* N_col, int64_t ncoarse, int64_t nnz_N,
+                                            const int32_t* cid, const double* W, const double* Wc,
+                                            int32_t iters, int32_t precision, uint32_t flags,
+                                            double* P_vals, void* stream, emin_report_t* report) {
+  return guarded([&] {
+    if (!M) throw Error(EMIN_ERR_ARG, "NULL operator");
+    if (M->nrows < 0 || M->nnz < 0 || ncoarse < 0 || nnz_N < 0)
+      throw Error(EMIN_ERR_ARG, "negative size");
+    if (flags & EMIN_FLAG_STAGED_PRODUCT)
+      throw Error(EMIN_ERR_ARG, "the staged product is not available without allocation");
+    // the pattern's longest row is not known before it is read; the bound
+    // takes the largest map (4 planes)
+    const size_t need = setup_with_pattern_bytes(M->nrows, ncoarse, nnz_N, M->nnz, 64);
+    if (need > kScratchBytes)
+      throw Error(EMIN_ERR_CAPACITY, "problem larger than the 64 MiB scratch buffer");
+    Arena ar(scratch_ptr(), kScratchBytes);
+    try {
+      run_setup_with_pattern(M, N_rowptr, N_col, ncoarse, nnz_N, cid, W, Wc, iters, precision,
+                             flags, P_vals, as_stream(stream), report, &ar);
+    } catch (...) {
+      (void)hipStreamSynchronize(as_stream(stream));
+      throw;
+    }
+  });
 }
 
 emin_status emin_setup_with_pattern(const emin_csr_t* M, const int64_t* N_rowptr,

@@ -53,6 +53,10 @@ void allow_lds(const void* f);
 class Arena {
  public:
   Arena() = default;
+  // a fixed buffer instead of chunks: allocation only bumps within
+  // [base, base + cap) and throws EMIN_ERR_CAPACITY beyond it (no device
+  // allocation ever happens)
+  Arena(void* base, size_t cap) : fixed_(true), cur_(static_cast<char*>(base)), left_(cap) {}
   Arena(const Arena&) = delete;
   Arena& operator=(const Arena&) = delete;
   ~Arena() { release(); }
@@ -61,6 +65,7 @@ class Arena {
   T* alloc(size_t n) {
     size_t b = (n ? n : 1) * sizeof(T);
     b = (b + 255) & ~size_t(255);
+    if (b > left_ && fixed_) throw Error(EMIN_ERR_CAPACITY, "scratch buffer capacity exceeded");
     if (b > left_) {
       const size_t chunk = b > kChunk ? b : kChunk;
       void* p = chunk_get(chunk);
@@ -77,6 +82,7 @@ class Arena {
   }
   // the caller guarantees that no queued work still uses the memory
   void release() {
+    if (fixed_) return;
     for (auto& c : chunks_) chunk_put(c.first, c.second);
     chunks_.clear();
     bytes_ = 0;
@@ -87,6 +93,7 @@ class Arena {
 
  private:
   static constexpr size_t kChunk = size_t(64) << 20;
+  bool fixed_ = false;
   std::vector<std::pair<void*, size_t>> chunks_;
   size_t bytes_ = 0;
   char* cur_ = nullptr;

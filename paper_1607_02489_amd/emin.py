@@ -121,6 +121,7 @@ def lib():
                                               C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                               C.c_int32, C.c_int32, C.c_uint32, C.c_void_p,
                                               C.c_void_p, C.c_void_p]
+        L.emin_setup_with_pattern_noalloc.argtypes = L.emin_setup_with_pattern.argtypes
         L.emin_pattern_info.argtypes = [C.c_void_p, P(c_sizes)]
         L.emin_pattern_view.argtypes = [C.c_void_p, C.c_int32, P(c_view)]
         L.emin_setup.argtypes = [C.c_void_p, P(c_system), P(c_params), C.c_void_p, C.c_void_p,
@@ -348,21 +349,24 @@ class Pattern:
 
 
 def setup_with_pattern(M_dev, N_dev, ncoarse, cid, W, Wc, iters, P, mixed=False, energy=False,
-                       validate=False, report=None, stream=None):
-    """emin_setup_with_pattern.  M_dev = (n, nnz, rowptr, col, val) and
-    N_dev = (nnz, rowptr, col) device tensors; cid, W, Wc, P device tensors."""
+                       validate=False, report=None, stream=None, noalloc=False):
+    """emin_setup_with_pattern (emin_setup_with_pattern_noalloc with
+    noalloc).  M_dev = (n, nnz, rowptr, col, val) and N_dev = (nnz, rowptr,
+    col) device tensors; cid, W, Wc, P device tensors."""
     n, mnnz, mrp, mcol, mval = M_dev
     nnnz, nrp, ncol = N_dev
     Mc = c_csr(n, n, mnnz, mrp.data_ptr(), mcol.data_ptr(), mval.data_ptr())
     flags = (EMIN_FLAG_ENERGY if energy else 0) | (EMIN_FLAG_VALIDATE if validate else 0)
-    _check(lib().emin_setup_with_pattern(C.byref(Mc), C.c_void_p(nrp.data_ptr()),
+    fn = lib().emin_setup_with_pattern_noalloc if noalloc else lib().emin_setup_with_pattern
+    _check(fn(C.byref(Mc), C.c_void_p(nrp.data_ptr()),
                                          C.c_void_p(ncol.data_ptr()), int(ncoarse), int(nnnz),
                                          C.c_void_p(cid.data_ptr()), C.c_void_p(W.data_ptr()),
                                          C.c_void_p(Wc.data_ptr()), iters,
                                          EMIN_PREC_MIXED if mixed else EMIN_PREC_F64, flags,
                                          C.c_void_p(P.data_ptr()), _stream(stream),
                                          C.c_void_p(report.data_ptr()) if report is not None
-                                         else None), "emin_setup_with_pattern")
+                                         else None),
+           "emin_setup_with_pattern_noalloc" if noalloc else "emin_setup_with_pattern")
 
 
 def autotune_stats() -> dict:
