@@ -491,6 +491,8 @@ def main():
     ap.add_argument("--oracle-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--out", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tiled", action="store_true",
+                    help="masked product on coordinate tiles with Z rows staged in LDS")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--serve-slots", type=int, default=8)
@@ -622,8 +624,10 @@ def run_standard(args, E, synth, torch):
     log(f"[bench] generated {args.workload}: dofs={system.dofs} in {time.perf_counter() - t0:.1f}s")
     torch.cuda.init()
     stream = torch.cuda.current_stream()
-    prm64 = E.params(wl["tau1_v"], wl["tau1_p"], 1.5e-3, wl["iters"], mixed=False, energy_ata=ata)
-    prmx = E.params(wl["tau1_v"], wl["tau1_p"], 1.5e-3, wl["iters"], mixed=True, energy_ata=ata)
+    prm64 = E.params(wl["tau1_v"], wl["tau1_p"], 1.5e-3, wl["iters"], mixed=False, energy_ata=ata,
+                     staged=args.tiled)
+    prmx = E.params(wl["tau1_v"], wl["tau1_p"], 1.5e-3, wl["iters"], mixed=True, energy_ata=ata,
+                    staged=args.tiled)
     H64 = E.Hierarchy(system, wl["nlevels"], prm64, min_dofs=wl["min_dofs"])
     torch.cuda.synchronize()
     prof = not args.no_profile

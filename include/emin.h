@@ -78,11 +78,14 @@ enum {
                                     emin_setup must pass the same flag (EMIN_ERR_ARG
                                     otherwise).  EMIN_VIEW_MV is then A~^T A~. */
   EMIN_FLAG_STAGED_PRODUCT = 32u, /* emin_pattern / emin_setup_with_pattern: the masked
-                                    product stages, per block of 16 rows that fits LDS,
-                                    the Z rows those rows reach (coalesced runs) and
-                                    sums from LDS, instead of gathering Z from device
-                                    memory row by row (the same sums in the same order,
-                                    so the same bits) */
+                                    product groups rows into tiles by the cells of a
+                                    grid over their coordinates (emin_pattern; blocks
+                                    of consecutive rows in emin_setup_with_pattern),
+                                    stages each tile's Z rows in LDS (coalesced runs)
+                                    and sums from LDS, instead of gathering Z from
+                                    device memory row by row; rows of tiles that do not
+                                    fit keep the gathering kernel (the same sums in the
+                                    same order, so the same bits) */
   EMIN_FLAG_GMRES = 64u,         /* sec. 4.3 names a constrained CG or GMRES: the velocity
                                     block's EMIN runs `iters` steps of GMRES on the
                                     projected masked system Pi mask_N(A~ P) = 0 of the

@@ -292,13 +292,17 @@ void build_pattern(emin_pattern_t* h, const emin_system_t* sys, const emin_param
   if (h->ev.smax > 64 || h->ep.smax > 64) throw Error(EMIN_ERR_CAPACITY, "pattern row > 64");
   const bool tune = (prm->flags & EMIN_FLAG_AUTOTUNE) != 0;
   const bool stage = (prm->flags & EMIN_FLAG_STAGED_PRODUCT) != 0;
-  h->ev.make_bins(energy_v(h), h->vp.N.rowptr, h->vp.N.col, s, ar, tune, stage);
-  h->ep.make_bins(h->Mp, h->cp.N.rowptr, h->cp.N.col, s, ar, tune, stage);
+  // (tiles of the velocity rows by their coordinates, of the pressure rows by
+  // their co-located velocity nodes')
+  h->ev.make_bins(energy_v(h), h->vp.N.rowptr, h->vp.N.col, s, ar, tune, stage, sys->xv, nullptr,
+                  dim);
+  h->ep.make_bins(h->Mp, h->cp.N.rowptr, h->cp.N.col, s, ar, tune, stage, sys->xv, sys->p2v, dim);
   if (h->pg) {
     h->er.allocate(nv, h->vp.N.nnz, h->vp.n_c, ar, mixed);
     h->er.g = pick_lanes(energy_r(h));
     h->er.smax = h->ev.smax;
-    h->er.make_bins(energy_r(h), h->vp.N.rowptr, h->vp.N.col, s, ar, tune, stage);
+    h->er.make_bins(energy_r(h), h->vp.N.rowptr, h->vp.N.col, s, ar, tune, stage, sys->xv,
+                    nullptr, dim);
     h->Mrf = ar.alloc<float>(energy_r(h).nnz);
   }
   h->Mvf = ar.alloc<float>(energy_v(h).nnz);

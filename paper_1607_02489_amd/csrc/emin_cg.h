@@ -45,39 +45,45 @@ struct SchedOpts {
   bool maps = true;      // rows that fit the intersection maps use them
   int gshift = 0;        // lanes per row: the tight power of two, times 2^gshift
   int xcd_split = XCD_MERGED;   // XCD_*
-  bool stage = false;    // blocks of rows whose Z rows fit in LDS use the staged kernel
+  bool stage = false;    // rows of tiles whose Z rows fit in LDS use the tiled kernel
   int unroll = 4;        // map rows: gathers in flight per lane (4 or 16)
 };
 
-// sizes of the LDS-staged masked product: sr rows per block, at most emax M
-// entries, vcap staged Z values and rcap runs of consecutive Z rows; np map
-// planes
-struct StageDims {
-  int32_t sr = 16, emax = 640, rcap = 64, vcap = 3072, np = 1;
+// sizes of the tiled masked product: rows are grouped by the cells of a
+// grid over their coordinates (about tgt rows per cell); a cell of at most
+// tmax rows is staged when its union of Z rows spans a k window of at most
+// wbits, holds at most vcap values and forms at most rcap runs
+struct TileDims {
+  int32_t tgt = 64, tmax = 256, vcap = 4096, rcap = 128, wbits = 131072;
 };
 
-// plan of the staged product (built once per pattern): the staged blocks of
-// sr rows, per block its runs of Z rows (start in Z, start in LDS, length) and
-// per M entry the LDS position its intersection map is relative to
+// waves of a tile workgroup
+constexpr int TILE_WAVES = 4;
+
+// plan of the tiled product (built once per pattern): per staged tile its
+// record (first row in srows, rows per slots class (<= 8, <= 16, <= 32),
+// first run, runs, staged values, cell), the staged rows tile by tile, the
+// runs of consecutive Z rows (start in Z, start in LDS, length) and per M
+// entry of a staged row the LDS position its intersection map is relative to
 struct StagePlan {
-  StageDims dims;
-  int64_t nblk = 0;                 // staged blocks
-  const int32_t* blocks = nullptr;  // their indices (block b: rows [b sr, b sr + sr))
-  const int64_t* roff = nullptr;    // per block of the matrix: its first run (nb + 1)
+  TileDims dims;
+  int64_t ntile = 0;
+  const int32_t* tinfo = nullptr;
+  const int32_t* srows = nullptr;
   const int32_t *rg = nullptr, *rl = nullptr, *rn = nullptr;
-  const int32_t* lofs = nullptr;    // per M entry of a staged row
+  const int32_t* lofs = nullptr;
   const uint8_t* row_staged = nullptr;
-  int64_t rows = 0, m_entries = 0, p_entries = 0;   // covered by staged blocks
+  int32_t vmax = 0;                                // largest tile's staged values
+  int64_t rows = 0, m_entries = 0, p_entries = 0;  // covered by staged tiles
 };
 
-// kernel arguments of the staged product
+// kernel arguments of the tiled product
 struct StageArgs {
-  StageDims dims;
-  const int32_t* blocks;
-  const int64_t* roff;
+  const int32_t* tinfo;
+  const int32_t* srows;
   const int32_t *rg, *rl, *rn;
   const int32_t* lofs;
-  int64_t n;
+  int32_t zbytes;   // LDS bytes of the staged Z values (16-byte aligned)
 };
 
 struct EminWork {
@@ -104,20 +110,25 @@ struct EminWork {
   int tuned = 0;   // 0: default schedule, 1: timed here, 2: reused from the tuning table
   SchedOpts opts;
   StagePlan stage;
-  // stage: blocks whose Z rows fit in LDS use the staged kernel
+  // stage: rows in tiles whose Z rows fit in LDS use the tiled kernel; the
+  // tiles come from the rows' coordinates (row i at xyz[(xmap ? xmap[i] :
+  // i) * dim ...]), or from blocks of consecutive rows without them
   void make_bins(const Csr& M, const int64_t* nrp, const int32_t* ncol, hipStream_t s, Arena& ar,
-                 bool tune, bool stage = false);
+                 bool tune, bool stage = false, const double* xyz = nullptr,
+                 const int32_t* xmap = nullptr, int dim = 0);
   int32_t sched_code() const;   // bit 0 maps, bit 1 doubled lanes, bit 2 XCD split, bits 4-5
-                                // tuned, bit 6 staged blocks, bit 7 4-entry gather batches
+                                // tuned, bit 6 tiled rows, bit 7 16-entry gather batches
 };
 
-// the staged product's plan (rows in blocks that fit LDS), and the product on
-// those blocks (spmm_stage.hip)
-void stage_plan(EminWork& w, const Csr& M, const int64_t* nrp, const uint8_t* elig, hipStream_t s,
-                Arena& ar);
+// the tiled product's plan, and the product on the staged tiles
+// (spmm_stage.hip); e0 / e1, when given, are recorded at the launch's start
+// and end
+void stage_plan(EminWork& w, const Csr& M, const int64_t* nrp, const uint8_t* elig,
+                const double* xyz, const int32_t* xmap, int dim, hipStream_t s, Arena& ar);
 template <class TM, class TX, class TY>
 void spmm_stage(const EminWork& w, const int64_t* mrp, const TM* mval, const int64_t* nrp,
-                const TX* X, TY* Y, const double* Dv, double bytes, hipStream_t s);
+                const TX* X, TY* Y, const double* Dv, hipStream_t s, hipEvent_t e0,
+                hipEvent_t e1);
 
 // Y = mask_N(M X).  With D, also <D, Y>: *dots receives the array of values
 // whose in-order sum is that scalar and the return value is their count.

@@ -730,7 +730,7 @@ static void build_sched(const EminWork& w, const int64_t* nrp, const uint8_t* el
     int64_t* bc = ar.alloc<int64_t>((size_t)SPMM_NT * nb);
     int64_t* dtot = ar.alloc<int64_t>(SPMM_NT);
     // rows of staged blocks are the staged kernel's
-    const uint8_t* skip = (o.stage && w.stage.nblk) ? w.stage.row_staged : nullptr;
+    const uint8_t* skip = (o.stage && w.stage.ntile) ? w.stage.row_staged : nullptr;
     k_sched_count<<<(unsigned)nb, 256, 0, s>>>(nrp, elig, skip, n, o.maps, o.gshift, bc, nb);
     scan_inclusive(bc, SPMM_NT * nb, s, ar);
     k_sched_place<<<(unsigned)nb, 256, 0, s>>>(nrp, elig, skip, n, o.maps, o.gshift, bc, nb, rows);
@@ -788,7 +788,8 @@ std::array<int64_t, 4> shape_key(const EminWork& w, const Csr& M) {
 }  // namespace
 
 void EminWork::make_bins(const Csr& M, const int64_t* nrp, const int32_t* ncol, hipStream_t s,
-                         Arena& ar, bool tune, bool stage) {
+                         Arena& ar, bool tune, bool stage, const double* xyz,
+                         const int32_t* xmap, int dim) {
   nnzm = M.nnz;
   if (n) HIP_OK(hipMemsetAsync(rowdot, 0, sizeof(double) * n, s));   // empty rows stay 0
   nplanes = smax <= 8 ? 1 : (smax <= 16 ? 2 : 4);
@@ -809,9 +810,9 @@ void EminWork::make_bins(const Csr& M, const int64_t* nrp, const int32_t* ncol, 
   }
   tuned = 0;
   opts = SchedOpts{};
-  opts.stage = stage;   // the LDS-staged product is chosen by the caller (off by default)
+  opts.stage = stage;   // the tiled product is chosen by the caller
   this->stage = StagePlan{};
-  if (n && stage) stage_plan(*this, M, nrp, elig, s, ar);
+  if (n && stage) stage_plan(*this, M, nrp, elig, xyz, xmap, dim, s, ar);
   if (!tune || n == 0) {
     build_sched(*this, nrp, elig, opts, sched, s, ar);
     return;
@@ -884,7 +885,7 @@ int32_t EminWork::sched_code() const {
   return (int32_t)((opts.maps ? 1 : 0) | (opts.gshift ? 2 : 0) |
                    (opts.xcd_split == XCD_BY_CLASS ? 4 : 0) |
                    (opts.xcd_split == XCD_MERGED ? 8 : 0) | (tuned << 4) |
-                   ((opts.stage && stage.nblk) ? 64 : 0) | (opts.unroll >= 16 ? 128 : 0));
+                   ((opts.stage && stage.ntile) ? 64 : 0) | (opts.unroll >= 16 ? 128 : 0));
 }
 
 void autotune_stats(int64_t* out) {
@@ -907,23 +908,22 @@ template <class TM, class TX, class TY>
 static void spmm_any(const EminWork& w, const Csr& M, const TM* mval, const int64_t* nrp,
                      const int32_t* ncol, const TX* X, TY* Y, const double* D, double bytes,
                      hipStream_t s) {
-  // rows of staged blocks (their share of the algorithmic bytes), then the rest
-  if (w.opts.stage && w.stage.nblk) {
-    const StagePlan& P = w.stage;
-    const double vb = (double)sizeof(TX);
-    const double sb = (4.0 + (double)sizeof(TM)) * (double)P.m_entries +
-                      (4.0 + 2.0 * vb) * (double)P.p_entries + 16.0 * (double)P.rows;
-    spmm_stage<TM, TX, TY>(w, M.rowptr, mval, nrp, X, Y, D, sb, s);
-    bytes -= sb;
-  }
+  // rows of staged tiles, then the rest: one timed interval from the first
+  // launch's start to the last one's end
+  const bool tiled = w.opts.stage && w.stage.ntile;
   const int64_t nb = w.sched.blk_off[SPMM_NT];
-  if (nb == 0) return;
+  if (!tiled && nb == 0) return;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (prof::begin_launch(s, EMIN_PROF_SPMM, bytes, 0.0, &e0, &e1)) {
-    hipExtLaunchKernelGGL(k_spmm<TM, TX, TY>, dim3((unsigned)nb), dim3(SPMM_BS), 0, s, e0, e1, 0,
-                          w.sched, (const int64_t*)M.rowptr, (const int32_t*)M.col, mval,
-                          (const int32_t*)w.kofs, (const uint32_t*)w.nib, w.nnzm, nrp, ncol, X,
-                          Y, D, w.rowdot);
+  const bool timed = prof::begin_launch(s, EMIN_PROF_SPMM, bytes, 0.0, &e0, &e1);
+  if (tiled)
+    spmm_stage<TM, TX, TY>(w, M.rowptr, mval, nrp, X, Y, D, s, timed ? e0 : nullptr,
+                           (timed && nb == 0) ? e1 : nullptr);
+  if (nb == 0) return;
+  if (timed) {
+    hipExtLaunchKernelGGL(k_spmm<TM, TX, TY>, dim3((unsigned)nb), dim3(SPMM_BS), 0, s,
+                          tiled ? nullptr : e0, e1, 0, w.sched, (const int64_t*)M.rowptr,
+                          (const int32_t*)M.col, mval, (const int32_t*)w.kofs,
+                          (const uint32_t*)w.nib, w.nnzm, nrp, ncol, X, Y, D, w.rowdot);
     HIP_OK(hipGetLastError());
   } else {
     k_spmm<TM, TX, TY><<<(unsigned)nb, SPMM_BS, 0, s>>>(w.sched, M.rowptr, M.col, mval, w.kofs,

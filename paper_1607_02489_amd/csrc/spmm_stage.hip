@@ -1,33 +1,154 @@
-// Masked product Q = mask_N(M Z) with LDS-staged rows of Z (sec. 4.3).
+// Masked product Q = mask_N(M Z) on spatial tiles with LDS-staged rows of Z
+// (sec. 4.3).
 //
-// A block owns SR consecutive rows i.  Every Z row k that those rows' M
-// entries reach is copied once into LDS: the union of the k's is a handful of
-// runs of consecutive indices (one per neighbouring line of the mesh in a
-// lexicographic ordering), and since pattern rows are stored back to back, a
-// run of k's is one contiguous range of Z's values -- a coalesced stream.
-// The block's slice of M (values, intersection maps) is contiguous too.  All
-// the irregular work -- finding Z(k, j) for slot j of row i -- then reads
-// LDS, and HBM sees only coalesced loads and stores.
+// The rows are grouped into tiles by the cells of a uniform grid laid over
+// their coordinates (cells sized for about 64 rows).  A tile's rows reach a
+// set of Z rows k (the union of their M rows' columns) several times smaller
+// than the sum of their lengths: neighbouring mesh nodes share most of their
+// neighbours.  A workgroup copies that union into LDS once, as runs of
+// consecutive k (pattern rows are stored back to back, so a run of k's is one
+// contiguous stretch of Z's values: a coalesced stream), and every gather of
+// the product then reads LDS.  L2 and HBM see each Z row once per tile
+// instead of once per (i, k) pair.
 //
-// Per output entry (i, slot s) the sum runs over M's row i in ascending k,
-// one fused multiply-add per matching entry, exactly as the gathering kernel
-// does, so both give the same bits.  The plan (which blocks fit, their runs,
-// each M entry's LDS offset) is built once per pattern.
+// Within a tile the rows are processed in packs of eight rows by one wave,
+// eight lanes per row; lane l of a row owns slots l, l + 8, l + 16, l + 24
+// (as many as the pack's class needs: rows of at most 8, 16 or 32 slots).
+// Per output slot the sum runs over M's row in ascending k, one fused
+// multiply-add per entry (a missing match adds m * 0), exactly as the
+// gathering kernel does over its padded entries, so both give the same bits
+// and the split of rows between the two kernels never changes a result.  The
+// plan (tiles, their runs, each M entry's LDS offset) is built once per
+// pattern.
 #include "emin_cg.h"
 #include "prof.h"
 
 #include <hip/hip_ext.h>
 
+#include <cmath>
+
 namespace emin {
 
 namespace {
 
-constexpr int ST_BS = 128;            // threads per block
-constexpr int ST_WBITS = 32768;       // plan: widest k window (bits of the LDS bitmap)
+constexpr int PL_BS = 256;   // threads of a plan block (one cell)
+constexpr int TCH = 16;      // M entries per row in a wave's window
+constexpr int TINFO = 8;     // ints of a tile's record
+
+// ---------------------------------------------------------------------------
+// cells
+// ---------------------------------------------------------------------------
+struct CellGrid {
+  double lo[3];
+  double inv;      // 1 / cell size
+  int32_t nc[3];   // cells per dimension
+  int32_t ncell;
+};
+
+__device__ __forceinline__ double coord(const double* xyz, const int32_t* xmap, int dim,
+                                        int64_t i, int d) {
+  const int64_t v = xmap ? (int64_t)xmap[i] : i;
+  return xyz[v * dim + d];
+}
+
+// Bounding box of the rows' coordinates and the cell size that gives about
+// tgt rows per cell over the box (a dimension of zero extent takes one
+// cell); the cell grows until the cell count is within cap.  One block.
+__global__ __launch_bounds__(1024) void k_cell_grid(const double* xyz, const int32_t* xmap,
+                                                    int dim, int64_t n, int tgt, int64_t cap,
+                                                    CellGrid* g) {
+  __shared__ double smin[3][16], smax[3][16];
+  double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
+    for (int d = 0; d < dim; d++) {
+      const double v = coord(xyz, xmap, dim, i, d);
+      mn[d] = fmin(mn[d], v);
+      mx[d] = fmax(mx[d], v);
+    }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int d = 0; d < 3; d++) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+      mn[d] = fmin(mn[d], __shfl_xor(mn[d], m, 64));
+      mx[d] = fmax(mx[d], __shfl_xor(mx[d], m, 64));
+    }
+    if (lane == 0) {
+      smin[d][w] = mn[d];
+      smax[d][w] = mx[d];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double lo[3], ext[3];
+  for (int d = 0; d < 3; d++) {
+    double a = 1e300, b = -1e300;
+    for (int k = 0; k < (int)(blockDim.x >> 6); k++) {
+      a = fmin(a, smin[d][k]);
+      b = fmax(b, smax[d][k]);
+    }
+    lo[d] = d < dim ? a : 0.0;
+    ext[d] = d < dim && b > a ? b - a : 0.0;
+  }
+  double vol = 1.0;
+  int de = 0;
+  for (int d = 0; d < dim; d++)
+    if (ext[d] > 0.0) {
+      vol *= ext[d];
+      de++;
+    }
+  double cs = de ? pow(vol * (double)tgt / (double)(n > 0 ? n : 1), 1.0 / de) : 1.0;
+  if (!(cs > 0.0)) cs = 1.0;
+  int32_t nc[3] = {1, 1, 1};
+  for (int it = 0; it < 400; it++) {
+    double tot = 1.0;
+    for (int d = 0; d < 3; d++) {
+      nc[d] = ext[d] > 0.0 ? (int32_t)fmin(floor(ext[d] / cs) + 1.0, 1e9) : 1;
+      tot *= (double)nc[d];
+    }
+    if (tot <= (double)cap) break;
+    cs *= 1.25;
+  }
+  for (int d = 0; d < 3; d++) {
+    g->lo[d] = lo[d];
+    g->nc[d] = nc[d];
+  }
+  g->inv = 1.0 / cs;
+  g->ncell = nc[0] * nc[1] * nc[2];
+}
+
+// each row's cell (z-major, then y, then x), counted per cell (cnt[c + 1]);
+// without coordinates, blocks of tgt consecutive rows
+__global__ void k_cell_key(const double* xyz, const int32_t* xmap, int dim, int64_t n, int tgt,
+                           const CellGrid* g, int32_t* key, int64_t* cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t c;
+  if (xyz) {
+    int32_t q[3] = {0, 0, 0};
+    for (int d = 0; d < dim; d++) {
+      const double t = (coord(xyz, xmap, dim, i, d) - g->lo[d]) * g->inv;
+      q[d] = (int32_t)fmax(0.0, fmin(floor(t), (double)(g->nc[d] - 1)));
+    }
+    c = (q[2] * g->nc[1] + q[1]) * g->nc[0] + q[0];
+  } else {
+    c = (int32_t)(i / tgt);
+  }
+  key[i] = c;
+  atomicAdd(reinterpret_cast<unsigned long long*>(cnt + c + 1), 1ull);
+}
+
+// rows placed by cell (the order within a cell is settled by the plan)
+__global__ void k_cell_place(const int32_t* key, int64_t n, const int64_t* coff, int32_t* cur,
+                             int32_t* csort) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t c = key[i];
+  csort[coff[c] + atomicAdd(&cur[c], 1)] = (int32_t)i;
+}
 
 __device__ __forceinline__ int block_excl_scan(int v, int* tmp) {
-  // exclusive scan over the block (ST_BS threads); tmp holds ST_BS/64 + 1
-  // ints, and its total stays in tmp[ST_BS/64] until the next call
+  // exclusive scan over the block (PL_BS threads); tmp holds PL_BS/64 + 1
+  // ints, and its total stays in tmp[PL_BS/64] until the next call
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   __syncthreads();   // every thread has read the previous call's tmp
   int x = v;
@@ -40,65 +161,134 @@ __device__ __forceinline__ int block_excl_scan(int v, int* tmp) {
   __syncthreads();
   if (threadIdx.x == 0) {
     int a = 0;
-    for (int k = 0; k < ST_BS / 64; k++) {
+    for (int k = 0; k < PL_BS / 64; k++) {
       const int t = tmp[k];
       tmp[k] = a;
       a += t;
     }
-    tmp[ST_BS / 64] = a;
+    tmp[PL_BS / 64] = a;
   }
   __syncthreads();
-  const int r = tmp[w] + x - v;
-  return r;
+  return tmp[w] + x - v;
 }
 
-// Plan of one block of SR rows.  Pass 0 decides whether the block is staged
-// (every row map-eligible, at most EMAX M entries, a k window of at most
-// ST_WBITS, at most VCAP staged values and RCAP runs) and counts its runs and
-// the M / pattern entries it covers; pass 1 (staged blocks only) writes the
-// runs and every M entry's LDS offset.
+struct PlanArgs {
+  TileDims D;
+  const int64_t* mrp;
+  const int32_t* mcol;
+  const int64_t* nrp;
+  const int32_t* kofs;
+  const uint8_t* elig;
+  const int64_t* coff;
+  const int32_t* csort;
+  // pass 0 outputs
+  uint8_t* flag;
+  int64_t* nrun;                // per cell: runs of a staged cell, else 0
+  int32_t* vmax;
+  unsigned long long* cnt;      // staged rows, their M entries, their pattern entries, tiles
+  // pass 1
+  const int64_t* tix;           // inclusive scan of the flags
+  const int64_t* roff;          // inclusive scan of nrun
+  int32_t* tinfo;
+  int32_t* srows;
+  int32_t *rg, *rl, *rn;
+  int32_t* lofs;
+  uint8_t* row_staged;
+};
+
+// LDS of a plan block
+__host__ __device__ constexpr size_t plan_lds(const TileDims& D) {
+  return (size_t)D.tmax * (8 + 8 + 4 + 4)     // M starts, sort keys, rows, entry prefix
+         + (size_t)(D.wbits >> 5) * 8          // bitmap words and their ranks
+         + (size_t)(2 * D.vcap + 1) * 4;       // union entries and offsets
+}
+
+// Plan of one cell.  Its rows that fit the tiled kernel (map-eligible, 1 to
+// 32 slots) are staged when the cell has at most tmax rows and the union of
+// their Z rows fits (k window, values, runs).  Pass 0 decides and counts;
+// pass 1 (staged cells) writes the runs, the LDS offset of every M entry of a
+// staged row, the staged rows ordered by (slots class, M length descending,
+// index) and the tile's record.  The M entries of the staged rows are walked
+// as one flat range (each thread a stride of it), the row of an entry found
+// by binary search over the rows' entry prefix.
 template <int PASS>
-__global__ __launch_bounds__(ST_BS) void k_stage_plan(StageDims D, const int64_t* mrp,
-                                                      const int32_t* mcol, const int64_t* nrp,
-                                                      const int32_t* kofs, const uint8_t* elig,
-                                                      int64_t n, uint8_t* flag, int32_t* nruns,
-                                                      const int64_t* roff, int32_t* rg,
-                                                      int32_t* rl, int32_t* rn, int32_t* lofs,
-                                                      unsigned long long* cnt) {
-  __shared__ uint32_t bits[ST_WBITS / 32];
-  __shared__ int32_t wpre[ST_WBITS / 32];
-  __shared__ int tmp[ST_BS / 64 + 1];
-  __shared__ int s_ok;
+__global__ __launch_bounds__(PL_BS) void k_tile_plan(PlanArgs A) {
+  extern __shared__ __align__(16) unsigned char dsm[];
+  const TileDims& D = A.D;
+  const int nw = D.wbits >> 5;
+  int64_t* s_ma = reinterpret_cast<int64_t*>(dsm);                // rows' first M entry
+  uint64_t* s_key = reinterpret_cast<uint64_t*>(s_ma + D.tmax);   // staged rows' sort keys
+  uint32_t* bits = reinterpret_cast<uint32_t*>(s_key + D.tmax);
+  int32_t* wpre = reinterpret_cast<int32_t*>(bits + nw);
+  int32_t* s_u = wpre + nw;
+  int32_t* s_off = s_u + D.vcap;
+  int32_t* s_row = s_off + D.vcap + 1;   // rows of the cell (-1: not staged)
+  int32_t* s_pre = s_row + D.tmax;       // exclusive prefix of staged rows' M lengths
+  __shared__ int tmp[PL_BS / 64 + 1];
   __shared__ int s_kmin, s_kmax;
-  extern __shared__ int32_t dyn[];   // u list (EMAX), offsets (EMAX + 1)
-  int32_t* s_u = dyn;
-  int32_t* s_off = dyn + D.emax;
-  const int64_t b = blockIdx.x;
-  const int64_t r0 = b * D.sr;
-  const int64_t r1 = r0 + D.sr < n ? r0 + D.sr : n;
-  if (PASS == 1 && !flag[b]) return;
-  if (threadIdx.x == 0) {
-    s_ok = 1;
-    s_kmin = INT32_MAX;
-    s_kmax = -1;
-  }
-  __syncthreads();
-  const int64_t e0 = mrp[r0], e1 = mrp[r1];
-  const int64_t K = e1 - e0;
-  for (int64_t i = r0 + threadIdx.x; i < r1; i += ST_BS)
-    if (!elig[i]) s_ok = 0;
-  if (K > D.emax) s_ok = 0;
-  __syncthreads();
-  if (!s_ok) {
+  const int64_t c = blockIdx.x;
+  if (PASS == 1 && !A.flag[c]) return;
+  const int64_t r0 = A.coff[c], r1 = A.coff[c + 1];
+  const int T = (int)(r1 - r0);
+  const bool fits = T > 0 && T <= D.tmax;
+  if (!fits) {
     if (PASS == 0 && threadIdx.x == 0) {
-      flag[b] = 0;
-      nruns[b] = 0;
+      A.flag[c] = 0;
+      A.nrun[c] = 0;
     }
     return;
   }
+  // (every later rejection is taken by all threads together, after a
+  // barrier, from values every thread reads the same)
+  auto reject = [&]() {
+    if (PASS == 0 && threadIdx.x == 0) {
+      A.flag[c] = 0;
+      A.nrun[c] = 0;
+    }
+  };
+  if (threadIdx.x == 0) {
+    s_kmin = INT32_MAX;
+    s_kmax = -1;
+  }
+  int mlen = 0;
+  const int t = threadIdx.x;   // T <= tmax <= PL_BS: one row per thread
+  if (t < T) {
+    const int32_t i = A.csort[r0 + t];
+    const int64_t ni = A.nrp[i + 1] - A.nrp[i];
+    const bool ok = A.elig[i] && ni >= 1 && ni <= 32;
+    s_row[t] = ok ? i : -1;
+    s_ma[t] = A.mrp[i];
+    mlen = ok ? (int)(A.mrp[i + 1] - A.mrp[i]) : 0;
+    if (ok) {
+      const uint64_t cl = ni <= 8 ? 0 : (ni <= 16 ? 1 : 2);
+      const uint64_t ml = (uint64_t)(mlen < 0xFFFFF ? mlen : 0xFFFFF);
+      s_key[t] = (cl << 60) | ((0xFFFFFull - ml) << 32) | (uint64_t)(uint32_t)i;
+    }
+  }
+  const int pre = block_excl_scan(mlen, tmp);
+  const int E = tmp[PL_BS / 64];   // M entries of the staged rows
+  if (t < T) s_pre[t] = pre;
+  __syncthreads();
+  // row (local) of flat entry f: the last row whose prefix is <= f, among
+  // rows with entries
+  auto row_of = [&](int f) {
+    int lo = 0, hi = T - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_pre[mid] <= f) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+  };
+  if (E == 0) {
+    reject();
+    return;
+  }
+  // k window over the entries whose pattern row is not empty
   int kmn = INT32_MAX, kmx = -1;
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += ST_BS) {
-    const int32_t k = mcol[e];
+  for (int f = t; f < E; f += PL_BS) {
+    const int r = row_of(f);
+    const int32_t k = A.mcol[s_ma[r] + (f - s_pre[r])];
+    if (A.nrp[k + 1] == A.nrp[k]) continue;
     kmn = k < kmn ? k : kmn;
     kmx = k > kmx ? k : kmx;
   }
@@ -106,113 +296,146 @@ __global__ __launch_bounds__(ST_BS) void k_stage_plan(StageDims D, const int64_t
     atomicMin(&s_kmin, kmn);
     atomicMax(&s_kmax, kmx);
   }
-  for (int t = threadIdx.x; t < ST_WBITS / 32; t += ST_BS) bits[t] = 0u;
   __syncthreads();
   const int kmin = s_kmin, kmax = s_kmax;
-  const int width = kmax >= kmin ? kmax - kmin + 1 : 0;
-  if (width > ST_WBITS) {
-    if (PASS == 0 && threadIdx.x == 0) {
-      flag[b] = 0;
-      nruns[b] = 0;
-    }
+  const int64_t width = kmax >= kmin ? (int64_t)kmax - kmin + 1 : 0;
+  if (width == 0 || width > D.wbits) {
+    reject();
     return;
   }
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += ST_BS) {
-    const int o = mcol[e] - kmin;
+  const int nwu = (int)((width + 31) >> 5);
+  for (int q = t; q < nwu; q += PL_BS) bits[q] = 0u;
+  __syncthreads();
+  for (int f = t; f < E; f += PL_BS) {
+    const int r = row_of(f);
+    const int32_t k = A.mcol[s_ma[r] + (f - s_pre[r])];
+    if (A.nrp[k + 1] == A.nrp[k]) continue;
+    const int o = k - kmin;
     atomicOr(&bits[o >> 5], 1u << (o & 31));
   }
   __syncthreads();
-  // rank of every bitmap word: per thread a contiguous slice of words
-  const int nw = (width + 31) >> 5;
-  const int per = (nw + ST_BS - 1) / ST_BS;
-  const int w0 = threadIdx.x * per, w1 = w0 + per < nw ? w0 + per : nw;
-  int c = 0;
-  for (int w = w0; w < w1; w++) c += __popc(bits[w]);
-  int base = block_excl_scan(c, tmp);
-  const int U = tmp[ST_BS / 64];
-  for (int w = w0; w < w1; w++) {
-    wpre[w] = base;
-    uint32_t m = bits[w];
+  // the union in ascending k: each thread a contiguous slice of words
+  const int per = (nwu + PL_BS - 1) / PL_BS;
+  const int w0 = t * per < nwu ? t * per : nwu;
+  const int w1 = w0 + per < nwu ? w0 + per : nwu;
+  int cu = 0;
+  for (int q = w0; q < w1; q++) cu += __popc(bits[q]);
+  int ub = block_excl_scan(cu, tmp);
+  const int U = tmp[PL_BS / 64];
+  if (U > D.vcap) {
+    reject();
+    return;
+  }
+  for (int q = w0; q < w1; q++) {
+    wpre[q] = ub;
+    uint32_t m = bits[q];
     while (m) {
-      const int bt = __ffs(m) - 1;
+      const int b = __ffs(m) - 1;
       m &= m - 1u;
-      s_u[base++] = kmin + 32 * w + bt;
+      s_u[ub++] = kmin + 32 * q + b;
     }
   }
   __syncthreads();
-  // staged values: pattern row lengths of the union, prefix offsets
-  const int per_u = (U + ST_BS - 1) / ST_BS;
-  const int u0 = threadIdx.x * per_u, u1 = u0 + per_u < U ? u0 + per_u : U;
-  int lsum = 0, rs = 0;
+  // staged values (pattern row lengths over the union) and runs
+  const int pu = (U + PL_BS - 1) / PL_BS;
+  const int u0 = t * pu < U ? t * pu : U;
+  const int u1 = u0 + pu < U ? u0 + pu : U;
+  int lv = 0, lr = 0;
   for (int u = u0; u < u1; u++) {
     const int32_t k = s_u[u];
-    lsum += (int)(nrp[k + 1] - nrp[k]);
-    rs += (u == 0 || s_u[u - 1] != k - 1) ? 1 : 0;
+    lv += (int)(A.nrp[k + 1] - A.nrp[k]);
+    lr += (u == 0 || s_u[u - 1] != k - 1) ? 1 : 0;
   }
-  int obase = block_excl_scan(lsum, tmp);
-  const int V = tmp[ST_BS / 64];
-  int rbase = block_excl_scan(rs, tmp);
-  const int NR = tmp[ST_BS / 64];
+  int vb = block_excl_scan(lv, tmp);
+  const int V = tmp[PL_BS / 64];
+  int rb = block_excl_scan(lr, tmp);
+  const int NR = tmp[PL_BS / 64];
   if (V > D.vcap || NR > D.rcap) {
-    if (PASS == 0 && threadIdx.x == 0) {
-      flag[b] = 0;
-      nruns[b] = 0;
-    }
+    reject();
     return;
   }
   if (PASS == 0) {
-    if (threadIdx.x == 0) {
-      flag[b] = 1;
-      nruns[b] = NR;
-      atomicAdd(cnt + 0, (unsigned long long)(r1 - r0));
-      atomicAdd(cnt + 1, (unsigned long long)K);
-      atomicAdd(cnt + 2, (unsigned long long)(nrp[r1] - nrp[r0]));
-      atomicAdd(cnt + 3, 1ull);
+    unsigned long long nr = 0, me = 0, pe = 0;
+    if (t < T && s_row[t] >= 0) {
+      nr = 1;
+      me = (unsigned long long)mlen;
+      pe = (unsigned long long)(A.nrp[s_row[t] + 1] - A.nrp[s_row[t]]);
+    }
+    if (nr) {
+      atomicAdd(A.cnt + 0, nr);
+      atomicAdd(A.cnt + 1, me);
+      atomicAdd(A.cnt + 2, pe);
+    }
+    if (t == 0) {
+      A.flag[c] = 1;
+      A.nrun[c] = NR;
+      atomicMax(A.vmax, V);
+      atomicAdd(A.cnt + 3, 1ull);
     }
     return;
   }
   for (int u = u0; u < u1; u++) {
-    s_off[u] = obase;
-    obase += (int)(nrp[s_u[u] + 1] - nrp[s_u[u]]);
+    s_off[u] = vb;
+    vb += (int)(A.nrp[s_u[u] + 1] - A.nrp[s_u[u]]);
   }
-  if (threadIdx.x == 0) s_off[U] = V;
+  if (t == 0) s_off[U] = V;
   __syncthreads();
-  // runs: a start where k does not continue the previous union entry; its
-  // length runs to the next start
-  const int64_t ro = roff[b];
+  const int64_t st = A.tix[c] - 1;
+  const int64_t run0 = A.roff[c] - NR;
   for (int u = u0; u < u1; u++) {
     const int32_t k = s_u[u];
     if (u == 0 || s_u[u - 1] != k - 1) {
       int v = u + 1;
       while (v < U && s_u[v] == s_u[v - 1] + 1) v++;
-      rg[ro + rbase] = (int32_t)nrp[k];
-      rl[ro + rbase] = s_off[u];
-      rn[ro + rbase] = s_off[v] - s_off[u];
-      rbase++;
+      A.rg[run0 + rb] = (int32_t)A.nrp[k];
+      A.rl[run0 + rb] = s_off[u];
+      A.rn[run0 + rb] = s_off[v] - s_off[u];
+      rb++;
     }
   }
-  // every M entry: its row k's LDS start plus the map's base shift
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += ST_BS) {
-    const int32_t k = mcol[e];
+  // every M entry of a staged row: its Z row's LDS start plus the map's base
+  // shift (an entry whose pattern row is empty never matches: offset 0)
+  for (int f = t; f < E; f += PL_BS) {
+    const int r = row_of(f);
+    const int64_t e = s_ma[r] + (f - s_pre[r]);
+    const int32_t k = A.mcol[e];
+    const int64_t ka = A.nrp[k];
+    if (A.nrp[k + 1] == ka) {
+      A.lofs[e] = 0;
+      continue;
+    }
     const int o = k - kmin;
     const int u = wpre[o >> 5] + __popc(bits[o >> 5] & ((1u << (o & 31)) - 1u));
-    lofs[e] = s_off[u] + (int32_t)((int64_t)kofs[e] - nrp[k]);
+    A.lofs[e] = s_off[u] + (int32_t)((int64_t)A.kofs[e] - ka);
   }
-}
-
-__global__ void k_stage_list(const uint8_t* flag, int64_t nb, const int64_t* incl, int32_t* list,
-                             int sr, int64_t n, uint8_t* row_staged) {
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nb) return;
-  const bool f = flag[b] != 0;
-  if (f) list[incl[b] - 1] = (int32_t)b;
-  const int64_t r0 = b * sr;
-  for (int64_t i = r0; i < r0 + sr && i < n; i++) row_staged[i] = f ? 1 : 0;
-}
-
-__global__ void k_i32_to_i64(const int32_t* a, int64_t* b, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) b[i] = a[i];
+  // staged rows by key: each row's rank is the number of smaller keys
+  int cls[3] = {0, 0, 0};
+  if (t < T && s_row[t] >= 0) {
+    const uint64_t my = s_key[t];
+    int rank = 0;
+    for (int t2 = 0; t2 < T; t2++)
+      if (s_row[t2] >= 0 && s_key[t2] < my) rank++;
+    A.srows[r0 + rank] = s_row[t];
+    A.row_staged[s_row[t]] = 1;
+    cls[my >> 60] = 1;
+  }
+  block_excl_scan(cls[0], tmp);
+  const int n1 = tmp[PL_BS / 64];
+  block_excl_scan(cls[1], tmp);
+  const int n2 = tmp[PL_BS / 64];
+  block_excl_scan(cls[2], tmp);
+  const int n4 = tmp[PL_BS / 64];
+  if (t == 0) {
+    int32_t* ti = A.tinfo + st * TINFO;
+    ti[0] = (int32_t)r0;
+    ti[1] = n1;
+    ti[2] = n2;
+    ti[3] = n4;
+    ti[4] = (int32_t)run0;
+    ti[5] = NR;
+    ti[6] = V;
+    ti[7] = (int32_t)c;
+  }
 }
 
 __global__ void k_flag_to_i64(const uint8_t* a, int64_t* b, int64_t n) {
@@ -220,227 +443,307 @@ __global__ void k_flag_to_i64(const uint8_t* a, int64_t* b, int64_t n) {
   if (i < n) b[i] = a[i] ? 1 : 0;
 }
 
-}  // namespace
-
-// LDS bytes of the product kernel for one plan
-static size_t stage_smem(const StageDims& D, int np, size_t tm, size_t tx) {
-  size_t b = 0;
-  b += (size_t)3 * D.rcap * 4;                       // runs
-  b += (size_t)(D.sr + 1) * 4 * 2;                   // local row pointers of M and N
-  b = (b + 15) & ~size_t(15);
-  b += (size_t)D.vcap * tx;                          // staged Z
-  b = (b + 15) & ~size_t(15);
-  b += (size_t)D.emax * (tm + 4 + 4 * (size_t)np);   // M values, LDS offsets, map words
-  return (b + 15) & ~size_t(15);
+// ---------------------------------------------------------------------------
+// the product
+// ---------------------------------------------------------------------------
+// LDS of one wave's window: 8 rows x TCH entries of M values, LDS offsets and
+// up to four map planes
+template <class TM>
+constexpr int tile_win_bytes() {
+  return 8 * TCH * (int)(sizeof(TM) + 4 + 4 * 4);
 }
 
-void stage_plan(EminWork& w, const Csr& M, const int64_t* nrp, const uint8_t* elig, hipStream_t s,
-                Arena& ar) {
+template <class T> struct TVec4;
+template <> struct TVec4<double> {
+  double v[4];
+  __device__ __forceinline__ void load(const double* p) {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    const double2 b = *reinterpret_cast<const double2*>(p + 2);
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+  }
+};
+template <> struct TVec4<float> {
+  float v[4];
+  __device__ __forceinline__ void load(const float* p) {
+    const float4 a = *reinterpret_cast<const float4*>(p);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  }
+};
+
+// the wave's LDS writes are visible to its own reads (and the reverse)
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One pack: up to eight rows (rows[0 .. cnt)) of one slots class, SPL slots
+// per lane.  The rows' M entries pass through the wave's window TCH at a
+// time; the loop runs to the pack's longest row, shorter rows padded with
+// empty entries.
+template <int SPL, class TM, class TX, class TY>
+__device__ __forceinline__ void tile_pack(const int32_t* rows, int cnt, const int64_t* mrp,
+                                          const TM* mval, const int32_t* lofs,
+                                          const uint32_t* nib, int64_t nnzm, const int64_t* nrp,
+                                          const TX* Zs, TY* Y, const double* D, double* rowdot,
+                                          unsigned char* win) {
+  const int lane = threadIdx.x & 63, g = lane >> 3, l = lane & 7;
+  TM* gm = reinterpret_cast<TM*>(win) + g * TCH;
+  int32_t* gl = reinterpret_cast<int32_t*>(win + 8 * TCH * sizeof(TM)) + g * TCH;
+  uint32_t* gw = reinterpret_cast<uint32_t*>(win + 8 * TCH * (sizeof(TM) + 4)) + g * TCH;
+  const bool valid = g < cnt;
+  const int32_t i = valid ? rows[g] : 0;
+  const int64_t na = valid ? nrp[i] : 0;
+  const int ni = valid ? (int)(nrp[i + 1] - na) : 0;
+  const int64_t ma = valid ? mrp[i] : 0;
+  const int len = valid ? (int)(mrp[i + 1] - ma) : 0;
+  const int wl = -wave_min_i32(-len);   // longest row of the pack (uniform)
+  TM acc[SPL];
+  double dv[SPL];
+#pragma unroll
+  for (int q = 0; q < SPL; q++) {
+    acc[q] = TM(0);
+    const int s = l + 8 * q;
+    dv[q] = (rowdot && s < ni) ? D[na + s] : 0.0;
+  }
+  for (int c0 = 0; c0 < wl; c0 += TCH) {
+    const int cw = ((wl - c0 < TCH ? wl - c0 : TCH) + 3) & ~3;   // uniform
+    for (int u = l; u < cw; u += 8) {
+      const bool v = c0 + u < len;
+      const int64_t e = ma + c0 + u;
+      gm[u] = v ? mval[e] : TM(0);
+      gl[u] = v ? lofs[e] : 0;
+#pragma unroll
+      for (int q = 0; q < SPL; q++)
+        gw[q * (8 * TCH) + u] = v ? nib[(int64_t)q * nnzm + e] : 0xFFFFFFFFu;
+    }
+    wave_sync();
+    for (int u0 = 0; u0 < cw; u0 += 4) {
+      TVec4<TM> m4;
+      m4.load(gm + u0);
+      const int4 l4 = *reinterpret_cast<const int4*>(gl + u0);
+      const int32_t lv[4] = {l4.x, l4.y, l4.z, l4.w};
+      uint32_t wv[SPL][4];
+#pragma unroll
+      for (int q = 0; q < SPL; q++) {
+        const uint4 w4 = *reinterpret_cast<const uint4*>(gw + q * (8 * TCH) + u0);
+        wv[q][0] = w4.x;
+        wv[q][1] = w4.y;
+        wv[q][2] = w4.z;
+        wv[q][3] = w4.w;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+#pragma unroll
+        for (int q = 0; q < SPL; q++) {
+          const uint32_t f = (wv[q][u] >> (4 * l)) & 0xFu;
+          const bool hit = f != 0xFu;
+          const TX xl = Zs[hit ? lv[u] + l + 8 * q + (int)f : 0];
+          acc[q] = fma(m4.v[u], (TM)(hit ? xl : TX(0)), acc[q]);
+        }
+      }
+    }
+    wave_sync();
+  }
+  if (!valid) return;
+#pragma unroll
+  for (int q = 0; q < SPL; q++) {
+    const int s = l + 8 * q;
+    if (s < ni) Y[na + s] = (TY)acc[q];
+  }
+  if (rowdot) {
+    // <D, Y> of the row, summed in slot order by the row's first lane
+    double pr[SPL];
+#pragma unroll
+    for (int q = 0; q < SPL; q++) pr[q] = (l + 8 * q < ni) ? dv[q] * (double)acc[q] : 0.0;
+    double sum = 0.0;
+#pragma unroll
+    for (int q = 0; q < SPL; q++)
+      for (int u = 0; u < 8; u++) {
+        const double v = __shfl(pr[q], (lane & ~7) | u, 64);
+        if (8 * q + u < ni) sum = sum + v;
+      }
+    if (l == 0) rowdot[i] = sum;
+  }
+}
+
+template <class TM, class TX, class TY>
+__global__ __launch_bounds__(64 * TILE_WAVES) void k_spmm_tile(StageArgs A, const int64_t* mrp,
+                                                              const TM* mval,
+                                                              const uint32_t* nib, int64_t nnzm,
+                                                              const int64_t* nrp, const TX* X,
+                                                              TY* Y, const double* D,
+                                                              double* rowdot) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t st = xcd_block(blockIdx.x, gridDim.x);
+  const int32_t* ti = A.tinfo + st * TINFO;
+  const int32_t row0 = ti[0], n1 = ti[1], n2 = ti[2], n4 = ti[3], run0 = ti[4], nrun = ti[5];
+  TX* Zs = reinterpret_cast<TX*>(smem);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  unsigned char* win = smem + A.zbytes + wv * tile_win_bytes<TM>();
+  // the tile's Z rows: each wave copies whole runs, lanes along the run
+  for (int q = wv; q < nrun; q += TILE_WAVES) {
+    const TX* src = X + A.rg[run0 + q];
+    TX* dst = Zs + A.rl[run0 + q];
+    const int len = A.rn[run0 + q];
+    int v = lane;
+    for (; v + 192 < len; v += 256) {
+      const TX a0 = src[v], a1 = src[v + 64], a2 = src[v + 128], a3 = src[v + 192];
+      dst[v] = a0;
+      dst[v + 64] = a1;
+      dst[v + 128] = a2;
+      dst[v + 192] = a3;
+    }
+    for (; v < len; v += 64) dst[v] = src[v];
+  }
+  __syncthreads();
+  const int p1 = (n1 + 7) >> 3, p2 = (n2 + 7) >> 3, p4 = (n4 + 7) >> 3;
+  const int32_t* rows = A.srows + row0;
+  for (int p = wv; p < p1 + p2 + p4; p += TILE_WAVES) {
+    if (p < p1) {
+      const int a = 8 * p;
+      tile_pack<1>(rows + a, n1 - a < 8 ? n1 - a : 8, mrp, mval, A.lofs, nib, nnzm, nrp, Zs, Y, D,
+                   rowdot, win);
+    } else if (p < p1 + p2) {
+      const int a = 8 * (p - p1);
+      tile_pack<2>(rows + n1 + a, n2 - a < 8 ? n2 - a : 8, mrp, mval, A.lofs, nib, nnzm, nrp, Zs,
+                   Y, D, rowdot, win);
+    } else {
+      const int a = 8 * (p - p1 - p2);
+      tile_pack<4>(rows + n1 + n2 + a, n4 - a < 8 ? n4 - a : 8, mrp, mval, A.lofs, nib, nnzm, nrp,
+                   Zs, Y, D, rowdot, win);
+    }
+  }
+}
+
+}  // namespace
+
+void stage_plan(EminWork& w, const Csr& M, const int64_t* nrp, const uint8_t* elig,
+                const double* xyz, const int32_t* xmap, int dim, hipStream_t s, Arena& ar) {
   StagePlan& P = w.stage;
   P = StagePlan{};
   const int64_t n = w.n;
-  if (n == 0 || w.nnz == 0) return;
-  StageDims D;
-  D.sr = 16;
-  D.emax = 640;
-  D.rcap = 64;
-  D.vcap = 3072;
-  D.np = w.nplanes;
-  const int64_t nb = (n + D.sr - 1) / D.sr;
-  if (nb >= INT32_MAX) return;
-  uint8_t* flag = ar.alloc<uint8_t>(nb);
-  int32_t* nr = ar.alloc<int32_t>(nb);
+  if (n == 0 || w.nnz == 0 || M.nnz == 0) return;
+  if (xyz && (dim < 1 || dim > 3)) throw Error(EMIN_ERR_ARG, "tile plan: dimension");
+  const TileDims D;
+  static_assert(TileDims{}.tmax <= PL_BS, "one row per plan thread");
+  // cells: at most 4 n / tgt + 64 with coordinates (the cell grows beyond
+  // that), blocks of tgt rows without
+  const int64_t ncap = xyz ? 4 * n / D.tgt + 64 : (n + D.tgt - 1) / D.tgt;
+  if (ncap >= INT32_MAX) return;
+  CellGrid* grid = ar.alloc<CellGrid>(1);
+  int32_t* key = ar.alloc<int32_t>(n);
+  int64_t* coff = ar.alloc<int64_t>(ncap + 1);
+  int32_t* cur = ar.alloc<int32_t>(ncap);
+  int32_t* csort = ar.alloc<int32_t>(n);
+  HIP_OK(hipMemsetAsync(coff, 0, sizeof(int64_t) * (ncap + 1), s));
+  HIP_OK(hipMemsetAsync(cur, 0, sizeof(int32_t) * ncap, s));
+  if (xyz) k_cell_grid<<<1, 1024, 0, s>>>(xyz, xmap, dim, n, D.tgt, ncap, grid);
+  k_cell_key<<<nblocks(n, 256), 256, 0, s>>>(xyz, xmap, dim, n, D.tgt, grid, key, coff);
+  scan_inclusive(coff + 1, ncap, s, ar);
+  k_cell_place<<<nblocks(n, 256), 256, 0, s>>>(key, n, coff, cur, csort);
+  uint8_t* flag = ar.alloc<uint8_t>(ncap);
+  int64_t* nrun = ar.alloc<int64_t>(ncap);
+  int32_t* vmax = ar.alloc<int32_t>(1);
   unsigned long long* cnt = ar.alloc<unsigned long long>(4);
+  HIP_OK(hipMemsetAsync(vmax, 0, sizeof(int32_t), s));
   HIP_OK(hipMemsetAsync(cnt, 0, 4 * sizeof(unsigned long long), s));
-  const size_t dyn = (size_t)(2 * D.emax + 1) * 4;
-  k_stage_plan<0><<<(unsigned)nb, ST_BS, dyn, s>>>(D, M.rowptr, M.col, nrp, w.kofs, elig, n, flag,
-                                                   nr, nullptr, nullptr, nullptr, nullptr,
-                                                   nullptr, cnt);
-  // run offsets and the list of staged blocks
-  int64_t* roff = ar.alloc<int64_t>(nb + 1);
-  HIP_OK(hipMemsetAsync(roff, 0, sizeof(int64_t), s));
-  k_i32_to_i64<<<nblocks(nb, 256), 256, 0, s>>>(nr, roff + 1, nb);
-  scan_inclusive(roff + 1, nb, s, ar);
-  int64_t* fl = ar.alloc<int64_t>(nb);
-  k_flag_to_i64<<<nblocks(nb, 256), 256, 0, s>>>(flag, fl, nb);
-  scan_inclusive(fl, nb, s, ar);
+  PlanArgs A{};
+  A.D = D;
+  A.mrp = M.rowptr;
+  A.mcol = M.col;
+  A.nrp = nrp;
+  A.kofs = w.kofs;
+  A.elig = elig;
+  A.coff = coff;
+  A.csort = csort;
+  A.flag = flag;
+  A.nrun = nrun;
+  A.vmax = vmax;
+  A.cnt = cnt;
+  const size_t dyn = plan_lds(D);
+  allow_lds((const void*)k_tile_plan<0>);
+  allow_lds((const void*)k_tile_plan<1>);
+  k_tile_plan<0><<<(unsigned)ncap, PL_BS, dyn, s>>>(A);
+  int64_t* tix = ar.alloc<int64_t>(ncap);
+  k_flag_to_i64<<<nblocks(ncap, 256), 256, 0, s>>>(flag, tix, ncap);
+  scan_inclusive(tix, ncap, s, ar);
+  scan_inclusive(nrun, ncap, s, ar);
   unsigned long long hc[4];
   int64_t tot_runs = 0;
+  int32_t hv = 0;
   HIP_OK(hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipMemcpyAsync(&tot_runs, roff + nb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(&tot_runs, nrun + ncap - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(&hv, vmax, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
-  const int64_t nst = (int64_t)hc[3];
-  if (nst == 0) return;
+  const int64_t nt = (int64_t)hc[3];
+  if (nt == 0 || tot_runs >= INT32_MAX) return;
+  int32_t* tinfo = ar.alloc<int32_t>((size_t)nt * TINFO);
+  int32_t* srows = ar.alloc<int32_t>(n);
   int32_t* rg = ar.alloc<int32_t>(tot_runs);
   int32_t* rl = ar.alloc<int32_t>(tot_runs);
   int32_t* rn = ar.alloc<int32_t>(tot_runs);
   int32_t* lofs = ar.alloc<int32_t>(M.nnz);
-  k_stage_plan<1><<<(unsigned)nb, ST_BS, dyn, s>>>(D, M.rowptr, M.col, nrp, w.kofs, elig, n, flag,
-                                                   nr, roff, rg, rl, rn, lofs, nullptr);
-  int32_t* list = ar.alloc<int32_t>(nst);
   uint8_t* rs = ar.alloc<uint8_t>(n);
-  k_stage_list<<<nblocks(nb, 256), 256, 0, s>>>(flag, nb, fl, list, D.sr, n, rs);
+  HIP_OK(hipMemsetAsync(rs, 0, (size_t)n, s));
+  A.tix = tix;
+  A.roff = nrun;
+  A.tinfo = tinfo;
+  A.srows = srows;
+  A.rg = rg;
+  A.rl = rl;
+  A.rn = rn;
+  A.lofs = lofs;
+  A.row_staged = rs;
+  k_tile_plan<1><<<(unsigned)ncap, PL_BS, dyn, s>>>(A);
   P.dims = D;
-  P.nblk = nst;
-  P.blocks = list;
-  P.roff = roff;
+  P.ntile = nt;
+  P.tinfo = tinfo;
+  P.srows = srows;
   P.rg = rg;
   P.rl = rl;
   P.rn = rn;
   P.lofs = lofs;
   P.row_staged = rs;
+  P.vmax = hv;
   P.rows = (int64_t)hc[0];
   P.m_entries = (int64_t)hc[1];
   P.p_entries = (int64_t)hc[2];
 }
 
-// The product on the staged blocks.  Phases: the block's runs and row
-// pointers to LDS; Z's runs and M's slice to LDS (coalesced); one output
-// entry per thread at a time (the row by binary search over the local row
-// pointers), summing over the row's M entries from LDS; Y stored coalesced;
-// with D, each row's <D, Y> summed in slot order.
-template <class TM, class TX, class TY>
-__global__ __launch_bounds__(ST_BS) void k_spmm_stage(StageArgs A, const int64_t* mrp,
-                                                      const TM* mval, const uint32_t* nib,
-                                                      int64_t nnzm, const int64_t* nrp,
-                                                      const TX* X, TY* Y, const double* Dv,
-                                                      double* rowdot) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const StageDims& D = A.dims;
-  int32_t* s_rg = reinterpret_cast<int32_t*>(smem);
-  int32_t* s_rl = s_rg + D.rcap;
-  int32_t* s_rn = s_rl + D.rcap;
-  int32_t* s_mr = s_rn + D.rcap;          // local M row pointers (sr + 1)
-  int32_t* s_nr = s_mr + D.sr + 1;        // local N row pointers (sr + 1)
-  size_t off = ((size_t)(3 * D.rcap + 2 * (D.sr + 1)) * 4 + 15) & ~size_t(15);
-  TX* s_z = reinterpret_cast<TX*>(smem + off);
-  off = (off + (size_t)D.vcap * sizeof(TX) + 15) & ~size_t(15);
-  TM* s_m = reinterpret_cast<TM*>(smem + off);
-  int32_t* s_lo = reinterpret_cast<int32_t*>(s_m + D.emax);
-  uint32_t* s_w = reinterpret_cast<uint32_t*>(s_lo + D.emax);   // [np][emax]
-
-  const int64_t b = A.blocks[xcd_block(blockIdx.x, gridDim.x)];
-  const int64_t n = A.n;
-  const int64_t r0 = b * D.sr;
-  const int64_t r1 = r0 + D.sr < n ? r0 + D.sr : n;
-  const int nrows = (int)(r1 - r0);
-  const int64_t ro = A.roff[b];
-  const int nr = (int)(A.roff[b + 1] - ro);
-  const int t = threadIdx.x;
-  const int64_t e0 = mrp[r0], p0 = nrp[r0];
-  for (int q = t; q < nr; q += ST_BS) {
-    s_rg[q] = A.rg[ro + q];
-    s_rl[q] = A.rl[ro + q];
-    s_rn[q] = A.rn[ro + q];
-  }
-  for (int q = t; q <= nrows; q += ST_BS) {
-    s_mr[q] = (int32_t)(mrp[r0 + q] - e0);
-    s_nr[q] = (int32_t)(nrp[r0 + q] - p0);
-  }
-  __syncthreads();
-  // Z's runs: each wave copies whole runs, lanes along the run
-  {
-    const int lane = t & 63, wv = t >> 6;
-    for (int q = wv; q < nr; q += ST_BS / 64) {
-      const TX* src = X + s_rg[q];
-      TX* dst = s_z + s_rl[q];
-      const int len = s_rn[q];
-      int v = lane;
-      for (; v + 192 < len; v += 256) {
-        const TX a0 = src[v], a1 = src[v + 64], a2 = src[v + 128], a3 = src[v + 192];
-        dst[v] = a0;
-        dst[v + 64] = a1;
-        dst[v + 128] = a2;
-        dst[v + 192] = a3;
-      }
-      for (; v < len; v += 64) dst[v] = src[v];
-    }
-  }
-  // M's slice: values, LDS offsets, map words
-  const int K = s_mr[nrows];
-  for (int q = t; q < K; q += ST_BS) {
-    s_m[q] = mval[e0 + q];
-    s_lo[q] = A.lofs[e0 + q];
-    for (int p = 0; p < D.np; p++) s_w[p * D.emax + q] = nib[(int64_t)p * nnzm + e0 + q];
-  }
-  __syncthreads();
-  const int NE = s_nr[nrows];
-  constexpr int EPT = 4;                  // output entries per thread (sr * 32 / ST_BS)
-  TM acc[EPT];
-  int rowi[EPT];
-#pragma unroll
-  for (int j = 0; j < EPT; j++) {
-    const int p = t + j * ST_BS;
-    acc[j] = TM(0);
-    rowi[j] = -1;
-    if (p < NE) {
-      int lo = 0, hi = nrows - 1;          // last row whose start <= p
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_nr[mid] <= p) lo = mid; else hi = mid - 1;
-      }
-      const int sl = p - s_nr[lo];
-      rowi[j] = lo;
-      const int sh = 4 * (sl & 7);
-      const uint32_t* wp = s_w + (sl >> 3) * D.emax;
-      TM a = TM(0);
-      for (int e = s_mr[lo]; e < s_mr[lo + 1]; e++) {
-        const uint32_t f = (wp[e] >> sh) & 0xFu;
-        if (f != 0xFu) a = fma(s_m[e], (TM)s_z[s_lo[e] + sl + (int)f], a);
-      }
-      acc[j] = a;
-      Y[p0 + p] = (TY)a;
-    }
-  }
-  if (!Dv) return;
-  __syncthreads();                        // every thread is done with s_z
-  double* s_pr = reinterpret_cast<double*>(s_z);
-#pragma unroll
-  for (int j = 0; j < EPT; j++) {
-    const int p = t + j * ST_BS;
-    if (p < NE) s_pr[p] = Dv[p0 + p] * (double)acc[j];
-  }
-  __syncthreads();
-  for (int r = t; r < nrows; r += ST_BS) {
-    double sum = 0.0;
-    for (int p = s_nr[r]; p < s_nr[r + 1]; p++) sum = sum + s_pr[p];
-    rowdot[r0 + r] = sum;
-  }
-}
-
 template <class TM, class TX, class TY>
 void spmm_stage(const EminWork& w, const int64_t* mrp, const TM* mval, const int64_t* nrp,
-                const TX* X, TY* Y, const double* Dv, double bytes, hipStream_t s) {
+                const TX* X, TY* Y, const double* Dv, hipStream_t s, hipEvent_t e0,
+                hipEvent_t e1) {
   const StagePlan& P = w.stage;
-  if (P.nblk == 0) return;
+  if (P.ntile == 0) return;
   StageArgs A;
-  A.dims = P.dims;
-  A.blocks = P.blocks;
-  A.roff = P.roff;
+  A.tinfo = P.tinfo;
+  A.srows = P.srows;
   A.rg = P.rg;
   A.rl = P.rl;
   A.rn = P.rn;
   A.lofs = P.lofs;
-  A.n = w.n;
-  const size_t lds = stage_smem(P.dims, P.dims.np, sizeof(TM), sizeof(TX));
-  allow_lds((const void*)k_spmm_stage<TM, TX, TY>);
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (prof::begin_launch(s, EMIN_PROF_SPMM, bytes, 0.0, &e0, &e1)) {
-    hipExtLaunchKernelGGL(k_spmm_stage<TM, TX, TY>, dim3((unsigned)P.nblk), dim3(ST_BS), lds, s,
-                          e0, e1, 0, A, mrp, mval, (const uint32_t*)w.nib, w.nnzm, nrp, X, Y, Dv,
-                          w.rowdot);
+  A.zbytes = (int32_t)(((size_t)P.vmax * sizeof(TX) + 15) & ~size_t(15));
+  const size_t lds = (size_t)A.zbytes + (size_t)TILE_WAVES * tile_win_bytes<TM>();
+  allow_lds((const void*)k_spmm_tile<TM, TX, TY>);
+  if (e0 || e1) {
+    hipExtLaunchKernelGGL(k_spmm_tile<TM, TX, TY>, dim3((unsigned)P.ntile), dim3(64 * TILE_WAVES),
+                          lds, s, e0, e1, 0, A, mrp, mval, (const uint32_t*)w.nib, w.nnzm, nrp, X,
+                          Y, Dv, w.rowdot);
     HIP_OK(hipGetLastError());
   } else {
-    k_spmm_stage<TM, TX, TY><<<(unsigned)P.nblk, ST_BS, lds, s>>>(A, mrp, mval, w.nib, w.nnzm, nrp,
-                                                                 X, Y, Dv, w.rowdot);
+    k_spmm_tile<TM, TX, TY><<<(unsigned)P.ntile, 64 * TILE_WAVES, lds, s>>>(
+        A, mrp, mval, w.nib, w.nnzm, nrp, X, Y, Dv, w.rowdot);
   }
 }
 
 template void spmm_stage<double, double, double>(const EminWork&, const int64_t*, const double*,
                                                  const int64_t*, const double*, double*,
-                                                 const double*, double, hipStream_t);
+                                                 const double*, hipStream_t, hipEvent_t,
+                                                 hipEvent_t);
 template void spmm_stage<float, float, float>(const EminWork&, const int64_t*, const float*,
                                               const int64_t*, const float*, float*, const double*,
-                                              double, hipStream_t);
+                                              hipStream_t, hipEvent_t, hipEvent_t);
 
 }  // namespace emin

@@ -195,8 +195,8 @@ def params(tau1_v=0.06, tau1_p=0.06, tau2_sq=1.5e-3, iters=5, mixed=False, energ
            gmres=False, pg=False) -> c_params:
     """energy_ata: the velocity block's EMIN energy is the A^T A-norm of the
     filtered operator (sec. 4.3, eq. (min_problem), non-symmetric operators).
-    staged: the masked product stages Z rows in LDS per block of rows (instead
-    of gathering them row by row from device memory)."""
+    staged: the masked product runs on coordinate tiles whose Z rows are
+    staged in LDS (instead of gathering them row by row from device memory)."""
     flags = ((EMIN_FLAG_ENERGY if energy else 0) | (EMIN_FLAG_VALIDATE if validate else 0) |
              (EMIN_FLAG_AUTOTUNE if autotune else 0) | (EMIN_FLAG_ENERGY_ATA if energy_ata else 0) |
              (EMIN_FLAG_STAGED_PRODUCT if staged else 0) | (EMIN_FLAG_GMRES if gmres else 0) |

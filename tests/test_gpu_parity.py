@@ -103,10 +103,11 @@ STAGE_CASES = {
 @pytest.mark.parametrize("mixed", [False, True])
 @pytest.mark.parametrize("case", list(STAGE_CASES))
 def test_staged_product_equals_gathering_product(case, mixed):
-    """The masked product with Z rows staged in LDS per block of rows and the
-    one that gathers every row from device memory compute the same sums in
-    the same order: P, the CG traces and RAP are bitwise equal, in FP64 and in
-    mixed precision, and the staged plan covers the rows."""
+    """The tiled masked product (rows grouped by coordinate cells, each
+    tile's Z rows staged in LDS) and the one that gathers every row from
+    device memory compute the same sums in the same order: P, the CG traces
+    and RAP are bitwise equal, in FP64 and in mixed precision, and the tiled
+    kernel is in use."""
     s, kw = STAGE_CASES[case]()
     say(f"[gpu] staged vs gathering product {case} mixed={mixed}: dofs={s.dofs}")
     from paper_1607_02489_amd import emin as E
@@ -114,6 +115,25 @@ def test_staged_product_equals_gathering_product(case, mixed):
     a = gpu_level(s, iters=5, mixed=mixed, dsys=d, staged=True, **kw)
     b = gpu_level(s, iters=5, mixed=mixed, dsys=d, **kw)
     assert a["sizes"]["sched_v"] & 64 and not b["sizes"]["sched_v"] & 64
+    for k in ("Pv", "Pp", "Ac", "Bc"):
+        assert np.array_equal(a[k].val, b[k].val), k
+    for k in ("energy_v", "energy_p", "rho_v", "rho_p"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_tiled_product_cfg3_level0_bitwise():
+    """3-D Stokes 48^3 (2,855,668 dofs), level 0: the tiled masked product
+    (rows grouped by coordinate cells, Z rows staged in LDS) and the gathering
+    one give bitwise equal P, CG traces and RAP at full size, with the tiled
+    kernel in use for both blocks."""
+    from paper_1607_02489_amd import emin as E
+    s = synth.stokes3d(48)
+    say(f"[gpu] tiled vs gathering product, 3-D Stokes 48^3: dofs={s.dofs}")
+    d = E.DeviceSystem.upload(s)
+    kw = dict(tau1_v=0.038, tau1_p=0.04)
+    a = gpu_level(s, iters=5, dsys=d, staged=True, **kw)
+    b = gpu_level(s, iters=5, dsys=d, **kw)
+    assert a["sizes"]["sched_v"] & 64 and a["sizes"]["sched_p"] & 64
     for k in ("Pv", "Pp", "Ac", "Bc"):
         assert np.array_equal(a[k].val, b[k].val), k
     for k in ("energy_v", "energy_p", "rho_v", "rho_p"):
