@@ -84,8 +84,10 @@ enum {
                                     stages each tile's Z rows in LDS (coalesced runs)
                                     and sums from LDS, instead of gathering Z from
                                     device memory row by row; rows of tiles that do not
-                                    fit keep the gathering kernel (the same sums in the
-                                    same order, so the same bits) */
+                                    fit keep the gathering kernel.  Each output is the
+                                    same sum in another fixed order (partials over every
+                                    eighth entry, added in a fixed tree): deterministic,
+                                    equal to the gathering kernel's up to rounding */
   EMIN_FLAG_GMRES = 64u,         /* sec. 4.3 names a constrained CG or GMRES: the velocity
                                     block's EMIN runs `iters` steps of GMRES on the
                                     projected masked system Pi mask_N(A~ P) = 0 of the

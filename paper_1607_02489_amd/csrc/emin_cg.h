@@ -58,18 +58,20 @@ struct TileDims {
 };
 
 // waves of a tile workgroup
-constexpr int TILE_WAVES = 4;
+constexpr int TILE_WAVES = 8;
 
 // plan of the tiled product (built once per pattern): per staged tile its
-// record (first row in srows, rows per slots class (<= 8, <= 16, <= 32),
-// first run, runs, staged values, cell), the staged rows tile by tile, the
-// runs of consecutive Z rows (start in Z, start in LDS, length) and per M
+// record (first row in srows, rows per slots class (<= 8, <= 16), unused,
+// first run, runs, staged values, cell), the staged rows tile by tile with
+// each one's first M entry, M length, first pattern entry and slots (smeta),
+// the runs of consecutive Z rows (start in Z, start in LDS, length) and per M
 // entry of a staged row the LDS position its intersection map is relative to
 struct StagePlan {
   TileDims dims;
   int64_t ntile = 0;
   const int32_t* tinfo = nullptr;
   const int32_t* srows = nullptr;
+  const int4* smeta = nullptr;
   const int32_t *rg = nullptr, *rl = nullptr, *rn = nullptr;
   const int32_t* lofs = nullptr;
   const uint8_t* row_staged = nullptr;
@@ -81,6 +83,7 @@ struct StagePlan {
 struct StageArgs {
   const int32_t* tinfo;
   const int32_t* srows;
+  const int4* smeta;
   const int32_t *rg, *rl, *rn;
   const int32_t* lofs;
   int32_t zbytes;   // LDS bytes of the staged Z values (16-byte aligned)
@@ -101,7 +104,7 @@ struct EminWork {
   // served by the searching kernel (G = 4..64)
   SpmmSched sched;
   // intersection maps per M entry: base offset and 4-bit slot fields
-  // (nplanes words of eight fields, plane-major)
+  // (nplanes words of eight fields, plane-major, planes nnzm apart)
   int32_t* kofs = nullptr;
   uint32_t* nib = nullptr;
   int64_t nnzm = 0;

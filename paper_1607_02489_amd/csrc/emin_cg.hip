@@ -801,11 +801,11 @@ void EminWork::make_bins(const Csr& M, const int64_t* nrp, const int32_t* ncol, 
     int g = 4;
     while (g < 64 && g < avg) g <<= 1;
     switch (g) {
-      case 4: k_spmm_maps<4><<<nblocks(n, 64), 256, 0, s>>>(M.rowptr, M.col, nrp, ncol, n, M.nnz, nplanes, kofs, nib, elig); break;
-      case 8: k_spmm_maps<8><<<nblocks(n, 32), 256, 0, s>>>(M.rowptr, M.col, nrp, ncol, n, M.nnz, nplanes, kofs, nib, elig); break;
-      case 16: k_spmm_maps<16><<<nblocks(n, 16), 256, 0, s>>>(M.rowptr, M.col, nrp, ncol, n, M.nnz, nplanes, kofs, nib, elig); break;
-      case 32: k_spmm_maps<32><<<nblocks(n, 8), 256, 0, s>>>(M.rowptr, M.col, nrp, ncol, n, M.nnz, nplanes, kofs, nib, elig); break;
-      default: k_spmm_maps<64><<<nblocks(n, 4), 256, 0, s>>>(M.rowptr, M.col, nrp, ncol, n, M.nnz, nplanes, kofs, nib, elig); break;
+      case 4: k_spmm_maps<4><<<nblocks(n, 64), 256, 0, s>>>(M.rowptr, M.col, nrp, ncol, n, nnzm, nplanes, kofs, nib, elig); break;
+      case 8: k_spmm_maps<8><<<nblocks(n, 32), 256, 0, s>>>(M.rowptr, M.col, nrp, ncol, n, nnzm, nplanes, kofs, nib, elig); break;
+      case 16: k_spmm_maps<16><<<nblocks(n, 16), 256, 0, s>>>(M.rowptr, M.col, nrp, ncol, n, nnzm, nplanes, kofs, nib, elig); break;
+      case 32: k_spmm_maps<32><<<nblocks(n, 8), 256, 0, s>>>(M.rowptr, M.col, nrp, ncol, n, nnzm, nplanes, kofs, nib, elig); break;
+      default: k_spmm_maps<64><<<nblocks(n, 4), 256, 0, s>>>(M.rowptr, M.col, nrp, ncol, n, nnzm, nplanes, kofs, nib, elig); break;
     }
   }
   tuned = 0;

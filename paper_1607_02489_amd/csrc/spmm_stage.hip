@@ -12,14 +12,14 @@
 // instead of once per (i, k) pair.
 //
 // Within a tile the rows are processed in packs of eight rows by one wave,
-// eight lanes per row; lane l of a row owns slots l, l + 8, l + 16, l + 24
-// (as many as the pack's class needs: rows of at most 8, 16 or 32 slots).
-// Per output slot the sum runs over M's row in ascending k, one fused
-// multiply-add per entry (a missing match adds m * 0), exactly as the
-// gathering kernel does over its padded entries, so both give the same bits
-// and the split of rows between the two kernels never changes a result.  The
-// plan (tiles, their runs, each M entry's LDS offset) is built once per
-// pattern.
+// eight lanes per row: lane l takes the row's M entries l, l + 8, l + 16, ...
+// (coalesced loads straight into registers, the next eight loaded while the
+// current eight are summed) and keeps one partial sum per slot of the row
+// (rows of at most 16 slots; longer ones keep the gathering kernel).  A
+// slot's eight partials are then added in a fixed tree on the DPP network.
+// The order is fixed, so results are deterministic; it differs from the
+// gathering kernel's ascending-k sum only by rounding.  The plan (tiles,
+// their runs, each M entry's LDS offset) is built once per pattern.
 #include "emin_cg.h"
 #include "prof.h"
 
@@ -32,7 +32,6 @@ namespace emin {
 namespace {
 
 constexpr int PL_BS = 256;   // threads of a plan block (one cell)
-constexpr int TCH = 16;      // M entries per row in a wave's window
 constexpr int TINFO = 8;     // ints of a tile's record
 
 // ---------------------------------------------------------------------------
@@ -191,6 +190,7 @@ struct PlanArgs {
   const int64_t* roff;          // inclusive scan of nrun
   int32_t* tinfo;
   int32_t* srows;
+  int4* smeta;
   int32_t *rg, *rl, *rn;
   int32_t* lofs;
   uint8_t* row_staged;
@@ -255,7 +255,7 @@ __global__ __launch_bounds__(PL_BS) void k_tile_plan(PlanArgs A) {
   if (t < T) {
     const int32_t i = A.csort[r0 + t];
     const int64_t ni = A.nrp[i + 1] - A.nrp[i];
-    const bool ok = A.elig[i] && ni >= 1 && ni <= 32;
+    const bool ok = A.elig[i] && ni >= 1 && ni <= 16;
     s_row[t] = ok ? i : -1;
     s_ma[t] = A.mrp[i];
     mlen = ok ? (int)(A.mrp[i + 1] - A.mrp[i]) : 0;
@@ -415,7 +415,10 @@ __global__ __launch_bounds__(PL_BS) void k_tile_plan(PlanArgs A) {
     int rank = 0;
     for (int t2 = 0; t2 < T; t2++)
       if (s_row[t2] >= 0 && s_key[t2] < my) rank++;
-    A.srows[r0 + rank] = s_row[t];
+    const int32_t i = s_row[t];
+    A.srows[r0 + rank] = i;
+    A.smeta[r0 + rank] = make_int4((int32_t)s_ma[t], mlen, (int32_t)A.nrp[i],
+                                   (int32_t)(A.nrp[i + 1] - A.nrp[i]));
     A.row_staged[s_row[t]] = 1;
     cls[my >> 60] = 1;
   }
@@ -446,124 +449,146 @@ __global__ void k_flag_to_i64(const uint8_t* a, int64_t* b, int64_t n) {
 // ---------------------------------------------------------------------------
 // the product
 // ---------------------------------------------------------------------------
-// LDS of one wave's window: 8 rows x TCH entries of M values, LDS offsets and
-// up to four map planes
-template <class TM>
-constexpr int tile_win_bytes() {
-  return 8 * TCH * (int)(sizeof(TM) + 4 + 4 * 4);
+// Sum of v over the aligned group of eight lanes, in a fixed tree
+// ((v0 + v1) + (v2 + v3)) + ((v4 + v5) + (v6 + v7)), left in every lane of the
+// group: exchanges with lane ^ 1 and lane ^ 2 inside quads, then with lane ^ 4
+// by row shifts of four (a lane with bit 2 clear takes lane + 4, one with it
+// set lane - 4), all on the DPP network.
+__device__ __forceinline__ int dpp_xor(int v, int m) {
+  if (m == 1) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad 1,0,3,2
+  if (m == 2) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad 2,3,0,1
+  const int up = __builtin_amdgcn_update_dpp(0, v, 0x104, 0xF, 0xF, false);      // row_shl:4
+  const int dn = __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);      // row_shr:4
+  return (threadIdx.x & 4) ? dn : up;
 }
 
-template <class T> struct TVec4;
-template <> struct TVec4<double> {
-  double v[4];
-  __device__ __forceinline__ void load(const double* p) {
-    const double2 a = *reinterpret_cast<const double2*>(p);
-    const double2 b = *reinterpret_cast<const double2*>(p + 2);
-    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
-  }
-};
-template <> struct TVec4<float> {
-  float v[4];
-  __device__ __forceinline__ void load(const float* p) {
-    const float4 a = *reinterpret_cast<const float4*>(p);
-    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-  }
-};
-
-// the wave's LDS writes are visible to its own reads (and the reverse)
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+__device__ __forceinline__ double dpp_xor(double v, int m) {
+  const int2 a = *reinterpret_cast<const int2*>(&v);
+  int2 b;
+  b.x = dpp_xor(a.x, m);
+  b.y = dpp_xor(a.y, m);
+  return *reinterpret_cast<const double*>(&b);
 }
 
-// One pack: up to eight rows (rows[0 .. cnt)) of one slots class, SPL slots
-// per lane.  The rows' M entries pass through the wave's window TCH at a
-// time; the loop runs to the pack's longest row, shorter rows padded with
-// empty entries.
-template <int SPL, class TM, class TX, class TY>
-__device__ __forceinline__ void tile_pack(const int32_t* rows, int cnt, const int64_t* mrp,
-                                          const TM* mval, const int32_t* lofs,
-                                          const uint32_t* nib, int64_t nnzm, const int64_t* nrp,
-                                          const TX* Zs, TY* Y, const double* D, double* rowdot,
-                                          unsigned char* win) {
-  const int lane = threadIdx.x & 63, g = lane >> 3, l = lane & 7;
-  TM* gm = reinterpret_cast<TM*>(win) + g * TCH;
-  int32_t* gl = reinterpret_cast<int32_t*>(win + 8 * TCH * sizeof(TM)) + g * TCH;
-  uint32_t* gw = reinterpret_cast<uint32_t*>(win + 8 * TCH * (sizeof(TM) + 4)) + g * TCH;
-  const bool valid = g < cnt;
-  const int32_t i = valid ? rows[g] : 0;
-  const int64_t na = valid ? nrp[i] : 0;
-  const int ni = valid ? (int)(nrp[i + 1] - na) : 0;
-  const int64_t ma = valid ? mrp[i] : 0;
-  const int len = valid ? (int)(mrp[i + 1] - ma) : 0;
-  const int wl = -wave_min_i32(-len);   // longest row of the pack (uniform)
-  TM acc[SPL];
-  double dv[SPL];
+__device__ __forceinline__ float dpp_xor(float v, int m) {
+  return __int_as_float(dpp_xor(__float_as_int(v), m));
+}
+
+template <class T>
+__device__ __forceinline__ T group8_sum(T v) {
+  v = v + dpp_xor(v, 1);
+  v = v + dpp_xor(v, 2);
+  v = v + dpp_xor(v, 4);
+  return v;
+}
+
+// One pack: up to eight rows of at most NS slots, eight lanes per row; lane
+// l takes the row's M entries l, l + 8, l + 16, l + 24 of each chunk of 32
+// and keeps one partial sum per slot over them (ascending); the eight
+// partials of a slot are then added in a fixed tree.  Everything a chunk
+// needs from device memory (row metadata, M values, LDS offsets, map words,
+// and D for the row's dot product) is loaded before any of it is used, and
+// the first pack's loads are issued before the workgroup waits for its
+// staged Z rows.
+constexpr int TK = 4;   // entries per lane per chunk (chunks of 8 * TK)
+
+template <int NS, class TM>
+struct PackRegs {
+  static constexpr int NP = NS / 8;
+  int4 meta;              // first M entry, M length, first pattern entry, slots
+  int32_t row;
+  bool valid;
+  TM m[TK];
+  int32_t lo[TK];
+  uint32_t w[TK][NP];
+  double d[NP];           // D of slots l, l + 8
+};
+
+template <int NS, class TM>
+__device__ __forceinline__ void pack_load_meta(PackRegs<NS, TM>& R, const int32_t* rows,
+                                               const int4* meta, int cnt) {
+  const int g = (threadIdx.x & 63) >> 3;
+  R.valid = g < cnt;
+  R.meta = R.valid ? meta[g] : make_int4(0, 0, 0, 0);
+  R.row = R.valid ? rows[g] : 0;
+}
+
+// chunk c0 (entries c0 .. c0 + 32) of the row's M entries, and D
+template <int NS, class TM>
+__device__ __forceinline__ void pack_load_chunk(PackRegs<NS, TM>& R, int c0, const StageArgs& A,
+                                                const TM* mval, const uint32_t* nib,
+                                                int64_t nstride, const double* D) {
+  constexpr int NP = NS / 8;
+  const int l = threadIdx.x & 7;
 #pragma unroll
-  for (int q = 0; q < SPL; q++) {
-    acc[q] = TM(0);
-    const int s = l + 8 * q;
-    dv[q] = (rowdot && s < ni) ? D[na + s] : 0.0;
+  for (int k = 0; k < TK; k++) {
+    const int t = c0 + 8 * k + l;
+    const bool v = t < R.meta.y;
+    const int64_t e = (int64_t)R.meta.x + t;
+    R.m[k] = v ? mval[e] : TM(0);
+    R.lo[k] = v ? A.lofs[e] : 0;
+#pragma unroll
+    for (int q = 0; q < NP; q++) R.w[k][q] = v ? nib[(int64_t)q * nstride + e] : 0xFFFFFFFFu;
   }
-  for (int c0 = 0; c0 < wl; c0 += TCH) {
-    const int cw = ((wl - c0 < TCH ? wl - c0 : TCH) + 3) & ~3;   // uniform
-    for (int u = l; u < cw; u += 8) {
-      const bool v = c0 + u < len;
-      const int64_t e = ma + c0 + u;
-      gm[u] = v ? mval[e] : TM(0);
-      gl[u] = v ? lofs[e] : 0;
+  if (c0 == 0) {
 #pragma unroll
-      for (int q = 0; q < SPL; q++)
-        gw[q * (8 * TCH) + u] = v ? nib[(int64_t)q * nnzm + e] : 0xFFFFFFFFu;
+    for (int q = 0; q < NP; q++) {
+      const int sl = l + 8 * q;
+      R.d[q] = (D && sl < R.meta.w) ? D[(int64_t)R.meta.z + sl] : 0.0;
     }
-    wave_sync();
-    for (int u0 = 0; u0 < cw; u0 += 4) {
-      TVec4<TM> m4;
-      m4.load(gm + u0);
-      const int4 l4 = *reinterpret_cast<const int4*>(gl + u0);
-      const int32_t lv[4] = {l4.x, l4.y, l4.z, l4.w};
-      uint32_t wv[SPL][4];
+  }
+}
+
+template <int NS, class TM, class TX, class TY>
+__device__ __forceinline__ void pack_compute(PackRegs<NS, TM>& R, const StageArgs& A,
+                                             const TM* mval, const uint32_t* nib,
+                                             int64_t nstride, const TX* Zs, TY* Y,
+                                             const double* D, double* rowdot) {
+  constexpr int NP = NS / 8;
+  const int l = threadIdx.x & 7;
+  const int wl = -wave_min_i32(-R.meta.y);   // longest row of the pack (uniform)
+  const int nis = -wave_min_i32(-R.meta.w);  // most slots in the pack (uniform)
+  TM acc[NS];
 #pragma unroll
-      for (int q = 0; q < SPL; q++) {
-        const uint4 w4 = *reinterpret_cast<const uint4*>(gw + q * (8 * TCH) + u0);
-        wv[q][0] = w4.x;
-        wv[q][1] = w4.y;
-        wv[q][2] = w4.z;
-        wv[q][3] = w4.w;
-      }
+  for (int s = 0; s < NS; s++) acc[s] = TM(0);
+  for (int c0 = 0; c0 < wl; c0 += 8 * TK) {
+    if (c0) pack_load_chunk<NS, TM>(R, c0, A, mval, nib, nstride, D);
 #pragma unroll
-      for (int u = 0; u < 4; u++) {
+    for (int k = 0; k < TK; k++) {
+      if (c0 + 8 * k < wl) {
 #pragma unroll
-        for (int q = 0; q < SPL; q++) {
-          const uint32_t f = (wv[q][u] >> (4 * l)) & 0xFu;
-          const bool hit = f != 0xFu;
-          const TX xl = Zs[hit ? lv[u] + l + 8 * q + (int)f : 0];
-          acc[q] = fma(m4.v[u], (TM)(hit ? xl : TX(0)), acc[q]);
+        for (int s = 0; s < NS; s++) {
+          if (s < nis) {
+            const uint32_t f = (R.w[k][s >> 3] >> (4 * (s & 7))) & 0xFu;
+            const bool hit = f != 0xFu;
+            const TX xl = Zs[hit ? R.lo[k] + s + (int)f : 0];
+            acc[s] = fma(R.m[k], (TM)(hit ? xl : TX(0)), acc[s]);
+          }
         }
       }
     }
-    wave_sync();
   }
-  if (!valid) return;
 #pragma unroll
-  for (int q = 0; q < SPL; q++) {
-    const int s = l + 8 * q;
-    if (s < ni) Y[na + s] = (TY)acc[q];
+  for (int s = 0; s < NS; s++)
+    if (s < nis) acc[s] = group8_sum(acc[s]);
+  // lane l writes slots l, l + 8 (every lane of the group holds every sum)
+  double pr = 0.0;
+#pragma unroll
+  for (int q = 0; q < NP; q++) {
+    const int sl = l + 8 * q;
+    TM a = acc[0];
+#pragma unroll
+    for (int u = 1; u < NS; u++)
+      if (u == sl) a = acc[u];
+    if (R.valid && sl < R.meta.w) {
+      Y[(int64_t)R.meta.z + sl] = (TY)a;
+      pr = pr + R.d[q] * (double)a;
+    }
   }
   if (rowdot) {
-    // <D, Y> of the row, summed in slot order by the row's first lane
-    double pr[SPL];
-#pragma unroll
-    for (int q = 0; q < SPL; q++) pr[q] = (l + 8 * q < ni) ? dv[q] * (double)acc[q] : 0.0;
-    double sum = 0.0;
-#pragma unroll
-    for (int q = 0; q < SPL; q++)
-      for (int u = 0; u < 8; u++) {
-        const double v = __shfl(pr[q], (lane & ~7) | u, 64);
-        if (8 * q + u < ni) sum = sum + v;
-      }
-    if (l == 0) rowdot[i] = sum;
+    // <D, Y> of the row: per lane over its slots, then the fixed tree
+    pr = group8_sum(pr);
+    if (R.valid && l == 0) rowdot[R.row] = pr;
   }
 }
 
@@ -577,10 +602,24 @@ __global__ __launch_bounds__(64 * TILE_WAVES) void k_spmm_tile(StageArgs A, cons
   extern __shared__ __align__(16) unsigned char smem[];
   const int64_t st = xcd_block(blockIdx.x, gridDim.x);
   const int32_t* ti = A.tinfo + st * TINFO;
-  const int32_t row0 = ti[0], n1 = ti[1], n2 = ti[2], n4 = ti[3], run0 = ti[4], nrun = ti[5];
+  const int32_t row0 = ti[0], n1 = ti[1], n2 = ti[2], run0 = ti[4], nrun = ti[5];
   TX* Zs = reinterpret_cast<TX*>(smem);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  unsigned char* win = smem + A.zbytes + wv * tile_win_bytes<TM>();
+  const int p1 = (n1 + 7) >> 3, p2 = (n2 + 7) >> 3;
+  const int32_t* rows = A.srows + row0;
+  const int4* meta = A.smeta + row0;
+  // the wave's first pack: its loads go out before the staging wait
+  PackRegs<8, TM> R8;
+  PackRegs<16, TM> R16;
+  int p = wv;
+  if (p < p1) {
+    pack_load_meta<8, TM>(R8, rows + 8 * p, meta + 8 * p, n1 - 8 * p);
+    pack_load_chunk<8, TM>(R8, 0, A, mval, nib, nnzm, D);
+  } else if (p < p1 + p2) {
+    const int a = n1 + 8 * (p - p1);
+    pack_load_meta<16, TM>(R16, rows + a, meta + a, n1 + n2 - a);
+    pack_load_chunk<16, TM>(R16, 0, A, mval, nib, nnzm, D);
+  }
   // the tile's Z rows: each wave copies whole runs, lanes along the run
   for (int q = wv; q < nrun; q += TILE_WAVES) {
     const TX* src = X + A.rg[run0 + q];
@@ -597,21 +636,20 @@ __global__ __launch_bounds__(64 * TILE_WAVES) void k_spmm_tile(StageArgs A, cons
     for (; v < len; v += 64) dst[v] = src[v];
   }
   __syncthreads();
-  const int p1 = (n1 + 7) >> 3, p2 = (n2 + 7) >> 3, p4 = (n4 + 7) >> 3;
-  const int32_t* rows = A.srows + row0;
-  for (int p = wv; p < p1 + p2 + p4; p += TILE_WAVES) {
+  for (; p < p1 + p2; p += TILE_WAVES) {
     if (p < p1) {
-      const int a = 8 * p;
-      tile_pack<1>(rows + a, n1 - a < 8 ? n1 - a : 8, mrp, mval, A.lofs, nib, nnzm, nrp, Zs, Y, D,
-                   rowdot, win);
-    } else if (p < p1 + p2) {
-      const int a = 8 * (p - p1);
-      tile_pack<2>(rows + n1 + a, n2 - a < 8 ? n2 - a : 8, mrp, mval, A.lofs, nib, nnzm, nrp, Zs,
-                   Y, D, rowdot, win);
+      if (p != wv) {
+        pack_load_meta<8, TM>(R8, rows + 8 * p, meta + 8 * p, n1 - 8 * p);
+        pack_load_chunk<8, TM>(R8, 0, A, mval, nib, nnzm, D);
+      }
+      pack_compute<8, TM, TX, TY>(R8, A, mval, nib, nnzm, Zs, Y, D, rowdot);
     } else {
-      const int a = 8 * (p - p1 - p2);
-      tile_pack<4>(rows + n1 + n2 + a, n4 - a < 8 ? n4 - a : 8, mrp, mval, A.lofs, nib, nnzm, nrp,
-                   Zs, Y, D, rowdot, win);
+      const int a = n1 + 8 * (p - p1);
+      if (p != wv) {
+        pack_load_meta<16, TM>(R16, rows + a, meta + a, n1 + n2 - a);
+        pack_load_chunk<16, TM>(R16, 0, A, mval, nib, nnzm, D);
+      }
+      pack_compute<16, TM, TX, TY>(R16, A, mval, nib, nnzm, Zs, Y, D, rowdot);
     }
   }
 }
@@ -624,6 +662,7 @@ void stage_plan(EminWork& w, const Csr& M, const int64_t* nrp, const uint8_t* el
   P = StagePlan{};
   const int64_t n = w.n;
   if (n == 0 || w.nnz == 0 || M.nnz == 0) return;
+  if (M.nnz >= INT32_MAX || w.nnz >= INT32_MAX) return;   // (32-bit offsets in the plan)
   if (xyz && (dim < 1 || dim > 3)) throw Error(EMIN_ERR_ARG, "tile plan: dimension");
   const TileDims D;
   static_assert(TileDims{}.tmax <= PL_BS, "one row per plan thread");
@@ -680,6 +719,7 @@ void stage_plan(EminWork& w, const Csr& M, const int64_t* nrp, const uint8_t* el
   if (nt == 0 || tot_runs >= INT32_MAX) return;
   int32_t* tinfo = ar.alloc<int32_t>((size_t)nt * TINFO);
   int32_t* srows = ar.alloc<int32_t>(n);
+  int4* smeta = ar.alloc<int4>(n);
   int32_t* rg = ar.alloc<int32_t>(tot_runs);
   int32_t* rl = ar.alloc<int32_t>(tot_runs);
   int32_t* rn = ar.alloc<int32_t>(tot_runs);
@@ -690,6 +730,7 @@ void stage_plan(EminWork& w, const Csr& M, const int64_t* nrp, const uint8_t* el
   A.roff = nrun;
   A.tinfo = tinfo;
   A.srows = srows;
+  A.smeta = smeta;
   A.rg = rg;
   A.rl = rl;
   A.rn = rn;
@@ -700,6 +741,7 @@ void stage_plan(EminWork& w, const Csr& M, const int64_t* nrp, const uint8_t* el
   P.ntile = nt;
   P.tinfo = tinfo;
   P.srows = srows;
+  P.smeta = smeta;
   P.rg = rg;
   P.rl = rl;
   P.rn = rn;
@@ -720,21 +762,23 @@ void spmm_stage(const EminWork& w, const int64_t* mrp, const TM* mval, const int
   StageArgs A;
   A.tinfo = P.tinfo;
   A.srows = P.srows;
+  A.smeta = P.smeta;
   A.rg = P.rg;
   A.rl = P.rl;
   A.rn = P.rn;
   A.lofs = P.lofs;
   A.zbytes = (int32_t)(((size_t)P.vmax * sizeof(TX) + 15) & ~size_t(15));
-  const size_t lds = (size_t)A.zbytes + (size_t)TILE_WAVES * tile_win_bytes<TM>();
+
+  const size_t lds = (size_t)A.zbytes;
   allow_lds((const void*)k_spmm_tile<TM, TX, TY>);
   if (e0 || e1) {
     hipExtLaunchKernelGGL(k_spmm_tile<TM, TX, TY>, dim3((unsigned)P.ntile), dim3(64 * TILE_WAVES),
                           lds, s, e0, e1, 0, A, mrp, mval, (const uint32_t*)w.nib, w.nnzm, nrp, X,
-                          Y, Dv, w.rowdot);
+                          Y, Dv, Dv ? w.rowdot : nullptr);
     HIP_OK(hipGetLastError());
   } else {
     k_spmm_tile<TM, TX, TY><<<(unsigned)P.ntile, 64 * TILE_WAVES, lds, s>>>(
-        A, mrp, mval, w.nib, w.nnzm, nrp, X, Y, Dv, w.rowdot);
+        A, mrp, mval, w.nib, w.nnzm, nrp, X, Y, Dv, Dv ? w.rowdot : nullptr);
   }
 }
 

@@ -104,28 +104,38 @@ STAGE_CASES = {
 @pytest.mark.parametrize("case", list(STAGE_CASES))
 def test_staged_product_equals_gathering_product(case, mixed):
     """The tiled masked product (rows grouped by coordinate cells, each
-    tile's Z rows staged in LDS) and the one that gathers every row from
-    device memory compute the same sums in the same order: P, the CG traces
-    and RAP are bitwise equal, in FP64 and in mixed precision, and the tiled
-    kernel is in use."""
+    tile's Z rows staged in LDS, partial sums over every eighth M entry added
+    in a fixed tree) and the one that gathers every row from device memory
+    compute the same sums in two fixed orders: in FP64 the tiled level
+    matches the oracle to 1e-10 and the gathering one to 1e-13 (rounding
+    only), two tiled builds are bitwise equal, and the tiled kernel is in
+    use; in mixed precision the two agree to the FP32 accumulation's 1e-5."""
     s, kw = STAGE_CASES[case]()
     say(f"[gpu] staged vs gathering product {case} mixed={mixed}: dofs={s.dofs}")
     from paper_1607_02489_amd import emin as E
     d = E.DeviceSystem.upload(s)
     a = gpu_level(s, iters=5, mixed=mixed, dsys=d, staged=True, **kw)
+    a2 = gpu_level(s, iters=5, mixed=mixed, dsys=d, staged=True, **kw)
     b = gpu_level(s, iters=5, mixed=mixed, dsys=d, **kw)
     assert a["sizes"]["sched_v"] & 64 and not b["sizes"]["sched_v"] & 64
+    tol = 1e-5 if mixed else 1e-13
     for k in ("Pv", "Pp", "Ac", "Bc"):
-        assert np.array_equal(a[k].val, b[k].val), k
+        assert np.array_equal(a[k].val, a2[k].val), k
+        assert np.array_equal(a[k].col, b[k].col), k
+        assert relfro(a[k].val, b[k].val) <= tol, k
+        assert rowmax_err(a[k], b[k]) <= 100 * tol, k
     for k in ("energy_v", "energy_p", "rho_v", "rho_p"):
-        assert np.array_equal(a[k], b[k]), k
+        assert np.array_equal(a[k], a2[k]), k
+        assert relfro(a[k], b[k]) <= tol, k
+    if not mixed:
+        compare_level(a, O.level(s, iters=5, **kw))
 
 
 def test_tiled_product_cfg3_level0_bitwise():
     """3-D Stokes 48^3 (2,855,668 dofs), level 0: the tiled masked product
     (rows grouped by coordinate cells, Z rows staged in LDS) and the gathering
-    one give bitwise equal P, CG traces and RAP at full size, with the tiled
-    kernel in use for both blocks."""
+    one give P, CG traces and RAP equal to rounding (1e-13) at full size, with
+    the tiled kernel in use for both blocks."""
     from paper_1607_02489_amd import emin as E
     s = synth.stokes3d(48)
     say(f"[gpu] tiled vs gathering product, 3-D Stokes 48^3: dofs={s.dofs}")
@@ -135,9 +145,11 @@ def test_tiled_product_cfg3_level0_bitwise():
     b = gpu_level(s, iters=5, dsys=d, **kw)
     assert a["sizes"]["sched_v"] & 64 and a["sizes"]["sched_p"] & 64
     for k in ("Pv", "Pp", "Ac", "Bc"):
-        assert np.array_equal(a[k].val, b[k].val), k
+        assert np.array_equal(a[k].col, b[k].col), k
+        assert relfro(a[k].val, b[k].val) <= 1e-13, k
+        assert rowmax_err(a[k], b[k]) <= 1e-11, k
     for k in ("energy_v", "energy_p", "rho_v", "rho_p"):
-        assert np.array_equal(a[k], b[k]), k
+        assert relfro(a[k], b[k]) <= 1e-13, k
 
 
 @pytest.mark.parametrize("case", ["oseen2d_16_uniform", "oseen2d_40_jitter", "oseen3d_6"])
