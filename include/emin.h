@@ -54,7 +54,8 @@ typedef enum {
   EMIN_ERR_DEVICE = 8,      /* HIP runtime error */
   EMIN_ERR_OOM = 9,         /* device allocation failed */
   EMIN_ERR_CAPACITY = 10,   /* a fixed per-row/per-ball capacity was exceeded */
-  EMIN_ERR_COLOCATE = 11    /* a coarse pressure without a co-located coarse velocity */
+  EMIN_ERR_COLOCATE = 11,   /* a coarse pressure without a co-located coarse velocity */
+  EMIN_ERR_CANCELLED = 12   /* a served request cancelled before it started */
 } emin_status;
 
 enum { EMIN_PREC_F64 = 0, EMIN_PREC_MIXED = 1 };
@@ -206,12 +207,32 @@ typedef struct {
 
 typedef struct emin_pattern_s emin_pattern_t;
 
+/* Device memory supplied by the caller (e.g. a framework's caching
+ * allocator).  alloc(bytes, ctx) returns device memory of the current device,
+ * at least 256-byte aligned, or NULL; free(ptr, ctx) takes back a block alloc
+ * returned.  Both are called from the thread that calls the library. */
+typedef struct {
+  void *(*alloc)(size_t bytes, void *ctx);
+  void (*free)(void *ptr, void *ctx);
+  void *ctx;
+} emin_allocator_t;
+
 /* Alg. 2 up to the patterns, plus the symbolic RAP and the coarse
  * descriptors (coordinates by injection, co-location map).  Borrows sys for
  * the call; the handle owns its device memory (hipMalloc) until destroyed.
  * Errors: ARG/SHAPE/PATTERN on bad inputs, CAPACITY, COLOCATE, DEVICE, OOM. */
 emin_status emin_pattern(const emin_system_t *sys, const emin_params_t *prm, void *stream,
                          emin_pattern_t **out);
+/* emin_pattern with every device block of the handle (the pattern phase's
+ * arrays, the EMIN workspace, the RAP plans) taken from *alloc and given
+ * back through it by emin_pattern_destroy (or when the call fails, after the
+ * stream has drained).  alloc = NULL: the library's own memory, as
+ * emin_pattern.  A block that is not 256-byte aligned is given back and the
+ * call fails with EMIN_ERR_ARG; alloc returning NULL fails it with
+ * EMIN_ERR_OOM.  The allocator must outlive the handle. */
+emin_status emin_pattern_alloc(const emin_system_t *sys, const emin_params_t *prm,
+                               const emin_allocator_t *alloc, void *stream,
+                               emin_pattern_t **out);
 
 /* emin_pattern with the coarse pressures C^(p) given instead of chosen by
  * Alg. 3 and the extra distance-3 pass (sec. 4.1): cp holds ncp ascending,
@@ -403,6 +424,11 @@ emin_status emin_server_poll(emin_server_t *srv, int64_t ticket, int32_t *done);
  * submit to start, run_ms = start to completion (host clock). */
 emin_status emin_server_wait(emin_server_t *srv, int64_t ticket, emin_hierarchy_t **result,
                              double *queue_ms, double *run_ms);
+/* Cancels a request that has not started: it leaves the queue, never runs,
+ * and its ticket completes with EMIN_ERR_CANCELLED (wait returns it; release
+ * frees the ticket).  *cancelled = 1 then, 0 for a request already running
+ * or done (unchanged).  Unknown ticket: EMIN_ERR_ARG. */
+emin_status emin_server_cancel(emin_server_t *srv, int64_t ticket, int32_t *cancelled);
 emin_status emin_server_release(emin_server_t *srv, int64_t ticket);
 emin_status emin_server_stats(emin_server_t *srv, int64_t *in_use, int32_t *queued,
                               int32_t *running);

@@ -676,6 +676,31 @@ emin_status emin_pattern(const emin_system_t* sys, const emin_params_t* prm, voi
   return EMIN_OK;
 }
 
+emin_status emin_pattern_alloc(const emin_system_t* sys, const emin_params_t* prm,
+                               const emin_allocator_t* alloc, void* stream, emin_pattern_t** out) {
+  if (!out) return EMIN_ERR_ARG;
+  *out = nullptr;
+  emin_pattern_t* h = nullptr;
+  emin_status st = guarded([&] {
+    check_system(sys);
+    check_params(prm);
+    h = new emin_pattern_s();
+    if (alloc) h->ar.use_allocator(*alloc);
+    build_pattern(h, sys, prm, as_stream(stream));
+  });
+  if (st != EMIN_OK) {
+    if (h) {
+      // the queued work that uses the handle's blocks ends before they go back
+      (void)hipStreamSynchronize(as_stream(stream));
+      delete h;
+    }
+    return st;
+  }
+  set_last_error("");
+  *out = h;
+  return EMIN_OK;
+}
+
 emin_status emin_pattern_with_cpoints(const emin_system_t* sys, const emin_params_t* prm,
                                       const int32_t* cp, int64_t ncp, void* stream,
                                       emin_pattern_t** out) {
@@ -760,6 +785,9 @@ emin_status emin_autotune_reset(void) {
 emin_status emin_pattern_info(const emin_pattern_t* h, emin_sizes_t* out) {
   if (!h || !out) return EMIN_ERR_ARG;
   *out = h->sizes;
+  // the handle keeps allocating after the pattern phase (FP32 RAP copies,
+  // GMRES workspace): report what it holds now
+  out->device_bytes = (int64_t)h->ar.bytes();
   return EMIN_OK;
 }
 
@@ -874,6 +902,7 @@ const char* emin_status_string(emin_status s) {
     case EMIN_ERR_OOM: return "ERR_OOM";
     case EMIN_ERR_CAPACITY: return "ERR_CAPACITY";
     case EMIN_ERR_COLOCATE: return "ERR_COLOCATE";
+    case EMIN_ERR_CANCELLED: return "ERR_CANCELLED";
   }
   return "UNKNOWN";
 }

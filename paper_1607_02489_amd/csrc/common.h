@@ -60,6 +60,14 @@ class Arena {
   Arena(const Arena&) = delete;
   Arena& operator=(const Arena&) = delete;
   ~Arena() { release(); }
+  // chunks from a caller's allocator instead of the library's cache (set
+  // before the first allocation)
+  void use_allocator(const emin_allocator_t& a) {
+    if (!chunks_.empty() || fixed_) throw Error(EMIN_ERR_ARG, "allocator set after allocation");
+    if (!a.alloc || !a.free) throw Error(EMIN_ERR_ARG, "allocator without alloc or free");
+    al_ = a;
+    has_al_ = true;
+  }
   // bump allocation from 64 MiB chunks (few allocations per handle)
   template <class T>
   T* alloc(size_t n) {
@@ -68,8 +76,12 @@ class Arena {
     if (b > left_ && fixed_) throw Error(EMIN_ERR_CAPACITY, "scratch buffer capacity exceeded");
     if (b > left_) {
       const size_t chunk = b > kChunk ? b : kChunk;
-      void* p = chunk_get(chunk);
+      void* p = has_al_ ? al_.alloc(chunk, al_.ctx) : chunk_get(chunk);
       if (!p) throw Error(EMIN_ERR_OOM, "device allocation failed");
+      if (has_al_ && (reinterpret_cast<uintptr_t>(p) & 255)) {
+        al_.free(p, al_.ctx);
+        throw Error(EMIN_ERR_ARG, "allocator returned memory not 256-byte aligned");
+      }
       chunks_.push_back({p, chunk});
       bytes_ += chunk;
       cur_ = static_cast<char*>(p);
@@ -83,7 +95,10 @@ class Arena {
   // the caller guarantees that no queued work still uses the memory
   void release() {
     if (fixed_) return;
-    for (auto& c : chunks_) chunk_put(c.first, c.second);
+    for (auto& c : chunks_) {
+      if (has_al_) al_.free(c.first, al_.ctx);
+      else chunk_put(c.first, c.second);
+    }
     chunks_.clear();
     bytes_ = 0;
     cur_ = nullptr;
@@ -94,6 +109,8 @@ class Arena {
  private:
   static constexpr size_t kChunk = size_t(64) << 20;
   bool fixed_ = false;
+  bool has_al_ = false;
+  emin_allocator_t al_{};
   std::vector<std::pair<void*, size_t>> chunks_;
   size_t bytes_ = 0;
   char* cur_ = nullptr;

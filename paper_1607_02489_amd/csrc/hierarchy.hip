@@ -180,7 +180,10 @@ emin_status emin_hierarchy_level(const emin_hierarchy_t* h, int32_t level, emin_
 int64_t emin_hierarchy_device_bytes(const emin_hierarchy_t* h) {
   if (!h) return 0;
   int64_t b = (int64_t)h->ar.bytes();
-  for (const emin_sizes_t& z : h->sizes) b += z.device_bytes;
+  for (const emin_pattern_t* p : h->pats) {
+    emin_sizes_t z;
+    if (emin_pattern_info(p, &z) == EMIN_OK) b += z.device_bytes;
+  }
   return b;
 }
 

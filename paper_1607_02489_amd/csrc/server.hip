@@ -29,13 +29,18 @@ struct Request {
   emin_hierarchy_t* result = nullptr;
   emin_status status = EMIN_OK;
   bool done = false;
+  bool started = false;
 };
 
 // device bytes one request is expected to hold: pattern handles, workspace
 // and coarse values scale with the input's nonzeros (measured ratio with
-// headroom), plus one arena chunk per level
-int64_t estimate_bytes(const emin_system_t& s, int32_t nlevels) {
-  const int64_t nz = s.Ahat.nnz + s.Bdiv.nnz;
+// headroom), plus one arena chunk per level; the A^T A energy operator of
+// the velocity block (EMIN_FLAG_ENERGY_ATA) has about three times the
+// nonzeros of the symmetric one in 2-D and more in 3-D, so the velocity
+// block's share is scaled by the operator's expected fill
+int64_t estimate_bytes(const emin_system_t& s, const emin_params_t& prm, int32_t nlevels) {
+  const int64_t fill = (prm.flags & EMIN_FLAG_ENERGY_ATA) ? (s.dim == 3 ? 6 : 3) : 1;
+  const int64_t nz = fill * s.Ahat.nnz + s.Bdiv.nnz;
   return 64 * nz + 256 * (s.Ahat.nrows + s.Bdiv.nrows) + (int64_t)(nlevels + 1) * (64ll << 20);
 }
 
@@ -66,6 +71,7 @@ struct emin_server_s {
         if (stop) break;
         r = queue.front();
         queue.pop_front();
+        r->started = true;
         in_use += r->estimate;
         r->held = r->estimate;
         running++;
@@ -112,7 +118,7 @@ emin_status emin_server_submit(emin_server_t* srv, const emin_system_t* sys,
   r->prm = *prm;
   r->nlevels = nlevels;
   r->min_dofs = min_dofs;
-  r->estimate = estimate_bytes(*sys, nlevels);
+  r->estimate = estimate_bytes(*sys, *prm, nlevels);
   r->t_submit = Clock::now();
   {
     std::lock_guard<std::mutex> lk(srv->mu);
@@ -151,6 +157,34 @@ emin_status emin_server_wait(emin_server_t* srv, int64_t ticket, emin_hierarchy_
   if (queue_ms) *queue_ms = ms(r->t_start - r->t_submit).count();
   if (run_ms) *run_ms = ms(r->t_done - r->t_start).count();
   return r->status;
+}
+
+emin_status emin_server_cancel(emin_server_t* srv, int64_t ticket, int32_t* cancelled) {
+  if (!srv) return EMIN_ERR_ARG;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->reqs.find(ticket);
+    if (it == srv->reqs.end()) return EMIN_ERR_ARG;
+    Request* r = it->second;
+    bool hit = false;
+    if (!r->started) {
+      for (auto q = srv->queue.begin(); q != srv->queue.end(); ++q)
+        if (*q == r) {
+          srv->queue.erase(q);
+          hit = true;
+          break;
+        }
+    }
+    if (hit) {
+      r->status = EMIN_ERR_CANCELLED;
+      r->t_start = r->t_done = Clock::now();
+      r->done = true;
+    }
+    if (cancelled) *cancelled = hit ? 1 : 0;
+  }
+  srv->cv_done.notify_all();
+  srv->cv_work.notify_all();   // the next queued request may fit now
+  return EMIN_OK;
 }
 
 emin_status emin_server_release(emin_server_t* srv, int64_t ticket) {

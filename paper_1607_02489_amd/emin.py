@@ -23,15 +23,16 @@ MAX_ITERS = 32
 (VIEW_PV, VIEW_PP, VIEW_AC, VIEW_BC, VIEW_MV, VIEW_MP, VIEW_S, VIEW_ORDER, VIEW_CP, VIEW_CBAR,
  VIEW_CV, VIEW_XVC, VIEW_P2VC, VIEW_KEEPV, VIEW_KEEPP, VIEW_DIR) = range(16)
 STATUS = ["OK", "ERR_ARG", "ERR_SHAPE", "ERR_PATTERN", "ERR_VALUE", "ERR_INFEASIBLE",
-          "ERR_BREAKDOWN", "ERR_BUDGET", "ERR_DEVICE", "ERR_OOM", "ERR_CAPACITY", "ERR_COLOCATE"]
-SYMBOLS = ["emin_pattern", "emin_pattern_info", "emin_pattern_view", "emin_setup", "emin_rap",
+          "ERR_BREAKDOWN", "ERR_BUDGET", "ERR_DEVICE", "ERR_OOM", "ERR_CAPACITY", "ERR_COLOCATE",
+          "ERR_CANCELLED"]
+SYMBOLS = ["emin_pattern", "emin_pattern_alloc", "emin_pattern_info", "emin_pattern_view", "emin_setup", "emin_rap",
            "emin_sync_report", "emin_memcpy_d2h", "emin_pattern_destroy", "emin_status_string",
            "emin_version", "emin_last_error", "emin_fp_probe", "emin_release_cached", "emin_profile_enable", "emin_profile_collect",
            "emin_hierarchy_build", "emin_hierarchy_resetup", "emin_hierarchy_info",
            "emin_hierarchy_level", "emin_hierarchy_device_bytes", "emin_hierarchy_destroy",
            "emin_hierarchy_build_batch", "emin_batch_create", "emin_batch_run",
            "emin_batch_destroy", "emin_server_create", "emin_server_submit", "emin_server_poll",
-           "emin_server_wait", "emin_server_release", "emin_server_stats", "emin_server_destroy",
+           "emin_server_wait", "emin_server_cancel", "emin_server_release", "emin_server_stats", "emin_server_destroy",
            "emin_pattern_with_cpoints", "emin_setup_with_pattern", "emin_profile_launches",
            "emin_setup_pg", "emin_rap_pg", "emin_galerkin", "emin_matrix_view",
            "emin_matrix_destroy", "emin_infsup"]
@@ -117,6 +118,8 @@ def lib():
         L.emin_pattern.argtypes = [P(c_system), P(c_params), C.c_void_p, P(C.c_void_p)]
         L.emin_pattern_with_cpoints.argtypes = [P(c_system), P(c_params), C.c_void_p, C.c_int64,
                                                 C.c_void_p, P(C.c_void_p)]
+        L.emin_pattern_alloc.argtypes = [P(c_system), P(c_params), P(c_allocator), C.c_void_p,
+                                         P(C.c_void_p)]
         L.emin_setup_with_pattern.argtypes = [P(c_csr), C.c_void_p, C.c_void_p, C.c_int64,
                                               C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                               C.c_int32, C.c_int32, C.c_uint32, C.c_void_p,
@@ -167,6 +170,7 @@ def lib():
         L.emin_server_wait.argtypes = [C.c_void_p, C.c_int64, P(C.c_void_p), P(C.c_double),
                                        P(C.c_double)]
         L.emin_server_release.argtypes = [C.c_void_p, C.c_int64]
+        L.emin_server_cancel.argtypes = [C.c_void_p, C.c_int64, P(C.c_int32)]
         L.emin_server_stats.argtypes = [C.c_void_p, P(C.c_int64), P(C.c_int32), P(C.c_int32)]
         L.emin_server_destroy.argtypes = [C.c_void_p]
         L.emin_server_destroy.restype = None
@@ -264,15 +268,58 @@ class DeviceSystem:
         return c_system(self.dim, A, B, self.xv, self.p2v, None, None, self.Gt or None)
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class c_allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
+class Allocator:
+    """An emin_allocator_t over Python callables alloc(nbytes) -> int device
+    pointer (0 on failure) and free(ptr).  Keep it alive while any handle
+    built with it exists."""
+
+    def __init__(self, alloc, free):
+        def _a(n, _ctx):
+            try:
+                return int(alloc(int(n))) or None
+            except Exception:
+                return None
+
+        def _f(p, _ctx):
+            free(int(p))
+        self._a, self._f = ALLOC_FN(_a), FREE_FN(_f)
+        self.c = c_allocator(self._a, self._f, None)
+
+
+def torch_allocator(stream=None) -> Allocator:
+    """Device memory from torch's caching allocator (on the current device and
+    the given stream, default the current one)."""
+    import torch
+    dev = torch.cuda.current_device()
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    return Allocator(lambda n: torch.cuda.caching_allocator_alloc(n, dev, st),
+                     torch.cuda.caching_allocator_delete)
+
+
 class Pattern:
     """emin_pattern handle of one level (emin_pattern_with_cpoints when
-    cpoints, a device int32 tensor of ascending coarse pressures, is given)."""
+    cpoints, a device int32 tensor of ascending coarse pressures, is given;
+    emin_pattern_alloc when allocator, an Allocator, is given)."""
 
-    def __init__(self, dsys: DeviceSystem, prm: c_params, stream=None, cpoints=None):
+    def __init__(self, dsys: DeviceSystem, prm: c_params, stream=None, cpoints=None,
+                 allocator=None):
         self.dsys = dsys
         self._c = dsys.c()
+        self.allocator = allocator
         h = C.c_void_p()
-        if cpoints is None:
+        if allocator is not None:
+            _check(lib().emin_pattern_alloc(C.byref(self._c), C.byref(prm),
+                                            C.byref(allocator.c), _stream(stream), C.byref(h)),
+                   "emin_pattern_alloc")
+        elif cpoints is None:
             _check(lib().emin_pattern(C.byref(self._c), C.byref(prm), _stream(stream),
                                       C.byref(h)), "emin_pattern")
         else:
@@ -367,6 +414,11 @@ def setup_with_pattern(M_dev, N_dev, ncoarse, cid, W, Wc, iters, P, mixed=False,
                                          C.c_void_p(report.data_ptr()) if report is not None
                                          else None),
            "emin_setup_with_pattern_noalloc" if noalloc else "emin_setup_with_pattern")
+
+
+def release_cached() -> int:
+    """emin_release_cached: frees the library's cached device chunks (bytes)."""
+    return int(lib().emin_release_cached())
 
 
 def autotune_stats() -> dict:
@@ -646,6 +698,12 @@ class Server:
         _check(lib().emin_server_wait(self.s, ticket, C.byref(h), C.byref(q), C.byref(r)),
                "emin_server_wait")
         return HierarchyView(h), q.value, r.value
+
+    def cancel(self, ticket) -> bool:
+        """emin_server_cancel: True when the request left the queue unstarted."""
+        c = C.c_int32()
+        _check(lib().emin_server_cancel(self.s, ticket, C.byref(c)), "emin_server_cancel")
+        return bool(c.value)
 
     def release(self, ticket):
         _check(lib().emin_server_release(self.s, ticket), "emin_server_release")

@@ -136,6 +136,52 @@ def test_server_rejects_over_budget():
     srv.close()
 
 
+def test_server_cancel_queued_request():
+    """emin_server_cancel: with a budget that admits one request at a time, a
+    request queued behind an unreleased one is cancelled (wait reports
+    EMIN_ERR_CANCELLED), a finished one is not, and the queue moves on."""
+    import torch
+    from paper_1607_02489_amd import emin as E
+    d = E.DeviceSystem.upload(synth.make_system(2, 16))
+    prm = E.params(iters=5)
+    srv = E.Server(budget_bytes=300 << 20, slots=2)
+    a = srv.submit(d, prm, 2)
+    srv.wait(a)
+    b = srv.submit(d, prm, 2)          # cannot fit while a holds its memory
+    assert srv.stats()["queued"] == 1
+    assert srv.cancel(b) and not srv.cancel(a)
+    with pytest.raises(E.EminError) as ei:
+        srv.wait(b)
+    assert ei.value.status == 12                     # ERR_CANCELLED
+    srv.release(b)
+    srv.release(a)
+    c = srv.submit(d, prm, 2)
+    view, _, _ = srv.wait(c)
+    torch.cuda.synchronize()
+    srv.release(c)
+    assert srv.stats() == dict(in_use=0, queued=0, running=0)
+    srv.close()
+
+
+def test_device_bytes_cover_a_mixed_hierarchy():
+    """The device bytes a hierarchy reports (what the server admits against)
+    cover the device memory its mixed-precision build took, FP32 RAP copies
+    included."""
+    import torch
+    from paper_1607_02489_amd import emin as E
+    d = E.DeviceSystem.upload(synth.oseen2d(64))
+    torch.cuda.synchronize()
+    E.release_cached()
+    free0 = torch.cuda.mem_get_info()[0]
+    h = E.NativeHierarchy(d, E.params(iters=5, mixed=True), 4, min_dofs=200)
+    torch.cuda.synchronize()
+    used = free0 - torch.cuda.mem_get_info()[0]
+    rep = h.device_bytes()
+    say(f"[gpu] mixed hierarchy: reported {rep / 2**20:.1f} MiB, device delta {used / 2**20:.1f} MiB")
+    assert rep >= used - (8 << 20)      # (allocation granularity)
+    h.close()
+
+
 def test_autotuned_schedule_same_results_and_reuse():
     """Every candidate schedule of the masked product sums the same products
     in the same order, so the autotuned level equals the default one bitwise;
