@@ -435,6 +435,43 @@ emin_status emin_server_stats(emin_server_t *srv, int64_t *in_use, int32_t *queu
 void emin_server_destroy(emin_server_t *srv);
 
 /* ------------------------------------------------------------------------
+ * Solve phase (sec. 5.2, sec. 6): Braess-Sarazin relaxation, V-cycle, GMRES
+ * ------------------------------------------------------------------------ */
+typedef struct emin_solver_s emin_solver_t;
+
+/* Multigrid solver on a hierarchy built from sys (level 0's arrays are
+ * borrowed for the solver's lifetime; coarse operators and transfers are the
+ * hierarchy's, which must outlive the solver).  Vectors are x = (u, p), u
+ * component-blocked (dim blocks of n_v), p of n_p.  Each level gets the
+ * Braess-Sarazin relaxation of eq. (bs): D = diag(sum_j |a_ij|) of the scalar
+ * velocity block (sec. 5.2), the Schur complement S = B D^-1 B^T formed
+ * explicitly, gs_sweeps forward Gauss-Seidel sweeps on it from zero, and the
+ * relaxation parameter omega (sec. 6 uses 5 sweeps and 0.666).  The V-cycle
+ * runs nu steps before and after the coarse correction with R = P^T and
+ * coarse_steps steps on the coarsest level (the paper uses Vanka there; see
+ * the design notes).  Synchronous.  Errors: ARG, SHAPE, OOM, DEVICE. */
+emin_status emin_solver_create(const emin_system_t *sys, const emin_hierarchy_t *h, int32_t nu,
+                               double omega, int32_t gs_sweeps, int32_t coarse_steps,
+                               void *stream, emin_solver_t **out);
+/* Vector length of a level and the number of Gauss-Seidel dependency levels
+ * of its Schur complement (either may be NULL). */
+emin_status emin_solver_info(const emin_solver_t *s, int32_t level, int64_t *n,
+                             int32_t *gs_levels);
+/* One Braess-Sarazin step x <- x + [D/omega, B^T; B, 0]^-1 (f - K x) on a
+ * level (device vectors of that level's length); stream-ordered. */
+emin_status emin_solver_bs_step(emin_solver_t *s, int32_t level, double *x, const double *f,
+                                void *stream);
+/* x = V-cycle applied to f on level 0, from x = 0; stream-ordered. */
+emin_status emin_solver_vcycle(emin_solver_t *s, const double *f, double *x, void *stream);
+/* GMRES from x = 0 preconditioned on the right by the V-cycle, without
+ * restart, until the residual estimate is at most rtol ||f|| or maxit steps;
+ * *its and *relres (host) receive the steps taken and the final relative
+ * residual estimate.  Synchronous. */
+emin_status emin_solver_gmres(emin_solver_t *s, const double *f, double *x, double rtol,
+                              int32_t maxit, int32_t *its, double *relres, void *stream);
+void emin_solver_destroy(emin_solver_t *s);
+
+/* ------------------------------------------------------------------------
  * Inf-sup diagnostic (sec. 6.1, Table 3)
  * ------------------------------------------------------------------------ */
 typedef struct emin_matrix_s emin_matrix_t;

@@ -35,7 +35,8 @@ SYMBOLS = ["emin_pattern", "emin_pattern_alloc", "emin_pattern_info", "emin_patt
            "emin_server_wait", "emin_server_cancel", "emin_server_release", "emin_server_stats", "emin_server_destroy",
            "emin_pattern_with_cpoints", "emin_setup_with_pattern", "emin_profile_launches",
            "emin_setup_pg", "emin_rap_pg", "emin_galerkin", "emin_matrix_view",
-           "emin_matrix_destroy", "emin_infsup"]
+           "emin_matrix_destroy", "emin_infsup", "emin_solver_create", "emin_solver_info",
+           "emin_solver_bs_step", "emin_solver_vcycle", "emin_solver_gmres", "emin_solver_destroy"]
 PROF_KINDS = ["spmm", "update", "spgemm", "alg3", "alg4", "vpattern", "r6", "r7"]
 EMIN_PROF_ONLY = 1 << 30
 
@@ -181,6 +182,16 @@ def lib():
         L.emin_infsup.argtypes = [P(c_csr), P(c_csr), P(c_csr), C.c_int32, C.c_int32, C.c_double,
                                   P(C.c_double), P(C.c_double), P(C.c_int32), P(C.c_int32),
                                   C.c_void_p]
+        L.emin_solver_create.argtypes = [P(c_system), C.c_void_p, C.c_int32, C.c_double,
+                                         C.c_int32, C.c_int32, C.c_void_p, P(C.c_void_p)]
+        L.emin_solver_info.argtypes = [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_int32)]
+        L.emin_solver_bs_step.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                          C.c_void_p]
+        L.emin_solver_vcycle.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.emin_solver_gmres.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                        C.c_int32, P(C.c_int32), P(C.c_double), C.c_void_p]
+        L.emin_solver_destroy.argtypes = [C.c_void_p]
+        L.emin_solver_destroy.restype = None
         L.emin_profile_enable.argtypes = [C.c_int]
         L.emin_autotune_stats.argtypes = [P(C.c_int64)]
         L.emin_profile_collect.argtypes = [P(c_kstat), C.c_int32]
@@ -593,6 +604,19 @@ class HierarchyView:
                     Bc=d2h(bc.value, z["nnz_Bc"], np.float64), pattern=p.value,
                     report=rep.value)
 
+    def level_csr(self, level):
+        """Host CSR tuples (nrows, ncols, rowptr, col, val) of one transfer
+        level's Pv, Pp (transfers) and Ac, Bc (the next level's operators)."""
+        d = self.level_host(level)
+        p = C.c_void_p(d["pattern"])
+        out = {}
+        for key, what in (("Pv", VIEW_PV), ("Pp", VIEW_PP), ("Ac", VIEW_AC), ("Bc", VIEW_BC)):
+            v = c_view()
+            _check(lib().emin_pattern_view(p, what, C.byref(v)), "emin_pattern_view")
+            out[key] = (int(v.n), int(v.ncols), d2h(v.rowptr, v.n + 1, np.int64),
+                        d2h(v.col, v.nnz, np.int32), d[key])
+        return out
+
     def device_bytes(self) -> int:
         return int(lib().emin_hierarchy_device_bytes(self.h))
 
@@ -793,3 +817,52 @@ def infsup(B: DeviceMatrix, Mv: DeviceMatrix, Mp: DeviceMatrix, dim: int, steps:
     if resid:
         return sig.value, nz.value, st.value, res.value
     return sig.value, nz.value, st.value
+
+
+class Solver:
+    """emin_solver_*: Braess-Sarazin V-cycle and V-cycle-preconditioned GMRES
+    on a NativeHierarchy built from dsys (both must outlive the solver)."""
+
+    def __init__(self, dsys: DeviceSystem, hier, nu=2, omega=0.666, gs_sweeps=5,
+                 coarse_steps=10, stream=None):
+        self.dsys, self.hier = dsys, hier
+        self._c = dsys.c()
+        h = C.c_void_p()
+        _check(lib().emin_solver_create(C.byref(self._c), hier.h, nu, omega, gs_sweeps,
+                                        coarse_steps, _stream(stream), C.byref(h)),
+               "emin_solver_create")
+        self.h = h
+
+    def info(self, level=0):
+        n, g = C.c_int64(), C.c_int32()
+        _check(lib().emin_solver_info(self.h, level, C.byref(n), C.byref(g)), "emin_solver_info")
+        return n.value, g.value
+
+    def bs_step(self, level, x, f, stream=None):
+        _check(lib().emin_solver_bs_step(self.h, level, C.c_void_p(x.data_ptr()),
+                                         C.c_void_p(f.data_ptr()), _stream(stream)),
+               "emin_solver_bs_step")
+
+    def vcycle(self, f, x, stream=None):
+        _check(lib().emin_solver_vcycle(self.h, C.c_void_p(f.data_ptr()),
+                                        C.c_void_p(x.data_ptr()), _stream(stream)),
+               "emin_solver_vcycle")
+
+    def gmres(self, f, x, rtol=1e-6, maxit=200, stream=None):
+        its, rel = C.c_int32(), C.c_double()
+        _check(lib().emin_solver_gmres(self.h, C.c_void_p(f.data_ptr()), C.c_void_p(x.data_ptr()),
+                                       rtol, maxit, C.byref(its), C.byref(rel), _stream(stream)),
+               "emin_solver_gmres")
+        return its.value, rel.value
+
+    def close(self):
+        if self.h:
+            _sync()
+            lib().emin_solver_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
