@@ -6,7 +6,8 @@
 // distance-3 ball with an LDS hash set and appends the source to each row it
 // reaches.  Rows are sorted afterwards, so the atomic append order does not
 // show.  Extra C^(v) points (non-Dirichlet F nodes with no C^(v) within
-// distance 3) are taken in ascending order by a single workgroup.
+// distance 3, taken in ascending order) are found in parallel as the ordered
+// independent set described at k_vconf.
 #include "coarsen.h"
 #include "prof.h"
 
@@ -26,31 +27,24 @@ __device__ __forceinline__ uint32_t vhash(uint32_t x) {
   return x;
 }
 
-// one wave per source c: BFS to depth 3, mark covered, append c to the rows
-__global__ __launch_bounds__(64 * VB_WAVES) void k_vbfs(const int64_t* grp, const int32_t* gcol,
-                                                        const int32_t* srcs, int64_t nsrc,
-                                                        const uint8_t* dir, uint8_t* cov,
-                                                        int32_t* vcnt, int32_t* vbuf, int* err) {
-  __shared__ int32_t hash_all[VB_WAVES][VHASH];
-  __shared__ int32_t ball_all[VB_WAVES][VBALL];
-  __shared__ int nb_all[VB_WAVES];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t si = (int64_t)blockIdx.x * VB_WAVES + w;
-  if (si >= nsrc) return;
-  int32_t* hs = hash_all[w];
-  int32_t* ball = ball_all[w];
+// The distance-3 ball of c in the wave's LDS list ball[0..nb): breadth-first
+// over the graph with an LDS hash set of the visited vertices.  Returns the
+// list length; *bad is set when the hash set or the list overflows.
+__device__ int wave_ball3(const int64_t* grp, const int32_t* gcol, int32_t c, int32_t* hs,
+                          int32_t* ball, int* nb, int lane, bool* bad) {
   for (int t = lane; t < VHASH; t += 64) hs[t] = -1;
-  const int32_t c = srcs[si];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   if (lane == 0) {
     ball[0] = c;
     hs[vhash((uint32_t)c) & (VHASH - 1)] = c;
-    nb_all[w] = 1;
+    *nb = 1;
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   int ls = 0, le = 1;
-  bool bad = false;
   for (int L = 0; L < 3; L++) {
     for (int f = ls + lane; f < le; f += 64) {
       const int32_t v = ball[f];
@@ -62,13 +56,13 @@ __global__ __launch_bounds__(64 * VB_WAVES) void k_vbfs(const int64_t* grp, cons
         while (true) {
           const int32_t old = atomicCAS(&hs[h], -1, u);
           if (old == -1) {
-            const int p = atomicAdd(&nb_all[w], 1);
-            if (p < VBALL) ball[p] = u; else bad = true;
+            const int p = atomicAdd(nb, 1);
+            if (p < VBALL) ball[p] = u; else *bad = true;
             break;
           }
           if (old == u) break;
           h = (h + 1) & (VHASH - 1);
-          if (++probes >= VHASH / 2) { bad = true; break; }
+          if (++probes >= VHASH / 2) { *bad = true; break; }
         }
       }
     }
@@ -76,8 +70,29 @@ __global__ __launch_bounds__(64 * VB_WAVES) void k_vbfs(const int64_t* grp, cons
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     ls = le;
-    le = min(nb_all[w], VBALL);
+    le = min(*nb, VBALL);
   }
+  return le;
+}
+
+// one wave per source c: mark its distance-3 ball covered and append c to
+// the rows it reaches (sources srcs[0..nsrc), or [0..*dcount) when dcount
+// is given)
+__global__ __launch_bounds__(64 * VB_WAVES) void k_vbfs(const int64_t* grp, const int32_t* gcol,
+                                                        const int32_t* srcs, int64_t nsrc,
+                                                        const int64_t* dcount,
+                                                        const uint8_t* dir, uint8_t* cov,
+                                                        int32_t* vcnt, int32_t* vbuf, int* err) {
+  __shared__ int32_t hash_all[VB_WAVES][VHASH];
+  __shared__ int32_t ball_all[VB_WAVES][VBALL];
+  __shared__ int nb_all[VB_WAVES];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t si = (int64_t)blockIdx.x * VB_WAVES + w;
+  if (si >= nsrc || (dcount && si >= *dcount)) return;
+  int32_t* ball = ball_all[w];
+  const int32_t c = srcs[si];
+  bool bad = false;
+  const int le = wave_ball3(grp, gcol, c, hash_all[w], ball, &nb_all[w], lane, &bad);
   if (bad) atomicOr(err, DERR_CAPACITY);
   for (int t = lane; t < le; t += 64) {
     const int32_t v = ball[t];
@@ -90,109 +105,136 @@ __global__ __launch_bounds__(64 * VB_WAVES) void k_vbfs(const int64_t* grp, cons
   }
 }
 
-// Extra C^(v), ascending: the smallest non-Dirichlet, uncovered, non-C node
-// at or after the cursor is converted, then its distance-3 ball is covered.
-// Visited marks: with nwin > 0, a bitmap in LDS over the index window
-// j ± 3·bw of the ball (bw = the graph's index bandwidth), cleared per ball;
-// otherwise per-vertex stamps in global memory.
-__global__ __launch_bounds__(1024) void k_vextras(const int64_t* grp, const int32_t* gcol,
-                                                  int64_t n, const uint8_t* dir, uint8_t* cv,
-                                                  uint8_t* cov, int32_t* vis, int32_t* extra,
-                                                  int32_t* nextra, int ballcap, int deg_cap,
-                                                  int64_t bw, int nwin, int* err) {
-  extern __shared__ int32_t ball[];
-  uint32_t* win = reinterpret_cast<uint32_t*>(ball + ballcap);
-  __shared__ int found_sh, nb_sh, ne_sh, bad_sh;
+// Extra C^(v) (sec. 4.2): taken in ascending order, each one covering its
+// distance-3 ball, among the eligible vertices (not C, not Dirichlet, not
+// covered by the C^(v) balls).  Vertex j is taken exactly when no smaller
+// taken vertex has j in its ball: the set is the lexicographically first
+// maximal independent set of the eligible vertices under "e reaches j within
+// distance 3".  It is computed in parallel with the same result: each
+// eligible e lists the smaller eligible vertices whose balls hold it
+// (k_vconf, one wave per eligible source, which appends itself to the lists
+// of the larger eligible vertices in its ball), then k_lfmis decides the
+// vertices in rounds: one is taken once every vertex on its list is decided
+// out, and is out once one on its list is taken.  The smallest undecided
+// vertex is decided in every round, so the rounds end.
+
+// the ball of eligible source ei: append ei to the list of every larger
+// eligible vertex in it (count pass: cnt; fill pass: col at rp + cursor)
+template <bool FILL>
+__global__ __launch_bounds__(64 * VB_WAVES) void k_vconf(const int64_t* grp, const int32_t* gcol,
+                                                         const int32_t* elist, int64_t m,
+                                                         const int32_t* eid, int32_t* cnt,
+                                                         const int64_t* rp, int32_t* col,
+                                                         int* err) {
+  __shared__ int32_t hash_all[VB_WAVES][VHASH];
+  __shared__ int32_t ball_all[VB_WAVES][VBALL];
+  __shared__ int nb_all[VB_WAVES];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t ei = (int64_t)blockIdx.x * VB_WAVES + w;
+  if (ei >= m) return;
+  int32_t* ball = ball_all[w];
+  const int32_t c = elist[ei];
+  bool bad = false;
+  const int le = wave_ball3(grp, gcol, c, hash_all[w], ball, &nb_all[w], lane, &bad);
+  if (bad) atomicOr(err, DERR_CAPACITY);
+  for (int t = lane; t < le; t += 64) {
+    const int32_t v = ball[t];
+    const int32_t k = eid[v];
+    if (v <= c || k < 0) continue;
+    const int slot = atomicAdd(&cnt[k], 1);
+    // (a ball cut short by an overflow may differ between the passes; the
+    // overflow is reported, and the fill stays inside the counted room)
+    if (FILL && rp[k] + slot < rp[k + 1]) col[rp[k] + slot] = (int32_t)ei;
+  }
+}
+
+// Rounds of the ordered independent set over the conflict lists, one
+// workgroup; state 0 undecided, 1 taken, 2 out.  States live in LDS when
+// they fit (lds), else in global memory read and written with agent-scope
+// atomics.
+template <bool LDS>
+__global__ __launch_bounds__(1024) void k_lfmis(const int64_t* rp, const int32_t* col, int64_t m,
+                                                uint8_t* gstate, const int32_t* elist,
+                                                uint8_t* cv, int32_t* out_taken) {
+  extern __shared__ uint8_t sstate[];
+  __shared__ int pending_sh, taken_sh;
+  uint8_t* st = LDS ? sstate : gstate;
   const int tid = threadIdx.x;
-  if (tid == 0) { ne_sh = 0; bad_sh = 0; }
-  int64_t cursor = 0;
-  int32_t stamp = 0;
+  auto ld = [&](int64_t i) -> uint8_t {
+    if (LDS) return __hip_atomic_load(&st[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return __hip_atomic_load(&st[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  auto stv = [&](int64_t i, uint8_t v) {
+    if (LDS) __hip_atomic_store(&st[i], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    else __hip_atomic_store(&st[i], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  for (int64_t i = tid; i < m; i += 1024) stv(i, 0);
+  if (tid == 0) taken_sh = 0;
+  __syncthreads();
   while (true) {
-    if (tid == 0) found_sh = INT32_MAX;
+    if (tid == 0) pending_sh = 0;
     __syncthreads();
-    // eight flags per thread per pass (vertices before the cursor are never
-    // eligible again, so the pass may start at the aligned position below it)
-    for (int64_t base = cursor & ~(int64_t)7; base < n; base += 8 * 1024) {
-      const int64_t v0 = base + (int64_t)tid * 8;
-      int f = INT32_MAX;
-      if (v0 + 8 <= n) {
-        const uint64_t bad = *reinterpret_cast<const uint64_t*>(cv + v0) |
-                             *reinterpret_cast<const uint64_t*>(dir + v0) |
-                             *reinterpret_cast<const uint64_t*>(cov + v0);
-        for (int q = 0; q < 8; q++)
-          if (((bad >> (8 * q)) & 0xFFu) == 0u) { f = (int)(v0 + q); break; }
-      } else {
-        for (int64_t v = v0; v < n; v++)
-          if (!cv[v] && !dir[v] && !cov[v]) { f = (int)v; break; }
+    bool pend = false;
+    for (int64_t i = tid; i < m; i += 1024) {
+      if (ld(i) != 0) continue;
+      bool all_out = true, any_in = false;
+      for (int64_t t = rp[i]; t < rp[i + 1]; t++) {
+        const uint8_t s = ld(col[t]);
+        if (s == 1) { any_in = true; break; }
+        if (s == 0) all_out = false;
       }
-      if (f != INT32_MAX) atomicMin(&found_sh, f);
-      __syncthreads();
-      const int ff = found_sh;
-      __syncthreads();
-      if (ff != INT32_MAX) break;
+      if (any_in) stv(i, 2);
+      else if (all_out) stv(i, 1);
+      else pend = true;
     }
-    const int j = found_sh;
-    if (j == INT32_MAX) break;
-    const int64_t lo = (int64_t)j - 3 * bw > 0 ? (int64_t)j - 3 * bw : 0;
-    if (nwin) {
-      for (int t = tid; t < nwin; t += 1024) win[t] = 0u;
-      __syncthreads();
-    }
-    if (tid == 0) {
-      cv[j] = 1;
-      extra[ne_sh] = j;
-      ne_sh++;
-      ball[0] = j;
-      if (nwin) {
-        const int64_t o = j - lo;
-        win[o >> 5] |= 1u << (o & 31);
-      } else {
-        atomicMax(&vis[j], stamp);
-      }
-      nb_sh = 1;
-    }
+    if (pend) pending_sh = 1;
     __syncthreads();
-    int ls = 0, le = 1;
-    const int per = 1024 / deg_cap;
-    for (int L = 0; L < 3; L++) {
-      for (int base = ls; base < le; base += per) {
-        const int f = base + tid / deg_cap;
-        const int slot = tid % deg_cap;
-        if (f < le) {
-          const int32_t v = ball[f];
-          for (int64_t e = grp[v] + slot; e < grp[v + 1]; e += deg_cap) {
-            const int32_t u = gcol[e];
-            if (u == v) continue;
-            bool fresh;
-            if (nwin) {
-              const int64_t o = (int64_t)u - lo;
-              const uint32_t bit = 1u << (o & 31);
-              fresh = (atomicOr(&win[o >> 5], bit) & bit) == 0u;
-            } else {
-              fresh = atomicMax(&vis[u], stamp) < stamp;
-            }
-            if (fresh) {
-              const int p = atomicAdd(&nb_sh, 1);
-              if (p < ballcap) ball[p] = u; else atomicOr(&bad_sh, 1);
-            }
-          }
-        }
-      }
-      __syncthreads();
-      ls = le;
-      le = min(nb_sh, ballcap);
-      __syncthreads();
-    }
-    for (int t = tid; t < le; t += 1024) cov[ball[t]] = 1;
+    const int more = pending_sh;
     __syncthreads();
-    stamp++;
-    cursor = (int64_t)j + 1;
-    if (bad_sh) break;
+    if (!more) break;
   }
-  if (tid == 0) {
-    *nextra = ne_sh;
-    if (bad_sh) atomicOr(err, DERR_CAPACITY);
-  }
+  int tk = 0;
+  for (int64_t i = tid; i < m; i += 1024)
+    if (ld(i) == 1) {
+      cv[elist[i]] = 1;
+      tk++;
+    }
+  atomicAdd(&taken_sh, tk);
+  __syncthreads();
+  if (tid == 0) *out_taken = taken_sh;
+}
+
+__global__ void k_elig_flags(const uint8_t* cv, const uint8_t* dir, const uint8_t* cov,
+                             int64_t n, int64_t* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = !cv[i] && !dir[i] && !cov[i];
+}
+
+__global__ void k_elig_compact(const int64_t* incl, const uint8_t* cv, const uint8_t* dir,
+                               const uint8_t* cov, int64_t n, int32_t* list, int32_t* eid) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const bool e = !cv[i] && !dir[i] && !cov[i];
+  const int32_t id = e ? (int32_t)(incl[i] - 1) : -1;
+  eid[i] = id;
+  if (e) list[id] = (int32_t)i;
+}
+
+// the taken vertices (cv set by k_lfmis) in ascending order
+__global__ void k_taken_list(const int64_t* incl, const int32_t* elist, const uint8_t* cv,
+                             int64_t m, int32_t* extra) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m && cv[elist[i]]) extra[incl[i] - 1] = elist[i];
+}
+
+__global__ void k_widen_i32(const int32_t* a, int64_t n, int64_t* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i];
+}
+
+__global__ void k_taken_flags(const int32_t* elist, const uint8_t* cv, int64_t m, int64_t* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) out[i] = cv[elist[i]] != 0;
 }
 
 // scalars gathered for one read-back into out[0..4] (a null source reads 0)
@@ -254,50 +296,59 @@ void velocity_pattern(const Csr& G, const uint8_t* dir, uint8_t* cv, VPatternOut
   uint8_t* cov = ar.alloc<uint8_t>(n);
   int32_t* vcnt = ar.alloc<int32_t>(n);
   int32_t* vbuf = ar.alloc<int32_t>((size_t)n * VCAP);
-  int32_t* vis = ar.alloc<int32_t>(n);
   HIP_OK(hipMemsetAsync(cov, 0, n, s));
   HIP_OK(hipMemsetAsync(vcnt, 0, sizeof(int32_t) * n, s));
-  HIP_OK(hipMemsetAsync(vis, 0xFF, sizeof(int32_t) * n, s));
-  // initial C^(v) list; its size, the longest graph row and the index
-  // bandwidth in one read-back
+  // initial C^(v) list
   int64_t* incl = ar.alloc<int64_t>(n + 1);
-  unsigned long long* mx2 = ar.alloc<unsigned long long>(2);
   int64_t* q = ar.alloc<int64_t>(5);
   if (n) k_flags_u8<<<nblocks(n, 256), 256, 0, s>>>(cv, n, incl);
   scan_inclusive(incl, n, s, ar);
-  max_row_len_dev(G.rowptr, n, mx2, s);
-  index_bandwidth_dev(G.rowptr, G.col, n, mx2 + 1, s);
-  k_gather_scalars<<<1, 64, 0, s>>>(n ? incl + n - 1 : nullptr, nullptr, mx2, mx2 + 1, nullptr, q);
-  int64_t hq[5];
-  HIP_OK(hipMemcpyAsync(hq, q, sizeof(hq), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipStreamSynchronize(s));
-  const int64_t n0 = hq[0];
+  const int64_t n0 = n ? d2h(incl + n - 1, s) : 0;
   int32_t* src0 = ar.alloc<int32_t>(n0);
   if (n) k_compact_u8<<<nblocks(n, 256), 256, 0, s>>>(incl, cv, n, src0, nullptr);
-  if (n0) k_vbfs<<<nblocks(n0, VB_WAVES), 64 * VB_WAVES, 0, s>>>(G.rowptr, G.col, src0, n0, dir,
+  if (n0) k_vbfs<<<nblocks(n0, VB_WAVES), 64 * VB_WAVES, 0, s>>>(G.rowptr, G.col, src0, n0, nullptr, dir,
                                                                   cov, vcnt, vbuf, err);
-  // extra points in ascending order
-  const int64_t maxdeg = hq[2];
-  int deg_cap = 1;
-  while (deg_cap < maxdeg && deg_cap < 1024) deg_cap <<= 1;
-  int32_t* extra = ar.alloc<int32_t>(n);
-  int32_t* nextra = ar.alloc<int32_t>(1);
-  int ballcap = 8192;
-  if (ballcap * 4 + 64 > lds_max) ballcap = (lds_max - 64) / 4;
-  // visited bitmap over the ball's index window when it fits beside the list
-  const int64_t bw = hq[3];
-  const int64_t words = (6 * bw + 1 + 31) / 32;
-  const int nwin = (int64_t)ballcap * 4 + words * 4 + 64 <= lds_max ? (int)words : 0;
-  const size_t lds = (size_t)ballcap * 4 + (size_t)nwin * 4;
-  allow_lds((const void*)k_vextras);
-  prof::Scope ps(s, EMIN_PROF_VPAT, 0.0);
-  k_vextras<<<1, 1024, lds, s>>>(G.rowptr, G.col, n, dir, cv, cov, vis, extra, nextra, ballcap,
-                                  deg_cap, bw, nwin, err);
-  HIP_OK(hipGetLastError());
-  out.n_extra = d2h(nextra, s);
-  if (out.n_extra)
-    k_vbfs<<<nblocks(out.n_extra, VB_WAVES), 64 * VB_WAVES, 0, s>>>(
-        G.rowptr, G.col, extra, out.n_extra, dir, cov, vcnt, vbuf, err);
+  // extra points: the eligible vertices, their conflict lists, the rounds
+  if (n) k_elig_flags<<<nblocks(n, 256), 256, 0, s>>>(cv, dir, cov, n, incl);
+  scan_inclusive(incl, n, s, ar);
+  const int64_t m = n ? d2h(incl + n - 1, s) : 0;
+  if (m) {
+    prof::Scope ps(s, EMIN_PROF_VPAT, 0.0);
+    int32_t* elist = ar.alloc<int32_t>(m);
+    int32_t* eid = ar.alloc<int32_t>(n);
+    k_elig_compact<<<nblocks(n, 256), 256, 0, s>>>(incl, cv, dir, cov, n, elist, eid);
+    int64_t* crp = ar.alloc<int64_t>(m + 1);
+    int32_t* ccnt = ar.alloc<int32_t>(m);
+    HIP_OK(hipMemsetAsync(ccnt, 0, sizeof(int32_t) * m, s));
+    k_vconf<false><<<nblocks(m, VB_WAVES), 64 * VB_WAVES, 0, s>>>(
+        G.rowptr, G.col, elist, m, eid, ccnt, nullptr, nullptr, err);
+    HIP_OK(hipMemsetAsync(crp, 0, sizeof(int64_t), s));
+    k_widen_i32<<<nblocks(m, 256), 256, 0, s>>>(ccnt, m, crp + 1);
+    scan_inclusive(crp + 1, m, s, ar);
+    const int64_t nconf = d2h(crp + m, s);
+    int32_t* ccol = ar.alloc<int32_t>(nconf > 0 ? nconf : 1);
+    HIP_OK(hipMemsetAsync(ccnt, 0, sizeof(int32_t) * m, s));
+    k_vconf<true><<<nblocks(m, VB_WAVES), 64 * VB_WAVES, 0, s>>>(
+        G.rowptr, G.col, elist, m, eid, ccnt, crp, ccol, err);
+    int32_t* ntaken = ar.alloc<int32_t>(1);
+    if (m + 64 <= lds_max) {
+      allow_lds((const void*)k_lfmis<true>);
+      k_lfmis<true><<<1, 1024, (size_t)m, s>>>(crp, ccol, m, nullptr, elist, cv, ntaken);
+    } else {
+      uint8_t* gst = ar.alloc<uint8_t>(m);
+      k_lfmis<false><<<1, 1024, 0, s>>>(crp, ccol, m, gst, elist, cv, ntaken);
+    }
+    HIP_OK(hipGetLastError());
+    // the taken vertices in ascending order; each covers its ball and joins
+    // the rows it reaches
+    int64_t* tincl = ar.alloc<int64_t>(m);
+    k_taken_flags<<<nblocks(m, 256), 256, 0, s>>>(elist, cv, m, tincl);
+    scan_inclusive(tincl, m, s, ar);
+    int32_t* extra = ar.alloc<int32_t>(m);
+    k_taken_list<<<nblocks(m, 256), 256, 0, s>>>(tincl, elist, cv, m, extra);
+    k_vbfs<<<nblocks(m, VB_WAVES), 64 * VB_WAVES, 0, s>>>(G.rowptr, G.col, extra, m, tincl + m - 1,
+                                                           dir, cov, vcnt, vbuf, err);
+  }
   // final numbering and the pattern: C^(v) size, the error flag and the
   // pattern size in one read-back
   if (n) k_flags_u8<<<nblocks(n, 256), 256, 0, s>>>(cv, n, incl);
@@ -314,6 +365,7 @@ void velocity_pattern(const Csr& G, const uint8_t* dir, uint8_t* cv, VPatternOut
   HIP_OK(hipStreamSynchronize(s));
   if (hc[4]) throw Error(EMIN_ERR_CAPACITY, "velocity pattern: row or ball capacity");
   out.n_c = hc[0];
+  out.n_extra = out.n_c - n0;
   out.N.nnz = hc[1];
   out.N.ncols = out.n_c;
   out.cid = ar.alloc<int32_t>(n);
