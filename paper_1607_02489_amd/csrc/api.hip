@@ -10,6 +10,8 @@ using namespace emin;
 
 struct emin_pattern_s {
   Arena ar;
+  // temporaries of the pattern build (released at its end, after its work)
+  Scratch tmp;
   int dim = 2;
   int64_t n_v = 0, n_p = 0, nnzA = 0, nnzB = 0;
   int lds_max = 65536;
@@ -202,6 +204,28 @@ static void ata_numeric(emin_pattern_t* h, hipStream_t s) {
   if (h->pg && !h->gmres) spgemm_numeric(view(h->Atv), view(h->AtvT), h->Er, h->erplan, s);
 }
 
+// A second stream (default priority, non-blocking) and two events per host
+// thread and device, for work of a pattern build that runs beside the main
+// stream's; kept until the process ends.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+
+SideStream& side_stream() {
+  thread_local SideStream per_dev[64];
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) throw Error(EMIN_ERR_DEVICE, "device index");
+  SideStream& x = per_dev[dev];
+  if (!x.s) {
+    HIP_OK(hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking));
+    HIP_OK(hipEventCreateWithFlags(&x.fork, hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&x.join, hipEventDisableTiming));
+  }
+  return x;
+}
+
 void build_pattern(emin_pattern_t* h, const emin_system_t* sys, const emin_params_t* prm,
                    hipStream_t s, const int32_t* cp_given = nullptr, int64_t ncp = 0) {
   Arena& ar = h->ar;
@@ -219,10 +243,18 @@ void build_pattern(emin_pattern_t* h, const emin_system_t* sys, const emin_param
   HIP_OK(hipMemsetAsync(h->derr, 0, sizeof(int), s));
   const CsrView A = in_view(sys->Ahat), B = in_view(sys->Bdiv);
   const bool vals = (prm->flags & EMIN_FLAG_VALIDATE) != 0;
+  h->ata = (prm->flags & EMIN_FLAG_ENERGY_ATA) != 0;
+  h->gmres = (prm->flags & EMIN_FLAG_GMRES) != 0;
+  if (h->ata && h->gmres)
+    throw Error(EMIN_ERR_ARG, "EMIN_FLAG_GMRES takes A~ itself, not the A^T A operator");
+  h->pg = (prm->flags & EMIN_FLAG_PETROV_GALERKIN) != 0;
   validate_csr(A, vals, h->derr, s);
   validate_csr(B, vals, h->derr, s);
   if (np) k_check_idx<<<nblocks(np, 256), 256, 0, s>>>(sys->p2v, np, nv, h->derr);
   check_derr(h, s);
+  // (the side stream's work below needs only the validated inputs)
+  SideStream& side = side_stream();
+  HIP_OK(hipEventRecord(side.fork, s));
 
   // pressure coordinates: those of the co-located velocity nodes
   h->xp = ar.alloc<double>((size_t)np * dim);
@@ -232,7 +264,7 @@ void build_pattern(emin_pattern_t* h, const emin_system_t* sys, const emin_param
   transpose_pattern(B, h->BT, h->bt_src, s, ar);
   h->BT.val = ar.alloc<double>(h->BT.nnz);
   gather_values(B.val, h->bt_src, h->BT.val, h->BT.nnz, s);
-  spgemm_symbolic(B, view(h->BT), h->Z, h->zplan, s, ar, h->derr);
+  spgemm_symbolic(B, view(h->BT), h->Z, h->zplan, s, ar, h->derr, false, &h->tmp);
   spgemm_numeric_aat(B, view(h->BT), h->Z, h->zplan, s);
   h->dZ = ar.alloc<double>(np);
   diag_of(view(h->Z), h->dZ, s);
@@ -240,28 +272,29 @@ void build_pattern(emin_pattern_t* h, const emin_system_t* sys, const emin_param
   filter_symbolic(view(h->Z), prm->tau1_p, h->dZ, h->keep_p, h->Atp, s, ar);
   symmetrize_symbolic(h->Atp, h->Mp, h->mp_ia, h->mp_ib, s, ar);
   symmetrize_numeric(h->Atp.val, h->mp_ia, h->mp_ib, h->Mp, s);
-  h->dA = ar.alloc<double>(nv);
-  diag_of(A, h->dA, s);
-  h->keep_v = ar.alloc<uint8_t>(A.nnz);
-  filter_symbolic(A, prm->tau1_v, h->dA, h->keep_v, h->Atv, s, ar);
-  symmetrize_symbolic(h->Atv, h->Mv, h->mv_ia, h->mv_ib, s, ar);
-  symmetrize_numeric(h->Atv.val, h->mv_ia, h->mv_ib, h->Mv, s);
-  // sec. 4.3, eq. (min_problem): the A^T A-norm for a non-symmetric block
-  h->ata = (prm->flags & EMIN_FLAG_ENERGY_ATA) != 0;
-  h->gmres = (prm->flags & EMIN_FLAG_GMRES) != 0;
-  if (h->ata && h->gmres)
-    throw Error(EMIN_ERR_ARG, "EMIN_FLAG_GMRES takes A~ itself, not the A^T A operator");
-  h->pg = (prm->flags & EMIN_FLAG_PETROV_GALERKIN) != 0;
-  if (h->ata || h->pg) {
-    transpose_pattern(view(h->Atv), h->AtvT, h->atvt_src, s, ar);
-    h->AtvT.val = ar.alloc<double>(h->AtvT.nnz);
-    if (h->ata) spgemm_symbolic(view(h->AtvT), view(h->Atv), h->Ev, h->evplan, s, ar, h->derr);
-    if (h->pg && !h->gmres)
-      spgemm_symbolic(view(h->Atv), view(h->AtvT), h->Er, h->erplan, s, ar, h->derr);
-    ata_numeric(h, s);
-  }
-  h->dir = ar.alloc<uint8_t>(nv);
-  dirichlet_rows(A, h->dir, s);
+  // the filtered velocity block, its energy operator and the Dirichlet rows
+  // do not depend on Alg. 3: they are queued on a side stream while the
+  // single-workgroup kernels of Alg. 3 run
+  auto velocity_filter = [&]() {
+    hipStream_t s2 = side.s;
+    try {
+      HIP_OK(hipStreamWaitEvent(s2, side.fork, 0));
+      h->dA = ar.alloc<double>(nv);
+      diag_of(A, h->dA, s2);
+      h->keep_v = ar.alloc<uint8_t>(A.nnz);
+      filter_symbolic(A, prm->tau1_v, h->dA, h->keep_v, h->Atv, s2, ar);
+      symmetrize_symbolic(h->Atv, h->Mv, h->mv_ia, h->mv_ib, s2, ar);
+      symmetrize_numeric(h->Atv.val, h->mv_ia, h->mv_ib, h->Mv, s2);
+      h->dir = ar.alloc<uint8_t>(nv);
+      dirichlet_rows(A, h->dir, s2);
+      HIP_OK(hipEventRecord(side.join, s2));
+      HIP_OK(hipStreamWaitEvent(s, side.join, 0));
+    } catch (...) {
+      // nothing queued on the side stream may outlive the handle's memory
+      (void)hipStreamSynchronize(s2);
+      throw;
+    }
+  };
 
   // Alg. 3 + extra distance-3 points on the graph of the pressure operator
   h->ca.grp = h->Mp.rowptr;
@@ -269,7 +302,25 @@ void build_pattern(emin_pattern_t* h, const emin_system_t* sys, const emin_param
   h->ca.n = np;
   h->ca.dim = dim;
   h->ca.x = h->xp;
-  coarsen_pressure(h->ca, h->cp, s, ar, h->lds_max, cp_given, ncp);
+  bool filtered = false;
+  coarsen_pressure(h->ca, h->cp, s, ar, h->lds_max, cp_given, ncp, [&]() {
+    velocity_filter();
+    filtered = true;
+  });
+  if (!filtered) velocity_filter();
+
+  // sec. 4.3, eq. (min_problem): the A^T A-norm for a non-symmetric block
+  if (h->ata || h->pg) {
+    transpose_pattern(view(h->Atv), h->AtvT, h->atvt_src, s, ar);
+    h->AtvT.val = ar.alloc<double>(h->AtvT.nnz);
+    if (h->ata)
+      spgemm_symbolic(view(h->AtvT), view(h->Atv), h->Ev, h->evplan, s, ar, h->derr, false,
+                      &h->tmp);
+    if (h->pg && !h->gmres)
+      spgemm_symbolic(view(h->Atv), view(h->AtvT), h->Er, h->erplan, s, ar, h->derr, false,
+                      &h->tmp);
+    ata_numeric(h, s);
+  }
 
   // Alg. 4 mid-points, co-located velocities, velocity pattern
   h->cbar = ar.alloc<uint8_t>(np);
@@ -317,8 +368,8 @@ void build_pattern(emin_pattern_t* h, const emin_system_t* sys, const emin_param
   Csr Pv = h->vp.N, Pp = h->cp.N;
   transpose_pattern(view(Pv), h->PvT, h->pvt_src, s, ar);
   h->PvT.val = ar.alloc<double>(h->PvT.nnz);
-  spgemm_symbolic(A, view(Pv), h->T, h->tplan, s, ar, h->derr, true);
-  spgemm_symbolic(view(h->PvT), view(h->T), h->Ac, h->acplan, s, ar, h->derr, true);
+  spgemm_symbolic(A, view(Pv), h->T, h->tplan, s, ar, h->derr, true, &h->tmp);
+  spgemm_symbolic(view(h->PvT), view(h->T), h->Ac, h->acplan, s, ar, h->derr, true, &h->tmp);
   h->X.nrows = (int64_t)dim * nv;
   h->X.ncols = (int64_t)dim * h->vp.n_c;
   h->X.nnz = (int64_t)dim * Pv.nnz;
@@ -332,10 +383,10 @@ void build_pattern(emin_pattern_t* h, const emin_system_t* sys, const emin_param
                                                              h->X.col, h->x_src);
   else
     HIP_OK(hipMemsetAsync(h->X.rowptr, 0, sizeof(int64_t), s));
-  spgemm_symbolic(B, view(h->X), h->U, h->uplan, s, ar, h->derr, true);
+  spgemm_symbolic(B, view(h->X), h->U, h->uplan, s, ar, h->derr, true, &h->tmp);
   transpose_pattern(view(Pp), h->PpT, h->ppt_src, s, ar);
   h->PpT.val = ar.alloc<double>(h->PpT.nnz);
-  spgemm_symbolic(view(h->PpT), view(h->U), h->Bc, h->bcplan, s, ar, h->derr, true);
+  spgemm_symbolic(view(h->PpT), view(h->U), h->Bc, h->bcplan, s, ar, h->derr, true, &h->tmp);
 
   // coarse descriptors: coordinates by injection, co-location map
   h->xv_c = ar.alloc<double>((size_t)h->vp.n_c * dim);
@@ -348,6 +399,7 @@ void build_pattern(emin_pattern_t* h, const emin_system_t* sys, const emin_param
                                                           h->cp.n_c, h->p2v_c, h->derr);
   check_derr(h, s);
   HIP_OK(hipStreamSynchronize(s));
+  h->tmp.release();
 
   emin_sizes_t& z = h->sizes;
   z.n_v = nv;
@@ -685,7 +737,10 @@ emin_status emin_pattern_alloc(const emin_system_t* sys, const emin_params_t* pr
     check_system(sys);
     check_params(prm);
     h = new emin_pattern_s();
-    if (alloc) h->ar.use_allocator(*alloc);
+    if (alloc) {
+      h->ar.use_allocator(*alloc);
+      h->tmp.ar.use_allocator(*alloc);
+    }
     build_pattern(h, sys, prm, as_stream(stream));
   });
   if (st != EMIN_OK) {

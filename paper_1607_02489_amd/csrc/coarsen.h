@@ -1,5 +1,7 @@
 // Coarse-point selection and sparsity patterns (Alg. 3, Alg. 4, sec. 4.2).
 #pragma once
+#include <functional>
+
 #include "common.h"
 
 namespace emin {
@@ -43,9 +45,13 @@ struct CoarsenOut {
 };
 
 // Alg. 3 and the extra distance-3 points, or, with cp_given (ncp ascending
-// fine indices, device memory), that C^(p) taken as given
+// fine indices, device memory), that C^(p) taken as given.  overlap, when
+// given, is called once the single-workgroup kernels are queued and before
+// the host waits for them, so that independent work the caller queues on
+// another stream runs beside them.
 void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar, int lds_max,
-                      const int32_t* cp_given = nullptr, int64_t ncp = 0);
+                      const int32_t* cp_given = nullptr, int64_t ncp = 0,
+                      const std::function<void()>& overlap = nullptr);
 
 // Alg. 4: C-bar^(p) flags (n_p) from the S sets; returns |C-bar^(p)| (the C
 // points and the mid-points added)

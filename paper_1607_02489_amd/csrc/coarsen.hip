@@ -721,7 +721,8 @@ __global__ void k_p_fill(CoarsenArgs D, const int32_t* cid, const int64_t* nrp, 
 }
 
 void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar, int lds_max,
-                      const int32_t* cp_given, int64_t ncp) {
+                      const int32_t* cp_given, int64_t ncp,
+                      const std::function<void()>& overlap) {
   const int64_t n = D.n;
   D.st = ar.alloc<uint8_t>(n);
   D.cnt = ar.alloc<int32_t>(n);
@@ -851,6 +852,9 @@ void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar,
   scan_inclusive(out.S.rowptr + 1, n, s, ar);
   int64_t* q = ar.alloc<int64_t>(5);
   k_coarse_summary<<<1, 64, 0, s>>>(D.meta, out.N.rowptr + n, out.S.rowptr + n, q);
+  // (before the read-back: a copy to pageable host memory returns only
+  // once the copy, and so everything queued before it, is done)
+  if (overlap) overlap();
   int64_t hq[5];
   HIP_OK(hipMemcpyAsync(hq, q, sizeof(hq), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));

@@ -198,11 +198,37 @@ struct SpgemmPlan {
 };
 constexpr int SPGEMM_SPLIT = 512;
 constexpr int SPGEMM_SPLIT_NC = 1024;
+// Device memory for stream-ordered temporaries that a handle reuses (the
+// stored bitmaps of the symbolic products): grown on demand, never shrunk,
+// and released by the owner once its queued work has completed.
+struct Scratch {
+  Arena ar;
+  void* p = nullptr;
+  size_t cap = 0;
+  void* get(size_t b) {
+    if (b > cap) {
+      p = ar.alloc<char>(b);
+      cap = b;
+    }
+    return p;
+  }
+  void release() {
+    ar.release();
+    p = nullptr;
+    cap = 0;
+  }
+};
+// the stored bitmaps of one symbolic product are kept up to this size (else
+// the product is formed once per pass)
+constexpr size_t kStoredBitmapMax = size_t(2) << 30;
 // split: rows of more than SPGEMM_SPLIT entries of A may be summed in chunks
 // (only for products whose values need not equal the single ascending chain
-// bit for bit)
+// bit for bit).  scratch: keep each output row's window bitmap between the
+// count and fill passes in it (one formation of the products instead of
+// two); the caller keeps the scratch memory until the queued work is done.
 void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& plan,
-                     hipStream_t s, Arena& ar, int* derr, bool split = false);
+                     hipStream_t s, Arena& ar, int* derr, bool split = false,
+                     Scratch* scratch = nullptr);
 void spgemm_numeric(const CsrView& A, const CsrView& B, const Csr& C, const SpgemmPlan& plan,
                     hipStream_t s);
 // C = A A^T (B of the symbolic pass was A^T): when A has at most 256 rows,

@@ -1210,6 +1210,210 @@ static void win_dispatch(int g, int64_t n, const CsrView& A, const CsrView& B, i
   }
 }
 
+// The same window method with the bitmaps kept: k_spgemm_bounds finds each
+// output row's window once (rows wider than wcap words are listed in ovf for
+// the hash kernels and keep no words), k_spgemm_bits builds the bitmap in
+// LDS, counts it and stores its words at the row's offset in a scratch
+// buffer, and k_spgemm_expand turns the stored words into the sorted column
+// list once the row pointers are known.  The products of A and B are formed
+// once instead of once per pass.
+template <int G>
+__global__ __launch_bounds__(256) void k_spgemm_bounds(int64_t n, const int64_t* arp,
+                                                      const int32_t* acol, const int64_t* brp,
+                                                      const int32_t* bcol, int wcap,
+                                                      int32_t* rlo, int32_t* rwords,
+                                                      int64_t* wcnt, int32_t* ovf, int* novf) {
+  constexpr int NG = 256 / G;
+  const int g = threadIdx.x / G, lane = threadIdx.x % G;
+  const int64_t row = xcd_block(blockIdx.x, gridDim.x) * NG + g;
+  if (row < n) {
+    const int64_t ea = arp[row], eb = arp[row + 1];
+    int32_t lo = INT32_MAX, hi = -1;
+    for (int64_t e = ea + lane; e < eb; e += G) {
+      const int32_t k = acol[e];
+      const int64_t b0 = brp[k], b1 = brp[k + 1];
+      if (b1 > b0) {
+        const int32_t f = bcol[b0], l = bcol[b1 - 1];
+        lo = f < lo ? f : lo;
+        hi = l > hi ? l : hi;
+      }
+    }
+#pragma unroll
+    for (int m = G / 2; m >= 1; m >>= 1) {
+      const int32_t ol = __shfl_xor(lo, m, G), oh = __shfl_xor(hi, m, G);
+      lo = ol < lo ? ol : lo;
+      hi = oh > hi ? oh : hi;
+    }
+    if (lane == 0) {
+      if (hi < 0) {
+        rlo[row] = 0;
+        rwords[row] = 0;
+        wcnt[row] = 0;
+      } else {
+        const int nw = (int)((((int64_t)hi - lo + 1) + 31) >> 5);
+        rlo[row] = lo;
+        rwords[row] = nw;
+        if (nw > wcap) {
+          ovf[atomicAdd(novf, 1)] = (int32_t)row;
+          wcnt[row] = 0;
+        } else {
+          wcnt[row] = nw;
+        }
+      }
+    }
+  }
+}
+
+// the widest stored window (block maxima, one atomic per 1024 rows)
+__global__ __launch_bounds__(256) void k_wcnt_max(const int64_t* wcnt, int64_t n,
+                                                 unsigned long long* mx) {
+  __shared__ unsigned long long part[4];
+  int64_t best = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+       i < n && i < (int64_t)(blockIdx.x + 1) * 1024; i += 256)
+    best = wcnt[i] > best ? wcnt[i] : best;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const int64_t o = __shfl_xor(best, m, 64);
+    best = o > best ? o : best;
+  }
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = (unsigned long long)best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long v = part[0];
+    for (int w = 1; w < 4; w++) v = part[w] > v ? part[w] : v;
+    if (v) atomicMax(mx, v);
+  }
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_spgemm_bits(int64_t n, const int64_t* arp,
+                                                    const int32_t* acol, const int64_t* brp,
+                                                    const int32_t* bcol, int wlds, int wcap,
+                                                    const int32_t* rlo, const int32_t* rwords,
+                                                    const int64_t* wincl, uint32_t* wbuf,
+                                                    int64_t* out_cnt) {
+  extern __shared__ uint32_t sbits[];
+  constexpr int NG = 256 / G;
+  const int g = threadIdx.x / G, lane = threadIdx.x % G;
+  uint32_t* words = sbits + (size_t)g * wlds;
+  const int64_t row = xcd_block(blockIdx.x, gridDim.x) * NG + g;
+  if (row >= n) return;   // whole group; the block never synchronises
+  const int nw = rwords[row];
+  if (nw == 0 || nw > wcap) return;   // empty (count stays 0), or a hash-kernel row
+  const int32_t lo = rlo[row];
+  for (int t = lane; t < nw; t += G) words[t] = 0u;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const int64_t ea = arp[row], eb = arp[row + 1];
+  for (int64_t e = ea + lane; e < eb; e += G) {
+    const int32_t k = acol[e];
+    const int64_t b0 = brp[k], b1 = brp[k + 1];
+    for (int64_t f = b0; f < b1; f += 4) {
+      int32_t j[4];
+#pragma unroll
+      for (int q = 0; q < 4; q++) j[q] = f + q < b1 ? bcol[f + q] - lo : -1;
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+        if (j[q] >= 0) atomicOr(&words[j[q] >> 5], 1u << (j[q] & 31));
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  uint32_t* dst = wbuf + (wincl[row] - nw);
+  int c = 0;
+  for (int t = lane; t < nw; t += G) {
+    const uint32_t wv = words[t];
+    c += __popc(wv);
+    dst[t] = wv;
+  }
+#pragma unroll
+  for (int m = G / 2; m >= 1; m >>= 1) c += __shfl_xor(c, m, G);
+  if (lane == 0) out_cnt[row + 1] = c;
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_spgemm_expand(int64_t n, int wcap, const int32_t* rlo,
+                                                      const int32_t* rwords,
+                                                      const int64_t* wincl,
+                                                      const uint32_t* wbuf, const int64_t* crp,
+                                                      int32_t* ccol) {
+  constexpr int NG = 256 / G;
+  const int g = threadIdx.x / G, lane = threadIdx.x % G;
+  const int64_t row = xcd_block(blockIdx.x, gridDim.x) * NG + g;
+  if (row >= n) return;
+  const int nw = rwords[row];
+  if (nw == 0 || nw > wcap) return;
+  const int32_t lo = rlo[row];
+  const uint32_t* src = wbuf + (wincl[row] - nw);
+  int32_t* out = ccol + crp[row];
+  // G consecutive words per step (coalesced), their set bits placed by a
+  // scan of the popcounts over the group
+  int run = 0;
+  for (int t0 = 0; t0 < nw; t0 += G) {
+    const int t = t0 + lane;
+    uint32_t m = t < nw ? src[t] : 0u;
+    const int c = __popc(m);
+    int incl = c;
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+      const int o = __shfl_up(incl, d, G);
+      if (lane >= d) incl += o;
+    }
+    int p = run + incl - c;
+    while (m) {
+      const int b = __builtin_ctz(m);
+      m &= m - 1u;
+      out[p++] = lo + 32 * t + b;
+    }
+    run += __shfl(incl, G - 1, G);
+  }
+}
+
+__global__ void k_bounds_summary(const int64_t* wincl, int64_t n, const int* lerr,
+                                 const unsigned long long* wmax, int64_t* out) {
+  if (threadIdx.x == 0) {
+    out[0] = n ? wincl[n - 1] : 0;
+    out[1] = lerr[1];
+    out[2] = (int64_t)*wmax;
+  }
+}
+
+template <int G>
+static void launch_stored(int64_t n, const CsrView& A, const CsrView& B, int wcap, int32_t* rlo,
+                          int32_t* rwords, int64_t* wcnt, int32_t* ovf, int* novf, int wlds,
+                          uint32_t* wbuf, int64_t* cnt, const int64_t* crp, int32_t* ccol,
+                          int which, hipStream_t s) {
+  constexpr int NG = 256 / G;
+  if (which == 0) {
+    k_spgemm_bounds<G><<<nblocks(n, NG), 256, 0, s>>>(n, A.rowptr, A.col, B.rowptr, B.col, wcap,
+                                                      rlo, rwords, wcnt, ovf, novf);
+  } else if (which == 1) {
+    const size_t lds = (size_t)NG * wlds * sizeof(uint32_t);
+    allow_lds((const void*)k_spgemm_bits<G>);
+    k_spgemm_bits<G><<<nblocks(n, NG), 256, lds, s>>>(n, A.rowptr, A.col, B.rowptr, B.col, wlds,
+                                                      wcap, rlo, rwords, wcnt, wbuf, cnt);
+  } else {
+    k_spgemm_expand<G><<<nblocks(n, NG), 256, 0, s>>>(n, wcap, rlo, rwords, wcnt, wbuf, crp,
+                                                      ccol);
+  }
+}
+
+static void stored_dispatch(int g, int64_t n, const CsrView& A, const CsrView& B, int wcap,
+                            int32_t* rlo, int32_t* rwords, int64_t* wcnt, int32_t* ovf, int* novf,
+                            int wlds, uint32_t* wbuf, int64_t* cnt, const int64_t* crp,
+                            int32_t* ccol, int which, hipStream_t s) {
+  switch (g) {
+    case 4: launch_stored<4>(n, A, B, wcap, rlo, rwords, wcnt, ovf, novf, wlds, wbuf, cnt, crp, ccol, which, s); break;
+    case 8: launch_stored<8>(n, A, B, wcap, rlo, rwords, wcnt, ovf, novf, wlds, wbuf, cnt, crp, ccol, which, s); break;
+    case 16: launch_stored<16>(n, A, B, wcap, rlo, rwords, wcnt, ovf, novf, wlds, wbuf, cnt, crp, ccol, which, s); break;
+    case 32: launch_stored<32>(n, A, B, wcap, rlo, rwords, wcnt, ovf, novf, wlds, wbuf, cnt, crp, ccol, which, s); break;
+    default: launch_stored<64>(n, A, B, wcap, rlo, rwords, wcnt, ovf, novf, wlds, wbuf, cnt, crp, ccol, which, s); break;
+  }
+}
+
 // hash kernels for a list of rows (those outside the window kernel's reach)
 template <int G>
 static void launch_sym_rows(const int32_t* rows, int64_t nrows, const CsrView& A,
@@ -1219,7 +1423,7 @@ static void launch_sym_rows(const int32_t* rows, int64_t nrows, const CsrView& A
 }
 
 void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& plan,
-                     hipStream_t s, Arena& ar, int* derr, bool split) {
+                     hipStream_t s, Arena& ar, int* derr, bool split, Scratch* scratch) {
   if (A.ncols != B.nrows) throw Error(EMIN_ERR_SHAPE, "spgemm: inner dimensions differ");
   C.nrows = A.nrows;
   C.ncols = B.ncols;
@@ -1236,12 +1440,46 @@ void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& pla
   int32_t* ovf = ar.alloc<int32_t>(A.nrows);    // rows wider than the window
   int32_t* ovf2 = ar.alloc<int32_t>(A.nrows);   // of those, rows the hash table cannot hold
   HIP_OK(hipMemsetAsync(lerr, 0, 4 * sizeof(int), s));
-  if (A.nrows)
-    win_dispatch(g, A.nrows, A, B, wcap, C.rowptr, nullptr, nullptr, ovf, lerr + 1, rwords, s);
   int hl[4];
-  HIP_OK(hipMemcpyAsync(hl, lerr, sizeof(hl), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipStreamSynchronize(s));
-  const int nwide = hl[1];
+  int nwide = 0;
+  // stored bitmaps: the windows first, then one pass that forms the products
+  bool stored = false;
+  int32_t* rlo = nullptr;
+  int64_t* wincl = nullptr;
+  uint32_t* wbuf = nullptr;
+  if (scratch && A.nrows) {
+    rlo = ar.alloc<int32_t>(A.nrows);
+    wincl = ar.alloc<int64_t>(A.nrows);
+    unsigned long long* wmax = ar.alloc<unsigned long long>(1);
+    int64_t* bs = ar.alloc<int64_t>(3);
+    HIP_OK(hipMemsetAsync(wmax, 0, sizeof(unsigned long long), s));
+    stored_dispatch(g, A.nrows, A, B, wcap, rlo, rwords, wincl, ovf, lerr + 1, 0, nullptr,
+                    nullptr, nullptr, nullptr, 0, s);
+    k_wcnt_max<<<nblocks(A.nrows, 1024), 256, 0, s>>>(wincl, A.nrows, wmax);
+    scan_inclusive(wincl, A.nrows, s, ar);
+    k_bounds_summary<<<1, 64, 0, s>>>(wincl, A.nrows, lerr, wmax, bs);
+    int64_t hb[3];
+    HIP_OK(hipMemcpyAsync(hb, bs, sizeof(hb), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    nwide = (int)hb[1];
+    if ((size_t)hb[0] * sizeof(uint32_t) <= kStoredBitmapMax) {
+      stored = true;
+      wbuf = static_cast<uint32_t*>(scratch->get((size_t)(hb[0] > 0 ? hb[0] : 1) * sizeof(uint32_t)));
+      const int wlds = (int)std::max<int64_t>(hb[2], 1);
+      stored_dispatch(g, A.nrows, A, B, wcap, rlo, rwords, wincl, nullptr, nullptr, wlds, wbuf,
+                      C.rowptr, nullptr, nullptr, 1, s);
+    } else {
+      // too many words to keep: the two-pass form (which lists the wide rows again)
+      HIP_OK(hipMemsetAsync(lerr + 1, 0, sizeof(int), s));
+    }
+  }
+  if (!stored) {
+    if (A.nrows)
+      win_dispatch(g, A.nrows, A, B, wcap, C.rowptr, nullptr, nullptr, ovf, lerr + 1, rwords, s);
+    HIP_OK(hipMemcpyAsync(hl, lerr, sizeof(hl), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    nwide = hl[1];
+  }
   // table per group within ~48 KiB per block (keys + compacted copy)
   int hcap = 64;
   while ((size_t)NG * 3 * hcap * sizeof(int32_t) <= 48 * 1024 && hcap < 4096) hcap <<= 1;
@@ -1300,7 +1538,10 @@ void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& pla
   // the window fill skips the wide rows; the hash kernels fill those (the
   // first hash fill skips the rows its table could not hold; the big table
   // does them)
-  if (A.nrows)
+  if (A.nrows && stored)
+    stored_dispatch(g, A.nrows, A, B, wcap, rlo, rwords, wincl, nullptr, nullptr, 0, wbuf,
+                    nullptr, C.rowptr, C.col, 2, s);
+  else if (A.nrows)
     win_dispatch(g, A.nrows, A, B, wcap, nullptr, C.rowptr, C.col, nullptr, nullptr, nullptr, s);
   if (nwide) {
     switch (g) {

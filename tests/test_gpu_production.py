@@ -175,6 +175,9 @@ def test_device_bytes_cover_a_mixed_hierarchy():
     free0 = torch.cuda.mem_get_info()[0]
     h = E.NativeHierarchy(d, E.params(iters=5, mixed=True), 4, min_dofs=200)
     torch.cuda.synchronize()
+    # (the builds' temporaries went back to the process-wide chunk cache,
+    # which no handle owns)
+    E.release_cached()
     used = free0 - torch.cuda.mem_get_info()[0]
     rep = h.device_bytes()
     say(f"[gpu] mixed hierarchy: reported {rep / 2**20:.1f} MiB, device delta {used / 2**20:.1f} MiB")
