@@ -763,8 +763,7 @@ void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar,
       k_balls_win<<<nblocks(m, BWIN_W), 64 * BWIN_W, lds_for(BLIST), s>>>(
           D.grp, D.gcol, m, sv, bw, (int)nwords, BLIST, bsize, b3, nullptr, 0, flags);
       int fl[2];
-      HIP_OK(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
-      HIP_OK(hipStreamSynchronize(s));
+      read_back(fl, flags, sizeof(fl), s);
       if (fl[0] == 0) {
         lcap = 64;
         while (lcap < BLIST && lcap < fl[1] + fl[1] / 4) lcap <<= 1;
@@ -774,8 +773,7 @@ void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar,
           HIP_OK(hipMemsetAsync(flags, 0, 2 * sizeof(int), s));
           k_balls_win<<<nblocks(n, BWIN_W), 64 * BWIN_W, lds_for(lcap), s>>>(
               D.grp, D.gcol, n, nullptr, bw, (int)nwords, lcap, bsize, b3, balls, stride, flags);
-          HIP_OK(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
-          HIP_OK(hipStreamSynchronize(s));
+          read_back(fl, flags, sizeof(fl), s);
           if (fl[0] == 0) {
             done = true;
             bmax = fl[1];
@@ -856,8 +854,7 @@ void coarsen_pressure(CoarsenArgs& D, CoarsenOut& out, hipStream_t s, Arena& ar,
   // once the copy, and so everything queued before it, is done)
   if (overlap) overlap();
   int64_t hq[5];
-  HIP_OK(hipMemcpyAsync(hq, q, sizeof(hq), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipStreamSynchronize(s));
+  read_back(hq, q, sizeof(hq), s);
   if (hq[2] & DERR_PATTERN) throw Error(EMIN_ERR_PATTERN, "given C points unsorted or out of range");
   if (hq[2] & DERR_CAPACITY) throw Error(EMIN_ERR_CAPACITY, "alg3: S set or BFS ball capacity");
   out.n_c = hq[0];

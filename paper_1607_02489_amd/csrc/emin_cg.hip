@@ -735,8 +735,7 @@ static void build_sched(const EminWork& w, const int64_t* nrp, const uint8_t* el
     scan_inclusive(bc, SPMM_NT * nb, s, ar);
     k_sched_place<<<(unsigned)nb, 256, 0, s>>>(nrp, elig, skip, n, o.maps, o.gshift, bc, nb, rows);
     k_sched_totals<<<1, 64, 0, s>>>(bc, nb, dtot);
-    HIP_OK(hipMemcpyAsync(tot, dtot, sizeof(tot), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
+    read_back(tot, dtot, sizeof(tot), s);
   }
   int64_t prev = 0, blocks = 0;
   for (int ty = 0; ty < SPMM_NT; ty++) {

@@ -388,8 +388,7 @@ int64_t midpoints(const Csr& S, const uint8_t* st, const double* x, int dim, dou
   k_order_place<<<(unsigned)nb, 256, 0, s>>>(key, n, bc, nb, order);
   k_order_total<<<1, 64, 0, s>>>(bc, NCLS * nb, err, toff + n, tot);
   int64_t th[3];
-  HIP_OK(hipMemcpyAsync(th, tot, sizeof(th), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipStreamSynchronize(s));
+  read_back(th, tot, sizeof(th), s);
   if (th[1]) throw Error(EMIN_ERR_CAPACITY, "alg4: S set longer than 32");
   const int64_t norder = th[0];
   const int64_t ttot = th[2];

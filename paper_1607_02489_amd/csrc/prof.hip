@@ -1,4 +1,7 @@
 // HIP-event profiler of kernel classes (see prof.h).
+#include <atomic>
+#include <chrono>
+#include <cstring>
 #include "prof.h"
 
 #include <map>
@@ -106,6 +109,76 @@ void* chunk_get(size_t bytes) {
 void chunk_put(void* p, size_t bytes) {
   std::lock_guard<std::mutex> g(cache_mu);
   cache.emplace(bytes, p);
+}
+
+// ---------------------------------------------------------------------------
+// small read-backs through pinned, device-mapped host memory
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kSlotBytes = 4096;   // payload bytes per read-back
+struct MappedSlot {
+  unsigned char* h = nullptr;   // host address: [0, 64) sequence word, then payload
+  unsigned char* d = nullptr;   // the same memory as the device sees it
+  uint64_t seq = 0;
+};
+
+MappedSlot& mapped_slot() {
+  thread_local MappedSlot per_dev[64];
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) throw Error(EMIN_ERR_DEVICE, "device index");
+  MappedSlot& m = per_dev[dev];
+  if (!m.h) {
+    void* h = nullptr;
+    HIP_OK(hipHostMalloc(&h, 64 + kSlotBytes, hipHostMallocMapped | hipHostMallocCoherent));
+    void* d = nullptr;
+    HIP_OK(hipHostGetDevicePointer(&d, h, 0));
+    *reinterpret_cast<volatile uint64_t*>(h) = 0;
+    m.h = static_cast<unsigned char*>(h);
+    m.d = static_cast<unsigned char*>(d);
+  }
+  return m;
+}
+
+// copies the payload into host memory, then (after a system-scope fence)
+// the sequence number that tells the host the payload has arrived
+__global__ void k_read_back(const unsigned char* src, int64_t n, unsigned char* slot,
+                            uint64_t seq) {
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) slot[64 + i] = src[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence_system();
+    __hip_atomic_store(reinterpret_cast<uint64_t*>(slot), seq, __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+}  // namespace
+
+void read_back(void* host, const void* dev, size_t bytes, hipStream_t s) {
+  if (bytes > kSlotBytes) {
+    HIP_OK(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    return;
+  }
+  MappedSlot& m = mapped_slot();
+  const uint64_t seq = ++m.seq;
+  k_read_back<<<1, 256, 0, s>>>(static_cast<const unsigned char*>(dev), (int64_t)bytes, m.d, seq);
+  HIP_OK(hipGetLastError());
+  // poll briefly (the common case: the stream is nearly drained); then wait
+  // on the stream, which also reports a failed kernel
+  const auto t0 = std::chrono::steady_clock::now();
+  const volatile uint64_t* flag = reinterpret_cast<const volatile uint64_t*>(m.h);
+  int n = 0;
+  while (*flag != seq) {
+    if ((++n & 255) == 0 &&
+        std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(200)) {
+      HIP_OK(hipStreamSynchronize(s));
+      if (*flag != seq) throw Error(EMIN_ERR_DEVICE, "read-back did not arrive");
+      break;
+    }
+  }
+  std::atomic_thread_fence(std::memory_order_acquire);
+  std::memcpy(host, m.h + 64, bytes);
 }
 }  // namespace emin
 

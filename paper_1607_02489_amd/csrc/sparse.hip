@@ -1459,8 +1459,7 @@ void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& pla
     scan_inclusive(wincl, A.nrows, s, ar);
     k_bounds_summary<<<1, 64, 0, s>>>(wincl, A.nrows, lerr, wmax, bs);
     int64_t hb[3];
-    HIP_OK(hipMemcpyAsync(hb, bs, sizeof(hb), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
+    read_back(hb, bs, sizeof(hb), s);
     nwide = (int)hb[1];
     if ((size_t)hb[0] * sizeof(uint32_t) <= kStoredBitmapMax) {
       stored = true;
@@ -1476,8 +1475,7 @@ void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& pla
   if (!stored) {
     if (A.nrows)
       win_dispatch(g, A.nrows, A, B, wcap, C.rowptr, nullptr, nullptr, ovf, lerr + 1, rwords, s);
-    HIP_OK(hipMemcpyAsync(hl, lerr, sizeof(hl), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
+    read_back(hl, lerr, sizeof(hl), s);
     nwide = hl[1];
   }
   // table per group within ~48 KiB per block (keys + compacted copy)
@@ -1492,8 +1490,7 @@ void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& pla
       case 32: launch_sym_rows<32>(ovf, nwide, A, B, hcap, C.rowptr, nullptr, nullptr, ovf2, lerr + 2, lerr, s); break;
       default: launch_sym_rows<64>(ovf, nwide, A, B, hcap, C.rowptr, nullptr, nullptr, ovf2, lerr + 2, lerr, s); break;
     }
-    HIP_OK(hipMemcpyAsync(hl, lerr, sizeof(hl), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
+    read_back(hl, lerr, sizeof(hl), s);
     nov = hl[2];
     if (nov) sym_big(ovf2, nov, A, B, big, C.rowptr, nullptr, nullptr, lerr, s);
   }
@@ -1508,8 +1505,7 @@ void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& pla
         C.rowptr, rwords, split ? A.rowptr : nullptr, A.rowptr, C.nrows, mx);
   k_sym_summary<<<1, 64, 0, s>>>(C.rowptr, C.nrows, lerr, mx, sm);
   int64_t hs[7];
-  HIP_OK(hipMemcpyAsync(hs, sm, sizeof(hs), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipStreamSynchronize(s));
+  read_back(hs, sm, sizeof(hs), s);
   C.nnz = hs[0];
   if (hs[1]) throw Error(EMIN_ERR_CAPACITY, "spgemm: output row exceeds the LDS table");
   plan.max_row = hs[2];

@@ -361,8 +361,7 @@ void velocity_pattern(const Csr& G, const uint8_t* dir, uint8_t* cv, VPatternOut
   k_gather_scalars<<<1, 64, 0, s>>>(n ? incl + n - 1 : nullptr, out.N.rowptr + n, nullptr,
                                     nullptr, err, q);
   int64_t hc[5];
-  HIP_OK(hipMemcpyAsync(hc, q, sizeof(hc), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipStreamSynchronize(s));
+  read_back(hc, q, sizeof(hc), s);
   if (hc[4]) throw Error(EMIN_ERR_CAPACITY, "velocity pattern: row or ball capacity");
   out.n_c = hc[0];
   out.n_extra = out.n_c - n0;
