@@ -724,6 +724,23 @@ def run_standard(args, E, synth, torch):
                                       "patterns)")
     breakdown = {k: dict(launches=v["launches"], ms=round(v["ms"], 3))
                  for k, v in phases.items()}
+    # the other kernel classes with an algorithmic byte count, over one build:
+    # the numeric sparse products (B B^T and the Galerkin products, 12 bytes
+    # per entry of A, B and C plus the row pointers) and the CG update (44
+    # bytes per pattern entry and 20 per row)
+    other_roofs = []
+    for kind, kernel, bound in (
+            ("spgemm", "k_spgemm_num (numeric B B^T and RAP products), every launch of a build",
+             "latency (LDS accumulation of gathered B rows)"),
+            ("update", "k_update (projection and CG update), every launch of a build", "hbm")):
+        v = phases.get(kind)
+        if v and v["ms"] > 0 and v.get("bytes", 0) > 0:
+            ach = v["bytes"] / (v["ms"] * 1e-3) / 1e9
+            other_roofs.append(dict(kernel=kernel, bound=bound, achieved=round(ach, 1),
+                                    peak=HBM_PEAK_GBS, unit="GB/s",
+                                    frac=round(ach / HBM_PEAK_GBS, 4),
+                                    algorithmic_bytes=round(v["bytes"]),
+                                    ms_per_build=round(v["ms"], 3), launches=v["launches"]))
     H64.close()
     return {
         "metric": "EMIN setup P-nnz*iters/s",
@@ -755,6 +772,7 @@ def run_standard(args, E, synth, torch):
                               "what": "FP64 emin_setup + emin_rap on all levels, patterns "
                                       "reused"},
         "kernel_ms_one_build": breakdown,
+        "rooflines_other": other_roofs,
         "level_sizes": [{k: z[k] for k in ("n_v", "n_p", "n_vc", "n_pc", "nnz_Pv", "nnz_Pp",
                                              "nnz_Mv", "nnz_Mp", "nnz_Ac", "nnz_Bc")}
                         for z in levels],

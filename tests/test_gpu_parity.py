@@ -354,6 +354,25 @@ def test_mixed_precision_level(case):
     assert np.linalg.norm(Pp @ np.ones(Pp.shape[1]) - 1.0) / np.sqrt(s.n_p) <= 1e-12
 
 
+def test_mixed_precision_ata_level():
+    """The A^T A-norm energy (EMIN_FLAG_ENERGY_ATA) in mixed precision: the
+    operator A~^T A~ holds squared magnitudes, converted to FP32 for the
+    masked product; P and RAP stay within 1e-5 of the FP64 oracle with the
+    same option, the patterns unchanged and the constraint met in FP64."""
+    from tests.gpu_util import same_pattern
+    s, kw = CASES["oseen2d_40_jitter"]()
+    say(f"[gpu] mixed precision A^T A, oseen2d_40_jitter: dofs={s.dofs}")
+    L = O.level(s, iters=5, energy_ata=True, **kw)
+    g = gpu_level(s, iters=5, mixed=True, energy_ata=True, **kw)
+    assert g["status"] == 0
+    for k in ("Pv", "Pp", "Ac", "Bc"):
+        assert same_pattern(g[k], getattr(L, k)), k
+        assert relfro(g[k].val, getattr(L, k).val) <= 1e-5, k
+    Pv = g["Pv"].to_scipy()
+    Wv = (~L.dir).astype(np.float64)
+    assert np.linalg.norm(Pv @ Wv[L.is_cv] - Wv) / np.linalg.norm(Wv) <= 1e-12
+
+
 @pytest.mark.parametrize("n", [12, 24])
 def test_mixed_resetup_chained_3d(n):
     """The mixed-precision form on a chained 3-D Stokes hierarchy: built in

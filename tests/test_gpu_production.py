@@ -94,6 +94,34 @@ def test_batch_graph_replays_match_eager():
         h.close()
 
 
+def test_batch_graph_replay_ata():
+    """The captured numeric phase with the A^T A-norm energy: the replay also
+    re-forms A~^T A~ from the new values before the masked products, and
+    equals an eager re-setup of twin hierarchies."""
+    import torch
+    from paper_1607_02489_amd import emin as E
+    systems = _systems()[:2]
+    prm = E.params(iters=5, energy_ata=True)
+    ds = [E.DeviceSystem.upload(s) for s in systems]
+    hs = E.build_batch(ds, prm, 3, max_parallel=2)
+    twins = [E.NativeHierarchy(d, prm, 3) for d in ds]
+    torch.cuda.synchronize()
+    B = E.Batch(hs)
+    for rep in range(2):
+        for d in ds:
+            d.keep[2].mul_(1.0 + 0.02 * (rep + 1))       # Ahat values, in place
+        torch.cuda.synchronize()
+        B.run()
+        for t in twins:
+            t.resetup()
+        torch.cuda.synchronize()
+        for h, t in zip(hs, twins):
+            _same(_levels(h), _levels(t))
+    B.close()
+    for h in hs + twins:
+        h.close()
+
+
 def test_server_mix_equals_alone_and_fifo_admission():
     import time
     import torch
