@@ -448,25 +448,36 @@ __global__ __launch_bounds__(256) void k_rowsum(const double* rowdot, int64_t n,
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
+// The row-local kernels below take G lanes per pattern row (a wave covers
+// 64 / G consecutive rows, so its loads are consecutive entries of the
+// pattern arrays): lane t holds entries t, t + G, ... of the row, the
+// projection's dot product is the lanes' sums added by a butterfly over the
+// group, and the block partials of <R,R> (and <P,MP>) are summed in a fixed
+// tree.
+
 // R = -Pi(MP), Z = R, partial <R,R>
-__global__ void k_init_r(const int64_t* rp, const int32_t* col, int64_t n, const int32_t* cid,
-                         const double* Wc, const double* G, const double* MP, double* R,
-                         double* Z, double* part) {
+template <int G>
+__global__ __launch_bounds__(256) void k_init_r(const int64_t* rp, const int32_t* col, int64_t n,
+                                               const int32_t* cid, const double* Wc,
+                                               const double* Gm, const double* MP, double* R,
+                                               double* Z, double* part) {
   __shared__ double lds[4];
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  constexpr int NG = 256 / G;
+  const int g = threadIdx.x / G, lane = threadIdx.x % G;
+  const int64_t i = (int64_t)blockIdx.x * NG + g;
   double rr = 0.0;
   if (i < n) {
     const int64_t a = rp[i], b = rp[i + 1];
     if (cid[i] >= 0) {
-      for (int64_t s = a; s < b; s++) { R[s] = 0.0; Z[s] = 0.0; }
+      for (int64_t s = a + lane; s < b; s += G) { R[s] = 0.0; Z[s] = 0.0; }
     } else {
-      double f = 0.0;
-      if (G[i] > 0.0) {
-        double dot = 0.0;
-        for (int64_t s = a; s < b; s++) dot = dot + (-MP[s]) * Wc[col[s]];
-        f = dot / G[i];
-      }
-      for (int64_t s = a; s < b; s++) {
+      double dot = 0.0;
+      for (int64_t s = a + lane; s < b; s += G) dot = dot + (-MP[s]) * Wc[col[s]];
+#pragma unroll
+      for (int m = G / 2; m >= 1; m >>= 1) dot += __shfl_xor(dot, m, G);
+      const double gi = Gm[i];
+      const double f = gi > 0.0 ? dot / gi : 0.0;
+      for (int64_t s = a + lane; s < b; s += G) {
         const double r = -MP[s] - f * Wc[col[s]];
         R[s] = r;
         Z[s] = r;
@@ -480,25 +491,29 @@ __global__ void k_init_r(const int64_t* rp, const int32_t* col, int64_t n, const
 
 // P += alpha Z; R -= alpha Pi(Q); partial <R,R>; with the energy trace also
 // MP += alpha Q and partial <P, MP>
-template <class TQ>
-__global__ void k_update(const int64_t* rp, const int32_t* col, int64_t n, const int32_t* cid,
-                         const double* Wc, const double* G, const double* Z, const TQ* Q,
-                         double* P, double* R, double* MP, const CgScalars* sc, double* part,
-                         double* part_e) {
+template <int G, class TQ>
+__global__ __launch_bounds__(256) void k_update(const int64_t* rp, const int32_t* col, int64_t n,
+                                               const int32_t* cid, const double* Wc,
+                                               const double* Gm, const double* Z, const TQ* Q,
+                                               double* P, double* R, double* MP,
+                                               const CgScalars* sc, double* part,
+                                               double* part_e) {
   __shared__ double lds[4];
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  constexpr int NG = 256 / G;
+  const int g = threadIdx.x / G, lane = threadIdx.x % G;
+  const int64_t i = (int64_t)blockIdx.x * NG + g;
   const double alpha = sc->alpha;
   double rr = 0.0, ee = 0.0;
   if (i < n) {
     const int64_t a = rp[i], b = rp[i + 1];
     if (cid[i] < 0) {
-      double f = 0.0;
-      if (G[i] > 0.0) {
-        double dot = 0.0;
-        for (int64_t s = a; s < b; s++) dot = dot + (double)Q[s] * Wc[col[s]];
-        f = dot / G[i];
-      }
-      for (int64_t s = a; s < b; s++) {
+      double dot = 0.0;
+      for (int64_t s = a + lane; s < b; s += G) dot = dot + (double)Q[s] * Wc[col[s]];
+#pragma unroll
+      for (int m = G / 2; m >= 1; m >>= 1) dot += __shfl_xor(dot, m, G);
+      const double gi = Gm[i];
+      const double f = gi > 0.0 ? dot / gi : 0.0;
+      for (int64_t s = a + lane; s < b; s += G) {
         const double q = (double)Q[s];
         const double pq = q - f * Wc[col[s]];
         const double p = P[s] + alpha * Z[s];
@@ -513,7 +528,7 @@ __global__ void k_update(const int64_t* rp, const int32_t* col, int64_t n, const
         }
       }
     } else if (MP) {
-      for (int64_t s = a; s < b; s++) {
+      for (int64_t s = a + lane; s < b; s += G) {
         const double mp = MP[s] + alpha * (double)Q[s];
         MP[s] = mp;
         ee += P[s] * mp;
@@ -525,6 +540,58 @@ __global__ void k_update(const int64_t* rp, const int32_t* col, int64_t n, const
   if (part_e) {
     t = block_sum(ee, lds);
     if (threadIdx.x == 0) part_e[blockIdx.x] = t;
+  }
+}
+
+// lanes per row of the row-local kernels: about the average pattern row
+static int update_lanes(int64_t n, int64_t nnz) {
+  const double avg = n ? (double)nnz / (double)n : 1.0;
+  int g = 4;
+  while (g < 32 && g < 0.8 * avg) g <<= 1;
+  return g;
+}
+
+template <int G>
+static int64_t launch_init_r(const EminWork& w, const int64_t* nrp, const int32_t* ncol,
+                             const int32_t* cid, hipStream_t s) {
+  const int64_t nb = nblocks(w.n, 256 / G);
+  k_init_r<G><<<(unsigned)nb, 256, 0, s>>>(nrp, ncol, w.n, cid, w.Wc, w.G, w.MP, w.R, w.Z, w.part);
+  return nb;
+}
+
+template <int G>
+static int64_t launch_update(const EminWork& w, const int64_t* nrp, const int32_t* ncol,
+                             const int32_t* cid, double* P, bool energy, bool mixed,
+                             hipStream_t s) {
+  const int64_t nb = nblocks(w.n, 256 / G);
+  if (mixed)
+    k_update<G, float><<<(unsigned)nb, 256, 0, s>>>(nrp, ncol, w.n, cid, w.Wc, w.G, w.Z, w.Qf, P,
+                                                    w.R, energy ? w.MP : nullptr, w.sc, w.part,
+                                                    energy ? w.part_e : nullptr);
+  else
+    k_update<G, double><<<(unsigned)nb, 256, 0, s>>>(nrp, ncol, w.n, cid, w.Wc, w.G, w.Z, w.Q, P,
+                                                     w.R, energy ? w.MP : nullptr, w.sc, w.part,
+                                                     energy ? w.part_e : nullptr);
+  return nb;
+}
+
+static int64_t init_r(const EminWork& w, const int64_t* nrp, const int32_t* ncol,
+                      const int32_t* cid, hipStream_t s) {
+  switch (update_lanes(w.n, w.nnz)) {
+    case 4: return launch_init_r<4>(w, nrp, ncol, cid, s);
+    case 8: return launch_init_r<8>(w, nrp, ncol, cid, s);
+    case 16: return launch_init_r<16>(w, nrp, ncol, cid, s);
+    default: return launch_init_r<32>(w, nrp, ncol, cid, s);
+  }
+}
+
+static int64_t cg_update(const EminWork& w, const int64_t* nrp, const int32_t* ncol,
+                         const int32_t* cid, double* P, bool energy, bool mixed, hipStream_t s) {
+  switch (update_lanes(w.n, w.nnz)) {
+    case 4: return launch_update<4>(w, nrp, ncol, cid, P, energy, mixed, s);
+    case 8: return launch_update<8>(w, nrp, ncol, cid, P, energy, mixed, s);
+    case 16: return launch_update<16>(w, nrp, ncol, cid, P, energy, mixed, s);
+    default: return launch_update<32>(w, nrp, ncol, cid, P, energy, mixed, s);
   }
 }
 
@@ -974,9 +1041,9 @@ void run_emin(EminWork& w, const Csr& M, const float* Mf, const int64_t* nrp, co
   int64_t np = masked_spmm(w, M, nrp, ncol, P, w.MP, P, w.part, &dots, s);
   k_finalize<<<1, 1024, 0, s>>>(dots, (int)np, w.sc, FIN_E0, 0, rp.energy, nullptr, nullptr,
                                 nullptr, nullptr);
-  k_init_r<<<nblocks(n, RB), RB, 0, s>>>(nrp, ncol, n, cid, w.Wc, w.G, w.MP, w.R, w.Z, w.part);
-  k_finalize<<<1, 1024, 0, s>>>(w.part, (int)nblocks(n, RB), w.sc, FIN_RHO0, 0, nullptr, rp.rho,
-                                nullptr, nullptr, nullptr);
+  const int64_t nbr = init_r(w, nrp, ncol, cid, s);
+  k_finalize<<<1, 1024, 0, s>>>(w.part, (int)nbr, w.sc, FIN_RHO0, 0, nullptr, rp.rho, nullptr,
+                                nullptr, nullptr);
   if (mixed) k_to_float<<<nblocks(nnz, 256), 256, 0, s>>>(w.Z, w.Zf, nnz);
   for (int it = 0; it < iters; it++) {
     if (mixed) {
@@ -988,24 +1055,18 @@ void run_emin(EminWork& w, const Csr& M, const float* Mf, const int64_t* nrp, co
     }
     k_finalize<<<1, 1024, 0, s>>>(dots, (int)np, w.sc, FIN_GAMMA, it, nullptr, nullptr,
                                   rp.gamma, rp.its, rp.status);
+    int64_t nbu = 0;
     {
     const double ub = (mixed ? 40.0 : 44.0) * (double)nnz + 20.0 * (double)n +
                       (energy ? 16.0 * (double)nnz : 0.0);
     prof::Scope pu(s, EMIN_PROF_UPDATE, ub);
-    if (mixed)
-      k_update<float><<<nblocks(n, RB), RB, 0, s>>>(nrp, ncol, n, cid, w.Wc, w.G, w.Z, w.Qf, P,
-                                                     w.R, energy ? w.MP : nullptr, w.sc, w.part,
-                                                     energy ? w.part_e : nullptr);
-    else
-      k_update<double><<<nblocks(n, RB), RB, 0, s>>>(nrp, ncol, n, cid, w.Wc, w.G, w.Z, w.Q, P,
-                                                      w.R, energy ? w.MP : nullptr, w.sc, w.part,
-                                                      energy ? w.part_e : nullptr);
+    nbu = cg_update(w, nrp, ncol, cid, P, energy, mixed, s);
     }
-    k_finalize<<<1, 1024, 0, s>>>(w.part, (int)nblocks(n, RB), w.sc, FIN_RHO, it, nullptr, rp.rho,
-                                  nullptr, nullptr, nullptr);
+    k_finalize<<<1, 1024, 0, s>>>(w.part, (int)nbu, w.sc, FIN_RHO, it, nullptr, rp.rho, nullptr,
+                                  nullptr, nullptr);
     if (energy)
-      k_finalize<<<1, 1024, 0, s>>>(w.part_e, (int)nblocks(n, RB), w.sc, FIN_E, it, rp.energy,
-                                    nullptr, nullptr, nullptr, nullptr);
+      k_finalize<<<1, 1024, 0, s>>>(w.part_e, (int)nbu, w.sc, FIN_E, it, rp.energy, nullptr,
+                                    nullptr, nullptr, nullptr);
     k_zupd<<<nblocks(nnz, 256), 256, 0, s>>>(w.R, w.Z, mixed ? w.Zf : nullptr, nnz, w.sc);
   }
 }

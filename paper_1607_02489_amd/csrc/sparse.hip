@@ -1563,6 +1563,125 @@ void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& pla
   plan.g_num = gn;
 }
 
+// Numeric product for few output rows: each row's entries are cut into S
+// slices of consecutive columns, one group of G lanes per (row, slice), so
+// that rows too few to fill the device still keep it busy.  The group takes
+// the row's A entries in ascending order, G at a time: lane q finds where
+// B's row of entry q meets the slice's column range (two binary searches);
+// then, entry by entry, the lanes add that part's products into the slice's
+// accumulators (slot of a column by binary search over the slice's sorted
+// columns in LDS).  The columns of one B row are distinct, so every c_ij
+// still receives its products in ascending order of A's row, each product
+// and each sum rounded separately.
+template <int G, class TV, class TO>
+__global__ __launch_bounds__(256) void k_spgemm_num_slices(const int64_t* arp,
+                                                          const int32_t* acol, const TV* aval,
+                                                          const int64_t* brp,
+                                                          const int32_t* bcol, const TV* bval,
+                                                          const int64_t* crp,
+                                                          const int32_t* ccol, TO* cval,
+                                                          int64_t n, int S, int L) {
+  extern __shared__ uint32_t lds_words[];
+  constexpr int NG = 256 / G;
+  const int g = threadIdx.x / G, lane = threadIdx.x % G;
+  int32_t* scol = reinterpret_cast<int32_t*>(lds_words) + (size_t)g * L;
+  TV* acc = reinterpret_cast<TV*>(lds_words + (size_t)NG * L) + (size_t)g * L;
+  const int64_t item = (int64_t)blockIdx.x * NG + g;
+  const int64_t row = item / S;
+  const int t = (int)(item % S);
+  if (row >= n) return;
+  const int64_t c0 = crp[row];
+  const int nc = (int)(crp[row + 1] - c0);
+  const int len = (nc + S - 1) / S;
+  const int s0 = t * len, s1 = s0 + len < nc ? s0 + len : nc;
+  if (s0 >= s1) return;
+  const int ns = s1 - s0;
+  for (int q = lane; q < ns; q += G) {
+    scol[q] = ccol[c0 + s0 + q];
+    acc[q] = TV(0);
+  }
+  group_sync_lds<G>();
+  const int32_t j0 = scol[0], j1 = scol[ns - 1];
+  const int64_t ea = arp[row], eb = arp[row + 1];
+  for (int64_t e0 = ea; e0 < eb; e0 += G) {
+    int64_t p0 = 0;
+    int pl = 0;
+    TV av = TV(0);
+    if (e0 + lane < eb) {
+      const int32_t k = acol[e0 + lane];
+      av = aval[e0 + lane];
+      const int64_t b0 = brp[k], b1 = brp[k + 1];
+      int64_t lo = b0, hi = b1;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (bcol[mid] < j0) lo = mid + 1; else hi = mid;
+      }
+      p0 = lo;
+      hi = b1;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (bcol[mid] <= j1) lo = mid + 1; else hi = mid;
+      }
+      pl = (int)(lo - p0);
+    }
+    const int cnt = (int)((eb - e0) < G ? (eb - e0) : G);
+    for (int q = 0; q < cnt; q++) {
+      const int64_t pq = __shfl(p0, q, G);
+      const int lq = __shfl(pl, q, G);
+      const TV aq = __shfl(av, q, G);
+      for (int o = lane; o < lq; o += G) {
+        const int32_t j = bcol[pq + o];
+        const TV b = bval[pq + o];
+        int lo = 0, hi = ns;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (scol[mid] < j) lo = mid + 1; else hi = mid;
+        }
+        acc_add(acc, lo, aq * b);
+      }
+      acc_order<TV>();
+    }
+  }
+  group_sync_lds<G>();
+  for (int q = lane; q < ns; q += G) cval[c0 + s0 + q] = (TO)acc[q];
+}
+
+// products with at most this many rows take the slice kernel (when their
+// rows are long enough to cut)
+constexpr int64_t SLICE_MAX_ROWS = 4096;
+
+template <class TV, class TO>
+static bool numeric_slices(const CsrView& A, const TV* aval, const CsrView& B, const TV* bval,
+                           const Csr& C, TO* cval, const SpgemmPlan& plan, hipStream_t s) {
+  if (A.nrows > SLICE_MAX_ROWS || A.nrows == 0 || plan.max_row < 64) return false;
+  // every group walks its row's whole A list, so A's rows must be short, and
+  // an average B row must still put several entries into each slice
+  const double avg_a = (double)A.nnz / (double)A.nrows;
+  const double avg_b = B.nrows ? (double)B.nnz / (double)B.nrows : 0.0;
+  if (avg_a > 512.0) return false;
+  constexpr int G = 32, NG = 256 / G;
+  // about 8K groups over the device, slices of at least 16 entries and at
+  // least 8 entries of an average B row, and the slice columns and
+  // accumulators of a block within 64 KiB
+  int64_t S = (8192 + A.nrows - 1) / A.nrows;
+  S = std::min<int64_t>(S, plan.max_row / 16);
+  S = std::min<int64_t>(S, (int64_t)(avg_b / 8.0));
+  if (S < 2) return false;
+  int64_t L = (plan.max_row + S - 1) / S;
+  while ((size_t)NG * L * (4 + sizeof(TV)) > 64 * 1024) {
+    S++;
+    L = (plan.max_row + S - 1) / S;
+  }
+  L = (L + 1) & ~int64_t(1);   // (keeps the accumulators 8-byte aligned)
+  const size_t lds = (size_t)NG * L * (4 + sizeof(TV));
+  allow_lds((const void*)k_spgemm_num_slices<G, TV, TO>);
+  const int64_t items = A.nrows * S;
+  k_spgemm_num_slices<G, TV, TO><<<nblocks(items, NG), 256, lds, s>>>(
+      A.rowptr, A.col, aval, B.rowptr, B.col, bval, C.rowptr, C.col, cval, A.nrows, (int)S,
+      (int)L);
+  return true;
+}
+
 template <int G, class TV, class TO>
 static void launch_num(const CsrView& A, const TV* aval, const CsrView& B, const TV* bval,
                        const Csr& C, TO* cval, int cap, int iw, const SpgemmPlan& plan,
@@ -1595,6 +1714,7 @@ static void numeric_any(const CsrView& A, const TV* aval, const CsrView& B, cons
   if (A.nrows == 0 || C.nnz == 0) return;
   prof::Scope ps(s, EMIN_PROF_SPGEMM,
                  (4.0 + sizeof(TV)) * (double)(A.nnz + B.nnz + C.nnz) + 16.0 * (double)A.nrows);
+  if (numeric_slices<TV, TO>(A, aval, B, bval, C, cval, plan, s)) return;
   const int g = plan.g_num;
   const int NG = 256 / g;
   // LDS: accumulators of the longest row (within ~96 KiB per block), and an
@@ -1719,16 +1839,19 @@ __global__ __launch_bounds__(64) void k_spgemm_aat(const int64_t* arp, const int
     const int64_t b0 = arp[j], b1 = arp[j + 1];
     double acc = 0.0;
     int64_t e = b0;
-    for (; e + 4 <= b1; e += 4) {
-      int32_t k[4];
-      double v[4];
+    // (sixteen entries' loads in flight per lane: a row j of a coarse B runs
+    // to a thousand entries, walked one lane per output)
+    constexpr int U = 16;
+    for (; e + U <= b1; e += U) {
+      int32_t k[U];
+      double v[U];
 #pragma unroll
-      for (int u = 0; u < 4; u++) {
+      for (int u = 0; u < U; u++) {
         k[u] = acol[e + u];
         v[u] = aval[e + u];
       }
 #pragma unroll
-      for (int u = 0; u < 4; u++) {
+      for (int u = 0; u < U; u++) {
         const int p = pos_of(k[u]);
         if (p >= 0) acc = acc + av[p] * v[u];
       }
