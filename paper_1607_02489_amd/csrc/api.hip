@@ -134,18 +134,23 @@ __global__ void k_p2v_coarse(const int32_t* clist_p, const int32_t* p2v, const i
 }
 
 // X = I_d (x) Pv: pattern and the map from X's entries to Pv's
-__global__ void k_kron_pattern(const int64_t* prp, const int32_t* pcol, int64_t n, int64_t nnz,
-                               int64_t nc, int dim, int64_t* xrp, int32_t* xcol, int32_t* xsrc) {
-  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= dim * n) return;
-  const int64_t c = r / n, i = r % n;
-  const int64_t base = c * nnz;
-  xrp[r] = base + prp[i];
-  if (r == dim * n - 1) xrp[r + 1] = base + prp[i + 1];
-  for (int64_t e = prp[i]; e < prp[i + 1]; e++) {
-    xcol[base + e] = (int32_t)(c * nc + pcol[e]);
-    xsrc[base + e] = (int32_t)e;
-  }
+// X = I_d (x) P: row c n + i of X is row i of P with its columns shifted by
+// c nc; one thread per entry of X (and per row pointer)
+__global__ void k_kron_entries(const int32_t* pcol, int64_t nnz, int64_t nc, int dim,
+                               int32_t* xcol, int32_t* xsrc) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= dim * nnz) return;
+  const int64_t c = e / nnz, e0 = e - c * nnz;
+  xcol[e] = (int32_t)(c * nc + pcol[e0]);
+  xsrc[e] = (int32_t)e0;
+}
+
+__global__ void k_kron_rowptr(const int64_t* prp, int64_t n, int64_t nnz, int dim, int64_t* xrp) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r > dim * n) return;
+  const int64_t c = r < dim * n ? r / n : dim - 1;
+  const int64_t i = r < dim * n ? r - c * n : n;
+  xrp[r] = c * nnz + prp[i];
 }
 
 void check_derr(emin_pattern_t* h, hipStream_t s) {
@@ -377,12 +382,15 @@ void build_pattern(emin_pattern_t* h, const emin_system_t* sys, const emin_param
   h->X.col = ar.alloc<int32_t>(h->X.nnz);
   h->X.val = ar.alloc<double>(h->X.nnz);
   h->x_src = ar.alloc<int32_t>(h->X.nnz);
-  if (nv)
-    k_kron_pattern<<<nblocks(h->X.nrows, 256), 256, 0, s>>>(Pv.rowptr, Pv.col, nv, Pv.nnz,
-                                                             h->vp.n_c, dim, h->X.rowptr,
+  if (nv) {
+    k_kron_rowptr<<<nblocks(h->X.nrows + 1, 256), 256, 0, s>>>(Pv.rowptr, nv, Pv.nnz, dim,
+                                                                h->X.rowptr);
+    if (h->X.nnz)
+      k_kron_entries<<<nblocks(h->X.nnz, 256), 256, 0, s>>>(Pv.col, Pv.nnz, h->vp.n_c, dim,
                                                              h->X.col, h->x_src);
-  else
+  } else {
     HIP_OK(hipMemsetAsync(h->X.rowptr, 0, sizeof(int64_t), s));
+  }
   spgemm_symbolic(B, view(h->X), h->U, h->uplan, s, ar, h->derr, true, &h->tmp);
   transpose_pattern(view(Pp), h->PpT, h->ppt_src, s, ar);
   h->PpT.val = ar.alloc<double>(h->PpT.nnz);

@@ -160,7 +160,8 @@ void run_emin_gmres(EminWork& w, const Csr& M, const float* Mf, const int64_t* n
 
 // building blocks shared by the CG and GMRES forms
 void gather_modes(const double* W, const int32_t* clist, int64_t nc, double* Wc, hipStream_t s);
-void emin_init(const int64_t* rp, const int32_t* col, int64_t n, const int32_t* cid,
+void emin_init(const int64_t* rp, const int32_t* col, int64_t n, int64_t nnz,
+               const int32_t* cid,
                const double* W, const double* Wc, double* G, double* P, int32_t* status,
                hipStream_t s);
 // Y = mask_N(M X) in FP64, or from FP32 copies (M's in Mf, X's made here)

@@ -38,24 +38,31 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
 
 // W_c = W restricted to the C points; Gram g_i = sum over the row's pattern
 // of W_c^2; P0 = W_i W_c / g_i on F rows (1/|N_i| for a 0/1 mode), 1 on C rows
-__global__ void k_emin_init(const int64_t* rp, const int32_t* col, int64_t n, const int32_t* cid,
-                            const double* W, const double* Wc, double* G, double* P,
-                            int32_t* status) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// (G lanes per pattern row; the Gram sum by a butterfly over the group)
+template <int G>
+__global__ __launch_bounds__(256) void k_emin_init(const int64_t* rp, const int32_t* col,
+                                                  int64_t n, const int32_t* cid, const double* W,
+                                                  const double* Wc, double* Gm, double* P,
+                                                  int32_t* status) {
+  constexpr int NG = 256 / G;
+  const int g = threadIdx.x / G, lane = threadIdx.x % G;
+  const int64_t i = (int64_t)blockIdx.x * NG + g;
   if (i >= n) return;
   const int64_t a = rp[i], b = rp[i + 1];
-  double g = 0.0;
-  for (int64_t s = a; s < b; s++) g = g + Wc[col[s]] * Wc[col[s]];
-  G[i] = g;
+  double gs = 0.0;
+  for (int64_t s = a + lane; s < b; s += G) gs = gs + Wc[col[s]] * Wc[col[s]];
+#pragma unroll
+  for (int m = G / 2; m >= 1; m >>= 1) gs += __shfl_xor(gs, m, G);
+  if (lane == 0) Gm[i] = gs;
   if (cid[i] >= 0) {
-    for (int64_t s = a; s < b; s++) P[s] = 1.0;
+    for (int64_t s = a + lane; s < b; s += G) P[s] = 1.0;
     return;
   }
-  if (g > 0.0) {
-    for (int64_t s = a; s < b; s++) P[s] = (W[i] * Wc[col[s]]) / g;
+  if (gs > 0.0) {
+    for (int64_t s = a + lane; s < b; s += G) P[s] = (W[i] * Wc[col[s]]) / gs;
   } else {
-    for (int64_t s = a; s < b; s++) P[s] = 0.0;
-    if (W[i] != 0.0) atomicMax(status, (int32_t)EMIN_ERR_INFEASIBLE);
+    for (int64_t s = a + lane; s < b; s += G) P[s] = 0.0;
+    if (lane == 0 && W[i] != 0.0) atomicMax(status, (int32_t)EMIN_ERR_INFEASIBLE);
   }
 }
 
@@ -551,6 +558,17 @@ static int update_lanes(int64_t n, int64_t nnz) {
   return g;
 }
 
+static void launch_emin_init(const int64_t* rp, const int32_t* col, int64_t n, int64_t nnz,
+                             const int32_t* cid, const double* W, const double* Wc, double* Gm,
+                             double* P, int32_t* status, hipStream_t s) {
+  switch (update_lanes(n, nnz)) {
+    case 4: k_emin_init<4><<<nblocks(n, 64), 256, 0, s>>>(rp, col, n, cid, W, Wc, Gm, P, status); break;
+    case 8: k_emin_init<8><<<nblocks(n, 32), 256, 0, s>>>(rp, col, n, cid, W, Wc, Gm, P, status); break;
+    case 16: k_emin_init<16><<<nblocks(n, 16), 256, 0, s>>>(rp, col, n, cid, W, Wc, Gm, P, status); break;
+    default: k_emin_init<32><<<nblocks(n, 8), 256, 0, s>>>(rp, col, n, cid, W, Wc, Gm, P, status); break;
+  }
+}
+
 template <int G>
 static int64_t launch_init_r(const EminWork& w, const int64_t* nrp, const int32_t* ncol,
                              const int32_t* cid, hipStream_t s) {
@@ -1035,7 +1053,7 @@ void run_emin(EminWork& w, const Csr& M, const float* Mf, const int64_t* nrp, co
   if (n == 0) return;
   // W_c = W on the C points (without a C list, the caller has filled w.Wc)
   if (w.nc && clist) k_gather_modes<<<nblocks(w.nc, 256), 256, 0, s>>>(W, clist, w.nc, w.Wc);
-  k_emin_init<<<nblocks(n, RB), RB, 0, s>>>(nrp, ncol, n, cid, W, w.Wc, w.G, P, rp.status);
+  launch_emin_init(nrp, ncol, n, nnz, cid, W, w.Wc, w.G, P, rp.status, s);
   // E0 = <P0, mask(M P0)> and R = -Pi(mask(M P0))
   const double* dots = nullptr;
   int64_t np = masked_spmm(w, M, nrp, ncol, P, w.MP, P, w.part, &dots, s);
@@ -1075,10 +1093,10 @@ void gather_modes(const double* W, const int32_t* clist, int64_t nc, double* Wc,
   if (nc) k_gather_modes<<<nblocks(nc, 256), 256, 0, s>>>(W, clist, nc, Wc);
 }
 
-void emin_init(const int64_t* rp, const int32_t* col, int64_t n, const int32_t* cid,
+void emin_init(const int64_t* rp, const int32_t* col, int64_t n, int64_t nnz, const int32_t* cid,
                const double* W, const double* Wc, double* G, double* P, int32_t* status,
                hipStream_t s) {
-  if (n) k_emin_init<<<nblocks(n, RB), RB, 0, s>>>(rp, col, n, cid, W, Wc, G, P, status);
+  if (n) launch_emin_init(rp, col, n, nnz, cid, W, Wc, G, P, status, s);
 }
 
 __global__ void k_to_double(const float* a, double* b, int64_t n) {

@@ -179,7 +179,7 @@ void run_emin_gmres(EminWork& w, const Csr& M, const float* Mf, const int64_t* n
   const unsigned nbv = nblocks(nnz, GB);
   const unsigned nbr = nblocks(n, GB);
   if (w.nc && clist) gather_modes(W, clist, w.nc, w.Wc, s);
-  emin_init(nrp, ncol, n, cid, W, w.Wc, w.G, P, rp.status, s);
+  emin_init(nrp, ncol, n, nnz, cid, W, w.Wc, w.G, P, rp.status, s);
   // R0 = -Pi mask(K P0) into v_0, beta = ||R0||
   masked_product(w, M, Mf, nrp, ncol, P, V, mixed, s);
   if (nnz) {

@@ -168,13 +168,13 @@ __global__ __launch_bounds__(256) void k_validate_g(const int64_t* rp, const int
 
 template <int G>
 __global__ __launch_bounds__(256) void k_transpose_fill_g(const int64_t* rp, const int32_t* col,
-                                                         int64_t n, int64_t* cursor,
+                                                         int64_t n, uint32_t* cursor,
                                                          int32_t* colT, int32_t* src) {
   const int64_t i = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
   const int lane = threadIdx.x % G;
   if (i >= n) return;
   for (int64_t e = rp[i] + lane; e < rp[i + 1]; e += G) {
-    const int64_t p = (int64_t)atomicAdd((unsigned long long*)&cursor[col[e]], 1ull);
+    const uint32_t p = atomicAdd(&cursor[col[e]], 1u);
     colT[p] = (int32_t)i;
     src[p] = (int32_t)e;
   }
@@ -279,9 +279,20 @@ void validate_csr(const CsrView& A, bool values, int* derr, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // transpose
 // ---------------------------------------------------------------------------
-__global__ void k_count_cols(const int32_t* col, int64_t nnz, int64_t* cnt) {
+// 32-bit counts and cursors of the transpose (positions below 2^31)
+__global__ void k_count_cols32(const int32_t* col, int64_t nnz, uint32_t* cnt) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < nnz) atomicAdd((unsigned long long*)&cnt[col[e] + 1], 1ull);
+  if (e < nnz) atomicAdd(&cnt[col[e]], 1u);
+}
+
+__global__ void k_widen_u32(const uint32_t* a, int64_t n, int64_t* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i];
+}
+
+__global__ void k_narrow_i64(const int64_t* a, int64_t n, uint32_t* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (uint32_t)a[i];
 }
 
 
@@ -470,15 +481,19 @@ void transpose_pattern(const CsrView& A, Csr& At, int32_t*& src, hipStream_t s, 
   At.nrows = A.ncols;
   At.ncols = A.nrows;
   At.nnz = A.nnz;
+  if (A.nnz >= INT32_MAX) throw Error(EMIN_ERR_CAPACITY, "transpose: nnz >= 2^31");
   At.rowptr = ar.alloc<int64_t>(At.nrows + 1);
-  HIP_OK(hipMemsetAsync(At.rowptr, 0, sizeof(int64_t) * (At.nrows + 1), s));
-  if (A.nnz) k_count_cols<<<nblocks(A.nnz, 256), 256, 0, s>>>(A.col, A.nnz, At.rowptr);
+  // (32-bit counts and positions)
+  uint32_t* cnt = ar.alloc<uint32_t>(At.nrows > 0 ? At.nrows : 1);
+  HIP_OK(hipMemsetAsync(cnt, 0, sizeof(uint32_t) * At.nrows, s));
+  HIP_OK(hipMemsetAsync(At.rowptr, 0, sizeof(int64_t), s));
+  if (A.nnz) k_count_cols32<<<nblocks(A.nnz, 256), 256, 0, s>>>(A.col, A.nnz, cnt);
+  if (At.nrows) k_widen_u32<<<nblocks(At.nrows, 256), 256, 0, s>>>(cnt, At.nrows, At.rowptr + 1);
   scan_inclusive(At.rowptr + 1, At.nrows, s, ar);
   At.col = ar.alloc<int32_t>(A.nnz);
   src = ar.alloc<int32_t>(A.nnz);
-  int64_t* cursor = ar.alloc<int64_t>(At.nrows + 1);
-  HIP_OK(hipMemcpyAsync(cursor, At.rowptr, sizeof(int64_t) * (At.nrows + 1),
-                        hipMemcpyDeviceToDevice, s));
+  uint32_t* cursor = cnt;   // the counts, overwritten with each row's first position
+  if (At.nrows) k_narrow_i64<<<nblocks(At.nrows, 256), 256, 0, s>>>(At.rowptr, At.nrows, cursor);
   if (A.nrows)
     ROWS_DISPATCH(lanes_for(A), k_transpose_fill_g, A.nrows, s, A.rowptr, A.col, A.nrows, cursor,
                   At.col, src);

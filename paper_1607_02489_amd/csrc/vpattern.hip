@@ -270,22 +270,32 @@ __global__ void k_v_counts(const uint8_t* cv, const uint8_t* dir, const int32_t*
   rp[i + 1] = cv[i] ? 1 : (dir[i] ? 0 : vcnt[i]);
 }
 
-__global__ void k_v_fill(const uint8_t* cv, const uint8_t* dir, int32_t* vcnt, int32_t* vbuf,
-                         const int32_t* cid, int64_t n, const int64_t* rp, int32_t* col) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// row i of N^(v): {itself} for a C^(v) node, nothing for a Dirichlet node,
+// else the coarse numbers of the C^(v) that reached it, ascending (distinct
+// sources, so the rank of a source among the row's gives its place); G
+// lanes per row
+template <int G>
+__global__ __launch_bounds__(256) void k_v_fill(const uint8_t* cv, const uint8_t* dir,
+                                               const int32_t* vcnt, const int32_t* vbuf,
+                                               const int32_t* cid, int64_t n, const int64_t* rp,
+                                               int32_t* col) {
+  const int64_t i = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
+  const int lane = threadIdx.x % G;
   if (i >= n) return;
   const int64_t p = rp[i];
-  if (cv[i]) { col[p] = cid[i]; return; }
-  if (dir[i]) return;
-  int32_t* b = vbuf + i * VCAP;
-  const int m = vcnt[i];
-  for (int a = 1; a < m; a++) {
-    const int32_t key = b[a];
-    int q = a;
-    while (q > 0 && b[q - 1] > key) { b[q] = b[q - 1]; q--; }
-    b[q] = key;
+  if (cv[i]) {
+    if (lane == 0) col[p] = cid[i];
+    return;
   }
-  for (int a = 0; a < m; a++) col[p + a] = cid[b[a]];
+  if (dir[i]) return;
+  const int32_t* b = vbuf + i * VCAP;
+  const int m = vcnt[i];
+  for (int t = lane; t < m; t += G) {
+    const int32_t key = b[t];
+    int rank = 0;
+    for (int u = 0; u < m; u++) rank += b[u] < key;
+    col[p + rank] = cid[key];
+  }
 }
 
 void velocity_pattern(const Csr& G, const uint8_t* dir, uint8_t* cv, VPatternOut& out,
@@ -372,8 +382,8 @@ void velocity_pattern(const Csr& G, const uint8_t* dir, uint8_t* cv, VPatternOut
   if (n) k_compact_u8<<<nblocks(n, 256), 256, 0, s>>>(incl, cv, n, out.clist, out.cid);
   out.N.col = ar.alloc<int32_t>(out.N.nnz);
   if (n)
-    k_v_fill<<<nblocks(n, 256), 256, 0, s>>>(cv, dir, vcnt, vbuf, out.cid, n, out.N.rowptr,
-                                              out.N.col);
+    k_v_fill<8><<<nblocks(n, 32), 256, 0, s>>>(cv, dir, vcnt, vbuf, out.cid, n, out.N.rowptr,
+                                                 out.N.col);
 }
 
 }  // namespace emin
