@@ -21,7 +21,6 @@
 
 namespace emin {
 
-constexpr int RB = 256;  // block size of row-wise kernels
 
 __device__ __forceinline__ double block_sum(double v, double* lds) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;

@@ -167,20 +167,6 @@ __global__ __launch_bounds__(256) void k_validate_g(const int64_t* rp, const int
 }
 
 template <int G>
-__global__ __launch_bounds__(256) void k_transpose_fill_g(const int64_t* rp, const int32_t* col,
-                                                         int64_t n, uint32_t* cursor,
-                                                         int32_t* colT, int32_t* src) {
-  const int64_t i = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
-  const int lane = threadIdx.x % G;
-  if (i >= n) return;
-  for (int64_t e = rp[i] + lane; e < rp[i + 1]; e += G) {
-    const uint32_t p = atomicAdd(&cursor[col[e]], 1u);
-    colT[p] = (int32_t)i;
-    src[p] = (int32_t)e;
-  }
-}
-
-template <int G>
 __global__ __launch_bounds__(256) void k_dirichlet_g(const int64_t* rp, const int32_t* col,
                                                     const double* val, int64_t n, uint8_t* dir) {
   const int64_t i = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
@@ -279,12 +265,6 @@ void validate_csr(const CsrView& A, bool values, int* derr, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // transpose
 // ---------------------------------------------------------------------------
-// 32-bit counts and cursors of the transpose (positions below 2^31)
-__global__ void k_count_cols32(const int32_t* col, int64_t nnz, uint32_t* cnt) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < nnz) atomicAdd(&cnt[col[e]], 1u);
-}
-
 __global__ void k_widen_u32(const uint32_t* a, int64_t n, int64_t* out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = a[i];
@@ -477,6 +457,126 @@ void sort_rows(const int64_t* rp, int64_t n, int32_t* key, int32_t* src, hipStre
   HIP_OK(hipGetLastError());
 }
 
+// Counts and fill of the transpose with one global atomic per distinct
+// column and block: a block takes R consecutive rows (about a thousand
+// entries), groups their entries by column in an LDS hash table, adds each
+// column's count to the global counter (count mode) or reserves that many
+// positions on the column's cursor (fill mode) in one atomic, and hands the
+// reserved positions out within the block.  The order inside a column is
+// arbitrary either way (sort_rows restores it).  A block whose columns do
+// not fit the table takes one global atomic per entry instead.
+// 32-bit counts and cursors of the transpose (positions below 2^31), one
+// global atomic per entry: for matrices whose columns hold few entries
+__global__ void k_count_cols32(const int32_t* col, int64_t nnz, uint32_t* cnt) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nnz) atomicAdd(&cnt[col[e]], 1u);
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_transpose_fill_g(const int64_t* rp, const int32_t* col,
+                                                         int64_t n, uint32_t* cursor,
+                                                         int32_t* colT, int32_t* src) {
+  const int64_t i = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
+  const int lane = threadIdx.x % G;
+  if (i >= n) return;
+  for (int64_t e = rp[i] + lane; e < rp[i + 1]; e += G) {
+    const uint32_t p = atomicAdd(&cursor[col[e]], 1u);
+    colT[p] = (int32_t)i;
+    src[p] = (int32_t)e;
+  }
+}
+
+constexpr int TR_HT = 2048;
+
+__device__ __forceinline__ uint32_t hash32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+__device__ __forceinline__ int row_in_block(const int64_t* srp, int nr, int64_t e) {
+  int lo = 0, hi = nr - 1;   // the last row r with srp[r] <= e
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (srp[mid] <= e) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_transpose_agg(const int64_t* rp, const int32_t* col,
+                                                      int64_t n, int R, uint32_t* cc,
+                                                      int32_t* colT, int32_t* src) {
+  __shared__ int32_t hkey[TR_HT];
+  __shared__ uint32_t hcnt[TR_HT];
+  __shared__ uint32_t hpos[TR_HT];
+  __shared__ int64_t srp[257];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * R;
+  if (r0 >= n) return;   // (uniform over the block)
+  const int nr = (int)(r0 + R < n ? R : n - r0);
+  for (int t = tid; t < TR_HT; t += 256) {
+    hkey[t] = -1;
+    hcnt[t] = 0u;
+  }
+  for (int t = tid; t <= nr; t += 256) srp[t] = rp[r0 + t];
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  const int64_t e0 = srp[0], e1 = srp[nr];
+  for (int64_t e = e0 + tid; e < e1; e += 256) {
+    const int32_t c = col[e];
+    uint32_t h = hash32((uint32_t)c) & (TR_HT - 1);
+    int probes = 0;
+    while (true) {
+      const int32_t old = atomicCAS(&hkey[h], -1, c);
+      if (old == -1 || old == c) {
+        atomicAdd(&hcnt[h], 1u);
+        break;
+      }
+      h = (h + 1) & (TR_HT - 1);
+      if (++probes >= TR_HT / 4) {
+        bad = 1;
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  if (bad) {
+    for (int64_t e = e0 + tid; e < e1; e += 256) {
+      const int32_t c = col[e];
+      const uint32_t p = atomicAdd(&cc[c], 1u);
+      if (FILL) {
+        colT[p] = (int32_t)(r0 + row_in_block(srp, nr, e));
+        src[p] = (int32_t)e;
+      }
+    }
+    return;
+  }
+  for (int t = tid; t < TR_HT; t += 256) {
+    const int32_t c = hkey[t];
+    if (c >= 0) {
+      const uint32_t k = hcnt[t];
+      if (FILL) hpos[t] = atomicAdd(&cc[c], k);
+      else atomicAdd(&cc[c], k);
+      hcnt[t] = 0u;   // (the fill's counter within the reserved run)
+    }
+  }
+  if (!FILL) return;
+  __syncthreads();
+  for (int64_t e = e0 + tid; e < e1; e += 256) {
+    const int32_t c = col[e];
+    uint32_t h = hash32((uint32_t)c) & (TR_HT - 1);
+    while (hkey[h] != c) h = (h + 1) & (TR_HT - 1);
+    const uint32_t p = hpos[h] + atomicAdd(&hcnt[h], 1u);
+    colT[p] = (int32_t)(r0 + row_in_block(srp, nr, e));
+    src[p] = (int32_t)e;
+  }
+}
+
 void transpose_pattern(const CsrView& A, Csr& At, int32_t*& src, hipStream_t s, Arena& ar) {
   At.nrows = A.ncols;
   At.ncols = A.nrows;
@@ -487,16 +587,33 @@ void transpose_pattern(const CsrView& A, Csr& At, int32_t*& src, hipStream_t s, 
   uint32_t* cnt = ar.alloc<uint32_t>(At.nrows > 0 ? At.nrows : 1);
   HIP_OK(hipMemsetAsync(cnt, 0, sizeof(uint32_t) * At.nrows, s));
   HIP_OK(hipMemsetAsync(At.rowptr, 0, sizeof(int64_t), s));
-  if (A.nnz) k_count_cols32<<<nblocks(A.nnz, 256), 256, 0, s>>>(A.col, A.nnz, cnt);
+  // block aggregation where a column collects many entries (the transposes
+  // of the prolongators: hundreds per coarse point); one atomic per entry
+  // where columns hold few (measured: the aggregation is 2x slower there)
+  const bool agg = A.ncols > 0 && (double)A.nnz / (double)A.ncols >= 32.0;
+  // rows per block: about a thousand entries
+  const double avg = A.nrows ? (double)A.nnz / (double)A.nrows : 1.0;
+  const int R = (int)std::max(1.0, std::min(256.0, 1024.0 / std::max(avg, 1.0)));
+  const unsigned tb = nblocks(A.nrows, R);
+  if (A.nnz) {
+    if (agg)
+      k_transpose_agg<false><<<tb, 256, 0, s>>>(A.rowptr, A.col, A.nrows, R, cnt, nullptr, nullptr);
+    else
+      k_count_cols32<<<nblocks(A.nnz, 256), 256, 0, s>>>(A.col, A.nnz, cnt);
+  }
   if (At.nrows) k_widen_u32<<<nblocks(At.nrows, 256), 256, 0, s>>>(cnt, At.nrows, At.rowptr + 1);
   scan_inclusive(At.rowptr + 1, At.nrows, s, ar);
   At.col = ar.alloc<int32_t>(A.nnz);
   src = ar.alloc<int32_t>(A.nnz);
   uint32_t* cursor = cnt;   // the counts, overwritten with each row's first position
   if (At.nrows) k_narrow_i64<<<nblocks(At.nrows, 256), 256, 0, s>>>(At.rowptr, At.nrows, cursor);
-  if (A.nrows)
-    ROWS_DISPATCH(lanes_for(A), k_transpose_fill_g, A.nrows, s, A.rowptr, A.col, A.nrows, cursor,
-                  At.col, src);
+  if (A.nnz) {
+    if (agg)
+      k_transpose_agg<true><<<tb, 256, 0, s>>>(A.rowptr, A.col, A.nrows, R, cursor, At.col, src);
+    else
+      ROWS_DISPATCH(lanes_for(A), k_transpose_fill_g, A.nrows, s, A.rowptr, A.col, A.nrows,
+                    cursor, At.col, src);
+  }
   sort_rows(At.rowptr, At.nrows, At.col, src, s, ar);
 }
 
@@ -513,14 +630,6 @@ void gather_values(const double* in, const int32_t* src, double* out, int64_t n,
 // SpGEMM, symbolic: G lanes per output row collect the distinct columns in an
 // LDS open-addressing table, then write them in ascending order (rank sort).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t hash32(uint32_t x) {
-  x ^= x >> 16;
-  x *= 0x7feb352du;
-  x ^= x >> 15;
-  x *= 0x846ca68bu;
-  x ^= x >> 16;
-  return x;
-}
 
 // Symbolic pass: a group of G lanes per output row inserts the columns
 // reached through A's row into an LDS open-addressing table.  Count mode
