@@ -713,6 +713,9 @@ def run_standard(args, E, synth, torch):
         roof["copy_gbs"] = round(copy_gbs, 1)
         roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
         roof["traffic"] = load_traffic("k_spmm", args.workload, "fp64" + ("_ata" if ata else ""))
+        if roof["traffic"] is None:
+            roof["traffic_note"] = ("no counter record in profiles/ for this workload and the "
+                                    "current source of the masked product")
 
     cpu = None
     acc = None

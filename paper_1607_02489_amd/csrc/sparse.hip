@@ -1410,7 +1410,7 @@ __global__ __launch_bounds__(256) void k_wcnt_max(const int64_t* wcnt, int64_t n
   }
 }
 
-template <int G>
+template <int G, bool FLAT>
 __global__ __launch_bounds__(256) void k_spgemm_bits(int64_t n, const int64_t* arp,
                                                     const int32_t* acol, const int64_t* brp,
                                                     const int32_t* bcol, int wlds, int wcap,
@@ -1431,16 +1431,54 @@ __global__ __launch_bounds__(256) void k_spgemm_bits(int64_t n, const int64_t* a
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const int64_t ea = arp[row], eb = arp[row + 1];
-  for (int64_t e = ea + lane; e < eb; e += G) {
-    const int32_t k = acol[e];
-    const int64_t b0 = brp[k], b1 = brp[k + 1];
-    for (int64_t f = b0; f < b1; f += 4) {
-      int32_t j[4];
+  if (!FLAT) {
+    // lane per A entry, walking its B row
+    for (int64_t e = ea + lane; e < eb; e += G) {
+      const int32_t k = acol[e];
+      const int64_t b0 = brp[k], b1 = brp[k + 1];
+      for (int64_t f = b0; f < b1; f += 4) {
+        int32_t j[4];
 #pragma unroll
-      for (int q = 0; q < 4; q++) j[q] = f + q < b1 ? bcol[f + q] - lo : -1;
+        for (int q = 0; q < 4; q++) j[q] = f + q < b1 ? bcol[f + q] - lo : -1;
 #pragma unroll
-      for (int q = 0; q < 4; q++)
-        if (j[q] >= 0) atomicOr(&words[j[q] >> 5], 1u << (j[q] & 31));
+        for (int q = 0; q < 4; q++)
+          if (j[q] >= 0) atomicOr(&words[j[q] >> 5], 1u << (j[q] & 31));
+      }
+    }
+  } else {
+    // the B rows of G consecutive A entries, flattened: lane t takes entries
+    // t, t + G, ... of their concatenation (the owner of entry f is the
+    // first lane whose inclusive length sum exceeds f)
+    for (int64_t e0 = ea; e0 < eb; e0 += G) {
+      const int64_t e = e0 + lane;
+      int64_t b0 = 0;
+      int len = 0;
+      if (e < eb) {
+        const int32_t k = acol[e];
+        b0 = brp[k];
+        len = (int)(brp[k + 1] - b0);
+      }
+      int incl = len;
+#pragma unroll
+      for (int d = 1; d < G; d <<= 1) {
+        const int o = __shfl_up(incl, d, G);
+        if (lane >= d) incl += o;
+      }
+      const int total = __shfl(incl, G - 1, G);
+      const int excl = incl - len;
+      for (int f0 = 0; f0 < total; f0 += G) {
+        const int f = f0 + lane;
+        int pos = 0;
+#pragma unroll
+        for (int st = G / 2; st >= 1; st >>= 1)
+          if (__shfl(incl, pos + st - 1, G) <= f) pos += st;
+        const int64_t sb = __shfl(b0, pos, G);
+        const int se = __shfl(excl, pos, G);
+        if (f < total) {
+          const int32_t j = bcol[sb + (f - se)] - lo;
+          atomicOr(&words[j >> 5], 1u << (j & 31));
+        }
+      }
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1510,15 +1548,26 @@ static void launch_stored(int64_t n, const CsrView& A, const CsrView& B, int wca
                           int32_t* rwords, int64_t* wcnt, int32_t* ovf, int* novf, int wlds,
                           uint32_t* wbuf, int64_t* cnt, const int64_t* crp, int32_t* ccol,
                           int which, hipStream_t s) {
+  // (long rows of A over B rows of a few dozen entries: flattened loads,
+  // measured faster there than a lane walking each row; elsewhere the walk)
+  const double avg_a = A.nrows ? (double)A.nnz / (double)A.nrows : 0.0;
+  const double avg_b = B.nrows ? (double)B.nnz / (double)B.nrows : 0.0;
+  const bool flat = avg_a >= 256.0 && avg_b >= 24.0 && avg_b < 64.0;
   constexpr int NG = 256 / G;
   if (which == 0) {
     k_spgemm_bounds<G><<<nblocks(n, NG), 256, 0, s>>>(n, A.rowptr, A.col, B.rowptr, B.col, wcap,
                                                       rlo, rwords, wcnt, ovf, novf);
   } else if (which == 1) {
     const size_t lds = (size_t)NG * wlds * sizeof(uint32_t);
-    allow_lds((const void*)k_spgemm_bits<G>);
-    k_spgemm_bits<G><<<nblocks(n, NG), 256, lds, s>>>(n, A.rowptr, A.col, B.rowptr, B.col, wlds,
-                                                      wcap, rlo, rwords, wcnt, wbuf, cnt);
+    if (flat) {
+      allow_lds((const void*)k_spgemm_bits<G, true>);
+      k_spgemm_bits<G, true><<<nblocks(n, NG), 256, lds, s>>>(
+          n, A.rowptr, A.col, B.rowptr, B.col, wlds, wcap, rlo, rwords, wcnt, wbuf, cnt);
+    } else {
+      allow_lds((const void*)k_spgemm_bits<G, false>);
+      k_spgemm_bits<G, false><<<nblocks(n, NG), 256, lds, s>>>(
+          n, A.rowptr, A.col, B.rowptr, B.col, wlds, wcap, rlo, rwords, wcnt, wbuf, cnt);
+    }
   } else {
     k_spgemm_expand<G><<<nblocks(n, NG), 256, 0, s>>>(n, wcap, rlo, rwords, wcnt, wbuf, crp,
                                                       ccol);
