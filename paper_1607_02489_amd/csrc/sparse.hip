@@ -1353,14 +1353,24 @@ __global__ __launch_bounds__(256) void k_spgemm_bounds(int64_t n, const int64_t*
   if (row < n) {
     const int64_t ea = arp[row], eb = arp[row + 1];
     int32_t lo = INT32_MAX, hi = -1;
-    for (int64_t e = ea + lane; e < eb; e += G) {
-      const int32_t k = acol[e];
-      const int64_t b0 = brp[k], b1 = brp[k + 1];
-      if (b1 > b0) {
-        const int32_t f = bcol[b0], l = bcol[b1 - 1];
-        lo = f < lo ? f : lo;
-        hi = l > hi ? l : hi;
+    // four A entries per lane at a time, their loads issued together
+    for (int64_t e0 = ea + lane; e0 < eb; e0 += 4 * G) {
+      int32_t k[4];
+      int64_t b0[4], b1[4];
+#pragma unroll
+      for (int q = 0; q < 4; q++) k[q] = e0 + q * G < eb ? acol[e0 + q * G] : -1;
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        b0[q] = k[q] >= 0 ? brp[k[q]] : 0;
+        b1[q] = k[q] >= 0 ? brp[k[q] + 1] : 0;
       }
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+        if (b1[q] > b0[q]) {
+          const int32_t f = bcol[b0[q]], l = bcol[b1[q] - 1];
+          lo = f < lo ? f : lo;
+          hi = l > hi ? l : hi;
+        }
     }
 #pragma unroll
     for (int m = G / 2; m >= 1; m >>= 1) {
@@ -1410,7 +1420,10 @@ __global__ __launch_bounds__(256) void k_wcnt_max(const int64_t* wcnt, int64_t n
   }
 }
 
-template <int G, bool FLAT>
+// MODE 0: a lane per A entry walking its B row; 1: flattened B rows; 2: four
+// A entries per lane with the first eight entries of their B rows loaded
+// together (short B rows, several rows of C per wave)
+template <int G, int MODE>
 __global__ __launch_bounds__(256) void k_spgemm_bits(int64_t n, const int64_t* arp,
                                                     const int32_t* acol, const int64_t* brp,
                                                     const int32_t* bcol, int wlds, int wcap,
@@ -1431,7 +1444,36 @@ __global__ __launch_bounds__(256) void k_spgemm_bits(int64_t n, const int64_t* a
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const int64_t ea = arp[row], eb = arp[row + 1];
-  if (!FLAT) {
+  if (MODE == 2) {
+    for (int64_t e0 = ea + lane; e0 < eb; e0 += 4 * G) {
+      int32_t k[4];
+      int64_t b0[4];
+      int len[4];
+#pragma unroll
+      for (int q = 0; q < 4; q++) k[q] = e0 + q * G < eb ? acol[e0 + q * G] : -1;
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        b0[q] = k[q] >= 0 ? brp[k[q]] : 0;
+        len[q] = k[q] >= 0 ? (int)(brp[k[q] + 1] - b0[q]) : 0;
+      }
+      int32_t j[4][8];
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+#pragma unroll
+        for (int t = 0; t < 8; t++) j[q][t] = t < len[q] ? bcol[b0[q] + t] - lo : -1;
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+#pragma unroll
+        for (int t = 0; t < 8; t++)
+          if (j[q][t] >= 0) atomicOr(&words[j[q][t] >> 5], 1u << (j[q][t] & 31));
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+        for (int t = 8; t < len[q]; t++) {
+          const int32_t jj = bcol[b0[q] + t] - lo;
+          atomicOr(&words[jj >> 5], 1u << (jj & 31));
+        }
+    }
+  } else if (MODE == 0) {
     // lane per A entry, walking its B row
     for (int64_t e = ea + lane; e < eb; e += G) {
       const int32_t k = acol[e];
@@ -1502,7 +1544,7 @@ __global__ __launch_bounds__(256) void k_spgemm_expand(int64_t n, int wcap, cons
                                                       const int64_t* wincl,
                                                       const uint32_t* wbuf, const int64_t* crp,
                                                       int32_t* ccol) {
-  constexpr int NG = 256 / G;
+  constexpr int NG = 256 / G, KW = 8;
   const int g = threadIdx.x / G, lane = threadIdx.x % G;
   const int64_t row = xcd_block(blockIdx.x, gridDim.x) * NG + g;
   if (row >= n) return;
@@ -1511,26 +1553,36 @@ __global__ __launch_bounds__(256) void k_spgemm_expand(int64_t n, int wcap, cons
   const int32_t lo = rlo[row];
   const uint32_t* src = wbuf + (wincl[row] - nw);
   int32_t* out = ccol + crp[row];
-  // G consecutive words per step (coalesced), their set bits placed by a
-  // scan of the popcounts over the group
+  // KW * G consecutive words per step, KW loads per lane in flight (lane l
+  // holds words l, l + G, ...); each group of G words then places its set
+  // bits by a scan of the popcounts over the group
   int run = 0;
-  for (int t0 = 0; t0 < nw; t0 += G) {
-    const int t = t0 + lane;
-    uint32_t m = t < nw ? src[t] : 0u;
-    const int c = __popc(m);
-    int incl = c;
+  for (int t0 = 0; t0 < nw; t0 += KW * G) {
+    uint32_t wv[KW];
 #pragma unroll
-    for (int d = 1; d < G; d <<= 1) {
-      const int o = __shfl_up(incl, d, G);
-      if (lane >= d) incl += o;
+    for (int k = 0; k < KW; k++) {
+      const int t = t0 + k * G + lane;
+      wv[k] = t < nw ? src[t] : 0u;
     }
-    int p = run + incl - c;
-    while (m) {
-      const int b = __builtin_ctz(m);
-      m &= m - 1u;
-      out[p++] = lo + 32 * t + b;
+#pragma unroll
+    for (int k = 0; k < KW; k++) {
+      const int t = t0 + k * G + lane;
+      uint32_t m = wv[k];
+      const int c = __popc(m);
+      int incl = c;
+#pragma unroll
+      for (int d = 1; d < G; d <<= 1) {
+        const int o = __shfl_up(incl, d, G);
+        if (lane >= d) incl += o;
+      }
+      int p = run + incl - c;
+      while (m) {
+        const int b = __builtin_ctz(m);
+        m &= m - 1u;
+        out[p++] = lo + 32 * t + b;
+      }
+      run += __shfl(incl, G - 1, G);
     }
-    run += __shfl(incl, G - 1, G);
   }
 }
 
@@ -1543,31 +1595,79 @@ __global__ void k_bounds_summary(const int64_t* wincl, int64_t n, const int* ler
   }
 }
 
+// the bounds kernel, and the bitmap kernel's MODE 2, with GQ lanes per row
+template <int GQ>
+static void launch_stored_q(int64_t n, const CsrView& A, const CsrView& B, int wcap,
+                            int32_t* rlo, int32_t* rwords, int64_t* wcnt, int32_t* ovf, int* novf,
+                            int wlds, uint32_t* wbuf, int64_t* cnt, int which, hipStream_t s) {
+  constexpr int NG = 256 / GQ;
+  if (which == 0) {
+    k_spgemm_bounds<GQ><<<nblocks(n, NG), 256, 0, s>>>(n, A.rowptr, A.col, B.rowptr, B.col,
+                                                       wcap, rlo, rwords, wcnt, ovf, novf);
+  } else {
+    allow_lds((const void*)k_spgemm_bits<GQ, 2>);
+    k_spgemm_bits<GQ, 2><<<nblocks(n, NG), 256, (size_t)NG * wlds * sizeof(uint32_t), s>>>(
+        n, A.rowptr, A.col, B.rowptr, B.col, wlds, wcap, rlo, rwords, wcnt, wbuf, cnt);
+  }
+}
+
+static void stored_q_dispatch(int gq, int64_t n, const CsrView& A, const CsrView& B, int wcap,
+                              int32_t* rlo, int32_t* rwords, int64_t* wcnt, int32_t* ovf,
+                              int* novf, int wlds, uint32_t* wbuf, int64_t* cnt, int which,
+                              hipStream_t s) {
+  switch (gq) {
+    case 4: launch_stored_q<4>(n, A, B, wcap, rlo, rwords, wcnt, ovf, novf, wlds, wbuf, cnt, which, s); break;
+    case 8: launch_stored_q<8>(n, A, B, wcap, rlo, rwords, wcnt, ovf, novf, wlds, wbuf, cnt, which, s); break;
+    case 16: launch_stored_q<16>(n, A, B, wcap, rlo, rwords, wcnt, ovf, novf, wlds, wbuf, cnt, which, s); break;
+    case 32: launch_stored_q<32>(n, A, B, wcap, rlo, rwords, wcnt, ovf, novf, wlds, wbuf, cnt, which, s); break;
+    default: launch_stored_q<64>(n, A, B, wcap, rlo, rwords, wcnt, ovf, novf, wlds, wbuf, cnt, which, s); break;
+  }
+}
+
 template <int G>
 static void launch_stored(int64_t n, const CsrView& A, const CsrView& B, int wcap, int32_t* rlo,
                           int32_t* rwords, int64_t* wcnt, int32_t* ovf, int* novf, int wlds,
                           uint32_t* wbuf, int64_t* cnt, const int64_t* crp, int32_t* ccol,
                           int which, hipStream_t s) {
   // (long rows of A over B rows of a few dozen entries: flattened loads,
-  // measured faster there than a lane walking each row; elsewhere the walk)
+  // measured faster there than a lane walking each row; short B rows: four
+  // A entries per lane, MODE 2; elsewhere the walk)
   const double avg_a = A.nrows ? (double)A.nnz / (double)A.nrows : 0.0;
   const double avg_b = B.nrows ? (double)B.nnz / (double)B.nrows : 0.0;
   const bool flat = avg_a >= 256.0 && avg_b >= 24.0 && avg_b < 64.0;
+  const bool batched = !flat && avg_b <= 16.0;   // MODE 2
   constexpr int NG = 256 / G;
-  if (which == 0) {
+  // the unrolled kernels keep four entries per lane in flight: a quarter of
+  // the lanes per row, more rows per wave, where that still leaves some 2048
+  // waves to hide the latency (measured slower below that) and, for the
+  // bitmaps of MODE 2, the block's bitmaps within the 32 KiB of LDS the walk
+  // uses (more cuts the occupancy: measured slower)
+  const int gq = G / 4 < 4 ? 4 : G / 4;
+  const bool many = (double)n * gq / 64.0 >= 2048.0;
+  const bool fits = (size_t)(256 / gq) * wlds * sizeof(uint32_t) <= 32 * 1024;
+  if (which == 0 && many) {
+    stored_q_dispatch(gq, n, A, B, wcap, rlo, rwords, wcnt, ovf, novf, 0, nullptr, nullptr, 0, s);
+  } else if (which == 0) {
     k_spgemm_bounds<G><<<nblocks(n, NG), 256, 0, s>>>(n, A.rowptr, A.col, B.rowptr, B.col, wcap,
                                                       rlo, rwords, wcnt, ovf, novf);
+  } else if (which == 1 && batched && many && fits) {
+    stored_q_dispatch(gq, n, A, B, wcap, rlo, rwords, wcnt, ovf, novf, wlds, wbuf, cnt, 1, s);
   } else if (which == 1) {
     const size_t lds = (size_t)NG * wlds * sizeof(uint32_t);
     if (flat) {
-      allow_lds((const void*)k_spgemm_bits<G, true>);
-      k_spgemm_bits<G, true><<<nblocks(n, NG), 256, lds, s>>>(
+      allow_lds((const void*)k_spgemm_bits<G, 1>);
+      k_spgemm_bits<G, 1><<<nblocks(n, NG), 256, lds, s>>>(
           n, A.rowptr, A.col, B.rowptr, B.col, wlds, wcap, rlo, rwords, wcnt, wbuf, cnt);
     } else {
-      allow_lds((const void*)k_spgemm_bits<G, false>);
-      k_spgemm_bits<G, false><<<nblocks(n, NG), 256, lds, s>>>(
+      allow_lds((const void*)k_spgemm_bits<G, 0>);
+      k_spgemm_bits<G, 0><<<nblocks(n, NG), 256, lds, s>>>(
           n, A.rowptr, A.col, B.rowptr, B.col, wlds, wcap, rlo, rwords, wcnt, wbuf, cnt);
     }
+  } else if ((double)n * 16 / 64.0 >= 2048.0) {
+    // (the expansion reads words only: 16 lanes per row whatever G, given
+    // rows enough to fill the machine)
+    k_spgemm_expand<16><<<nblocks(n, 16), 256, 0, s>>>(n, wcap, rlo, rwords, wcnt, wbuf, crp,
+                                                       ccol);
   } else {
     k_spgemm_expand<G><<<nblocks(n, NG), 256, 0, s>>>(n, wcap, rlo, rwords, wcnt, wbuf, crp,
                                                       ccol);
