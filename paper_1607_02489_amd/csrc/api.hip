@@ -234,6 +234,7 @@ SideStream& side_stream() {
 void build_pattern(emin_pattern_t* h, const emin_system_t* sys, const emin_params_t* prm,
                    hipStream_t s, const int32_t* cp_given = nullptr, int64_t ncp = 0) {
   Arena& ar = h->ar;
+  StreamUse use_ar(h->ar, s), use_tmp(h->tmp.ar, s);
   const int dim = sys->dim;
   const int64_t nv = sys->Ahat.nrows, np = sys->Bdiv.nrows;
   h->dim = dim;
@@ -438,6 +439,7 @@ void check_same_structure(const emin_pattern_t* h, const emin_system_t* sys) {
 
 void run_setup(emin_pattern_t* h, const emin_system_t* sys, const emin_params_t* prm, double* Pv,
                double* Pp, hipStream_t s, emin_report_t* rep, double* Rvt = nullptr) {
+  StreamUse use_ar(h->ar, s);
   check_same_structure(h, sys);
   check_params(prm);
   if (((prm->flags & EMIN_FLAG_ENERGY_ATA) != 0) != h->ata)
@@ -502,6 +504,7 @@ void run_setup(emin_pattern_t* h, const emin_system_t* sys, const emin_params_t*
 
 void run_rap(emin_pattern_t* h, const emin_system_t* sys, const double* Pv, const double* Pp,
              double* Acv, double* Bcv, int precision, hipStream_t s) {
+  StreamUse use_ar(h->ar, s);
   check_same_structure(h, sys);
   if (precision != EMIN_PREC_F64 && precision != EMIN_PREC_MIXED)
     throw Error(EMIN_ERR_ARG, "unknown precision");
@@ -570,6 +573,7 @@ void run_setup_with_pattern(const emin_csr_t* Min, const int64_t* nrp, const int
     throw Error(EMIN_ERR_ARG, "NULL array");
   if (Min->nnz >= INT32_MAX || nnz >= INT32_MAX) throw Error(EMIN_ERR_CAPACITY, "nnz >= 2^31");
   Arena own;
+  StreamUse use_own(own, s);
   Arena& ar = ext ? *ext : own;
   int* derr = ar.alloc<int>(1);
   HIP_OK(hipMemsetAsync(derr, 0, sizeof(int), s));
@@ -613,6 +617,7 @@ void run_setup_with_pattern(const emin_csr_t* Min, const int64_t* nrp, const int
 // pattern, or Bdiv itself)
 void run_rap_pg(emin_pattern_t* h, const emin_system_t* sys, const double* Pv, const double* Pp,
                 const double* Rvt, double* Acv, double* Bcv, double* Gctv, hipStream_t s) {
+  StreamUse use_ar(h->ar, s);
   check_same_structure(h, sys);
   if (!h->pg) throw Error(EMIN_ERR_ARG, "pattern built without EMIN_FLAG_PETROV_GALERKIN");
   if ((h->sizes.nnz_Pv && (!Pv || !Rvt)) || (h->sizes.nnz_Pp && !Pp) || (h->Ac.nnz && !Acv) ||

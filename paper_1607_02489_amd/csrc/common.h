@@ -4,6 +4,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <memory>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -39,11 +40,26 @@ enum DevErr : int {
 // ---------------------------------------------------------------------------
 // device memory owned by a handle
 // ---------------------------------------------------------------------------
-// Process-wide cache of device chunks: handles return their chunks here
-// instead of calling hipFree (which would wait for the whole device), and new
-// handles take cached chunks first.  emin_release_cached() frees the cache.
+// The completion point of queued work: an event, destroyed with its last
+// owner.  An empty token stands for "no work queued".
+struct EventBox {
+  hipEvent_t e = nullptr;
+  EventBox() = default;
+  EventBox(const EventBox&) = delete;
+  EventBox& operator=(const EventBox&) = delete;
+  ~EventBox() {
+    if (e) (void)hipEventDestroy(e);
+  }
+};
+using WorkToken = std::shared_ptr<EventBox>;
+
+// Process-wide cache of device chunks (with an ownership ledger): handles
+// return their chunks here instead of calling hipFree (which would wait for
+// the whole device), and new allocations on the same device take cached
+// chunks first, once the work last queued on them has completed.
+// emin_release_cached() frees the cache.
 void* chunk_get(size_t bytes);
-void chunk_put(void* p, size_t bytes);
+void chunk_put(void* p, size_t bytes, WorkToken done);
 
 // Lets kernel f take up to the device's LDS per block (less its static LDS)
 // as dynamic LDS.  Set once per kernel and device, under a lock, so host
@@ -92,14 +108,62 @@ class Arena {
     left_ -= b;
     return static_cast<T*>(r);
   }
-  // the caller guarantees that no queued work still uses the memory
+  // Notes that work using this arena's memory has been queued on s up to
+  // now (the arena keeps the latest such point, made to follow the previous
+  // one when the stream differs).  Not while s is being captured into a
+  // graph: the replays of a graph are the caller's to finish before the
+  // release.  On any failure it waits for s instead.
+  void used_on(hipStream_t s) noexcept {
+    if (fixed_ || chunks_.empty()) return;
+    // errors of the calls below are handled here (by waiting instead): a
+    // clean last-error state is left clean for the caller's launch checks
+    struct KeepClean {
+      bool clean = hipPeekAtLastError() == hipSuccess;
+      ~KeepClean() {
+        if (clean) (void)hipGetLastError();
+      }
+    } keep;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) {
+      (void)hipStreamSynchronize(s);
+      return;
+    }
+    if (cs != hipStreamCaptureStatusNone) return;
+    if (last_ && last_s_ != s && hipStreamWaitEvent(s, last_->e, 0) != hipSuccess)
+      (void)hipEventSynchronize(last_->e);
+    if (!last_) {
+      try {
+        last_ = std::make_shared<EventBox>();
+      } catch (...) {
+        (void)hipStreamSynchronize(s);
+        return;
+      }
+      if (hipEventCreateWithFlags(&last_->e, hipEventDisableTiming) != hipSuccess) {
+        last_->e = nullptr;
+        last_.reset();
+        (void)hipStreamSynchronize(s);
+        return;
+      }
+    }
+    if (hipEventRecord(last_->e, s) != hipSuccess) (void)hipStreamSynchronize(s);
+    last_s_ = s;
+  }
+  // Gives the chunks back.  Work queued on them and noted by used_on() may
+  // still be running: the cache hands them out again only after it has
+  // completed.  A caller's allocator gets them back after it has completed.
   void release() {
     if (fixed_) return;
     for (auto& c : chunks_) {
-      if (has_al_) al_.free(c.first, al_.ctx);
-      else chunk_put(c.first, c.second);
+      if (has_al_) {
+        if (last_) (void)hipEventSynchronize(last_->e);
+        al_.free(c.first, al_.ctx);
+      } else {
+        chunk_put(c.first, c.second, last_);
+      }
     }
     chunks_.clear();
+    last_.reset();
+    last_s_ = nullptr;
     bytes_ = 0;
     cur_ = nullptr;
     left_ = 0;
@@ -112,9 +176,25 @@ class Arena {
   bool has_al_ = false;
   emin_allocator_t al_{};
   std::vector<std::pair<void*, size_t>> chunks_;
+  WorkToken last_;                 // latest point of queued work (used_on)
+  hipStream_t last_s_ = nullptr;   // the stream it was recorded on
   size_t bytes_ = 0;
   char* cur_ = nullptr;
   size_t left_ = 0;
+};
+
+// Notes, on leaving its scope (normally or by an exception), that work
+// using the arena's memory was queued on s (Arena::used_on).
+class StreamUse {
+ public:
+  StreamUse(Arena& a, hipStream_t s) : a_(a), s_(s) {}
+  StreamUse(const StreamUse&) = delete;
+  StreamUse& operator=(const StreamUse&) = delete;
+  ~StreamUse() { a_.used_on(s_); }
+
+ private:
+  Arena& a_;
+  hipStream_t s_;
 };
 
 // a CSR matrix in device memory (rowptr int64, col int32, val double/float)

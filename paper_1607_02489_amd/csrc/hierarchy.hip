@@ -138,6 +138,7 @@ emin_status emin_hierarchy_build(const emin_system_t* sys, const emin_params_t* 
     return st;
   }
   h->coarsest = cur;
+  h->ar.used_on(s);
   *out = h;
   return EMIN_OK;
 }
@@ -147,6 +148,7 @@ emin_status emin_hierarchy_resetup(emin_hierarchy_t* h, const emin_system_t* sys
   if (h->pats.empty()) return EMIN_OK;
   h->sys[0] = *sys;
   try {
+    StreamUse use_ar(h->ar, reinterpret_cast<hipStream_t>(stream));
     return resetup_levels(h, reinterpret_cast<hipStream_t>(stream));
   } catch (const Error& e) {
     return e.code;

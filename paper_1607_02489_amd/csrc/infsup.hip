@@ -281,6 +281,7 @@ emin_status emin_galerkin(const emin_csr_t* M, const emin_csr_t* P, void* stream
       throw Error(EMIN_ERR_SHAPE, "P^T M P: M must be square with P's row count");
     h = new emin_matrix_s();
     Arena& ar = h->ar;
+    StreamUse use_ar(h->ar, s);
     int* derr = ar.alloc<int>(1);
     HIP_OK(hipMemsetAsync(derr, 0, sizeof(int), s));
     const CsrView Mv = viewof(*M), Pv = viewof(*P);
@@ -333,6 +334,7 @@ emin_status emin_infsup(const emin_csr_t* B, const emin_csr_t* Mv, const emin_cs
       throw Error(EMIN_ERR_SHAPE, "B must be n_p x d*n_v with M_p n_p x n_p, M_v n_v x n_v");
     const int m = (int)std::min<int64_t>(steps, np);
     Arena ar;
+    StreamUse use_ar(ar, s);
     try {
       int* derr = ar.alloc<int>(1);
       HIP_OK(hipMemsetAsync(derr, 0, sizeof(int), s));

@@ -1,7 +1,10 @@
 // HIP-event profiler of kernel classes (see prof.h).
 #include <atomic>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include "chunk_cache.h"
 #include "prof.h"
 
 #include <map>
@@ -71,8 +74,41 @@ void end(int token, hipStream_t s) {
 
 namespace emin {
 namespace {
-std::mutex cache_mu;
-std::multimap<size_t, void*> cache;
+// the device side of the chunk cache: hipMalloc/hipFree, events as tokens
+struct HipChunks {
+  using Token = WorkToken;
+  void* alloc(size_t bytes) {
+    void* p = nullptr;
+    return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+  }
+  void free(void* p) { (void)hipFree(p); }
+  // (hipErrorNotReady is an answer here, not an error: it is taken out of the
+  // thread's last-error state, which a later launch check reads; with an
+  // error already pending there the query is skipped, keeping that error)
+  bool done(const Token& t) {
+    if (!t) return true;
+    if (hipPeekAtLastError() != hipSuccess) return false;
+    const hipError_t q = hipEventQuery(t->e);
+    if (q != hipSuccess) (void)hipGetLastError();
+    return q == hipSuccess;
+  }
+  void wait(const Token& t) {
+    if (t) (void)hipEventSynchronize(t->e);
+  }
+  [[noreturn]] void fail(const char* msg) {
+    std::fprintf(stderr, "emin: %s\n", msg);
+    std::abort();
+  }
+};
+ChunkCache<HipChunks>& chunk_cache() {
+  static ChunkCache<HipChunks>* c = new ChunkCache<HipChunks>();   // outlives exit-time releases
+  return *c;
+}
+int current_device() {
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  return dev;
+}
 }  // namespace
 
 void allow_lds(const void* f) {
@@ -91,24 +127,12 @@ void allow_lds(const void* f) {
   done.insert({f, dev});
 }
 
-void* chunk_get(size_t bytes) {
-  {
-    std::lock_guard<std::mutex> g(cache_mu);
-    auto it = cache.find(bytes);
-    if (it != cache.end()) {
-      void* p = it->second;
-      cache.erase(it);
-      return p;
-    }
-  }
-  void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
-  return p;
-}
+void* chunk_get(size_t bytes) { return chunk_cache().get(bytes, current_device()); }
 
-void chunk_put(void* p, size_t bytes) {
-  std::lock_guard<std::mutex> g(cache_mu);
-  cache.emplace(bytes, p);
+void chunk_put(void* p, size_t bytes, WorkToken done) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  chunk_cache().put(p, bytes, dev, std::move(done));
 }
 
 // ---------------------------------------------------------------------------
@@ -184,16 +208,7 @@ void read_back(void* host, const void* dev, size_t bytes, hipStream_t s) {
 
 extern "C" {
 
-int64_t emin_release_cached(void) {
-  std::lock_guard<std::mutex> g(emin::cache_mu);
-  int64_t freed = 0;
-  for (auto& kv : emin::cache) {
-    (void)hipFree(kv.second);
-    freed += (int64_t)kv.first;
-  }
-  emin::cache.clear();
-  return freed;
-}
+int64_t emin_release_cached(void) { return (int64_t)emin::chunk_cache().release_all(); }
 
 emin_status emin_profile_enable(int enable) {
   std::lock_guard<std::mutex> g(emin::prof::mu);

@@ -541,6 +541,7 @@ emin_status emin_solver_vcycle(emin_solver_t* S, const double* f, double* x, voi
   if (!S || !f || !x) return EMIN_ERR_ARG;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   return guard([&] {
+    StreamUse use_ar(S->ar, s);
     vcycle(S, 0, f, x, s);
     HIP_OK(hipGetLastError());
   });
@@ -551,6 +552,7 @@ emin_status emin_solver_gmres(emin_solver_t* S, const double* f, double* x, doub
   if (!S || !f || !x || maxit < 1 || !(rtol >= 0.0)) return EMIN_ERR_ARG;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   return guard([&] {
+    StreamUse use_ar(S->ar, s);
     const SolverLevel& L0 = S->L[0];
     const int64_t n = L0.n;
     const int m = maxit;
