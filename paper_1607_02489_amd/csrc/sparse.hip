@@ -1423,18 +1423,24 @@ __global__ __launch_bounds__(256) void k_wcnt_max(const int64_t* wcnt, int64_t n
 // MODE 0: a lane per A entry walking its B row; 1: flattened B rows; 2: four
 // A entries per lane with the first eight entries of their B rows loaded
 // together (short B rows, several rows of C per wave)
+// nsl > 1 (sliced form, for few long rows): nsl groups per row, each taking
+// an equal share of the row's A entries and OR-ing its bitmap into the row's
+// stored words (zeroed beforehand); the counts then come from
+// k_spgemm_bits_count
 template <int G, int MODE>
 __global__ __launch_bounds__(256) void k_spgemm_bits(int64_t n, const int64_t* arp,
                                                     const int32_t* acol, const int64_t* brp,
                                                     const int32_t* bcol, int wlds, int wcap,
                                                     const int32_t* rlo, const int32_t* rwords,
                                                     const int64_t* wincl, uint32_t* wbuf,
-                                                    int64_t* out_cnt) {
+                                                    int64_t* out_cnt, int nsl = 1) {
   extern __shared__ uint32_t sbits[];
   constexpr int NG = 256 / G;
   const int g = threadIdx.x / G, lane = threadIdx.x % G;
   uint32_t* words = sbits + (size_t)g * wlds;
-  const int64_t row = xcd_block(blockIdx.x, gridDim.x) * NG + g;
+  const int64_t gid = xcd_block(blockIdx.x, gridDim.x) * NG + g;
+  const int64_t row = gid / nsl;
+  const int sl = (int)(gid - row * nsl);
   if (row >= n) return;   // whole group; the block never synchronises
   const int nw = rwords[row];
   if (nw == 0 || nw > wcap) return;   // empty (count stays 0), or a hash-kernel row
@@ -1443,7 +1449,12 @@ __global__ __launch_bounds__(256) void k_spgemm_bits(int64_t n, const int64_t* a
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  const int64_t ea = arp[row], eb = arp[row + 1];
+  int64_t ea = arp[row], eb = arp[row + 1];
+  if (nsl > 1) {
+    const int64_t len = eb - ea, a0 = ea;
+    ea = a0 + len * sl / nsl;
+    eb = a0 + len * (sl + 1) / nsl;
+  }
   if (MODE == 2) {
     for (int64_t e0 = ea + lane; e0 < eb; e0 += 4 * G) {
       int32_t k[4];
@@ -1527,12 +1538,40 @@ __global__ __launch_bounds__(256) void k_spgemm_bits(int64_t n, const int64_t* a
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   uint32_t* dst = wbuf + (wincl[row] - nw);
+  if (nsl > 1) {
+    for (int t = lane; t < nw; t += G) {
+      const uint32_t wv = words[t];
+      if (wv) atomicOr(&dst[t], wv);
+    }
+    return;
+  }
   int c = 0;
   for (int t = lane; t < nw; t += G) {
     const uint32_t wv = words[t];
     c += __popc(wv);
     dst[t] = wv;
   }
+#pragma unroll
+  for (int m = G / 2; m >= 1; m >>= 1) c += __shfl_xor(c, m, G);
+  if (lane == 0) out_cnt[row + 1] = c;
+}
+
+// entries of each row of the sliced form: the set bits of its stored words
+template <int G>
+__global__ __launch_bounds__(256) void k_spgemm_bits_count(int64_t n, int wcap,
+                                                          const int32_t* rwords,
+                                                          const int64_t* wincl,
+                                                          const uint32_t* wbuf,
+                                                          int64_t* out_cnt) {
+  constexpr int NG = 256 / G;
+  const int g = threadIdx.x / G, lane = threadIdx.x % G;
+  const int64_t row = (int64_t)blockIdx.x * NG + g;
+  if (row >= n) return;
+  const int nw = rwords[row];
+  if (nw == 0 || nw > wcap) return;
+  const uint32_t* src = wbuf + (wincl[row] - nw);
+  int c = 0;
+  for (int t = lane; t < nw; t += G) c += __popc(src[t]);
 #pragma unroll
   for (int m = G / 2; m >= 1; m >>= 1) c += __shfl_xor(c, m, G);
   if (lane == 0) out_cnt[row + 1] = c;
@@ -1628,7 +1667,7 @@ template <int G>
 static void launch_stored(int64_t n, const CsrView& A, const CsrView& B, int wcap, int32_t* rlo,
                           int32_t* rwords, int64_t* wcnt, int32_t* ovf, int* novf, int wlds,
                           uint32_t* wbuf, int64_t* cnt, const int64_t* crp, int32_t* ccol,
-                          int which, hipStream_t s) {
+                          int which, int64_t wtotal, hipStream_t s) {
   // (long rows of A over B rows of a few dozen entries: flattened loads,
   // measured faster there than a lane walking each row; short B rows: four
   // A entries per lane, MODE 2; elsewhere the walk)
@@ -1645,6 +1684,20 @@ static void launch_stored(int64_t n, const CsrView& A, const CsrView& B, int wca
   const int gq = G / 4 < 4 ? 4 : G / 4;
   const bool many = (double)n * gq / 64.0 >= 2048.0;
   const bool fits = (size_t)(256 / gq) * wlds * sizeof(uint32_t) <= 32 * 1024;
+  // few rows of many products: several groups per row, up to about 2048
+  // groups in all, each with at least 8 products per lane (the latency of
+  // a lone group walking a long row is what bounds such a launch); where
+  // a slice is too short to give each lane two A entries to walk, B rows of
+  // two dozen entries or more are flattened over the lanes instead
+  // (measured: the walk is faster for long slices, the flattened loads for
+  // short ones)
+  int nsl = 1;
+  if (which == 1 && !many && n > 0) {
+    const double want = std::ceil(2048.0 / (double)n);
+    const double most = std::min(std::floor(avg_a * avg_b / (8.0 * G)), std::floor(avg_a));
+    nsl = (int)std::max(1.0, std::min(std::min(want, most), 64.0));
+  }
+  const bool flat_sl = flat || (avg_a / nsl < 2.0 * G && avg_b >= 24.0);
   if (which == 0 && many) {
     stored_q_dispatch(gq, n, A, B, wcap, rlo, rwords, wcnt, ovf, novf, 0, nullptr, nullptr, 0, s);
   } else if (which == 0) {
@@ -1652,6 +1705,21 @@ static void launch_stored(int64_t n, const CsrView& A, const CsrView& B, int wca
                                                       rlo, rwords, wcnt, ovf, novf);
   } else if (which == 1 && batched && many && fits) {
     stored_q_dispatch(gq, n, A, B, wcap, rlo, rwords, wcnt, ovf, novf, wlds, wbuf, cnt, 1, s);
+  } else if (which == 1 && nsl > 1) {
+    // few rows: nsl groups per row OR into the zeroed words, then the counts
+    const size_t lds = (size_t)NG * wlds * sizeof(uint32_t);
+    HIP_OK(hipMemsetAsync(wbuf, 0, (size_t)wtotal * sizeof(uint32_t), s));
+    const int64_t ngr = n * nsl;
+    if (flat_sl) {
+      allow_lds((const void*)k_spgemm_bits<G, 1>);
+      k_spgemm_bits<G, 1><<<nblocks(ngr, NG), 256, lds, s>>>(
+          n, A.rowptr, A.col, B.rowptr, B.col, wlds, wcap, rlo, rwords, wcnt, wbuf, cnt, nsl);
+    } else {
+      allow_lds((const void*)k_spgemm_bits<G, 0>);
+      k_spgemm_bits<G, 0><<<nblocks(ngr, NG), 256, lds, s>>>(
+          n, A.rowptr, A.col, B.rowptr, B.col, wlds, wcap, rlo, rwords, wcnt, wbuf, cnt, nsl);
+    }
+    k_spgemm_bits_count<G><<<nblocks(n, NG), 256, 0, s>>>(n, wcap, rwords, wcnt, wbuf, cnt);
   } else if (which == 1) {
     const size_t lds = (size_t)NG * wlds * sizeof(uint32_t);
     if (flat) {
@@ -1677,13 +1745,13 @@ static void launch_stored(int64_t n, const CsrView& A, const CsrView& B, int wca
 static void stored_dispatch(int g, int64_t n, const CsrView& A, const CsrView& B, int wcap,
                             int32_t* rlo, int32_t* rwords, int64_t* wcnt, int32_t* ovf, int* novf,
                             int wlds, uint32_t* wbuf, int64_t* cnt, const int64_t* crp,
-                            int32_t* ccol, int which, hipStream_t s) {
+                            int32_t* ccol, int which, int64_t wtotal, hipStream_t s) {
   switch (g) {
-    case 4: launch_stored<4>(n, A, B, wcap, rlo, rwords, wcnt, ovf, novf, wlds, wbuf, cnt, crp, ccol, which, s); break;
-    case 8: launch_stored<8>(n, A, B, wcap, rlo, rwords, wcnt, ovf, novf, wlds, wbuf, cnt, crp, ccol, which, s); break;
-    case 16: launch_stored<16>(n, A, B, wcap, rlo, rwords, wcnt, ovf, novf, wlds, wbuf, cnt, crp, ccol, which, s); break;
-    case 32: launch_stored<32>(n, A, B, wcap, rlo, rwords, wcnt, ovf, novf, wlds, wbuf, cnt, crp, ccol, which, s); break;
-    default: launch_stored<64>(n, A, B, wcap, rlo, rwords, wcnt, ovf, novf, wlds, wbuf, cnt, crp, ccol, which, s); break;
+    case 4: launch_stored<4>(n, A, B, wcap, rlo, rwords, wcnt, ovf, novf, wlds, wbuf, cnt, crp, ccol, which, wtotal, s); break;
+    case 8: launch_stored<8>(n, A, B, wcap, rlo, rwords, wcnt, ovf, novf, wlds, wbuf, cnt, crp, ccol, which, wtotal, s); break;
+    case 16: launch_stored<16>(n, A, B, wcap, rlo, rwords, wcnt, ovf, novf, wlds, wbuf, cnt, crp, ccol, which, wtotal, s); break;
+    case 32: launch_stored<32>(n, A, B, wcap, rlo, rwords, wcnt, ovf, novf, wlds, wbuf, cnt, crp, ccol, which, wtotal, s); break;
+    default: launch_stored<64>(n, A, B, wcap, rlo, rwords, wcnt, ovf, novf, wlds, wbuf, cnt, crp, ccol, which, wtotal, s); break;
   }
 }
 
@@ -1727,7 +1795,7 @@ void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& pla
     int64_t* bs = ar.alloc<int64_t>(3);
     HIP_OK(hipMemsetAsync(wmax, 0, sizeof(unsigned long long), s));
     stored_dispatch(g, A.nrows, A, B, wcap, rlo, rwords, wincl, ovf, lerr + 1, 0, nullptr,
-                    nullptr, nullptr, nullptr, 0, s);
+                    nullptr, nullptr, nullptr, 0, 0, s);
     k_wcnt_max<<<nblocks(A.nrows, 1024), 256, 0, s>>>(wincl, A.nrows, wmax);
     scan_inclusive(wincl, A.nrows, s, ar);
     k_bounds_summary<<<1, 64, 0, s>>>(wincl, A.nrows, lerr, wmax, bs);
@@ -1739,7 +1807,7 @@ void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& pla
       wbuf = static_cast<uint32_t*>(scratch->get((size_t)(hb[0] > 0 ? hb[0] : 1) * sizeof(uint32_t)));
       const int wlds = (int)std::max<int64_t>(hb[2], 1);
       stored_dispatch(g, A.nrows, A, B, wcap, rlo, rwords, wincl, nullptr, nullptr, wlds, wbuf,
-                      C.rowptr, nullptr, nullptr, 1, s);
+                      C.rowptr, nullptr, nullptr, 1, hb[0], s);
     } else {
       // too many words to keep: the two-pass form (which lists the wide rows again)
       HIP_OK(hipMemsetAsync(lerr + 1, 0, sizeof(int), s));
@@ -1809,7 +1877,7 @@ void spgemm_symbolic(const CsrView& A, const CsrView& B, Csr& C, SpgemmPlan& pla
   // does them)
   if (A.nrows && stored)
     stored_dispatch(g, A.nrows, A, B, wcap, rlo, rwords, wincl, nullptr, nullptr, 0, wbuf,
-                    nullptr, C.rowptr, C.col, 2, s);
+                    nullptr, C.rowptr, C.col, 2, 0, s);
   else if (A.nrows)
     win_dispatch(g, A.nrows, A, B, wcap, nullptr, C.rowptr, C.col, nullptr, nullptr, nullptr, s);
   if (nwide) {
