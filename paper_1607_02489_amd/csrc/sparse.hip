@@ -1966,21 +1966,49 @@ __global__ __launch_bounds__(256) void k_spgemm_num_slices(const int64_t* arp,
       pl = (int)(lo - p0);
     }
     const int cnt = (int)((eb - e0) < G ? (eb - e0) : G);
-    for (int q = 0; q < cnt; q++) {
-      const int64_t pq = __shfl(p0, q, G);
-      const int lq = __shfl(pl, q, G);
-      const TV aq = __shfl(av, q, G);
-      for (int o = lane; o < lq; o += G) {
-        const int32_t j = bcol[pq + o];
-        const TV b = bval[pq + o];
-        int lo = 0, hi = ns;
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (scol[mid] < j) lo = mid + 1; else hi = mid;
-        }
-        acc_add(acc, lo, aq * b);
+    auto slot = [&](int32_t j) {
+      int lo = 0, hi = ns;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (scol[mid] < j) lo = mid + 1; else hi = mid;
       }
-      acc_order<TV>();
+      return lo;
+    };
+    // SU entries at a time: the first G entries of each one's B range are
+    // loaded together, then added in the entries' order (the rest of a range
+    // longer than the group follows its entry's first part)
+    constexpr int SU = 8;
+    for (int q0 = 0; q0 < cnt; q0 += SU) {
+      int64_t pq[SU];
+      int lq[SU], sl[SU];
+      TV aq[SU], pr[SU];
+#pragma unroll
+      for (int u = 0; u < SU; u++) {
+        const int q = q0 + u;
+        pq[u] = __shfl(p0, q, G);
+        lq[u] = q < cnt ? __shfl(pl, q, G) : 0;
+        aq[u] = __shfl(av, q, G);
+        int32_t j = -1;
+        TV b = TV(0);
+        if (lane < lq[u]) {
+          j = bcol[pq[u] + lane];
+          b = bval[pq[u] + lane];
+        }
+        sl[u] = j;
+        pr[u] = b;
+      }
+#pragma unroll
+      for (int u = 0; u < SU; u++) sl[u] = sl[u] >= 0 ? slot(sl[u]) : -1;
+#pragma unroll
+      for (int u = 0; u < SU; u++) {
+        if (sl[u] >= 0) acc_add(acc, sl[u], aq[u] * pr[u]);
+        for (int o = G + lane; o < lq[u]; o += G) {
+          const int32_t j = bcol[pq[u] + o];
+          const TV b = bval[pq[u] + o];
+          acc_add(acc, slot(j), aq[u] * b);
+        }
+        acc_order<TV>();
+      }
     }
   }
   group_sync_lds<G>();
