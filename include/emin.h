@@ -225,8 +225,9 @@ emin_status emin_pattern(const emin_system_t *sys, const emin_params_t *prm, voi
                          emin_pattern_t **out);
 /* emin_pattern with every device block of the handle (the pattern phase's
  * arrays, the EMIN workspace, the RAP plans) taken from *alloc and given
- * back through it by emin_pattern_destroy (or when the call fails, after the
- * stream has drained).  alloc = NULL: the library's own memory, as
+ * back through it by emin_pattern_destroy, once the work the library queued
+ * on the block has completed (or when the call fails, after the stream has
+ * drained).  alloc = NULL: the library's own memory, as
  * emin_pattern.  A block that is not 256-byte aligned is given back and the
  * call fails with EMIN_ERR_ARG; alloc returning NULL fails it with
  * EMIN_ERR_OOM.  The allocator must outlive the handle. */
@@ -345,11 +346,15 @@ emin_status emin_sync_report(const emin_report_t *report, void *stream, emin_rep
 emin_status emin_memcpy_d2h(void *dst_host, const void *src_dev, size_t bytes, void *stream);
 
 /* Releases the handle.  Its device memory returns to a process-wide cache of
- * chunks that later handles reuse (no hipFree, so no device-wide wait); the
- * caller must make sure no queued work still uses the handle (synchronise
- * the streams it was used on).  NULL-safe. */
+ * chunks that later allocations on the same device reuse (no hipFree, so no
+ * device-wide wait).  Work that this library's calls queued on the handle is
+ * tracked: its chunks are handed out again only after the last such work has
+ * completed.  Two cases stay the caller's to finish before the call: its own
+ * work that reads the handle's arrays (emin_pattern_view), and replays of a
+ * graph captured from the handle's calls.  NULL-safe. */
 void emin_pattern_destroy(emin_pattern_t *h);
-/* Frees the cached device chunks; returns the bytes released. */
+/* Frees the cached device chunks (after the work last queued on each has
+ * completed); returns the bytes released. */
 int64_t emin_release_cached(void);
 
 /* Autotuner bookkeeping (process-wide): out[0] shapes tuned by timing,
@@ -388,7 +393,7 @@ emin_status emin_hierarchy_level(const emin_hierarchy_t *h, int32_t level, emin_
                                  const double **Bc, const emin_report_t **report);
 /* Device memory held by the hierarchy and its pattern handles (bytes). */
 int64_t emin_hierarchy_device_bytes(const emin_hierarchy_t *h);
-/* Same contract as emin_pattern_destroy (no queued work may use it). */
+/* Same contract as emin_pattern_destroy. */
 void emin_hierarchy_destroy(emin_hierarchy_t *h);
 
 /* Batched form: builds count hierarchies concurrently, one host thread and
