@@ -92,3 +92,38 @@ def test_failing_allocator_reports_oom_and_gives_back():
         f"{ei.value.status}, outstanding {len(out2)}")
     assert ei.value.status == 9         # EMIN_ERR_OOM
     assert calls2[0] == nblocks and not out2
+
+
+def test_destroy_with_queued_work_keeps_chunks_from_reuse():
+    """A handle destroyed while its set-up is still queued on one stream: its
+    chunks go back to the cache with that work's completion point, so a level
+    built at once on a second stream takes other memory until the work has
+    run.  Both results equal the level built alone."""
+    import torch
+    from paper_1607_02489_amd import emin as E
+    s = synth.stokes3d(16)
+    say(f"[gpu] destroy with queued work, 3-D Stokes 16^3: dofs={s.dofs}")
+    d = E.DeviceSystem.upload(s)
+    prm = E.params(iters=5)
+    ref, want = _level(E, d, prm)
+    ref.close()
+    torch.cuda.synchronize()
+    E.release_cached()
+    f64 = dict(dtype=torch.float64, device="cuda")
+    pat = E.Pattern(d, prm)
+    z = pat.sizes
+    bufs = [torch.empty(max(z[k], 1), **f64) for k in ("nnz_Pv", "nnz_Pp", "nnz_Ac", "nnz_Bc")]
+    Pv, Pp, Ac, Bc = (t.data_ptr() for t in bufs)
+    for _ in range(4):            # enough queued work to outlast the next build's allocations
+        pat.setup(prm, Pv, Pp)
+        pat.rap(Pv, Pp, Ac, Bc)
+    pat.close()                   # its set-ups may still be running
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        other, got = _level(E, d, prm)
+    torch.cuda.synchronize()
+    first = [t.cpu().numpy() for t in bufs]
+    for a, b, c in zip(first, got, want):
+        assert np.array_equal(a[:len(c)], c)
+        assert np.array_equal(b, c)
+    other.close()
