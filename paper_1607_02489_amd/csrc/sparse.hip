@@ -2325,21 +2325,62 @@ void filter_numeric(const CsrView& A, const uint8_t* keep, const double* d, cons
 // ---------------------------------------------------------------------------
 // M = (A + A^T)/2 on the union pattern, m_ij = (a_ij + a_ji)*0.5
 // ---------------------------------------------------------------------------
-__global__ void k_union(const int64_t* arp, const int32_t* acol, const int64_t* trp,
-                        const int32_t* tcol, const int32_t* tsrc, int64_t n, int64_t* cnt,
-                        const int64_t* mrp, int32_t* mcol, int32_t* ia, int32_t* ib) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Row i of the union pattern: a merge of A's row i with row i of A^T (the
+// transposed entries carry their source position in A), one thread per row;
+// ia/ib give each union entry's position in A for a_ij and a_ji (-1: absent).
+// UB consecutive rows per block, their entries of A and of the transpose
+// first staged in LDS with coalesced loads (a per-thread walk over global
+// memory is bound by its dependent, scattered loads); a block whose rows hold
+// more than UCAP entries of either merges from global memory instead.
+constexpr int UB = 128, UCAP = 4096;
+__global__ __launch_bounds__(UB) void k_union_blk(const int64_t* arp, const int32_t* acol,
+                                                  const int64_t* trp, const int32_t* tcol,
+                                                  const int32_t* tsrc, int64_t n, int64_t* cnt,
+                                                  const int64_t* mrp, int32_t* mcol, int32_t* ia,
+                                                  int32_t* ib) {
+  __shared__ int32_t sa[UCAP], st[UCAP], ss[UCAP];
+  const int64_t i0 = (int64_t)blockIdx.x * UB;
+  const int64_t i1 = i0 + UB < n ? i0 + UB : n;
+  const int64_t ba = arp[i0], bt = trp[i0];
+  const int64_t na = arp[i1] - ba, nt = trp[i1] - bt;
+  const bool staged = na <= UCAP && nt <= UCAP;   // uniform over the block
+  if (staged) {
+    for (int64_t t = threadIdx.x; t < na; t += UB) sa[t] = acol[ba + t];
+    for (int64_t t = threadIdx.x; t < nt; t += UB) {
+      st[t] = tcol[bt + t];
+      ss[t] = tsrc[bt + t];
+    }
+  }
+  __syncthreads();
+  const int64_t i = i0 + threadIdx.x;
   if (i >= n) return;
   int64_t a = arp[i], ae = arp[i + 1], b = trp[i], be = trp[i + 1];
   int64_t p = mrp ? mrp[i] : 0, c = 0;
-  while (a < ae || b < be) {
-    int32_t j;
-    int32_t x = -1, y = -1;
-    if (b >= be || (a < ae && acol[a] < tcol[b])) { j = acol[a]; x = (int32_t)a; a++; }
-    else if (a >= ae || tcol[b] < acol[a]) { j = tcol[b]; y = tsrc[b]; b++; }
-    else { j = acol[a]; x = (int32_t)a; y = tsrc[b]; a++; b++; }
-    if (mcol) { mcol[p + c] = j; ia[p + c] = x; ib[p + c] = y; }
-    c++;
+  if (staged) {
+    int la = (int)(a - ba);
+    const int lae = (int)(ae - ba);
+    int lb = (int)(b - bt);
+    const int lbe = (int)(be - bt);
+    while (la < lae || lb < lbe) {
+      int32_t j, x = -1, y = -1;
+      const int32_t ca = la < lae ? sa[la] : INT32_MAX;
+      const int32_t ct = lb < lbe ? st[lb] : INT32_MAX;
+      if (ca < ct) { j = ca; x = (int32_t)(ba + la); la++; }
+      else if (ct < ca) { j = ct; y = ss[lb]; lb++; }
+      else { j = ca; x = (int32_t)(ba + la); y = ss[lb]; la++; lb++; }
+      if (mcol) { mcol[p + c] = j; ia[p + c] = x; ib[p + c] = y; }
+      c++;
+    }
+  } else {
+    while (a < ae || b < be) {
+      int32_t j;
+      int32_t x = -1, y = -1;
+      if (b >= be || (a < ae && acol[a] < tcol[b])) { j = acol[a]; x = (int32_t)a; a++; }
+      else if (a >= ae || tcol[b] < acol[a]) { j = tcol[b]; y = tsrc[b]; b++; }
+      else { j = acol[a]; x = (int32_t)a; y = tsrc[b]; a++; b++; }
+      if (mcol) { mcol[p + c] = j; ia[p + c] = x; ib[p + c] = y; }
+      c++;
+    }
   }
   if (cnt) cnt[i + 1] = c;
 }
@@ -2361,17 +2402,17 @@ void symmetrize_symbolic(const Csr& A, Csr& M, int32_t*& ia, int32_t*& ib, hipSt
   M.nrows = M.ncols = A.nrows;
   M.rowptr = ar.alloc<int64_t>(A.nrows + 1);
   if (A.nrows)
-    k_union<<<nblocks(A.nrows, 256), 256, 0, s>>>(A.rowptr, A.col, T.rowptr, T.col, tsrc,
-                                                   A.nrows, M.rowptr, nullptr, nullptr, nullptr,
-                                                   nullptr);
+    k_union_blk<<<nblocks(A.nrows, UB), UB, 0, s>>>(A.rowptr, A.col, T.rowptr, T.col, tsrc,
+                                                     A.nrows, M.rowptr, nullptr, nullptr,
+                                                     nullptr, nullptr);
   M.nnz = rowptr_from_counts(M.rowptr, A.nrows, s, ar);
   M.col = ar.alloc<int32_t>(M.nnz);
   M.val = ar.alloc<double>(M.nnz);
   ia = ar.alloc<int32_t>(M.nnz);
   ib = ar.alloc<int32_t>(M.nnz);
   if (A.nrows)
-    k_union<<<nblocks(A.nrows, 256), 256, 0, s>>>(A.rowptr, A.col, T.rowptr, T.col, tsrc,
-                                                   A.nrows, nullptr, M.rowptr, M.col, ia, ib);
+    k_union_blk<<<nblocks(A.nrows, UB), UB, 0, s>>>(A.rowptr, A.col, T.rowptr, T.col, tsrc,
+                                                     A.nrows, nullptr, M.rowptr, M.col, ia, ib);
 }
 
 void symmetrize_numeric(const double* aval, const int32_t* ia, const int32_t* ib, Csr& M,
