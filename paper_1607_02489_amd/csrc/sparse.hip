@@ -235,10 +235,24 @@ __global__ __launch_bounds__(256) void k_filter_fill_g(const int64_t* rp, const 
     const bool k = ok && j != i && keep[e];
     const bool dropped = ok && j != i && !keep[e];
     uint64_t md = group_ballot<G>(dropped);
-    while (md) {
-      const int t = __builtin_ctzll(md);
-      md &= md - 1ull;
-      lump = lump + __shfl(v, t, G);
+    if constexpr (G == 64) {
+      // the group is the wave: t is uniform, and a lane read through the
+      // scalar unit is far shorter than a shuffle on this serial chain
+      const int64_t vb = __double_as_longlong(v);
+      const int32_t vlo = (int32_t)(vb & 0xffffffffll), vhi = (int32_t)(vb >> 32);
+      while (md) {
+        const int t = __builtin_ctzll(md);
+        md &= md - 1ull;
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane(vlo, t);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane(vhi, t);
+        lump = lump + __longlong_as_double((int64_t)(((uint64_t)hi << 32) | lo));
+      }
+    } else {
+      while (md) {
+        const int t = __builtin_ctzll(md);
+        md &= md - 1ull;
+        lump = lump + __shfl(v, t, G);
+      }
     }
     const uint64_t mk = group_ballot<G>(k);
     if (k) {
