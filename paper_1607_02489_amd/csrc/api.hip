@@ -288,11 +288,11 @@ void build_pattern(emin_pattern_t* h, const emin_system_t* sys, const emin_param
       h->dA = ar.alloc<double>(nv);
       diag_of(A, h->dA, s2);
       h->keep_v = ar.alloc<uint8_t>(A.nnz);
-      filter_symbolic(A, prm->tau1_v, h->dA, h->keep_v, h->Atv, s2, ar);
+      h->dir = ar.alloc<uint8_t>(nv);
+      // (the Dirichlet flags come from the filter's count pass)
+      filter_symbolic(A, prm->tau1_v, h->dA, h->keep_v, h->Atv, s2, ar, h->dir);
       symmetrize_symbolic(h->Atv, h->Mv, h->mv_ia, h->mv_ib, s2, ar);
       symmetrize_numeric(h->Atv.val, h->mv_ia, h->mv_ib, h->Mv, s2);
-      h->dir = ar.alloc<uint8_t>(nv);
-      dirichlet_rows(A, h->dir, s2);
       HIP_OK(hipEventRecord(side.join, s2));
       HIP_OK(hipStreamWaitEvent(s, side.join, 0));
     } catch (...) {

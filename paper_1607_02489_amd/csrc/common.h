@@ -331,10 +331,12 @@ void spgemm_numeric_f32(const CsrView& A, const float* aval, const CsrView& B, c
                         hipStream_t s);
 void gather_values_f(const float* in, const int32_t* src, float* out, int64_t n, hipStream_t s);
 
-// filter of eq. (e:filtering) with lumping; keep mask per entry of A
+// filter of eq. (e:filtering) with lumping; keep mask per entry of A; dir
+// (optional): the rows' Dirichlet flags from the same pass (1 where no
+// off-diagonal value of the row is nonzero)
 void diag_of(const CsrView& A, double* d, hipStream_t s);
 void filter_symbolic(const CsrView& A, double tau1, const double* d, uint8_t* keep, Csr& At,
-                     hipStream_t s, Arena& ar);
+                     hipStream_t s, Arena& ar, uint8_t* dir = nullptr);
 void filter_numeric(const CsrView& A, const uint8_t* keep, const double* d, const Csr& At,
                     hipStream_t s);
 // M = (A + A^T)/2 on the union pattern; ia/ib = entry of A / of A (transposed
@@ -343,7 +345,6 @@ void symmetrize_symbolic(const Csr& A, Csr& M, int32_t*& ia, int32_t*& ib, hipSt
                          Arena& ar);
 void symmetrize_numeric(const double* aval, const int32_t* ia, const int32_t* ib, Csr& M,
                         hipStream_t s);
-void dirichlet_rows(const CsrView& A, uint8_t* dir, hipStream_t s);
 void validate_csr(const CsrView& A, bool values, int* derr, hipStream_t s);
 
 // ---------------------------------------------------------------------------

@@ -166,30 +166,20 @@ __global__ __launch_bounds__(256) void k_validate_g(const int64_t* rp, const int
   if (badv) atomicOr(derr, DERR_VALUE);
 }
 
-template <int G>
-__global__ __launch_bounds__(256) void k_dirichlet_g(const int64_t* rp, const int32_t* col,
-                                                    const double* val, int64_t n, uint8_t* dir) {
-  const int64_t i = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
-  const int lane = threadIdx.x % G;
-  if (i >= n) return;
-  bool nz = false;
-  for (int64_t e = rp[i] + lane; e < rp[i + 1]; e += G)
-    if (col[e] != i && val[e] != 0.0) nz = true;
-  const uint64_t m = group_ballot<G>(nz);
-  if (lane == 0) dir[i] = m ? 0 : 1;
-}
-
-// eq. (e:filtering), squared form, per entry; the row count adds the diagonal
+// eq. (e:filtering), squared form, per entry; the row count adds the diagonal.
+// dir (optional): the Dirichlet flags of the rows, from the same pass (a row
+// is Dirichlet when no off-diagonal value is nonzero)
 template <int G>
 __global__ __launch_bounds__(256) void k_filter_count_g(const int64_t* rp, const int32_t* col,
                                                        const double* val, int64_t n, double t2,
                                                        const double* d, uint8_t* keep,
-                                                       int64_t* cnt) {
+                                                       int64_t* cnt, uint8_t* dir) {
   const int64_t i = (int64_t)blockIdx.x * (256 / G) + threadIdx.x / G;
   const int lane = threadIdx.x % G;
   if (i >= n) return;
   const double di = d[i];
   int64_t c = 1;
+  bool nz = false;
   for (int64_t e0 = rp[i]; e0 < rp[i + 1]; e0 += G) {
     const int64_t e = e0 + lane;
     bool kept_off = false;
@@ -202,12 +192,17 @@ __global__ __launch_bounds__(256) void k_filter_count_g(const int64_t* rp, const
         const double rhs = t2 * fabs(di * d[j]);
         k = lhs > rhs;
         kept_off = k;
+        if (v != 0.0) nz = true;
       }
       keep[e] = k;
     }
     c += __popcll(group_ballot<G>(kept_off));
   }
-  if (lane == 0) cnt[i + 1] = c;
+  const uint64_t m = group_ballot<G>(nz);
+  if (lane == 0) {
+    cnt[i + 1] = c;
+    if (dir) dir[i] = m ? 0 : 1;
+  }
 }
 
 // Filtered row: kept off-diagonals in column order with the diagonal at its
@@ -2314,13 +2309,13 @@ void diag_of(const CsrView& A, double* d, hipStream_t s) {
 
 
 void filter_symbolic(const CsrView& A, double tau1, const double* d, uint8_t* keep, Csr& At,
-                     hipStream_t s, Arena& ar) {
+                     hipStream_t s, Arena& ar, uint8_t* dir) {
   At.nrows = At.ncols = A.nrows;
   At.rowptr = ar.alloc<int64_t>(A.nrows + 1);
   const double t2 = tau1 * tau1;
   if (A.nrows)
     ROWS_DISPATCH(lanes_for(A), k_filter_count_g, A.nrows, s, A.rowptr, A.col, A.val, A.nrows, t2,
-                  d, keep, At.rowptr);
+                  d, keep, At.rowptr, dir);
   At.nnz = rowptr_from_counts(At.rowptr, A.nrows, s, ar);
   At.col = ar.alloc<int32_t>(At.nnz);
   At.val = ar.alloc<double>(At.nnz);
@@ -2434,11 +2429,5 @@ void symmetrize_numeric(const double* aval, const int32_t* ia, const int32_t* ib
   if (M.nnz) k_sym_vals<<<nblocks(M.nnz, 256), 256, 0, s>>>(aval, ia, ib, M.val, M.nnz);
 }
 
-// a Dirichlet row has no nonzero off-diagonal value
-
-void dirichlet_rows(const CsrView& A, uint8_t* dir, hipStream_t s) {
-  if (A.nrows)
-    ROWS_DISPATCH(lanes_for(A), k_dirichlet_g, A.nrows, s, A.rowptr, A.col, A.val, A.nrows, dir);
-}
 
 }  // namespace emin
